@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the MGAR topology-optimisation hot path on one MI355X.
+
+A step is one optimisation cycle of the 128^3 trilinear-hex heat-conduction
+problem: density filter, SIMP conductivity, the solve (MGAR reanalysis with
+MGCG fallback, or plain MGCG for the reference loop) to relative residual
+1e-8, compliance and sensitivities, and the OC update. All inputs live in HBM
+before the timed region. Warmup steps run the first cycles of the loop (the
+cycles below N_on use MGCG in both loops); the timed steps continue it.
+
+Prints one JSON line:
+  value          DOF-solves/s of the MGAR loop (free DOFs x solves / second)
+  ms_per_step    MGAR loop, milliseconds per optimisation cycle
+  mgcg           the same figures for the plain-MGCG loop on the same GPU
+  roofline       the finest-grid stencil kernel named there: algorithmic bytes
+                 per launch / average launch time from HIP events around each
+                 launch in the timed region, against 8 TB/s
+  cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
+                 solve of the same grid
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# finest-grid stencil kernel reported in the roofline object (mode bit of mgar_profile)
+ROOF_MODE = 1          # apply + dot: q = K p, p.q  (one launch per CG iteration, finest grid only)
+ROOF_KERNEL = "k_stencil<3, SM_APPLY_DOT> (finest grid, q = K p with p.q)"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch):
+    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar)
+    for _ in range(warmup):
+        opt.step()
+    opt.h.mgar_profile(1 << ROOF_MODE)
+    opt.h.mgar_profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [opt.step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n, ms, by = opt.h.mgar_profile_read()
+    opt.h.mgar_profile(0)
+    el = t1 - t0
+    paths = {"mgcg": 0, "accept": 0, "fallback": 0}
+    for r in recs:
+        paths[["mgcg", "accept", "fallback"][r.path]] += 1
+    out = {
+        "elapsed_s": el,
+        "s_per_opt_iter": el / steps,
+        "cg_iters_mean": sum(r.cg_iters for r in recs) / steps,
+        "paths": paths,
+        "final_compliance": recs[-1].compliance,
+        "kernel_launches": n,
+        "kernel_ms_total": ms,
+        "kernel_bytes_total": by,
+    }
+    opt.h.close()
+    return out
+
+
+def cpu_baseline(prob, W):
+    """One full oracle MGCG solve on the benchmark grid (FP64, SciPy), timed
+    with perf_counter; cores = process CPU time / wall time."""
+    import numpy as np
+    from oracle import solvers
+    xphys = W.reseeded_density(prob, 0)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    _, st = s.mgcg(xphys, np.zeros(prob.nnodes), prob.tol)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    free = int(s.fep.free.size)
+    return {
+        "value": free / wall,
+        "unit": "DOF-solves/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": (f"one oracle MGCG solve (assembled CSR K, 6-level V-cycle, dense coarsest "
+                   f"Cholesky) of the {prob.nelx}^3 grid from T0 = 0 at rel. residual "
+                   f"{prob.tol:g}, densities uniform(0.3, 0.5) seed 0; {st.cg_iters} CG iterations, "
+                   f"{wall:.1f} s wall incl. assembly"),
+        "seconds": wall,
+        "cpu_model": _cpu_model(),
+        "os_cpu_count": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=71, help="timed optimisation cycles")
+    ap.add_argument("--warmup", type=int, default=9, help="untimed cycles before the timed ones")
+    ap.add_argument("--config", default="c3", help="workload: c0, c1, c2 or c3 (default 128^3)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent designs would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2210_00947_amd import mgar as M
+    from paper_2210_00947_amd.topopt import TopOpt
+
+    M.lib()
+    prob = W.CONFIGS[args.config]
+    nfix = 1
+    for a in range(prob.dim):
+        nfix *= prob.fix_hi[a] - prob.fix_lo[a] + 1
+    free = prob.nnodes - nfix
+    log(f"[bench] {prob.name}: {prob.nnodes} nodes, {free} free DOFs; warmup {args.warmup}, steps {args.steps}")
+    mg_ar = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch)
+    log(f"[bench] MGAR loop: {mg_ar['s_per_opt_iter']*1e3:.3f} ms/cycle, paths {mg_ar['paths']}")
+    mgcg = None
+    if not args.no_mgcg:
+        mgcg = run_loop(prob, False, args.warmup, args.steps, W, TopOpt, torch)
+        log(f"[bench] MGCG loop: {mgcg['s_per_opt_iter']*1e3:.3f} ms/cycle")
+    value = free * args.steps / mg_ar["elapsed_s"]
+    roof = None
+    if mg_ar["kernel_launches"] > 0:
+        avg_s = mg_ar["kernel_ms_total"] / mg_ar["kernel_launches"] * 1e-3
+        per_launch = mg_ar["kernel_bytes_total"] / mg_ar["kernel_launches"]
+        achieved = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": ROOF_KERNEL,
+                "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
+                "launches": mg_ar["kernel_launches"]}
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle (one MGCG solve) ...")
+        cpu = cpu_baseline(prob, W)
+        log(f"[bench] oracle: {cpu['seconds']:.1f} s")
+    out = {
+        "metric": "s/opt-iter & DOF-solves/s at 128^3 hex, MGAR vs MGCG @rel.res 1e-8; HBM GB/s",
+        "value": value,
+        "unit": "DOF-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mg_ar["s_per_opt_iter"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{prob.name}: SIMP heat-conduction topology optimisation, "
+                                f"{prob.nelx}x{prob.nely}x{prob.nelz} trilinear hex, {prob.levels} MG levels, "
+                                f"MGAR m=2 eps1=tol={prob.tol:g}, OC move {prob.move}, "
+                                f"cycles {args.warmup + 1}..{args.warmup + args.steps}"),
+                   "nodes": prob.nnodes, "free_dofs": free, "levels": prob.levels},
+        "s_per_opt_iter": {"mgar": mg_ar["s_per_opt_iter"],
+                           "mgcg": mgcg["s_per_opt_iter"] if mgcg else None},
+        "dof_solves_per_s": {"mgar": value,
+                             "mgcg": free * args.steps / mgcg["elapsed_s"] if mgcg else None},
+        "mgar": mg_ar,
+        "mgcg": mgcg,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

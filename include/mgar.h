@@ -1,0 +1,178 @@
+/*
+ * mgar.h -- C ABI of libmgar.so, a gfx950 (MI355X) implementation of the solve
+ * path of Multigrid Assisted Reanalysis (MGAR) for SIMP heat-conduction
+ * topology optimisation.
+ *
+ * Problem (Eq 2-5): steady isotropic conduction on a structured grid of unit
+ * square (2D, bilinear) or cubic (3D, trilinear) cells, discretised to
+ * K(rho~) t = q, with the SIMP conductivity of Eq 4 per element, Dirichlet
+ * T = 0 on a box of nodes and a fixed internal heat source.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Numbering: node (i, j, k) -> i + (nelx+1) * (j + (nely+1) * k); element
+ *   (ex, ey, ez) -> ex + nelx * (ey + nely * ez); in 2D k = ez = 0.
+ *   An N-vector has (nelx+1)(nely+1)(nelz+1) entries (nelz+1 := 1 in 2D), an
+ *   E-vector nelx*nely*nelz entries (nelz := 1 in 2D).
+ * Memory: every array argument is a DEVICE pointer to contiguous FP64 data,
+ *   owned by the caller, unless the comment says "host". The library never
+ *   frees or keeps caller memory beyond a call. Outputs must not alias inputs
+ *   unless stated.
+ * Streams: all work is enqueued on the stream given to mgar_setup (or
+ *   mgar_set_stream) in stream order. Entry points that return host scalars
+ *   (stats, compliance, lambda) synchronise that stream before returning.
+ * Dirichlet nodes: every N-vector the library writes is exactly 0 there;
+ *   N-vector inputs are read as 0 there.
+ * Errors: nothing throws across the ABI. 0 = success; > 0 = warning with the
+ *   outputs written; < 0 = error, outputs unspecified but no memory owned by
+ *   the caller is touched beyond the outputs. mgar_strerror() gives text.
+ * Threading: a handle may be used by one host thread at a time.
+ */
+#ifndef MGAR_H
+#define MGAR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGAR_OK 0
+#define MGAR_W_NOT_CONVERGED 1   /* cg_max reached; outputs hold the last iterate */
+#define MGAR_E_ARG (-1)          /* bad argument or null pointer */
+#define MGAR_E_DIMS (-2)         /* elements per axis not a multiple of 2^(levels-1), or coarsest grid too large */
+#define MGAR_E_SINGULAR (-3)     /* the coarsest grid holds no Dirichlet node */
+#define MGAR_E_HIP (-4)          /* HIP runtime error */
+#define MGAR_E_NOT_SPD (-5)      /* non-positive pivot in the reduced or coarsest system */
+#define MGAR_E_PRECISION (-6)    /* unsupported precision mode */
+#define MGAR_E_STATE (-7)        /* reanalysis called before any MGCG solve set K0 */
+
+#define MGAR_PATH_MGCG 0         /* pure MGCG solve */
+#define MGAR_PATH_ACCEPT 1       /* reduced (reanalysis) solution accepted, Eq 28 */
+#define MGAR_PATH_FALLBACK 2     /* reduced solution rejected; MGCG from it, K0 renewed */
+
+#define MGAR_PREC_FP64 0         /* every operation in FP64 */
+#define MGAR_PREC_MIXED 1        /* FP32 multigrid over BF16 densities inside FP64 iterative refinement */
+
+#define MGAR_MAX_BASIS 8
+
+typedef struct mgar_handle mgar_handle;
+
+/* Problem and solver parameters (Sec. 2.1-3.2). */
+typedef struct {
+  int dim;                /* 2 or 3 */
+  int nelx, nely, nelz;   /* elements per axis; nelz ignored in 2D */
+  int levels;             /* number of MG grids including the finest (the paper's nl, Sec. 3.2) */
+  int fix_lo[3];          /* inclusive node-index box of Dirichlet (T = 0) nodes, finest grid */
+  int fix_hi[3];          /*   (third entries ignored in 2D) */
+  double k0, kmin, penal; /* SIMP, Eq 4: 1, 1e-3, 3 */
+  double omega;           /* damped-Jacobi weight (Sec. 2.2 (ii)); 0.8 */
+  int n_basis;            /* m, reanalysis basis size (Eq 14), 1..MGAR_MAX_BASIS; 2 */
+  double eps_accept;      /* eps1 of Eq 28 */
+  int cg_max;             /* maximum CG iterations per MGCG solve */
+  int basis_x0_zero;      /* 0: V-cycle initial guess r_{i-1} as printed in Eq 17; 1: zero */
+  int precision;          /* MGAR_PREC_FP64 or MGAR_PREC_MIXED */
+  double filter_r;        /* cone density-filter radius, Eq 7-8 (element lengths) */
+} mgar_params;
+
+/* Per-solve report. */
+typedef struct {
+  int path;               /* MGAR_PATH_* */
+  int cg_iters;           /* CG iterations (each applies one V-cycle) */
+  int vcycles;            /* V-cycles, including those that built the basis */
+  int refinements;        /* outer FP64 refinement steps (mixed mode) */
+  double res_ca;          /* Eq 28 residual of the reduced solution (NaN for pure MGCG) */
+  double res_final;       /* ||q - K t|| / ||q|| of the returned t: recursive residual of the last CG iterate */
+  float ms;               /* device time of the call, milliseconds */
+} mgar_stats;
+
+/* Fill *p with the defaults above for a grid; fix box empty. */
+void mgar_default_params(mgar_params* p);
+
+/* Create a handle: validates the grid (levels, divisibility, a Dirichlet node
+ * on the coarsest grid, coarsest grid at most 1024 nodes), allocates all
+ * device workspace, precomputes the filter normalisation. `stream` is a
+ * hipStream_t (NULL = default stream). Returns MGAR_OK and *out, or an error. */
+int mgar_setup(const mgar_params* p, void* stream, mgar_handle** out);
+void mgar_destroy(mgar_handle* h);
+int mgar_set_stream(mgar_handle* h, void* stream);
+const char* mgar_strerror(int code);
+/* Sizes: nodes, elements, and the nodes of grid `level`. */
+int mgar_sizes(const mgar_handle* h, int level, long long* nnodes, long long* nelem);
+
+/* Nodal heat load from a per-element source Qe (E-vector, source per unit
+ * volume): q_i = sum over elements e at node i of Qe_e * |e| / 2^d, 0 on
+ * Dirichlet nodes (consistent Q1 load of Eq 3). */
+int mgar_load_vector(mgar_handle* h, const double* Qe, double* q);
+
+/* Density filter, Eq 6-8: xphys_e = sum_j w_ej x_j / sum_j w_ej with the cone
+ * weight w_ej = max(0, r - |c_e - c_j|), truncated at the domain boundary. */
+int mgar_density_filter(mgar_handle* h, const double* x, double* xphys);
+
+/* MGCG: PCG preconditioned by one V-cycle on K(xphys), started from T0 (may be
+ * NULL = 0), until ||r||/||q|| <= tol or cg_max iterations. Makes K(xphys) the
+ * factorised matrix K0 used by mgar_solve. T: N-vector output. stats may be
+ * NULL. Returns MGAR_OK or MGAR_W_NOT_CONVERGED. */
+int mgcg_solve(mgar_handle* h, const double* xphys, const double* q, const double* T0,
+               double tol, double* T, mgar_stats* stats);
+
+/* MGAR reanalysis (Eq 12-21, Eq 28, Sec. 3.1): basis r_1 = T0, r_i = one
+ * V-cycle on K0 for K0 r_i = -(K - K0) r_{i-1}; Gram-Schmidt; reduced solve;
+ * accept when Res <= eps_accept, else MGCG from the reduced solution to tol,
+ * renewing K0. Requires a previous mgcg_solve (MGAR_E_STATE otherwise). */
+int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const double* T0,
+               double tol, double* T, mgar_stats* stats);
+
+/* Compliance and sensitivities (Eq 5, 9-11): *compliance (host) = q^T T;
+ * dc = filter adjoint of -p (k0-kmin) xphys^(p-1) T_e^T KE T_e; dv = filter
+ * adjoint of 1. dc, dv: E-vector outputs. */
+int sens_filter(mgar_handle* h, const double* xphys, const double* T, const double* q,
+                double* dc, double* dv, double* compliance);
+
+/* Optimality-criteria update: x_new = clamp(x sqrt(max(0,-dc)/(dv lambda)),
+ * max(0, x-move), min(1, x+move)) with lambda bisected on [0, 1e9] until
+ * (l2-l1)/(l1+l2) <= 1e-10 so that the filtered volume sum_e dv_e x_new_e
+ * meets volfrac * E. *lambda (host) receives the final midpoint; may be NULL. */
+int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv,
+              double volfrac, double move, double* x_new, double* lambda);
+
+/* Drop K0: the next mgar_solve returns MGAR_E_STATE until an mgcg_solve. */
+int mgar_reset(mgar_handle* h);
+
+/* ---- Operator-level entry points (same conventions). `level` 0 is the
+ * finest grid; grid l has elements of edge 2^l. Element conductivities `k`
+ * are E_l-vectors of grid `level`. -------------------------------------- */
+
+/* y = K_l(k) x (Eq 3 on grid l, rediscretised). */
+int mgar_op_apply(mgar_handle* h, int level, const double* k, const double* x, double* y);
+/* One damped-Jacobi sweep on grid l: out = x + omega D^-1 (b - K_l x). */
+int mgar_op_jacobi(mgar_handle* h, int level, const double* k, const double* b,
+                   const double* x, double* out);
+/* Restriction of Table 1 step 2: rc = P_l^T rf (grid l -> grid l+1). */
+int mgar_op_restrict(mgar_handle* h, int level, const double* rf, double* rc);
+/* Interpolation of Table 1 step 4: xf += P_l xc (grid l+1 -> grid l). */
+int mgar_op_prolong(mgar_handle* h, int level, const double* xc, double* xf);
+/* Coarse conductivity: kc = mean of the 2^d children of each grid-(l+1) element. */
+int mgar_op_coarsen(mgar_handle* h, int level, const double* kf, double* kc);
+/* Make K(xphys) the factorised matrix K0: SIMP, coarse conductivities and the
+ * coarsest-grid inverse (Table 1 step 3). */
+int mgar_build_hierarchy(mgar_handle* h, const double* xphys);
+/* One V-cycle of Table 1 on the K0 hierarchy: x = MG(K0, b, x0); x0 may be NULL (zero). */
+int mgar_vcycle(mgar_handle* h, const double* b, const double* x0, double* x);
+/* b = -(K(xphys) - K0) r: the right-hand side of Eq 15/17. */
+int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b);
+
+/* ---- Instrumentation. ------------------------------------------------------
+ * Kernel timing for roofline reports: while enabled, every launch of a
+ * finest-grid stencil kernel whose mode bit is set in `mode_mask` is bracketed
+ * by two HIP events on the handle's stream (bit i = mode i: 0 apply, 1 apply +
+ * dot, 2 residual, 3 Jacobi sweep, 4 Jacobi sweep + dot, 5 sweep from zero,
+ * 6 -dK apply). mgar_profile_read returns, and resets, the number of such
+ * launches, their summed event time in milliseconds and their summed
+ * algorithmic HBM bytes (every operand vector read once, every result written
+ * once). mode_mask = 0 disables timing. */
+int mgar_profile(mgar_handle* h, unsigned mode_mask);
+int mgar_profile_read(mgar_handle* h, long long* launches, double* total_ms, double* total_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGAR_H */

@@ -182,3 +182,29 @@ class FEProblem:
         out = np.zeros(self.grid.nnodes)
         out[self.free] = vf
         return out
+
+
+def apply_rows(grid: Grid, kelem: np.ndarray, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """(K x)_i for the selected node ids only, straight from the element sum of
+    Eq 3: y_i = sum_{e contains i} k_e sum_c KE[c_i, c] x_{node(e, c)}. For
+    spot checks on grids too large to assemble."""
+    ke = element_matrix(grid.dim, grid.h)
+    nc = grid.node_coords()[rows]
+    dims = [grid.nx, grid.ny] + ([grid.nz] if grid.dim == 3 else [])
+    out = np.zeros(len(rows))
+    for off in itertools.product((-1, 0), repeat=grid.dim):
+        ec = [nc[:, a] + off[a] for a in range(grid.dim)]
+        ok = np.ones(len(rows), dtype=bool)
+        for a in range(grid.dim):
+            ok &= (ec[a] >= 0) & (ec[a] < dims[a])
+        e = grid.elem_id(ec[0], ec[1], ec[2] if grid.dim == 3 else 0)
+        e = np.where(ok, e, 0)
+        ci = sum(((-off[a]) << a) for a in range(grid.dim))   # corner of node i in cell e
+        acc = np.zeros(len(rows))
+        for c in range(grid.ncorner):
+            bx, by, bz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+            nid = grid.node_id(ec[0] + bx, ec[1] + by, (ec[2] + bz) if grid.dim == 3 else 0)
+            nid = np.where(ok, nid, 0)
+            acc += ke[ci, c] * x[nid]
+        out += np.where(ok, kelem[e] * acc, 0.0)
+    return out

@@ -1,0 +1,768 @@
+// Host orchestration of libmgar: handle, MG hierarchy, V-cycle, MGCG, MGAR
+// reanalysis, sensitivities and the OC update, behind the C ABI of mgar.h.
+//
+// Every numerical step runs in the kernels of stencil.hip, vec.hip and
+// topopt.hip on the handle's stream. The host only sequences launches and
+// reads back a few scalars (stopping flags, the Eq 28 residual, compliance).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "mgar.h"
+#include "mgar_launch.h"
+
+namespace {
+
+struct LevelBuf {
+  Geo g;
+  double* k = nullptr;   // element conductivities of the K0 hierarchy on this grid
+  double* b = nullptr;   // right-hand side (grids >= 1)
+  double* xa = nullptr;  // iterate before the post-smoother
+  double* xb = nullptr;  // iterate after the post-smoother (grids >= 1)
+};
+
+}  // namespace
+
+struct mgar_handle {
+  mgar_params p;
+  hipStream_t s = nullptr;
+  int L = 0;
+  std::vector<LevelBuf> lv;
+  long long N = 0, E = 0;
+  double* kcur = nullptr;                 // K(xphys) of the current call, finest grid
+  double* rtmp = nullptr;                 // residual scratch (finest size)
+  double* Ainv = nullptr;                 // coarsest-grid inverse
+  int* dstatus = nullptr;                 // device status word (coarsest pivots)
+  double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
+  double *pa = nullptr, *pb = nullptr, *pc = nullptr;  // partial-sum buffers
+  long long part_cap = 0;
+  double* scal = nullptr;                 // device scalars
+  CgState* st = nullptr;
+  MgarDev* md = nullptr;
+  OcDev* oc = nullptr;
+  double *R = nullptr, *Wm = nullptr;     // basis block and K times basis, N x m
+  double *invHs = nullptr, *wvol = nullptr, *gtmp = nullptr;
+  int* tap_off = nullptr;
+  double* tap_w = nullptr;
+  int ntap = 0;
+  bool has_k0 = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // kernel timing (instrumentation)
+  unsigned prof_mask = 0;
+  std::vector<hipEvent_t> prof_ev;        // pool, pairs
+  std::vector<double> prof_bytes;         // bytes of each recorded pair
+  std::vector<int> prof_tag;              // CG iteration of each pair (-1: not in a CG loop)
+  size_t prof_used = 0;
+  long long prof_launches = 0;
+  double prof_ms = 0.0, prof_total_bytes = 0.0;
+};
+
+namespace {
+
+#define HIPCK(x)                                  \
+  do {                                            \
+    hipError_t err_ = (x);                        \
+    if (err_ != hipSuccess) return MGAR_E_HIP;    \
+  } while (0)
+
+#define LAUNCHCK() HIPCK(hipGetLastError())
+
+Geo make_geo(const mgar_params& p, int l) {
+  Geo g;
+  std::memset(&g, 0, sizeof(g));
+  const int s = 1 << l;
+  g.dim = p.dim;
+  g.nx = p.nelx / s;
+  g.ny = p.nely / s;
+  g.nz = (p.dim == 3) ? p.nelz / s : 1;
+  g.nnx = g.nx + 1;
+  g.nny = g.ny + 1;
+  g.nnz = (p.dim == 3) ? g.nz + 1 : 1;
+  auto cdiv = [](int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); };
+  auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+  // coarse node I is fixed iff the finest node I*2^l lies in the box
+  g.f0x = cdiv(p.fix_lo[0], s); g.f1x = fdiv(p.fix_hi[0], s);
+  g.f0y = cdiv(p.fix_lo[1], s); g.f1y = fdiv(p.fix_hi[1], s);
+  if (p.dim == 3) { g.f0z = cdiv(p.fix_lo[2], s); g.f1z = fdiv(p.fix_hi[2], s); }
+  else { g.f0z = 0; g.f1z = 0; }
+  g.h = (double)s;
+  g.nn = (long long)g.nnx * g.nny * g.nnz;
+  g.ne = (long long)g.nx * g.ny * g.nz;
+  return g;
+}
+
+long long count_fixed(const Geo& g) {
+  auto span = [](int lo, int hi, int n) -> long long {
+    const int a = lo < 0 ? 0 : lo, b = hi > n - 1 ? n - 1 : hi;
+    return b >= a ? (long long)(b - a + 1) : 0;
+  };
+  return span(g.f0x, g.f1x, g.nnx) * span(g.f0y, g.f1y, g.nny) * span(g.f0z, g.f1z, g.nnz);
+}
+
+template <typename T>
+int dalloc(T** p, long long n) {
+  if (n <= 0) n = 1;
+  HIPCK(hipMalloc((void**)p, sizeof(T) * (size_t)n));
+  return MGAR_OK;
+}
+
+#define ACK(x)                      \
+  do {                              \
+    int rc_ = (x);                  \
+    if (rc_ != MGAR_OK) return rc_; \
+  } while (0)
+
+int validate(const mgar_params* p) {
+  if (!p) return MGAR_E_ARG;
+  if (p->dim != 2 && p->dim != 3) return MGAR_E_ARG;
+  if (p->nelx < 1 || p->nely < 1 || (p->dim == 3 && p->nelz < 1)) return MGAR_E_ARG;
+  if (p->levels < 1 || p->levels > 16) return MGAR_E_ARG;
+  if (p->n_basis < 1 || p->n_basis > MGAR_MAX_BASIS) return MGAR_E_ARG;
+  if (!(p->omega > 0.0) || !(p->filter_r > 0.0) || p->cg_max < 0) return MGAR_E_ARG;
+  if (!(p->k0 > 0.0) || !(p->kmin > 0.0) || !(p->penal >= 1.0)) return MGAR_E_ARG;
+  if (p->precision != MGAR_PREC_FP64) return MGAR_E_PRECISION;
+  if ((int)std::ceil(p->filter_r) > 6) return MGAR_E_ARG;
+  const int s = 1 << (p->levels - 1);
+  if (p->nelx % s || p->nely % s || (p->dim == 3 && p->nelz % s)) return MGAR_E_DIMS;
+  return MGAR_OK;
+}
+
+// ------------------------------------------------------------------ MG
+
+int build_hierarchy(mgar_handle* h) {
+  for (int l = 1; l < h->L; ++l) launch_coarsen(h->lv[l - 1].g, h->lv[l].g, h->lv[l - 1].k, h->lv[l].k, h->s);
+  HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->s));
+  launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// Algorithmic bytes of one stencil launch (each operand read once, result written once).
+double stencil_bytes(const Geo& g, int mode) {
+  const double N = (double)g.nn, E = (double)g.ne;
+  switch (mode) {
+    case SM_APPLY: case SM_APPLY_DOT: return 8.0 * (2 * N + E);
+    case SM_RESID: case SM_JACOBI: case SM_JACOBI_DOT: return 8.0 * (3 * N + E);
+    case SM_JACOBI0: return 8.0 * (2 * N + E);
+    case SM_NEG_DK: return 8.0 * (2 * N + 2 * E);
+  }
+  return 0.0;
+}
+
+// Stencil launch on grid `level`; finest-grid launches selected by the
+// profiling mask are bracketed by HIP events on the same stream.
+int stencil_at(mgar_handle* h, int level, int mode, const double* x, const double* k,
+               const double* kref, const double* b, double* out, double omega, double* part,
+               const int* done, int* nparts = nullptr, int tag = -1) {
+  const Geo& g = h->lv[level].g;
+  const bool timed = level == 0 && (h->prof_mask >> mode) & 1u;
+  if (timed) {
+    if (h->prof_used + 2 > h->prof_ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIPCK(hipEventCreate(&e));
+        h->prof_ev.push_back(e);
+      }
+    }
+    HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
+  }
+  const int np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s);
+  if (nparts) *nparts = np;
+  if (timed) {
+    HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
+    h->prof_bytes.push_back(stencil_bytes(g, mode));
+    h->prof_tag.push_back(tag);
+    h->prof_used += 2;
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// Accumulate the recorded event pairs (the stream must be idle). Pairs tagged
+// with a CG iteration at or beyond `cutoff` belong to iterations that were
+// enqueued after the stopping test fired; their kernels returned at once, so
+// they are dropped.
+int profile_harvest(mgar_handle* h, int cutoff = 1 << 30) {
+  if (h->prof_used == 0) return MGAR_OK;
+  HIPCK(hipEventSynchronize(h->prof_ev[h->prof_used - 1]));
+  for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+    if (h->prof_tag[i / 2] >= cutoff) continue;
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, h->prof_ev[i], h->prof_ev[i + 1]));
+    h->prof_ms += ms;
+    h->prof_total_bytes += h->prof_bytes[i / 2];
+    h->prof_launches += 1;
+  }
+  h->prof_used = 0;
+  h->prof_bytes.clear();
+  h->prof_tag.clear();
+  return MGAR_OK;
+}
+
+// One V-cycle (Table 1) on the K0 hierarchy: out = MG(K0, b0, x0). With
+// dot_part set, the finest post-smoother also writes partials of b0 . out.
+int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, double* dot_part,
+           const int* done, int tag = -1) {
+  const int L = h->L;
+  const double w = h->p.omega;
+  if (L == 1) {
+    launch_coarse_solve(h->lv[0].g, h->Ainv, b0, out, done, h->s);
+    if (dot_part) launch_dot(b0, out, h->N, dot_part, done, h->s);
+    LAUNCHCK();
+    return MGAR_OK;
+  }
+  for (int l = 0; l < L - 1; ++l) {
+    LevelBuf& v = h->lv[l];
+    const double* b = (l == 0) ? b0 : v.b;
+    if (l == 0 && x0) ACK(stencil_at(h, l, SM_JACOBI, x0, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
+    else ACK(stencil_at(h, l, SM_JACOBI0, nullptr, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
+    ACK(stencil_at(h, l, SM_RESID, v.xa, v.k, nullptr, b, h->rtmp, w, nullptr, done, nullptr, tag));
+    launch_restrict(v.g, h->lv[l + 1].g, h->rtmp, h->lv[l + 1].b, done, h->s);
+  }
+  launch_coarse_solve(h->lv[L - 1].g, h->Ainv, h->lv[L - 1].b, h->lv[L - 1].xa, done, h->s);
+  const double* xfin = h->lv[L - 1].xa;
+  for (int l = L - 2; l >= 0; --l) {
+    LevelBuf& v = h->lv[l];
+    const double* b = (l == 0) ? b0 : v.b;
+    launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
+    double* o = (l == 0) ? out : v.xb;
+    ACK(stencil_at(h, l, (l == 0 && dot_part) ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w,
+                   dot_part, done, nullptr, tag));
+    xfin = o;
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// PCG with one V-cycle as preconditioner on K(kfine); x (h->cx) holds the
+// initial guess on entry and the solution on exit; h->qm the masked load.
+int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, double* relres) {
+  const Geo& g = h->lv[0].g;
+  const long long N = h->N;
+  ACK(stencil_at(h, 0, SM_RESID, h->cx, kfine, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
+  const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
+  const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+  launch_cg_init(h->st, h->pb, nq, h->pa, nr, h->s);
+  LAUNCHCK();
+  const int* done = &h->st->done;
+  int it = 0;
+  int chunk = 3;
+  double rr_prev = -1.0;
+  int it_prev = 0;
+  CgState hs;
+  launch_cg_check(h->st, h->pa, nr, 0, tol, h->p.cg_max, h->s);
+  for (;;) {
+    // Enqueue up to `chunk` iterations; once the stopping test fires on the
+    // device every later kernel returns immediately, so the iterates are those
+    // of a loop that tests before every iteration.
+    for (int c = 0; c < chunk && it < h->p.cg_max; ++c, ++it) {
+      ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, it));
+      const int nz = (h->L == 1) ? vec_num_blocks(N) : stencil_num_partials(g);
+      launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
+      launch_p_update(h->cz, h->cp, N, h->st, it, h->s);
+      int nw = 0;
+      ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, kfine, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, it));
+      launch_finalize(h->pc, nw, &h->st->pw, done, h->s);
+      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, it, h->pa, h->s);
+      launch_cg_check(h->st, h->pa, nr, it + 1, tol, h->p.cg_max, h->s);
+      LAUNCHCK();
+    }
+    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+    if (hs.done) break;
+    // predict the remaining iterations from the observed contraction rate
+    const double rr = hs.rr;
+    int next = 4;
+    if (rr_prev > 0.0 && rr > 0.0 && it > it_prev) {
+      const double rate = std::pow(rr / rr_prev, 0.5 / (double)(it - it_prev));
+      const double goal = tol * std::sqrt(hs.qq) / std::sqrt(rr);
+      if (rate > 0.0 && rate < 0.999 && goal < 1.0) next = (int)std::ceil(std::log(goal) / std::log(rate));
+    }
+    if (next < 1) next = 1;
+    if (next > 16) next = 16;
+    rr_prev = rr;
+    it_prev = it;
+    chunk = next;
+  }
+  ACK(profile_harvest(h, hs.iters));
+  *iters = hs.iters;
+  *conv = hs.converged;
+  *relres = (hs.qq > 0.0) ? std::sqrt(hs.rr / hs.qq) : 0.0;
+  return MGAR_OK;
+}
+
+int check_coarse(mgar_handle* h) {
+  int st = 0;
+  HIPCK(hipMemcpyAsync(&st, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  return st ? MGAR_E_NOT_SPD : MGAR_OK;
+}
+
+void stats_init(mgar_stats* st) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->res_ca = std::nan("");
+  st->res_final = std::nan("");
+}
+
+int finish_timing(mgar_handle* h, mgar_stats* st) {
+  HIPCK(hipEventRecord(h->e1, h->s));
+  HIPCK(hipEventSynchronize(h->e1));
+  if (st) {
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, h->e0, h->e1));
+    st->ms = ms;
+  }
+  return MGAR_OK;
+}
+
+// Gram-Schmidt (classical, applied twice) over the m basis columns in h->R.
+int orthonormalise(mgar_handle* h) {
+  const int m = h->p.n_basis;
+  const long long N = h->N;
+  for (int j = 0; j < m; ++j) {
+    double* v = h->R + (long long)j * N;
+    int np = launch_dot(v, v, N, h->pa, nullptr, h->s);
+    launch_finalize(h->pa, np, &h->md->n0[j], nullptr, h->s);
+    if (j > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
+        launch_finalize_multi(h->pa, np, j, h->md->c, h->s);
+        launch_gs_update(v, h->R, j, N, h->md->c, N, h->s);
+      }
+    }
+    np = launch_dot(v, v, N, h->pa, nullptr, h->s);
+    launch_finalize(h->pa, np, &h->scal[0], nullptr, h->s);
+    launch_gs_normalize(v, N, h->md, j, &h->scal[0], h->s);
+    LAUNCHCK();
+  }
+  return MGAR_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void mgar_default_params(mgar_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 2;
+  p->levels = 1;
+  p->fix_lo[0] = p->fix_lo[1] = p->fix_lo[2] = 0;
+  p->fix_hi[0] = p->fix_hi[1] = p->fix_hi[2] = -1;
+  p->k0 = 1.0;
+  p->kmin = 1e-3;
+  p->penal = 3.0;
+  p->omega = 0.8;
+  p->n_basis = 2;
+  p->eps_accept = 1e-8;
+  p->cg_max = 200;
+  p->basis_x0_zero = 0;
+  p->precision = MGAR_PREC_FP64;
+  p->filter_r = 1.5;
+}
+
+const char* mgar_strerror(int code) {
+  switch (code) {
+    case MGAR_OK: return "ok";
+    case MGAR_W_NOT_CONVERGED: return "warning: cg_max reached before the tolerance";
+    case MGAR_E_ARG: return "bad argument or null pointer";
+    case MGAR_E_DIMS: return "elements per axis not a multiple of 2^(levels-1), or coarsest grid above 1024 nodes";
+    case MGAR_E_SINGULAR: return "coarsest grid has no Dirichlet node";
+    case MGAR_E_HIP: return "HIP runtime error";
+    case MGAR_E_NOT_SPD: return "non-positive pivot in the reduced or coarsest system";
+    case MGAR_E_PRECISION: return "unsupported precision mode";
+    case MGAR_E_STATE: return "reanalysis needs a factorised K0: run mgcg_solve first";
+    default: return "unknown error";
+  }
+}
+
+void mgar_destroy(mgar_handle* h) {
+  if (!h) return;
+  for (auto& v : h->lv) {
+    if (v.k) (void)hipFree(v.k);
+    if (v.b) (void)hipFree(v.b);
+    if (v.xa) (void)hipFree(v.xa);
+    if (v.xb) (void)hipFree(v.xb);
+  }
+  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp,
+                  h->cw, h->pa, h->pb, h->pc, h->scal, h->st, h->md, h->oc, h->R, h->Wm,
+                  h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  if (h->e0) (void)hipEventDestroy(h->e0);
+  if (h->e1) (void)hipEventDestroy(h->e1);
+  delete h;
+}
+
+static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
+  ACK(validate(p));
+  mgar_handle* h = new mgar_handle();
+  *out = h;
+  h->p = *p;
+  if (p->dim == 2) { h->p.nelz = 0; h->p.fix_lo[2] = 0; h->p.fix_hi[2] = 0; }
+  h->s = (hipStream_t)stream;
+  h->L = p->levels;
+  h->lv.resize(h->L);
+  for (int l = 0; l < h->L; ++l) h->lv[l].g = make_geo(h->p, l);
+  const Geo& g0 = h->lv[0].g;
+  const Geo& gc = h->lv[h->L - 1].g;
+  if (gc.nn > 1024) return MGAR_E_DIMS;
+  if (count_fixed(gc) == 0) return MGAR_E_SINGULAR;
+  h->N = g0.nn;
+  h->E = g0.ne;
+  for (int l = 0; l < h->L; ++l) {
+    LevelBuf& v = h->lv[l];
+    ACK(dalloc(&v.k, v.g.ne));
+    ACK(dalloc(&v.xa, v.g.nn));
+    if (l > 0) {
+      ACK(dalloc(&v.b, v.g.nn));
+      ACK(dalloc(&v.xb, v.g.nn));
+    }
+  }
+  const long long N = h->N, E = h->E;
+  ACK(dalloc(&h->kcur, E));
+  ACK(dalloc(&h->rtmp, N));
+  ACK(dalloc(&h->Ainv, gc.nn * gc.nn));
+  ACK(dalloc(&h->dstatus, 4));
+  ACK(dalloc(&h->qm, N));
+  ACK(dalloc(&h->cx, N));
+  ACK(dalloc(&h->cr, N));
+  ACK(dalloc(&h->cz, N));
+  ACK(dalloc(&h->cp, N));
+  ACK(dalloc(&h->cw, N));
+  long long cap = stencil_num_partials(g0);
+  cap = cap > 1024LL * 64 ? cap : 1024LL * 64;   // multi-value partials (Gram, OC)
+  h->part_cap = cap;
+  ACK(dalloc(&h->pa, cap));
+  ACK(dalloc(&h->pb, cap));
+  ACK(dalloc(&h->pc, cap));
+  ACK(dalloc(&h->scal, 16));
+  ACK(dalloc(&h->st, 1));
+  ACK(dalloc(&h->md, 1));
+  ACK(dalloc(&h->oc, 1));
+  ACK(dalloc(&h->R, N * p->n_basis));
+  ACK(dalloc(&h->Wm, N * p->n_basis));
+  ACK(dalloc(&h->invHs, E));
+  ACK(dalloc(&h->wvol, E));
+  ACK(dalloc(&h->gtmp, E));
+  HIPCK(hipEventCreate(&h->e0));
+  HIPCK(hipEventCreate(&h->e1));
+  // cone filter taps (Eq 7-8): offsets within the radius, weight r - distance
+  {
+    const int Rw = (int)std::ceil(p->filter_r);
+    std::vector<int> off;
+    std::vector<double> w;
+    const int rz = (p->dim == 3) ? Rw : 0;
+    for (int dz = -rz; dz <= rz; ++dz)
+      for (int dy = -Rw; dy <= Rw; ++dy)
+        for (int dx = -Rw; dx <= Rw; ++dx) {
+          const double d = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+          const double wt = p->filter_r - d;
+          if (wt > 0.0) {
+            off.push_back(dx); off.push_back(dy); off.push_back(dz);
+            w.push_back(wt);
+          }
+        }
+    h->ntap = (int)w.size();
+    ACK(dalloc(&h->tap_off, (long long)off.size()));
+    ACK(dalloc(&h->tap_w, (long long)w.size()));
+    HIPCK(hipMemcpy(h->tap_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(h->tap_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice));
+  }
+  launch_filter_hs(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, h->s);
+  // w = H^T (1/Hs): the filtered-volume weights, which are also dv
+  launch_filter_fwd(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, nullptr, h->wvol, h->s);
+  LAUNCHCK();
+  HIPCK(hipStreamSynchronize(h->s));
+  return MGAR_OK;
+}
+
+int mgar_setup(const mgar_params* p, void* stream, mgar_handle** out) {
+  if (!out) return MGAR_E_ARG;
+  *out = nullptr;
+  mgar_handle* h = nullptr;
+  const int rc = setup_impl(p, stream, &h);
+  if (rc != MGAR_OK) {
+    mgar_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return MGAR_OK;
+}
+
+int mgar_set_stream(mgar_handle* h, void* stream) {
+  if (!h) return MGAR_E_ARG;
+  h->s = (hipStream_t)stream;
+  return MGAR_OK;
+}
+
+int mgar_sizes(const mgar_handle* h, int level, long long* nnodes, long long* nelem) {
+  if (!h || level < 0 || level >= h->L) return MGAR_E_ARG;
+  if (nnodes) *nnodes = h->lv[level].g.nn;
+  if (nelem) *nelem = h->lv[level].g.ne;
+  return MGAR_OK;
+}
+
+int mgar_load_vector(mgar_handle* h, const double* Qe, double* q) {
+  if (!h || !Qe || !q) return MGAR_E_ARG;
+  launch_load(h->lv[0].g, Qe, q, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_density_filter(mgar_handle* h, const double* x, double* xphys) {
+  if (!h || !x || !xphys) return MGAR_E_ARG;
+  launch_filter_fwd(h->lv[0].g, h->tap_off, h->tap_w, h->ntap, x, h->invHs, xphys, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgcg_solve(mgar_handle* h, const double* xphys, const double* q, const double* T0,
+               double tol, double* T, mgar_stats* stats) {
+  if (!h || !xphys || !q || !T) return MGAR_E_ARG;
+  stats_init(stats);
+  HIPCK(hipEventRecord(h->e0, h->s));
+  const Geo& g = h->lv[0].g;
+  launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  launch_copy(h->kcur, h->lv[0].k, h->E, h->s);
+  ACK(build_hierarchy(h));
+  launch_mask_copy(g, q, h->qm, h->s);
+  if (T0) launch_mask_copy(g, T0, h->cx, h->s);
+  else HIPCK(hipMemsetAsync(h->cx, 0, sizeof(double) * h->N, h->s));
+  int iters = 0, conv = 0;
+  double rel = 0.0;
+  ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+  launch_copy(h->cx, T, h->N, h->s);
+  LAUNCHCK();
+  ACK(check_coarse(h));
+  h->has_k0 = true;
+  ACK(finish_timing(h, stats));
+  if (stats) {
+    stats->path = MGAR_PATH_MGCG;
+    stats->cg_iters = iters;
+    stats->vcycles = iters;
+    stats->res_final = rel;
+  }
+  return conv ? MGAR_OK : MGAR_W_NOT_CONVERGED;
+}
+
+int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const double* T0,
+               double tol, double* T, mgar_stats* stats) {
+  if (!h || !xphys || !q || !T) return MGAR_E_ARG;
+  if (!h->has_k0) return MGAR_E_STATE;
+  stats_init(stats);
+  HIPCK(hipEventRecord(h->e0, h->s));
+  const Geo& g = h->lv[0].g;
+  const long long N = h->N;
+  const int m = h->p.n_basis;
+  launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  launch_mask_copy(g, q, h->qm, h->s);
+  // r_1 = t_prev
+  if (T0) launch_mask_copy(g, T0, h->R, h->s);
+  else HIPCK(hipMemsetAsync(h->R, 0, sizeof(double) * N, h->s));
+  // r_i = MG(K0, -dK r_{i-1}, x0, P)   (Eq 17)
+  for (int i = 1; i < m; ++i) {
+    const double* prev = h->R + (long long)(i - 1) * N;
+    ACK(stencil_at(h, 0, SM_NEG_DK, prev, h->kcur, h->lv[0].k, nullptr, h->cz, 0.0, nullptr, nullptr));
+    ACK(vcycle(h, h->cz, h->p.basis_x0_zero ? nullptr : prev, h->R + (long long)i * N, nullptr, nullptr));
+  }
+  // Eq 18 (as Gram-Schmidt), Eq 19-21
+  ACK(orthonormalise(h));
+  for (int j = 0; j < m; ++j)
+    ACK(stencil_at(h, 0, SM_APPLY, h->R + (long long)j * N, h->kcur, nullptr, nullptr,
+                   h->Wm + (long long)j * N, 0.0, nullptr, nullptr));
+  int np = launch_gram(h->R, h->Wm, h->qm, m, N, N, h->pa, h->s);
+  launch_gram_finalize(h->pa, np, m, h->md, h->s);
+  np = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s);
+  launch_finalize(h->pa, np, &h->md->res2, nullptr, h->s);
+  np = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+  launch_finalize(h->pb, np, &h->md->qq, nullptr, h->s);
+  LAUNCHCK();
+  MgarDev hm;
+  HIPCK(hipMemcpyAsync(&hm, h->md, sizeof(MgarDev), hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  const double res = (hm.qq > 0.0) ? std::sqrt(hm.res2 / hm.qq) : 0.0;
+  if (stats) {
+    stats->res_ca = res;
+    stats->vcycles = m - 1;
+  }
+  if (hm.spd_fail) return MGAR_E_NOT_SPD;
+  int rc = MGAR_OK;
+  if (res <= h->p.eps_accept) {
+    launch_copy(h->cx, T, N, h->s);
+    LAUNCHCK();
+    if (stats) {
+      stats->path = MGAR_PATH_ACCEPT;
+      stats->res_final = res;
+    }
+  } else {
+    // reconstruction: K becomes the new K0, MGCG from the reduced solution
+    launch_copy(h->kcur, h->lv[0].k, h->E, h->s);
+    ACK(build_hierarchy(h));
+    int iters = 0, conv = 0;
+    double rel = 0.0;
+    ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+    launch_copy(h->cx, T, N, h->s);
+    LAUNCHCK();
+    ACK(check_coarse(h));
+    if (stats) {
+      stats->path = MGAR_PATH_FALLBACK;
+      stats->cg_iters = iters;
+      stats->vcycles += iters;
+      stats->res_final = rel;
+    }
+    rc = conv ? MGAR_OK : MGAR_W_NOT_CONVERGED;
+  }
+  ACK(finish_timing(h, stats));
+  return rc;
+}
+
+int sens_filter(mgar_handle* h, const double* xphys, const double* T, const double* q, double* dc,
+                double* dv, double* compliance) {
+  if (!h || !xphys || !T || !q || !dc || !dv) return MGAR_E_ARG;
+  const Geo& g = h->lv[0].g;
+  launch_sens_elem(g, xphys, T, h->invHs, h->p.k0, h->p.kmin, h->p.penal, h->gtmp, h->s);
+  launch_filter_fwd(g, h->tap_off, h->tap_w, h->ntap, h->gtmp, nullptr, dc, h->s);
+  launch_copy(h->wvol, dv, h->E, h->s);
+  LAUNCHCK();
+  if (compliance) {
+    launch_mask_copy(g, q, h->qm, h->s);
+    const int np = launch_dot(h->qm, T, h->N, h->pa, nullptr, h->s);
+    launch_finalize(h->pa, np, &h->scal[1], nullptr, h->s);
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(compliance, &h->scal[1], sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+  }
+  return MGAR_OK;
+}
+
+int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv, double volfrac,
+              double move, double* x_new, double* lambda) {
+  if (!h || !x || !dc || !dv || !x_new) return MGAR_E_ARG;
+  const double target = volfrac * (double)h->E;
+  launch_oc_init(h->oc, h->s);
+  OcDev ho;
+  int passes = 0;
+  for (;;) {
+    const int chunk = passes == 0 ? 12 : 2;
+    for (int c = 0; c < chunk; ++c) {
+      const int np = launch_oc_pass(x, dc, dv, h->E, move, h->oc, h->pa, h->s);
+      launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);
+    }
+    passes += chunk;
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(&ho, h->oc, sizeof(OcDev), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+    if (ho.done || passes > 64) break;
+  }
+  launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
+  LAUNCHCK();
+  if (lambda) *lambda = 0.5 * (ho.l1 + ho.l2);
+  return MGAR_OK;
+}
+
+int mgar_reset(mgar_handle* h) {
+  if (!h) return MGAR_E_ARG;
+  h->has_k0 = false;
+  return MGAR_OK;
+}
+
+int mgar_op_apply(mgar_handle* h, int level, const double* k, const double* x, double* y) {
+  if (!h || !k || !x || !y || level < 0 || level >= h->L) return MGAR_E_ARG;
+  const Geo& g = h->lv[level].g;
+  launch_mask_copy(g, x, h->rtmp, h->s);
+  launch_stencil(g, SM_APPLY, h->rtmp, k, nullptr, nullptr, y, 0.0, nullptr, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_op_jacobi(mgar_handle* h, int level, const double* k, const double* b, const double* x,
+                   double* out) {
+  if (!h || !k || !b || !x || !out || level < 0 || level >= h->L) return MGAR_E_ARG;
+  const Geo& g = h->lv[level].g;
+  launch_mask_copy(g, x, h->rtmp, h->s);
+  launch_mask_copy(g, b, h->cz, h->s);
+  launch_stencil(g, SM_JACOBI, h->rtmp, k, nullptr, h->cz, out, h->p.omega, nullptr, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_op_restrict(mgar_handle* h, int level, const double* rf, double* rc) {
+  if (!h || !rf || !rc || level < 0 || level + 1 >= h->L) return MGAR_E_ARG;
+  launch_mask_copy(h->lv[level].g, rf, h->rtmp, h->s);
+  launch_restrict(h->lv[level].g, h->lv[level + 1].g, h->rtmp, rc, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_op_prolong(mgar_handle* h, int level, const double* xc, double* xf) {
+  if (!h || !xc || !xf || level < 0 || level + 1 >= h->L) return MGAR_E_ARG;
+  launch_mask_copy(h->lv[level + 1].g, xc, h->rtmp, h->s);
+  launch_mask_copy(h->lv[level].g, xf, xf, h->s);
+  launch_prolong(h->lv[level].g, h->lv[level + 1].g, h->rtmp, xf, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_op_coarsen(mgar_handle* h, int level, const double* kf, double* kc) {
+  if (!h || !kf || !kc || level < 0 || level + 1 >= h->L) return MGAR_E_ARG;
+  launch_coarsen(h->lv[level].g, h->lv[level + 1].g, kf, kc, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_build_hierarchy(mgar_handle* h, const double* xphys) {
+  if (!h || !xphys) return MGAR_E_ARG;
+  launch_simp(xphys, h->lv[0].k, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  ACK(build_hierarchy(h));
+  ACK(check_coarse(h));
+  h->has_k0 = true;
+  return MGAR_OK;
+}
+
+int mgar_vcycle(mgar_handle* h, const double* b, const double* x0, double* x) {
+  if (!h || !b || !x) return MGAR_E_ARG;
+  if (!h->has_k0) return MGAR_E_STATE;
+  const Geo& g = h->lv[0].g;
+  launch_mask_copy(g, b, h->cz, h->s);
+  if (x0) launch_mask_copy(g, x0, h->cr, h->s);
+  ACK(vcycle(h, h->cz, x0 ? h->cr : nullptr, x, nullptr, nullptr));
+  return MGAR_OK;
+}
+
+int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b) {
+  if (!h || !xphys || !r || !b) return MGAR_E_ARG;
+  if (!h->has_k0) return MGAR_E_STATE;
+  const Geo& g = h->lv[0].g;
+  launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  launch_mask_copy(g, r, h->rtmp, h->s);
+  launch_stencil(g, SM_NEG_DK, h->rtmp, h->kcur, h->lv[0].k, nullptr, b, 0.0, nullptr, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_profile(mgar_handle* h, unsigned mode_mask) {
+  if (!h) return MGAR_E_ARG;
+  h->prof_mask = mode_mask;
+  return MGAR_OK;
+}
+
+int mgar_profile_read(mgar_handle* h, long long* launches, double* total_ms, double* total_bytes) {
+  if (!h) return MGAR_E_ARG;
+  HIPCK(hipStreamSynchronize(h->s));
+  ACK(profile_harvest(h));
+  if (launches) *launches = h->prof_launches;
+  if (total_ms) *total_ms = h->prof_ms;
+  if (total_bytes) *total_bytes = h->prof_total_bytes;
+  h->prof_launches = 0;
+  h->prof_ms = 0.0;
+  h->prof_total_bytes = 0.0;
+  return MGAR_OK;
+}
+
+}  // extern "C"

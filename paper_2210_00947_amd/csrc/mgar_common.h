@@ -1,0 +1,100 @@
+// Internal definitions shared by the libmgar translation units: grid geometry
+// of one MG level, device-side solver state, and wave64 reduction helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#define MGAR_WAVE 64
+#define MGAR_MAXB 8
+
+// Geometry of one grid level. In 2D nz = nnz = 1 so that E = nx*ny and
+// N = nnx*nny under the same indexing formulas as 3D.
+struct Geo {
+  int dim;
+  int nx, ny, nz;            // elements per axis
+  int nnx, nny, nnz;         // nodes per axis
+  int f0x, f1x, f0y, f1y, f0z, f1z;  // Dirichlet node box, inclusive (empty if f0 > f1)
+  double h;                  // cell edge of this level (2^l)
+  long long nn, ne;          // node and element counts
+};
+
+__host__ __device__ inline bool geo_fixed(const Geo& g, int i, int j, int k) {
+  return i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y && k >= g.f0z && k <= g.f1z;
+}
+
+__host__ __device__ inline long long geo_node(const Geo& g, int i, int j, int k) {
+  return (long long)i + (long long)g.nnx * ((long long)j + (long long)g.nny * k);
+}
+
+__host__ __device__ inline long long geo_elem(const Geo& g, int ex, int ey, int ez) {
+  return (long long)ex + (long long)g.nx * ((long long)ey + (long long)g.ny * ez);
+}
+
+// PCG state in device memory. Every field has a single writer per kernel.
+struct CgState {
+  double qq;                 // ||q||^2 over free nodes
+  double rr;                 // latest ||r||^2
+  double rz[2];              // r.z by iteration parity
+  double pw;                 // p.(K p)
+  int done;                  // set once the stopping test fires
+  int iters;                 // iterations performed at exit
+  int converged;             // 1 = tolerance met, 0 = cg_max reached
+  int pad;
+};
+
+// Reanalysis (reduced-basis) state in device memory.
+struct MgarDev {
+  double n0[MGAR_MAXB];      // column norm before projection
+  double c[MGAR_MAXB];       // projection coefficients
+  int active[MGAR_MAXB];     // 1 = column kept
+  double KR[MGAR_MAXB * MGAR_MAXB];
+  double qR[MGAR_MAXB];
+  double y[MGAR_MAXB];
+  double res2;               // ||K Q y - q||^2
+  double qq;                 // ||q||^2
+  int spd_fail;
+  int pad;
+};
+
+// OC bisection state in device memory (speculative bisection tree).
+#define OC_DEPTH 5
+#define OC_NCAND ((1 << OC_DEPTH) - 1)
+struct OcDev {
+  double l1, l2;             // current bracket
+  double lam_last;           // last evaluated midpoint
+  double cand[OC_NCAND];     // midpoints of the next OC_DEPTH bisection levels (heap order)
+  int done;
+  int steps;
+  int pad[2];
+};
+
+// ---------------------------------------------------------------- reductions
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = MGAR_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, MGAR_WAVE);
+  return v;
+}
+
+// Deterministic block sum; result valid in every thread. `sh` needs
+// blockDim/64 doubles of LDS. Contains __syncthreads (call from all threads).
+__device__ inline double block_sum(double v, double* sh) {
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nw = (nt + MGAR_WAVE - 1) / MGAR_WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((t & (MGAR_WAVE - 1)) == 0) sh[t / MGAR_WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += sh[w];
+  return s;
+}
+
+__device__ inline int flat_tid() {
+  return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+
+__device__ inline int flat_bid() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}

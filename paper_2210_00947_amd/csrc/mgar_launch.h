@@ -1,0 +1,84 @@
+// Host-side launch wrappers of the libmgar kernels (one definition per .hip file).
+#pragma once
+#include "mgar_common.h"
+
+// Matrix-free stencil modes (y = K_l x with the rediscretised Q1 operator).
+enum StencilMode {
+  SM_APPLY = 0,      // out = K x
+  SM_APPLY_DOT = 1,  // out = K x;            partial += x . out
+  SM_RESID = 2,      // out = b - K x
+  SM_JACOBI = 3,     // out = x + w D^-1 (b - K x)
+  SM_JACOBI_DOT = 4, // as SM_JACOBI;         partial += b . out
+  SM_JACOBI0 = 5,    // out = w D^-1 b        (sweep from a zero guess; x unused)
+  SM_NEG_DK = 6,     // out = -(K(k) - K(kref)) x
+};
+
+// stencil.hip ----------------------------------------------------------------
+// Returns the number of block partials written to `part` (0 for modes without a dot).
+int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
+                   const double* b, double* out, double omega, double* part, const int* done,
+                   hipStream_t s);
+int stencil_num_partials(const Geo& g);
+void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
+                     hipStream_t s);
+void launch_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf, const int* done,
+                    hipStream_t s);
+void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, hipStream_t s);
+void launch_coarse_build(const Geo& g, const double* k, double* A, int* status, hipStream_t s);
+void launch_coarse_solve(const Geo& g, const double* A, const double* b, double* x,
+                         const int* done, hipStream_t s);
+void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s);
+
+// vec.hip --------------------------------------------------------------------
+int vec_num_blocks(long long n);
+// partial[b] = sum over block b of a.b ; returns number of partials
+int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
+               hipStream_t s);
+// out = sum(part[0..n)) in a fixed order (single block)
+void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s);
+void launch_cg_check(CgState* st, const double* part, int np, int it, double tol, int cg_max,
+                     hipStream_t s);
+void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
+                    hipStream_t s);
+void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
+                     hipStream_t s);
+int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
+                     const CgState* st, int it, double* part, hipStream_t s);
+void launch_copy(const double* a, double* b, long long n, hipStream_t s);
+void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s);
+// Gram-Schmidt / reduced system helpers
+int launch_multidot(const double* Q, int ncols, long long ld, const double* v, long long n,
+                    double* part, hipStream_t s);
+void launch_finalize_multi(const double* part, int np, int nv, double* out, hipStream_t s);
+void launch_gs_update(double* v, const double* Q, int ncols, long long ld, const double* c,
+                      long long n, hipStream_t s);
+void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const double* nrm2_after,
+                         hipStream_t s);
+int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,
+                long long n, double* part, hipStream_t s);
+void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s);
+int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s);
+
+// topopt.hip -----------------------------------------------------------------
+struct FilterTaps {
+  int ntap;
+  int off[3 * 2197];   // dx, dy, dz per tap (window up to 13^3)
+  double w[2197];
+};
+void launch_simp(const double* xphys, double* k, long long n, double k0, double kmin, double penal,
+                 hipStream_t s);
+void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s);
+void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, const double* x,
+                       const double* invHs, double* y, hipStream_t s);
+void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, double* invHs,
+                      hipStream_t s);
+void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const double* invHs,
+                      double k0, double kmin, double penal, double* gout, hipStream_t s);
+void launch_oc_init(OcDev* oc, hipStream_t s);
+int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
+                   const OcDev* oc, double* part, hipStream_t s);
+void launch_oc_walk(OcDev* oc, const double* part, int np, double target, double tol,
+                    hipStream_t s);
+void launch_oc_final(const double* x, const double* dc, const double* dv, long long n, double move,
+                     const OcDev* oc, double* xnew, hipStream_t s);

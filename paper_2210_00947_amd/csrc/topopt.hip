@@ -1,0 +1,287 @@
+// Element-level kernels of the optimisation loop: SIMP conductivity (Eq 4),
+// consistent load, cone density filter and its adjoint (Eq 6-9, 11), element
+// compliance sensitivity (Eq 10), and the optimality-criteria update.
+#include "mgar_launch.h"
+
+namespace {
+
+constexpr int TBX = 64, TBY = 4;
+constexpr int VB = 256;
+constexpr int VMAXB = 1024;
+constexpr int FB = 1024;
+
+dim3 elem_grid(const Geo& g) {
+  return dim3((g.nx + TBX - 1) / TBX, (g.ny + TBY - 1) / TBY, g.nz);
+}
+dim3 node_grid(const Geo& g) {
+  return dim3((g.nnx + TBX - 1) / TBX, (g.nny + TBY - 1) / TBY, g.nnz);
+}
+int nblocks(long long n) {
+  long long nb = (n + VB - 1) / VB;
+  return (int)(nb > VMAXB ? VMAXB : (nb < 1 ? 1 : nb));
+}
+
+__device__ inline double simp_pow(double x, double p) {
+  return (p == 3.0) ? x * x * x : pow(x, p);
+}
+
+__global__ __launch_bounds__(VB) void k_simp(const double* __restrict__ xp, double* __restrict__ k,
+                                             long long n, double k0, double kmin, double p) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    k[i] = kmin + (k0 - kmin) * simp_pow(xp[i], p);
+}
+
+// q_i = sum over cells e at node i of Qe_e |e| / 2^d; 0 on Dirichlet nodes.
+template <int DIM>
+__global__ __launch_bounds__(TBX* TBY) void k_load(Geo g, const double* __restrict__ Qe,
+                                                   double* __restrict__ q) {
+  const int i = blockIdx.x * TBX + threadIdx.x;
+  const int j = blockIdx.y * TBY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nnx || j >= g.nny) return;
+  double s = 0.0;
+  if (!geo_fixed(g, i, j, k)) {
+    for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          const int ex = i - 1 + a, ey = j - 1 + b, ez = (DIM == 3) ? k - 1 + c : 0;
+          if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+          s += Qe[geo_elem(g, ex, ey, ez)];
+        }
+    const double vol = (DIM == 3) ? g.h * g.h * g.h : g.h * g.h;
+    s *= vol / (DIM == 3 ? 8.0 : 4.0);
+  }
+  q[geo_node(g, i, j, k)] = s;
+}
+
+// y_e = (sum_j w_ej x_j) * scale_e over the in-grid taps (scale = 1 if null).
+// With scale = 1/Hs this is the forward filter; with g = dc~/Hs and no scale it
+// is the adjoint (the cone weight is symmetric in e and j).
+__global__ __launch_bounds__(TBX* TBY) void k_filter(Geo g, const int* __restrict__ off,
+                                                     const double* __restrict__ w, int ntap,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ scale,
+                                                     double* __restrict__ y) {
+  const int ex = blockIdx.x * TBX + threadIdx.x;
+  const int ey = blockIdx.y * TBY + threadIdx.y;
+  const int ez = blockIdx.z;
+  if (ex >= g.nx || ey >= g.ny) return;
+  double s = 0.0;
+  for (int t = 0; t < ntap; ++t) {
+    const int jx = ex + off[3 * t], jy = ey + off[3 * t + 1], jz = ez + off[3 * t + 2];
+    if (jx < 0 || jx >= g.nx || jy < 0 || jy >= g.ny || jz < 0 || jz >= g.nz) continue;
+    s += w[t] * x[geo_elem(g, jx, jy, jz)];
+  }
+  const long long e = geo_elem(g, ex, ey, ez);
+  y[e] = scale ? s * scale[e] : s;
+}
+
+__global__ __launch_bounds__(TBX* TBY) void k_filter_hs(Geo g, const int* __restrict__ off,
+                                                        const double* __restrict__ w, int ntap,
+                                                        double* __restrict__ invHs) {
+  const int ex = blockIdx.x * TBX + threadIdx.x;
+  const int ey = blockIdx.y * TBY + threadIdx.y;
+  const int ez = blockIdx.z;
+  if (ex >= g.nx || ey >= g.ny) return;
+  double s = 0.0;
+  for (int t = 0; t < ntap; ++t) {
+    const int jx = ex + off[3 * t], jy = ey + off[3 * t + 1], jz = ez + off[3 * t + 2];
+    if (jx < 0 || jx >= g.nx || jy < 0 || jy >= g.ny || jz < 0 || jz >= g.nz) continue;
+    s += w[t];
+  }
+  invHs[geo_elem(g, ex, ey, ez)] = 1.0 / s;
+}
+
+template <int DIM>
+__device__ inline double ke_unit(int ca, int cb) {
+  const int hd = __popc(ca ^ cb);
+  if (DIM == 2) return hd == 0 ? 2.0 / 3.0 : (hd == 1 ? -1.0 / 6.0 : -1.0 / 3.0);
+  return hd == 0 ? 1.0 / 3.0 : (hd == 1 ? 0.0 : -1.0 / 12.0);
+}
+
+// g_e = -p (k0 - kmin) xphys_e^(p-1) T_e^T KE T_e / Hs_e (Eq 10 divided by the
+// filter normalisation, ready for the adjoint gather of Eq 9/11).
+template <int DIM>
+__global__ __launch_bounds__(TBX* TBY) void k_sens(Geo g, const double* __restrict__ xphys,
+                                                   const double* __restrict__ T,
+                                                   const double* __restrict__ invHs, double k0,
+                                                   double kmin, double p, double* __restrict__ gout) {
+  const int ex = blockIdx.x * TBX + threadIdx.x;
+  const int ey = blockIdx.y * TBY + threadIdx.y;
+  const int ez = blockIdx.z;
+  if (ex >= g.nx || ey >= g.ny) return;
+  constexpr int NC = (DIM == 3) ? 8 : 4;
+  double t[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int ni = ex + (c & 1), nj = ey + ((c >> 1) & 1), nk = (DIM == 3) ? ez + ((c >> 2) & 1) : 0;
+    t[c] = geo_fixed(g, ni, nj, nk) ? 0.0 : T[geo_node(g, ni, nj, nk)];
+  }
+  double en = 0.0;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    double ya = 0.0;
+#pragma unroll
+    for (int b = 0; b < NC; ++b) ya += ke_unit<DIM>(a, b) * t[b];
+    en += t[a] * ya;
+  }
+  const long long e = geo_elem(g, ex, ey, ez);
+  const double xp = xphys[e];
+  const double dpow = (p == 3.0) ? xp * xp : pow(xp, p - 1.0);
+  gout[e] = -p * (k0 - kmin) * dpow * en * invHs[e];
+}
+
+// ------------------------------------------------------------------- OC
+// Speculative bisection: one pass evaluates the filtered volume at the
+// OC_NCAND midpoints of the next OC_DEPTH bisection levels; a single-thread walk
+// then replays the bisection decisions exactly in order.
+
+__device__ void oc_fill_candidates(OcDev* oc) {
+  double lo[OC_NCAND], hi[OC_NCAND];
+  lo[0] = oc->l1;
+  hi[0] = oc->l2;
+  for (int n = 0; n < OC_NCAND; ++n) {
+    const double m = 0.5 * (hi[n] + lo[n]);
+    oc->cand[n] = m;
+    if (2 * n + 2 < OC_NCAND) {
+      lo[2 * n + 1] = m; hi[2 * n + 1] = hi[n];   // volume too large: l1 = mid
+      lo[2 * n + 2] = lo[n]; hi[2 * n + 2] = m;   // otherwise: l2 = mid
+    }
+  }
+}
+
+__global__ void k_oc_init(OcDev* oc) {
+  oc->l1 = 0.0;
+  oc->l2 = 1e9;
+  oc->lam_last = 0.5e9;
+  oc->done = 0;
+  oc->steps = 0;
+  oc_fill_candidates(oc);
+}
+
+__global__ __launch_bounds__(VB) void k_oc_pass(const double* __restrict__ x,
+                                                const double* __restrict__ dc,
+                                                const double* __restrict__ dv, long long n,
+                                                double move, const OcDev* __restrict__ oc,
+                                                double* __restrict__ part) {
+  if (oc->done) return;
+  __shared__ double rs[OC_NCAND];
+  __shared__ double red[VB / MGAR_WAVE][OC_NCAND];
+  if (threadIdx.x < OC_NCAND) rs[threadIdx.x] = 1.0 / sqrt(oc->cand[threadIdx.x]);
+  __syncthreads();
+  double s[OC_NCAND];
+#pragma unroll
+  for (int t = 0; t < OC_NCAND; ++t) s[t] = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    const double xi = x[i], wi = dv[i];
+    const double B = fmax(0.0, -dc[i]) / wi;
+    const double c = xi * sqrt(B);
+    const double lo = fmax(0.0, xi - move), hi = fmin(1.0, xi + move);
+#pragma unroll
+    for (int t = 0; t < OC_NCAND; ++t) s[t] += wi * fmax(lo, fmin(hi, c * rs[t]));
+  }
+  const int lane = threadIdx.x & (MGAR_WAVE - 1), wv = threadIdx.x / MGAR_WAVE;
+#pragma unroll
+  for (int t = 0; t < OC_NCAND; ++t) {
+    const double v = wave_sum(s[t]);
+    if (lane == 0) red[wv][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < OC_NCAND) {
+    double v = 0.0;
+    for (int w = 0; w < VB / MGAR_WAVE; ++w) v += red[w][threadIdx.x];
+    part[blockIdx.x * OC_NCAND + threadIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(FB) void k_oc_walk(OcDev* oc, const double* __restrict__ part, int np,
+                                                double target, double tol) {
+  if (oc->done) return;
+  __shared__ double sh[FB / MGAR_WAVE];
+  __shared__ double S[OC_NCAND];
+  for (int t = 0; t < OC_NCAND; ++t) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < np; b += FB) v += part[b * OC_NCAND + t];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) S[t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double l1 = oc->l1, l2 = oc->l2;
+  int node = 0, done = 0, steps = oc->steps;
+  double last = oc->lam_last;
+  for (int lev = 0; lev < OC_DEPTH; ++lev) {
+    if (!((l2 - l1) / (l1 + l2) > tol)) { done = 1; break; }
+    const double lmid = oc->cand[node];
+    last = lmid;
+    ++steps;
+    if (S[node] > target) { l1 = lmid; node = 2 * node + 1; }
+    else { l2 = lmid; node = 2 * node + 2; }
+  }
+  if (!done && !((l2 - l1) / (l1 + l2) > tol)) done = 1;
+  oc->l1 = l1; oc->l2 = l2; oc->lam_last = last; oc->steps = steps; oc->done = done;
+  if (!done) oc_fill_candidates(oc);
+}
+
+__global__ __launch_bounds__(VB) void k_oc_final(const double* __restrict__ x,
+                                                 const double* __restrict__ dc,
+                                                 const double* __restrict__ dv, long long n,
+                                                 double move, const OcDev* __restrict__ oc,
+                                                 double* __restrict__ xnew) {
+  const double lam = oc->lam_last;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    const double xi = x[i];
+    const double B = fmax(0.0, -dc[i]) / dv[i];
+    const double v = xi * sqrt(B / lam);
+    xnew[i] = fmax(0.0, fmax(xi - move, fmin(1.0, fmin(xi + move, v))));
+  }
+}
+
+}  // namespace
+
+void launch_simp(const double* xphys, double* k, long long n, double k0, double kmin, double penal,
+                 hipStream_t s) {
+  k_simp<<<nblocks(n), VB, 0, s>>>(xphys, k, n, k0, kmin, penal);
+}
+
+void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s) {
+  if (g.dim == 2) k_load<2><<<node_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, Qe, q);
+  else k_load<3><<<node_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, Qe, q);
+}
+
+void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, const double* x,
+                       const double* invHs, double* y, hipStream_t s) {
+  k_filter<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);
+}
+
+void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, double* invHs,
+                      hipStream_t s) {
+  k_filter_hs<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, invHs);
+}
+
+void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const double* invHs,
+                      double k0, double kmin, double penal, double* gout, hipStream_t s) {
+  if (g.dim == 2)
+    k_sens<2><<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, xphys, T, invHs, k0, kmin, penal, gout);
+  else
+    k_sens<3><<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, xphys, T, invHs, k0, kmin, penal, gout);
+}
+
+void launch_oc_init(OcDev* oc, hipStream_t s) { k_oc_init<<<1, 1, 0, s>>>(oc); }
+
+int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
+                   const OcDev* oc, double* part, hipStream_t s) {
+  const int nb = nblocks(n);
+  k_oc_pass<<<nb, VB, 0, s>>>(x, dc, dv, n, move, oc, part);
+  return nb;
+}
+
+void launch_oc_walk(OcDev* oc, const double* part, int np, double target, double tol,
+                    hipStream_t s) {
+  k_oc_walk<<<1, FB, 0, s>>>(oc, part, np, target, tol);
+}
+
+void launch_oc_final(const double* x, const double* dc, const double* dv, long long n, double move,
+                     const OcDev* oc, double* xnew, hipStream_t s) {
+  k_oc_final<<<nblocks(n), VB, 0, s>>>(x, dc, dv, n, move, oc, xnew);
+}

@@ -1,0 +1,415 @@
+// Vector kernels: deterministic FP64 reductions, PCG updates, Gram-Schmidt and
+// the reduced (reanalysis) system.
+//
+// Reductions are two-stage and order-fixed: every block writes one partial per
+// value (wave64 shuffle tree, then LDS across waves), and a single-block
+// finalize sums the partials in index order. Reruns are bitwise identical.
+#include "mgar_launch.h"
+
+namespace {
+
+constexpr int VB = 256;          // threads per block for vector kernels
+constexpr int VMAXB = 1024;      // maximum blocks (so at most 1024 partials)
+constexpr int FB = 1024;         // finalize block size
+
+__global__ __launch_bounds__(VB) void k_dot(const double* __restrict__ a,
+                                            const double* __restrict__ b, long long n,
+                                            double* __restrict__ part,
+                                            const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[VB / MGAR_WAVE];
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    s += a[i] * b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  return block_sum(s, sh);
+}
+
+__global__ __launch_bounds__(FB) void k_finalize(const double* __restrict__ part, int n,
+                                                 double* __restrict__ out,
+                                                 const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double s = sum_partials(part, n, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// Stopping test before iteration `it` (||r|| <= tol ||q|| or it == cg_max).
+__global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __restrict__ part,
+                                                 int np, int it, double tol, int cg_max) {
+  if (st->done) return;
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double rr = sum_partials(part, np, sh);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    if (sqrt(rr) <= tol * sqrt(st->qq)) {
+      st->done = 1; st->converged = 1; st->iters = it;
+    } else if (it >= cg_max) {
+      st->done = 1; st->converged = 0; st->iters = it;
+    }
+  }
+}
+
+__global__ __launch_bounds__(FB) void k_cg_init(CgState* st, const double* __restrict__ pq, int nq,
+                                                const double* __restrict__ pr, int nr) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double qq = sum_partials(pq, nq, sh);
+  const double rr = sum_partials(pr, nr, sh);
+  if (threadIdx.x == 0) {
+    st->qq = qq; st->rr = rr; st->rz[0] = st->rz[1] = 0.0; st->pw = 0.0;
+    st->done = 0; st->iters = 0; st->converged = 0;
+  }
+}
+
+// p = z + beta p, beta = rz_k / rz_{k-1} (Fletcher-Reeves); p = z at k = 0.
+__global__ __launch_bounds__(VB) void k_p_update(const double* __restrict__ z, double* __restrict__ p,
+                                                 long long n, const CgState* __restrict__ st,
+                                                 int it) {
+  if (st->done) return;
+  const double beta = (it == 0) ? 0.0 : st->rz[it & 1] / st->rz[(it - 1) & 1];
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
+}
+
+// x += alpha p, r -= alpha w, partial ||r||^2, alpha = rz / (p . w).
+__global__ __launch_bounds__(VB) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ w, long long n,
+                                                  const CgState* __restrict__ st, int it,
+                                                  double* __restrict__ part) {
+  if (st->done) return;
+  __shared__ double sh[VB / MGAR_WAVE];
+  const double alpha = st->rz[it & 1] / st->pw;
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * w[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(VB) void k_copy(const double* __restrict__ a, double* __restrict__ b,
+                                             long long n) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    b[i] = a[i];
+}
+
+__global__ __launch_bounds__(VB) void k_scale_into(const double* __restrict__ a,
+                                                   double* __restrict__ b, double alpha,
+                                                   long long n) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    b[i] = alpha * a[i];
+}
+
+// part[b * NC + c] = block-b partial of Q[:, c] . v
+template <int NC>
+__global__ __launch_bounds__(VB) void k_multidot(const double* __restrict__ Q, long long ld,
+                                                 const double* __restrict__ v, long long n,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    const double vi = v[i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] += Q[c * ld + i] * vi;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double t = block_sum(s[c], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * NC + c] = t;
+  }
+}
+
+// out[v] = sum_b part[b * nv + v], v < nv (one block, fixed order).
+__global__ __launch_bounds__(FB) void k_finalize_multi(const double* __restrict__ part, int np,
+                                                       int nv, double* __restrict__ out) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < np; b += FB) s += part[b * nv + v];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[v] = s;
+  }
+}
+
+// v -= sum_c coef[c] Q[:, c]
+template <int NC>
+__global__ __launch_bounds__(VB) void k_gs_update(double* __restrict__ v, const double* __restrict__ Q,
+                                                  long long ld, const double* __restrict__ coef,
+                                                  long long n) {
+  double c[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) c[j] = coef[j];
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double s = v[i];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) s -= c[j] * Q[j * ld + i];
+    v[i] = s;
+  }
+}
+
+// Normalise column `col` (v) by its post-projection norm, or zero it when the
+// norm fell below 1e-10 of the pre-projection norm (or the column was zero).
+__global__ __launch_bounds__(VB) void k_gs_normalize(double* __restrict__ v, long long n,
+                                                     MgarDev* md, int col,
+                                                     const double* __restrict__ nrm2_after) {
+  const double n0 = sqrt(md->n0[col]);   // n0 holds the squared pre-projection norm
+  const double n1 = sqrt(*nrm2_after);
+  const bool keep = (n0 > 0.0) && (n1 >= 1e-10 * n0);
+  const double s = keep ? 1.0 / n1 : 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    v[i] = keep ? v[i] * s : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) md->active[col] = keep ? 1 : 0;
+}
+
+// Gram products of the reduced system: K_R[a][b] = Q_a . W_b (a <= b) and
+// q_R[a] = Q_a . q. Values per block: M(M+1)/2 + M, upper triangle row by row.
+template <int M>
+__global__ __launch_bounds__(VB) void k_gram(const double* __restrict__ Q, const double* __restrict__ W,
+                                             const double* __restrict__ q, long long ld, long long n,
+                                             double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  constexpr int NV = M * (M + 1) / 2 + M;
+  double s[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) s[c] = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double qa[M], wa[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      qa[a] = Q[a * ld + i];
+      wa[a] = W[a * ld + i];
+    }
+    const double qi = q[i];
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int b = a; b < M; ++b) s[idx++] += qa[a] * wa[b];
+#pragma unroll
+    for (int a = 0; a < M; ++a) s[idx + a] += qa[a] * qi;
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const double t = block_sum(s[c], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * NV + c] = t;
+  }
+}
+
+__global__ __launch_bounds__(FB) void k_gram_finalize(const double* __restrict__ part, int np, int m,
+                                                      MgarDev* md) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const int nv = m * (m + 1) / 2 + m;
+  int idx = 0;
+  for (int a = 0; a < m; ++a)
+    for (int b = a; b < m; ++b, ++idx) {
+      double s = 0.0;
+      for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + idx];
+      s = block_sum(s, sh);
+      if (threadIdx.x == 0) {
+        md->KR[a * MGAR_MAXB + b] = s;
+        md->KR[b * MGAR_MAXB + a] = s;
+      }
+    }
+  for (int a = 0; a < m; ++a) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + idx + a];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) md->qR[a] = s;
+  }
+}
+
+// Solve K_R y = q_R over the active columns by Cholesky (m <= 8, one thread).
+__device__ void reduced_solve(const MgarDev* md, int m, double* y, int* fail) {
+  double L[MGAR_MAXB][MGAR_MAXB];
+  double rhs[MGAR_MAXB];
+  int idx[MGAR_MAXB];
+  int na = 0;
+  for (int a = 0; a < m; ++a)
+    if (md->active[a]) idx[na++] = a;
+  for (int a = 0; a < m; ++a) y[a] = 0.0;
+  *fail = 0;
+  for (int a = 0; a < na; ++a) {
+    rhs[a] = md->qR[idx[a]];
+    for (int b = 0; b < na; ++b) L[a][b] = md->KR[idx[a] * MGAR_MAXB + idx[b]];
+  }
+  for (int j = 0; j < na; ++j) {
+    double d = L[j][j];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) { *fail = 1; return; }
+    d = sqrt(d);
+    L[j][j] = d;
+    for (int i = j + 1; i < na; ++i) {
+      double s = L[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      L[i][j] = s / d;
+    }
+  }
+  double z[MGAR_MAXB];
+  for (int i = 0; i < na; ++i) {
+    double s = rhs[i];
+    for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
+    z[i] = s / L[i][i];
+  }
+  for (int i = na - 1; i >= 0; --i) {
+    double s = z[i];
+    for (int k = i + 1; k < na; ++k) s -= L[k][i] * y[idx[k]];
+    y[idx[i]] = s / L[i][i];
+  }
+}
+
+// t = Q y, res = W y - q, partial ||res||^2 (y solved redundantly per block).
+template <int M>
+__global__ __launch_bounds__(VB) void k_combine(const double* __restrict__ Q,
+                                                const double* __restrict__ W,
+                                                const double* __restrict__ q, long long ld,
+                                                long long n, MgarDev* md, double* __restrict__ t,
+                                                double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  __shared__ double ys[MGAR_MAXB];
+  if (threadIdx.x == 0) {
+    double y[MGAR_MAXB];
+    int fail;
+    reduced_solve(md, M, y, &fail);
+    for (int a = 0; a < MGAR_MAXB; ++a) ys[a] = (a < M) ? y[a] : 0.0;
+    if (blockIdx.x == 0) {
+      for (int a = 0; a < M; ++a) md->y[a] = y[a];
+      md->spd_fail = fail;
+    }
+  }
+  __syncthreads();
+  double y[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) y[a] = ys[a];
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double ti = 0.0, wi = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      ti += y[a] * Q[a * ld + i];
+      wi += y[a] * W[a * ld + i];
+    }
+    t[i] = ti;
+    const double ri = wi - q[i];
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+#define MGAR_DISPATCH_M(m, CALL)                                    \
+  switch (m) {                                                      \
+    case 1: CALL(1); break; case 2: CALL(2); break;                 \
+    case 3: CALL(3); break; case 4: CALL(4); break;                 \
+    case 5: CALL(5); break; case 6: CALL(6); break;                 \
+    case 7: CALL(7); break; default: CALL(8); break;                \
+  }
+
+}  // namespace
+
+int vec_num_blocks(long long n) {
+  long long nb = (n + VB - 1) / VB;
+  if (nb > VMAXB) nb = VMAXB;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
+               hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+  k_dot<<<nb, VB, 0, s>>>(a, b, n, part, done);
+  return nb;
+}
+
+void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s) {
+  k_finalize<<<1, FB, 0, s>>>(part, n, out, done);
+}
+
+void launch_cg_check(CgState* st, const double* part, int np, int it, double tol, int cg_max,
+                     hipStream_t s) {
+  k_cg_check<<<1, FB, 0, s>>>(st, part, np, it, tol, cg_max);
+}
+
+void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
+                    hipStream_t s) {
+  k_cg_init<<<1, FB, 0, s>>>(st, part_qq, nq, part_rr, nr);
+}
+
+void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
+                     hipStream_t s) {
+  k_p_update<<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st, it);
+}
+
+int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
+                     const CgState* st, int it, double* part, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+  k_cg_update<<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part);
+  return nb;
+}
+
+void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
+  k_copy<<<vec_num_blocks(n), VB, 0, s>>>(a, b, n);
+}
+
+void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s) {
+  k_scale_into<<<vec_num_blocks(n), VB, 0, s>>>(a, b, alpha, n);
+}
+
+int launch_multidot(const double* Q, int ncols, long long ld, const double* v, long long n,
+                    double* part, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+#define CALL_MD(M) k_multidot<M><<<nb, VB, 0, s>>>(Q, ld, v, n, part)
+  MGAR_DISPATCH_M(ncols, CALL_MD)
+#undef CALL_MD
+  return nb;
+}
+
+void launch_finalize_multi(const double* part, int np, int nv, double* out, hipStream_t s) {
+  k_finalize_multi<<<1, FB, 0, s>>>(part, np, nv, out);
+}
+
+void launch_gs_update(double* v, const double* Q, int ncols, long long ld, const double* c,
+                      long long n, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+#define CALL_UP(M) k_gs_update<M><<<nb, VB, 0, s>>>(v, Q, ld, c, n)
+  MGAR_DISPATCH_M(ncols, CALL_UP)
+#undef CALL_UP
+}
+
+void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const double* nrm2_after,
+                         hipStream_t s) {
+  k_gs_normalize<<<vec_num_blocks(n), VB, 0, s>>>(v, n, md, col, nrm2_after);
+}
+
+int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,
+                long long n, double* part, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+#define CALL_G(M) k_gram<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, part)
+  MGAR_DISPATCH_M(m, CALL_G)
+#undef CALL_G
+  return nb;
+}
+
+void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s) {
+  k_gram_finalize<<<1, FB, 0, s>>>(part, np, m, md);
+}
+
+int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+#define CALL_C(M) k_combine<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, md, t, part)
+  MGAR_DISPATCH_M(m, CALL_C)
+#undef CALL_C
+  return nb;
+}

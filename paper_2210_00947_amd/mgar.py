@@ -1,0 +1,290 @@
+"""Thin ctypes binding of libmgar.so (include/mgar.h).
+
+Argument marshalling only: every numerical step runs in the HIP library. The
+functions keep the C names. Tensors are torch CUDA (HIP) tensors, FP64 and
+contiguous; work is enqueued on torch's current stream unless the handle was
+given another one. There is no fallback: if the library is missing, or a
+tensor is not on the GPU, a call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgar.so")
+
+MGAR_OK = 0
+MGAR_W_NOT_CONVERGED = 1
+MGAR_E_ARG = -1
+MGAR_E_DIMS = -2
+MGAR_E_SINGULAR = -3
+MGAR_E_HIP = -4
+MGAR_E_NOT_SPD = -5
+MGAR_E_PRECISION = -6
+MGAR_E_STATE = -7
+PATH_MGCG, PATH_ACCEPT, PATH_FALLBACK = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+EXPORTS = [
+    "mgar_default_params", "mgar_setup", "mgar_destroy", "mgar_set_stream", "mgar_strerror",
+    "mgar_sizes", "mgar_load_vector", "mgar_density_filter", "mgcg_solve", "mgar_solve",
+    "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
+    "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
+    "mgar_vcycle", "mgar_op_dk", "mgar_profile", "mgar_profile_read",
+]
+
+
+class mgar_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("nelx", ctypes.c_int), ("nely", ctypes.c_int),
+        ("nelz", ctypes.c_int), ("levels", ctypes.c_int),
+        ("fix_lo", ctypes.c_int * 3), ("fix_hi", ctypes.c_int * 3),
+        ("k0", ctypes.c_double), ("kmin", ctypes.c_double), ("penal", ctypes.c_double),
+        ("omega", ctypes.c_double), ("n_basis", ctypes.c_int), ("eps_accept", ctypes.c_double),
+        ("cg_max", ctypes.c_int), ("basis_x0_zero", ctypes.c_int), ("precision", ctypes.c_int),
+        ("filter_r", ctypes.c_double),
+    ]
+
+
+class mgar_stats(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int), ("cg_iters", ctypes.c_int), ("vcycles", ctypes.c_int),
+        ("refinements", ctypes.c_int), ("res_ca", ctypes.c_double),
+        ("res_final", ctypes.c_double), ("ms", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MgarError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libmgar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2210_00947_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, VP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        LL = ctypes.c_longlong
+        L.mgar_default_params.argtypes = [ctypes.POINTER(mgar_params)]
+        L.mgar_default_params.restype = None
+        L.mgar_setup.argtypes = [ctypes.POINTER(mgar_params), VP, ctypes.POINTER(P)]
+        L.mgar_destroy.argtypes = [P]
+        L.mgar_destroy.restype = None
+        L.mgar_set_stream.argtypes = [P, VP]
+        L.mgar_strerror.argtypes = [I]
+        L.mgar_strerror.restype = ctypes.c_char_p
+        L.mgar_sizes.argtypes = [P, I, ctypes.POINTER(LL), ctypes.POINTER(LL)]
+        L.mgar_load_vector.argtypes = [P, VP, VP]
+        L.mgar_density_filter.argtypes = [P, VP, VP]
+        for f in ("mgcg_solve", "mgar_solve"):
+            getattr(L, f).argtypes = [P, VP, VP, VP, D, VP, ctypes.POINTER(mgar_stats)]
+        L.sens_filter.argtypes = [P, VP, VP, VP, VP, VP, ctypes.POINTER(D)]
+        L.oc_update.argtypes = [P, VP, VP, VP, D, D, VP, ctypes.POINTER(D)]
+        L.mgar_reset.argtypes = [P]
+        L.mgar_op_apply.argtypes = [P, I, VP, VP, VP]
+        L.mgar_op_jacobi.argtypes = [P, I, VP, VP, VP, VP]
+        L.mgar_op_restrict.argtypes = [P, I, VP, VP]
+        L.mgar_op_prolong.argtypes = [P, I, VP, VP]
+        L.mgar_op_coarsen.argtypes = [P, I, VP, VP]
+        L.mgar_build_hierarchy.argtypes = [P, VP]
+        L.mgar_vcycle.argtypes = [P, VP, VP, VP]
+        L.mgar_op_dk.argtypes = [P, VP, VP, VP]
+        L.mgar_profile.argtypes = [P, ctypes.c_uint]
+        L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
+        for f in EXPORTS:
+            if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror"):
+                getattr(L, f).restype = I
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().mgar_strerror(int(code)).decode()
+
+
+def _ptr(t, n=None, name="tensor"):
+    """Device pointer of an FP64 contiguous GPU tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc, where, warn_ok=True):
+    if rc < 0 or (rc > 0 and not warn_ok):
+        raise MgarError(rc, where)
+    return rc
+
+
+def params_for(prob, n_basis=2, eps_accept=None, cg_max=200, omega=0.8, basis_x0_zero=False,
+               precision=PREC_FP64):
+    """mgar_params from a workloads.Problem description."""
+    p = mgar_params()
+    lib().mgar_default_params(ctypes.byref(p))
+    p.dim, p.nelx, p.nely = prob.dim, prob.nelx, prob.nely
+    p.nelz = prob.nelz if prob.dim == 3 else 0
+    p.levels = prob.levels
+    for a in range(3):
+        p.fix_lo[a] = prob.fix_lo[a]
+        p.fix_hi[a] = prob.fix_hi[a]
+    p.k0, p.kmin, p.penal = prob.k0, prob.kmin, prob.penal
+    p.omega = omega
+    p.n_basis = n_basis
+    p.eps_accept = prob.tol if eps_accept is None else eps_accept
+    p.cg_max = cg_max
+    p.basis_x0_zero = int(bool(basis_x0_zero))
+    p.precision = precision
+    p.filter_r = prob.filter_r
+    return p
+
+
+class Handle:
+    """Owns one mgar_handle. Methods keep the names of the C entry points."""
+
+    def __init__(self, params: mgar_params, stream=None):
+        import torch
+        self._L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(self._L.mgar_setup(ctypes.byref(params), ctypes.c_void_p(stream), ctypes.byref(h)),
+               "mgar_setup", warn_ok=False)
+        self.h = h
+        self.params = params
+        nn, ne = ctypes.c_longlong(), ctypes.c_longlong()
+        self._L.mgar_sizes(h, 0, ctypes.byref(nn), ctypes.byref(ne))
+        self.N, self.E = nn.value, ne.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mgar_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self, level):
+        nn, ne = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(self._L.mgar_sizes(self.h, level, ctypes.byref(nn), ctypes.byref(ne)), "mgar_sizes")
+        return nn.value, ne.value
+
+    def set_stream(self, stream):
+        _check(self._L.mgar_set_stream(self.h, ctypes.c_void_p(stream)), "mgar_set_stream")
+
+    def mgar_load_vector(self, Qe, q):
+        _check(self._L.mgar_load_vector(self.h, _ptr(Qe, self.E, "Qe"), _ptr(q, self.N, "q")),
+               "mgar_load_vector")
+
+    def mgar_density_filter(self, x, xphys):
+        _check(self._L.mgar_density_filter(self.h, _ptr(x, self.E, "x"), _ptr(xphys, self.E, "xphys")),
+               "mgar_density_filter")
+
+    def _solve(self, fn, xphys, q, T0, tol, T):
+        st = mgar_stats()
+        rc = fn(self.h, _ptr(xphys, self.E, "xphys"), _ptr(q, self.N, "q"),
+                _ptr(T0, self.N, "T0"), float(tol), _ptr(T, self.N, "T"), ctypes.byref(st))
+        _check(rc, fn.__name__)
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def mgcg_solve(self, xphys, q, T0, tol, T):
+        return self._solve(self._L.mgcg_solve, xphys, q, T0, tol, T)
+
+    def mgar_solve(self, xphys, q, T0, tol, T):
+        return self._solve(self._L.mgar_solve, xphys, q, T0, tol, T)
+
+    def sens_filter(self, xphys, T, q, dc, dv):
+        c = ctypes.c_double()
+        _check(self._L.sens_filter(self.h, _ptr(xphys, self.E, "xphys"), _ptr(T, self.N, "T"),
+                                   _ptr(q, self.N, "q"), _ptr(dc, self.E, "dc"),
+                                   _ptr(dv, self.E, "dv"), ctypes.byref(c)), "sens_filter")
+        return c.value
+
+    def oc_update(self, x, dc, dv, volfrac, move, x_new):
+        lam = ctypes.c_double()
+        _check(self._L.oc_update(self.h, _ptr(x, self.E, "x"), _ptr(dc, self.E, "dc"),
+                                 _ptr(dv, self.E, "dv"), float(volfrac), float(move),
+                                 _ptr(x_new, self.E, "x_new"), ctypes.byref(lam)), "oc_update")
+        return lam.value
+
+    def mgar_reset(self):
+        _check(self._L.mgar_reset(self.h), "mgar_reset")
+
+    def mgar_op_apply(self, level, k, x, y):
+        nn, ne = self.sizes(level)
+        _check(self._L.mgar_op_apply(self.h, level, _ptr(k, ne, "k"), _ptr(x, nn, "x"),
+                                     _ptr(y, nn, "y")), "mgar_op_apply")
+
+    def mgar_op_jacobi(self, level, k, b, x, out):
+        nn, ne = self.sizes(level)
+        _check(self._L.mgar_op_jacobi(self.h, level, _ptr(k, ne, "k"), _ptr(b, nn, "b"),
+                                      _ptr(x, nn, "x"), _ptr(out, nn, "out")), "mgar_op_jacobi")
+
+    def mgar_op_restrict(self, level, rf, rc):
+        nf, _ = self.sizes(level)
+        nc, _ = self.sizes(level + 1)
+        _check(self._L.mgar_op_restrict(self.h, level, _ptr(rf, nf, "rf"), _ptr(rc, nc, "rc")),
+               "mgar_op_restrict")
+
+    def mgar_op_prolong(self, level, xc, xf):
+        nf, _ = self.sizes(level)
+        nc, _ = self.sizes(level + 1)
+        _check(self._L.mgar_op_prolong(self.h, level, _ptr(xc, nc, "xc"), _ptr(xf, nf, "xf")),
+               "mgar_op_prolong")
+
+    def mgar_op_coarsen(self, level, kf, kc):
+        _, ef = self.sizes(level)
+        _, ec = self.sizes(level + 1)
+        _check(self._L.mgar_op_coarsen(self.h, level, _ptr(kf, ef, "kf"), _ptr(kc, ec, "kc")),
+               "mgar_op_coarsen")
+
+    def mgar_build_hierarchy(self, xphys):
+        _check(self._L.mgar_build_hierarchy(self.h, _ptr(xphys, self.E, "xphys")),
+               "mgar_build_hierarchy", warn_ok=False)
+
+    def mgar_vcycle(self, b, x0, x):
+        _check(self._L.mgar_vcycle(self.h, _ptr(b, self.N, "b"), _ptr(x0, self.N, "x0"),
+                                   _ptr(x, self.N, "x")), "mgar_vcycle")
+
+    def mgar_op_dk(self, xphys, r, b):
+        _check(self._L.mgar_op_dk(self.h, _ptr(xphys, self.E, "xphys"), _ptr(r, self.N, "r"),
+                                  _ptr(b, self.N, "b")), "mgar_op_dk")
+
+
+    def mgar_profile(self, mode_mask):
+        _check(self._L.mgar_profile(self.h, ctypes.c_uint(mode_mask)), "mgar_profile")
+
+    def mgar_profile_read(self):
+        n, ms, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        _check(self._L.mgar_profile_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+               "mgar_profile_read")
+        return n.value, ms.value, by.value
+
+
+def n_on(maxit: int) -> int:
+    """Activation parameter of the loop: MGCG while the cycle is below 2/15 of maxit."""
+    return (2 * maxit) // 15

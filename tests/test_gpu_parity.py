@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs. Operators at 1e-13 relative (FP64, different summation
+order); solves at 1e-8 relative L2 with identical iteration counts and paths."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fe, mg, solvers, topopt
+from tests.gpu_util import dev, host, masked_random, rel_err, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-13
+T_TOL = 1e-8
+
+PROBS = [
+    W.tiny_2d(40, 40, 3),
+    W.tiny_2d(48, 32, 4),
+    W.tiny_3d(16, 16, 16, 3),
+    W.tiny_3d(16, 16, 24, 4),
+]
+IDS = [p.name for p in PROBS]
+
+
+def handle(prob, **kw):
+    require_gpu()
+    from paper_2210_00947_amd import mgar as M
+    return M.Handle(M.params_for(prob, **kw))
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_apply_and_jacobi_every_level(prob):
+    h = handle(prob)
+    hier = mg.Hierarchy(prob, fe.simp(W.random_density(prob.nelem, 3, 0.0, 1.0)))
+    import torch
+    for l, lv in enumerate(hier.levels):
+        g = lv.grid
+        k = W.random_density(g.nelem, 10 + l, 1e-3, 1.0)
+        Kl = fe.assemble(g, k)[lv.free][:, lv.free]
+        x = masked_random(g.nnodes, lv.fixed, 20 + l)
+        want = np.zeros(g.nnodes)
+        want[lv.free] = Kl @ x[lv.free]
+        xg = dev(W.random_vector(g.nnodes, 20 + l))   # nonzero on fixed nodes: must be ignored
+        y = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+        h.mgar_op_apply(l, dev(k), xg, y)
+        assert rel_err(host(y), want) < OP_TOL, (l, rel_err(host(y), want))
+        b = masked_random(g.nnodes, lv.fixed, 30 + l)
+        D = Kl.diagonal()
+        wantj = np.zeros(g.nnodes)
+        wantj[lv.free] = x[lv.free] + 0.8 * (b[lv.free] - Kl @ x[lv.free]) / D
+        h.mgar_op_jacobi(l, dev(k), dev(b), xg, y)
+        assert rel_err(host(y), wantj) < OP_TOL
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_transfers_and_coarsening(prob):
+    h = handle(prob)
+    hier = mg.Hierarchy(prob, np.ones(prob.nelem))
+    import torch
+    for l in range(hier.L - 1):
+        lf, lc = hier.levels[l], hier.levels[l + 1]
+        gf, gc = lf.grid, lc.grid
+        Pfull = mg.interpolation(prob.dim, gf.nx, gf.ny, gf.nz)
+        # restriction
+        rf = masked_random(gf.nnodes, lf.fixed, 40 + l)
+        want = np.zeros(gc.nnodes)
+        want[lc.free] = hier.P[l].T @ rf[lf.free]
+        rc = torch.empty(gc.nnodes, dtype=torch.float64, device="cuda")
+        h.mgar_op_restrict(l, dev(rf), rc)
+        assert rel_err(host(rc), want) < OP_TOL
+        # interpolation + correction
+        xc = masked_random(gc.nnodes, lc.fixed, 50 + l)
+        xf0 = masked_random(gf.nnodes, lf.fixed, 60 + l)
+        wantp = xf0.copy()
+        wantp[lf.free] += hier.P[l] @ xc[lc.free]
+        xf = dev(xf0)
+        h.mgar_op_prolong(l, dev(xc), xf)
+        assert rel_err(host(xf), wantp) < OP_TOL
+        # coarse conductivity
+        kf = W.random_density(gf.nelem, 70 + l, 1e-3, 1.0)
+        kc = torch.empty(gc.nelem, dtype=torch.float64, device="cuda")
+        h.mgar_op_coarsen(l, dev(kf), kc)
+        assert rel_err(host(kc), mg.coarsen_conductivity(kf, prob.dim, gf.nx, gf.ny, gf.nz)) < 1e-15
+        del Pfull
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+@pytest.mark.parametrize("with_guess", [False, True])
+def test_vcycle(prob, with_guess):
+    h = handle(prob)
+    xphys = W.random_density(prob.nelem, 5, 0.0, 1.0)
+    hier = mg.Hierarchy(prob, fe.simp(xphys))
+    h.mgar_build_hierarchy(dev(xphys))
+    lv = hier.levels[0]
+    b = masked_random(prob.nnodes, lv.fixed, 6)
+    x0 = masked_random(prob.nnodes, lv.fixed, 7) if with_guess else np.zeros(prob.nnodes)
+    want = np.zeros(prob.nnodes)
+    want[lv.free] = hier.vcycle(0, b[lv.free], x0[lv.free])
+    import torch
+    x = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_vcycle(dev(b), dev(x0) if with_guess else None, x)
+    assert rel_err(host(x), want) < 1e-11
+
+
+def test_vcycle_single_level_is_exact_solve():
+    prob = W.tiny_2d(8, 8, 1)
+    h = handle(prob)
+    xphys = W.random_density(prob.nelem, 8, 0.0, 1.0)
+    h.mgar_build_hierarchy(dev(xphys))
+    fep = fe.FEProblem(prob)
+    K = fep.K_free(xphys)
+    b = masked_random(prob.nnodes, fep.fixed, 9)
+    import torch
+    x = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_vcycle(dev(b), None, x)
+    want = fep.to_full(solvers.exact_solve(K, b[fep.free]))
+    assert rel_err(host(x), want) < 1e-11
+
+
+def _load(prob, h):
+    import torch
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    return q
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_load_vector(prob):
+    h = handle(prob)
+    fep = fe.FEProblem(prob)
+    assert rel_err(host(_load(prob, h)), fep.q) < 1e-15
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_mgcg_parity(prob):
+    import torch
+    h = handle(prob)
+    q = _load(prob, h)
+    xphys = W.random_density(prob.nelem, 11, 0.0, 1.0)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    t_or, st_or = s.mgcg(xphys, np.zeros(prob.nnodes), 1e-8)
+    T = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    st = h.mgcg_solve(dev(xphys), q, None, 1e-8, T)
+    assert st["rc"] == 0 and st["path"] == 0
+    assert st["cg_iters"] == st_or.cg_iters
+    assert rel_l2(host(T), t_or) < T_TOL
+    # recursive residuals agree to round-off in units of ||q||
+    assert abs(st["res_final"] - st_or.res_final) <= 1e-11
+    # and against the exact solve
+    fep = s.fep
+    texact = fep.to_full(solvers.exact_solve(fep.K_free(xphys), fep.to_free(fep.q)))
+    assert rel_l2(host(T), texact) < 1e-6
+
+
+@pytest.mark.parametrize("prob", PROBS, ids=IDS)
+@pytest.mark.parametrize("m,eps,x0zero", [(2, 1e-8, False), (2, 0.5, False), (3, 0.5, True),
+                                           (1, 0.5, False), (4, 1e-8, True)])
+def test_mgar_parity(prob, m, eps, x0zero):
+    import torch
+    h = handle(prob, n_basis=m, eps_accept=eps, basis_x0_zero=x0zero)
+    q = _load(prob, h)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(n_basis=m, eps_accept=eps, basis_x0_zero=x0zero))
+    x0 = W.random_density(prob.nelem, 21, 0.2, 0.8)
+    x1 = np.clip(x0 + 0.02 * W.random_vector(prob.nelem, 22), 0, 1)
+    x2 = np.clip(x1 + 0.02 * W.random_vector(prob.nelem, 23), 0, 1)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    T2 = torch.empty_like(T0)
+    t0, _ = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    t_prev, Tin = t0, T0
+    for xx, Tout in ((x1, T1), (x2, T2)):
+        t_or, st_or = s.mgar(xx, t_prev, 1e-8)
+        st = h.mgar_solve(dev(xx), q, Tin, 1e-8, Tout)
+        assert st["path"] == st_or.path
+        assert abs(st["res_ca"] - st_or.res_ca) <= 1e-8 * st_or.res_ca
+        assert st["cg_iters"] == st_or.cg_iters
+        assert rel_l2(host(Tout), t_or) < T_TOL
+        t_prev, Tin = t_or, Tout
+
+
+@pytest.mark.parametrize("prob", PROBS[:3], ids=IDS[:3])
+def test_dk_apply(prob):
+    import torch
+    h = handle(prob)
+    x0 = W.random_density(prob.nelem, 31, 0.0, 1.0)
+    x1 = W.random_density(prob.nelem, 32, 0.0, 1.0)
+    h.mgar_build_hierarchy(dev(x0))
+    fep = fe.FEProblem(prob)
+    r = masked_random(prob.nnodes, fep.fixed, 33)
+    want = fep.to_full(-((fep.K_free(x1) - fep.K_free(x0)) @ r[fep.free]))
+    b = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_op_dk(dev(x1), dev(r), b)
+    assert rel_err(host(b), want) < OP_TOL
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_filter_sensitivity_oc(prob):
+    import torch
+    h = handle(prob)
+    fep = fe.FEProblem(prob)
+    filt = topopt.Filter(fep.grid, prob.filter_r)
+    x = W.random_density(prob.nelem, 41, 0.1, 0.9)
+    xp = torch.empty(prob.nelem, dtype=torch.float64, device="cuda")
+    h.mgar_density_filter(dev(x), xp)
+    xph = filt.forward(x)
+    assert rel_err(host(xp), xph) < 1e-14
+    t = fep.to_full(solvers.exact_solve(fep.K_free(xph), fep.to_free(fep.q)))
+    f, dc, dv, _ = topopt.sensitivity(fep, filt, xph, t)
+    dcg = torch.empty_like(xp)
+    dvg = torch.empty_like(xp)
+    q = _load(prob, h)
+    fg = h.sens_filter(dev(xph), dev(t), q, dcg, dvg)
+    assert abs(fg - f) <= 1e-13 * abs(f)
+    # element energies t_e^T KE t_e cancel (KE has zero row sums), so allow a few
+    # hundred ulps of the largest entry
+    assert rel_err(host(dcg), dc) < 1e-12
+    assert rel_err(host(dvg), dv) < 1e-14
+    xn, lam, _ = topopt.oc_update(x, dc, dv, filt, prob.volfrac, prob.move)
+    xng = torch.empty_like(xp)
+    lamg = h.oc_update(dev(x), dev(dc), dev(dv), prob.volfrac, prob.move, xng)
+    assert abs(lamg - lam) <= 1e-9 * lam
+    assert np.abs(host(xng) - xn).max() < 1e-9
+
+
+def test_loop_c0_matches_oracle():
+    require_gpu()
+    from paper_2210_00947_amd.topopt import TopOpt
+    prob = W.C0
+    x_or, _, _, recs = topopt.run_loop(prob)
+    opt = TopOpt(prob, W.element_source(prob))
+    cyc = opt.run()
+    xg = host(opt.x)
+    for a, b in zip(cyc, recs):
+        assert a.path == b.path, (a.cycle, a.path, b.path)
+        assert abs(a.compliance - b.compliance) <= 1e-8 * b.compliance
+        assert a.cg_iters == b.cg_iters
+    assert np.abs(xg - x_or).max() < 1e-6
+
+
+# ------------------------------------------------------------ full-size spot checks
+
+def test_apply_c3_sampled_rows():
+    """Finest-level apply at 128^3 on 4096 sampled nodes, computed one by one by
+    the oracle's element sum."""
+    import torch
+    prob = W.C3
+    h = handle(prob)
+    g = fe.Grid(3, 128, 128, 128)
+    fixed = fe.fixed_mask_from_box(g, prob.fix_lo, prob.fix_hi)
+    k = W.random_density(g.nelem, 51, 1e-3, 1.0)
+    x = W.random_vector(g.nnodes, 52)
+    x[fixed] = 0.0
+    y = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_op_apply(0, dev(k), dev(x), y)
+    rng = np.random.default_rng(53)
+    rows = np.concatenate([rng.integers(0, g.nnodes, 4000),
+                           [0, g.nnodes - 1, g.node_id(64, 64, 0), g.node_id(128, 0, 64)]])
+    want = fe.apply_rows(g, k, x, rows)
+    want[fixed[rows]] = 0.0
+    assert rel_err(host(y)[rows], want) < OP_TOL
+
+
+def test_mgcg_c2_true_residual():
+    """Full 64^3 solve: the oracle's assembled K gives the true residual of the
+    GPU temperature."""
+    import torch
+    prob = W.C2
+    h = handle(prob)
+    q = _load(prob, h)
+    xphys = W.random_density(prob.nelem, 61, 0.0, 1.0)
+    T = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    st = h.mgcg_solve(dev(xphys), q, None, 1e-8, T)
+    assert st["rc"] == 0
+    fep = fe.FEProblem(prob)
+    K = fep.K_free(xphys)
+    t = host(T)
+    r = fep.to_free(fep.q) - K @ t[fep.free]
+    assert np.linalg.norm(r) / np.linalg.norm(fep.to_free(fep.q)) < 2e-8
+    assert np.all(t[fep.fixed] == 0)

@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # finest-grid stencil kernel reported in the roofline object (mode bit of mgar_profile)
 ROOF_MODE = 1          # apply + dot: q = K p, p.q  (one launch per CG iteration, finest grid only)
-ROOF_KERNEL = "k_stencil<3, SM_APPLY_DOT> (finest grid, q = K p with p.q)"
+ROOF_KERNEL = "k_stencil_z<SM_APPLY_DOT> (finest grid, q = K p with p.q)"
 
 
 def log(*a):

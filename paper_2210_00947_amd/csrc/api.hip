@@ -36,6 +36,7 @@ struct mgar_handle {
   int* dstatus = nullptr;                 // device status word (coarsest pivots)
   double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
   double *pa = nullptr, *pb = nullptr, *pc = nullptr;  // partial-sum buffers
+  unsigned* cnt = nullptr;                // last-block counters of in-launch reductions
   long long part_cap = 0;
   double* scal = nullptr;                 // device scalars
   CgState* st = nullptr;
@@ -47,6 +48,8 @@ struct mgar_handle {
   double* tap_w = nullptr;
   int ntap = 0;
   bool has_k0 = false;
+  int lt = 1;                             // first grid handled by the V-cycle tail kernel
+  TailSpec tail;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // kernel timing (instrumentation)
   unsigned prof_mask = 0;
@@ -154,7 +157,8 @@ double stencil_bytes(const Geo& g, int mode) {
 // profiling mask are bracketed by HIP events on the same stream.
 int stencil_at(mgar_handle* h, int level, int mode, const double* x, const double* k,
                const double* kref, const double* b, double* out, double omega, double* part,
-               const int* done, int* nparts = nullptr, int tag = -1) {
+               const int* done, int* nparts = nullptr, int tag = -1, unsigned* cnt = nullptr,
+               double* rout = nullptr) {
   const Geo& g = h->lv[level].g;
   const bool timed = level == 0 && (h->prof_mask >> mode) & 1u;
   if (timed) {
@@ -167,11 +171,40 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
     }
     HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
   }
-  const int np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s);
+  const int np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout);
   if (nparts) *nparts = np;
   if (timed) {
     HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
     h->prof_bytes.push_back(stencil_bytes(g, mode));
+    h->prof_tag.push_back(tag);
+    h->prof_used += 2;
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// Fused interpolation + post-smoother on grid `level` (profiled like the
+// Jacobi modes; its algorithmic bytes add the coarse correction read).
+int prolong_smooth_at(mgar_handle* h, int level, const double* xa, const double* ec, const double* b,
+                      double* out, double* part, const int* done, int tag) {
+  const Geo& g = h->lv[level].g;
+  const int mode = part ? SM_JACOBI_DOT : SM_JACOBI;
+  const bool timed = level == 0 && (h->prof_mask >> mode) & 1u;
+  if (timed) {
+    if (h->prof_used + 2 > h->prof_ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIPCK(hipEventCreate(&e));
+        h->prof_ev.push_back(e);
+      }
+    }
+    HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
+  }
+  launch_prolong_smooth(g, h->lv[level + 1].g, xa, ec, h->lv[level].k, b, out, h->p.omega, part, done,
+                        h->s);
+  if (timed) {
+    HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
+    h->prof_bytes.push_back(stencil_bytes(g, mode) + 8.0 * (double)h->lv[level + 1].g.nn);
     h->prof_tag.push_back(tag);
     h->prof_used += 2;
   }
@@ -203,16 +236,17 @@ int profile_harvest(mgar_handle* h, int cutoff = 1 << 30) {
 // One V-cycle (Table 1) on the K0 hierarchy: out = MG(K0, b0, x0). With
 // dot_part set, the finest post-smoother also writes partials of b0 . out.
 int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, double* dot_part,
-           const int* done, int tag = -1) {
+           const int* done, int tag = -1, unsigned* dcnt = nullptr, double* dout = nullptr) {
   const int L = h->L;
   const double w = h->p.omega;
   if (L == 1) {
     launch_coarse_solve(h->lv[0].g, h->Ainv, b0, out, done, h->s);
-    if (dot_part) launch_dot(b0, out, h->N, dot_part, done, h->s);
+    if (dot_part) launch_dot(b0, out, h->N, dot_part, done, h->s, dcnt, dout);
     LAUNCHCK();
     return MGAR_OK;
   }
-  for (int l = 0; l < L - 1; ++l) {
+  const int lt = h->lt;   // grids lt..L-1 run inside one workgroup
+  for (int l = 0; l < lt; ++l) {
     LevelBuf& v = h->lv[l];
     const double* b = (l == 0) ? b0 : v.b;
     if (l == 0 && x0) ACK(stencil_at(h, l, SM_JACOBI, x0, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
@@ -220,15 +254,20 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
     ACK(stencil_at(h, l, SM_RESID, v.xa, v.k, nullptr, b, h->rtmp, w, nullptr, done, nullptr, tag));
     launch_restrict(v.g, h->lv[l + 1].g, h->rtmp, h->lv[l + 1].b, done, h->s);
   }
-  launch_coarse_solve(h->lv[L - 1].g, h->Ainv, h->lv[L - 1].b, h->lv[L - 1].xa, done, h->s);
-  const double* xfin = h->lv[L - 1].xa;
-  for (int l = L - 2; l >= 0; --l) {
+  launch_vtail(h->tail, h->lv[lt].b, h->lv[lt].xb, h->Ainv, w, done, h->s);
+  const double* xfin = h->lv[lt].xb;
+  for (int l = lt - 1; l >= 0; --l) {
     LevelBuf& v = h->lv[l];
     const double* b = (l == 0) ? b0 : v.b;
-    launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
     double* o = (l == 0) ? out : v.xb;
-    ACK(stencil_at(h, l, (l == 0 && dot_part) ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w,
-                   dot_part, done, nullptr, tag));
+    double* dp = (l == 0) ? dot_part : nullptr;
+    if (false && stencil_fuses_prolong(v.g)) {
+      ACK(prolong_smooth_at(h, l, v.xa, xfin, b, o, dp, done, tag));
+    } else {
+      launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
+      ACK(stencil_at(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w, dp, done,
+                     nullptr, tag, dp ? dcnt : nullptr, dp ? dout : nullptr));
+    }
     xfin = o;
   }
   LAUNCHCK();
@@ -240,10 +279,11 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
 int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, double* relres) {
   const Geo& g = h->lv[0].g;
   const long long N = h->N;
+  const int cg_max = h->p.cg_max;
   ACK(stencil_at(h, 0, SM_RESID, h->cx, kfine, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
   const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
   const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
-  launch_cg_init(h->st, h->pb, nq, h->pa, nr, h->s);
+  launch_cg_init(h->st, h->pb, nq, h->pa, nr, tol, cg_max, h->s);
   LAUNCHCK();
   const int* done = &h->st->done;
   int it = 0;
@@ -251,12 +291,12 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
   double rr_prev = -1.0;
   int it_prev = 0;
   CgState hs;
-  launch_cg_check(h->st, h->pa, nr, 0, tol, h->p.cg_max, h->s);
   for (;;) {
-    // Enqueue up to `chunk` iterations; once the stopping test fires on the
-    // device every later kernel returns immediately, so the iterates are those
-    // of a loop that tests before every iteration.
-    for (int c = 0; c < chunk && it < h->p.cg_max; ++c, ++it) {
+    // Enqueue up to `chunk` iterations. The stopping test runs on the device
+    // (before iteration 0 in cg_init, then at the end of every update); once
+    // it fires, every later kernel returns immediately, so the iterates are
+    // those of a loop that tests before every iteration.
+    for (int c = 0; c < chunk && it < cg_max; ++c, ++it) {
       ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, it));
       const int nz = (h->L == 1) ? vec_num_blocks(N) : stencil_num_partials(g);
       launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
@@ -264,13 +304,14 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
       int nw = 0;
       ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, kfine, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, it));
       launch_finalize(h->pc, nw, &h->st->pw, done, h->s);
-      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, it, h->pa, h->s);
-      launch_cg_check(h->st, h->pa, nr, it + 1, tol, h->p.cg_max, h->s);
+      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, it, h->pa, nullptr, tol, cg_max, h->s);
+      launch_cg_check(h->st, h->pa, nr, it + 1, tol, cg_max, h->s);
       LAUNCHCK();
     }
     HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
     if (hs.done) break;
+    if (it >= cg_max) return MGAR_E_HIP;   // the device test must have fired by now
     // predict the remaining iterations from the observed contraction rate
     const double rr = hs.rr;
     int next = 4;
@@ -389,7 +430,7 @@ void mgar_destroy(mgar_handle* h) {
     if (v.xb) (void)hipFree(v.xb);
   }
   void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp,
-                  h->cw, h->pa, h->pb, h->pc, h->scal, h->st, h->md, h->oc, h->R, h->Wm,
+                  h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -442,6 +483,8 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->pb, cap));
   ACK(dalloc(&h->pc, cap));
   ACK(dalloc(&h->scal, 16));
+  ACK(dalloc(&h->cnt, 16));
+  HIPCK(hipMemset(h->cnt, 0, 16 * sizeof(unsigned)));
   ACK(dalloc(&h->st, 1));
   ACK(dalloc(&h->md, 1));
   ACK(dalloc(&h->oc, 1));
@@ -452,6 +495,17 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->gtmp, E));
   HIPCK(hipEventCreate(&h->e0));
   HIPCK(hipEventCreate(&h->e1));
+  if (h->L >= 2) {
+    std::vector<Geo> gs(h->L);
+    std::vector<double*> ks(h->L);
+    for (int l = 0; l < h->L; ++l) { gs[l] = h->lv[l].g; ks[l] = h->lv[l].k; }
+    h->lt = h->L - 1;
+    for (int lt = 1; lt < h->L; ++lt) {
+      TailSpec T;
+      if (tail_plan(gs.data(), ks.data(), lt, h->L, &T)) { h->lt = lt; break; }
+    }
+    if (!tail_plan(gs.data(), ks.data(), h->lt, h->L, &h->tail)) return MGAR_E_DIMS;
+  }
   // cone filter taps (Eq 7-8): offsets within the radius, weight r - distance
   {
     const int Rw = (int)std::ceil(p->filter_r);
@@ -645,11 +699,11 @@ int oc_update(mgar_handle* h, const double* x, const double* dc, const double* d
               double move, double* x_new, double* lambda) {
   if (!h || !x || !dc || !dv || !x_new) return MGAR_E_ARG;
   const double target = volfrac * (double)h->E;
-  launch_oc_init(h->oc, h->s);
+  launch_oc_init(h->oc, target, h->s);
   OcDev ho;
   int passes = 0;
   for (;;) {
-    const int chunk = passes == 0 ? 12 : 2;
+    const int chunk = passes == 0 ? 5 : 2;   // typically 4-6 passes
     for (int c = 0; c < chunk; ++c) {
       const int np = launch_oc_pass(x, dc, dv, h->E, move, h->oc, h->pa, h->s);
       launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);

@@ -44,7 +44,7 @@ struct CgState {
 
 // Reanalysis (reduced-basis) state in device memory.
 struct MgarDev {
-  double n0[MGAR_MAXB];      // column norm before projection
+  double n0[MGAR_MAXB];      // squared column norm before projection
   double c[MGAR_MAXB];       // projection coefficients
   int active[MGAR_MAXB];     // 1 = column kept
   double KR[MGAR_MAXB * MGAR_MAXB];
@@ -56,15 +56,20 @@ struct MgarDev {
   int pad;
 };
 
-// OC bisection state in device memory (speculative bisection tree).
-#define OC_DEPTH 5
-#define OC_NCAND ((1 << OC_DEPTH) - 1)
+// OC bisection state in device memory. The filtered volume S(lambda) is
+// non-increasing in lambda, so evaluating it at candidate values brackets the
+// root: lo_known is the largest evaluated lambda with S > target, hi_known the
+// smallest with S <= target. Every bisection midpoint outside (lo_known,
+// hi_known) is then decided without another evaluation.
+#define OC_NCAND 15
 struct OcDev {
-  double l1, l2;             // current bracket
-  double lam_last;           // last evaluated midpoint
-  double cand[OC_NCAND];     // midpoints of the next OC_DEPTH bisection levels (heap order)
+  double l1, l2;             // current bisection bracket
+  double lam_last;           // last midpoint the bisection evaluated
+  double lo_known, hi_known; // evaluated bracket of the root
+  double s_lo, s_hi;         // S at lo_known and hi_known (when evaluated)
+  double cand[OC_NCAND];     // candidates for the next pass
   int done;
-  int steps;
+  int steps;                 // bisection steps replayed so far
   int pad[2];
 };
 
@@ -89,6 +94,37 @@ __device__ inline double block_sum(double v, double* sh) {
   double s = 0.0;
   for (int w = 0; w < nw; ++w) s += sh[w];
   return s;
+}
+
+// Grid-level reduction without a second launch: every block stores its
+// partial, then one thread per block bumps a device-scope counter; the block
+// that sees the count reach nb sums all partials in index order (so the
+// result is the same whichever block finishes last), writes *out and resets
+// the counter. Returns true in the threads of that last block. Call from
+// all threads; `s` must be valid in thread 0.
+__device__ inline bool grid_reduce(double s, int bid, int nb, double* __restrict__ part,
+                                   unsigned* __restrict__ cnt, double* __restrict__ out,
+                                   double* sh, double* total) {
+  __shared__ int last;
+  const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  if (t == 0) {
+    part[bid] = s;
+    __threadfence();
+    last = (atomicAdd(cnt, 1u) == (unsigned)(nb - 1));
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double v = 0.0;
+  for (int i = t; i < nb; i += nt) v += __builtin_nontemporal_load(part + i);
+  v = block_sum(v, sh);
+  if (t == 0) {
+    if (out) *out = v;
+    *cnt = 0u;
+  }
+  if (total) *total = v;
+  return true;
 }
 
 __device__ inline int flat_tid() {

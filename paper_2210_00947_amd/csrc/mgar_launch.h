@@ -14,13 +14,23 @@ enum StencilMode {
 };
 
 // stencil.hip ----------------------------------------------------------------
-// Returns the number of block partials written to `part` (0 for modes without a dot).
+// Returns the number of block partials written to `part` (0 for modes without a
+// dot). With cnt != null the dot is also reduced in the same launch (last block
+// sums the partials in order) and stored to *rout.
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s);
+                   hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr);
 int stencil_num_partials(const Geo& g);
 void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
                      hipStream_t s);
+// Post-smoother with the coarse correction interpolated on the fly:
+// out = x + w D^-1 (b - K x), x = xa + P ec (Table 1 steps 4-5 in one pass);
+// with part != null also partials of b . out. Only for grids where
+// stencil_fuses_prolong() is true.
+bool stencil_fuses_prolong(const Geo& g);
+int launch_prolong_smooth(const Geo& g, const Geo& gc, const double* xa, const double* ec,
+                          const double* k, const double* b, double* out, double omega,
+                          double* part, const int* done, hipStream_t s);
 void launch_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf, const int* done,
                     hipStream_t s);
 void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, hipStream_t s);
@@ -29,21 +39,43 @@ void launch_coarse_solve(const Geo& g, const double* A, const double* b, double*
                          const int* done, hipStream_t s);
 void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s);
 
+// Bottom of the V-cycle in one workgroup: grids lt..L-1 of a hierarchy with
+// their vectors in LDS. b_in: right-hand side on grid lt; x_out: the V-cycle
+// result on grid lt.
+#define MGAR_MAX_TAIL 8
+struct TailSpec {
+  int nl;                          // grids in the tail (>= 1); the last is the coarsest
+  int lds_doubles;                 // LDS footprint
+  Geo g[MGAR_MAX_TAIL];
+  const double* k[MGAR_MAX_TAIL];  // cell conductivities (global memory)
+  int off_b[MGAR_MAX_TAIL], off_xa[MGAR_MAX_TAIL], off_xb[MGAR_MAX_TAIL], off_k[MGAR_MAX_TAIL];
+};
+// Fills the LDS layout; returns false if grids lt.. do not fit.
+bool tail_plan(const Geo* g, double* const* k, int lt, int L, TailSpec* T);
+void launch_vtail(const TailSpec& T, const double* b_in, double* x_out, const double* Ainv,
+                  double omega, const int* done, hipStream_t s);
+
 // vec.hip --------------------------------------------------------------------
 int vec_num_blocks(long long n);
 // partial[b] = sum over block b of a.b ; returns number of partials
 int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
-               hipStream_t s);
+               hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr);
 // out = sum(part[0..n)) in a fixed order (single block)
 void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s);
+// Stopping test before iteration it from the partials of ||r||^2.
 void launch_cg_check(CgState* st, const double* part, int np, int it, double tol, int cg_max,
                      hipStream_t s);
+// ||q||^2 and ||r_0||^2 from partials, and the stopping test before iteration 0.
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
-                    hipStream_t s);
+                    double tol, int cg_max, hipStream_t s);
 void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
                      hipStream_t s);
+// x += alpha p, r -= alpha w and partials of ||r||^2; with cnt != null the sum
+// is also reduced in the launch and the stopping test for iteration it+1
+// applied by the last block (costs a device-scope fence per block).
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     const CgState* st, int it, double* part, hipStream_t s);
+                     CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
+                     hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s);
 // Gram-Schmidt / reduced system helpers
@@ -75,7 +107,7 @@ void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, d
                       hipStream_t s);
 void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const double* invHs,
                       double k0, double kmin, double penal, double* gout, hipStream_t s);
-void launch_oc_init(OcDev* oc, hipStream_t s);
+void launch_oc_init(OcDev* oc, double target, hipStream_t s);
 int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
                    const OcDev* oc, double* part, hipStream_t s);
 void launch_oc_walk(OcDev* oc, const double* part, int np, double target, double tol,

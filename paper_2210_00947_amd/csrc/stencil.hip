@@ -11,6 +11,8 @@
 // Every N-vector the kernels read is exactly 0 on Dirichlet nodes, and every
 // N-vector they write is set to 0 there; nodes outside the grid only occur in
 // cells outside the grid, whose conductivity is taken as 0.
+#include <algorithm>
+
 #include "mgar_launch.h"
 
 namespace {
@@ -103,7 +105,9 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const double* __res
                                                       const double* __restrict__ b,
                                                       double* __restrict__ out, double omega,
                                                       double* __restrict__ part,
-                                                      const int* __restrict__ done) {
+                                                      const int* __restrict__ done,
+                                                      unsigned* __restrict__ cnt,
+                                                      double* __restrict__ rout) {
   if (done && *done) return;
   __shared__ double sh[TBX * TBY / MGAR_WAVE];
   const int i = blockIdx.x * TBX + threadIdx.x;
@@ -148,7 +152,292 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const double* __res
   }
   if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
     const double s = block_sum(dotv, sh);
-    if (flat_tid() == 0) part[flat_bid()] = s;
+    if (cnt) grid_reduce(s, flat_bid(), gridDim.x * gridDim.y * gridDim.z, part, cnt, rout, sh, nullptr);
+    else if (flat_tid() == 0) part[flat_bid()] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3D z-marching stencil for the large grids. A block owns a TXW x TYH tile of
+// node columns and walks KZ consecutive z-planes. Each plane of x (tile plus a
+// one-node halo) and each plane of cell conductivities (tile plus the cells
+// below-left of it) passes through a ring of LDS slots: while node plane k is
+// computed from LDS, the next plane is already in flight in registers. A
+// thread thus issues about four global loads per plane and reads its 21
+// weighted neighbours from LDS. Tiles split each row evenly (129 = 3 x 43), so
+// no block is left with a single column.
+// Block ids are remapped so that each XCD (blocks are dealt round-robin to the
+// 8 XCDs) receives a contiguous range of tiles, z-chunk slowest: halo rows and
+// planes shared by neighbouring tiles then hit in that XCD's L2.
+constexpr int ZT = 256;
+constexpr int XCAP = 420;   // >= (TXW+2)(TYH+2)
+constexpr int CCAP = 360;   // >= (TXW+1)(TYH+1)
+
+__device__ inline int xcd_remap(int bid, int nb) {
+  const int xcd = bid & 7, local = bid >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+// x-plane fill policies: XP_PLAIN reads x; XP_PROLONG reads xa + P e_c, the
+// iterate after the coarse-grid correction of Table 1 step 4 (interpolated on
+// the fly, so the corrected iterate is never written to memory).
+enum { XP_PLAIN = 0, XP_PROLONG = 1 };
+
+// Per-thread description of one LDS fill slot of the x plane: the node's
+// offset inside a plane and, for the interpolated fill, its coarse-grid
+// neighbourhood in x and y. Built once per block, so a plane fill is a few
+// multiply-adds.
+struct XSlot {
+  long long off;      // ii + nnx * jj (node offset within a plane)
+  long long coff;     // I0 + nnxc * J0 (coarse offset within a coarse plane)
+  int ok;             // slot inside the tile halo and the grid
+  int fxy;            // (ii, jj) inside the Dirichlet box in x and y
+  int ni, nj;         // coarse neighbours along x and y (1 or 2)
+  double wi, wj;      // their weights (1 or 1/2)
+};
+
+__device__ inline XSlot make_xslot(const Geo& g, const Geo& gc, int i0, int j0, int XW, int XN,
+                                   int idx) {
+  XSlot sl;
+  const int ii = i0 - 1 + idx % XW, jj = j0 - 1 + idx / XW;
+  sl.ok = idx < XN && ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny;
+  sl.off = (long long)ii + (long long)g.nnx * jj;
+  sl.fxy = ii >= g.f0x && ii <= g.f1x && jj >= g.f0y && jj <= g.f1y;
+  sl.ni = (ii & 1) ? 2 : 1;
+  sl.nj = (jj & 1) ? 2 : 1;
+  sl.wi = (ii & 1) ? 0.5 : 1.0;
+  sl.wj = (jj & 1) ? 0.5 : 1.0;
+  sl.coff = (long long)(ii >> 1) + (long long)gc.nnx * (jj >> 1);
+  return sl;
+}
+
+template <int XP>
+__device__ inline double zfill_x(const Geo& g, const Geo& gc, const double* __restrict__ x,
+                                 const double* __restrict__ ec, const XSlot& sl, int p) {
+  if (!sl.ok || p < 0 || p >= g.nnz) return 0.0;
+  const long long pl = (long long)g.nnx * g.nny;
+  double v = x[sl.off + pl * p];
+  if (XP == XP_PROLONG && !(sl.fxy && p >= g.f0z && p <= g.f1z)) {
+    const long long cpl = (long long)gc.nnx * gc.nny;
+    const int nk = (p & 1) ? 2 : 1;
+    const double wk = (p & 1) ? 0.5 : 1.0;
+    const double* e0 = ec + sl.coff + cpl * (p >> 1);
+    double s = 0.0;
+    for (int c = 0; c < nk; ++c) {
+      double sy = 0.0;
+      for (int b = 0; b < sl.nj; ++b) {
+        const double* r = e0 + c * cpl + b * gc.nnx;
+        sy += sl.wi * (sl.ni == 2 ? r[0] + r[1] : r[0]);
+      }
+      s += sl.wj * sy;
+    }
+    v += wk * s;
+  }
+  return v;
+}
+
+struct CSlot {
+  long long off;      // ex + nx * ey (cell offset within a cell plane)
+  int ok;
+};
+
+__device__ inline CSlot make_cslot(const Geo& g, int i0, int j0, int CW, int CN, int idx) {
+  CSlot sl;
+  const int ex = i0 - 1 + idx % CW, ey = j0 - 1 + idx / CW;
+  sl.ok = idx < CN && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
+  sl.off = (long long)ex + (long long)g.nx * ey;
+  return sl;
+}
+
+template <bool DK>
+__device__ inline double zfill_c(const Geo& g, const double* __restrict__ k,
+                                 const double* __restrict__ kref, const CSlot& sl, int ez) {
+  if (!sl.ok || ez < 0 || ez >= g.nz) return 0.0;
+  const long long e = sl.off + (long long)g.nx * g.ny * ez;
+  return DK ? k[e] - kref[e] : k[e];
+}
+
+template <int MODE, int XP, int ZD = 1>
+__global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
+                                                  int KZ, const double* __restrict__ x,
+                                                  const double* __restrict__ ec,
+                                                  const double* __restrict__ k,
+                                                  const double* __restrict__ kref,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ out, double omega,
+                                                  double* __restrict__ part,
+                                                  const int* __restrict__ done,
+                                                  unsigned* __restrict__ cnt,
+                                                  double* __restrict__ rout) {
+  if (done && *done) return;
+  constexpr bool DK = (MODE == SM_NEG_DK);
+  constexpr bool NEEDX = (MODE != SM_JACOBI0);
+  constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
+                          MODE == SM_JACOBI0);
+  __shared__ double Xs[2][XCAP];
+  __shared__ double Cs[2][CCAP];
+  __shared__ double sh[ZT / MGAR_WAVE];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int nxy = ntx * nty;
+  const int txy = t % nxy, zc = t / nxy;
+  const int i0 = (txy % ntx) * TXW, j0 = (txy / ntx) * TYH;
+  const int XW = TXW + 2, XN = XW * (TYH + 2);
+  const int CW = TXW + 1, CN = CW * (TYH + 1);
+  const int tid = threadIdx.x;
+  const int lx = tid % TXW, ly = tid / TXW;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool act = ly < TYH && i < g.nnx && j < g.nny;
+  const int k0 = zc * KZ;
+  const int k1 = min(k0 + KZ, g.nnz);
+  const long long pl = (long long)g.nnx * g.nny;
+  const long long nxy_off = (long long)i + (long long)g.nnx * j;
+  const XSlot xs0 = make_xslot(g, gc, i0, j0, XW, XN, tid);
+  const XSlot xs1 = make_xslot(g, gc, i0, j0, XW, XN, tid + ZT);
+  const CSlot cs0 = make_cslot(g, i0, j0, CW, CN, tid);
+  const CSlot cs1 = make_cslot(g, i0, j0, CW, CN, tid + ZT);
+  // LDS index of this thread's node (x planes) and of its lower-left cell
+  const int xc = act ? (ly + 1) * XW + (lx + 1) : XW + 1;
+  const int cb = act ? ly * CW + lx : 0;
+
+#define ZX(sl, p) (NEEDX ? zfill_x<XP>(g, gc, x, ec, (sl), (p)) : 0.0)
+#define ZC(sl, ez) zfill_c<DK>(g, k, kref, (sl), (ez))
+#define ZB(p) ((NEEDB && act && (p) < k1) ? b[nxy_off + pl * (p)] : 0.0)
+
+  // register queue of global loads: entry d holds x plane kk+1+d, cell plane
+  // kk+d and b of plane kk+d for the step of node plane kk
+  double qx0[ZD], qx1[ZD], qc0[ZD], qc1[ZD], qb[ZD];
+  // rolling register window: 3x3 of three x planes, 2x2 of two cell planes
+  double W0[3][3], W1[3][3], W2[3][3], V0[2][2], V1[2][2];
+
+  // prologue: planes k0-1 and k0 and cells k0-1 go through LDS into W0, W1, V0
+  if (tid < XN) { Xs[0][tid] = ZX(xs0, k0 - 1); Xs[1][tid] = ZX(xs0, k0); }
+  if (tid + ZT < XN) { Xs[0][tid + ZT] = ZX(xs1, k0 - 1); Xs[1][tid + ZT] = ZX(xs1, k0); }
+  if (tid < CN) Cs[0][tid] = ZC(cs0, k0 - 1);
+  if (tid + ZT < CN) Cs[0][tid + ZT] = ZC(cs1, k0 - 1);
+#pragma unroll
+  for (int d = 0; d < ZD; ++d) {
+    qx0[d] = ZX(xs0, k0 + 1 + d);
+    qx1[d] = ZX(xs1, k0 + 1 + d);
+    qc0[d] = ZC(cs0, k0 + d);
+    qc1[d] = ZC(cs1, k0 + d);
+    qb[d] = ZB(k0 + d);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      W0[dy][dx] = Xs[0][xc + (dy - 1) * XW + dx - 1];
+      W1[dy][dx] = Xs[1][xc + (dy - 1) * XW + dx - 1];
+    }
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) V0[bb][a] = Cs[0][cb + bb * CW + a];
+  __syncthreads();
+
+  const bool colfix = act && i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y;
+  const double hc = g.h * (1.0 / 3.0), hf = g.h * (1.0 / 12.0);
+  double dotv = 0.0;
+
+  // One node plane kk: stage plane kk+1 and cells kk through LDS slot s, read
+  // this thread's window of them into C and CB, refill the load queue, and
+  // apply the stencil with A (plane kk-1), B (plane kk), C (plane kk+1),
+  // CA (cells below), CB (cells above).
+#define ZSTEP(A, B, C, CA, CB, s)                                                            \
+  {                                                                                          \
+    if (tid < XN) Xs[s][tid] = qx0[0];                                                       \
+    if (tid + ZT < XN) Xs[s][tid + ZT] = qx1[0];                                             \
+    if (tid < CN) Cs[s][tid] = qc0[0];                                                       \
+    if (tid + ZT < CN) Cs[s][tid + ZT] = qc1[0];                                             \
+    const double bn = qb[0];                                                                 \
+    _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
+      qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1];                                              \
+      qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
+      qb[d] = qb[d + 1];                                                                     \
+    }                                                                                        \
+    __syncthreads();                                                                         \
+    if (NEEDX) {                                                                             \
+      _Pragma("unroll") for (int dy = 0; dy < 3; ++dy)                                       \
+      _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                                       \
+        C[dy][dx] = Xs[s][xc + (dy - 1) * XW + dx - 1];                                      \
+    }                                                                                        \
+    _Pragma("unroll") for (int bb = 0; bb < 2; ++bb)                                         \
+    _Pragma("unroll") for (int a = 0; a < 2; ++a) CB[bb][a] = Cs[s][cb + bb * CW + a];       \
+    {                                                                                        \
+      const int pf = kk + ZD;                                                                \
+      const bool more = pf < k1;                                                             \
+      qx0[ZD - 1] = more ? ZX(xs0, pf + 1) : 0.0;                                            \
+      qx1[ZD - 1] = more ? ZX(xs1, pf + 1) : 0.0;                                            \
+      qc0[ZD - 1] = more ? ZC(cs0, pf) : 0.0;                                                \
+      qc1[ZD - 1] = more ? ZC(cs1, pf) : 0.0;                                                \
+      qb[ZD - 1] = more ? ZB(pf) : 0.0;                                                      \
+    }                                                                                        \
+    if (act) {                                                                               \
+      double r = 0.0;                                                                        \
+      if (!(colfix && kk >= g.f0z && kk <= g.f1z)) {                                         \
+        /* cell sums: t = below + above (centre-plane diagonals), column and */            \
+        /* row sums per plane (edge midpoints of planes kk-1 and kk+1)        */            \
+        const double t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];                 \
+        const double t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];                 \
+        const double ks = (t00 + t01) + (t10 + t11);                                       \
+        double s1 = 0.0;                                                                     \
+        if (NEEDX) {                                                                         \
+          s1 = t00 * B[0][0] + t01 * B[0][2] + t10 * B[2][0] + t11 * B[2][2];                \
+          s1 += (CA[0][0] + CA[1][0]) * A[1][0] + (CA[0][1] + CA[1][1]) * A[1][2];           \
+          s1 += (CA[0][0] + CA[0][1]) * A[0][1] + (CA[1][0] + CA[1][1]) * A[2][1];           \
+          s1 += CA[0][0] * A[0][0] + CA[0][1] * A[0][2] + CA[1][0] * A[2][0] + CA[1][1] * A[2][2]; \
+          s1 += (CB[0][0] + CB[1][0]) * C[1][0] + (CB[0][1] + CB[1][1]) * C[1][2];           \
+          s1 += (CB[0][0] + CB[0][1]) * C[0][1] + (CB[1][0] + CB[1][1]) * C[2][1];           \
+          s1 += CB[0][0] * C[0][0] + CB[0][1] * C[0][2] + CB[1][0] * C[2][0] + CB[1][1] * C[2][2]; \
+        }                                                                                    \
+        const double xcv = NEEDX ? B[1][1] : 0.0;                                            \
+        const double y = NEEDX ? (hc * ks * xcv - hf * s1) : 0.0;                            \
+        const double diag = hc * ks;                                                         \
+        if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {                                      \
+          r = y;                                                                             \
+          if (MODE == SM_APPLY_DOT) dotv += xcv * r;                                         \
+        } else if (MODE == SM_RESID) {                                                       \
+          r = bn - y;                                                                        \
+        } else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) {                             \
+          r = xcv + omega * (bn - y) / diag;                                                 \
+          if (MODE == SM_JACOBI_DOT) dotv += bn * r;                                         \
+        } else if (MODE == SM_JACOBI0) {                                                     \
+          r = omega * bn / diag;                                                             \
+        } else if (MODE == SM_NEG_DK) {                                                      \
+          r = -y;                                                                            \
+        }                                                                                    \
+      }                                                                                      \
+      out[nxy_off + pl * kk] = r;                                                            \
+    }                                                                                        \
+    ++kk;                                                                                    \
+  }
+
+  // Six steps rotate the three x windows and the two cell windows back to
+  // their starting roles, so the window never moves between registers.
+  int kk = k0;
+  while (kk + 6 <= k1) {
+    ZSTEP(W0, W1, W2, V0, V1, 0)
+    ZSTEP(W1, W2, W0, V1, V0, 1)
+    ZSTEP(W2, W0, W1, V0, V1, 0)
+    ZSTEP(W0, W1, W2, V1, V0, 1)
+    ZSTEP(W1, W2, W0, V0, V1, 0)
+    ZSTEP(W2, W0, W1, V1, V0, 1)
+  }
+  if (kk < k1) ZSTEP(W0, W1, W2, V0, V1, 0)
+  if (kk < k1) ZSTEP(W1, W2, W0, V1, V0, 1)
+  if (kk < k1) ZSTEP(W2, W0, W1, V0, V1, 0)
+  if (kk < k1) ZSTEP(W0, W1, W2, V1, V0, 1)
+  if (kk < k1) ZSTEP(W1, W2, W0, V0, V1, 0)
+#undef ZSTEP
+#undef ZX
+#undef ZC
+#undef ZB
+  if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
+    const double sum = block_sum(dotv, sh);
+    if (cnt) grid_reduce(sum, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
+    else if (threadIdx.x == 0) part[blockIdx.x] = sum;
   }
 }
 
@@ -311,6 +600,138 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, const double
   if (t == 0 && bad) status[0] = 1;
 }
 
+// Register-resident variant for n <= 128: thread (tr, tc) of a 32 x 32 layout
+// owns entries (tr + 32a, tc + 32b), a, b < 4, for the whole elimination; only
+// the pivot row and column pass through LDS. Same arithmetic as above.
+template <int DIM>
+__global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, const double* __restrict__ k,
+                                                                 double* __restrict__ A,
+                                                                 int* __restrict__ status) {
+  __shared__ double colp[128];
+  __shared__ double rowp[128];
+  const int n = (int)g.nn;
+  const int t = threadIdx.x;
+  const int tc = t & 31, tr = t >> 5;
+  // Entry (i, j) straight from the element sum: the cells shared by nodes i
+  // and j, each adding k_e KE[c_i][c_j]; identity rows/columns on Dirichlet
+  // nodes. No memory round trips.
+  int ci3[4][3], cj3[4][3];
+  bool fi[4], fj[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = min(tr + 32 * a, n - 1), j = min(tc + 32 * a, n - 1);
+    ci3[a][0] = i % g.nnx; ci3[a][1] = (i / g.nnx) % g.nny; ci3[a][2] = i / (g.nnx * g.nny);
+    cj3[a][0] = j % g.nnx; cj3[a][1] = (j / g.nnx) % g.nny; cj3[a][2] = j / (g.nnx * g.nny);
+    fi[a] = geo_fixed(g, ci3[a][0], ci3[a][1], ci3[a][2]);
+    fj[a] = geo_fixed(g, cj3[a][0], cj3[a][1], cj3[a][2]);
+  }
+  double R[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      double v = 0.0;
+      if (i < n && j < n) {
+        if (fi[a] || fj[b]) {
+          v = (i == j) ? 1.0 : 0.0;
+        } else {
+          const int dx = cj3[b][0] - ci3[a][0], dy = cj3[b][1] - ci3[a][1], dz = cj3[b][2] - ci3[a][2];
+          if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+            for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+              for (int bb = 0; bb < 2; ++bb)
+                for (int aa = 0; aa < 2; ++aa) {
+                  const int ex = ci3[a][0] - 1 + aa, ey = ci3[a][1] - 1 + bb,
+                            ez = (DIM == 3) ? ci3[a][2] - 1 + c : 0;
+                  if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+                  // j must be a corner of this cell
+                  const int bx = cj3[b][0] - ex, by = cj3[b][1] - ey, bz = (DIM == 3) ? cj3[b][2] - ez : 0;
+                  if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                  const int cci = (1 - aa) + 2 * (1 - bb) + (DIM == 3 ? 4 * (1 - c) : 0);
+                  const int ccj = bx + 2 * by + 4 * bz;
+                  v += k[geo_elem(g, ex, ey, ez)] * ke_entry<DIM>(cci, ccj, g.h);
+                }
+          }
+        }
+      }
+      R[a][b] = v;
+    }
+  int bad = 0;
+  for (int p = 0; p < n; ++p) {
+    const int pa = p >> 5, pr = p & 31;
+    if (tr == pr) {   // this thread row holds row p (at slot pa)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tc + 32 * b;
+        if (j < n) rowp[j] = (pa == 0 ? R[0][b] : pa == 1 ? R[1][b] : pa == 2 ? R[2][b] : R[3][b]);
+      }
+    }
+    if (tc == pr) {   // this thread column holds column p (at slot pa)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = tr + 32 * a;
+        if (i < n) colp[i] = (pa == 0 ? R[a][0] : pa == 1 ? R[a][1] : pa == 2 ? R[a][2] : R[a][3]);
+      }
+    }
+    __syncthreads();
+    const double piv = rowp[p];
+    if (!(piv > 0.0)) bad = 1;
+    const double inv = 1.0 / piv;
+    double rj[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = tc + 32 * b;
+      rj[b] = (j < n) ? rowp[j] * inv : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = tr + 32 * a;
+      const double ci = (i < n) ? colp[i] : 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) R[a][b] -= ci * rj[b];
+    }
+    // pivot row and column: a_pj = a_pj / a_pp, a_ip = -a_ip / a_pp, a_pp = 1 / a_pp
+    if (tr == pr) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tc + 32 * b;
+        const double v = (j == p) ? inv : rj[b];
+        if (pa == 0) R[0][b] = v; else if (pa == 1) R[1][b] = v; else if (pa == 2) R[2][b] = v; else R[3][b] = v;
+      }
+    }
+    if (tc == pr) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = tr + 32 * a;
+        if (i == p || i >= n) continue;
+        const double v = -colp[i] * inv;
+        if (pa == 0) R[a][0] = v; else if (pa == 1) R[a][1] = v; else if (pa == 2) R[a][2] = v; else R[a][3] = v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      if (i < n && j < n) A[i * n + j] = R[a][b];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      if (i < n && j < n && j > i) {
+        const double v = 0.5 * (A[i * n + j] + A[j * n + i]);
+        A[i * n + j] = v;
+        A[j * n + i] = v;
+      }
+    }
+  if (t == 0 && bad) status[0] = 1;
+}
+
 // x = A^-1 b on the coarsest grid (A symmetric: column reads are coalesced).
 __global__ __launch_bounds__(256) void k_coarse_solve(int n, const double* __restrict__ A,
                                                       const double* __restrict__ b,
@@ -334,6 +755,150 @@ __global__ __launch_bounds__(TBX* TBY) void k_mask_copy(Geo g, const double* __r
   out[n] = geo_fixed(g, i, j, k) ? 0.0 : in[n];
 }
 
+// ---------------------------------------------------------------------------
+// V-cycle tail: one workgroup runs the down-sweep, the coarsest solve and the
+// up-sweep of the bottom grids, exchanging data through LDS between steps
+// (barriers instead of kernel boundaries). Node loops are strided over the
+// 1024 threads; node coordinates are recovered by division (small grids).
+constexpr int TT = 1024;
+
+__device__ inline void tnode_ijk(const Geo& g, int n, int& i, int& j, int& k) {
+  const int pl = g.nnx * g.nny;
+  k = n / pl;
+  const int r = n - k * pl;
+  j = r / g.nnx;
+  i = r - j * g.nnx;
+}
+
+template <int DIM, int MODE>
+__device__ void tail_stencil(const Geo& g, const double* x, const double* k, const double* b,
+                             double* out, double omega) {
+  for (int n = threadIdx.x; n < (int)g.nn; n += TT) {
+    int i, j, kz;
+    tnode_ijk(g, n, i, j, kz);
+    double r = 0.0;
+    if (!geo_fixed(g, i, j, kz)) {
+      double kv[2][2][2];
+      load_cells<DIM, false>(g, k, nullptr, i, j, kz, kv);
+      double ks = 0.0, y = 0.0;
+      if (MODE == SM_JACOBI0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) ks += kv[c][bb][a];
+      } else {
+        y = node_apply<DIM>(g, x, i, j, kz, kv, ks);
+      }
+      const double diag = (DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ks;
+      if (MODE == SM_JACOBI0) r = omega * b[n] / diag;
+      else if (MODE == SM_RESID) r = b[n] - y;
+      else r = x[n] + omega * (b[n] - y) / diag;   // SM_JACOBI
+    }
+    out[n] = r;
+  }
+}
+
+template <int DIM>
+__device__ void tail_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc) {
+  for (int n = threadIdx.x; n < (int)gc.nn; n += TT) {
+    int I, J, K;
+    tnode_ijk(gc, n, I, J, K);
+    double s = 0.0;
+    if (!geo_fixed(gc, I, J, K)) {
+      for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
+        double sy = 0.0;
+        for (int b = -1; b <= 1; ++b) {
+          double sx = 0.0;
+          for (int a = -1; a <= 1; ++a) sx += (a == 0 ? 1.0 : 0.5) * ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
+          sy += (b == 0 ? 1.0 : 0.5) * sx;
+        }
+        s += (c == 0 ? 1.0 : 0.5) * sy;
+      }
+    }
+    rc[n] = s;
+  }
+}
+
+template <int DIM>
+__device__ void tail_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf) {
+  for (int n = threadIdx.x; n < (int)gf.nn; n += TT) {
+    int i, j, k;
+    tnode_ijk(gf, n, i, j, k);
+    if (geo_fixed(gf, i, j, k)) continue;
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
+    const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0,
+                 wk = (DIM == 3 && (k & 1)) ? 0.5 : 1.0;
+    double s = 0.0;
+    for (int c = 0; c < nk; ++c) {
+      double sy = 0.0;
+      for (int b = 0; b < nj; ++b) {
+        double sx = 0.0;
+        for (int a = 0; a < ni; ++a) sx += xc[geo_node(gc, I0 + a, J0 + b, K0 + c)];
+        sy += wi * sx;
+      }
+      s += wj * sy;
+    }
+    xf[n] += wk * s;
+  }
+}
+
+// x = A^-1 b with A symmetric (n <= 1024): `tpr` threads per row, each summing
+// a strided share of the columns, combined by a wave shuffle tree.
+__device__ void tail_coarse(int n, const double* __restrict__ A, const double* b, double* x) {
+  int tpr = 1;
+  while (tpr * 2 * n <= TT && tpr < 64) tpr *= 2;
+  const int row = threadIdx.x / tpr, sub = threadIdx.x % tpr;
+  double s = 0.0;
+  if (row < n)
+    for (int jj = sub; jj < n; jj += tpr) s += A[(long long)jj * n + row] * b[jj];
+  for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, MGAR_WAVE);
+  if (row < n && sub == 0) x[row] = s;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TT) void k_vtail(TailSpec T, const double* __restrict__ bin,
+                                              double* __restrict__ xout,
+                                              const double* __restrict__ Ainv, double omega,
+                                              const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ double lds[];
+  const int nl = T.nl;
+  for (int l = 0; l < nl; ++l)
+    for (int e = threadIdx.x; e < (int)T.g[l].ne; e += TT) lds[T.off_k[l] + e] = T.k[l][e];
+  for (int n = threadIdx.x; n < (int)T.g[0].nn; n += TT) lds[T.off_b[0] + n] = bin[n];
+  __syncthreads();
+  for (int l = 0; l + 1 < nl; ++l) {
+    const Geo& g = T.g[l];
+    double* b = lds + T.off_b[l];
+    double* xa = lds + T.off_xa[l];
+    double* xb = lds + T.off_xb[l];
+    const double* kk = lds + T.off_k[l];
+    tail_stencil<DIM, SM_JACOBI0>(g, nullptr, kk, b, xa, omega);
+    __syncthreads();
+    tail_stencil<DIM, SM_RESID>(g, xa, kk, b, xb, omega);
+    __syncthreads();
+    tail_restrict<DIM>(g, T.g[l + 1], xb, lds + T.off_b[l + 1]);
+    __syncthreads();
+  }
+  tail_coarse((int)T.g[nl - 1].nn, Ainv, lds + T.off_b[nl - 1], lds + T.off_xa[nl - 1]);
+  __syncthreads();
+  const double* xfin = lds + T.off_xa[nl - 1];
+  for (int l = nl - 2; l >= 0; --l) {
+    const Geo& g = T.g[l];
+    double* xa = lds + T.off_xa[l];
+    double* xb = lds + T.off_xb[l];
+    tail_prolong<DIM>(g, T.g[l + 1], xfin, xa);
+    __syncthreads();
+    tail_stencil<DIM, SM_JACOBI>(g, xa, lds + T.off_k[l], lds + T.off_b[l], xb, omega);
+    __syncthreads();
+    xfin = xb;
+  }
+  for (int n = threadIdx.x; n < (int)T.g[0].nn; n += TT) xout[n] = xfin[n];
+}
+
 dim3 node_grid(const Geo& g) {
   return dim3((g.nnx + TBX - 1) / TBX, (g.nny + TBY - 1) / TBY, g.nnz);
 }
@@ -341,32 +906,92 @@ dim3 node_grid(const Geo& g) {
 template <int DIM>
 void stencil_dispatch(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                       const double* b, double* out, double omega, double* part, const int* done,
-                      hipStream_t s) {
+                      unsigned* cnt, double* rout, hipStream_t s) {
   const dim3 grid = node_grid(g), blk(TBX, TBY, 1);
   switch (mode) {
-    case SM_APPLY: k_stencil<DIM, SM_APPLY><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_APPLY_DOT: k_stencil<DIM, SM_APPLY_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_RESID: k_stencil<DIM, SM_RESID><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_JACOBI: k_stencil<DIM, SM_JACOBI><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_JACOBI_DOT: k_stencil<DIM, SM_JACOBI_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_JACOBI0: k_stencil<DIM, SM_JACOBI0><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
-    case SM_NEG_DK: k_stencil<DIM, SM_NEG_DK><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done); break;
+    case SM_APPLY: k_stencil<DIM, SM_APPLY><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_APPLY_DOT: k_stencil<DIM, SM_APPLY_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_RESID: k_stencil<DIM, SM_RESID><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_JACOBI: k_stencil<DIM, SM_JACOBI><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_JACOBI_DOT: k_stencil<DIM, SM_JACOBI_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_JACOBI0: k_stencil<DIM, SM_JACOBI0><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_NEG_DK: k_stencil<DIM, SM_NEG_DK><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
   }
+}
+
+constexpr int ZMARCH_MIN_NODES = 20000;
+constexpr int ZKZ = 12;   // z-planes per block (swept: 4..32; 12 is best at 129^3)
+
+bool use_zmarch(const Geo& g) { return g.dim == 3 && g.nn >= ZMARCH_MIN_NODES; }
+
+struct ZShape { int TXW, TYH, ntx, nty, nzc; };
+
+ZShape zmarch_shape(const Geo& g) {
+  ZShape z;
+  z.ntx = (g.nnx + 63) / 64;
+  z.TXW = (g.nnx + z.ntx - 1) / z.ntx;
+  int tyh = ZT / z.TXW;
+  tyh = std::min(tyh, XCAP / (z.TXW + 2) - 2);
+  tyh = std::min(tyh, CCAP / (z.TXW + 1) - 1);
+  z.TYH = std::max(tyh, 1);
+  z.nty = (g.nny + z.TYH - 1) / z.TYH;
+  z.nzc = (g.nnz + ZKZ - 1) / ZKZ;
+  return z;
+}
+
+void zmarch_dispatch(const Geo& g, const Geo* gc, int mode, const double* x, const double* ec,
+                     const double* k, const double* kref, const double* b, double* out,
+                     double omega, double* part, const int* done, unsigned* cnt, double* rout,
+                     hipStream_t s) {
+  const ZShape z = zmarch_shape(g);
+  const int nb = z.ntx * z.nty * z.nzc;
+  const Geo gcc = gc ? *gc : g;
+#define ZCALL(M, XPOL) k_stencil_z<M, XPOL><<<nb, ZT, 0, s>>>(g, gcc, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out, omega, part, done, cnt, rout)
+  if (gc) {
+    if (mode == SM_JACOBI) ZCALL(SM_JACOBI, XP_PROLONG);
+    else ZCALL(SM_JACOBI_DOT, XP_PROLONG);
+    return;
+  }
+  switch (mode) {
+    case SM_APPLY: ZCALL(SM_APPLY, XP_PLAIN); break;
+    case SM_APPLY_DOT: ZCALL(SM_APPLY_DOT, XP_PLAIN); break;
+    case SM_RESID: ZCALL(SM_RESID, XP_PLAIN); break;
+    case SM_JACOBI: ZCALL(SM_JACOBI, XP_PLAIN); break;
+    case SM_JACOBI_DOT: ZCALL(SM_JACOBI_DOT, XP_PLAIN); break;
+    case SM_JACOBI0: ZCALL(SM_JACOBI0, XP_PLAIN); break;
+    case SM_NEG_DK: ZCALL(SM_NEG_DK, XP_PLAIN); break;
+  }
+#undef ZCALL
 }
 
 }  // namespace
 
 int stencil_num_partials(const Geo& g) {
+  if (use_zmarch(g)) {
+    const ZShape z = zmarch_shape(g);
+    return z.ntx * z.nty * z.nzc;
+  }
   const dim3 grid = node_grid(g);
   return (int)(grid.x * grid.y * grid.z);
 }
 
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s) {
-  if (g.dim == 2) stencil_dispatch<2>(g, mode, x, k, kref, b, out, omega, part, done, s);
-  else stencil_dispatch<3>(g, mode, x, k, kref, b, out, omega, part, done, s);
+                   hipStream_t s, unsigned* cnt, double* rout) {
+  if (use_zmarch(g)) zmarch_dispatch(g, nullptr, mode, x, nullptr, k, kref, b, out, omega, part, done, cnt, rout, s);
+  else if (g.dim == 2) stencil_dispatch<2>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
+  else stencil_dispatch<3>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
   return (mode == SM_APPLY_DOT || mode == SM_JACOBI_DOT) ? stencil_num_partials(g) : 0;
+}
+
+bool stencil_fuses_prolong(const Geo& g) { return use_zmarch(g); }
+
+int launch_prolong_smooth(const Geo& g, const Geo& gc, const double* xa, const double* ec,
+                          const double* k, const double* b, double* out, double omega,
+                          double* part, const int* done, hipStream_t s) {
+  zmarch_dispatch(g, &gc, part ? SM_JACOBI_DOT : SM_JACOBI, xa, ec, k, nullptr, b, out, omega, part,
+                  done, nullptr, nullptr, s);
+  return part ? stencil_num_partials(g) : 0;
 }
 
 void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
@@ -390,14 +1015,44 @@ void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, 
 }
 
 void launch_coarse_build(const Geo& g, const double* k, double* A, int* status, hipStream_t s) {
-  if (g.dim == 2) k_coarse_build<2><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
-  else k_coarse_build<3><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+  if (g.nn <= 128) {
+    if (g.dim == 2) k_coarse_build_reg<2><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    else k_coarse_build_reg<3><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+  } else {
+    if (g.dim == 2) k_coarse_build<2><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    else k_coarse_build<3><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+  }
 }
 
 void launch_coarse_solve(const Geo& g, const double* A, const double* b, double* x,
                          const int* done, hipStream_t s) {
   const int n = (int)g.nn;
   k_coarse_solve<<<(n + 255) / 256, 256, 0, s>>>(n, A, b, x, done);
+}
+
+bool tail_plan(const Geo* g, double* const* k, int lt, int L, TailSpec* T) {
+  const int nl = L - lt;
+  if (nl < 1 || nl > MGAR_MAX_TAIL) return false;
+  int off = 0;
+  for (int l = 0; l < nl; ++l) {
+    const Geo& gl = g[lt + l];
+    T->g[l] = gl;
+    T->k[l] = k[lt + l];
+    T->off_b[l] = off; off += (int)gl.nn;
+    T->off_xa[l] = off; off += (int)gl.nn;
+    T->off_xb[l] = off; off += (int)gl.nn;
+    T->off_k[l] = off; off += (int)gl.ne;
+  }
+  T->nl = nl;
+  T->lds_doubles = off;
+  return off * 8 <= 64 * 1024 && g[lt].nn <= 4096;
+}
+
+void launch_vtail(const TailSpec& T, const double* b_in, double* x_out, const double* Ainv,
+                  double omega, const int* done, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)T.lds_doubles;
+  if (T.g[0].dim == 2) k_vtail<2><<<1, TT, lds, s>>>(T, b_in, x_out, Ainv, omega, done);
+  else k_vtail<3><<<1, TT, lds, s>>>(T, b_in, x_out, Ainv, omega, done);
 }
 
 void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s) {

@@ -132,31 +132,53 @@ __global__ __launch_bounds__(TBX* TBY) void k_sens(Geo g, const double* __restri
 }
 
 // ------------------------------------------------------------------- OC
-// Speculative bisection: one pass evaluates the filtered volume at the
-// OC_NCAND midpoints of the next OC_DEPTH bisection levels; a single-thread walk
-// then replays the bisection decisions exactly in order.
+// Bisection on lambda in [0, 1e9] until (l2-l1)/(l1+l2) <= tol, deciding each
+// midpoint m by S(m) > target, with S(lambda) = sum_e dv_e x_new_e(lambda)
+// non-increasing in lambda. Each pass evaluates S at OC_NCAND candidates in the
+// still-undecided range; a single-thread walk then replays the bisection
+// midpoints in order, deciding each one from the evaluated bracket, until a
+// midpoint falls inside it. The midpoints, and so lam_last, are the same
+// floating-point values a plain bisection computes.
+// Candidate placement: geometric while the range spans more than a factor 64;
+// otherwise 7 points evenly over the range plus 8 points clustered around a
+// secant estimate in u = lambda^-1/2 (S is close to affine in u, since unclamped
+// elements contribute dv x sqrt(B) u).
 
-__device__ void oc_fill_candidates(OcDev* oc) {
-  double lo[OC_NCAND], hi[OC_NCAND];
-  lo[0] = oc->l1;
-  hi[0] = oc->l2;
-  for (int n = 0; n < OC_NCAND; ++n) {
-    const double m = 0.5 * (hi[n] + lo[n]);
-    oc->cand[n] = m;
-    if (2 * n + 2 < OC_NCAND) {
-      lo[2 * n + 1] = m; hi[2 * n + 1] = hi[n];   // volume too large: l1 = mid
-      lo[2 * n + 2] = lo[n]; hi[2 * n + 2] = m;   // otherwise: l2 = mid
-    }
+__device__ void oc_fill_candidates(OcDev* oc, double target) {
+  double a = fmax(oc->l1, oc->lo_known);
+  const double b = fmin(oc->l2, oc->hi_known);
+  if (a <= 0.0 || b > 64.0 * a) {
+    if (a <= 0.0) a = b * 1e-40;
+    const double r = log(b / a) / (OC_NCAND + 1);
+    for (int t = 0; t < OC_NCAND; ++t) oc->cand[t] = a * exp(r * (t + 1));
+    return;
+  }
+  constexpr int NLIN = 7;
+  for (int t = 0; t < NLIN; ++t) oc->cand[t] = a + (b - a) * (t + 1) / (NLIN + 1);
+  double est = 0.5 * (a + b);
+  if (oc->lo_known > 0.0 && oc->hi_known < INFINITY && oc->s_lo > oc->s_hi) {
+    const double ul = 1.0 / sqrt(oc->lo_known), uh = 1.0 / sqrt(oc->hi_known);
+    const double u = uh + (target - oc->s_hi) * (ul - uh) / (oc->s_lo - oc->s_hi);
+    if (u > 0.0) est = fmin(b, fmax(a, 1.0 / (u * u)));
+  }
+  const double d = (b - a) / ((b - a > 0.01 * a) ? 128.0 : 16384.0);
+  for (int t = NLIN; t < OC_NCAND; ++t) {
+    const double c = est + d * (t - NLIN - 3.5);
+    oc->cand[t] = fmin(b, fmax(a, c));
   }
 }
 
-__global__ void k_oc_init(OcDev* oc) {
+__global__ void k_oc_init(OcDev* oc, double target) {
   oc->l1 = 0.0;
   oc->l2 = 1e9;
   oc->lam_last = 0.5e9;
+  oc->lo_known = 0.0;
+  oc->hi_known = INFINITY;
+  oc->s_lo = 0.0;
+  oc->s_hi = 0.0;
   oc->done = 0;
   oc->steps = 0;
-  oc_fill_candidates(oc);
+  oc_fill_candidates(oc, target);
 }
 
 __global__ __launch_bounds__(VB) void k_oc_pass(const double* __restrict__ x,
@@ -197,30 +219,39 @@ __global__ __launch_bounds__(VB) void k_oc_pass(const double* __restrict__ x,
 __global__ __launch_bounds__(FB) void k_oc_walk(OcDev* oc, const double* __restrict__ part, int np,
                                                 double target, double tol) {
   if (oc->done) return;
-  __shared__ double sh[FB / MGAR_WAVE];
   __shared__ double S[OC_NCAND];
-  for (int t = 0; t < OC_NCAND; ++t) {
+  const int lane = threadIdx.x & (MGAR_WAVE - 1), wv = threadIdx.x / MGAR_WAVE;
+  for (int t = wv; t < OC_NCAND; t += FB / MGAR_WAVE) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < np; b += FB) v += part[b * OC_NCAND + t];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) S[t] = v;
+    for (int b = lane; b < np; b += MGAR_WAVE) v += part[b * OC_NCAND + t];
+    v = wave_sum(v);
+    if (lane == 0) S[t] = v;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double l1 = oc->l1, l2 = oc->l2;
-  int node = 0, done = 0, steps = oc->steps;
-  double last = oc->lam_last;
-  for (int lev = 0; lev < OC_DEPTH; ++lev) {
-    if (!((l2 - l1) / (l1 + l2) > tol)) { done = 1; break; }
-    const double lmid = oc->cand[node];
-    last = lmid;
-    ++steps;
-    if (S[node] > target) { l1 = lmid; node = 2 * node + 1; }
-    else { l2 = lmid; node = 2 * node + 2; }
+  double lo = oc->lo_known, hi = oc->hi_known, slo = oc->s_lo, shi = oc->s_hi;
+  for (int t = 0; t < OC_NCAND; ++t) {
+    const double c = oc->cand[t];
+    if (S[t] > target) {
+      if (c > lo) { lo = c; slo = S[t]; }
+    } else if (c < hi) {
+      hi = c; shi = S[t];
+    }
   }
-  if (!done && !((l2 - l1) / (l1 + l2) > tol)) done = 1;
-  oc->l1 = l1; oc->l2 = l2; oc->lam_last = last; oc->steps = steps; oc->done = done;
-  if (!done) oc_fill_candidates(oc);
+  double l1 = oc->l1, l2 = oc->l2, last = oc->lam_last;
+  int steps = oc->steps, done = 0;
+  for (;;) {
+    if (!((l2 - l1) / (l1 + l2) > tol)) { done = 1; break; }
+    const double m = 0.5 * (l2 + l1);
+    if (m <= lo) l1 = m;
+    else if (m >= hi) l2 = m;
+    else break;
+    last = m;
+    ++steps;
+  }
+  oc->l1 = l1; oc->l2 = l2; oc->lam_last = last; oc->steps = steps;
+  oc->lo_known = lo; oc->hi_known = hi; oc->s_lo = slo; oc->s_hi = shi; oc->done = done;
+  if (!done) oc_fill_candidates(oc, target);
 }
 
 __global__ __launch_bounds__(VB) void k_oc_final(const double* __restrict__ x,
@@ -267,7 +298,7 @@ void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const 
     k_sens<3><<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, xphys, T, invHs, k0, kmin, penal, gout);
 }
 
-void launch_oc_init(OcDev* oc, hipStream_t s) { k_oc_init<<<1, 1, 0, s>>>(oc); }
+void launch_oc_init(OcDev* oc, double target, hipStream_t s) { k_oc_init<<<1, 1, 0, s>>>(oc, target); }
 
 int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
                    const OcDev* oc, double* part, hipStream_t s) {

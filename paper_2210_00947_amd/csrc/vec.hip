@@ -15,14 +15,16 @@ constexpr int FB = 1024;         // finalize block size
 __global__ __launch_bounds__(VB) void k_dot(const double* __restrict__ a,
                                             const double* __restrict__ b, long long n,
                                             double* __restrict__ part,
-                                            const int* __restrict__ done) {
+                                            const int* __restrict__ done,
+                                            unsigned* __restrict__ cnt, double* __restrict__ rout) {
   if (done && *done) return;
   __shared__ double sh[VB / MGAR_WAVE];
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     s += a[i] * b[i];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (cnt) grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
+  else if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 __device__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
@@ -40,30 +42,17 @@ __global__ __launch_bounds__(FB) void k_finalize(const double* __restrict__ part
   if (threadIdx.x == 0) *out = s;
 }
 
-// Stopping test before iteration `it` (||r|| <= tol ||q|| or it == cg_max).
-__global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __restrict__ part,
-                                                 int np, int it, double tol, int cg_max) {
-  if (st->done) return;
-  __shared__ double sh[FB / MGAR_WAVE];
-  const double rr = sum_partials(part, np, sh);
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    if (sqrt(rr) <= tol * sqrt(st->qq)) {
-      st->done = 1; st->converged = 1; st->iters = it;
-    } else if (it >= cg_max) {
-      st->done = 1; st->converged = 0; st->iters = it;
-    }
-  }
-}
-
 __global__ __launch_bounds__(FB) void k_cg_init(CgState* st, const double* __restrict__ pq, int nq,
-                                                const double* __restrict__ pr, int nr) {
+                                                const double* __restrict__ pr, int nr, double tol,
+                                                int cg_max) {
   __shared__ double sh[FB / MGAR_WAVE];
   const double qq = sum_partials(pq, nq, sh);
   const double rr = sum_partials(pr, nr, sh);
   if (threadIdx.x == 0) {
     st->qq = qq; st->rr = rr; st->rz[0] = st->rz[1] = 0.0; st->pw = 0.0;
     st->done = 0; st->iters = 0; st->converged = 0;
+    if (sqrt(rr) <= tol * sqrt(qq)) { st->done = 1; st->converged = 1; }
+    else if (cg_max <= 0) { st->done = 1; }
   }
 }
 
@@ -77,12 +66,16 @@ __global__ __launch_bounds__(VB) void k_p_update(const double* __restrict__ z, d
     p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
 }
 
-// x += alpha p, r -= alpha w, partial ||r||^2, alpha = rz / (p . w).
+// x += alpha p, r -= alpha w with alpha = rz / (p . w); ||r||^2 reduced in
+// the same launch, and the last block applies the stopping test that precedes
+// iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max).
 __global__ __launch_bounds__(VB) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p,
                                                   const double* __restrict__ w, long long n,
-                                                  const CgState* __restrict__ st, int it,
-                                                  double* __restrict__ part) {
+                                                  CgState* __restrict__ st, int it,
+                                                  double* __restrict__ part,
+                                                  unsigned* __restrict__ cnt, double tol,
+                                                  int cg_max) {
   if (st->done) return;
   __shared__ double sh[VB / MGAR_WAVE];
   const double alpha = st->rz[it & 1] / st->pw;
@@ -94,7 +87,36 @@ __global__ __launch_bounds__(VB) void k_cg_update(double* __restrict__ x, double
     s += ri * ri;
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (!cnt) {
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    return;
+  }
+  double rr = 0.0;
+  if (grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, nullptr, sh, &rr) && threadIdx.x == 0) {
+    st->rr = rr;
+    if (sqrt(rr) <= tol * sqrt(st->qq)) {
+      st->done = 1; st->converged = 1; st->iters = it + 1;
+    } else if (it + 1 >= cg_max) {
+      st->done = 1; st->converged = 0; st->iters = it + 1;
+    }
+  }
+}
+
+// Stopping test before iteration `it` from the ||r||^2 partials of the last
+// update (||r|| <= tol ||q||, or it == cg_max).
+__global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __restrict__ part,
+                                                 int np, int it, double tol, int cg_max) {
+  if (st->done) return;
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double rr = sum_partials(part, np, sh);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    if (sqrt(rr) <= tol * sqrt(st->qq)) {
+      st->done = 1; st->converged = 1; st->iters = it;
+    } else if (it >= cg_max) {
+      st->done = 1; st->converged = 0; st->iters = it;
+    }
+  }
 }
 
 __global__ __launch_bounds__(VB) void k_copy(const double* __restrict__ a, double* __restrict__ b,
@@ -326,9 +348,9 @@ int vec_num_blocks(long long n) {
 }
 
 int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
-               hipStream_t s) {
+               hipStream_t s, unsigned* cnt, double* rout) {
   const int nb = vec_num_blocks(n);
-  k_dot<<<nb, VB, 0, s>>>(a, b, n, part, done);
+  k_dot<<<nb, VB, 0, s>>>(a, b, n, part, done, cnt, rout);
   return nb;
 }
 
@@ -342,8 +364,8 @@ void launch_cg_check(CgState* st, const double* part, int np, int it, double tol
 }
 
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
-                    hipStream_t s) {
-  k_cg_init<<<1, FB, 0, s>>>(st, part_qq, nq, part_rr, nr);
+                    double tol, int cg_max, hipStream_t s) {
+  k_cg_init<<<1, FB, 0, s>>>(st, part_qq, nq, part_rr, nr, tol, cg_max);
 }
 
 void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
@@ -352,9 +374,10 @@ void launch_p_update(const double* z, double* p, long long n, const CgState* st,
 }
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     const CgState* st, int it, double* part, hipStream_t s) {
+                     CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
+                     hipStream_t s) {
   const int nb = vec_num_blocks(n);
-  k_cg_update<<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part);
+  k_cg_update<<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part, cnt, tol, cg_max);
   return nb;
 }
 

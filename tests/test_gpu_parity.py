@@ -18,6 +18,8 @@ PROBS = [
     W.tiny_2d(48, 32, 4),
     W.tiny_3d(16, 16, 16, 3),
     W.tiny_3d(16, 16, 24, 4),
+    W.tiny_3d(32, 32, 32, 4),      # finest grid above the z-marching threshold
+    W.tiny_3d(48, 32, 16, 3),      # non-cubic, z-marching on the finest grid
 ]
 IDS = [p.name for p in PROBS]
 

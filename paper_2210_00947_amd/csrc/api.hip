@@ -161,20 +161,25 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
                double* rout = nullptr) {
   const Geo& g = h->lv[level].g;
   const bool timed = level == 0 && (h->prof_mask >> mode) & 1u;
-  if (timed) {
-    if (h->prof_used + 2 > h->prof_ev.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        HIPCK(hipEventCreate(&e));
-        h->prof_ev.push_back(e);
-      }
+  if (timed && h->prof_used + 2 > h->prof_ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      HIPCK(hipEventCreate(&e));
+      h->prof_ev.push_back(e);
     }
-    HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
   }
-  const int np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout);
+  int np;
+  if (timed && stencil_records_events(g)) {
+    // events recorded by the launch itself at kernel start and end
+    np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout,
+                        h->prof_ev[h->prof_used], h->prof_ev[h->prof_used + 1]);
+  } else {
+    if (timed) HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
+    np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout);
+    if (timed) HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
+  }
   if (nparts) *nparts = np;
   if (timed) {
-    HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
     h->prof_bytes.push_back(stencil_bytes(g, mode));
     h->prof_tag.push_back(tag);
     h->prof_used += 2;

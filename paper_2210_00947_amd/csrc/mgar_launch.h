@@ -17,9 +17,12 @@ enum StencilMode {
 // Returns the number of block partials written to `part` (0 for modes without a
 // dot). With cnt != null the dot is also reduced in the same launch (last block
 // sums the partials in order) and stored to *rout.
+// ev0/ev1 (z-marching grids only): events recorded at kernel start and end.
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr);
+                   hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+bool stencil_records_events(const Geo& g);
 int stencil_num_partials(const Geo& g);
 void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
                      hipStream_t s);

@@ -13,6 +13,8 @@
 // cells outside the grid, whose conductivity is taken as 0.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "mgar_launch.h"
 
 namespace {
@@ -942,11 +944,22 @@ ZShape zmarch_shape(const Geo& g) {
 void zmarch_dispatch(const Geo& g, const Geo* gc, int mode, const double* x, const double* ec,
                      const double* k, const double* kref, const double* b, double* out,
                      double omega, double* part, const int* done, unsigned* cnt, double* rout,
-                     hipStream_t s) {
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const ZShape z = zmarch_shape(g);
   const int nb = z.ntx * z.nty * z.nzc;
   const Geo gcc = gc ? *gc : g;
-#define ZCALL(M, XPOL) k_stencil_z<M, XPOL><<<nb, ZT, 0, s>>>(g, gcc, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out, omega, part, done, cnt, rout)
+  // With events, the launch goes through hipExtLaunchKernelGGL, which records
+  // them at the start and end of the kernel itself (no dispatch latency).
+#define ZCALL(M, XPOL)                                                                          \
+  do {                                                                                          \
+    if (ev0)                                                                                    \
+      hipExtLaunchKernelGGL((k_stencil_z<M, XPOL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, gcc, \
+                            z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out, omega, part, \
+                            done, cnt, rout);                                                   \
+    else                                                                                        \
+      k_stencil_z<M, XPOL><<<nb, ZT, 0, s>>>(g, gcc, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, \
+                                             b, out, omega, part, done, cnt, rout);            \
+  } while (0)
   if (gc) {
     if (mode == SM_JACOBI) ZCALL(SM_JACOBI, XP_PROLONG);
     else ZCALL(SM_JACOBI_DOT, XP_PROLONG);
@@ -977,14 +990,15 @@ int stencil_num_partials(const Geo& g) {
 
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s, unsigned* cnt, double* rout) {
-  if (use_zmarch(g)) zmarch_dispatch(g, nullptr, mode, x, nullptr, k, kref, b, out, omega, part, done, cnt, rout, s);
+                   hipStream_t s, unsigned* cnt, double* rout, hipEvent_t ev0, hipEvent_t ev1) {
+  if (use_zmarch(g)) zmarch_dispatch(g, nullptr, mode, x, nullptr, k, kref, b, out, omega, part, done, cnt, rout, s, ev0, ev1);
   else if (g.dim == 2) stencil_dispatch<2>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
   else stencil_dispatch<3>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
   return (mode == SM_APPLY_DOT || mode == SM_JACOBI_DOT) ? stencil_num_partials(g) : 0;
 }
 
 bool stencil_fuses_prolong(const Geo& g) { return use_zmarch(g); }
+bool stencil_records_events(const Geo& g) { return use_zmarch(g); }
 
 int launch_prolong_smooth(const Geo& g, const Geo& gc, const double* xa, const double* ec,
                           const double* k, const double* b, double* out, double omega,

@@ -12,6 +12,10 @@ Prints one JSON line:
   value          DOF-solves/s of the MGAR loop (free DOFs x solves / second)
   ms_per_step    MGAR loop, milliseconds per optimisation cycle
   mgcg           the same figures for the plain-MGCG loop on the same GPU
+  mgar_mixed     the MGAR loop in the mixed-precision form (FP32 multigrid and
+                 inner PCG over BF16 densities inside FP64 iterative refinement,
+                 same 1e-8 FP64 residual test); reported beside value, which
+                 stays the all-FP64 loop
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events around each
                  launch in the timed region, against 8 TB/s
@@ -38,8 +42,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch):
-    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar)
+def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0):
+    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision)
     for _ in range(warmup):
         opt.step()
     opt.h.mgar_profile(1 << ROOF_MODE)
@@ -59,6 +63,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch):
         "elapsed_s": el,
         "s_per_opt_iter": el / steps,
         "cg_iters_mean": sum(r.cg_iters for r in recs) / steps,
+        "refinements_mean": sum(r.refinements for r in recs) / steps,
         "paths": paths,
         "final_compliance": recs[-1].compliance,
         "kernel_launches": n,
@@ -118,6 +123,8 @@ def main():
     ap.add_argument("--config", default="c3", help="workload: c0, c1, c2 or c3 (default 128^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -142,6 +149,10 @@ def main():
     if not args.no_mgcg:
         mgcg = run_loop(prob, False, args.warmup, args.steps, W, TopOpt, torch)
         log(f"[bench] MGCG loop: {mgcg['s_per_opt_iter']*1e3:.3f} ms/cycle")
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED)
+        log(f"[bench] mixed-precision MGAR loop: {mixed['s_per_opt_iter']*1e3:.3f} ms/cycle")
     value = free * args.steps / mg_ar["elapsed_s"]
     roof = None
     if mg_ar["kernel_launches"] > 0:
@@ -176,11 +187,14 @@ def main():
                                 f"cycles {args.warmup + 1}..{args.warmup + args.steps}"),
                    "nodes": prob.nnodes, "free_dofs": free, "levels": prob.levels},
         "s_per_opt_iter": {"mgar": mg_ar["s_per_opt_iter"],
-                           "mgcg": mgcg["s_per_opt_iter"] if mgcg else None},
+                           "mgcg": mgcg["s_per_opt_iter"] if mgcg else None,
+                           "mgar_mixed": mixed["s_per_opt_iter"] if mixed else None},
         "dof_solves_per_s": {"mgar": value,
-                             "mgcg": free * args.steps / mgcg["elapsed_s"] if mgcg else None},
+                             "mgcg": free * args.steps / mgcg["elapsed_s"] if mgcg else None,
+                             "mgar_mixed": free * args.steps / mixed["elapsed_s"] if mixed else None},
         "mgar": mg_ar,
         "mgcg": mgcg,
+        "mgar_mixed": mixed,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -71,6 +71,8 @@ typedef struct {
   int basis_x0_zero;      /* 0: V-cycle initial guess r_{i-1} as printed in Eq 17; 1: zero */
   int precision;          /* MGAR_PREC_FP64 or MGAR_PREC_MIXED */
   double filter_r;        /* cone density-filter radius, Eq 7-8 (element lengths) */
+  double inner_tol;       /* MGAR_PREC_MIXED: each inner FP32 PCG solve stops once its
+                           * residual has dropped by this factor (0 < inner_tol < 1) */
 } mgar_params;
 
 /* Per-solve report. */
@@ -159,6 +161,9 @@ int mgar_build_hierarchy(mgar_handle* h, const double* xphys);
 int mgar_vcycle(mgar_handle* h, const double* b, const double* x0, double* x);
 /* b = -(K(xphys) - K0) r: the right-hand side of Eq 15/17. */
 int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b);
+/* Densities as stored by the mixed-precision mode: out[e] = BF16 bits of x[e],
+ * rounded to nearest even through FP32. out: E uint16 values (device). */
+int mgar_op_bf16(mgar_handle* h, const double* x, void* out);
 
 /* ---- Instrumentation. ------------------------------------------------------
  * Kernel timing for roofline reports: while enabled, every launch of a

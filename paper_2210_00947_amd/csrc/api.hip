@@ -50,6 +50,17 @@ struct mgar_handle {
   bool has_k0 = false;
   int lt = 1;                             // first grid handled by the V-cycle tail kernel
   TailSpec tail;
+  // mixed precision: FP32 multigrid and inner PCG over BF16 densities
+  bool mixed = false;
+  uint16_t* dens = nullptr;               // BF16 physical densities of the current call
+  uint16_t* dens0 = nullptr;              // BF16 densities of K0 (finest grid of the FP32 hierarchy)
+  std::vector<float*> kf, bf, xaf, xbf;   // FP32 hierarchy: cells (grids >= 1) and vectors
+  float *rtmpf = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *w32 = nullptr,
+        *d32 = nullptr;
+  int ltf = 1;
+  TailSpec tailf;
+  float kmin_f = 0.f, kdiff_f = 0.f;
+  int refine_max = 40;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // kernel timing (instrumentation)
   unsigned prof_mask = 0;
@@ -124,7 +135,9 @@ int validate(const mgar_params* p) {
   if (p->n_basis < 1 || p->n_basis > MGAR_MAX_BASIS) return MGAR_E_ARG;
   if (!(p->omega > 0.0) || !(p->filter_r > 0.0) || p->cg_max < 0) return MGAR_E_ARG;
   if (!(p->k0 > 0.0) || !(p->kmin > 0.0) || !(p->penal >= 1.0)) return MGAR_E_ARG;
-  if (p->precision != MGAR_PREC_FP64) return MGAR_E_PRECISION;
+  if (p->precision != MGAR_PREC_FP64 && p->precision != MGAR_PREC_MIXED) return MGAR_E_PRECISION;
+  if (p->precision == MGAR_PREC_MIXED && p->penal != 3.0) return MGAR_E_PRECISION;
+  if (p->precision == MGAR_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return MGAR_E_ARG;
   if ((int)std::ceil(p->filter_r) > 6) return MGAR_E_ARG;
   const int s = 1 << (p->levels - 1);
   if (p->nelx % s || p->nely % s || (p->dim == 3 && p->nelz % s)) return MGAR_E_DIMS;
@@ -188,35 +201,6 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
   return MGAR_OK;
 }
 
-// Fused interpolation + post-smoother on grid `level` (profiled like the
-// Jacobi modes; its algorithmic bytes add the coarse correction read).
-int prolong_smooth_at(mgar_handle* h, int level, const double* xa, const double* ec, const double* b,
-                      double* out, double* part, const int* done, int tag) {
-  const Geo& g = h->lv[level].g;
-  const int mode = part ? SM_JACOBI_DOT : SM_JACOBI;
-  const bool timed = level == 0 && (h->prof_mask >> mode) & 1u;
-  if (timed) {
-    if (h->prof_used + 2 > h->prof_ev.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        HIPCK(hipEventCreate(&e));
-        h->prof_ev.push_back(e);
-      }
-    }
-    HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
-  }
-  launch_prolong_smooth(g, h->lv[level + 1].g, xa, ec, h->lv[level].k, b, out, h->p.omega, part, done,
-                        h->s);
-  if (timed) {
-    HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
-    h->prof_bytes.push_back(stencil_bytes(g, mode) + 8.0 * (double)h->lv[level + 1].g.nn);
-    h->prof_tag.push_back(tag);
-    h->prof_used += 2;
-  }
-  LAUNCHCK();
-  return MGAR_OK;
-}
-
 // Accumulate the recorded event pairs (the stream must be idle). Pairs tagged
 // with a CG iteration at or beyond `cutoff` belong to iterations that were
 // enqueued after the stopping test fired; their kernels returned at once, so
@@ -266,16 +250,145 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
     const double* b = (l == 0) ? b0 : v.b;
     double* o = (l == 0) ? out : v.xb;
     double* dp = (l == 0) ? dot_part : nullptr;
-    if (false && stencil_fuses_prolong(v.g)) {
-      ACK(prolong_smooth_at(h, l, v.xa, xfin, b, o, dp, done, tag));
-    } else {
-      launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
-      ACK(stencil_at(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w, dp, done,
-                     nullptr, tag, dp ? dcnt : nullptr, dp ? dout : nullptr));
-    }
+    launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
+    ACK(stencil_at(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w, dp, done,
+                   nullptr, tag, dp ? dcnt : nullptr, dp ? dout : nullptr));
     xfin = o;
   }
   LAUNCHCK();
+  return MGAR_OK;
+}
+
+// ---------------------------------------------------------------- mixed precision
+// FP32 stencil on grid `level` of the BF16/FP32 hierarchy: the finest grid reads
+// BF16 densities (SIMP applied on load), coarser grids FP32 cell conductivities.
+int stencil32(mgar_handle* h, int level, int mode, const float* x, const float* b, float* out,
+              double* part, const int* done, const uint16_t* dens = nullptr,
+              const uint16_t* densref = nullptr) {
+  const Geo& g = h->lv[level].g;
+  if (level == 0) {
+    const CellB k{dens ? dens : h->dens0, h->kmin_f, h->kdiff_f};
+    const CellB kr{densref ? densref : h->dens0, h->kmin_f, h->kdiff_f};
+    launch_stencil_t<float, CellB>(g, mode, x, k, kr, b, out, h->p.omega, part, done, h->s);
+  } else {
+    const CellF k{h->kf[level]};
+    launch_stencil_t<float, CellF>(g, mode, x, k, k, b, out, h->p.omega, part, done, h->s);
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// K0 := K(BF16 densities of `dens`): cell means of every coarser grid in FP32
+// and the coarsest inverse in FP64.
+int build_hierarchy32(mgar_handle* h) {
+  const int L = h->L;
+  launch_copy_u16(h->dens, h->dens0, h->E, h->s);
+  const CellB k0{h->dens0, h->kmin_f, h->kdiff_f};
+  if (L >= 2) launch_coarsen_t<CellB, float>(h->lv[0].g, h->lv[1].g, k0, h->kf[1], h->s);
+  for (int l = 2; l < L; ++l)
+    launch_coarsen_t<CellF, float>(h->lv[l - 1].g, h->lv[l].g, CellF{h->kf[l - 1]}, h->kf[l], h->s);
+  HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->s));
+  if (L == 1) launch_coarse_build_t<CellB>(h->lv[0].g, k0, h->Ainv, h->dstatus, h->s);
+  else launch_coarse_build_t<CellF>(h->lv[L - 1].g, CellF{h->kf[L - 1]}, h->Ainv, h->dstatus, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// One FP32 V-cycle on the BF16/FP32 K0 hierarchy (same sequence as vcycle()).
+int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, double* dot_part,
+             const int* done) {
+  const int L = h->L;
+  if (L == 1) {
+    launch_coarse_solve_t<float>(h->lv[0].g, h->Ainv, b0, out, done, h->s);
+    if (dot_part) launch_dot_t<float, float>(b0, out, h->N, dot_part, done, h->s);
+    LAUNCHCK();
+    return MGAR_OK;
+  }
+  const int lt = h->ltf;
+  for (int l = 0; l < lt; ++l) {
+    const float* b = (l == 0) ? b0 : h->bf[l];
+    if (l == 0 && x0) ACK(stencil32(h, l, SM_JACOBI, x0, b, h->xaf[l], nullptr, done));
+    else ACK(stencil32(h, l, SM_JACOBI0, nullptr, b, h->xaf[l], nullptr, done));
+    ACK(stencil32(h, l, SM_RESID, h->xaf[l], b, h->rtmpf, nullptr, done));
+    launch_restrict_t<float>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf, h->bf[l + 1], done, h->s);
+  }
+  launch_vtail_t<float>(h->tailf, h->bf[lt], h->xbf[lt], h->Ainv, h->p.omega, done, h->s);
+  const float* xfin = h->xbf[lt];
+  for (int l = lt - 1; l >= 0; --l) {
+    const float* b = (l == 0) ? b0 : h->bf[l];
+    launch_prolong_t<float>(h->lv[l].g, h->lv[l + 1].g, xfin, h->xaf[l], done, h->s);
+    float* o = (l == 0) ? out : h->xbf[l];
+    double* dp = (l == 0) ? dot_part : nullptr;
+    ACK(stencil32(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, h->xaf[l], b, o, dp, done));
+    xfin = o;
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// Inner FP32 PCG: solve K32 d = r32 from d = 0 until ||r|| <= tol_in ||r32_0||
+// or max_it iterations; FP64 accumulation of every inner product.
+int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
+  const long long N = h->N;
+  const Geo& g = h->lv[0].g;
+  HIPCK(hipMemsetAsync(h->d32, 0, sizeof(float) * N, h->s));
+  const int nr = launch_dot_t<float, float>(h->r32, h->r32, N, h->pa, nullptr, h->s);
+  launch_cg_init(h->st, h->pa, nr, h->pa, nr, tol_in, max_it, h->s);
+  const int* done = &h->st->done;
+  int it = 0, chunk = 4;
+  CgState hs;
+  for (;;) {
+    for (int c = 0; c < chunk && it < max_it; ++c, ++it) {
+      ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
+      const int nz = (h->L == 1) ? vec_num_blocks(N) : stencil_num_partials(g);
+      launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
+      launch_p_update_t<float>(h->z32, h->p32, N, h->st, it, h->s);
+      ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, h->dens));
+      launch_finalize(h->pc, stencil_num_partials(g), &h->st->pw, done, h->s);
+      launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, it, h->pa, nullptr, tol_in,
+                                max_it, h->s);
+      launch_cg_check(h->st, h->pa, nr, it + 1, tol_in, max_it, h->s);
+      LAUNCHCK();
+    }
+    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+    if (hs.done) break;
+    if (it >= max_it) return MGAR_E_HIP;
+    chunk = 2;
+  }
+  *iters = hs.iters;
+  return MGAR_OK;
+}
+
+// FP64 iterative refinement around the FP32 solver: r = q - K64 x in FP64,
+// d ~ K32^-1 r in FP32, x += d, until ||r|| <= tol ||q|| (or the CG budget is
+// spent). x in h->cx on entry and exit.
+int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relres, int* nref) {
+  const long long N = h->N;
+  const Geo& g = h->lv[0].g;
+  const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+  launch_finalize(h->pb, nq, &h->scal[2], nullptr, h->s);
+  int total = 0, ref = 0;
+  *conv = 0;
+  for (;; ++ref) {
+    ACK(stencil_at(h, 0, SM_RESID, h->cx, h->kcur, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
+    const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
+    launch_finalize(h->pa, nr, &h->scal[3], nullptr, h->s);
+    double qr[2];
+    HIPCK(hipMemcpyAsync(qr, &h->scal[2], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+    *relres = qr[0] > 0.0 ? std::sqrt(qr[1] / qr[0]) : 0.0;
+    if (*relres <= tol) { *conv = 1; break; }
+    if (total >= h->p.cg_max || ref >= h->refine_max) break;
+    launch_mask_copy_t<double, float>(g, h->cr, h->r32, h->s);
+    int its = 0;
+    ACK(pcg32(h, h->p.inner_tol, h->p.cg_max - total, &its));
+    total += its;
+    launch_add_f32(h->cx, h->d32, N, h->s);
+    LAUNCHCK();
+  }
+  *iters = total;
+  *nref = ref;
   return MGAR_OK;
 }
 
@@ -409,6 +522,7 @@ void mgar_default_params(mgar_params* p) {
   p->basis_x0_zero = 0;
   p->precision = MGAR_PREC_FP64;
   p->filter_r = 1.5;
+  p->inner_tol = 1e-2;
 }
 
 const char* mgar_strerror(int code) {
@@ -438,6 +552,12 @@ void mgar_destroy(mgar_handle* h) {
                   h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto* v : {&h->kf, &h->bf, &h->xaf, &h->xbf})
+    for (float* q : *v)
+      if (q) (void)hipFree(q);
+  void* mptrs[] = {h->dens, h->dens0, h->rtmpf, h->r32, h->z32, h->p32, h->w32, h->d32};
+  for (void* q : mptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   if (h->e0) (void)hipEventDestroy(h->e0);
@@ -502,14 +622,51 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   HIPCK(hipEventCreate(&h->e1));
   if (h->L >= 2) {
     std::vector<Geo> gs(h->L);
-    std::vector<double*> ks(h->L);
+    std::vector<const void*> ks(h->L);
     for (int l = 0; l < h->L; ++l) { gs[l] = h->lv[l].g; ks[l] = h->lv[l].k; }
     h->lt = h->L - 1;
     for (int lt = 1; lt < h->L; ++lt) {
       TailSpec T;
-      if (tail_plan(gs.data(), ks.data(), lt, h->L, &T)) { h->lt = lt; break; }
+      if (tail_plan(gs.data(), ks.data(), lt, h->L, sizeof(double), &T)) { h->lt = lt; break; }
     }
-    if (!tail_plan(gs.data(), ks.data(), h->lt, h->L, &h->tail)) return MGAR_E_DIMS;
+    if (!tail_plan(gs.data(), ks.data(), h->lt, h->L, sizeof(double), &h->tail)) return MGAR_E_DIMS;
+  }
+  if (p->precision == MGAR_PREC_MIXED) {
+    h->mixed = true;
+    h->kmin_f = (float)p->kmin;
+    h->kdiff_f = (float)(p->k0 - p->kmin);
+    ACK(dalloc(&h->dens, E));
+    ACK(dalloc(&h->dens0, E));
+    h->kf.assign(h->L, nullptr);
+    h->bf.assign(h->L, nullptr);
+    h->xaf.assign(h->L, nullptr);
+    h->xbf.assign(h->L, nullptr);
+    for (int l = 0; l < h->L; ++l) {
+      const Geo& gl = h->lv[l].g;
+      ACK(dalloc(&h->xaf[l], gl.nn));
+      if (l > 0) {
+        ACK(dalloc(&h->kf[l], gl.ne));
+        ACK(dalloc(&h->bf[l], gl.nn));
+        ACK(dalloc(&h->xbf[l], gl.nn));
+      }
+    }
+    ACK(dalloc(&h->rtmpf, N));
+    ACK(dalloc(&h->r32, N));
+    ACK(dalloc(&h->z32, N));
+    ACK(dalloc(&h->p32, N));
+    ACK(dalloc(&h->w32, N));
+    ACK(dalloc(&h->d32, N));
+    if (h->L >= 2) {
+      std::vector<Geo> gs(h->L);
+      std::vector<const void*> ks(h->L);
+      for (int l = 0; l < h->L; ++l) { gs[l] = h->lv[l].g; ks[l] = h->kf[l]; }
+      h->ltf = h->L - 1;
+      for (int lt = 1; lt < h->L; ++lt) {
+        TailSpec T;
+        if (tail_plan(gs.data(), ks.data(), lt, h->L, sizeof(float), &T)) { h->ltf = lt; break; }
+      }
+      if (!tail_plan(gs.data(), ks.data(), h->ltf, h->L, sizeof(float), &h->tailf)) return MGAR_E_DIMS;
+    }
   }
   // cone filter taps (Eq 7-8): offsets within the radius, weight r - distance
   {
@@ -588,14 +745,21 @@ int mgcg_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   HIPCK(hipEventRecord(h->e0, h->s));
   const Geo& g = h->lv[0].g;
   launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  int nref = 0;
   launch_copy(h->kcur, h->lv[0].k, h->E, h->s);
-  ACK(build_hierarchy(h));
+  if (h->mixed) {
+    launch_cast_bf16(xphys, h->dens, h->E, h->s);
+    ACK(build_hierarchy32(h));
+  } else {
+    ACK(build_hierarchy(h));
+  }
   launch_mask_copy(g, q, h->qm, h->s);
   if (T0) launch_mask_copy(g, T0, h->cx, h->s);
   else HIPCK(hipMemsetAsync(h->cx, 0, sizeof(double) * h->N, h->s));
   int iters = 0, conv = 0;
   double rel = 0.0;
-  ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+  if (h->mixed) ACK(solve_mixed(h, tol, &iters, &conv, &rel, &nref));
+  else ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
   launch_copy(h->cx, T, h->N, h->s);
   LAUNCHCK();
   ACK(check_coarse(h));
@@ -605,6 +769,7 @@ int mgcg_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
     stats->path = MGAR_PATH_MGCG;
     stats->cg_iters = iters;
     stats->vcycles = iters;
+    stats->refinements = nref;
     stats->res_final = rel;
   }
   return conv ? MGAR_OK : MGAR_W_NOT_CONVERGED;
@@ -620,6 +785,7 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   const long long N = h->N;
   const int m = h->p.n_basis;
   launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  if (h->mixed) launch_cast_bf16(xphys, h->dens, h->E, h->s);
   launch_mask_copy(g, q, h->qm, h->s);
   // r_1 = t_prev
   if (T0) launch_mask_copy(g, T0, h->R, h->s);
@@ -627,8 +793,19 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   // r_i = MG(K0, -dK r_{i-1}, x0, P)   (Eq 17)
   for (int i = 1; i < m; ++i) {
     const double* prev = h->R + (long long)(i - 1) * N;
-    ACK(stencil_at(h, 0, SM_NEG_DK, prev, h->kcur, h->lv[0].k, nullptr, h->cz, 0.0, nullptr, nullptr));
-    ACK(vcycle(h, h->cz, h->p.basis_x0_zero ? nullptr : prev, h->R + (long long)i * N, nullptr, nullptr));
+    if (h->mixed) {
+      // -dK r in FP64 from the FP64 conductivities (a difference of two nearby
+      // operators: BF16 densities would lose most of its digits), then one FP32
+      // V-cycle on the BF16 K0 hierarchy; the column is kept in FP64
+      ACK(stencil_at(h, 0, SM_NEG_DK, prev, h->kcur, h->lv[0].k, nullptr, h->cz, 0.0, nullptr, nullptr));
+      launch_mask_copy_t<double, float>(g, h->cz, h->z32, h->s);
+      if (!h->p.basis_x0_zero) launch_mask_copy_t<double, float>(g, prev, h->r32, h->s);
+      ACK(vcycle32(h, h->z32, h->p.basis_x0_zero ? nullptr : h->r32, h->w32, nullptr, nullptr));
+      launch_mask_copy_t<float, double>(g, h->w32, h->R + (long long)i * N, h->s);
+    } else {
+      ACK(stencil_at(h, 0, SM_NEG_DK, prev, h->kcur, h->lv[0].k, nullptr, h->cz, 0.0, nullptr, nullptr));
+      ACK(vcycle(h, h->cz, h->p.basis_x0_zero ? nullptr : prev, h->R + (long long)i * N, nullptr, nullptr));
+    }
   }
   // Eq 18 (as Gram-Schmidt), Eq 19-21
   ACK(orthonormalise(h));
@@ -661,11 +838,17 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
     }
   } else {
     // reconstruction: K becomes the new K0, MGCG from the reduced solution
-    launch_copy(h->kcur, h->lv[0].k, h->E, h->s);
-    ACK(build_hierarchy(h));
-    int iters = 0, conv = 0;
+    int iters = 0, conv = 0, nref = 0;
     double rel = 0.0;
-    ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+    launch_copy(h->kcur, h->lv[0].k, h->E, h->s);
+    if (h->mixed) {
+      ACK(build_hierarchy32(h));
+      ACK(solve_mixed(h, tol, &iters, &conv, &rel, &nref));
+    } else {
+      ACK(build_hierarchy(h));
+      ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+    }
+    if (stats) stats->refinements = nref;
     launch_copy(h->cx, T, N, h->s);
     LAUNCHCK();
     ACK(check_coarse(h));
@@ -778,7 +961,12 @@ int mgar_op_coarsen(mgar_handle* h, int level, const double* kf, double* kc) {
 int mgar_build_hierarchy(mgar_handle* h, const double* xphys) {
   if (!h || !xphys) return MGAR_E_ARG;
   launch_simp(xphys, h->lv[0].k, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
-  ACK(build_hierarchy(h));
+  if (h->mixed) {
+    launch_cast_bf16(xphys, h->dens, h->E, h->s);
+    ACK(build_hierarchy32(h));
+  } else {
+    ACK(build_hierarchy(h));
+  }
   ACK(check_coarse(h));
   h->has_k0 = true;
   return MGAR_OK;
@@ -788,6 +976,14 @@ int mgar_vcycle(mgar_handle* h, const double* b, const double* x0, double* x) {
   if (!h || !b || !x) return MGAR_E_ARG;
   if (!h->has_k0) return MGAR_E_STATE;
   const Geo& g = h->lv[0].g;
+  if (h->mixed) {
+    launch_mask_copy_t<double, float>(g, b, h->z32, h->s);
+    if (x0) launch_mask_copy_t<double, float>(g, x0, h->r32, h->s);
+    ACK(vcycle32(h, h->z32, x0 ? h->r32 : nullptr, h->w32, nullptr, nullptr));
+    launch_mask_copy_t<float, double>(g, h->w32, x, h->s);
+    LAUNCHCK();
+    return MGAR_OK;
+  }
   launch_mask_copy(g, b, h->cz, h->s);
   if (x0) launch_mask_copy(g, x0, h->cr, h->s);
   ACK(vcycle(h, h->cz, x0 ? h->cr : nullptr, x, nullptr, nullptr));
@@ -801,6 +997,13 @@ int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b) 
   launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
   launch_mask_copy(g, r, h->rtmp, h->s);
   launch_stencil(g, SM_NEG_DK, h->rtmp, h->kcur, h->lv[0].k, nullptr, b, 0.0, nullptr, nullptr, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+int mgar_op_bf16(mgar_handle* h, const double* x, void* out) {
+  if (!h || !x || !out) return MGAR_E_ARG;
+  launch_cast_bf16(x, static_cast<uint16_t*>(out), h->E, h->s);
   LAUNCHCK();
   return MGAR_OK;
 }

@@ -30,6 +30,31 @@ __host__ __device__ inline long long geo_elem(const Geo& g, int ex, int ey, int 
   return (long long)ex + (long long)g.nx * ((long long)ey + (long long)g.ny * ez);
 }
 
+// Cell-conductivity loaders. Kernels read cell conductivities through one of
+// these: an FP64 array, an FP32 array, or BF16-stored physical densities with
+// the SIMP law (Eq 4, p = 3) applied in FP32 on load.
+struct CellD {
+  const double* p;
+  __device__ double operator()(long long e) const { return p[e]; }
+};
+struct CellF {
+  const float* p;
+  __device__ float operator()(long long e) const { return p[e]; }
+};
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
+  union { uint32_t u; float f; } v;
+  v.u = (uint32_t)b << 16;
+  return v.f;
+}
+struct CellB {
+  const uint16_t* p;
+  float kmin, kdiff;
+  __device__ float operator()(long long e) const {
+    const float r = bf16_bits_to_f32(p[e]);
+    return kmin + kdiff * (r * r * r);
+  }
+};
+
 // PCG state in device memory. Every field has a single writer per kernel.
 struct CgState {
   double qq;                 // ||q||^2 over free nodes

@@ -14,33 +14,58 @@ enum StencilMode {
 };
 
 // stencil.hip ----------------------------------------------------------------
+// Value type T (double or float) and cell loader CL (CellD, CellF, CellB) are
+// template parameters; FP64 entry points keep plain-pointer overloads.
+template <typename T, typename CL>
+int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out,
+                     double omega, double* part, const int* done, hipStream_t s,
+                     unsigned* cnt = nullptr, double* rout = nullptr, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr);
 // Returns the number of block partials written to `part` (0 for modes without a
 // dot). With cnt != null the dot is also reduced in the same launch (last block
-// sums the partials in order) and stored to *rout.
-// ev0/ev1 (z-marching grids only): events recorded at kernel start and end.
+// sums the partials in order) and stored to *rout. ev0/ev1 (z-marching grids
+// only): events recorded at kernel start and end.
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
                    hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr,
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 bool stencil_records_events(const Geo& g);
 int stencil_num_partials(const Geo& g);
-void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
-                     hipStream_t s);
-// Post-smoother with the coarse correction interpolated on the fly:
-// out = x + w D^-1 (b - K x), x = xa + P ec (Table 1 steps 4-5 in one pass);
-// with part != null also partials of b . out. Only for grids where
-// stencil_fuses_prolong() is true.
-bool stencil_fuses_prolong(const Geo& g);
-int launch_prolong_smooth(const Geo& g, const Geo& gc, const double* xa, const double* ec,
-                          const double* k, const double* b, double* out, double omega,
-                          double* part, const int* done, hipStream_t s);
-void launch_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf, const int* done,
-                    hipStream_t s);
-void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, hipStream_t s);
-void launch_coarse_build(const Geo& g, const double* k, double* A, int* status, hipStream_t s);
-void launch_coarse_solve(const Geo& g, const double* A, const double* b, double* x,
-                         const int* done, hipStream_t s);
-void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s);
+template <typename T>
+void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);
+template <typename T>
+void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s);
+template <typename CL, typename TO>
+void launch_coarsen_t(const Geo& gf, const Geo& gc, CL kf, TO* kc, hipStream_t s);
+template <typename CL>
+void launch_coarse_build_t(const Geo& g, CL k, double* A, int* status, hipStream_t s);
+template <typename T>
+void launch_coarse_solve_t(const Geo& g, const double* A, const T* b, T* x, const int* done,
+                           hipStream_t s);
+template <typename TI, typename TO>
+void launch_mask_copy_t(const Geo& g, const TI* in, TO* out, hipStream_t s);
+
+inline void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc,
+                            const int* done, hipStream_t s) {
+  launch_restrict_t<double>(gf, gc, rf, rc, done, s);
+}
+inline void launch_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf,
+                           const int* done, hipStream_t s) {
+  launch_prolong_t<double>(gf, gc, xc, xf, done, s);
+}
+inline void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, hipStream_t s) {
+  launch_coarsen_t<CellD, double>(gf, gc, CellD{kf}, kc, s);
+}
+inline void launch_coarse_build(const Geo& g, const double* k, double* A, int* status, hipStream_t s) {
+  launch_coarse_build_t<CellD>(g, CellD{k}, A, status, s);
+}
+inline void launch_coarse_solve(const Geo& g, const double* A, const double* b, double* x,
+                                const int* done, hipStream_t s) {
+  launch_coarse_solve_t<double>(g, A, b, x, done, s);
+}
+inline void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s) {
+  launch_mask_copy_t<double, double>(g, in, out, s);
+}
 
 // Bottom of the V-cycle in one workgroup: grids lt..L-1 of a hierarchy with
 // their vectors in LDS. b_in: right-hand side on grid lt; x_out: the V-cycle
@@ -48,21 +73,39 @@ void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s
 #define MGAR_MAX_TAIL 8
 struct TailSpec {
   int nl;                          // grids in the tail (>= 1); the last is the coarsest
-  int lds_doubles;                 // LDS footprint
+  int lds_elems;                   // LDS footprint in values
+  int elem;                        // bytes per value
   Geo g[MGAR_MAX_TAIL];
-  const double* k[MGAR_MAX_TAIL];  // cell conductivities (global memory)
+  const void* k[MGAR_MAX_TAIL];    // cell conductivities (global memory, value type)
   int off_b[MGAR_MAX_TAIL], off_xa[MGAR_MAX_TAIL], off_xb[MGAR_MAX_TAIL], off_k[MGAR_MAX_TAIL];
 };
 // Fills the LDS layout; returns false if grids lt.. do not fit.
-bool tail_plan(const Geo* g, double* const* k, int lt, int L, TailSpec* T);
-void launch_vtail(const TailSpec& T, const double* b_in, double* x_out, const double* Ainv,
-                  double omega, const int* done, hipStream_t s);
+bool tail_plan(const Geo* g, const void* const* k, int lt, int L, size_t elem, TailSpec* T);
+template <typename T>
+void launch_vtail_t(const TailSpec& TS, const T* b_in, T* x_out, const double* Ainv, double omega,
+                    const int* done, hipStream_t s);
+inline void launch_vtail(const TailSpec& TS, const double* b_in, double* x_out, const double* Ainv,
+                         double omega, const int* done, hipStream_t s) {
+  launch_vtail_t<double>(TS, b_in, x_out, Ainv, omega, done, s);
+}
 
 // vec.hip --------------------------------------------------------------------
 int vec_num_blocks(long long n);
 // partial[b] = sum over block b of a.b ; returns number of partials
 int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
                hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr);
+template <typename TA, typename TB>
+int launch_dot_t(const TA* a, const TB* b, long long n, double* part, const int* done, hipStream_t s,
+                 unsigned* cnt = nullptr, double* rout = nullptr);
+template <typename T>
+void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, int it, hipStream_t s);
+template <typename T>
+int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, int it,
+                       double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s);
+// FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
+void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
+void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
+void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s);
 // out = sum(part[0..n)) in a fixed order (single block)
 void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s);
 // Stopping test before iteration it from the partials of ||r||^2.

@@ -21,10 +21,15 @@ namespace {
 
 constexpr int TBX = 64, TBY = 4;
 
-template <int DIM, bool DK>
-__device__ inline void load_cells(const Geo& g, const double* __restrict__ k,
-                                  const double* __restrict__ kref, int i, int j, int kz,
-                                  double (&kv)[2][2][2]) {
+template <typename T>
+struct CellP {
+  const T* p;
+  __device__ T operator()(long long e) const { return p[e]; }
+};
+
+template <int DIM, bool DK, typename T, typename CL>
+__device__ inline void load_cells(const Geo& g, const CL& k, const CL& kref, int i, int j, int kz,
+                                  T (&kv)[2][2][2]) {
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -34,46 +39,47 @@ __device__ inline void load_cells(const Geo& g, const double* __restrict__ k,
         const int ex = i - 1 + a, ey = j - 1 + b, ez = (DIM == 3) ? kz - 1 + c : 0;
         const bool in = (DIM == 3 || c == 0) && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny &&
                         ez >= 0 && ez < g.nz;
-        double v = 0.0;
+        T v = T(0);
         if (in) {
           const long long e = geo_elem(g, ex, ey, ez);
-          v = k[e];
-          if (DK) v -= kref[e];
+          v = T(k(e));
+          if (DK) v -= T(kref(e));
         }
         kv[c][b][a] = v;
       }
 }
 
-__device__ inline double ldx(const Geo& g, const double* __restrict__ x, int i, int j, int k) {
+template <typename T>
+__device__ inline T ldx(const Geo& g, const T* __restrict__ x, int i, int j, int k) {
   const bool in = i >= 0 && i < g.nnx && j >= 0 && j < g.nny && k >= 0 && k < g.nnz;
-  return in ? x[geo_node(g, i, j, k)] : 0.0;
+  return in ? x[geo_node(g, i, j, k)] : T(0);
 }
 
 // (K x)_i for node (i, j, kz) given the 2^d cell conductivities around it.
-template <int DIM>
-__device__ inline double node_apply(const Geo& g, const double* __restrict__ x, int i, int j,
-                                    int kz, const double (&kv)[2][2][2], double& ksum) {
+template <int DIM, typename T>
+__device__ inline T node_apply(const Geo& g, const T* __restrict__ x, int i, int j, int kz,
+                               const T (&kv)[2][2][2], T& ksum) {
   if (DIM == 2) {
-    double xv[3][3];
+    T xv[3][3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) xv[dy][dx] = ldx(g, x, i + dx - 1, j + dy - 1, 0);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int sx = a ? 2 : 0, sy = b ? 2 : 0;
-        const double ke = kv[0][b][a];
+        const T ke = kv[0][b][a];
         s0 += ke;
         s1 += ke * (xv[1][sx] + xv[sy][1]);
         s2 += ke * xv[sy][sx];
       }
     ksum = s0;
-    return (2.0 / 3.0) * s0 * xv[1][1] - (1.0 / 6.0) * s1 - (1.0 / 3.0) * s2;
+    return T(2.0 / 3.0) * s0 * xv[1][1] - T(1.0 / 6.0) * s1 - T(1.0 / 3.0) * s2;
   } else {
-    double xv[3][3][3];
+    T xv[3][3][3];
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
@@ -81,9 +87,9 @@ __device__ inline double node_apply(const Geo& g, const double* __restrict__ x, 
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
           const int nz = (dx != 1) + (dy != 1) + (dz != 1);
-          xv[dz][dy][dx] = (nz == 1) ? 0.0 : ldx(g, x, i + dx - 1, j + dy - 1, kz + dz - 1);
+          xv[dz][dy][dx] = (nz == 1) ? T(0) : ldx(g, x, i + dx - 1, j + dy - 1, kz + dz - 1);
         }
-    double s0 = 0.0, s1 = 0.0;
+    T s0 = T(0), s1 = T(0);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -91,21 +97,19 @@ __device__ inline double node_apply(const Geo& g, const double* __restrict__ x, 
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const int sx = a ? 2 : 0, sy = b ? 2 : 0, sz = c ? 2 : 0;
-          const double ke = kv[c][b][a];
+          const T ke = kv[c][b][a];
           s0 += ke;
           s1 += ke * (xv[1][sy][sx] + xv[sz][1][sx] + xv[sz][sy][1] + xv[sz][sy][sx]);
         }
     ksum = s0;
-    return g.h * ((1.0 / 3.0) * s0 * xv[1][1][1] - (1.0 / 12.0) * s1);
+    return T(g.h) * (T(1.0 / 3.0) * s0 * xv[1][1][1] - T(1.0 / 12.0) * s1);
   }
 }
 
-template <int DIM, int MODE>
-__global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const double* __restrict__ x,
-                                                      const double* __restrict__ k,
-                                                      const double* __restrict__ kref,
-                                                      const double* __restrict__ b,
-                                                      double* __restrict__ out, double omega,
+template <int DIM, int MODE, typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const T* __restrict__ x, CL k, CL kref,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ out, T omega,
                                                       double* __restrict__ part,
                                                       const int* __restrict__ done,
                                                       unsigned* __restrict__ cnt,
@@ -119,14 +123,14 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const double* __res
   double dotv = 0.0;
   if (valid) {
     const long long n = geo_node(g, i, j, kz);
-    double r = 0.0;
+    T r = T(0);
     if (!geo_fixed(g, i, j, kz)) {
-      double kv[2][2][2];
+      T kv[2][2][2];
       load_cells<DIM, MODE == SM_NEG_DK>(g, k, kref, i, j, kz, kv);
-      double ksum = 0.0;
-      double y = 0.0;
+      T ksum = T(0);
+      T y = T(0);
       if (MODE != SM_JACOBI0) {
-        y = node_apply<DIM>(g, x, i, j, kz, kv, ksum);
+        y = node_apply<DIM, T>(g, x, i, j, kz, kv, ksum);
       } else {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -135,15 +139,15 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const double* __res
 #pragma unroll
             for (int a = 0; a < 2; ++a) ksum += kv[c][bb][a];
       }
-      const double diag = (DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
+      const T diag = T(DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
       if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {
         r = y;
-        if (MODE == SM_APPLY_DOT) dotv = x[n] * r;
+        if (MODE == SM_APPLY_DOT) dotv = (double)x[n] * (double)r;
       } else if (MODE == SM_RESID) {
         r = b[n] - y;
       } else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) {
         r = x[n] + omega * (b[n] - y) / diag;
-        if (MODE == SM_JACOBI_DOT) dotv = b[n] * r;
+        if (MODE == SM_JACOBI_DOT) dotv = (double)b[n] * (double)r;
       } else if (MODE == SM_JACOBI0) {
         r = omega * b[n] / diag;
       } else if (MODE == SM_NEG_DK) {
@@ -214,25 +218,25 @@ __device__ inline XSlot make_xslot(const Geo& g, const Geo& gc, int i0, int j0, 
   return sl;
 }
 
-template <int XP>
-__device__ inline double zfill_x(const Geo& g, const Geo& gc, const double* __restrict__ x,
-                                 const double* __restrict__ ec, const XSlot& sl, int p) {
-  if (!sl.ok || p < 0 || p >= g.nnz) return 0.0;
+template <int XP, typename T>
+__device__ inline T zfill_x(const Geo& g, const Geo& gc, const T* __restrict__ x,
+                            const T* __restrict__ ec, const XSlot& sl, int p) {
+  if (!sl.ok || p < 0 || p >= g.nnz) return T(0);
   const long long pl = (long long)g.nnx * g.nny;
-  double v = x[sl.off + pl * p];
+  T v = x[sl.off + pl * p];
   if (XP == XP_PROLONG && !(sl.fxy && p >= g.f0z && p <= g.f1z)) {
     const long long cpl = (long long)gc.nnx * gc.nny;
     const int nk = (p & 1) ? 2 : 1;
-    const double wk = (p & 1) ? 0.5 : 1.0;
-    const double* e0 = ec + sl.coff + cpl * (p >> 1);
-    double s = 0.0;
+    const T wk = T((p & 1) ? 0.5 : 1.0);
+    const T* e0 = ec + sl.coff + cpl * (p >> 1);
+    T s = T(0);
     for (int c = 0; c < nk; ++c) {
-      double sy = 0.0;
+      T sy = T(0);
       for (int b = 0; b < sl.nj; ++b) {
-        const double* r = e0 + c * cpl + b * gc.nnx;
-        sy += sl.wi * (sl.ni == 2 ? r[0] + r[1] : r[0]);
+        const T* r = e0 + c * cpl + b * gc.nnx;
+        sy += T(sl.wi) * (sl.ni == 2 ? r[0] + r[1] : r[0]);
       }
-      s += sl.wj * sy;
+      s += T(sl.wj) * sy;
     }
     v += wk * s;
   }
@@ -252,22 +256,19 @@ __device__ inline CSlot make_cslot(const Geo& g, int i0, int j0, int CW, int CN,
   return sl;
 }
 
-template <bool DK>
-__device__ inline double zfill_c(const Geo& g, const double* __restrict__ k,
-                                 const double* __restrict__ kref, const CSlot& sl, int ez) {
-  if (!sl.ok || ez < 0 || ez >= g.nz) return 0.0;
+template <bool DK, typename T, typename CL>
+__device__ inline T zfill_c(const Geo& g, const CL& k, const CL& kref, const CSlot& sl, int ez) {
+  if (!sl.ok || ez < 0 || ez >= g.nz) return T(0);
   const long long e = sl.off + (long long)g.nx * g.ny * ez;
-  return DK ? k[e] - kref[e] : k[e];
+  return DK ? T(k(e)) - T(kref(e)) : T(k(e));
 }
 
-template <int MODE, int XP, int ZD = 1>
-__global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
-                                                  int KZ, const double* __restrict__ x,
-                                                  const double* __restrict__ ec,
-                                                  const double* __restrict__ k,
-                                                  const double* __restrict__ kref,
-                                                  const double* __restrict__ b,
-                                                  double* __restrict__ out, double omega,
+template <int MODE, int XP, int ZD, typename T, typename CL>
+__global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
+                                                  int KZ, const T* __restrict__ x,
+                                                  const T* __restrict__ ec, CL k, CL kref,
+                                                  const T* __restrict__ b,
+                                                  T* __restrict__ out, T omega,
                                                   double* __restrict__ part,
                                                   const int* __restrict__ done,
                                                   unsigned* __restrict__ cnt,
@@ -277,8 +278,8 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
   constexpr bool NEEDX = (MODE != SM_JACOBI0);
   constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
                           MODE == SM_JACOBI0);
-  __shared__ double Xs[2][XCAP];
-  __shared__ double Cs[2][CCAP];
+  __shared__ T Xs[2][XCAP];
+  __shared__ T Cs[2][CCAP];
   __shared__ double sh[ZT / MGAR_WAVE];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int nxy = ntx * nty;
@@ -302,15 +303,15 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
   const int xc = act ? (ly + 1) * XW + (lx + 1) : XW + 1;
   const int cb = act ? ly * CW + lx : 0;
 
-#define ZX(sl, p) (NEEDX ? zfill_x<XP>(g, gc, x, ec, (sl), (p)) : 0.0)
-#define ZC(sl, ez) zfill_c<DK>(g, k, kref, (sl), (ez))
-#define ZB(p) ((NEEDB && act && (p) < k1) ? b[nxy_off + pl * (p)] : 0.0)
+#define ZX(sl, p) (NEEDX ? zfill_x<XP, T>(g, gc, x, ec, (sl), (p)) : T(0))
+#define ZC(sl, ez) zfill_c<DK, T, CL>(g, k, kref, (sl), (ez))
+#define ZB(p) ((NEEDB && act && (p) < k1) ? b[nxy_off + pl * (p)] : T(0))
 
   // register queue of global loads: entry d holds x plane kk+1+d, cell plane
   // kk+d and b of plane kk+d for the step of node plane kk
-  double qx0[ZD], qx1[ZD], qc0[ZD], qc1[ZD], qb[ZD];
+  T qx0[ZD], qx1[ZD], qc0[ZD], qc1[ZD], qb[ZD];
   // rolling register window: 3x3 of three x planes, 2x2 of two cell planes
-  double W0[3][3], W1[3][3], W2[3][3], V0[2][2], V1[2][2];
+  T W0[3][3], W1[3][3], W2[3][3], V0[2][2], V1[2][2];
 
   // prologue: planes k0-1 and k0 and cells k0-1 go through LDS into W0, W1, V0
   if (tid < XN) { Xs[0][tid] = ZX(xs0, k0 - 1); Xs[1][tid] = ZX(xs0, k0); }
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
   __syncthreads();
 
   const bool colfix = act && i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y;
-  const double hc = g.h * (1.0 / 3.0), hf = g.h * (1.0 / 12.0);
+  const T hc = T(g.h * (1.0 / 3.0)), hf = T(g.h * (1.0 / 12.0));
   double dotv = 0.0;
 
   // One node plane kk: stage plane kk+1 and cells kk through LDS slot s, read
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
     if (tid + ZT < XN) Xs[s][tid + ZT] = qx1[0];                                             \
     if (tid < CN) Cs[s][tid] = qc0[0];                                                       \
     if (tid + ZT < CN) Cs[s][tid + ZT] = qc1[0];                                             \
-    const double bn = qb[0];                                                                 \
+    const T bn = qb[0];                                                                 \
     _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
       qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1];                                              \
       qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
@@ -370,21 +371,21 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
     {                                                                                        \
       const int pf = kk + ZD;                                                                \
       const bool more = pf < k1;                                                             \
-      qx0[ZD - 1] = more ? ZX(xs0, pf + 1) : 0.0;                                            \
-      qx1[ZD - 1] = more ? ZX(xs1, pf + 1) : 0.0;                                            \
-      qc0[ZD - 1] = more ? ZC(cs0, pf) : 0.0;                                                \
-      qc1[ZD - 1] = more ? ZC(cs1, pf) : 0.0;                                                \
-      qb[ZD - 1] = more ? ZB(pf) : 0.0;                                                      \
+      qx0[ZD - 1] = more ? ZX(xs0, pf + 1) : T(0);                                            \
+      qx1[ZD - 1] = more ? ZX(xs1, pf + 1) : T(0);                                            \
+      qc0[ZD - 1] = more ? ZC(cs0, pf) : T(0);                                                \
+      qc1[ZD - 1] = more ? ZC(cs1, pf) : T(0);                                                \
+      qb[ZD - 1] = more ? ZB(pf) : T(0);                                                      \
     }                                                                                        \
     if (act) {                                                                               \
-      double r = 0.0;                                                                        \
+      T r = T(0);                                                                            \
       if (!(colfix && kk >= g.f0z && kk <= g.f1z)) {                                         \
         /* cell sums: t = below + above (centre-plane diagonals), column and */            \
         /* row sums per plane (edge midpoints of planes kk-1 and kk+1)        */            \
-        const double t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];                 \
-        const double t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];                 \
-        const double ks = (t00 + t01) + (t10 + t11);                                       \
-        double s1 = 0.0;                                                                     \
+        const T t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];                      \
+        const T t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];                      \
+        const T ks = (t00 + t01) + (t10 + t11);                                            \
+        T s1 = T(0);                                                                         \
         if (NEEDX) {                                                                         \
           s1 = t00 * B[0][0] + t01 * B[0][2] + t10 * B[2][0] + t11 * B[2][2];                \
           s1 += (CA[0][0] + CA[1][0]) * A[1][0] + (CA[0][1] + CA[1][1]) * A[1][2];           \
@@ -394,17 +395,17 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
           s1 += (CB[0][0] + CB[0][1]) * C[0][1] + (CB[1][0] + CB[1][1]) * C[2][1];           \
           s1 += CB[0][0] * C[0][0] + CB[0][1] * C[0][2] + CB[1][0] * C[2][0] + CB[1][1] * C[2][2]; \
         }                                                                                    \
-        const double xcv = NEEDX ? B[1][1] : 0.0;                                            \
-        const double y = NEEDX ? (hc * ks * xcv - hf * s1) : 0.0;                            \
-        const double diag = hc * ks;                                                         \
+        const T xcv = NEEDX ? B[1][1] : T(0);                                                \
+        const T y = NEEDX ? (hc * ks * xcv - hf * s1) : T(0);                                \
+        const T diag = hc * ks;                                                              \
         if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {                                      \
           r = y;                                                                             \
-          if (MODE == SM_APPLY_DOT) dotv += xcv * r;                                         \
+          if (MODE == SM_APPLY_DOT) dotv += (double)xcv * (double)r;                         \
         } else if (MODE == SM_RESID) {                                                       \
           r = bn - y;                                                                        \
         } else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) {                             \
           r = xcv + omega * (bn - y) / diag;                                                 \
-          if (MODE == SM_JACOBI_DOT) dotv += bn * r;                                         \
+          if (MODE == SM_JACOBI_DOT) dotv += (double)bn * (double)r;                         \
         } else if (MODE == SM_JACOBI0) {                                                     \
           r = omega * bn / diag;                                                             \
         } else if (MODE == SM_NEG_DK) {                                                      \
@@ -445,40 +446,40 @@ __global__ __launch_bounds__(ZT) void k_stencil_z(Geo g, Geo gc, int TXW, int TY
 
 // Restriction r_c = P^T r_f: coarse node (I,J,K) gathers the fine nodes
 // (2I+a, 2J+b, 2K+c), a,b,c in {-1,0,1}, with weight prod(1 if 0 else 1/2).
-template <int DIM>
-__global__ __launch_bounds__(TBX* TBY) void k_restrict(Geo gf, Geo gc, const double* __restrict__ rf,
-                                                       double* __restrict__ rc,
+template <int DIM, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_restrict(Geo gf, Geo gc, const T* __restrict__ rf,
+                                                       T* __restrict__ rc,
                                                        const int* __restrict__ done) {
   if (done && *done) return;
   const int I = blockIdx.x * TBX + threadIdx.x;
   const int J = blockIdx.y * TBY + threadIdx.y;
   const int K = blockIdx.z;
   if (I >= gc.nnx || J >= gc.nny) return;
-  double s = 0.0;
+  T s = T(0);
   if (!geo_fixed(gc, I, J, K)) {
 #pragma unroll
     for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
-      double sy = 0.0;
+      T sy = T(0);
 #pragma unroll
       for (int b = -1; b <= 1; ++b) {
-        double sx = 0.0;
+        T sx = T(0);
 #pragma unroll
         for (int a = -1; a <= 1; ++a) {
-          const double v = ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
-          sx += (a == 0 ? 1.0 : 0.5) * v;
+          const T v = ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
+          sx += T(a == 0 ? 1.0 : 0.5) * v;
         }
-        sy += (b == 0 ? 1.0 : 0.5) * sx;
+        sy += T(b == 0 ? 1.0 : 0.5) * sx;
       }
-      s += (c == 0 ? 1.0 : 0.5) * sy;
+      s += T(c == 0 ? 1.0 : 0.5) * sy;
     }
   }
   rc[geo_node(gc, I, J, K)] = s;
 }
 
 // Interpolation and correction x_f += P x_c (bi-/trilinear; fixed fine rows are 0).
-template <int DIM>
-__global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const double* __restrict__ xc,
-                                                      double* __restrict__ xf,
+template <int DIM, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const T* __restrict__ xc,
+                                                      T* __restrict__ xf,
                                                       const int* __restrict__ done) {
   if (done && *done) return;
   const int i = blockIdx.x * TBX + threadIdx.x;
@@ -488,13 +489,13 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const doub
   if (geo_fixed(gf, i, j, k)) return;
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0,
-               wk = (DIM == 3 && (k & 1)) ? 0.5 : 1.0;
-  double s = 0.0;
+  const T wi = T((i & 1) ? 0.5 : 1.0), wj = T((j & 1) ? 0.5 : 1.0),
+          wk = T((DIM == 3 && (k & 1)) ? 0.5 : 1.0);
+  T s = T(0);
   for (int c = 0; c < nk; ++c) {
-    double sy = 0.0;
+    T sy = T(0);
     for (int b = 0; b < nj; ++b) {
-      double sx = 0.0;
+      T sx = T(0);
       for (int a = 0; a < ni; ++a) sx += xc[geo_node(gc, I0 + a, J0 + b, K0 + c)];
       sy += wi * sx;
     }
@@ -504,8 +505,8 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const doub
 }
 
 // Coarse conductivity: mean of the 2^d children.
-template <int DIM>
-__global__ void k_coarsen(Geo gf, Geo gc, const double* __restrict__ kf, double* __restrict__ kc) {
+template <int DIM, typename CL, typename TO>
+__global__ void k_coarsen(Geo gf, Geo gc, CL kf, TO* __restrict__ kc) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= gc.ne) return;
   const int ex = (int)(e % gc.nx);
@@ -516,8 +517,8 @@ __global__ void k_coarsen(Geo gf, Geo gc, const double* __restrict__ kf, double*
   for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
     for (int b = 0; b < 2; ++b)
       for (int a = 0; a < 2; ++a)
-        s += kf[geo_elem(gf, 2 * ex + a, 2 * ey + b, DIM == 3 ? 2 * ez + c : 0)];
-  kc[e] = s * (DIM == 3 ? 0.125 : 0.25);
+        s += (double)kf(geo_elem(gf, 2 * ex + a, 2 * ey + b, DIM == 3 ? 2 * ez + c : 0));
+  kc[e] = (TO)(s * (DIM == 3 ? 0.125 : 0.25));
 }
 
 // Q1 element matrix entry between local corners ca, cb for cell edge h.
@@ -534,9 +535,8 @@ constexpr int CB_MAXN = 1024;
 // Coarsest grid: assemble the dense N_c x N_c matrix (identity rows/columns on
 // Dirichlet nodes), then invert it in place by Gauss-Jordan elimination without
 // pivoting (valid for SPD matrices) and symmetrise. One workgroup.
-template <int DIM>
-__global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, const double* __restrict__ k,
-                                                             double* __restrict__ A,
+template <int DIM, typename CL>
+__global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double* __restrict__ A,
                                                              int* __restrict__ status) {
   __shared__ double colp[CB_MAXN];
   __shared__ double rowp[CB_MAXN];
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, const double
         for (int a = 0; a < 2; ++a) {
           const int ex = ii - 1 + a, ey = jj - 1 + b, ez = (DIM == 3) ? kk - 1 + c : 0;
           if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
-          const double ke = k[geo_elem(g, ex, ey, ez)];
+          const double ke = (double)k(geo_elem(g, ex, ey, ez));
           // corner of node i in this cell
           const int ci = (1 - a) + 2 * (1 - b) + (DIM == 3 ? 4 * (1 - c) : 0);
           for (int cc = 0; cc < (DIM == 3 ? 8 : 4); ++cc) {
@@ -605,9 +605,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, const double
 // Register-resident variant for n <= 128: thread (tr, tc) of a 32 x 32 layout
 // owns entries (tr + 32a, tc + 32b), a, b < 4, for the whole elimination; only
 // the pivot row and column pass through LDS. Same arithmetic as above.
-template <int DIM>
-__global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, const double* __restrict__ k,
-                                                                 double* __restrict__ A,
+template <int DIM, typename CL>
+__global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, CL k, double* __restrict__ A,
                                                                  int* __restrict__ status) {
   __shared__ double colp[128];
   __shared__ double rowp[128];
@@ -651,7 +650,7 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, const do
                   if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
                   const int cci = (1 - aa) + 2 * (1 - bb) + (DIM == 3 ? 4 * (1 - c) : 0);
                   const int ccj = bx + 2 * by + 4 * bz;
-                  v += k[geo_elem(g, ex, ey, ez)] * ke_entry<DIM>(cci, ccj, g.h);
+                  v += (double)k(geo_elem(g, ex, ey, ez)) * ke_entry<DIM>(cci, ccj, g.h);
                 }
           }
         }
@@ -735,26 +734,27 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, const do
 }
 
 // x = A^-1 b on the coarsest grid (A symmetric: column reads are coalesced).
+template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(int n, const double* __restrict__ A,
-                                                      const double* __restrict__ b,
-                                                      double* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ x,
                                                       const int* __restrict__ done) {
   if (done && *done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += A[(long long)j * n + i] * b[j];
-  x[i] = s;
+  for (int j = 0; j < n; ++j) s += A[(long long)j * n + i] * (double)b[j];
+  x[i] = (T)s;
 }
 
-__global__ __launch_bounds__(TBX* TBY) void k_mask_copy(Geo g, const double* __restrict__ in,
-                                                        double* __restrict__ out) {
+template <typename TI, typename TO>
+__global__ __launch_bounds__(TBX* TBY) void k_mask_copy(Geo g, const TI* __restrict__ in,
+                                                        TO* __restrict__ out) {
   const int i = blockIdx.x * TBX + threadIdx.x;
   const int j = blockIdx.y * TBY + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nnx || j >= g.nny) return;
   const long long n = geo_node(g, i, j, k);
-  out[n] = geo_fixed(g, i, j, k) ? 0.0 : in[n];
+  out[n] = geo_fixed(g, i, j, k) ? TO(0) : (TO)in[n];
 }
 
 // ---------------------------------------------------------------------------
@@ -772,17 +772,17 @@ __device__ inline void tnode_ijk(const Geo& g, int n, int& i, int& j, int& k) {
   i = r - j * g.nnx;
 }
 
-template <int DIM, int MODE>
-__device__ void tail_stencil(const Geo& g, const double* x, const double* k, const double* b,
-                             double* out, double omega) {
+template <int DIM, int MODE, typename T>
+__device__ void tail_stencil(const Geo& g, const T* x, const T* k, const T* b, T* out, T omega) {
   for (int n = threadIdx.x; n < (int)g.nn; n += TT) {
     int i, j, kz;
     tnode_ijk(g, n, i, j, kz);
-    double r = 0.0;
+    T r = T(0);
     if (!geo_fixed(g, i, j, kz)) {
-      double kv[2][2][2];
-      load_cells<DIM, false>(g, k, nullptr, i, j, kz, kv);
-      double ks = 0.0, y = 0.0;
+      T kv[2][2][2];
+      const CellP<T> kl{k};
+      load_cells<DIM, false>(g, kl, kl, i, j, kz, kv);
+      T ks = T(0), y = T(0);
       if (MODE == SM_JACOBI0) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -791,9 +791,9 @@ __device__ void tail_stencil(const Geo& g, const double* x, const double* k, con
 #pragma unroll
             for (int a = 0; a < 2; ++a) ks += kv[c][bb][a];
       } else {
-        y = node_apply<DIM>(g, x, i, j, kz, kv, ks);
+        y = node_apply<DIM, T>(g, x, i, j, kz, kv, ks);
       }
-      const double diag = (DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ks;
+      const T diag = T(DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ks;
       if (MODE == SM_JACOBI0) r = omega * b[n] / diag;
       else if (MODE == SM_RESID) r = b[n] - y;
       else r = x[n] + omega * (b[n] - y) / diag;   // SM_JACOBI
@@ -802,42 +802,42 @@ __device__ void tail_stencil(const Geo& g, const double* x, const double* k, con
   }
 }
 
-template <int DIM>
-__device__ void tail_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc) {
+template <int DIM, typename T>
+__device__ void tail_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc) {
   for (int n = threadIdx.x; n < (int)gc.nn; n += TT) {
     int I, J, K;
     tnode_ijk(gc, n, I, J, K);
-    double s = 0.0;
+    T s = T(0);
     if (!geo_fixed(gc, I, J, K)) {
       for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
-        double sy = 0.0;
+        T sy = T(0);
         for (int b = -1; b <= 1; ++b) {
-          double sx = 0.0;
-          for (int a = -1; a <= 1; ++a) sx += (a == 0 ? 1.0 : 0.5) * ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
-          sy += (b == 0 ? 1.0 : 0.5) * sx;
+          T sx = T(0);
+          for (int a = -1; a <= 1; ++a) sx += T(a == 0 ? 1.0 : 0.5) * ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
+          sy += T(b == 0 ? 1.0 : 0.5) * sx;
         }
-        s += (c == 0 ? 1.0 : 0.5) * sy;
+        s += T(c == 0 ? 1.0 : 0.5) * sy;
       }
     }
     rc[n] = s;
   }
 }
 
-template <int DIM>
-__device__ void tail_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf) {
+template <int DIM, typename T>
+__device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf) {
   for (int n = threadIdx.x; n < (int)gf.nn; n += TT) {
     int i, j, k;
     tnode_ijk(gf, n, i, j, k);
     if (geo_fixed(gf, i, j, k)) continue;
     const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
     const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-    const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0,
-                 wk = (DIM == 3 && (k & 1)) ? 0.5 : 1.0;
-    double s = 0.0;
+    const T wi = T((i & 1) ? 0.5 : 1.0), wj = T((j & 1) ? 0.5 : 1.0),
+            wk = T((DIM == 3 && (k & 1)) ? 0.5 : 1.0);
+    T s = T(0);
     for (int c = 0; c < nk; ++c) {
-      double sy = 0.0;
+      T sy = T(0);
       for (int b = 0; b < nj; ++b) {
-        double sx = 0.0;
+        T sx = T(0);
         for (int a = 0; a < ni; ++a) sx += xc[geo_node(gc, I0 + a, J0 + b, K0 + c)];
         sy += wi * sx;
       }
@@ -849,76 +849,79 @@ __device__ void tail_prolong(const Geo& gf, const Geo& gc, const double* xc, dou
 
 // x = A^-1 b with A symmetric (n <= 1024): `tpr` threads per row, each summing
 // a strided share of the columns, combined by a wave shuffle tree.
-__device__ void tail_coarse(int n, const double* __restrict__ A, const double* b, double* x) {
+template <typename T>
+__device__ void tail_coarse(int n, const double* __restrict__ A, const T* b, T* x) {
   int tpr = 1;
   while (tpr * 2 * n <= TT && tpr < 64) tpr *= 2;
   const int row = threadIdx.x / tpr, sub = threadIdx.x % tpr;
   double s = 0.0;
   if (row < n)
-    for (int jj = sub; jj < n; jj += tpr) s += A[(long long)jj * n + row] * b[jj];
+    for (int jj = sub; jj < n; jj += tpr) s += A[(long long)jj * n + row] * (double)b[jj];
   for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, MGAR_WAVE);
-  if (row < n && sub == 0) x[row] = s;
+  if (row < n && sub == 0) x[row] = (T)s;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(TT) void k_vtail(TailSpec T, const double* __restrict__ bin,
-                                              double* __restrict__ xout,
-                                              const double* __restrict__ Ainv, double omega,
+template <int DIM, typename T>
+__global__ __launch_bounds__(TT) void k_vtail(TailSpec TS, const T* __restrict__ bin,
+                                              T* __restrict__ xout,
+                                              const double* __restrict__ Ainv, T omega,
                                               const int* __restrict__ done) {
   if (done && *done) return;
-  extern __shared__ double lds[];
-  const int nl = T.nl;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const int nl = TS.nl;
   for (int l = 0; l < nl; ++l)
-    for (int e = threadIdx.x; e < (int)T.g[l].ne; e += TT) lds[T.off_k[l] + e] = T.k[l][e];
-  for (int n = threadIdx.x; n < (int)T.g[0].nn; n += TT) lds[T.off_b[0] + n] = bin[n];
+    for (int e = threadIdx.x; e < (int)TS.g[l].ne; e += TT) lds[TS.off_k[l] + e] = static_cast<const T*>(TS.k[l])[e];
+  for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) lds[TS.off_b[0] + n] = bin[n];
   __syncthreads();
   for (int l = 0; l + 1 < nl; ++l) {
-    const Geo& g = T.g[l];
-    double* b = lds + T.off_b[l];
-    double* xa = lds + T.off_xa[l];
-    double* xb = lds + T.off_xb[l];
-    const double* kk = lds + T.off_k[l];
-    tail_stencil<DIM, SM_JACOBI0>(g, nullptr, kk, b, xa, omega);
+    const Geo& g = TS.g[l];
+    T* b = lds + TS.off_b[l];
+    T* xa = lds + TS.off_xa[l];
+    T* xb = lds + TS.off_xb[l];
+    const T* kk = lds + TS.off_k[l];
+    tail_stencil<DIM, SM_JACOBI0, T>(g, nullptr, kk, b, xa, omega);
     __syncthreads();
-    tail_stencil<DIM, SM_RESID>(g, xa, kk, b, xb, omega);
+    tail_stencil<DIM, SM_RESID, T>(g, xa, kk, b, xb, omega);
     __syncthreads();
-    tail_restrict<DIM>(g, T.g[l + 1], xb, lds + T.off_b[l + 1]);
+    tail_restrict<DIM, T>(g, TS.g[l + 1], xb, lds + TS.off_b[l + 1]);
     __syncthreads();
   }
-  tail_coarse((int)T.g[nl - 1].nn, Ainv, lds + T.off_b[nl - 1], lds + T.off_xa[nl - 1]);
+  tail_coarse((int)TS.g[nl - 1].nn, Ainv, lds + TS.off_b[nl - 1], lds + TS.off_xa[nl - 1]);
   __syncthreads();
-  const double* xfin = lds + T.off_xa[nl - 1];
+  const T* xfin = lds + TS.off_xa[nl - 1];
   for (int l = nl - 2; l >= 0; --l) {
-    const Geo& g = T.g[l];
-    double* xa = lds + T.off_xa[l];
-    double* xb = lds + T.off_xb[l];
-    tail_prolong<DIM>(g, T.g[l + 1], xfin, xa);
+    const Geo& g = TS.g[l];
+    T* xa = lds + TS.off_xa[l];
+    T* xb = lds + TS.off_xb[l];
+    tail_prolong<DIM, T>(g, TS.g[l + 1], xfin, xa);
     __syncthreads();
-    tail_stencil<DIM, SM_JACOBI>(g, xa, lds + T.off_k[l], lds + T.off_b[l], xb, omega);
+    tail_stencil<DIM, SM_JACOBI, T>(g, xa, lds + TS.off_k[l], lds + TS.off_b[l], xb, omega);
     __syncthreads();
     xfin = xb;
   }
-  for (int n = threadIdx.x; n < (int)T.g[0].nn; n += TT) xout[n] = xfin[n];
+  for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) xout[n] = xfin[n];
 }
 
 dim3 node_grid(const Geo& g) {
   return dim3((g.nnx + TBX - 1) / TBX, (g.nny + TBY - 1) / TBY, g.nnz);
 }
 
-template <int DIM>
-void stencil_dispatch(const Geo& g, int mode, const double* x, const double* k, const double* kref,
-                      const double* b, double* out, double omega, double* part, const int* done,
-                      unsigned* cnt, double* rout, hipStream_t s) {
+template <int DIM, typename T, typename CL>
+void stencil_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out, T omega,
+                      double* part, const int* done, unsigned* cnt, double* rout, hipStream_t s) {
   const dim3 grid = node_grid(g), blk(TBX, TBY, 1);
+#define SCALL(M) k_stencil<DIM, M, T, CL><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout)
   switch (mode) {
-    case SM_APPLY: k_stencil<DIM, SM_APPLY><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_APPLY_DOT: k_stencil<DIM, SM_APPLY_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_RESID: k_stencil<DIM, SM_RESID><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_JACOBI: k_stencil<DIM, SM_JACOBI><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_JACOBI_DOT: k_stencil<DIM, SM_JACOBI_DOT><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_JACOBI0: k_stencil<DIM, SM_JACOBI0><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
-    case SM_NEG_DK: k_stencil<DIM, SM_NEG_DK><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); break;
+    case SM_APPLY: SCALL(SM_APPLY); break;
+    case SM_APPLY_DOT: SCALL(SM_APPLY_DOT); break;
+    case SM_RESID: SCALL(SM_RESID); break;
+    case SM_JACOBI: SCALL(SM_JACOBI); break;
+    case SM_JACOBI_DOT: SCALL(SM_JACOBI_DOT); break;
+    case SM_JACOBI0: SCALL(SM_JACOBI0); break;
+    case SM_NEG_DK: SCALL(SM_NEG_DK); break;
   }
+#undef SCALL
 }
 
 constexpr int ZMARCH_MIN_NODES = 20000;
@@ -941,38 +944,34 @@ ZShape zmarch_shape(const Geo& g) {
   return z;
 }
 
-void zmarch_dispatch(const Geo& g, const Geo* gc, int mode, const double* x, const double* ec,
-                     const double* k, const double* kref, const double* b, double* out,
-                     double omega, double* part, const int* done, unsigned* cnt, double* rout,
-                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+template <typename T, typename CL>
+void zmarch_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out, T omega,
+                     double* part, const int* done, unsigned* cnt, double* rout, hipStream_t s,
+                     hipEvent_t ev0, hipEvent_t ev1) {
   const ZShape z = zmarch_shape(g);
   const int nb = z.ntx * z.nty * z.nzc;
-  const Geo gcc = gc ? *gc : g;
+  const T* ec = nullptr;
   // With events, the launch goes through hipExtLaunchKernelGGL, which records
   // them at the start and end of the kernel itself (no dispatch latency).
-#define ZCALL(M, XPOL)                                                                          \
-  do {                                                                                          \
-    if (ev0)                                                                                    \
-      hipExtLaunchKernelGGL((k_stencil_z<M, XPOL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, gcc, \
-                            z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out, omega, part, \
-                            done, cnt, rout);                                                   \
-    else                                                                                        \
-      k_stencil_z<M, XPOL><<<nb, ZT, 0, s>>>(g, gcc, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, \
-                                             b, out, omega, part, done, cnt, rout);            \
+#define ZCALL(M)                                                                                 \
+  do {                                                                                           \
+    if (ev0)                                                                                     \
+      hipExtLaunchKernelGGL((k_stencil_z<M, XP_PLAIN, 1, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, \
+                            0, g, g, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out,     \
+                            omega, part, done, cnt, rout);                                       \
+    else                                                                                         \
+      k_stencil_z<M, XP_PLAIN, 1, T, CL><<<nb, ZT, 0, s>>>(g, g, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, \
+                                                           k, kref, b, out, omega, part, done,   \
+                                                           cnt, rout);                           \
   } while (0)
-  if (gc) {
-    if (mode == SM_JACOBI) ZCALL(SM_JACOBI, XP_PROLONG);
-    else ZCALL(SM_JACOBI_DOT, XP_PROLONG);
-    return;
-  }
   switch (mode) {
-    case SM_APPLY: ZCALL(SM_APPLY, XP_PLAIN); break;
-    case SM_APPLY_DOT: ZCALL(SM_APPLY_DOT, XP_PLAIN); break;
-    case SM_RESID: ZCALL(SM_RESID, XP_PLAIN); break;
-    case SM_JACOBI: ZCALL(SM_JACOBI, XP_PLAIN); break;
-    case SM_JACOBI_DOT: ZCALL(SM_JACOBI_DOT, XP_PLAIN); break;
-    case SM_JACOBI0: ZCALL(SM_JACOBI0, XP_PLAIN); break;
-    case SM_NEG_DK: ZCALL(SM_NEG_DK, XP_PLAIN); break;
+    case SM_APPLY: ZCALL(SM_APPLY); break;
+    case SM_APPLY_DOT: ZCALL(SM_APPLY_DOT); break;
+    case SM_RESID: ZCALL(SM_RESID); break;
+    case SM_JACOBI: ZCALL(SM_JACOBI); break;
+    case SM_JACOBI_DOT: ZCALL(SM_JACOBI_DOT); break;
+    case SM_JACOBI0: ZCALL(SM_JACOBI0); break;
+    case SM_NEG_DK: ZCALL(SM_NEG_DK); break;
   }
 #undef ZCALL
 }
@@ -988,63 +987,90 @@ int stencil_num_partials(const Geo& g) {
   return (int)(grid.x * grid.y * grid.z);
 }
 
-int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
-                   const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s, unsigned* cnt, double* rout, hipEvent_t ev0, hipEvent_t ev1) {
-  if (use_zmarch(g)) zmarch_dispatch(g, nullptr, mode, x, nullptr, k, kref, b, out, omega, part, done, cnt, rout, s, ev0, ev1);
-  else if (g.dim == 2) stencil_dispatch<2>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
-  else stencil_dispatch<3>(g, mode, x, k, kref, b, out, omega, part, done, cnt, rout, s);
+bool stencil_records_events(const Geo& g) { return use_zmarch(g); }
+
+template <typename T, typename CL>
+int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out,
+                     double omega, double* part, const int* done, hipStream_t s, unsigned* cnt,
+                     double* rout, hipEvent_t ev0, hipEvent_t ev1) {
+  if (use_zmarch(g))
+    zmarch_dispatch<T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s, ev0, ev1);
+  else if (g.dim == 2)
+    stencil_dispatch<2, T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s);
+  else
+    stencil_dispatch<3, T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s);
   return (mode == SM_APPLY_DOT || mode == SM_JACOBI_DOT) ? stencil_num_partials(g) : 0;
 }
 
-bool stencil_fuses_prolong(const Geo& g) { return use_zmarch(g); }
-bool stencil_records_events(const Geo& g) { return use_zmarch(g); }
+template int launch_stencil_t<double, CellD>(const Geo&, int, const double*, CellD, CellD, const double*,
+                                             double*, double, double*, const int*, hipStream_t,
+                                             unsigned*, double*, hipEvent_t, hipEvent_t);
+template int launch_stencil_t<float, CellF>(const Geo&, int, const float*, CellF, CellF, const float*,
+                                            float*, double, double*, const int*, hipStream_t,
+                                            unsigned*, double*, hipEvent_t, hipEvent_t);
+template int launch_stencil_t<float, CellB>(const Geo&, int, const float*, CellB, CellB, const float*,
+                                            float*, double, double*, const int*, hipStream_t,
+                                            unsigned*, double*, hipEvent_t, hipEvent_t);
 
-int launch_prolong_smooth(const Geo& g, const Geo& gc, const double* xa, const double* ec,
-                          const double* k, const double* b, double* out, double omega,
-                          double* part, const int* done, hipStream_t s) {
-  zmarch_dispatch(g, &gc, part ? SM_JACOBI_DOT : SM_JACOBI, xa, ec, k, nullptr, b, out, omega, part,
-                  done, nullptr, nullptr, s);
-  return part ? stencil_num_partials(g) : 0;
+int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
+                   const double* b, double* out, double omega, double* part, const int* done,
+                   hipStream_t s, unsigned* cnt, double* rout, hipEvent_t ev0, hipEvent_t ev1) {
+  return launch_stencil_t<double, CellD>(g, mode, x, CellD{k}, CellD{kref}, b, out, omega, part, done, s,
+                                         cnt, rout, ev0, ev1);
 }
 
-void launch_restrict(const Geo& gf, const Geo& gc, const double* rf, double* rc, const int* done,
-                     hipStream_t s) {
+template <typename T>
+void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s) {
   const dim3 grid = node_grid(gc), blk(TBX, TBY, 1);
-  if (gf.dim == 2) k_restrict<2><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
-  else k_restrict<3><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
+  if (gf.dim == 2) k_restrict<2, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
+  else k_restrict<3, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
 }
+template void launch_restrict_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
+template void launch_restrict_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);
 
-void launch_prolong(const Geo& gf, const Geo& gc, const double* xc, double* xf, const int* done,
-                    hipStream_t s) {
+template <typename T>
+void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s) {
   const dim3 grid = node_grid(gf), blk(TBX, TBY, 1);
-  if (gf.dim == 2) k_prolong<2><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
-  else k_prolong<3><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
+  if (gf.dim == 2) k_prolong<2, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
+  else k_prolong<3, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
 }
+template void launch_prolong_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
+template void launch_prolong_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);
 
-void launch_coarsen(const Geo& gf, const Geo& gc, const double* kf, double* kc, hipStream_t s) {
+template <typename CL, typename TO>
+void launch_coarsen_t(const Geo& gf, const Geo& gc, CL kf, TO* kc, hipStream_t s) {
   const int nb = (int)((gc.ne + 255) / 256);
-  if (gf.dim == 2) k_coarsen<2><<<nb, 256, 0, s>>>(gf, gc, kf, kc);
-  else k_coarsen<3><<<nb, 256, 0, s>>>(gf, gc, kf, kc);
+  if (gf.dim == 2) k_coarsen<2, CL, TO><<<nb, 256, 0, s>>>(gf, gc, kf, kc);
+  else k_coarsen<3, CL, TO><<<nb, 256, 0, s>>>(gf, gc, kf, kc);
 }
+template void launch_coarsen_t<CellD, double>(const Geo&, const Geo&, CellD, double*, hipStream_t);
+template void launch_coarsen_t<CellF, float>(const Geo&, const Geo&, CellF, float*, hipStream_t);
+template void launch_coarsen_t<CellB, float>(const Geo&, const Geo&, CellB, float*, hipStream_t);
 
-void launch_coarse_build(const Geo& g, const double* k, double* A, int* status, hipStream_t s) {
+template <typename CL>
+void launch_coarse_build_t(const Geo& g, CL k, double* A, int* status, hipStream_t s) {
   if (g.nn <= 128) {
-    if (g.dim == 2) k_coarse_build_reg<2><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
-    else k_coarse_build_reg<3><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    if (g.dim == 2) k_coarse_build_reg<2, CL><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    else k_coarse_build_reg<3, CL><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
   } else {
-    if (g.dim == 2) k_coarse_build<2><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
-    else k_coarse_build<3><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    if (g.dim == 2) k_coarse_build<2, CL><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
+    else k_coarse_build<3, CL><<<1, CB_THREADS, 0, s>>>(g, k, A, status);
   }
 }
+template void launch_coarse_build_t<CellD>(const Geo&, CellD, double*, int*, hipStream_t);
+template void launch_coarse_build_t<CellF>(const Geo&, CellF, double*, int*, hipStream_t);
+template void launch_coarse_build_t<CellB>(const Geo&, CellB, double*, int*, hipStream_t);
 
-void launch_coarse_solve(const Geo& g, const double* A, const double* b, double* x,
-                         const int* done, hipStream_t s) {
+template <typename T>
+void launch_coarse_solve_t(const Geo& g, const double* A, const T* b, T* x, const int* done,
+                           hipStream_t s) {
   const int n = (int)g.nn;
-  k_coarse_solve<<<(n + 255) / 256, 256, 0, s>>>(n, A, b, x, done);
+  k_coarse_solve<T><<<(n + 255) / 256, 256, 0, s>>>(n, A, b, x, done);
 }
+template void launch_coarse_solve_t<double>(const Geo&, const double*, const double*, double*, const int*, hipStream_t);
+template void launch_coarse_solve_t<float>(const Geo&, const double*, const float*, float*, const int*, hipStream_t);
 
-bool tail_plan(const Geo* g, double* const* k, int lt, int L, TailSpec* T) {
+bool tail_plan(const Geo* g, const void* const* k, int lt, int L, size_t elem, TailSpec* T) {
   const int nl = L - lt;
   if (nl < 1 || nl > MGAR_MAX_TAIL) return false;
   int off = 0;
@@ -1058,17 +1084,25 @@ bool tail_plan(const Geo* g, double* const* k, int lt, int L, TailSpec* T) {
     T->off_k[l] = off; off += (int)gl.ne;
   }
   T->nl = nl;
-  T->lds_doubles = off;
-  return off * 8 <= 64 * 1024 && g[lt].nn <= 4096;
+  T->lds_elems = off;
+  T->elem = (int)elem;
+  return (size_t)off * elem <= 64 * 1024 && g[lt].nn <= 4096;
 }
 
-void launch_vtail(const TailSpec& T, const double* b_in, double* x_out, const double* Ainv,
-                  double omega, const int* done, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)T.lds_doubles;
-  if (T.g[0].dim == 2) k_vtail<2><<<1, TT, lds, s>>>(T, b_in, x_out, Ainv, omega, done);
-  else k_vtail<3><<<1, TT, lds, s>>>(T, b_in, x_out, Ainv, omega, done);
+template <typename T>
+void launch_vtail_t(const TailSpec& TS, const T* b_in, T* x_out, const double* Ainv, double omega,
+                    const int* done, hipStream_t s) {
+  const size_t lds = sizeof(T) * (size_t)TS.lds_elems;
+  if (TS.g[0].dim == 2) k_vtail<2, T><<<1, TT, lds, s>>>(TS, b_in, x_out, Ainv, (T)omega, done);
+  else k_vtail<3, T><<<1, TT, lds, s>>>(TS, b_in, x_out, Ainv, (T)omega, done);
 }
+template void launch_vtail_t<double>(const TailSpec&, const double*, double*, const double*, double, const int*, hipStream_t);
+template void launch_vtail_t<float>(const TailSpec&, const float*, float*, const double*, double, const int*, hipStream_t);
 
-void launch_mask_copy(const Geo& g, const double* in, double* out, hipStream_t s) {
-  k_mask_copy<<<node_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, in, out);
+template <typename TI, typename TO>
+void launch_mask_copy_t(const Geo& g, const TI* in, TO* out, hipStream_t s) {
+  k_mask_copy<TI, TO><<<node_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, in, out);
 }
+template void launch_mask_copy_t<double, double>(const Geo&, const double*, double*, hipStream_t);
+template void launch_mask_copy_t<double, float>(const Geo&, const double*, float*, hipStream_t);
+template void launch_mask_copy_t<float, double>(const Geo&, const float*, double*, hipStream_t);

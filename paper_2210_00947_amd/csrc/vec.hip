@@ -12,8 +12,9 @@ constexpr int VB = 256;          // threads per block for vector kernels
 constexpr int VMAXB = 1024;      // maximum blocks (so at most 1024 partials)
 constexpr int FB = 1024;         // finalize block size
 
-__global__ __launch_bounds__(VB) void k_dot(const double* __restrict__ a,
-                                            const double* __restrict__ b, long long n,
+template <typename TA, typename TB>
+__global__ __launch_bounds__(VB) void k_dot(const TA* __restrict__ a,
+                                            const TB* __restrict__ b, long long n,
                                             double* __restrict__ part,
                                             const int* __restrict__ done,
                                             unsigned* __restrict__ cnt, double* __restrict__ rout) {
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(VB) void k_dot(const double* __restrict__ a,
   __shared__ double sh[VB / MGAR_WAVE];
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
-    s += a[i] * b[i];
+    s += (double)a[i] * (double)b[i];
   s = block_sum(s, sh);
   if (cnt) grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
   else if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -57,11 +58,12 @@ __global__ __launch_bounds__(FB) void k_cg_init(CgState* st, const double* __res
 }
 
 // p = z + beta p, beta = rz_k / rz_{k-1} (Fletcher-Reeves); p = z at k = 0.
-__global__ __launch_bounds__(VB) void k_p_update(const double* __restrict__ z, double* __restrict__ p,
+template <typename T>
+__global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __restrict__ p,
                                                  long long n, const CgState* __restrict__ st,
                                                  int it) {
   if (st->done) return;
-  const double beta = (it == 0) ? 0.0 : st->rz[it & 1] / st->rz[(it - 1) & 1];
+  const T beta = (T)((it == 0) ? 0.0 : st->rz[it & 1] / st->rz[(it - 1) & 1]);
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
 }
@@ -69,22 +71,23 @@ __global__ __launch_bounds__(VB) void k_p_update(const double* __restrict__ z, d
 // x += alpha p, r -= alpha w with alpha = rz / (p . w); ||r||^2 reduced in
 // the same launch, and the last block applies the stopping test that precedes
 // iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max).
-__global__ __launch_bounds__(VB) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
-                                                  const double* __restrict__ p,
-                                                  const double* __restrict__ w, long long n,
+template <typename T>
+__global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
+                                                  const T* __restrict__ p,
+                                                  const T* __restrict__ w, long long n,
                                                   CgState* __restrict__ st, int it,
                                                   double* __restrict__ part,
                                                   unsigned* __restrict__ cnt, double tol,
                                                   int cg_max) {
   if (st->done) return;
   __shared__ double sh[VB / MGAR_WAVE];
-  const double alpha = st->rz[it & 1] / st->pw;
+  const T alpha = (T)(st->rz[it & 1] / st->pw);
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
     x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * w[i];
+    const T ri = r[i] - alpha * w[i];
     r[i] = ri;
-    s += ri * ri;
+    s += (double)ri * (double)ri;
   }
   s = block_sum(s, sh);
   if (!cnt) {
@@ -330,6 +333,28 @@ __global__ __launch_bounds__(VB) void k_combine(const double* __restrict__ Q,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Round to BF16 with round-to-nearest-even, going through FP32 exactly as a
+// float -> bfloat16 conversion of an FP32 value does (NaN kept quiet).
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
+  const uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7fffu + lsb) >> 16);
+}
+
+__global__ __launch_bounds__(VB) void k_cast_bf16(const double* __restrict__ a, uint16_t* __restrict__ b,
+                                                  long long n) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    b[i] = f32_to_bf16_rne((float)a[i]);
+}
+
+// x += d with d in FP32 and x in FP64 (the refinement update).
+__global__ __launch_bounds__(VB) void k_add_f32(double* __restrict__ x, const float* __restrict__ d,
+                                                long long n) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    x[i] += (double)d[i];
+}
+
 #define MGAR_DISPATCH_M(m, CALL)                                    \
   switch (m) {                                                      \
     case 1: CALL(1); break; case 2: CALL(2); break;                 \
@@ -347,11 +372,21 @@ int vec_num_blocks(long long n) {
   return (int)nb;
 }
 
+template <typename TA, typename TB>
+int launch_dot_t(const TA* a, const TB* b, long long n, double* part, const int* done, hipStream_t s,
+                 unsigned* cnt, double* rout) {
+  const int nb = vec_num_blocks(n);
+  k_dot<TA, TB><<<nb, VB, 0, s>>>(a, b, n, part, done, cnt, rout);
+  return nb;
+}
+template int launch_dot_t<double, double>(const double*, const double*, long long, double*, const int*,
+                                          hipStream_t, unsigned*, double*);
+template int launch_dot_t<float, float>(const float*, const float*, long long, double*, const int*,
+                                        hipStream_t, unsigned*, double*);
+
 int launch_dot(const double* a, const double* b, long long n, double* part, const int* done,
                hipStream_t s, unsigned* cnt, double* rout) {
-  const int nb = vec_num_blocks(n);
-  k_dot<<<nb, VB, 0, s>>>(a, b, n, part, done, cnt, rout);
-  return nb;
+  return launch_dot_t<double, double>(a, b, n, part, done, s, cnt, rout);
 }
 
 void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s) {
@@ -368,17 +403,34 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
   k_cg_init<<<1, FB, 0, s>>>(st, part_qq, nq, part_rr, nr, tol, cg_max);
 }
 
+template <typename T>
+void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, int it, hipStream_t s) {
+  k_p_update<T><<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st, it);
+}
+template void launch_p_update_t<double>(const double*, double*, long long, const CgState*, int, hipStream_t);
+template void launch_p_update_t<float>(const float*, float*, long long, const CgState*, int, hipStream_t);
+
 void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
                      hipStream_t s) {
-  k_p_update<<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st, it);
+  launch_p_update_t<double>(z, p, n, st, it, s);
 }
+
+template <typename T>
+int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, int it,
+                       double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part, cnt, tol, cg_max);
+  return nb;
+}
+template int launch_cg_update_t<double>(double*, double*, const double*, const double*, long long,
+                                        CgState*, int, double*, unsigned*, double, int, hipStream_t);
+template int launch_cg_update_t<float>(float*, float*, const float*, const float*, long long,
+                                       CgState*, int, double*, unsigned*, double, int, hipStream_t);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
                      CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
                      hipStream_t s) {
-  const int nb = vec_num_blocks(n);
-  k_cg_update<<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part, cnt, tol, cg_max);
-  return nb;
+  return launch_cg_update_t<double>(x, r, p, w, n, st, it, part, cnt, tol, cg_max, s);
 }
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
@@ -435,4 +487,16 @@ int launch_combine(const double* Q, const double* W, const double* q, int m, lon
   MGAR_DISPATCH_M(m, CALL_C)
 #undef CALL_C
   return nb;
+}
+
+void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s) {
+  k_cast_bf16<<<vec_num_blocks(n), VB, 0, s>>>(a, b, n);
+}
+
+void launch_add_f32(double* x, const float* d, long long n, hipStream_t s) {
+  k_add_f32<<<vec_num_blocks(n), VB, 0, s>>>(x, d, n);
+}
+
+void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s) {
+  (void)hipMemcpyAsync(b, a, sizeof(uint16_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
 }

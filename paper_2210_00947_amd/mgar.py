@@ -32,7 +32,7 @@ EXPORTS = [
     "mgar_sizes", "mgar_load_vector", "mgar_density_filter", "mgcg_solve", "mgar_solve",
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
-    "mgar_vcycle", "mgar_op_dk", "mgar_profile", "mgar_profile_read",
+    "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_profile", "mgar_profile_read",
 ]
 
 
@@ -44,7 +44,7 @@ class mgar_params(ctypes.Structure):
         ("k0", ctypes.c_double), ("kmin", ctypes.c_double), ("penal", ctypes.c_double),
         ("omega", ctypes.c_double), ("n_basis", ctypes.c_int), ("eps_accept", ctypes.c_double),
         ("cg_max", ctypes.c_int), ("basis_x0_zero", ctypes.c_int), ("precision", ctypes.c_int),
-        ("filter_r", ctypes.c_double),
+        ("filter_r", ctypes.c_double), ("inner_tol", ctypes.c_double),
     ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.mgar_build_hierarchy.argtypes = [P, VP]
         L.mgar_vcycle.argtypes = [P, VP, VP, VP]
         L.mgar_op_dk.argtypes = [P, VP, VP, VP]
+        L.mgar_op_bf16.argtypes = [P, VP, VP]
         L.mgar_profile.argtypes = [P, ctypes.c_uint]
         L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
         for f in EXPORTS:
@@ -137,7 +138,7 @@ def _check(rc, where, warn_ok=True):
 
 
 def params_for(prob, n_basis=2, eps_accept=None, cg_max=200, omega=0.8, basis_x0_zero=False,
-               precision=PREC_FP64):
+               precision=PREC_FP64, inner_tol=None):
     """mgar_params from a workloads.Problem description."""
     p = mgar_params()
     lib().mgar_default_params(ctypes.byref(p))
@@ -155,6 +156,8 @@ def params_for(prob, n_basis=2, eps_accept=None, cg_max=200, omega=0.8, basis_x0
     p.basis_x0_zero = int(bool(basis_x0_zero))
     p.precision = precision
     p.filter_r = prob.filter_r
+    if inner_tol is not None:
+        p.inner_tol = inner_tol
     return p
 
 
@@ -274,6 +277,14 @@ class Handle:
         _check(self._L.mgar_op_dk(self.h, _ptr(xphys, self.E, "xphys"), _ptr(r, self.N, "r"),
                                   _ptr(b, self.N, "b")), "mgar_op_dk")
 
+
+    def mgar_op_bf16(self, x, out):
+        """out: int16 GPU tensor with E entries (the BF16 bit patterns)."""
+        import torch
+        if out.dtype != torch.int16 or not out.is_cuda or out.numel() != self.E:
+            raise ValueError("out must be an int16 GPU tensor with E entries")
+        _check(self._L.mgar_op_bf16(self.h, _ptr(x, self.E, "x"), ctypes.c_void_p(out.data_ptr())),
+               "mgar_op_bf16")
 
     def mgar_profile(self, mode_mask):
         _check(self._L.mgar_profile(self.h, ctypes.c_uint(mode_mask)), "mgar_profile")

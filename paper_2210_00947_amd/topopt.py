@@ -25,15 +25,18 @@ class Cycle:
     res_final: float
     solve_ms: float
     lam: float
+    refinements: int = 0
 
 
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
-                 eps_accept=None, basis_x0_zero=False, device="cuda"):
+                 eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
+                 device="cuda"):
         self.prob = prob
         self.use_mgar = use_mgar
         self.params = M.params_for(prob, n_basis=n_basis, eps_accept=eps_accept, cg_max=cg_max,
-                                   basis_x0_zero=basis_x0_zero)
+                                   basis_x0_zero=basis_x0_zero, precision=precision,
+                                   inner_tol=inner_tol)
         self.h = M.Handle(self.params)
         N, E = self.h.N, self.h.E
         f64 = dict(dtype=torch.float64, device=device)
@@ -66,7 +69,7 @@ class TopOpt:
         self.x, self.xnew = self.xnew, self.x
         self.T, self.T_prev = self.T_prev, self.T
         return Cycle(self.k, f, st["path"], st["cg_iters"], st["res_ca"], st["res_final"],
-                     st["ms"], lam)
+                     st["ms"], lam, st["refinements"])
 
     def run(self, ncycles=None):
         n = self.prob.maxit if ncycles is None else ncycles

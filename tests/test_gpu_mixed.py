@@ -1,0 +1,135 @@
+"""Mixed-precision form on the GPU (FP32 multigrid and inner PCG over BF16
+densities, FP64 inner products, reduced solve and outer refinement residual)
+against the FP64 CPU oracle. Tolerances are stated per result; the measured
+errors are printed (pytest -s) and recorded in the design doc."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fe, mg, solvers, topopt
+from tests.gpu_util import dev, host, masked_random, rel_err, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+PROBS = [W.tiny_2d(40, 40, 3), W.tiny_3d(16, 16, 16, 3), W.tiny_3d(32, 32, 32, 4)]
+IDS = [p.name for p in PROBS]
+
+
+def mhandle(prob, **kw):
+    require_gpu()
+    from paper_2210_00947_amd import mgar as M
+    return M.Handle(M.params_for(prob, precision=M.PREC_MIXED, **kw))
+
+
+def bf16_round(x):
+    """Independent BF16 rounding: torch CPU float64 -> float32 -> bfloat16."""
+    import torch
+    t = torch.as_tensor(np.asarray(x, dtype=np.float64)).to(torch.float32).to(torch.bfloat16)
+    return t.to(torch.float64).numpy(), t.view(torch.int16).numpy()
+
+
+def test_bf16_cast_bit_exact():
+    import torch
+    prob = W.tiny_3d(16, 16, 16, 3)
+    h = mhandle(prob)
+    x = W.random_density(prob.nelem, 1, 0.0, 1.0)
+    # values on and next to BF16 rounding ties, and exact endpoints
+    x[:8] = [0.0, 1.0, 0.5, 0.3, 1.0 + 2 ** -8, 1.0 + 2 ** -9, 0.75 + 2 ** -10, 1e-30]
+    out = torch.empty(prob.nelem, dtype=torch.int16, device="cuda")
+    h.mgar_op_bf16(dev(x), out)
+    _, bits = bf16_round(x)
+    assert np.array_equal(host(out), bits)
+
+
+@pytest.mark.parametrize("prob", PROBS, ids=IDS)
+def test_mixed_vcycle(prob):
+    import torch
+    h = mhandle(prob)
+    xphys = W.random_density(prob.nelem, 5, 0.0, 1.0)
+    h.mgar_build_hierarchy(dev(xphys))
+    xb, _ = bf16_round(xphys)
+    hier = mg.Hierarchy(prob, fe.simp(xb))
+    lv = hier.levels[0]
+    b = masked_random(prob.nnodes, lv.fixed, 6)
+    want = np.zeros(prob.nnodes)
+    want[lv.free] = hier.vcycle(0, b[lv.free], np.zeros(lv.free.size))
+    x = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_vcycle(dev(b), None, x)
+    # FP32 arithmetic over the BF16-rounded operator: stated tolerance 2e-5
+    err = rel_err(host(x), want)
+    print(f"mixed V-cycle max rel err {prob.name}: {err:.2e}")
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("prob", PROBS + [W.C1], ids=IDS + ["c1"])
+def test_mixed_mgcg(prob):
+    import torch
+    h = mhandle(prob)
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    xphys = W.random_density(prob.nelem, 11, 0.0, 1.0)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    t_or, _ = s.mgcg(xphys, np.zeros(prob.nnodes), 1e-8)
+    T = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    st = h.mgcg_solve(dev(xphys), q, None, 1e-8, T)
+    assert st["rc"] == 0 and st["refinements"] >= 1
+    t = host(T)
+    fep = s.fep
+    r = fep.to_free(fep.q) - fep.K_free(xphys) @ t[fep.free]
+    res = np.linalg.norm(r) / np.linalg.norm(fep.to_free(fep.q))
+    err = rel_l2(t, t_or)
+    print(f"mixed MGCG {prob.name}: true rel. residual {res:.2e}, T rel L2 err {err:.2e}, "
+          f"{st['cg_iters']} inner its, {st['refinements']} refinements")
+    assert res <= 1.001e-8
+    assert err < 1e-6
+    assert np.all(t[fep.fixed] == 0)
+
+
+@pytest.mark.parametrize("prob", PROBS, ids=IDS)
+@pytest.mark.parametrize("eps,change", [(1e-8, "noise"), (0.5, "scale"), (0.5, "scale+noise")])
+def test_mixed_mgar(prob, eps, change):
+    import torch
+    h = mhandle(prob, eps_accept=eps)
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(eps_accept=eps))
+    x0 = W.random_density(prob.nelem, 21, 0.2, 0.8)
+    if change == "noise":
+        x1 = np.clip(x0 + 0.02 * W.random_vector(prob.nelem, 22), 0, 1)
+    else:
+        x1 = np.clip(1.01 * x0 + (1e-3 if change == "scale+noise" else 0.0)
+                     * W.random_vector(prob.nelem, 22), 0, 1)
+    t0, _ = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    t1, st_or = s.mgar(x1, t0, 1e-8)
+    st = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+    print(f"mixed MGAR {prob.name} eps {eps}: path {st['path']} (oracle {st_or.path}), "
+          f"Res {st['res_ca']:.4e} (oracle {st_or.res_ca:.4e}), T rel err {rel_l2(host(T1), t1):.2e}")
+    # Res is computed in FP64 on a basis built in FP32 over BF16 densities
+    assert abs(st["res_ca"] - st_or.res_ca) <= 1e-2 * st_or.res_ca
+    assert st["path"] == st_or.path == (2 if change == "noise" else 1)
+    tol = 1e-6 if st["path"] == 2 else 1e-4
+    assert rel_l2(host(T1), t1) < tol
+
+
+def test_mixed_loop_c0_errors():
+    """Full 50-cycle loop, mixed precision on the GPU against the FP64 oracle:
+    stated tolerances compliance 1e-6 rel., final design 1e-4 max-abs."""
+    require_gpu()
+    from paper_2210_00947_amd import mgar as M
+    from paper_2210_00947_amd.topopt import TopOpt
+    prob = W.C0
+    x_or, _, t_or, recs = topopt.run_loop(prob)
+    opt = TopOpt(prob, W.element_source(prob), precision=M.PREC_MIXED)
+    cyc = opt.run()
+    xg = host(opt.x)
+    cerr = max(abs(a.compliance - b.compliance) / b.compliance for a, b in zip(cyc, recs))
+    xerr = float(np.abs(xg - x_or).max())
+    terr = rel_l2(host(opt.temperature), t_or)
+    print(f"mixed loop C0: max compliance rel err {cerr:.2e}, final x max abs err {xerr:.2e}, "
+          f"final T rel err {terr:.2e}, refinements/cycle "
+          f"{np.mean([c.refinements for c in cyc]):.2f}, inner its/cycle {np.mean([c.cg_iters for c in cyc]):.1f}")
+    assert cerr < 1e-6
+    assert xerr < 1e-4

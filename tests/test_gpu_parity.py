@@ -181,6 +181,30 @@ def test_mgar_parity(prob, m, eps, x0zero):
         t_prev, Tin = t_or, Tout
 
 
+@pytest.mark.parametrize("prob", PROBS, ids=IDS)
+@pytest.mark.parametrize("m,noise", [(2, 0.0), (2, 1e-3), (4, 1e-3)])
+def test_mgar_accept_path(prob, m, noise):
+    """A small design change (uniform 1% scaling, optional noise): the reduced
+    solution is accepted (Eq 28 with eps1 = 0.5) and returned as Q y."""
+    import torch
+    eps = 0.5
+    h = handle(prob, n_basis=m, eps_accept=eps)
+    q = _load(prob, h)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(n_basis=m, eps_accept=eps))
+    x0 = W.random_density(prob.nelem, 21, 0.2, 0.8)
+    x1 = np.clip(1.01 * x0 + noise * W.random_vector(prob.nelem, 22), 0, 1)
+    t0, _ = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    t1, st_or = s.mgar(x1, t0, 1e-8)
+    st = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+    assert st_or.path == 1 and st["path"] == 1
+    assert st["cg_iters"] == 0
+    assert abs(st["res_ca"] - st_or.res_ca) <= 1e-7 * st_or.res_ca
+    assert rel_l2(host(T1), t1) < 1e-9
+
+
 @pytest.mark.parametrize("prob", PROBS[:3], ids=IDS[:3])
 def test_dk_apply(prob):
     import torch

@@ -60,6 +60,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0):
     for r in recs:
         paths[["mgcg", "accept", "fallback"][r.path]] += 1
     out = {
+        "tuned_shapes": opt.tune_source,
         "elapsed_s": el,
         "s_per_opt_iter": el / steps,
         "cg_iters_mean": sum(r.cg_iters for r in recs) / steps,

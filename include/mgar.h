@@ -165,6 +165,30 @@ int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b);
  * rounded to nearest even through FP32. out: E uint16 values (device). */
 int mgar_op_bf16(mgar_handle* h, const double* x, void* out);
 
+/* ---- Launch-shape tuning. ----------------------------------------------------
+ * Every stencil launch on grid `level` in mode `mode` (0 apply, 1 apply + dot,
+ * 2 residual, 3 Jacobi sweep, 4 Jacobi sweep + dot, 5 sweep from zero, 6 -dK
+ * apply) of precision class `cls` (0: FP64 kernels; 1: FP32 kernels of
+ * MGAR_PREC_MIXED) uses a launch shape of four ints {kind, kz, zd, ntx}:
+ * kind 0 = one thread per node; kind 1 = z-marching blocks (3D) over ntx tiles
+ * across x, kz node planes per block, a zd-deep (1 or 2) load queue. Every
+ * shape computes each node with the same arithmetic; only the summation order
+ * of the dot products of modes 1 and 4 depends on the shape. Setup installs a
+ * default shape everywhere.
+ *
+ * mgar_autotune times every candidate shape of each (class, level, mode) the
+ * solvers launch (classes of the handle's precision, grids above the
+ * single-workgroup tail), `reps` launches each on scratch data it allocates and
+ * frees, and installs the fastest. best_us (host, may be NULL) receives the
+ * winning average launch time in microseconds at [(cls*levels + level)*7 + mode]
+ * (0 where nothing was tuned); it must hold 2*levels*7 doubles. Not to be
+ * called while other work of the handle is in flight.
+ * mgar_tune_get / mgar_tune_set read and install one shape (host int[4]), e.g.
+ * from a cache; set returns MGAR_E_ARG for a shape the grid cannot take. */
+int mgar_autotune(mgar_handle* h, int reps, double* best_us);
+int mgar_tune_get(const mgar_handle* h, int cls, int level, int mode, int* shape);
+int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape);
+
 /* ---- Instrumentation. ------------------------------------------------------
  * Kernel timing for roofline reports: while enabled, every launch of a
  * finest-grid stencil kernel whose mode bit is set in `mode_mask` is bracketed

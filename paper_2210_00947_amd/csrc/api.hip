@@ -4,6 +4,8 @@
 // Every numerical step runs in the kernels of stencil.hip, vec.hip and
 // topopt.hip on the handle's stream. The host only sequences launches and
 // reads back a few scalars (stopping flags, the Eq 28 residual, compliance).
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -61,6 +63,8 @@ struct mgar_handle {
   TailSpec tailf;
   float kmin_f = 0.f, kdiff_f = 0.f;
   int refine_max = 40;
+  // launch shape of every stencil: [class: 0 FP64, 1 FP32][grid level][mode]
+  std::vector<std::array<StencilCfg, 7>> scfg[2];
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // kernel timing (instrumentation)
   unsigned prof_mask = 0;
@@ -166,6 +170,11 @@ double stencil_bytes(const Geo& g, int mode) {
   return 0.0;
 }
 
+// Block partials written by a dot-producing stencil mode on the finest grid.
+int nparts_at(const mgar_handle* h, int cls, int mode) {
+  return stencil_num_partials(h->lv[0].g, &h->scfg[cls][0][mode]);
+}
+
 // Stencil launch on grid `level`; finest-grid launches selected by the
 // profiling mask are bracketed by HIP events on the same stream.
 int stencil_at(mgar_handle* h, int level, int mode, const double* x, const double* k,
@@ -182,13 +191,15 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
     }
   }
   int np;
-  if (timed && stencil_records_events(g)) {
+  const StencilCfg* cfg = &h->scfg[0][level][mode];
+  if (timed && stencil_records_events(g, cfg)) {
     // events recorded by the launch itself at kernel start and end
     np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout,
-                        h->prof_ev[h->prof_used], h->prof_ev[h->prof_used + 1]);
+                        h->prof_ev[h->prof_used], h->prof_ev[h->prof_used + 1], cfg);
   } else {
     if (timed) HIPCK(hipEventRecord(h->prof_ev[h->prof_used], h->s));
-    np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout);
+    np = launch_stencil(g, mode, x, k, kref, b, out, omega, part, done, h->s, cnt, rout, nullptr,
+                        nullptr, cfg);
     if (timed) HIPCK(hipEventRecord(h->prof_ev[h->prof_used + 1], h->s));
   }
   if (nparts) *nparts = np;
@@ -269,10 +280,12 @@ int stencil32(mgar_handle* h, int level, int mode, const float* x, const float* 
   if (level == 0) {
     const CellB k{dens ? dens : h->dens0, h->kmin_f, h->kdiff_f};
     const CellB kr{densref ? densref : h->dens0, h->kmin_f, h->kdiff_f};
-    launch_stencil_t<float, CellB>(g, mode, x, k, kr, b, out, h->p.omega, part, done, h->s);
+    launch_stencil_t<float, CellB>(g, mode, x, k, kr, b, out, h->p.omega, part, done, h->s, nullptr,
+                                   nullptr, nullptr, nullptr, &h->scfg[1][level][mode]);
   } else {
     const CellF k{h->kf[level]};
-    launch_stencil_t<float, CellF>(g, mode, x, k, k, b, out, h->p.omega, part, done, h->s);
+    launch_stencil_t<float, CellF>(g, mode, x, k, k, b, out, h->p.omega, part, done, h->s, nullptr,
+                                   nullptr, nullptr, nullptr, &h->scfg[1][level][mode]);
   }
   LAUNCHCK();
   return MGAR_OK;
@@ -330,7 +343,6 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
 // or max_it iterations; FP64 accumulation of every inner product.
 int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
   const long long N = h->N;
-  const Geo& g = h->lv[0].g;
   HIPCK(hipMemsetAsync(h->d32, 0, sizeof(float) * N, h->s));
   const int nr = launch_dot_t<float, float>(h->r32, h->r32, N, h->pa, nullptr, h->s);
   launch_cg_init(h->st, h->pa, nr, h->pa, nr, tol_in, max_it, h->s);
@@ -340,11 +352,11 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
   for (;;) {
     for (int c = 0; c < chunk && it < max_it; ++c, ++it) {
       ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
-      const int nz = (h->L == 1) ? vec_num_blocks(N) : stencil_num_partials(g);
+      const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
       launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
       launch_p_update_t<float>(h->z32, h->p32, N, h->st, it, h->s);
       ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, h->dens));
-      launch_finalize(h->pc, stencil_num_partials(g), &h->st->pw, done, h->s);
+      launch_finalize(h->pc, nparts_at(h, 1, SM_APPLY_DOT), &h->st->pw, done, h->s);
       launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, it, h->pa, nullptr, tol_in,
                                 max_it, h->s);
       launch_cg_check(h->st, h->pa, nr, it + 1, tol_in, max_it, h->s);
@@ -395,7 +407,6 @@ int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relre
 // PCG with one V-cycle as preconditioner on K(kfine); x (h->cx) holds the
 // initial guess on entry and the solution on exit; h->qm the masked load.
 int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, double* relres) {
-  const Geo& g = h->lv[0].g;
   const long long N = h->N;
   const int cg_max = h->p.cg_max;
   ACK(stencil_at(h, 0, SM_RESID, h->cx, kfine, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
@@ -416,7 +427,7 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     // those of a loop that tests before every iteration.
     for (int c = 0; c < chunk && it < cg_max; ++c, ++it) {
       ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, it));
-      const int nz = (h->L == 1) ? vec_num_blocks(N) : stencil_num_partials(g);
+      const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
       launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
       launch_p_update(h->cz, h->cp, N, h->st, it, h->s);
       int nw = 0;
@@ -575,6 +586,10 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   h->L = p->levels;
   h->lv.resize(h->L);
   for (int l = 0; l < h->L; ++l) h->lv[l].g = make_geo(h->p, l);
+  for (int c = 0; c < 2; ++c) {
+    h->scfg[c].resize(h->L);
+    for (int l = 0; l < h->L; ++l) h->scfg[c][l].fill(stencil_default_cfg(h->lv[l].g));
+  }
   const Geo& g0 = h->lv[0].g;
   const Geo& gc = h->lv[h->L - 1].g;
   if (gc.nn > 1024) return MGAR_E_DIMS;
@@ -602,6 +617,11 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->cp, N));
   ACK(dalloc(&h->cw, N));
   long long cap = stencil_num_partials(g0);
+  {
+    StencilCfg cand[64];
+    const int nc = stencil_candidates(g0, cand, 64);
+    for (int i = 0; i < nc; ++i) cap = std::max<long long>(cap, stencil_num_partials(g0, &cand[i]));
+  }
   cap = cap > 1024LL * 64 ? cap : 1024LL * 64;   // multi-value partials (Gram, OC)
   h->part_cap = cap;
   ACK(dalloc(&h->pa, cap));
@@ -918,7 +938,8 @@ int mgar_op_apply(mgar_handle* h, int level, const double* k, const double* x, d
   if (!h || !k || !x || !y || level < 0 || level >= h->L) return MGAR_E_ARG;
   const Geo& g = h->lv[level].g;
   launch_mask_copy(g, x, h->rtmp, h->s);
-  launch_stencil(g, SM_APPLY, h->rtmp, k, nullptr, nullptr, y, 0.0, nullptr, nullptr, h->s);
+  launch_stencil(g, SM_APPLY, h->rtmp, k, nullptr, nullptr, y, 0.0, nullptr, nullptr, h->s, nullptr,
+                 nullptr, nullptr, nullptr, &h->scfg[0][level][SM_APPLY]);
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -929,7 +950,8 @@ int mgar_op_jacobi(mgar_handle* h, int level, const double* k, const double* b, 
   const Geo& g = h->lv[level].g;
   launch_mask_copy(g, x, h->rtmp, h->s);
   launch_mask_copy(g, b, h->cz, h->s);
-  launch_stencil(g, SM_JACOBI, h->rtmp, k, nullptr, h->cz, out, h->p.omega, nullptr, nullptr, h->s);
+  launch_stencil(g, SM_JACOBI, h->rtmp, k, nullptr, h->cz, out, h->p.omega, nullptr, nullptr, h->s,
+                 nullptr, nullptr, nullptr, nullptr, &h->scfg[0][level][SM_JACOBI]);
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -996,7 +1018,8 @@ int mgar_op_dk(mgar_handle* h, const double* xphys, const double* r, double* b) 
   const Geo& g = h->lv[0].g;
   launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
   launch_mask_copy(g, r, h->rtmp, h->s);
-  launch_stencil(g, SM_NEG_DK, h->rtmp, h->kcur, h->lv[0].k, nullptr, b, 0.0, nullptr, nullptr, h->s);
+  launch_stencil(g, SM_NEG_DK, h->rtmp, h->kcur, h->lv[0].k, nullptr, b, 0.0, nullptr, nullptr, h->s,
+                 nullptr, nullptr, nullptr, nullptr, &h->scfg[0][0][SM_NEG_DK]);
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -1006,6 +1029,135 @@ int mgar_op_bf16(mgar_handle* h, const double* x, void* out) {
   launch_cast_bf16(x, static_cast<uint16_t*>(out), h->E, h->s);
   LAUNCHCK();
   return MGAR_OK;
+}
+
+// ---------------------------------------------------------------- launch-shape tuning
+
+int mgar_tune_get(const mgar_handle* h, int cls, int level, int mode, int* shape) {
+  if (!h || !shape || cls < 0 || cls > 1 || level < 0 || level >= h->L || mode < 0 || mode > 6)
+    return MGAR_E_ARG;
+  const StencilCfg& c = h->scfg[cls][level][mode];
+  shape[0] = c.kind;
+  shape[1] = c.kz;
+  shape[2] = c.zd;
+  shape[3] = c.ntx;
+  return MGAR_OK;
+}
+
+int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape) {
+  if (!h || !shape || cls < 0 || cls > 1 || level < 0 || level >= h->L || mode < 0 || mode > 6)
+    return MGAR_E_ARG;
+  const StencilCfg c{shape[0], shape[1], shape[2], shape[3]};
+  const Geo& g = h->lv[level].g;
+  if (!stencil_cfg_valid(g, c)) return MGAR_E_ARG;
+  if (stencil_num_partials(g, &c) > h->part_cap) return MGAR_E_ARG;
+  h->scfg[cls][level][mode] = c;
+  return MGAR_OK;
+}
+
+namespace {
+
+// Times every candidate shape of one (class, level, mode) on scratch data and
+// keeps the fastest. Returns the best average launch time in microseconds.
+int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd, double* bd,
+             double* od, double* kd, uint16_t* kb, hipEvent_t e0, hipEvent_t e1, double* best_us) {
+  const Geo& g = h->lv[level].g;
+  StencilCfg cand[64];
+  const int nc = stencil_candidates(g, cand, 64);
+  double best = -1.0;
+  int bi = 0;
+  for (int i = 0; i < nc; ++i) {
+    if (stencil_num_partials(g, &cand[i]) > h->part_cap) continue;
+    auto launch = [&]() {
+      if (cls == 0) {
+        launch_stencil(g, mode, xd, kd, kd + g.ne, bd, od, h->p.omega, h->pa, nullptr, h->s, nullptr,
+                       nullptr, nullptr, nullptr, &cand[i]);
+      } else if (level == 0) {
+        const CellB k{kb, h->kmin_f, h->kdiff_f}, kr{kb + g.ne, h->kmin_f, h->kdiff_f};
+        launch_stencil_t<float, CellB>(g, mode, (const float*)xd, k, kr, (const float*)bd, (float*)od,
+                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, nullptr,
+                                       nullptr, &cand[i]);
+      } else {
+        const CellF k{(const float*)kd}, kr{(const float*)kd + g.ne};
+        launch_stencil_t<float, CellF>(g, mode, (const float*)xd, k, kr, (const float*)bd, (float*)od,
+                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, nullptr,
+                                       nullptr, &cand[i]);
+      }
+    };
+    launch();
+    launch();
+    HIPCK(hipEventRecord(e0, h->s));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCK(hipEventRecord(e1, h->s));
+    HIPCK(hipEventSynchronize(e1));
+    LAUNCHCK();
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * (double)ms / reps;
+    if (best < 0.0 || us < best) { best = us; bi = i; }
+  }
+  if (best >= 0.0) h->scfg[cls][level][mode] = cand[bi];
+  *best_us = best;
+  return MGAR_OK;
+}
+
+}  // namespace
+
+int mgar_autotune(mgar_handle* h, int reps, double* best_us) {
+  if (!h || reps < 1) return MGAR_E_ARG;
+  const int L = h->L;
+  if (best_us)
+    for (int i = 0; i < 2 * L * 7; ++i) best_us[i] = 0.0;
+  const long long N = h->N, E = h->E;
+  double *xd = nullptr, *bd = nullptr, *od = nullptr, *kd = nullptr;
+  uint16_t* kb = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MGAR_OK;
+  do {
+    if (hipMalloc((void**)&xd, sizeof(double) * N) != hipSuccess ||
+        hipMalloc((void**)&bd, sizeof(double) * N) != hipSuccess ||
+        hipMalloc((void**)&od, sizeof(double) * N) != hipSuccess ||
+        hipMalloc((void**)&kd, sizeof(double) * 2 * E) != hipSuccess ||
+        hipMalloc((void**)&kb, sizeof(uint16_t) * 2 * E) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      rc = MGAR_E_HIP;
+      break;
+    }
+    const int ncls = h->mixed ? 2 : 1;
+    for (int cls = 0; cls < ncls && rc == MGAR_OK; ++cls) {
+      // scratch contents: smooth positive values of the class's element type
+      if (cls == 0) {
+        launch_fill_t<double>(xd, N, 0.5f, 0.001f, h->s);
+        launch_fill_t<double>(bd, N, 0.1f, 0.001f, h->s);
+        launch_fill_t<double>(kd, 2 * E, 0.3f, 0.005f, h->s);
+      } else {
+        launch_fill_t<float>((float*)xd, N, 0.5f, 0.001f, h->s);
+        launch_fill_t<float>((float*)bd, N, 0.1f, 0.001f, h->s);
+        launch_fill_t<float>((float*)kd, 2 * E, 0.3f, 0.005f, h->s);
+        launch_fill_bf16(kb, 2 * E, h->s);
+      }
+      const int lt = (cls == 0) ? h->lt : h->ltf;
+      for (int l = 0; l < L && rc == MGAR_OK; ++l) {
+        if (l > 0 && l >= lt) break;   // grids below handled by the tail kernel
+        for (int m = 0; m < 7 && rc == MGAR_OK; ++m) {
+          // coarser grids only run the smoother sweeps and the residual
+          if (l > 0 && m != SM_JACOBI0 && m != SM_RESID && m != SM_JACOBI) continue;
+          double us = 0.0;
+          rc = tune_one(h, cls, l, m, reps, xd, bd, od, kd, kb, e0, e1, &us);
+          if (best_us) best_us[(cls * L + l) * 7 + m] = us;
+        }
+      }
+    }
+  } while (0);
+  (void)hipStreamSynchronize(h->s);
+  if (xd) (void)hipFree(xd);
+  if (bd) (void)hipFree(bd);
+  if (od) (void)hipFree(od);
+  if (kd) (void)hipFree(kd);
+  if (kb) (void)hipFree(kb);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int mgar_profile(mgar_handle* h, unsigned mode_mask) {

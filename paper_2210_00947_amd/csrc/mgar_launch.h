@@ -14,23 +14,40 @@ enum StencilMode {
 };
 
 // stencil.hip ----------------------------------------------------------------
+// Launch shape of a stencil on one grid. kind 0: node-parallel kernel (one
+// thread per node, 64x4 blocks). kind 1: z-marching kernel (3D only): the node
+// grid is cut into ntx x nty column tiles of width ceil(nnx/ntx) <= 64 and
+// height filling 256 threads, and into z-chunks of kz node planes; each block
+// marches one chunk with a load queue zd planes deep (1 or 2). The arithmetic
+// of every node is the same for every shape; only the order in which block
+// partials of a dot are summed depends on it.
+struct StencilCfg {
+  int kind, kz, zd, ntx;
+};
+StencilCfg stencil_default_cfg(const Geo& g);
+bool stencil_cfg_valid(const Geo& g, const StencilCfg& c);
+// Candidate shapes for the tuner (the default first); returns how many were
+// written (at most `cap`).
+int stencil_candidates(const Geo& g, StencilCfg* out, int cap);
 // Value type T (double or float) and cell loader CL (CellD, CellF, CellB) are
-// template parameters; FP64 entry points keep plain-pointer overloads.
+// template parameters; FP64 entry points keep plain-pointer overloads. cfg
+// null = stencil_default_cfg(g).
 template <typename T, typename CL>
 int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out,
                      double omega, double* part, const int* done, hipStream_t s,
                      unsigned* cnt = nullptr, double* rout = nullptr, hipEvent_t ev0 = nullptr,
-                     hipEvent_t ev1 = nullptr);
+                     hipEvent_t ev1 = nullptr, const StencilCfg* cfg = nullptr);
 // Returns the number of block partials written to `part` (0 for modes without a
 // dot). With cnt != null the dot is also reduced in the same launch (last block
-// sums the partials in order) and stored to *rout. ev0/ev1 (z-marching grids
+// sums the partials in order) and stored to *rout. ev0/ev1 (z-marching shapes
 // only): events recorded at kernel start and end.
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
                    hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-bool stencil_records_events(const Geo& g);
-int stencil_num_partials(const Geo& g);
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                   const StencilCfg* cfg = nullptr);
+bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
+int stencil_num_partials(const Geo& g, const StencilCfg* cfg = nullptr);
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T>
@@ -123,6 +140,9 @@ int launch_cg_update(double* x, double* r, const double* p, const double* w, lon
                      CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
                      hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
+template <typename T>
+void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s);
+void launch_fill_bf16(uint16_t* a, long long n, hipStream_t s);
 void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s);
 // Gram-Schmidt / reduced system helpers
 int launch_multidot(const double* Q, int ncols, long long ld, const double* v, long long n,

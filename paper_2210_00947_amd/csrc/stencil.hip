@@ -55,7 +55,33 @@ __device__ inline T ldx(const Geo& g, const T* __restrict__ x, int i, int j, int
   return in ? x[geo_node(g, i, j, k)] : T(0);
 }
 
-// (K x)_i for node (i, j, kz) given the 2^d cell conductivities around it.
+// (K x)_i in 3D from the 3x3 windows of node planes kz-1 (A), kz (B) and kz+1
+// (C), centred on the node, and the 2x2 windows of cell conductivities below
+// (CA) and above (CB) it ([y][x], index 0 = the lower neighbour). With the
+// trilinear element matrix only the 8 cell centres (weight h/3 on the node)
+// and the 12 edge- plus 8 corner-diagonal neighbours (weight -h/12) couple;
+// face neighbours have weight 0. ks returns the sum of the 8 conductivities,
+// so that the diagonal of K is hc * ks. Every 3D stencil kernel evaluates this
+// one expression, so results do not depend on the kernel or launch shape.
+template <typename T, bool NEEDX>
+__device__ inline T apply27(const T (&A)[3][3], const T (&B)[3][3], const T (&C)[3][3],
+                            const T (&CA)[2][2], const T (&CB)[2][2], T hc, T hf, T& ks) {
+  const T t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];
+  const T t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];
+  ks = (t00 + t01) + (t10 + t11);
+  if (!NEEDX) return T(0);
+  T s1 = t00 * B[0][0] + t01 * B[0][2] + t10 * B[2][0] + t11 * B[2][2];
+  s1 += (CA[0][0] + CA[1][0]) * A[1][0] + (CA[0][1] + CA[1][1]) * A[1][2];
+  s1 += (CA[0][0] + CA[0][1]) * A[0][1] + (CA[1][0] + CA[1][1]) * A[2][1];
+  s1 += CA[0][0] * A[0][0] + CA[0][1] * A[0][2] + CA[1][0] * A[2][0] + CA[1][1] * A[2][2];
+  s1 += (CB[0][0] + CB[1][0]) * C[1][0] + (CB[0][1] + CB[1][1]) * C[1][2];
+  s1 += (CB[0][0] + CB[0][1]) * C[0][1] + (CB[1][0] + CB[1][1]) * C[2][1];
+  s1 += CB[0][0] * C[0][0] + CB[0][1] * C[0][2] + CB[1][0] * C[2][0] + CB[1][1] * C[2][2];
+  return hc * ks * B[1][1] - hf * s1;
+}
+
+// (K x)_i for node (i, j, kz) given the 2^d cell conductivities around it;
+// ksum returns the conductivity sum that scales the diagonal.
 template <int DIM, typename T>
 __device__ inline T node_apply(const Geo& g, const T* __restrict__ x, int i, int j, int kz,
                                const T (&kv)[2][2][2], T& ksum) {
@@ -89,20 +115,8 @@ __device__ inline T node_apply(const Geo& g, const T* __restrict__ x, int i, int
           const int nz = (dx != 1) + (dy != 1) + (dz != 1);
           xv[dz][dy][dx] = (nz == 1) ? T(0) : ldx(g, x, i + dx - 1, j + dy - 1, kz + dz - 1);
         }
-    T s0 = T(0), s1 = T(0);
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int sx = a ? 2 : 0, sy = b ? 2 : 0, sz = c ? 2 : 0;
-          const T ke = kv[c][b][a];
-          s0 += ke;
-          s1 += ke * (xv[1][sy][sx] + xv[sz][1][sx] + xv[sz][sy][1] + xv[sz][sy][sx]);
-        }
-    ksum = s0;
-    return T(g.h) * (T(1.0 / 3.0) * s0 * xv[1][1][1] - T(1.0 / 12.0) * s1);
+    return apply27<T, true>(xv[0], xv[1], xv[2], kv[0], kv[1], T(g.h * (1.0 / 3.0)),
+                            T(g.h * (1.0 / 12.0)), ksum);
   }
 }
 
@@ -131,13 +145,11 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const T* __restrict
       T y = T(0);
       if (MODE != SM_JACOBI0) {
         y = node_apply<DIM, T>(g, x, i, j, kz, kv, ksum);
+      } else if (DIM == 3) {
+        const T z3[3][3] = {};
+        (void)apply27<T, false>(z3, z3, z3, kv[0], kv[1], T(0), T(0), ksum);
       } else {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) ksum += kv[c][bb][a];
+        ksum = ((kv[0][0][0] + kv[0][0][1]) + kv[0][1][0]) + kv[0][1][1];
       }
       const T diag = T(DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
       if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {
@@ -264,7 +276,7 @@ __device__ inline T zfill_c(const Geo& g, const CL& k, const CL& kref, const CSl
 }
 
 template <int MODE, int XP, int ZD, typename T, typename CL>
-__global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
+__global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 : 3))) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
                                                   int KZ, const T* __restrict__ x,
                                                   const T* __restrict__ ec, CL k, CL kref,
                                                   const T* __restrict__ b,
@@ -380,23 +392,9 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (act) {                                                                               \
       T r = T(0);                                                                            \
       if (!(colfix && kk >= g.f0z && kk <= g.f1z)) {                                         \
-        /* cell sums: t = below + above (centre-plane diagonals), column and */            \
-        /* row sums per plane (edge midpoints of planes kk-1 and kk+1)        */            \
-        const T t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];                      \
-        const T t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];                      \
-        const T ks = (t00 + t01) + (t10 + t11);                                            \
-        T s1 = T(0);                                                                         \
-        if (NEEDX) {                                                                         \
-          s1 = t00 * B[0][0] + t01 * B[0][2] + t10 * B[2][0] + t11 * B[2][2];                \
-          s1 += (CA[0][0] + CA[1][0]) * A[1][0] + (CA[0][1] + CA[1][1]) * A[1][2];           \
-          s1 += (CA[0][0] + CA[0][1]) * A[0][1] + (CA[1][0] + CA[1][1]) * A[2][1];           \
-          s1 += CA[0][0] * A[0][0] + CA[0][1] * A[0][2] + CA[1][0] * A[2][0] + CA[1][1] * A[2][2]; \
-          s1 += (CB[0][0] + CB[1][0]) * C[1][0] + (CB[0][1] + CB[1][1]) * C[1][2];           \
-          s1 += (CB[0][0] + CB[0][1]) * C[0][1] + (CB[1][0] + CB[1][1]) * C[2][1];           \
-          s1 += CB[0][0] * C[0][0] + CB[0][1] * C[0][2] + CB[1][0] * C[2][0] + CB[1][1] * C[2][2]; \
-        }                                                                                    \
+        T ks;                                                                                \
+        const T y = apply27<T, NEEDX>(A, B, C, CA, CB, hc, hf, ks);                          \
         const T xcv = NEEDX ? B[1][1] : T(0);                                                \
-        const T y = NEEDX ? (hc * ks * xcv - hf * s1) : T(0);                                \
         const T diag = hc * ks;                                                              \
         if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {                                      \
           r = y;                                                                             \
@@ -925,30 +923,27 @@ void stencil_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T
 }
 
 constexpr int ZMARCH_MIN_NODES = 20000;
-constexpr int ZKZ = 12;   // z-planes per block (swept: 4..32; 12 is best at 129^3)
-
-bool use_zmarch(const Geo& g) { return g.dim == 3 && g.nn >= ZMARCH_MIN_NODES; }
+constexpr int ZKZ = 12;   // default z-planes per block (best at 129^3 with zd = 1)
 
 struct ZShape { int TXW, TYH, ntx, nty, nzc; };
 
-ZShape zmarch_shape(const Geo& g) {
+ZShape zmarch_shape(const Geo& g, const StencilCfg& c) {
   ZShape z;
-  z.ntx = (g.nnx + 63) / 64;
+  z.ntx = c.ntx;
   z.TXW = (g.nnx + z.ntx - 1) / z.ntx;
   int tyh = ZT / z.TXW;
   tyh = std::min(tyh, XCAP / (z.TXW + 2) - 2);
   tyh = std::min(tyh, CCAP / (z.TXW + 1) - 1);
   z.TYH = std::max(tyh, 1);
   z.nty = (g.nny + z.TYH - 1) / z.TYH;
-  z.nzc = (g.nnz + ZKZ - 1) / ZKZ;
+  z.nzc = (g.nnz + c.kz - 1) / c.kz;
   return z;
 }
 
-template <typename T, typename CL>
-void zmarch_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out, T omega,
-                     double* part, const int* done, unsigned* cnt, double* rout, hipStream_t s,
-                     hipEvent_t ev0, hipEvent_t ev1) {
-  const ZShape z = zmarch_shape(g);
+template <int ZD, typename T, typename CL>
+void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, CL k, CL kref,
+                   const T* b, T* out, T omega, double* part, const int* done, unsigned* cnt,
+                   double* rout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nb = z.ntx * z.nty * z.nzc;
   const T* ec = nullptr;
   // With events, the launch goes through hipExtLaunchKernelGGL, which records
@@ -956,13 +951,13 @@ void zmarch_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T*
 #define ZCALL(M)                                                                                 \
   do {                                                                                           \
     if (ev0)                                                                                     \
-      hipExtLaunchKernelGGL((k_stencil_z<M, XP_PLAIN, 1, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, \
-                            0, g, g, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, k, kref, b, out,     \
+      hipExtLaunchKernelGGL((k_stencil_z<M, XP_PLAIN, ZD, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, \
+                            0, g, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, ec, k, kref, b, out,      \
                             omega, part, done, cnt, rout);                                       \
     else                                                                                         \
-      k_stencil_z<M, XP_PLAIN, 1, T, CL><<<nb, ZT, 0, s>>>(g, g, z.TXW, z.TYH, z.ntx, z.nty, ZKZ, x, ec, \
-                                                           k, kref, b, out, omega, part, done,   \
-                                                           cnt, rout);                           \
+      k_stencil_z<M, XP_PLAIN, ZD, T, CL><<<nb, ZT, 0, s>>>(g, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, ec, \
+                                                            k, kref, b, out, omega, part, done,  \
+                                                            cnt, rout);                          \
   } while (0)
   switch (mode) {
     case SM_APPLY: ZCALL(SM_APPLY); break;
@@ -978,45 +973,103 @@ void zmarch_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T*
 
 }  // namespace
 
-int stencil_num_partials(const Geo& g) {
-  if (use_zmarch(g)) {
-    const ZShape z = zmarch_shape(g);
+StencilCfg stencil_default_cfg(const Geo& g) {
+  StencilCfg c{0, 0, 0, 0};
+  if (g.dim == 3 && g.nn >= ZMARCH_MIN_NODES) c = StencilCfg{1, ZKZ, 1, (g.nnx + 63) / 64};
+  return c;
+}
+
+bool stencil_cfg_valid(const Geo& g, const StencilCfg& c) {
+  if (c.kind == 0) return true;
+  if (c.kind != 1 || g.dim != 3) return false;
+  if (c.kz < 1 || c.kz > 64 || (c.zd != 1 && c.zd != 2)) return false;
+  if (c.ntx < 1 || c.ntx > g.nnx) return false;
+  const int txw = (g.nnx + c.ntx - 1) / c.ntx;
+  if (txw > 64 || txw < 4) return false;
+  const ZShape z = zmarch_shape(g, c);
+  return (long long)(z.TXW + 2) * (z.TYH + 2) <= XCAP && (long long)(z.TXW + 1) * (z.TYH + 1) <= CCAP &&
+         (long long)z.TXW * z.TYH <= ZT;
+}
+
+int stencil_candidates(const Geo& g, StencilCfg* out, int cap) {
+  int n = 0;
+  auto add = [&](StencilCfg c) {
+    if (n < cap && stencil_cfg_valid(g, c)) out[n++] = c;
+  };
+  add(stencil_default_cfg(g));
+  if (g.dim != 3) return n;
+  if (stencil_default_cfg(g).kind == 1) add(StencilCfg{0, 0, 0, 0});
+  const int kzs[] = {4, 6, 8, 12, 16, 24};
+  const int widths[] = {64, 32};
+  for (int w : widths)
+    for (int zd = 1; zd <= 2; ++zd)
+      for (int kz : kzs) {
+        const StencilCfg c{1, kz, zd, (g.nnx + w - 1) / w};
+        const StencilCfg d = stencil_default_cfg(g);
+        if (d.kind == 1 && c.kz == d.kz && c.zd == d.zd && c.ntx == d.ntx) continue;
+        add(c);
+      }
+  return n;
+}
+
+static StencilCfg resolve_cfg(const Geo& g, const StencilCfg* cfg) {
+  return (cfg && stencil_cfg_valid(g, *cfg)) ? *cfg : stencil_default_cfg(g);
+}
+
+int stencil_num_partials(const Geo& g, const StencilCfg* cfg) {
+  const StencilCfg c = resolve_cfg(g, cfg);
+  if (c.kind == 1) {
+    const ZShape z = zmarch_shape(g, c);
     return z.ntx * z.nty * z.nzc;
   }
   const dim3 grid = node_grid(g);
   return (int)(grid.x * grid.y * grid.z);
 }
 
-bool stencil_records_events(const Geo& g) { return use_zmarch(g); }
+bool stencil_records_events(const Geo& g, const StencilCfg* cfg) {
+  return resolve_cfg(g, cfg).kind == 1;
+}
 
 template <typename T, typename CL>
 int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out,
                      double omega, double* part, const int* done, hipStream_t s, unsigned* cnt,
-                     double* rout, hipEvent_t ev0, hipEvent_t ev1) {
-  if (use_zmarch(g))
-    zmarch_dispatch<T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s, ev0, ev1);
-  else if (g.dim == 2)
+                     double* rout, hipEvent_t ev0, hipEvent_t ev1, const StencilCfg* cfg) {
+  const StencilCfg c = resolve_cfg(g, cfg);
+  if (c.kind == 1) {
+    const ZShape z = zmarch_shape(g, c);
+    if (c.zd == 2)
+      zmarch_launch<2, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
+                              ev0, ev1);
+    else
+      zmarch_launch<1, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
+                              ev0, ev1);
+  } else if (g.dim == 2) {
     stencil_dispatch<2, T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s);
-  else
+  } else {
     stencil_dispatch<3, T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s);
-  return (mode == SM_APPLY_DOT || mode == SM_JACOBI_DOT) ? stencil_num_partials(g) : 0;
+  }
+  return (mode == SM_APPLY_DOT || mode == SM_JACOBI_DOT) ? stencil_num_partials(g, &c) : 0;
 }
 
 template int launch_stencil_t<double, CellD>(const Geo&, int, const double*, CellD, CellD, const double*,
                                              double*, double, double*, const int*, hipStream_t,
-                                             unsigned*, double*, hipEvent_t, hipEvent_t);
+                                             unsigned*, double*, hipEvent_t, hipEvent_t,
+                                             const StencilCfg*);
 template int launch_stencil_t<float, CellF>(const Geo&, int, const float*, CellF, CellF, const float*,
                                             float*, double, double*, const int*, hipStream_t,
-                                            unsigned*, double*, hipEvent_t, hipEvent_t);
+                                            unsigned*, double*, hipEvent_t, hipEvent_t,
+                                            const StencilCfg*);
 template int launch_stencil_t<float, CellB>(const Geo&, int, const float*, CellB, CellB, const float*,
                                             float*, double, double*, const int*, hipStream_t,
-                                            unsigned*, double*, hipEvent_t, hipEvent_t);
+                                            unsigned*, double*, hipEvent_t, hipEvent_t,
+                                            const StencilCfg*);
 
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
-                   hipStream_t s, unsigned* cnt, double* rout, hipEvent_t ev0, hipEvent_t ev1) {
+                   hipStream_t s, unsigned* cnt, double* rout, hipEvent_t ev0, hipEvent_t ev1,
+                   const StencilCfg* cfg) {
   return launch_stencil_t<double, CellD>(g, mode, x, CellD{k}, CellD{kref}, b, out, omega, part, done, s,
-                                         cnt, rout, ev0, ev1);
+                                         cnt, rout, ev0, ev1, cfg);
 }
 
 template <typename T>

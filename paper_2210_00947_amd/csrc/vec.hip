@@ -128,6 +128,19 @@ __global__ __launch_bounds__(VB) void k_copy(const double* __restrict__ a, doubl
     b[i] = a[i];
 }
 
+// a[i] = v0 + dv * (i mod 97): deterministic non-constant fill for timing runs.
+template <typename T>
+__global__ __launch_bounds__(VB) void k_fill(T* __restrict__ a, long long n, float v0, float dv) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    a[i] = (T)(v0 + dv * (float)(i % 97));
+}
+
+__global__ __launch_bounds__(VB) void k_fill_bf16(uint16_t* __restrict__ a, long long n) {
+  // BF16 values 0.25 .. 0.98 (exponent field of 0.5, varied mantissa)
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    a[i] = (uint16_t)(0x3E80u + (unsigned)(i % 97));
+}
+
 __global__ __launch_bounds__(VB) void k_scale_into(const double* __restrict__ a,
                                                    double* __restrict__ b, double alpha,
                                                    long long n) {
@@ -435,6 +448,17 @@ int launch_cg_update(double* x, double* r, const double* p, const double* w, lon
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
   k_copy<<<vec_num_blocks(n), VB, 0, s>>>(a, b, n);
+}
+
+template <typename T>
+void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s) {
+  k_fill<T><<<vec_num_blocks(n), VB, 0, s>>>(a, n, v0, dv);
+}
+template void launch_fill_t<double>(double*, long long, float, float, hipStream_t);
+template void launch_fill_t<float>(float*, long long, float, float, hipStream_t);
+
+void launch_fill_bf16(uint16_t* a, long long n, hipStream_t s) {
+  k_fill_bf16<<<vec_num_blocks(n), VB, 0, s>>>(a, n);
 }
 
 void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s) {

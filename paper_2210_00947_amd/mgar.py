@@ -32,7 +32,8 @@ EXPORTS = [
     "mgar_sizes", "mgar_load_vector", "mgar_density_filter", "mgcg_solve", "mgar_solve",
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
-    "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_profile", "mgar_profile_read",
+    "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
+    "mgar_tune_set", "mgar_profile", "mgar_profile_read",
 ]
 
 
@@ -285,6 +286,23 @@ class Handle:
             raise ValueError("out must be an int16 GPU tensor with E entries")
         _check(self._L.mgar_op_bf16(self.h, _ptr(x, self.E, "x"), ctypes.c_void_p(out.data_ptr())),
                "mgar_op_bf16")
+
+    def mgar_autotune(self, reps=20):
+        """Time the candidate launch shapes and install the fastest; returns the
+        winning times (microseconds) as a list indexed [cls][level][mode]."""
+        L = self.params.levels
+        buf = (ctypes.c_double * (2 * L * 7))()
+        _check(self._L.mgar_autotune(self.h, int(reps), buf), "mgar_autotune")
+        return [[[buf[(c * L + l) * 7 + m] for m in range(7)] for l in range(L)] for c in range(2)]
+
+    def mgar_tune_get(self, cls, level, mode):
+        s = (ctypes.c_int * 4)()
+        _check(self._L.mgar_tune_get(self.h, int(cls), int(level), int(mode), s), "mgar_tune_get")
+        return list(s)
+
+    def mgar_tune_set(self, cls, level, mode, shape):
+        s = (ctypes.c_int * 4)(*[int(v) for v in shape])
+        _check(self._L.mgar_tune_set(self.h, int(cls), int(level), int(mode), s), "mgar_tune_set")
 
     def mgar_profile(self, mode_mask):
         _check(self._L.mgar_profile(self.h, ctypes.c_uint(mode_mask)), "mgar_profile")

@@ -31,13 +31,17 @@ class Cycle:
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
                  eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
-                 device="cuda"):
+                 autotune=True, device="cuda"):
         self.prob = prob
         self.use_mgar = use_mgar
         self.params = M.params_for(prob, n_basis=n_basis, eps_accept=eps_accept, cg_max=cg_max,
                                    basis_x0_zero=basis_x0_zero, precision=precision,
                                    inner_tol=inner_tol)
         self.h = M.Handle(self.params)
+        self.tune_source = None
+        if autotune:
+            from . import tune
+            _, self.tune_source = tune.autotune(self.h, self.params, tune.device_arch())
         N, E = self.h.N, self.h.E
         f64 = dict(dtype=torch.float64, device=device)
         self.Qe = torch.as_tensor(qelem, **f64).contiguous()

@@ -1,0 +1,93 @@
+"""Launch shapes on the GPU: every valid shape gives bit-identical stencil
+outputs, invalid ones are refused, and solves after the tuner still match the
+oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fe, solvers
+from tests.gpu_util import dev, host, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [[0, 0, 0, 0], [1, 4, 1, 1], [1, 6, 2, 2], [1, 12, 1, 1], [1, 24, 2, 2], [1, 5, 1, 3],
+          [1, 7, 2, 1], [1, 64, 1, 1]]
+
+
+def handle(prob, **kw):
+    require_gpu()
+    from paper_2210_00947_amd import mgar as M
+    return M.Handle(M.params_for(prob, **kw))
+
+
+@pytest.mark.parametrize("prob", [W.tiny_3d(32, 32, 32, 4), W.tiny_3d(48, 32, 16, 3)],
+                         ids=["32x32x32", "48x32x16"])
+def test_apply_and_jacobi_bit_identical_across_shapes(prob):
+    import torch
+    h = handle(prob)
+    g = fe.Grid(3, prob.nelx, prob.nely, prob.nelz)
+    fixed = fe.fixed_mask_from_box(g, prob.fix_lo, prob.fix_hi)
+    k = W.random_density(g.nelem, 81, 1e-3, 1.0)
+    x = W.random_vector(g.nnodes, 82)
+    b = W.random_vector(g.nnodes, 83)
+    x[fixed] = 0.0
+    b[fixed] = 0.0
+    ref_y = ref_j = None
+    for s in SHAPES:
+        h.mgar_tune_set(0, 0, 0, s)
+        h.mgar_tune_set(0, 0, 3, s)
+        assert h.mgar_tune_get(0, 0, 0) == s
+        y = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+        j = torch.empty_like(y)
+        h.mgar_op_apply(0, dev(k), dev(x), y)
+        h.mgar_op_jacobi(0, dev(k), dev(b), dev(x), j)
+        y, j = host(y), host(j)
+        if ref_y is None:
+            ref_y, ref_j = y, j
+            K = fe.assemble(g, k)
+            want = K @ x
+            want[fixed] = 0.0
+            assert np.abs(y - want).max() <= 1e-13 * np.abs(want).max()
+        assert np.array_equal(y, ref_y), s
+        assert np.array_equal(j, ref_j), s
+
+
+def test_invalid_shapes_refused():
+    from paper_2210_00947_amd import mgar as M
+    prob = W.tiny_3d(32, 32, 32, 4)
+    h = handle(prob)
+    before = h.mgar_tune_get(0, 0, 1)
+    for bad in ([1, 0, 1, 1], [1, 4, 3, 1], [2, 4, 1, 1], [1, 4, 1, 0], [1, 4, 1, 34], [1, 65, 1, 1]):
+        with pytest.raises(M.MgarError):
+            h.mgar_tune_set(0, 0, 1, bad)
+    assert h.mgar_tune_get(0, 0, 1) == before
+    p2 = W.tiny_2d(40, 40, 3)
+    h2 = handle(p2)
+    with pytest.raises(M.MgarError):
+        h2.mgar_tune_set(0, 0, 1, [1, 8, 1, 1])     # z-marching needs 3D
+    with pytest.raises(M.MgarError):
+        h.mgar_tune_set(0, 9, 1, [0, 0, 0, 0])      # no such level
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_solves_after_autotune_match_oracle(precision):
+    import torch
+    prob = W.tiny_3d(32, 32, 32, 4)
+    h = handle(prob, precision=precision)
+    best = h.mgar_autotune(3)
+    assert best[0][0][1] > 0.0                      # finest apply + dot was timed
+    if precision == 1:
+        assert best[1][0][1] > 0.0
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    xphys = W.random_density(prob.nelem, 11, 0.0, 1.0)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    t_or, st_or = s.mgcg(xphys, np.zeros(prob.nnodes), 1e-8)
+    T = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    st = h.mgcg_solve(dev(xphys), q, None, 1e-8, T)
+    assert st["rc"] == 0
+    if precision == 0:
+        assert st["cg_iters"] == st_or.cg_iters
+        assert rel_l2(host(T), t_or) < 1e-8
+    else:
+        assert rel_l2(host(T), t_or) < 1e-6

@@ -33,13 +33,19 @@ __host__ __device__ inline long long geo_elem(const Geo& g, int ex, int ey, int 
 // Cell-conductivity loaders. Kernels read cell conductivities through one of
 // these: an FP64 array, an FP32 array, or BF16-stored physical densities with
 // the SIMP law (Eq 4, p = 3) applied in FP32 on load.
+// Each loader also says how to turn one raw stored element (type E) into a
+// conductivity, for kernels that fetch the raw elements themselves.
 struct CellD {
+  using E = double;
   const double* p;
   __device__ double operator()(long long e) const { return p[e]; }
+  __device__ double value(double v) const { return v; }
 };
 struct CellF {
+  using E = float;
   const float* p;
   __device__ float operator()(long long e) const { return p[e]; }
+  __device__ float value(float v) const { return v; }
 };
 __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
   union { uint32_t u; float f; } v;
@@ -47,12 +53,14 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
   return v.f;
 }
 struct CellB {
+  using E = uint16_t;
   const uint16_t* p;
   float kmin, kdiff;
-  __device__ float operator()(long long e) const {
-    const float r = bf16_bits_to_f32(p[e]);
+  __device__ float value(uint16_t h) const {
+    const float r = bf16_bits_to_f32(h);
     return kmin + kdiff * (r * r * r);
   }
+  __device__ float operator()(long long e) const { return value(p[e]); }
 };
 
 // PCG state in device memory. Every field has a single writer per kernel.

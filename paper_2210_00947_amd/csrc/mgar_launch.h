@@ -18,7 +18,7 @@ enum StencilMode {
 // thread per node, 64x4 blocks). kind 1: z-marching kernel (3D only): the node
 // grid is cut into ntx x nty column tiles of width ceil(nnx/ntx) <= 64 and
 // height filling 256 threads, and into z-chunks of kz node planes; each block
-// marches one chunk with a load queue zd planes deep (1 or 2). The arithmetic
+// marches one chunk with a load queue zd planes deep (1 to 4). The arithmetic
 // of every node is the same for every shape; only the order in which block
 // partials of a dot are summed depends on it.
 struct StencilCfg {

@@ -180,16 +180,21 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const T* __restrict
 // node columns and walks KZ consecutive z-planes. Each plane of x (tile plus a
 // one-node halo) and each plane of cell conductivities (tile plus the cells
 // below-left of it) passes through a ring of LDS slots: while node plane k is
-// computed from LDS, the next plane is already in flight in registers. A
-// thread thus issues about four global loads per plane and reads its 21
-// weighted neighbours from LDS. Tiles split each row evenly (129 = 3 x 43), so
-// no block is left with a single column.
+// computed from LDS, the next ZD planes are already in flight in registers.
+// A thread issues five global loads per plane (two x slots, two cell slots
+// and its own b) and reads its 21 weighted neighbours from LDS. The fills are
+// branch-free: every thread stores both of its slots each plane; a slot
+// outside the tile halo or the grid loads from a clamped in-grid address and
+// stores 0. Tiles split each row evenly (129 = 3 x 43), so no block is left
+// with a single column.
 // Block ids are remapped so that each XCD (blocks are dealt round-robin to the
 // 8 XCDs) receives a contiguous range of tiles, z-chunk slowest: halo rows and
 // planes shared by neighbouring tiles then hit in that XCD's L2.
 constexpr int ZT = 256;
-constexpr int XCAP = 420;   // >= (TXW+2)(TYH+2)
-constexpr int CCAP = 360;   // >= (TXW+1)(TYH+1)
+constexpr int XCAP = 420;   // >= (TXW+2)(TYH+2): halo-tile nodes of one plane
+constexpr int CCAP = 360;   // >= (TXW+1)(TYH+1): cells of one plane around the tile
+constexpr int ZSLOT = 2 * ZT;  // LDS slots per staged plane (two per thread)
+static_assert(XCAP <= ZSLOT && CCAP <= ZSLOT, "two fill slots per thread must cover a plane");
 
 __device__ inline int xcd_remap(int bid, int nb) {
   const int xcd = bid & 7, local = bid >> 3;
@@ -197,101 +202,71 @@ __device__ inline int xcd_remap(int bid, int nb) {
   return xcd * q + (xcd < r ? xcd : r) + local;
 }
 
-// x-plane fill policies: XP_PLAIN reads x; XP_PROLONG reads xa + P e_c, the
-// iterate after the coarse-grid correction of Table 1 step 4 (interpolated on
-// the fly, so the corrected iterate is never written to memory).
-enum { XP_PLAIN = 0, XP_PROLONG = 1 };
+// Buffer-resource access (gfx9 family descriptor: raw, stride 0, range
+// checked). A load whose byte offset lies beyond the range returns 0 and a
+// store there is dropped, so halo slots outside the grid, planes outside the
+// z-range and threads outside the tile need no branch: they just use an
+// offset at or above ZOOB. Offsets are 32-bit, so a z-marching grid must keep
+// every array below 2 GiB (checked by stencil_cfg_valid).
+constexpr unsigned ZOOB = 0x80000000u;
 
-// Per-thread description of one LDS fill slot of the x plane: the node's
-// offset inside a plane and, for the interpolated fill, its coarse-grid
-// neighbourhood in x and y. Built once per block, so a plane fill is a few
-// multiply-adds.
-struct XSlot {
-  long long off;      // ii + nnx * jj (node offset within a plane)
-  long long coff;     // I0 + nnxc * J0 (coarse offset within a coarse plane)
-  int ok;             // slot inside the tile halo and the grid
-  int fxy;            // (ii, jj) inside the Dirichlet box in x and y
-  int ni, nj;         // coarse neighbours along x and y (1 or 2)
-  double wi, wj;      // their weights (1 or 1/2)
-};
-
-__device__ inline XSlot make_xslot(const Geo& g, const Geo& gc, int i0, int j0, int XW, int XN,
-                                   int idx) {
-  XSlot sl;
-  const int ii = i0 - 1 + idx % XW, jj = j0 - 1 + idx / XW;
-  sl.ok = idx < XN && ii >= 0 && ii < g.nnx && jj >= 0 && jj < g.nny;
-  sl.off = (long long)ii + (long long)g.nnx * jj;
-  sl.fxy = ii >= g.f0x && ii <= g.f1x && jj >= g.f0y && jj <= g.f1y;
-  sl.ni = (ii & 1) ? 2 : 1;
-  sl.nj = (jj & 1) ? 2 : 1;
-  sl.wi = (ii & 1) ? 0.5 : 1.0;
-  sl.wj = (jj & 1) ? 0.5 : 1.0;
-  sl.coff = (long long)(ii >> 1) + (long long)gc.nnx * (jj >> 1);
-  return sl;
+__device__ inline __amdgpu_buffer_rsrc_t zrsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <int XP, typename T>
-__device__ inline T zfill_x(const Geo& g, const Geo& gc, const T* __restrict__ x,
-                            const T* __restrict__ ec, const XSlot& sl, int p) {
-  if (!sl.ok || p < 0 || p >= g.nnz) return T(0);
-  const long long pl = (long long)g.nnx * g.nny;
-  T v = x[sl.off + pl * p];
-  if (XP == XP_PROLONG && !(sl.fxy && p >= g.f0z && p <= g.f1z)) {
-    const long long cpl = (long long)gc.nnx * gc.nny;
-    const int nk = (p & 1) ? 2 : 1;
-    const T wk = T((p & 1) ? 0.5 : 1.0);
-    const T* e0 = ec + sl.coff + cpl * (p >> 1);
-    T s = T(0);
-    for (int c = 0; c < nk; ++c) {
-      T sy = T(0);
-      for (int b = 0; b < sl.nj; ++b) {
-        const T* r = e0 + c * cpl + b * gc.nnx;
-        sy += T(sl.wi) * (sl.ni == 2 ? r[0] + r[1] : r[0]);
-      }
-      s += T(sl.wj) * sy;
-    }
-    v += wk * s;
-  }
-  return v;
+template <typename E>
+__device__ inline E zbload(const __amdgpu_buffer_rsrc_t& r, unsigned off);
+template <>
+__device__ inline double zbload<double>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline float zbload<float>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline uint16_t zbload<uint16_t>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
 }
 
-struct CSlot {
-  long long off;      // ex + nx * ey (cell offset within a cell plane)
-  int ok;
-};
-
-__device__ inline CSlot make_cslot(const Geo& g, int i0, int j0, int CW, int CN, int idx) {
-  CSlot sl;
-  const int ex = i0 - 1 + idx % CW, ey = j0 - 1 + idx / CW;
-  sl.ok = idx < CN && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
-  sl.off = (long long)ex + (long long)g.nx * ey;
-  return sl;
+typedef unsigned int zu32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void zbstore(double v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(zu32x2, v), r, (int)off, 0, 0);
+}
+__device__ inline void zbstore(float v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
 }
 
-template <bool DK, typename T, typename CL>
-__device__ inline T zfill_c(const Geo& g, const CL& k, const CL& kref, const CSlot& sl, int ez) {
-  if (!sl.ok || ez < 0 || ez >= g.nz) return T(0);
-  const long long e = sl.off + (long long)g.nx * g.ny * ez;
-  return DK ? T(k(e)) - T(kref(e)) : T(k(e));
+// Byte offset, inside one plane of extent nxl x nyl, of LDS fill slot idx:
+// position (i0 - 1 + idx % W, j0 - 1 + idx / W) of the tile halo, or ZOOB when
+// the slot is not a real position (past the n slots, or outside the plane).
+__device__ inline unsigned zslot_off(int i0, int j0, int W, int n, int idx, int nxl, int nyl,
+                                     unsigned esz) {
+  const int ii = i0 - 1 + idx % W, jj = j0 - 1 + idx / W;
+  const bool ok = idx < n && ii >= 0 && ii < nxl && jj >= 0 && jj < nyl;
+  return ok ? (unsigned)(ii + nxl * jj) * esz : ZOOB;
 }
 
-template <int MODE, int XP, int ZD, typename T, typename CL>
-__global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 : 3))) void k_stencil_z(Geo g, Geo gc, int TXW, int TYH, int ntx, int nty,
-                                                  int KZ, const T* __restrict__ x,
-                                                  const T* __restrict__ ec, CL k, CL kref,
-                                                  const T* __restrict__ b,
-                                                  T* __restrict__ out, T omega,
-                                                  double* __restrict__ part,
-                                                  const int* __restrict__ done,
-                                                  unsigned* __restrict__ cnt,
-                                                  double* __restrict__ rout) {
+// Offset of plane p (any int) for a slot offset: out of range -> >= ZOOB.
+__device__ inline unsigned zplane(unsigned soff, int p, int np, unsigned plb) {
+  return (p >= 0 && p < np) ? soff + (unsigned)p * plb : ZOOB;
+}
+
+template <int MODE, int ZD, typename T, typename CL>
+__global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu((ZD == 1 || sizeof(T) == 4) ? 4 : 3))) void k_stencil_z(
+    Geo g, int TXW, int TYH, int ntx, int nty, int KZ, const T* __restrict__ x, CL k, CL kref,
+    const T* __restrict__ b, T* __restrict__ out, T omega, double* __restrict__ part,
+    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout) {
   if (done && *done) return;
+  using E = typename CL::E;
   constexpr bool DK = (MODE == SM_NEG_DK);
   constexpr bool NEEDX = (MODE != SM_JACOBI0);
   constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
                           MODE == SM_JACOBI0);
-  __shared__ T Xs[2][XCAP];
-  __shared__ T Cs[2][CCAP];
+  constexpr bool DOT = (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT);
+  constexpr unsigned TS = sizeof(T), ES = sizeof(E);
+  __shared__ T Xs[2][ZSLOT];
+  __shared__ T Cs[2][ZSLOT];
   __shared__ double sh[ZT / MGAR_WAVE];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int nxy = ntx * nty;
@@ -305,37 +280,62 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 
   const bool act = ly < TYH && i < g.nnx && j < g.nny;
   const int k0 = zc * KZ;
   const int k1 = min(k0 + KZ, g.nnz);
-  const long long pl = (long long)g.nnx * g.nny;
-  const long long nxy_off = (long long)i + (long long)g.nnx * j;
-  const XSlot xs0 = make_xslot(g, gc, i0, j0, XW, XN, tid);
-  const XSlot xs1 = make_xslot(g, gc, i0, j0, XW, XN, tid + ZT);
-  const CSlot cs0 = make_cslot(g, i0, j0, CW, CN, tid);
-  const CSlot cs1 = make_cslot(g, i0, j0, CW, CN, tid + ZT);
+  const unsigned plb = (unsigned)(g.nnx * g.nny) * TS;      // node plane, bytes
+  const unsigned cplb = (unsigned)(g.nx * g.ny) * ES;       // cell plane, bytes
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(x, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rb = zrsrc(b, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t ro = zrsrc(out, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
+  const __amdgpu_buffer_rsrc_t rkr = zrsrc(kref.p, g.ne * ES);
+  const unsigned own = act ? (unsigned)(i + g.nnx * j) * TS : ZOOB;   // this thread's node column
+  const unsigned xs0 = zslot_off(i0, j0, XW, XN, tid, g.nnx, g.nny, TS);
+  const unsigned xs1 = zslot_off(i0, j0, XW, XN, tid + ZT, g.nnx, g.nny, TS);
+  const unsigned cs0 = zslot_off(i0, j0, CW, CN, tid, g.nx, g.ny, ES);
+  const unsigned cs1 = zslot_off(i0, j0, CW, CN, tid + ZT, g.nx, g.ny, ES);
   // LDS index of this thread's node (x planes) and of its lower-left cell
   const int xc = act ? (ly + 1) * XW + (lx + 1) : XW + 1;
   const int cb = act ? ly * CW + lx : 0;
 
-#define ZX(sl, p) (NEEDX ? zfill_x<XP, T>(g, gc, x, ec, (sl), (p)) : T(0))
-#define ZC(sl, ez) zfill_c<DK, T, CL>(g, k, kref, (sl), (ez))
-#define ZB(p) ((NEEDB && act && (p) < k1) ? b[nxy_off + pl * (p)] : T(0))
+  // raw loads: x plane p of a slot, cell plane ez of a slot (both cell arrays
+  // for the dK mode), b of this thread's node in plane p
+#define ZX(so, p) (NEEDX ? zbload<T>(rx, zplane((so), (p), g.nnz, plb)) : T(0))
+#define ZB(p) (NEEDB ? zbload<T>(rb, zplane(own, (p), g.nnz, plb)) : T(0))
+  // cell value of a raw element pair (k, kref). An out-of-range load reads a
+  // raw 0, which is a zero conductivity for FP64/FP32 cells but a density for
+  // BF16 cells; those are masked by a multiply (a select on a loaded value
+  // would be compiled into a branch around the load).
+  constexpr bool CMASK = sizeof(E) == 2;
+#define ZCV(e, er) (DK ? T(k.value(e)) - T(kref.value(er)) : T(k.value(e)))
+#define ZCM(e, er, ok) (CMASK ? ZCV(e, er) * ((ok) ? T(1) : T(0)) : ZCV(e, er))
 
-  // register queue of global loads: entry d holds x plane kk+1+d, cell plane
-  // kk+d and b of plane kk+d for the step of node plane kk
-  T qx0[ZD], qx1[ZD], qc0[ZD], qc1[ZD], qb[ZD];
+  // register queue of raw global loads: entry d holds x plane kk+1+d, cell
+  // plane kk+d and b of plane kk+d for the step of node plane kk
+  T qx0[ZD], qx1[ZD], qb[ZD];
+  E qc0[ZD], qc1[ZD], qr0[ZD], qr1[ZD];
   // rolling register window: 3x3 of three x planes, 2x2 of two cell planes
   T W0[3][3], W1[3][3], W2[3][3], V0[2][2], V1[2][2];
 
   // prologue: planes k0-1 and k0 and cells k0-1 go through LDS into W0, W1, V0
-  if (tid < XN) { Xs[0][tid] = ZX(xs0, k0 - 1); Xs[1][tid] = ZX(xs0, k0); }
-  if (tid + ZT < XN) { Xs[0][tid + ZT] = ZX(xs1, k0 - 1); Xs[1][tid + ZT] = ZX(xs1, k0); }
-  if (tid < CN) Cs[0][tid] = ZC(cs0, k0 - 1);
-  if (tid + ZT < CN) Cs[0][tid + ZT] = ZC(cs1, k0 - 1);
+  {
+    const unsigned c0 = zplane(cs0, k0 - 1, g.nz, cplb), c1 = zplane(cs1, k0 - 1, g.nz, cplb);
+    Xs[0][tid] = ZX(xs0, k0 - 1);
+    Xs[1][tid] = ZX(xs0, k0);
+    Xs[0][tid + ZT] = ZX(xs1, k0 - 1);
+    Xs[1][tid + ZT] = ZX(xs1, k0);
+    const E e0 = zbload<E>(rk, c0), e1 = zbload<E>(rk, c1);
+    const E r0 = DK ? zbload<E>(rkr, c0) : E(0), r1 = DK ? zbload<E>(rkr, c1) : E(0);
+    Cs[0][tid] = ZCM(e0, r0, c0 < ZOOB);
+    Cs[0][tid + ZT] = ZCM(e1, r1, c1 < ZOOB);
+  }
 #pragma unroll
   for (int d = 0; d < ZD; ++d) {
     qx0[d] = ZX(xs0, k0 + 1 + d);
     qx1[d] = ZX(xs1, k0 + 1 + d);
-    qc0[d] = ZC(cs0, k0 + d);
-    qc1[d] = ZC(cs1, k0 + d);
+    const unsigned c0 = zplane(cs0, k0 + d, g.nz, cplb), c1 = zplane(cs1, k0 + d, g.nz, cplb);
+    qc0[d] = zbload<E>(rk, c0);
+    qc1[d] = zbload<E>(rk, c1);
+    qr0[d] = DK ? zbload<E>(rkr, c0) : E(0);
+    qr1[d] = DK ? zbload<E>(rkr, c1) : E(0);
     qb[d] = ZB(k0 + d);
   }
   __syncthreads();
@@ -354,22 +354,25 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 
 
   const bool colfix = act && i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y;
   const T hc = T(g.h * (1.0 / 3.0)), hf = T(g.h * (1.0 / 12.0));
+  const double actd = act ? 1.0 : 0.0;
   double dotv = 0.0;
 
   // One node plane kk: stage plane kk+1 and cells kk through LDS slot s, read
   // this thread's window of them into C and CB, refill the load queue, and
   // apply the stencil with A (plane kk-1), B (plane kk), C (plane kk+1),
-  // CA (cells below), CB (cells above).
+  // CA (cells below), CB (cells above). The body has no branch, so the loads
+  // of the queue stay in flight across steps.
 #define ZSTEP(A, B, C, CA, CB, s)                                                            \
   {                                                                                          \
-    if (tid < XN) Xs[s][tid] = qx0[0];                                                       \
-    if (tid + ZT < XN) Xs[s][tid + ZT] = qx1[0];                                             \
-    if (tid < CN) Cs[s][tid] = qc0[0];                                                       \
-    if (tid + ZT < CN) Cs[s][tid + ZT] = qc1[0];                                             \
-    const T bn = qb[0];                                                                 \
+    Xs[s][tid] = qx0[0];                                                                     \
+    Xs[s][tid + ZT] = qx1[0];                                                                \
+    Cs[s][tid] = ZCM(qc0[0], qr0[0], cs0 < ZOOB && kk < g.nz);                               \
+    Cs[s][tid + ZT] = ZCM(qc1[0], qr1[0], cs1 < ZOOB && kk < g.nz);                          \
+    const T bn = qb[0];                                                                      \
     _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
       qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1];                                              \
       qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
+      qr0[d] = qr0[d + 1]; qr1[d] = qr1[d + 1];                                              \
       qb[d] = qb[d + 1];                                                                     \
     }                                                                                        \
     __syncthreads();                                                                         \
@@ -382,36 +385,29 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 
     _Pragma("unroll") for (int a = 0; a < 2; ++a) CB[bb][a] = Cs[s][cb + bb * CW + a];       \
     {                                                                                        \
       const int pf = kk + ZD;                                                                \
-      const bool more = pf < k1;                                                             \
-      qx0[ZD - 1] = more ? ZX(xs0, pf + 1) : T(0);                                            \
-      qx1[ZD - 1] = more ? ZX(xs1, pf + 1) : T(0);                                            \
-      qc0[ZD - 1] = more ? ZC(cs0, pf) : T(0);                                                \
-      qc1[ZD - 1] = more ? ZC(cs1, pf) : T(0);                                                \
-      qb[ZD - 1] = more ? ZB(pf) : T(0);                                                      \
+      qx0[ZD - 1] = ZX(xs0, pf + 1);                                                         \
+      qx1[ZD - 1] = ZX(xs1, pf + 1);                                                         \
+      const unsigned c0 = zplane(cs0, pf, g.nz, cplb), c1 = zplane(cs1, pf, g.nz, cplb);     \
+      qc0[ZD - 1] = zbload<E>(rk, c0);                                                       \
+      qc1[ZD - 1] = zbload<E>(rk, c1);                                                       \
+      if (DK) qr0[ZD - 1] = zbload<E>(rkr, c0);                                              \
+      if (DK) qr1[ZD - 1] = zbload<E>(rkr, c1);                                              \
+      qb[ZD - 1] = ZB(pf);                                                                   \
     }                                                                                        \
-    if (act) {                                                                               \
-      T r = T(0);                                                                            \
-      if (!(colfix && kk >= g.f0z && kk <= g.f1z)) {                                         \
-        T ks;                                                                                \
-        const T y = apply27<T, NEEDX>(A, B, C, CA, CB, hc, hf, ks);                          \
-        const T xcv = NEEDX ? B[1][1] : T(0);                                                \
-        const T diag = hc * ks;                                                              \
-        if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) {                                      \
-          r = y;                                                                             \
-          if (MODE == SM_APPLY_DOT) dotv += (double)xcv * (double)r;                         \
-        } else if (MODE == SM_RESID) {                                                       \
-          r = bn - y;                                                                        \
-        } else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) {                             \
-          r = xcv + omega * (bn - y) / diag;                                                 \
-          if (MODE == SM_JACOBI_DOT) dotv += (double)bn * (double)r;                         \
-        } else if (MODE == SM_JACOBI0) {                                                     \
-          r = omega * bn / diag;                                                             \
-        } else if (MODE == SM_NEG_DK) {                                                      \
-          r = -y;                                                                            \
-        }                                                                                    \
-      }                                                                                      \
-      out[nxy_off + pl * kk] = r;                                                            \
-    }                                                                                        \
+    T ks;                                                                                    \
+    const T y = apply27<T, NEEDX>(A, B, C, CA, CB, hc, hf, ks);                              \
+    const T xcv = NEEDX ? B[1][1] : T(0);                                                    \
+    const T diag = hc * ks;                                                                  \
+    T r = T(0);                                                                              \
+    if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) r = y;                                     \
+    else if (MODE == SM_RESID) r = bn - y;                                                   \
+    else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) r = xcv + omega * (bn - y) / diag;  \
+    else if (MODE == SM_JACOBI0) r = omega * bn / diag;                                      \
+    else if (MODE == SM_NEG_DK) r = -y;                                                      \
+    r = (colfix && kk >= g.f0z && kk <= g.f1z) ? T(0) : r;                                   \
+    if (MODE == SM_APPLY_DOT) dotv += actd * ((double)xcv * (double)r);                      \
+    if (MODE == SM_JACOBI_DOT) dotv += actd * ((double)bn * (double)r);                      \
+    zbstore(r, ro, own + (unsigned)kk * plb);                                                \
     ++kk;                                                                                    \
   }
 
@@ -433,9 +429,10 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu(ZD == 1 ? 4 
   if (kk < k1) ZSTEP(W1, W2, W0, V0, V1, 0)
 #undef ZSTEP
 #undef ZX
-#undef ZC
 #undef ZB
-  if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
+#undef ZCV
+#undef ZCM
+  if (DOT) {
     const double sum = block_sum(dotv, sh);
     if (cnt) grid_reduce(sum, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
     else if (threadIdx.x == 0) part[blockIdx.x] = sum;
@@ -923,7 +920,7 @@ void stencil_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T
 }
 
 constexpr int ZMARCH_MIN_NODES = 20000;
-constexpr int ZKZ = 12;   // default z-planes per block (best at 129^3 with zd = 1)
+constexpr int ZKZ = 16;   // default z-planes per block (with a two-plane load queue)
 
 struct ZShape { int TXW, TYH, ntx, nty, nzc; };
 
@@ -945,19 +942,17 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
                    const T* b, T* out, T omega, double* part, const int* done, unsigned* cnt,
                    double* rout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nb = z.ntx * z.nty * z.nzc;
-  const T* ec = nullptr;
   // With events, the launch goes through hipExtLaunchKernelGGL, which records
   // them at the start and end of the kernel itself (no dispatch latency).
 #define ZCALL(M)                                                                                 \
   do {                                                                                           \
     if (ev0)                                                                                     \
-      hipExtLaunchKernelGGL((k_stencil_z<M, XP_PLAIN, ZD, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, \
-                            0, g, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, ec, k, kref, b, out,      \
-                            omega, part, done, cnt, rout);                                       \
+      hipExtLaunchKernelGGL((k_stencil_z<M, ZD, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, \
+                            z.TXW, z.TYH, z.ntx, z.nty, kz, x, k, kref, b, out, omega, part, done, \
+                            cnt, rout);                                                          \
     else                                                                                         \
-      k_stencil_z<M, XP_PLAIN, ZD, T, CL><<<nb, ZT, 0, s>>>(g, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, ec, \
-                                                            k, kref, b, out, omega, part, done,  \
-                                                            cnt, rout);                          \
+      k_stencil_z<M, ZD, T, CL><<<nb, ZT, 0, s>>>(g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, k, kref, b, \
+                                                  out, omega, part, done, cnt, rout);            \
   } while (0)
   switch (mode) {
     case SM_APPLY: ZCALL(SM_APPLY); break;
@@ -975,17 +970,21 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
 
 StencilCfg stencil_default_cfg(const Geo& g) {
   StencilCfg c{0, 0, 0, 0};
-  if (g.dim == 3 && g.nn >= ZMARCH_MIN_NODES) c = StencilCfg{1, ZKZ, 1, (g.nnx + 63) / 64};
+  if (g.dim == 3 && g.nn >= ZMARCH_MIN_NODES) {
+    const StencilCfg z{1, ZKZ, 2, (g.nnx + 63) / 64};
+    if (stencil_cfg_valid(g, z)) c = z;
+  }
   return c;
 }
 
 bool stencil_cfg_valid(const Geo& g, const StencilCfg& c) {
   if (c.kind == 0) return true;
   if (c.kind != 1 || g.dim != 3) return false;
-  if (c.kz < 1 || c.kz > 64 || (c.zd != 1 && c.zd != 2)) return false;
+  if (c.kz < 1 || c.kz > 64 || c.zd < 1 || c.zd > 4) return false;
   if (c.ntx < 1 || c.ntx > g.nnx) return false;
   const int txw = (g.nnx + c.ntx - 1) / c.ntx;
   if (txw > 64 || txw < 4) return false;
+  if (g.nn * 8 >= (1LL << 31) || g.ne * 8 >= (1LL << 31)) return false;   // 32-bit buffer offsets
   const ZShape z = zmarch_shape(g, c);
   return (long long)(z.TXW + 2) * (z.TYH + 2) <= XCAP && (long long)(z.TXW + 1) * (z.TYH + 1) <= CCAP &&
          (long long)z.TXW * z.TYH <= ZT;
@@ -1002,7 +1001,7 @@ int stencil_candidates(const Geo& g, StencilCfg* out, int cap) {
   const int kzs[] = {4, 6, 8, 12, 16, 24};
   const int widths[] = {64, 32};
   for (int w : widths)
-    for (int zd = 1; zd <= 2; ++zd)
+    for (int zd = 1; zd <= 4; ++zd)
       for (int kz : kzs) {
         const StencilCfg c{1, kz, zd, (g.nnx + w - 1) / w};
         const StencilCfg d = stencil_default_cfg(g);
@@ -1037,7 +1036,13 @@ int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T*
   const StencilCfg c = resolve_cfg(g, cfg);
   if (c.kind == 1) {
     const ZShape z = zmarch_shape(g, c);
-    if (c.zd == 2)
+    if (c.zd == 4)
+      zmarch_launch<4, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
+                              ev0, ev1);
+    else if (c.zd == 3)
+      zmarch_launch<3, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
+                              ev0, ev1);
+    else if (c.zd == 2)
       zmarch_launch<2, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
                               ev0, ev1);
     else

@@ -10,7 +10,7 @@ from tests.gpu_util import dev, host, rel_l2, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [[0, 0, 0, 0], [1, 4, 1, 1], [1, 6, 2, 2], [1, 12, 1, 1], [1, 24, 2, 2], [1, 5, 1, 3],
+SHAPES = [[0, 0, 0, 0], [1, 4, 1, 1], [1, 6, 2, 2], [1, 12, 1, 1], [1, 24, 2, 2], [1, 5, 1, 3], [1, 5, 3, 2], [1, 8, 4, 1],
           [1, 7, 2, 1], [1, 64, 1, 1]]
 
 
@@ -57,7 +57,7 @@ def test_invalid_shapes_refused():
     prob = W.tiny_3d(32, 32, 32, 4)
     h = handle(prob)
     before = h.mgar_tune_get(0, 0, 1)
-    for bad in ([1, 0, 1, 1], [1, 4, 3, 1], [2, 4, 1, 1], [1, 4, 1, 0], [1, 4, 1, 34], [1, 65, 1, 1]):
+    for bad in ([1, 0, 1, 1], [1, 4, 5, 1], [2, 4, 1, 1], [1, 4, 1, 0], [1, 4, 1, 34], [1, 65, 1, 1]):
         with pytest.raises(M.MgarError):
             h.mgar_tune_set(0, 0, 1, bad)
     assert h.mgar_tune_get(0, 0, 1) == before

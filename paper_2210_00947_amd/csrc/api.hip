@@ -1059,8 +1059,11 @@ namespace {
 
 // Times every candidate shape of one (class, level, mode) on scratch data and
 // keeps the fastest. Returns the best average launch time in microseconds.
+// Each timed launch is bracketed by its own pair of events, so launches never
+// overlap each other and small grids are timed as they run inside a solve.
 int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd, double* bd,
-             double* od, double* kd, uint16_t* kb, hipEvent_t e0, hipEvent_t e1, double* best_us) {
+             double* od, double* kd, uint16_t* kb, const std::vector<hipEvent_t>& ev,
+             double* best_us) {
   const Geo& g = h->lv[level].g;
   StencilCfg cand[64];
   const int nc = stencil_candidates(g, cand, 64);
@@ -1086,14 +1089,20 @@ int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd,
     };
     launch();
     launch();
-    HIPCK(hipEventRecord(e0, h->s));
-    for (int r = 0; r < reps; ++r) launch();
-    HIPCK(hipEventRecord(e1, h->s));
-    HIPCK(hipEventSynchronize(e1));
+    for (int r = 0; r < reps; ++r) {
+      HIPCK(hipEventRecord(ev[2 * r], h->s));
+      launch();
+      HIPCK(hipEventRecord(ev[2 * r + 1], h->s));
+    }
+    HIPCK(hipEventSynchronize(ev[2 * reps - 1]));
     LAUNCHCK();
-    float ms = 0.f;
-    HIPCK(hipEventElapsedTime(&ms, e0, e1));
-    const double us = 1e3 * (double)ms / reps;
+    double us = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+      us += 1e3 * (double)ms;
+    }
+    us /= reps;
     if (best < 0.0 || us < best) { best = us; bi = i; }
   }
   if (best >= 0.0) h->scfg[cls][level][mode] = cand[bi];
@@ -1111,18 +1120,20 @@ int mgar_autotune(mgar_handle* h, int reps, double* best_us) {
   const long long N = h->N, E = h->E;
   double *xd = nullptr, *bd = nullptr, *od = nullptr, *kd = nullptr;
   uint16_t* kb = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
   int rc = MGAR_OK;
   do {
     if (hipMalloc((void**)&xd, sizeof(double) * N) != hipSuccess ||
         hipMalloc((void**)&bd, sizeof(double) * N) != hipSuccess ||
         hipMalloc((void**)&od, sizeof(double) * N) != hipSuccess ||
         hipMalloc((void**)&kd, sizeof(double) * 2 * E) != hipSuccess ||
-        hipMalloc((void**)&kb, sizeof(uint16_t) * 2 * E) != hipSuccess ||
-        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        hipMalloc((void**)&kb, sizeof(uint16_t) * 2 * E) != hipSuccess) {
       rc = MGAR_E_HIP;
       break;
     }
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) rc = MGAR_E_HIP;
+    if (rc != MGAR_OK) break;
     const int ncls = h->mixed ? 2 : 1;
     for (int cls = 0; cls < ncls && rc == MGAR_OK; ++cls) {
       // scratch contents: smooth positive values of the class's element type
@@ -1143,7 +1154,7 @@ int mgar_autotune(mgar_handle* h, int reps, double* best_us) {
           // coarser grids only run the smoother sweeps and the residual
           if (l > 0 && m != SM_JACOBI0 && m != SM_RESID && m != SM_JACOBI) continue;
           double us = 0.0;
-          rc = tune_one(h, cls, l, m, reps, xd, bd, od, kd, kb, e0, e1, &us);
+          rc = tune_one(h, cls, l, m, reps, xd, bd, od, kd, kb, ev, &us);
           if (best_us) best_us[(cls * L + l) * 7 + m] = us;
         }
       }
@@ -1155,8 +1166,8 @@ int mgar_autotune(mgar_handle* h, int reps, double* best_us) {
   if (od) (void)hipFree(od);
   if (kd) (void)hipFree(kd);
   if (kb) (void)hipFree(kb);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   return rc;
 }
 

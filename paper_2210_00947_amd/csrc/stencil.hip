@@ -27,6 +27,62 @@ struct CellP {
   __device__ T operator()(long long e) const { return p[e]; }
 };
 
+// Buffer-resource access (gfx9 family descriptor: raw, stride 0, range
+// checked). A load whose byte offset lies beyond the range returns 0 and a
+// store there is dropped, so neighbours outside the grid, halo slots, planes
+// outside a z-range and threads past the grid need no branch: they just use
+// an offset at or above ZOOB, and every load of a kernel stays in flight
+// together. Offsets are 32-bit: the buffer kernels are used while every array
+// of the grid stays below 2 GiB (grid_fits_buffers); larger grids take the
+// pointer kernels.
+constexpr unsigned ZOOB = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t zrsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename E>
+__device__ inline E zbload(const __amdgpu_buffer_rsrc_t& r, unsigned off);
+template <>
+__device__ inline double zbload<double>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline float zbload<float>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline uint16_t zbload<uint16_t>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+
+typedef unsigned int zu32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void zbstore(double v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(zu32x2, v), r, (int)off, 0, 0);
+}
+__device__ inline void zbstore(float v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+// Node coordinates of flat index n (x fastest); threads of the buffer kernels
+// are laid out flat over the nodes, so every lane of a wave has a node.
+__device__ inline void node_ijk(const Geo& g, long long n, int& i, int& j, int& k) {
+  const long long r = n / g.nnx;
+  i = (int)(n - r * g.nnx);
+  j = (int)(r % g.nny);
+  k = (int)(r / g.nny);
+}
+
+// Byte offset of node (i, j, k) / cell (ex, ey, ez), or ZOOB outside the grid.
+__device__ inline unsigned node_boff(const Geo& g, int i, int j, int k, unsigned esz) {
+  const bool in = i >= 0 && i < g.nnx && j >= 0 && j < g.nny && k >= 0 && k < g.nnz;
+  return in ? (unsigned)(i + g.nnx * (j + g.nny * k)) * esz : ZOOB;
+}
+__device__ inline unsigned cell_boff(const Geo& g, int ex, int ey, int ez, unsigned esz) {
+  const bool in = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz;
+  return in ? (unsigned)(ex + g.nx * (ey + g.ny * ez)) * esz : ZOOB;
+}
+
 template <int DIM, bool DK, typename T, typename CL>
 __device__ inline void load_cells(const Geo& g, const CL& k, const CL& kref, int i, int j, int kz,
                                   T (&kv)[2][2][2]) {
@@ -175,6 +231,109 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const T* __restrict
   }
 }
 
+// Node-parallel stencil on buffer loads: all 2^d cell and up to 21 neighbour
+// loads of a thread are issued together (no branch separates them); the
+// per-node arithmetic is that of k_stencil. Threads past the grid and nodes
+// outside it read 0 and store nothing.
+template <int DIM, int MODE, typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_stencil_b(Geo g, const T* __restrict__ x, CL k, CL kref,
+                                                        const T* __restrict__ b, T* __restrict__ out,
+                                                        T omega, double* __restrict__ part,
+                                                        const int* __restrict__ done,
+                                                        unsigned* __restrict__ cnt,
+                                                        double* __restrict__ rout) {
+  if (done && *done) return;
+  using E = typename CL::E;
+  constexpr unsigned TS = sizeof(T), ES = sizeof(E);
+  constexpr bool DK = (MODE == SM_NEG_DK);
+  constexpr bool CMASK = sizeof(E) == 2;   // a raw 0 of a BF16 array is not a zero conductivity
+  __shared__ double sh[TBX * TBY / MGAR_WAVE];
+  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
+  const bool valid = n < g.nn;
+  int i, j, kz;
+  node_ijk(g, n, i, j, kz);   // past the grid: kz >= nnz, so every offset is out of range
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(x, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rb = zrsrc(b, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t ro = zrsrc(out, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
+  const __amdgpu_buffer_rsrc_t rkr = zrsrc(kref.p, g.ne * ES);
+  const unsigned own = node_boff(g, i, j, kz, TS);   // ZOOB for threads past the grid
+  T kv[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (DIM == 2 && c == 1) { kv[c][bb][a] = T(0); continue; }
+        const unsigned o = cell_boff(g, i - 1 + a, j - 1 + bb, DIM == 3 ? kz - 1 + c : 0, ES);
+        T v = T(k.value(zbload<E>(rk, o)));
+        if (DK) v -= T(kref.value(zbload<E>(rkr, o)));
+        kv[c][bb][a] = CMASK ? v * (o < ZOOB ? T(1) : T(0)) : v;
+      }
+  T ksum = T(0), y = T(0), xn = T(0);
+  if (DIM == 2) {
+    T xv[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) xv[dy][dx] = zbload<T>(rx, node_boff(g, i + dx - 1, j + dy - 1, 0, TS));
+    xn = xv[1][1];
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int sx = a ? 2 : 0, sy = bb ? 2 : 0;
+        const T ke = kv[0][bb][a];
+        s0 += ke;
+        s1 += ke * (xv[1][sx] + xv[sy][1]);
+        s2 += ke * xv[sy][sx];
+      }
+    ksum = s0;
+    y = T(2.0 / 3.0) * s0 * xv[1][1] - T(1.0 / 6.0) * s1 - T(1.0 / 3.0) * s2;
+  } else {
+    T xv[3][3][3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const int nzr = (dx != 1) + (dy != 1) + (dz != 1);
+          xv[dz][dy][dx] = (nzr == 1 || MODE == SM_JACOBI0)
+                               ? T(0)
+                               : zbload<T>(rx, node_boff(g, i + dx - 1, j + dy - 1, kz + dz - 1, TS));
+        }
+    xn = xv[1][1][1];
+    if (MODE != SM_JACOBI0)
+      y = apply27<T, true>(xv[0], xv[1], xv[2], kv[0], kv[1], T(g.h * (1.0 / 3.0)), T(g.h * (1.0 / 12.0)),
+                           ksum);
+    else
+      (void)apply27<T, false>(xv[0], xv[1], xv[2], kv[0], kv[1], T(0), T(0), ksum);
+  }
+  if (DIM == 2 && MODE == SM_JACOBI0)
+    ksum = ((kv[0][0][0] + kv[0][0][1]) + kv[0][1][0]) + kv[0][1][1];
+  const T bn = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT || MODE == SM_JACOBI0)
+                   ? zbload<T>(rb, own)
+                   : T(0);
+  const T diag = T(DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
+  T r = T(0);
+  if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) r = y;
+  else if (MODE == SM_RESID) r = bn - y;
+  else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) r = xn + omega * (bn - y) / diag;
+  else if (MODE == SM_JACOBI0) r = omega * bn / diag;
+  else if (MODE == SM_NEG_DK) r = -y;
+  r = geo_fixed(g, i, j, kz) ? T(0) : r;
+  zbstore(r, ro, own);
+  if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
+    const double d = (MODE == SM_APPLY_DOT) ? (double)xn * (double)r : (double)bn * (double)r;
+    const double s = block_sum(valid ? d : 0.0, sh);
+    if (cnt) grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
+    else if (flat_tid() == 0) part[blockIdx.x] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 3D z-marching stencil for the large grids. A block owns a TXW x TYH tile of
 // node columns and walks KZ consecutive z-planes. Each plane of x (tile plus a
@@ -200,41 +359,6 @@ __device__ inline int xcd_remap(int bid, int nb) {
   const int xcd = bid & 7, local = bid >> 3;
   const int q = nb >> 3, r = nb & 7;
   return xcd * q + (xcd < r ? xcd : r) + local;
-}
-
-// Buffer-resource access (gfx9 family descriptor: raw, stride 0, range
-// checked). A load whose byte offset lies beyond the range returns 0 and a
-// store there is dropped, so halo slots outside the grid, planes outside the
-// z-range and threads outside the tile need no branch: they just use an
-// offset at or above ZOOB. Offsets are 32-bit, so a z-marching grid must keep
-// every array below 2 GiB (checked by stencil_cfg_valid).
-constexpr unsigned ZOOB = 0x80000000u;
-
-__device__ inline __amdgpu_buffer_rsrc_t zrsrc(const void* p, long long bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-
-template <typename E>
-__device__ inline E zbload(const __amdgpu_buffer_rsrc_t& r, unsigned off);
-template <>
-__device__ inline double zbload<double>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-}
-template <>
-__device__ inline float zbload<float>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-template <>
-__device__ inline uint16_t zbload<uint16_t>(const __amdgpu_buffer_rsrc_t& r, unsigned off) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
-}
-
-typedef unsigned int zu32x2 __attribute__((ext_vector_type(2)));
-__device__ inline void zbstore(double v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(zu32x2, v), r, (int)off, 0, 0);
-}
-__device__ inline void zbstore(float v, const __amdgpu_buffer_rsrc_t& r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
 }
 
 // Byte offset, inside one plane of extent nxl x nyl, of LDS fill slot idx:
@@ -354,7 +478,6 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu((ZD == 1 || 
 
   const bool colfix = act && i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y;
   const T hc = T(g.h * (1.0 / 3.0)), hf = T(g.h * (1.0 / 12.0));
-  const double actd = act ? 1.0 : 0.0;
   double dotv = 0.0;
 
   // One node plane kk: stage plane kk+1 and cells kk through LDS slot s, read
@@ -405,8 +528,8 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu((ZD == 1 || 
     else if (MODE == SM_JACOBI0) r = omega * bn / diag;                                      \
     else if (MODE == SM_NEG_DK) r = -y;                                                      \
     r = (colfix && kk >= g.f0z && kk <= g.f1z) ? T(0) : r;                                   \
-    if (MODE == SM_APPLY_DOT) dotv += actd * ((double)xcv * (double)r);                      \
-    if (MODE == SM_JACOBI_DOT) dotv += actd * ((double)bn * (double)r);                      \
+    if (MODE == SM_APPLY_DOT) dotv += act ? (double)xcv * (double)r : 0.0;                   \
+    if (MODE == SM_JACOBI_DOT) dotv += act ? (double)bn * (double)r : 0.0;                   \
     zbstore(r, ro, own + (unsigned)kk * plb);                                                \
     ++kk;                                                                                    \
   }
@@ -497,6 +620,76 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const T* _
     s += wj * sy;
   }
   xf[geo_node(gf, i, j, k)] += wk * s;
+}
+
+// Buffer-load forms of the two transfers: every load of a thread in flight at
+// once, nothing outside the grid read, same arithmetic as the kernels above.
+template <int DIM, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T* __restrict__ rf,
+                                                         T* __restrict__ rc,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr unsigned TS = sizeof(T);
+  int I, J, K;
+  node_ijk(gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), I, J, K);
+  const __amdgpu_buffer_rsrc_t rr = zrsrc(rf, gf.nn * TS);
+  const __amdgpu_buffer_rsrc_t ro = zrsrc(rc, gc.nn * TS);
+  T s = T(0);
+#pragma unroll
+  for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
+    T sy = T(0);
+#pragma unroll
+    for (int bb = -1; bb <= 1; ++bb) {
+      T sx = T(0);
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        const T v = zbload<T>(rr, node_boff(gf, 2 * I + a, 2 * J + bb, 2 * K + c, TS));
+        sx += T(a == 0 ? 1.0 : 0.5) * v;
+      }
+      sy += T(bb == 0 ? 1.0 : 0.5) * sx;
+    }
+    s += T(c == 0 ? 1.0 : 0.5) * sy;
+  }
+  s = geo_fixed(gc, I, J, K) ? T(0) : s;
+  zbstore(s, ro, node_boff(gc, I, J, K, TS));
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_prolong_b(Geo gf, Geo gc, const T* __restrict__ xc,
+                                                        T* __restrict__ xf,
+                                                        const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr unsigned TS = sizeof(T);
+  int i, j, k;
+  node_ijk(gf, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), i, j, k);
+  const __amdgpu_buffer_rsrc_t rc = zrsrc(xc, gc.nn * TS);
+  const __amdgpu_buffer_rsrc_t rf = zrsrc(xf, gf.nn * TS);
+  // fixed fine rows of P are 0: such nodes (and threads past the grid) use an
+  // out-of-range offset, so they read 0 and their store is dropped
+  const unsigned own = geo_fixed(gf, i, j, k) ? ZOOB : node_boff(gf, i, j, k, TS);
+  const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+  // second coarse neighbour along an axis only for odd fine indices
+  const T mi = T(i & 1), mj = T(j & 1), mk = T(DIM == 3 ? (k & 1) : 0);
+  const T wi = T((i & 1) ? 0.5 : 1.0), wj = T((j & 1) ? 0.5 : 1.0),
+          wk = T((DIM == 3 && (k & 1)) ? 0.5 : 1.0);
+  T v[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        v[c][bb][a] = (DIM == 2 && c == 1) ? T(0) : zbload<T>(rc, node_boff(gc, I0 + a, J0 + bb, K0 + c, TS));
+  const T xo = zbload<T>(rf, own);
+  T sc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const T s0 = v[c][0][0] + mi * v[c][0][1];
+    const T s1 = v[c][1][0] + mi * v[c][1][1];
+    sc[c] = wi * s0 + mj * (wi * s1);
+  }
+  const T s = wj * sc[0] + mk * (wj * sc[1]);
+  zbstore(xo + wk * s, rf, own);
 }
 
 // Coarse conductivity: mean of the 2^d children.
@@ -901,12 +1094,24 @@ __global__ __launch_bounds__(TT) void k_vtail(TailSpec TS, const T* __restrict__
 dim3 node_grid(const Geo& g) {
   return dim3((g.nnx + TBX - 1) / TBX, (g.nny + TBY - 1) / TBY, g.nnz);
 }
+// flat launch of the buffer kernels: one thread per node
+dim3 flat_grid(const Geo& g) { return dim3((unsigned)((g.nn + TBX * TBY - 1) / (TBX * TBY))); }
+
+// Buffer kernels need every array of the grid below 2 GiB (32-bit offsets).
+bool grid_fits_buffers(const Geo& g) { return g.nn * 8 < (1LL << 31) && g.ne * 8 < (1LL << 31); }
 
 template <int DIM, typename T, typename CL>
 void stencil_dispatch(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out, T omega,
                       double* part, const int* done, unsigned* cnt, double* rout, hipStream_t s) {
-  const dim3 grid = node_grid(g), blk(TBX, TBY, 1);
-#define SCALL(M) k_stencil<DIM, M, T, CL><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout)
+  const dim3 grid = node_grid(g), fgrid = flat_grid(g), blk(TBX, TBY, 1);
+  const bool buf = grid_fits_buffers(g);
+#define SCALL(M)                                                                                   \
+  do {                                                                                             \
+    if (buf)                                                                                       \
+      k_stencil_b<DIM, M, T, CL><<<fgrid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); \
+    else                                                                                           \
+      k_stencil<DIM, M, T, CL><<<grid, blk, 0, s>>>(g, x, k, kref, b, out, omega, part, done, cnt, rout); \
+  } while (0)
   switch (mode) {
     case SM_APPLY: SCALL(SM_APPLY); break;
     case SM_APPLY_DOT: SCALL(SM_APPLY_DOT); break;
@@ -1021,7 +1226,7 @@ int stencil_num_partials(const Geo& g, const StencilCfg* cfg) {
     const ZShape z = zmarch_shape(g, c);
     return z.ntx * z.nty * z.nzc;
   }
-  const dim3 grid = node_grid(g);
+  const dim3 grid = grid_fits_buffers(g) ? flat_grid(g) : node_grid(g);
   return (int)(grid.x * grid.y * grid.z);
 }
 
@@ -1080,8 +1285,13 @@ int launch_stencil(const Geo& g, int mode, const double* x, const double* k, con
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s) {
   const dim3 grid = node_grid(gc), blk(TBX, TBY, 1);
-  if (gf.dim == 2) k_restrict<2, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
-  else k_restrict<3, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
+  if (grid_fits_buffers(gf)) {
+    if (gf.dim == 2) k_restrict_b<2, T><<<flat_grid(gc), blk, 0, s>>>(gf, gc, rf, rc, done);
+    else k_restrict_b<3, T><<<flat_grid(gc), blk, 0, s>>>(gf, gc, rf, rc, done);
+  } else {
+    if (gf.dim == 2) k_restrict<2, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
+    else k_restrict<3, T><<<grid, blk, 0, s>>>(gf, gc, rf, rc, done);
+  }
 }
 template void launch_restrict_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
 template void launch_restrict_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);
@@ -1089,8 +1299,13 @@ template void launch_restrict_t<float>(const Geo&, const Geo&, const float*, flo
 template <typename T>
 void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s) {
   const dim3 grid = node_grid(gf), blk(TBX, TBY, 1);
-  if (gf.dim == 2) k_prolong<2, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
-  else k_prolong<3, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
+  if (grid_fits_buffers(gf)) {
+    if (gf.dim == 2) k_prolong_b<2, T><<<flat_grid(gf), blk, 0, s>>>(gf, gc, xc, xf, done);
+    else k_prolong_b<3, T><<<flat_grid(gf), blk, 0, s>>>(gf, gc, xc, xf, done);
+  } else {
+    if (gf.dim == 2) k_prolong<2, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
+    else k_prolong<3, T><<<grid, blk, 0, s>>>(gf, gc, xc, xf, done);
+  }
 }
 template void launch_prolong_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
 template void launch_prolong_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);

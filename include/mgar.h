@@ -189,6 +189,39 @@ int mgar_autotune(mgar_handle* h, int reps, double* best_us);
 int mgar_tune_get(const mgar_handle* h, int cls, int level, int mode, int* shape);
 int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape);
 
+/* ---- Batched solves (many independent designs at once). --------------------
+ * A batch holds `ndesigns` designs of uneven grids (2D and 3D may be mixed),
+ * each described by its own mgar_params (FP64 only; n_basis, omega,
+ * eps_accept, cg_max and basis_x0_zero must agree across designs; levels >= 2).
+ * The designs' K(xphys) t = q are solved together: every stage of the V-cycle
+ * and of the PCG iteration is one launch per dimension over all designs'
+ * grids, with per-design PCG state on the device, so converged designs drop
+ * out and one PCG iteration is captured once as a hipGraph and replayed until
+ * every design stopped. Each design gets the same solution as its own
+ * mgcg_solve / mgar_solve up to the summation order of dot products.
+ * Arrays are concatenations over designs in params order: design d's nodes
+ * start at node_off[d] and its elements at elem_off[d] (mgar_batch_layout;
+ * both host arrays of ndesigns + 1 entries, the last = totals). stats: host
+ * array of ndesigns reports (may be NULL). stream NULL: the batch works on a
+ * stream of its own, ordered after the caller's default stream; every call
+ * returns with its work complete. */
+typedef struct mgar_batch mgar_batch;
+int mgar_batch_setup(const mgar_params* p, int ndesigns, void* stream, mgar_batch** out);
+void mgar_batch_destroy(mgar_batch* b);
+int mgar_batch_layout(const mgar_batch* b, long long* node_off, long long* elem_off);
+/* 1 (default): replay the captured PCG iteration graph; 0: launch eagerly. */
+int mgar_batch_set_graph(mgar_batch* b, int use_graph);
+/* Per design, as mgar_load_vector. */
+int mgar_batch_load_vector(mgar_batch* b, const double* Qe, double* q);
+/* Per design, as mgcg_solve (T0 may be NULL = 0) and mgar_solve (requires a
+ * previous mgcg_batch_solve: MGAR_E_STATE otherwise). Returns MGAR_OK,
+ * MGAR_W_NOT_CONVERGED if any design hit cg_max, or an error. In the batched
+ * reanalysis only designs whose reduced solution is rejected renew K0. */
+int mgcg_batch_solve(mgar_batch* b, const double* xphys, const double* q, const double* T0,
+                     double tol, double* T, mgar_stats* stats);
+int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const double* T0,
+                     double tol, double* T, mgar_stats* stats);
+
 /* ---- Instrumentation. ------------------------------------------------------
  * Kernel timing for roofline reports: while enabled, every launch of a
  * finest-grid stencil kernel whose mode bit is set in `mode_mask` is bracketed

@@ -1191,3 +1191,8 @@ int mgar_profile_read(mgar_handle* h, long long* launches, double* total_ms, dou
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- shared with batch.hip
+Geo mgar_internal_geo(const mgar_params& p, int level) { return make_geo(p, level); }
+long long mgar_internal_count_fixed(const Geo& g) { return count_fixed(g); }
+int mgar_internal_validate(const mgar_params* p) { return validate(p); }

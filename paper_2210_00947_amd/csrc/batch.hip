@@ -1,0 +1,665 @@
+// Batched solves: many independent designs (uneven grids, 2D and 3D) advanced
+// together. Every stage of a V-cycle, of a PCG iteration and of the
+// reanalysis step is ONE launch per dimension group over a work list of
+// (design, grid) items, so a batch of small designs costs about as many
+// launches as one design. Convergence is per design: the PCG state of each
+// design (BCgState, iteration counter included) lives on the device and every
+// kernel skips the blocks of designs that are done, so the launches of a PCG
+// iteration are captured once in a hipGraph and replayed until all designs
+// have stopped.
+//
+// Arrays passed through the ABI are concatenations over designs in the order
+// of the params array (layout from mgar_batch_layout). The arithmetic per
+// design is that of the single-design FP64 path (same stencil, transfer,
+// smoother, tail and coarsest-inverse code); only dot products are summed in
+// a different block order.
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+#include "mgar.h"
+#include "mgar_launch.h"
+
+namespace {
+
+#define BHIP(x)                                   \
+  do {                                            \
+    hipError_t err_ = (x);                        \
+    if (err_ != hipSuccess) return MGAR_E_HIP;    \
+  } while (0)
+#define BACK(x)                                   \
+  do {                                            \
+    int rc_ = (x);                                \
+    if (rc_ != MGAR_OK) return rc_;               \
+  } while (0)
+#define BLAUNCH() BHIP(hipGetLastError())
+
+constexpr int ST_STRIDE = (int)(sizeof(BCgState) / sizeof(int));
+constexpr int MD_STRIDE = (int)(sizeof(MgarDev) / sizeof(double));
+static_assert(sizeof(BCgState) % sizeof(int) == 0, "BCgState stride");
+static_assert(sizeof(MgarDev) % sizeof(double) == 0, "MgarDev stride");
+constexpr int ITERS_PER_GRAPH = 4;
+
+template <typename T>
+int dalloc(T** p, long long n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  BHIP(hipMalloc((void**)p, sizeof(T) * (size_t)n));
+  return MGAR_OK;
+}
+
+// A list of work items in device memory (host copy kept for block counts).
+struct ItemList {
+  std::vector<BItem> h;
+  BItem* d = nullptr;
+  int nblk = 0;
+  int n() const { return (int)h.size(); }
+};
+
+struct Design {
+  mgar_params p;
+  int L = 0, lt = 1;
+  std::vector<Geo> g;
+  long long noff = 0, eoff = 0;          // offsets in the concatenated finest arrays
+  std::vector<long long> aoff, aeoff;    // offsets in the group arenas, levels >= 1
+  long long Aoff = 0;                    // offset of the coarsest inverse
+};
+
+struct Group {
+  int dim = 0;
+  std::vector<int> designs;
+  int maxL = 0, maxlt = 0;
+  // arenas of grids >= 1 (index l; entry 0 unused)
+  std::vector<double*> b, xa, xb, rt, k;
+  std::vector<ItemList> down, restr, prol, coarsen;   // per level
+  ItemList fine;          // finest grid of every design: vector and dot items
+  ItemList cells;         // finest cells of every design
+  BTail* tails = nullptr;
+  int ntails = 0, tail_lds = 0;
+  BCoarse* cb_reg = nullptr;
+  BCoarse* cb_gen = nullptr;
+  int n_reg = 0, n_gen = 0;
+};
+
+int upload(ItemList& L) {
+  int first = 0;
+  for (BItem& it : L.h) {
+    it.first = first;
+    first += it.nblk;
+  }
+  L.nblk = first;
+  if (L.h.empty()) return MGAR_OK;
+  BACK(dalloc(&L.d, (long long)L.h.size()));
+  BHIP(hipMemcpy(L.d, L.h.data(), sizeof(BItem) * L.h.size(), hipMemcpyHostToDevice));
+  return MGAR_OK;
+}
+
+BItem make_item(const Geo& g, const Geo& gc, long long off, long long coff, long long eoff,
+                long long ceoff, int design, int nblk) {
+  BItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.g = g;
+  it.gc = gc;
+  it.off = off;
+  it.coff = coff;
+  it.eoff = eoff;
+  it.ceoff = ceoff;
+  it.design = design;
+  it.nblk = nblk;
+  return it;
+}
+
+int blocks_of(long long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+struct mgar_batch {
+  int nd = 0;
+  hipStream_t s = nullptr;
+  std::vector<Design> d;
+  std::vector<Group> grp;
+  long long N = 0, E = 0, Atot = 0;
+  int m = 2;
+  double omega = 0.8, eps = 1e-8;
+  int cg_max = 200;
+  int basis_x0_zero = 0;
+  bool has_k0 = false;
+  bool use_graph = true;
+  // finest-grid concatenations
+  double *kcur = nullptr, *k0 = nullptr;
+  double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
+  double *xa0 = nullptr, *rt0 = nullptr;
+  double *R = nullptr, *Wm = nullptr;
+  double* Ainv = nullptr;
+  double *pa = nullptr, *pb = nullptr, *pc = nullptr;
+  BCgState* st = nullptr;
+  MgarDev* md = nullptr;
+  int *keep = nullptr, *path = nullptr, *status = nullptr;
+  double *res = nullptr, *nrm = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double tol_captured = -1.0;
+  // Work runs on `s`. A graph cannot be captured on the legacy default
+  // stream, so when the caller passes NULL the batch owns a stream of its own
+  // (default priority) and orders it after the caller's stream at every entry.
+  hipStream_t user_s = nullptr;
+  bool own_stream = false;
+  hipEvent_t ein = nullptr;
+};
+
+namespace {
+
+const int* st_done(const mgar_batch* b) { return &b->st[0].done; }
+
+// ---------------------------------------------------------------- stages
+
+// One V-cycle of Table 1 for every design of group G on its K0 hierarchy:
+// out = MG(b0, x0) (x0 may be null = zero guess); with part, the final sweep
+// also writes the partials of b0 . out per finest block. skip: designs to leave
+// untouched.
+int bvcycle(mgar_batch* B, Group& G, const double* b0, const double* x0, double* out, double* part,
+            const int* skip) {
+  const int ss = ST_STRIDE;
+  for (int l = 0; l < G.maxlt; ++l) {
+    ItemList& D = G.down[l];
+    if (D.h.empty()) continue;
+    const double* bl = (l == 0) ? b0 : G.b[l];
+    double* xal = (l == 0) ? B->xa0 : G.xa[l];
+    double* rtl = (l == 0) ? B->rt0 : G.rt[l];
+    const double* kl = (l == 0) ? B->k0 : G.k[l];
+    if (l == 0 && x0)
+      launch_bstencil(G.dim, SM_JACOBI, D.d, D.n(), D.nblk, x0, kl, nullptr, bl, xal, B->omega, nullptr,
+                      skip, ss, B->s);
+    else
+      launch_bstencil(G.dim, SM_JACOBI0, D.d, D.n(), D.nblk, bl, kl, nullptr, bl, xal, B->omega, nullptr,
+                      skip, ss, B->s);
+    launch_bstencil(G.dim, SM_RESID, D.d, D.n(), D.nblk, xal, kl, nullptr, bl, rtl, B->omega, nullptr,
+                    skip, ss, B->s);
+    ItemList& Rs = G.restr[l];
+    launch_brestrict(G.dim, Rs.d, Rs.n(), Rs.nblk, rtl, G.b[l + 1], skip, ss, B->s);
+  }
+  launch_bvtail(G.dim, G.tails, G.ntails, G.tail_lds, B->omega, skip, ss, B->s);
+  for (int l = G.maxlt - 1; l >= 0; --l) {
+    ItemList& D = G.down[l];
+    if (D.h.empty()) continue;
+    const double* bl = (l == 0) ? b0 : G.b[l];
+    double* xal = (l == 0) ? B->xa0 : G.xa[l];
+    const double* kl = (l == 0) ? B->k0 : G.k[l];
+    ItemList& P = G.prol[l];
+    launch_bprolong(G.dim, P.d, P.n(), P.nblk, G.xb[l + 1], xal, skip, ss, B->s);
+    double* o = (l == 0) ? out : G.xb[l];
+    const int mode = (l == 0 && part) ? SM_JACOBI_DOT : SM_JACOBI;
+    launch_bstencil(G.dim, mode, D.d, D.n(), D.nblk, xal, kl, nullptr, bl, o, B->omega, part, skip, ss,
+                    B->s);
+  }
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+// K0 := K(kcur) for every design of G whose keep flag is 0 (all with keep null):
+// finest cells, cell means of every coarser grid, coarsest inverses.
+int bbuild(mgar_batch* B, Group& G, const int* keep) {
+  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, B->kcur, B->k0, keep, 1, B->s);
+  for (int l = 0; l + 1 < G.maxL; ++l) {
+    ItemList& C = G.coarsen[l];
+    launch_bcoarsen(G.dim, C.d, C.n(), C.nblk, (l == 0) ? B->k0 : G.k[l], G.k[l + 1], keep, 1, B->s);
+  }
+  launch_bcoarse_build(G.dim, G.cb_reg, G.n_reg, true, B->status, keep, 1, B->s);
+  launch_bcoarse_build(G.dim, G.cb_gen, G.n_gen, false, B->status, keep, 1, B->s);
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+// One PCG iteration for every design of G that is not done (device-side
+// iteration counters, so the sequence can be captured and replayed).
+int biter(mgar_batch* B, Group& G, double tol) {
+  ItemList& F = G.fine;
+  const int* skip = st_done(B);
+  double* rz = &B->st[0].rz[0];
+  BACK(bvcycle(B, G, B->cr, nullptr, B->cz, B->pb, skip));
+  launch_bfinalize(F.d, F.n(), B->pb, 1, rz, (int)(sizeof(BCgState) / sizeof(double)), &B->st[0].it, skip,
+                   ST_STRIDE, B->s);
+  launch_bp_update(F.d, F.n(), F.nblk, B->cz, B->cp, B->st, B->s);
+  launch_bstencil(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, B->cp, B->kcur, nullptr, nullptr, B->cw, 0.0,
+                  B->pc, skip, ST_STRIDE, B->s);
+  launch_bfinalize(F.d, F.n(), B->pc, 1, &B->st[0].pw, (int)(sizeof(BCgState) / sizeof(double)), nullptr,
+                   skip, ST_STRIDE, B->s);
+  launch_bcg_update(F.d, F.n(), F.nblk, B->cx, B->cr, B->cp, B->cw, B->st, B->pa, B->s);
+  launch_bcg_check(F.d, F.n(), B->st, B->pa, tol, B->cg_max, B->s);
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+int enqueue_iters(mgar_batch* B, double tol, int n) {
+  for (int i = 0; i < n; ++i)
+    for (Group& G : B->grp) BACK(biter(B, G, tol));
+  return MGAR_OK;
+}
+
+// PCG from cx for every design (those with keep_done set stay as they are):
+// r = q - K x, stopping test, then iterations until every design stopped.
+int bpcg(mgar_batch* B, double tol, const int* keep_done) {
+  for (Group& G : B->grp) {
+    ItemList& F = G.fine;
+    launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
+                    nullptr, 0, B->s);
+    launch_bdot(F.d, F.n(), F.nblk, B->cr, B->cr, B->pa, nullptr, 0, B->s);
+    launch_bdot(F.d, F.n(), F.nblk, B->qm, B->qm, B->pb, nullptr, 0, B->s);
+    launch_bcg_init(F.d, F.n(), B->st, B->pb, B->pa, tol, B->cg_max, keep_done, B->s);
+  }
+  BLAUNCH();
+  // (re)capture the iteration graph when the tolerance it was built for changed
+  if (B->use_graph && (!B->gexec || B->tol_captured != tol)) {
+    if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
+    if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+    BHIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_iters(B, tol, ITERS_PER_GRAPH);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->s, &gr);
+    if (rc != MGAR_OK) return rc;
+    BHIP(e);
+    B->graph = gr;
+    BHIP(hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0));
+    B->tol_captured = tol;
+  }
+  std::vector<BCgState> hs(B->nd);
+  int done_iters = 0;
+  for (;;) {
+    BHIP(hipMemcpyAsync(hs.data(), B->st, sizeof(BCgState) * B->nd, hipMemcpyDeviceToHost, B->s));
+    BHIP(hipStreamSynchronize(B->s));
+    bool all = true;
+    for (const BCgState& x : hs) all = all && x.done;
+    if (all) break;
+    if (done_iters > B->cg_max + ITERS_PER_GRAPH) return MGAR_E_HIP;   // the device test must have fired
+    if (B->use_graph) BHIP(hipGraphLaunch(B->gexec, B->s));
+    else BACK(enqueue_iters(B, tol, ITERS_PER_GRAPH));
+    done_iters += ITERS_PER_GRAPH;
+  }
+  return MGAR_OK;
+}
+
+int finish(mgar_batch* B, double* T, mgar_stats* stats, int default_path) {
+  launch_copy(B->cx, T, B->N, B->s);
+  BLAUNCH();
+  BHIP(hipEventRecord(B->e1, B->s));
+  std::vector<BCgState> hs(B->nd);
+  std::vector<int> hp(B->nd, default_path), hstat(B->nd, 0);
+  std::vector<double> hr(B->nd, NAN);
+  BHIP(hipMemcpyAsync(hs.data(), B->st, sizeof(BCgState) * B->nd, hipMemcpyDeviceToHost, B->s));
+  BHIP(hipMemcpyAsync(hstat.data(), B->status, sizeof(int) * B->nd, hipMemcpyDeviceToHost, B->s));
+  if (default_path < 0) {
+    BHIP(hipMemcpyAsync(hp.data(), B->path, sizeof(int) * B->nd, hipMemcpyDeviceToHost, B->s));
+    BHIP(hipMemcpyAsync(hr.data(), B->res, sizeof(double) * B->nd, hipMemcpyDeviceToHost, B->s));
+  }
+  BHIP(hipStreamSynchronize(B->s));
+  float ms = 0.f;
+  BHIP(hipEventElapsedTime(&ms, B->e0, B->e1));
+  int rc = MGAR_OK;
+  for (int i = 0; i < B->nd; ++i) {
+    if (hstat[i]) return MGAR_E_NOT_SPD;
+    const bool accepted = (hp[i] == MGAR_PATH_ACCEPT);
+    if (!accepted && !hs[i].conv) rc = MGAR_W_NOT_CONVERGED;
+    if (stats) {
+      mgar_stats& o = stats[i];
+      std::memset(&o, 0, sizeof(o));
+      o.path = hp[i];
+      o.cg_iters = accepted ? 0 : hs[i].it;
+      o.vcycles = (default_path < 0 ? B->m - 1 : 0) + o.cg_iters;
+      o.refinements = 0;
+      o.res_ca = hr[i];
+      o.res_final = accepted ? hr[i] : (hs[i].qq > 0.0 ? std::sqrt(hs[i].rr / hs[i].qq) : 0.0);
+      o.ms = ms;
+    }
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mgar_batch_destroy(mgar_batch* b) {
+  if (!b) return;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
+  for (Group& G : b->grp) {
+    for (size_t l = 0; l < G.b.size(); ++l) { f(G.b[l]); f(G.xa[l]); f(G.xb[l]); f(G.rt[l]); f(G.k[l]); }
+    for (auto* v : {&G.down, &G.restr, &G.prol, &G.coarsen})
+      for (ItemList& L : *v) f(L.d);
+    f(G.fine.d); f(G.cells.d); f(G.tails); f(G.cb_reg); f(G.cb_gen);
+  }
+  for (void* p : {(void*)b->kcur, (void*)b->k0, (void*)b->qm, (void*)b->cx, (void*)b->cr, (void*)b->cz,
+                  (void*)b->cp, (void*)b->cw, (void*)b->xa0, (void*)b->rt0, (void*)b->R, (void*)b->Wm,
+                  (void*)b->Ainv, (void*)b->pa, (void*)b->pb, (void*)b->pc, (void*)b->st, (void*)b->md,
+                  (void*)b->keep, (void*)b->path, (void*)b->status, (void*)b->res, (void*)b->nrm})
+    f(p);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  if (b->ein) (void)hipEventDestroy(b->ein);
+  if (b->own_stream && b->s) (void)hipStreamDestroy(b->s);
+  delete b;
+}
+
+static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_batch* B) {
+  B->nd = nd;
+  B->user_s = (hipStream_t)stream;
+  if (B->user_s) {
+    B->s = B->user_s;
+  } else {
+    BHIP(hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking));
+    B->own_stream = true;
+  }
+  B->m = p[0].n_basis;
+  B->omega = p[0].omega;
+  B->eps = p[0].eps_accept;
+  B->cg_max = p[0].cg_max;
+  B->basis_x0_zero = p[0].basis_x0_zero;
+  B->d.resize(nd);
+  for (int i = 0; i < nd; ++i) {
+    BACK(mgar_internal_validate(&p[i]));
+    if (p[i].precision != MGAR_PREC_FP64) return MGAR_E_PRECISION;
+    if (p[i].levels < 2) return MGAR_E_DIMS;
+    if (p[i].n_basis != B->m || p[i].omega != B->omega || p[i].eps_accept != B->eps ||
+        p[i].cg_max != B->cg_max || p[i].basis_x0_zero != B->basis_x0_zero)
+      return MGAR_E_ARG;
+    Design& D = B->d[i];
+    D.p = p[i];
+    if (D.p.dim == 2) { D.p.nelz = 0; D.p.fix_lo[2] = 0; D.p.fix_hi[2] = 0; }
+    D.L = D.p.levels;
+    for (int l = 0; l < D.L; ++l) D.g.push_back(mgar_internal_geo(D.p, l));
+    const Geo& gc = D.g[D.L - 1];
+    if (gc.nn > 1024) return MGAR_E_DIMS;
+    if (mgar_internal_count_fixed(gc) == 0) return MGAR_E_SINGULAR;
+    if (D.g[0].nn * 8 >= (1LL << 31)) return MGAR_E_DIMS;
+    D.noff = B->N;
+    D.eoff = B->E;
+    B->N += D.g[0].nn;
+    B->E += D.g[0].ne;
+    D.Aoff = B->Atot;
+    B->Atot += gc.nn * gc.nn;
+  }
+  // groups by dimension
+  for (int dim = 2; dim <= 3; ++dim) {
+    Group G;
+    G.dim = dim;
+    for (int i = 0; i < nd; ++i)
+      if (B->d[i].p.dim == dim) G.designs.push_back(i);
+    if (G.designs.empty()) continue;
+    for (int i : G.designs) G.maxL = std::max(G.maxL, B->d[i].L);
+    G.b.assign(G.maxL, nullptr);
+    G.xa.assign(G.maxL, nullptr);
+    G.xb.assign(G.maxL, nullptr);
+    G.rt.assign(G.maxL, nullptr);
+    G.k.assign(G.maxL, nullptr);
+    // arenas of grids >= 1
+    for (int l = 1; l < G.maxL; ++l) {
+      long long nn = 0, ne = 0;
+      for (int i : G.designs) {
+        Design& D = B->d[i];
+        D.aoff.resize(D.L, 0);
+        D.aeoff.resize(D.L, 0);
+        if (l < D.L) {
+          D.aoff[l] = nn;
+          D.aeoff[l] = ne;
+          nn += D.g[l].nn;
+          ne += D.g[l].ne;
+        }
+      }
+      BACK(dalloc(&G.b[l], nn));
+      BACK(dalloc(&G.xa[l], nn));
+      BACK(dalloc(&G.xb[l], nn));
+      BACK(dalloc(&G.rt[l], nn));
+      BACK(dalloc(&G.k[l], ne));
+    }
+    B->grp.push_back(G);
+  }
+  // tail level of every design (same rule as a single handle)
+  for (Group& G : B->grp) {
+    std::vector<BTail> tails;
+    std::vector<BCoarse> creg, cgen;
+    for (int i : G.designs) {
+      Design& D = B->d[i];
+      std::vector<const void*> ks(D.L, nullptr);
+      ks[0] = nullptr;
+      for (int l = 1; l < D.L; ++l) ks[l] = G.k[l] + D.aeoff[l];
+      TailSpec T;
+      D.lt = -1;
+      for (int lt = 1; lt < D.L; ++lt)
+        if (tail_plan(D.g.data(), ks.data(), lt, D.L, sizeof(double), &T)) { D.lt = lt; break; }
+      if (D.lt < 0) return MGAR_E_DIMS;
+      BTail bt;
+      std::memset(&bt, 0, sizeof(bt));
+      (void)tail_plan(D.g.data(), ks.data(), D.lt, D.L, sizeof(double), &bt.ts);
+      bt.bin = G.b[D.lt] + D.aoff[D.lt];
+      bt.xout = G.xb[D.lt] + D.aoff[D.lt];
+      bt.design = i;
+      tails.push_back(bt);
+      G.tail_lds = std::max(G.tail_lds, bt.ts.lds_elems);
+      G.maxlt = std::max(G.maxlt, D.lt);
+      BCoarse c;
+      std::memset(&c, 0, sizeof(c));
+      c.g = D.g[D.L - 1];
+      c.k = G.k[D.L - 1] + D.aeoff[D.L - 1];
+      c.design = i;
+      (c.g.nn <= 128 ? creg : cgen).push_back(c);
+    }
+    // Ainv pointers once allocated below
+    G.ntails = (int)tails.size();
+    BACK(dalloc(&G.tails, G.ntails));
+    // patch A pointers after Ainv exists
+    if (!B->Ainv) BACK(dalloc(&B->Ainv, B->Atot));
+    for (BTail& t : tails) t.A = B->Ainv + B->d[t.design].Aoff;
+    for (BCoarse& c : creg) c.A = B->Ainv + B->d[c.design].Aoff;
+    for (BCoarse& c : cgen) c.A = B->Ainv + B->d[c.design].Aoff;
+    BHIP(hipMemcpy(G.tails, tails.data(), sizeof(BTail) * tails.size(), hipMemcpyHostToDevice));
+    G.n_reg = (int)creg.size();
+    G.n_gen = (int)cgen.size();
+    BACK(dalloc(&G.cb_reg, G.n_reg));
+    BACK(dalloc(&G.cb_gen, G.n_gen));
+    if (G.n_reg) BHIP(hipMemcpy(G.cb_reg, creg.data(), sizeof(BCoarse) * creg.size(), hipMemcpyHostToDevice));
+    if (G.n_gen) BHIP(hipMemcpy(G.cb_gen, cgen.data(), sizeof(BCoarse) * cgen.size(), hipMemcpyHostToDevice));
+    if ((size_t)G.tail_lds * sizeof(double) > 64 * 1024) return MGAR_E_DIMS;
+    // work lists
+    G.down.resize(G.maxL);
+    G.restr.resize(G.maxL);
+    G.prol.resize(G.maxL);
+    G.coarsen.resize(G.maxL);
+    for (int i : G.designs) {
+      Design& D = B->d[i];
+      const Geo& g0 = D.g[0];
+      G.fine.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, batch_item_blocks(g0)));
+      G.cells.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, blocks_of(g0.ne)));
+      for (int l = 0; l < D.L; ++l) {
+        const long long off = (l == 0) ? D.noff : D.aoff[l];
+        const long long eo = (l == 0) ? D.eoff : D.aeoff[l];
+        if (l < D.lt) {
+          const Geo &gf = D.g[l], &gc = D.g[l + 1];
+          G.down[l].h.push_back(make_item(gf, gf, off, 0, eo, 0, i, batch_item_blocks(gf)));
+          G.restr[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                           batch_item_blocks(gc)));
+          G.prol[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                          batch_item_blocks(gf)));
+        }
+        if (l + 1 < D.L) {
+          const Geo &gf = D.g[l], &gc = D.g[l + 1];
+          G.coarsen[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                             blocks_of(gc.ne)));
+        }
+      }
+    }
+    BACK(upload(G.fine));
+    BACK(upload(G.cells));
+    for (int l = 0; l < G.maxL; ++l) {
+      BACK(upload(G.down[l]));
+      BACK(upload(G.restr[l]));
+      BACK(upload(G.prol[l]));
+      BACK(upload(G.coarsen[l]));
+    }
+  }
+  // finest-grid workspace
+  const long long N = B->N, E = B->E;
+  BACK(dalloc(&B->kcur, E));
+  BACK(dalloc(&B->k0, E));
+  for (double** v : {&B->qm, &B->cx, &B->cr, &B->cz, &B->cp, &B->cw, &B->xa0, &B->rt0}) BACK(dalloc(v, N));
+  BACK(dalloc(&B->R, N * B->m));
+  BACK(dalloc(&B->Wm, N * B->m));
+  long long nb = 0;
+  for (Group& G : B->grp) nb = std::max<long long>(nb, G.fine.nblk);
+  const long long nv = (long long)B->m * (B->m + 1) / 2 + B->m;
+  BACK(dalloc(&B->pa, nb * std::max<long long>(nv, 8)));
+  BACK(dalloc(&B->pb, nb * std::max<long long>(nv, 8)));
+  BACK(dalloc(&B->pc, nb * std::max<long long>(nv, 8)));
+  BACK(dalloc(&B->st, nd));
+  BACK(dalloc(&B->md, nd));
+  BACK(dalloc(&B->keep, nd));
+  BACK(dalloc(&B->path, nd));
+  BACK(dalloc(&B->status, nd));
+  BACK(dalloc(&B->res, nd));
+  BACK(dalloc(&B->nrm, nd));
+  BHIP(hipMemset(B->st, 0, sizeof(BCgState) * nd));
+  BHIP(hipMemset(B->md, 0, sizeof(MgarDev) * nd));
+  BHIP(hipMemset(B->status, 0, sizeof(int) * nd));
+  BHIP(hipMemset(B->keep, 0, sizeof(int) * nd));
+  BHIP(hipEventCreate(&B->e0));
+  BHIP(hipEventCreate(&B->e1));
+  BHIP(hipEventCreateWithFlags(&B->ein, hipEventDisableTiming));
+  return MGAR_OK;
+}
+
+// Order the batch's own stream after the caller's (NULL) stream.
+static int enter(mgar_batch* b) {
+  if (!b->own_stream) return MGAR_OK;
+  BHIP(hipEventRecord(b->ein, b->user_s));
+  BHIP(hipStreamWaitEvent(b->s, b->ein, 0));
+  return MGAR_OK;
+}
+
+int mgar_batch_setup(const mgar_params* p, int ndesigns, void* stream, mgar_batch** out) {
+  if (!p || !out || ndesigns < 1) return MGAR_E_ARG;
+  *out = nullptr;
+  mgar_batch* B = new mgar_batch();
+  const int rc = batch_setup_impl(p, ndesigns, stream, B);
+  if (rc != MGAR_OK) {
+    mgar_batch_destroy(B);
+    return rc;
+  }
+  *out = B;
+  return MGAR_OK;
+}
+
+int mgar_batch_layout(const mgar_batch* b, long long* node_off, long long* elem_off) {
+  if (!b || !node_off || !elem_off) return MGAR_E_ARG;
+  for (int i = 0; i < b->nd; ++i) {
+    node_off[i] = b->d[i].noff;
+    elem_off[i] = b->d[i].eoff;
+  }
+  node_off[b->nd] = b->N;
+  elem_off[b->nd] = b->E;
+  return MGAR_OK;
+}
+
+int mgar_batch_set_graph(mgar_batch* b, int use_graph) {
+  if (!b) return MGAR_E_ARG;
+  b->use_graph = use_graph != 0;
+  return MGAR_OK;
+}
+
+int mgar_batch_load_vector(mgar_batch* b, const double* Qe, double* q) {
+  if (!b || !Qe || !q) return MGAR_E_ARG;
+  BACK(enter(b));
+  for (const Design& D : b->d) launch_load(D.g[0], Qe + D.eoff, q + D.noff, b->s);
+  BLAUNCH();
+  BHIP(hipStreamSynchronize(b->s));
+  return MGAR_OK;
+}
+
+int mgcg_batch_solve(mgar_batch* b, const double* xphys, const double* q, const double* T0, double tol,
+                     double* T, mgar_stats* stats) {
+  if (!b || !xphys || !q || !T) return MGAR_E_ARG;
+  BACK(enter(b));
+  BHIP(hipEventRecord(b->e0, b->s));
+  const mgar_params& p0 = b->d[0].p;
+  launch_simp(xphys, b->kcur, b->E, p0.k0, p0.kmin, p0.penal, b->s);
+  BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
+  for (Group& G : b->grp) {
+    BACK(bbuild(b, G, nullptr));
+    launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, q, b->qm, b->s);
+    if (T0) launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, T0, b->cx, b->s);
+  }
+  if (!T0) BHIP(hipMemsetAsync(b->cx, 0, sizeof(double) * b->N, b->s));
+  BLAUNCH();
+  BACK(bpcg(b, tol, nullptr));
+  b->has_k0 = true;
+  return finish(b, T, stats, MGAR_PATH_MGCG);
+}
+
+int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const double* T0, double tol,
+                     double* T, mgar_stats* stats) {
+  if (!b || !xphys || !q || !T) return MGAR_E_ARG;
+  if (!b->has_k0) return MGAR_E_STATE;
+  BACK(enter(b));
+  BHIP(hipEventRecord(b->e0, b->s));
+  const mgar_params& p0 = b->d[0].p;
+  const long long N = b->N;
+  const int m = b->m;
+  const int mds = MD_STRIDE;
+  double* mdd = reinterpret_cast<double*>(b->md);
+  launch_simp(xphys, b->kcur, b->E, p0.k0, p0.kmin, p0.penal, b->s);
+  BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
+  for (Group& G : b->grp) {
+    ItemList& F = G.fine;
+    launch_bmask_copy(F.d, F.n(), F.nblk, q, b->qm, b->s);
+    // r_1 = t_prev, r_i = MG(K0, -dK r_{i-1}, x0) (Eq 17)
+    if (T0) launch_bmask_copy(F.d, F.n(), F.nblk, T0, b->R, b->s);
+    else BHIP(hipMemsetAsync(b->R, 0, sizeof(double) * N, b->s));
+    for (int i = 1; i < m; ++i) {
+      const double* prev = b->R + (long long)(i - 1) * N;
+      launch_bstencil(G.dim, SM_NEG_DK, F.d, F.n(), F.nblk, prev, b->kcur, b->k0, nullptr, b->cz, 0.0,
+                      nullptr, nullptr, 0, b->s);
+      BACK(bvcycle(b, G, b->cz, b->basis_x0_zero ? nullptr : prev, b->R + (long long)i * N, nullptr,
+                   nullptr));
+    }
+    // Gram-Schmidt applied twice per column (same rule as the single path)
+    for (int j = 0; j < m; ++j) {
+      double* v = b->R + (long long)j * N;
+      launch_bdot(F.d, F.n(), F.nblk, v, v, b->pa, nullptr, 0, b->s);
+      launch_bfinalize(F.d, F.n(), b->pa, 1, mdd + offsetof(MgarDev, n0) / sizeof(double) + j, mds, nullptr,
+                       nullptr, 0, b->s);
+      if (j > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_bmultidot(F.d, F.n(), F.nblk, b->R, N, j, v, b->pa, b->s);
+          launch_bfinalize(F.d, F.n(), b->pa, j, mdd + offsetof(MgarDev, c) / sizeof(double), mds, nullptr,
+                           nullptr, 0, b->s);
+          launch_bgs_update(F.d, F.n(), F.nblk, v, b->R, N, j, b->md, b->s);
+        }
+      }
+      launch_bdot(F.d, F.n(), F.nblk, v, v, b->pa, nullptr, 0, b->s);
+      launch_bfinalize(F.d, F.n(), b->pa, 1, b->nrm, 1, nullptr, nullptr, 0, b->s);
+      launch_bgs_normalize(F.d, F.n(), F.nblk, v, b->md, j, b->nrm, 1, b->s);
+    }
+    // Eq 19-21 and Eq 28
+    for (int j = 0; j < m; ++j)
+      launch_bstencil(G.dim, SM_APPLY, F.d, F.n(), F.nblk, b->R + (long long)j * N, b->kcur, nullptr, nullptr,
+                      b->Wm + (long long)j * N, 0.0, nullptr, nullptr, 0, b->s);
+    launch_bgram(F.d, F.n(), F.nblk, b->R, b->Wm, b->qm, N, m, b->pa, b->s);
+    launch_bgram_finalize(F.d, F.n(), b->pa, m, b->md, b->s);
+    launch_bcombine(F.d, F.n(), F.nblk, b->R, b->Wm, b->qm, N, m, b->md, b->cx, b->pa, b->s);
+    launch_bfinalize(F.d, F.n(), b->pa, 1, mdd + offsetof(MgarDev, res2) / sizeof(double), mds, nullptr,
+                     nullptr, 0, b->s);
+    launch_bdot(F.d, F.n(), F.nblk, b->qm, b->qm, b->pb, nullptr, 0, b->s);
+    launch_bfinalize(F.d, F.n(), b->pb, 1, mdd + offsetof(MgarDev, qq) / sizeof(double), mds, nullptr,
+                     nullptr, 0, b->s);
+    launch_bdecide(F.d, F.n(), b->md, b->st, b->eps, b->keep, b->path, b->res, b->s);
+    // rejected designs: K becomes the new K0, MGCG from the reduced solution
+    BACK(bbuild(b, G, b->keep));
+  }
+  BLAUNCH();
+  BACK(bpcg(b, tol, b->keep));
+  return finish(b, T, stats, -1);
+}
+
+}  // extern "C"

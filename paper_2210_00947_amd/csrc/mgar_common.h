@@ -75,6 +75,18 @@ struct CgState {
   int pad;
 };
 
+// PCG state of one design of a batch. The iteration counter lives on the
+// device, so one captured iteration can be replayed any number of times.
+struct BCgState {
+  double qq, rr;             // ||q||^2, latest ||r||^2
+  double rz[2];              // r.z by iteration parity
+  double pw;                 // p.(K p)
+  int it;                    // iterations done
+  int done;                  // stopping test fired (or design excluded from this solve)
+  int conv;                  // 1 = tolerance met
+  int pad;
+};
+
 // Reanalysis (reduced-basis) state in device memory.
 struct MgarDev {
   double n0[MGAR_MAXB];      // squared column norm before projection

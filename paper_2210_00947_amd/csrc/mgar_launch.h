@@ -1,6 +1,7 @@
 // Host-side launch wrappers of the libmgar kernels (one definition per .hip file).
 #pragma once
 #include "mgar_common.h"
+#include "mgar.h"
 
 // Matrix-free stencil modes (y = K_l x with the rediscretised Q1 operator).
 enum StencilMode {
@@ -157,6 +158,92 @@ int launch_gram(const double* Q, const double* W, const double* q, int m, long l
 void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s);
 int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
                    long long n, MgarDev* md, double* t, double* part, hipStream_t s);
+
+// api.hip helpers shared with batch.hip (grid of a level, Dirichlet count,
+// parameter validation of one design).
+Geo mgar_internal_geo(const mgar_params& p, int level);
+long long mgar_internal_count_fixed(const Geo& g);
+int mgar_internal_validate(const mgar_params* p);
+
+// Batched launches (several designs per launch) ----------------------------
+// One work item per design and grid; items are sorted by `first`, the first
+// block of the item in the launch, and a block finds its item by bisection.
+// Offsets index the caller's concatenated arrays (node offsets for vectors,
+// element offsets for cells; "c" = the coarse grid of a transfer).
+struct BItem {
+  Geo g, gc;
+  long long off, coff, eoff, ceoff;
+  int design, first, nblk, pad;
+};
+// Single-workgroup jobs: one block per design.
+struct BTail {
+  TailSpec ts;
+  const double* bin;
+  double* xout;
+  const double* A;
+  int design, pad;
+};
+struct BCoarse {
+  Geo g;
+  const double* k;
+  double* A;
+  int design, pad;
+};
+// skip (may be null): a block of design d returns at once when
+// skip[d * sstride] != 0 (e.g. &BCgState::done of converged designs).
+// stencil.hip
+int batch_item_blocks(const Geo& g);   // blocks of one item of a node-parallel launch
+void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
+                     const double* k, const double* kref, const double* b, double* out, double omega,
+                     double* part, const int* skip, int sstride, hipStream_t s);
+void launch_brestrict(int dim, const BItem* items, int nit, int nblk, const double* rf, double* rc,
+                      const int* skip, int sstride, hipStream_t s);
+void launch_bprolong(int dim, const BItem* items, int nit, int nblk, const double* xc, double* xf,
+                     const int* skip, int sstride, hipStream_t s);
+void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const double* kf, double* kc,
+                     const int* skip, int sstride, hipStream_t s);
+void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
+                       hipStream_t s);
+void launch_bvtail(int dim, const BTail* jobs, int njobs, int lds_elems, double omega,
+                   const int* skip, int sstride, hipStream_t s);
+void launch_bcoarse_build(int dim, const BCoarse* jobs, int njobs, bool reg, int* status,
+                          const int* skip, int sstride, hipStream_t s);
+// vec.hip (items of the finest grid; vectors concatenated per design)
+void launch_bdot(const BItem* items, int nit, int nblk, const double* a, const double* b,
+                 double* part, const int* skip, int sstride, hipStream_t s);
+// out[d * ostride + v] = sum of design d's partials of value v (nv values per
+// block); with itsel, the target is shifted by (itsel[d * sstride] & 1).
+void launch_bfinalize(const BItem* items, int nit, const double* part, int nv, double* out,
+                      int ostride, const int* itsel, const int* skip, int sstride, hipStream_t s);
+void launch_bcg_init(const BItem* items, int nit, BCgState* st, const double* part_qq,
+                     const double* part_rr, double tol, int cg_max, const int* keep_done,
+                     hipStream_t s);
+void launch_bp_update(const BItem* items, int nit, int nblk, const double* z, double* p,
+                      const BCgState* st, hipStream_t s);
+void launch_bcg_update(const BItem* items, int nit, int nblk, double* x, double* r, const double* p,
+                       const double* w, const BCgState* st, double* part, hipStream_t s);
+void launch_bcg_check(const BItem* items, int nit, BCgState* st, const double* part, double tol,
+                      int cg_max, hipStream_t s);
+void launch_bmultidot(const BItem* items, int nit, int nblk, const double* Q, long long ld, int nc,
+                      const double* v, double* part, hipStream_t s);
+void launch_bgs_update(const BItem* items, int nit, int nblk, double* v, const double* Q, long long ld,
+                       int nc, const MgarDev* md, hipStream_t s);
+void launch_bgs_normalize(const BItem* items, int nit, int nblk, double* v, MgarDev* md, int col,
+                          const double* nrm2, int nstride, hipStream_t s);
+void launch_bgram(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+                  const double* q, long long ld, int m, double* part, hipStream_t s);
+void launch_bgram_finalize(const BItem* items, int nit, const double* part, int m, MgarDev* md,
+                           hipStream_t s);
+void launch_bcombine(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+                     const double* q, long long ld, int m, MgarDev* md, double* t, double* part,
+                     hipStream_t s);
+// per design: Res = sqrt(res2 / qq); accept (path 1) when Res <= eps: the
+// design's PCG state is marked done and keep[d] = 1 (K0 kept); otherwise
+// path 2 and keep[d] = 0 (K0 renewed, MGCG runs). res_out[d] = Res.
+void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, double eps, int* keep,
+                    int* path, double* res_out, hipStream_t s);
+void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
+                        const int* skip, int sstride, hipStream_t s);
 
 // topopt.hip -----------------------------------------------------------------
 struct FilterTaps {

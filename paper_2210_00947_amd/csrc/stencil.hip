@@ -235,20 +235,16 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil(Geo g, const T* __restrict
 // loads of a thread are issued together (no branch separates them); the
 // per-node arithmetic is that of k_stencil. Threads past the grid and nodes
 // outside it read 0 and store nothing.
+// Node n (flat index) of grid g: writes out[n] and returns this node's term
+// of the dot of modes 1 and 4 (0 past the grid).
 template <int DIM, int MODE, typename T, typename CL>
-__global__ __launch_bounds__(TBX* TBY) void k_stencil_b(Geo g, const T* __restrict__ x, CL k, CL kref,
-                                                        const T* __restrict__ b, T* __restrict__ out,
-                                                        T omega, double* __restrict__ part,
-                                                        const int* __restrict__ done,
-                                                        unsigned* __restrict__ cnt,
-                                                        double* __restrict__ rout) {
-  if (done && *done) return;
+__device__ inline double stencil_b_point(const Geo& g, long long n, const T* __restrict__ x, CL k,
+                                         CL kref, const T* __restrict__ b, T* __restrict__ out,
+                                         T omega) {
   using E = typename CL::E;
   constexpr unsigned TS = sizeof(T), ES = sizeof(E);
   constexpr bool DK = (MODE == SM_NEG_DK);
   constexpr bool CMASK = sizeof(E) == 2;   // a raw 0 of a BF16 array is not a zero conductivity
-  __shared__ double sh[TBX * TBY / MGAR_WAVE];
-  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
   const bool valid = n < g.nn;
   int i, j, kz;
   node_ijk(g, n, i, j, kz);   // past the grid: kz >= nnz, so every offset is out of range
@@ -277,7 +273,8 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil_b(Geo g, const T* __restri
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) xv[dy][dx] = zbload<T>(rx, node_boff(g, i + dx - 1, j + dy - 1, 0, TS));
+      for (int dx = 0; dx < 3; ++dx)
+        xv[dy][dx] = (MODE == SM_JACOBI0) ? T(0) : zbload<T>(rx, node_boff(g, i + dx - 1, j + dy - 1, 0, TS));
     xn = xv[1][1];
     T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
@@ -326,9 +323,24 @@ __global__ __launch_bounds__(TBX* TBY) void k_stencil_b(Geo g, const T* __restri
   else if (MODE == SM_NEG_DK) r = -y;
   r = geo_fixed(g, i, j, kz) ? T(0) : r;
   zbstore(r, ro, own);
+  const double d = (MODE == SM_APPLY_DOT) ? (double)xn * (double)r
+                   : (MODE == SM_JACOBI_DOT) ? (double)bn * (double)r : 0.0;
+  return valid ? d : 0.0;
+}
+
+template <int DIM, int MODE, typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_stencil_b(Geo g, const T* __restrict__ x, CL k, CL kref,
+                                                        const T* __restrict__ b, T* __restrict__ out,
+                                                        T omega, double* __restrict__ part,
+                                                        const int* __restrict__ done,
+                                                        unsigned* __restrict__ cnt,
+                                                        double* __restrict__ rout) {
+  if (done && *done) return;
+  __shared__ double sh[TBX * TBY / MGAR_WAVE];
+  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
+  const double d = stencil_b_point<DIM, MODE, T, CL>(g, n, x, k, kref, b, out, omega);
   if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
-    const double d = (MODE == SM_APPLY_DOT) ? (double)xn * (double)r : (double)bn * (double)r;
-    const double s = block_sum(valid ? d : 0.0, sh);
+    const double s = block_sum(d, sh);
     if (cnt) grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
     else if (flat_tid() == 0) part[blockIdx.x] = s;
   }
@@ -625,13 +637,11 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const T* _
 // Buffer-load forms of the two transfers: every load of a thread in flight at
 // once, nothing outside the grid read, same arithmetic as the kernels above.
 template <int DIM, typename T>
-__global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T* __restrict__ rf,
-                                                         T* __restrict__ rc,
-                                                         const int* __restrict__ done) {
-  if (done && *done) return;
+__device__ inline void restrict_b_point(const Geo& gf, const Geo& gc, long long nc,
+                                        const T* __restrict__ rf, T* __restrict__ rc) {
   constexpr unsigned TS = sizeof(T);
   int I, J, K;
-  node_ijk(gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), I, J, K);
+  node_ijk(gc, nc, I, J, K);
   const __amdgpu_buffer_rsrc_t rr = zrsrc(rf, gf.nn * TS);
   const __amdgpu_buffer_rsrc_t ro = zrsrc(rc, gc.nn * TS);
   T s = T(0);
@@ -655,13 +665,19 @@ __global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(TBX* TBY) void k_prolong_b(Geo gf, Geo gc, const T* __restrict__ xc,
-                                                        T* __restrict__ xf,
-                                                        const int* __restrict__ done) {
+__global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T* __restrict__ rf,
+                                                         T* __restrict__ rc,
+                                                         const int* __restrict__ done) {
   if (done && *done) return;
+  restrict_b_point<DIM, T>(gf, gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), rf, rc);
+}
+
+template <int DIM, typename T>
+__device__ inline void prolong_b_point(const Geo& gf, const Geo& gc, long long nf,
+                                       const T* __restrict__ xc, T* __restrict__ xf) {
   constexpr unsigned TS = sizeof(T);
   int i, j, k;
-  node_ijk(gf, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), i, j, k);
+  node_ijk(gf, nf, i, j, k);
   const __amdgpu_buffer_rsrc_t rc = zrsrc(xc, gc.nn * TS);
   const __amdgpu_buffer_rsrc_t rf = zrsrc(xf, gf.nn * TS);
   // fixed fine rows of P are 0: such nodes (and threads past the grid) use an
@@ -690,6 +706,14 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong_b(Geo gf, Geo gc, const T*
   }
   const T s = wj * sc[0] + mk * (wj * sc[1]);
   zbstore(xo + wk * s, rf, own);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_prolong_b(Geo gf, Geo gc, const T* __restrict__ xc,
+                                                        T* __restrict__ xf,
+                                                        const int* __restrict__ done) {
+  if (done && *done) return;
+  prolong_b_point<DIM, T>(gf, gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), xc, xf);
 }
 
 // Coarse conductivity: mean of the 2^d children.
@@ -724,8 +748,8 @@ constexpr int CB_MAXN = 1024;
 // Dirichlet nodes), then invert it in place by Gauss-Jordan elimination without
 // pivoting (valid for SPD matrices) and symmetrise. One workgroup.
 template <int DIM, typename CL>
-__global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double* __restrict__ A,
-                                                             int* __restrict__ status) {
+__device__ inline void coarse_build_body(const Geo& g, CL k, double* __restrict__ A,
+                                         int* __restrict__ status) {
   __shared__ double colp[CB_MAXN];
   __shared__ double rowp[CB_MAXN];
   const int n = (int)g.nn;
@@ -790,12 +814,18 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double
   if (t == 0 && bad) status[0] = 1;
 }
 
+template <int DIM, typename CL>
+__global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double* __restrict__ A,
+                                                             int* __restrict__ status) {
+  coarse_build_body<DIM, CL>(g, k, A, status);
+}
+
 // Register-resident variant for n <= 128: thread (tr, tc) of a 32 x 32 layout
 // owns entries (tr + 32a, tc + 32b), a, b < 4, for the whole elimination; only
 // the pivot row and column pass through LDS. Same arithmetic as above.
 template <int DIM, typename CL>
-__global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, CL k, double* __restrict__ A,
-                                                                 int* __restrict__ status) {
+__device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restrict__ A,
+                                             int* __restrict__ status) {
   __shared__ double colp[128];
   __shared__ double rowp[128];
   const int n = (int)g.nn;
@@ -919,6 +949,12 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, CL k, do
       }
     }
   if (t == 0 && bad) status[0] = 1;
+}
+
+template <int DIM, typename CL>
+__global__ __launch_bounds__(CB_THREADS) void k_coarse_build_reg(Geo g, CL k, double* __restrict__ A,
+                                                                 int* __restrict__ status) {
+  coarse_build_reg_body<DIM, CL>(g, k, A, status);
 }
 
 // x = A^-1 b on the coarsest grid (A symmetric: column reads are coalesced).
@@ -1050,11 +1086,8 @@ __device__ void tail_coarse(int n, const double* __restrict__ A, const T* b, T* 
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(TT) void k_vtail(TailSpec TS, const T* __restrict__ bin,
-                                              T* __restrict__ xout,
-                                              const double* __restrict__ Ainv, T omega,
-                                              const int* __restrict__ done) {
-  if (done && *done) return;
+__device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin, T* __restrict__ xout,
+                                  const double* __restrict__ Ainv, T omega) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int nl = TS.nl;
@@ -1089,6 +1122,15 @@ __global__ __launch_bounds__(TT) void k_vtail(TailSpec TS, const T* __restrict__
     xfin = xb;
   }
   for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) xout[n] = xfin[n];
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(TT) void k_vtail(TailSpec TS, const T* __restrict__ bin,
+                                              T* __restrict__ xout,
+                                              const double* __restrict__ Ainv, T omega,
+                                              const int* __restrict__ done) {
+  if (done && *done) return;
+  vtail_body<DIM, T>(TS, bin, xout, Ainv, omega);
 }
 
 dim3 node_grid(const Geo& g) {
@@ -1169,6 +1211,126 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
     case SM_NEG_DK: ZCALL(SM_NEG_DK); break;
   }
 #undef ZCALL
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches over several designs (FP64). Each block finds its work item
+// by bisection over the items' first blocks and runs the same per-node code as
+// the single-grid buffer kernels on that item's grid and arrays.
+__device__ inline int bitem_find(const BItem* __restrict__ items, int nit, int blk) {
+  int lo = 0, hi = nit - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline bool bskip(const int* skip, int sstride, int design) {
+  return skip && skip[(long long)design * sstride] != 0;
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(TBX* TBY) void kb_stencil(const BItem* __restrict__ items, int nit,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ k,
+                                                       const double* __restrict__ kref,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ out, double omega,
+                                                       double* __restrict__ part,
+                                                       const int* __restrict__ skip, int sstride) {
+  __shared__ double sh[TBX * TBY / MGAR_WAVE];
+  const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
+  if (bskip(skip, sstride, it.design)) return;
+  const Geo g = it.g;
+  const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  const double d = stencil_b_point<DIM, MODE, double, CellD>(
+      g, n, x + it.off, CellD{k + it.eoff}, CellD{kref ? kref + it.eoff : k + it.eoff},
+      b ? b + it.off : x + it.off, out + it.off, omega);
+  if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
+    const double s = block_sum(d, sh);
+    if (flat_tid() == 0) part[blockIdx.x] = s;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TBX* TBY) void kb_restrict(const BItem* __restrict__ items, int nit,
+                                                        const double* __restrict__ rf,
+                                                        double* __restrict__ rc,
+                                                        const int* __restrict__ skip, int sstride) {
+  const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
+  if (bskip(skip, sstride, it.design)) return;
+  const Geo gf = it.g, gc = it.gc;
+  restrict_b_point<DIM, double>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+                                rf + it.off, rc + it.coff);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TBX* TBY) void kb_prolong(const BItem* __restrict__ items, int nit,
+                                                       const double* __restrict__ xc,
+                                                       double* __restrict__ xf,
+                                                       const int* __restrict__ skip, int sstride) {
+  const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
+  if (bskip(skip, sstride, it.design)) return;
+  const Geo gf = it.g, gc = it.gc;
+  prolong_b_point<DIM, double>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+                               xc + it.coff, xf + it.off);
+}
+
+// coarse cells of item it.gc from fine cells of it.g (one thread per coarse cell)
+template <int DIM>
+__global__ __launch_bounds__(TBX* TBY) void kb_coarsen(const BItem* __restrict__ items, int nit,
+                                                       const double* __restrict__ kf,
+                                                       double* __restrict__ kc,
+                                                       const int* __restrict__ skip, int sstride) {
+  const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
+  if (bskip(skip, sstride, it.design)) return;
+  const Geo gf = it.g, gc = it.gc;
+  const long long e = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  if (e >= gc.ne) return;
+  const int ex = (int)(e % gc.nx);
+  const long long r = e / gc.nx;
+  const int ey = (int)(r % gc.ny);
+  const int ez = (int)(r / gc.ny);
+  const double* f = kf + it.eoff;
+  double s = 0.0;
+  for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+    for (int bb = 0; bb < 2; ++bb)
+      for (int a = 0; a < 2; ++a) s += f[geo_elem(gf, 2 * ex + a, 2 * ey + bb, DIM == 3 ? 2 * ez + c : 0)];
+  kc[it.ceoff + e] = s * (DIM == 3 ? 0.125 : 0.25);
+}
+
+__global__ __launch_bounds__(TBX* TBY) void kb_mask_copy(const BItem* __restrict__ items, int nit,
+                                                         const double* __restrict__ in,
+                                                         double* __restrict__ out) {
+  const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
+  const Geo g = it.g;
+  const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  if (n >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, n, i, j, k);
+  out[it.off + n] = geo_fixed(g, i, j, k) ? 0.0 : in[it.off + n];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TT) void kb_vtail(const BTail* __restrict__ jobs, double omega,
+                                               const int* __restrict__ skip, int sstride) {
+  const BTail& jb = jobs[blockIdx.x];
+  if (bskip(skip, sstride, jb.design)) return;
+  vtail_body<DIM, double>(jb.ts, jb.bin, jb.xout, jb.A, omega);
+}
+
+template <int DIM, bool REG>
+__global__ __launch_bounds__(CB_THREADS) void kb_coarse_build(const BCoarse* __restrict__ jobs,
+                                                              int* __restrict__ status,
+                                                              const int* __restrict__ skip,
+                                                              int sstride) {
+  const BCoarse& jb = jobs[blockIdx.x];
+  if (bskip(skip, sstride, jb.design)) return;
+  const Geo g = jb.g;
+  if (REG) coarse_build_reg_body<DIM, CellD>(g, CellD{jb.k}, jb.A, status + jb.design);
+  else coarse_build_body<DIM, CellD>(g, CellD{jb.k}, jb.A, status + jb.design);
 }
 
 }  // namespace
@@ -1379,3 +1541,78 @@ void launch_mask_copy_t(const Geo& g, const TI* in, TO* out, hipStream_t s) {
 template void launch_mask_copy_t<double, double>(const Geo&, const double*, double*, hipStream_t);
 template void launch_mask_copy_t<double, float>(const Geo&, const double*, float*, hipStream_t);
 template void launch_mask_copy_t<float, double>(const Geo&, const float*, double*, hipStream_t);
+
+// ---------------------------------------------------------------- batched launchers
+
+int batch_item_blocks(const Geo& g) { return (int)((g.nn + TBX * TBY - 1) / (TBX * TBY)); }
+
+void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
+                     const double* k, const double* kref, const double* b, double* out, double omega,
+                     double* part, const int* skip, int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+#define BCALL(D, M) kb_stencil<D, M><<<nblk, blk, 0, s>>>(items, nit, x, k, kref, b, out, omega, part, skip, sstride)
+#define BMODES(D)                                                 \
+  switch (mode) {                                                 \
+    case SM_APPLY: BCALL(D, SM_APPLY); break;                     \
+    case SM_APPLY_DOT: BCALL(D, SM_APPLY_DOT); break;             \
+    case SM_RESID: BCALL(D, SM_RESID); break;                     \
+    case SM_JACOBI: BCALL(D, SM_JACOBI); break;                   \
+    case SM_JACOBI_DOT: BCALL(D, SM_JACOBI_DOT); break;           \
+    case SM_JACOBI0: BCALL(D, SM_JACOBI0); break;                 \
+    case SM_NEG_DK: BCALL(D, SM_NEG_DK); break;                   \
+  }
+  if (dim == 2) { BMODES(2) } else { BMODES(3) }
+#undef BMODES
+#undef BCALL
+}
+
+void launch_brestrict(int dim, const BItem* items, int nit, int nblk, const double* rf, double* rc,
+                      const int* skip, int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_restrict<2><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
+  else kb_restrict<3><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
+}
+
+void launch_bprolong(int dim, const BItem* items, int nit, int nblk, const double* xc, double* xf,
+                     const int* skip, int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_prolong<2><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
+  else kb_prolong<3><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
+}
+
+void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const double* kf, double* kc,
+                     const int* skip, int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_coarsen<2><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
+  else kb_coarsen<3><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
+}
+
+void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
+                       hipStream_t s) {
+  if (nblk <= 0) return;
+  kb_mask_copy<<<nblk, dim3(TBX, TBY, 1), 0, s>>>(items, nit, in, out);
+}
+
+void launch_bvtail(int dim, const BTail* jobs, int njobs, int lds_elems, double omega,
+                   const int* skip, int sstride, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t lds = sizeof(double) * (size_t)lds_elems;
+  if (dim == 2) kb_vtail<2><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
+  else kb_vtail<3><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
+}
+
+void launch_bcoarse_build(int dim, const BCoarse* jobs, int njobs, bool reg, int* status,
+                          const int* skip, int sstride, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (reg) {
+    if (dim == 2) kb_coarse_build<2, true><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+    else kb_coarse_build<3, true><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+  } else {
+    if (dim == 2) kb_coarse_build<2, false><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+    else kb_coarse_build<3, false><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+  }
+}

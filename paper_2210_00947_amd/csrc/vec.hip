@@ -4,6 +4,7 @@
 // Reductions are two-stage and order-fixed: every block writes one partial per
 // value (wave64 shuffle tree, then LDS across waves), and a single-block
 // finalize sums the partials in index order. Reruns are bitwise identical.
+#include "mgar.h"
 #include "mgar_launch.h"
 
 namespace {
@@ -368,6 +369,313 @@ __global__ __launch_bounds__(VB) void k_add_f32(double* __restrict__ x, const fl
     x[i] += (double)d[i];
 }
 
+// ---------------------------------------------------------------------------
+// Batched vector kernels over several designs: one work item per design (its
+// finest grid), the design's nodes at item.off of the concatenated vectors,
+// and its partials in blocks item.first .. item.first + item.nblk - 1.
+__device__ inline int vb_find(const BItem* __restrict__ items, int nit, int blk) {
+  int lo = 0, hi = nit - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline bool vb_skip(const int* skip, int sstride, int design) {
+  return skip && skip[(long long)design * sstride] != 0;
+}
+
+__global__ __launch_bounds__(VB) void kb_dot(const BItem* __restrict__ items, int nit,
+                                             const double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ part, const int* __restrict__ skip,
+                                             int sstride) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  if (vb_skip(skip, sstride, it.design)) return;
+  const long long n = it.g.nn;
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const double s = block_sum(i < n ? a[it.off + i] * b[it.off + i] : 0.0, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// one block per item: out[d * ostride + v (+ (itsel[d*sstride] & 1))] = sum of
+// the item's partials of value v
+__global__ __launch_bounds__(FB) void kb_finalize(const BItem* __restrict__ items,
+                                                  const double* __restrict__ part, int nv,
+                                                  double* __restrict__ out, int ostride,
+                                                  const int* __restrict__ itsel,
+                                                  const int* __restrict__ skip, int sstride) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const BItem& it = items[blockIdx.x];
+  if (vb_skip(skip, sstride, it.design)) return;
+  const int shift = itsel ? (itsel[(long long)it.design * sstride] & 1) : 0;
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < it.nblk; b += FB) s += part[(long long)(it.first + b) * nv + v];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[(long long)it.design * ostride + v + shift] = s;
+  }
+}
+
+// Stopping test before iteration 0 (same rule as k_cg_init); designs with
+// keep_done[d] != 0 stay done (their reduced solution was accepted).
+__global__ __launch_bounds__(FB) void kb_cg_init(const BItem* __restrict__ items, BCgState* st,
+                                                 const double* __restrict__ pq,
+                                                 const double* __restrict__ pr, double tol, int cg_max,
+                                                 const int* __restrict__ keep_done) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const BItem& it = items[blockIdx.x];
+  const int d = it.design;
+  double qq = 0.0, rr = 0.0;
+  for (int b = threadIdx.x; b < it.nblk; b += FB) {
+    qq += pq[it.first + b];
+    rr += pr[it.first + b];
+  }
+  qq = block_sum(qq, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    BCgState& s = st[d];
+    s.qq = qq; s.rr = rr; s.rz[0] = s.rz[1] = 0.0; s.pw = 0.0;
+    s.it = 0; s.done = 0; s.conv = 0;
+    if (keep_done && keep_done[d]) { s.done = 1; s.conv = 1; }
+    else if (sqrt(rr) <= tol * sqrt(qq)) { s.done = 1; s.conv = 1; }
+    else if (cg_max <= 0) { s.done = 1; }
+  }
+}
+
+__global__ __launch_bounds__(VB) void kb_p_update(const BItem* __restrict__ items, int nit,
+                                                  const double* __restrict__ z, double* __restrict__ p,
+                                                  const BCgState* __restrict__ st) {
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  const BCgState& s = st[it.design];
+  if (s.done) return;
+  const int k = s.it;
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  if (i >= it.g.nn) return;
+  const long long n = it.off + i;
+  if (k == 0) p[n] = z[n];
+  else p[n] = z[n] + (s.rz[k & 1] / s.rz[(k - 1) & 1]) * p[n];
+}
+
+__global__ __launch_bounds__(VB) void kb_cg_update(const BItem* __restrict__ items, int nit,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ w,
+                                                   const BCgState* __restrict__ st,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  const BCgState& s = st[it.design];
+  if (s.done) return;
+  const double alpha = s.rz[s.it & 1] / s.pw;
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  double v = 0.0;
+  if (i < it.g.nn) {
+    const long long n = it.off + i;
+    x[n] += alpha * p[n];
+    const double ri = r[n] - alpha * w[n];
+    r[n] = ri;
+    v = ri * ri;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// one block per item: ||r||^2 from the update's partials, then the stopping
+// test that precedes the next iteration
+__global__ __launch_bounds__(FB) void kb_cg_check(const BItem* __restrict__ items, BCgState* st,
+                                                  const double* __restrict__ part, double tol,
+                                                  int cg_max) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const BItem& it = items[blockIdx.x];
+  BCgState& s = st[it.design];
+  if (s.done) return;
+  double rr = 0.0;
+  for (int b = threadIdx.x; b < it.nblk; b += FB) rr += part[it.first + b];
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    s.rr = rr;
+    s.it += 1;
+    if (sqrt(rr) <= tol * sqrt(s.qq)) { s.done = 1; s.conv = 1; }
+    else if (s.it >= cg_max) { s.done = 1; s.conv = 0; }
+  }
+}
+
+template <int NC>
+__global__ __launch_bounds__(VB) void kb_multidot(const BItem* __restrict__ items, int nit,
+                                                  const double* __restrict__ Q, long long ld,
+                                                  const double* __restrict__ v,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const bool in = i < it.g.nn;
+  const long long n = it.off + i;
+  const double vi = in ? v[n] : 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double s = block_sum(in ? Q[c * ld + n] * vi : 0.0, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * NC + c] = s;
+  }
+}
+
+template <int NC>
+__global__ __launch_bounds__(VB) void kb_gs_update(const BItem* __restrict__ items, int nit,
+                                                   double* __restrict__ v, const double* __restrict__ Q,
+                                                   long long ld, const MgarDev* __restrict__ md) {
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  if (i >= it.g.nn) return;
+  const long long n = it.off + i;
+  const double* c = md[it.design].c;
+  double s = v[n];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) s -= c[j] * Q[j * ld + n];
+  v[n] = s;
+}
+
+__global__ __launch_bounds__(VB) void kb_gs_normalize(const BItem* __restrict__ items, int nit,
+                                                      double* __restrict__ v, MgarDev* md, int col,
+                                                      const double* __restrict__ nrm2, int nstride) {
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  MgarDev& m = md[it.design];
+  const double n0 = sqrt(m.n0[col]);
+  const double n1 = sqrt(nrm2[(long long)it.design * nstride]);
+  const bool keep = (n0 > 0.0) && (n1 >= 1e-10 * n0);
+  const double sc = keep ? 1.0 / n1 : 0.0;
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  if (i < it.g.nn) {
+    const long long n = it.off + i;
+    v[n] = keep ? v[n] * sc : 0.0;
+  }
+  if (blockIdx.x == it.first && threadIdx.x == 0) m.active[col] = keep ? 1 : 0;
+}
+
+template <int M>
+__global__ __launch_bounds__(VB) void kb_gram(const BItem* __restrict__ items, int nit,
+                                              const double* __restrict__ Q, const double* __restrict__ W,
+                                              const double* __restrict__ q, long long ld,
+                                              double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  constexpr int NV = M * (M + 1) / 2 + M;
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const bool in = i < it.g.nn;
+  const long long n = it.off + i;
+  double qa[M], wa[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    qa[a] = in ? Q[a * ld + n] : 0.0;
+    wa[a] = in ? W[a * ld + n] : 0.0;
+  }
+  const double qi = in ? q[n] : 0.0;
+  double s[NV];
+  int idx = 0;
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int b = a; b < M; ++b) s[idx++] = qa[a] * wa[b];
+#pragma unroll
+  for (int a = 0; a < M; ++a) s[idx + a] = qa[a] * qi;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const double t = block_sum(s[c], sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * NV + c] = t;
+  }
+}
+
+__global__ __launch_bounds__(FB) void kb_gram_finalize(const BItem* __restrict__ items,
+                                                       const double* __restrict__ part, int m,
+                                                       MgarDev* md) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const BItem& it = items[blockIdx.x];
+  MgarDev& g = md[it.design];
+  const int nv = m * (m + 1) / 2 + m;
+  int idx = 0;
+  for (int a = 0; a < m; ++a)
+    for (int b = a; b < m; ++b, ++idx) {
+      double s = 0.0;
+      for (int k = threadIdx.x; k < it.nblk; k += FB) s += part[(long long)(it.first + k) * nv + idx];
+      s = block_sum(s, sh);
+      if (threadIdx.x == 0) {
+        g.KR[a * MGAR_MAXB + b] = s;
+        g.KR[b * MGAR_MAXB + a] = s;
+      }
+    }
+  for (int a = 0; a < m; ++a) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < it.nblk; k += FB) s += part[(long long)(it.first + k) * nv + idx + a];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) g.qR[a] = s;
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(VB) void kb_combine(const BItem* __restrict__ items, int nit,
+                                                 const double* __restrict__ Q,
+                                                 const double* __restrict__ W,
+                                                 const double* __restrict__ q, long long ld,
+                                                 MgarDev* md, double* __restrict__ t,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  __shared__ double ys[MGAR_MAXB];
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  MgarDev& g = md[it.design];
+  if (threadIdx.x == 0) {
+    double y[MGAR_MAXB];
+    int fail;
+    reduced_solve(&g, M, y, &fail);
+    for (int a = 0; a < MGAR_MAXB; ++a) ys[a] = (a < M) ? y[a] : 0.0;
+    if (blockIdx.x == it.first) {
+      for (int a = 0; a < M; ++a) g.y[a] = y[a];
+      g.spd_fail = fail;
+    }
+  }
+  __syncthreads();
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  double s = 0.0;
+  if (i < it.g.nn) {
+    const long long n = it.off + i;
+    double ti = 0.0, wi = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      ti += ys[a] * Q[a * ld + n];
+      wi += ys[a] * W[a * ld + n];
+    }
+    t[n] = ti;
+    const double ri = wi - q[n];
+    s = ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void kb_decide(const BItem* __restrict__ items, int nit, MgarDev* md, BCgState* st,
+                          double eps, int* __restrict__ keep, int* __restrict__ path,
+                          double* __restrict__ res_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nit) return;
+  const int d = items[k].design;
+  const MgarDev& g = md[d];
+  const double res = (g.qq > 0.0) ? sqrt(g.res2 / g.qq) : 0.0;
+  res_out[d] = res;
+  const bool acc = !g.spd_fail && res <= eps;
+  keep[d] = acc ? 1 : 0;
+  path[d] = acc ? MGAR_PATH_ACCEPT : MGAR_PATH_FALLBACK;
+  if (acc) { st[d].done = 1; st[d].conv = 1; st[d].it = 0; }
+}
+
+__global__ __launch_bounds__(VB) void kb_copy_cells(const BItem* __restrict__ items, int nit,
+                                                    const double* __restrict__ a, double* __restrict__ b,
+                                                    const int* __restrict__ skip, int sstride) {
+  const BItem& it = items[vb_find(items, nit, blockIdx.x)];
+  if (vb_skip(skip, sstride, it.design)) return;
+  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  if (i < it.g.ne) b[it.eoff + i] = a[it.eoff + i];
+}
+
 #define MGAR_DISPATCH_M(m, CALL)                                    \
   switch (m) {                                                      \
     case 1: CALL(1); break; case 2: CALL(2); break;                 \
@@ -523,4 +831,77 @@ void launch_add_f32(double* x, const float* d, long long n, hipStream_t s) {
 
 void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s) {
   (void)hipMemcpyAsync(b, a, sizeof(uint16_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+}
+
+// ---------------------------------------------------------------- batched launchers
+
+void launch_bdot(const BItem* items, int nit, int nblk, const double* a, const double* b,
+                 double* part, const int* skip, int sstride, hipStream_t s) {
+  if (nblk > 0) kb_dot<<<nblk, VB, 0, s>>>(items, nit, a, b, part, skip, sstride);
+}
+void launch_bfinalize(const BItem* items, int nit, const double* part, int nv, double* out,
+                      int ostride, const int* itsel, const int* skip, int sstride, hipStream_t s) {
+  if (nit > 0) kb_finalize<<<nit, FB, 0, s>>>(items, part, nv, out, ostride, itsel, skip, sstride);
+}
+void launch_bcg_init(const BItem* items, int nit, BCgState* st, const double* part_qq,
+                     const double* part_rr, double tol, int cg_max, const int* keep_done,
+                     hipStream_t s) {
+  if (nit > 0) kb_cg_init<<<nit, FB, 0, s>>>(items, st, part_qq, part_rr, tol, cg_max, keep_done);
+}
+void launch_bp_update(const BItem* items, int nit, int nblk, const double* z, double* p,
+                      const BCgState* st, hipStream_t s) {
+  if (nblk > 0) kb_p_update<<<nblk, VB, 0, s>>>(items, nit, z, p, st);
+}
+void launch_bcg_update(const BItem* items, int nit, int nblk, double* x, double* r, const double* p,
+                       const double* w, const BCgState* st, double* part, hipStream_t s) {
+  if (nblk > 0) kb_cg_update<<<nblk, VB, 0, s>>>(items, nit, x, r, p, w, st, part);
+}
+void launch_bcg_check(const BItem* items, int nit, BCgState* st, const double* part, double tol,
+                      int cg_max, hipStream_t s) {
+  if (nit > 0) kb_cg_check<<<nit, FB, 0, s>>>(items, st, part, tol, cg_max);
+}
+void launch_bmultidot(const BItem* items, int nit, int nblk, const double* Q, long long ld, int nc,
+                      const double* v, double* part, hipStream_t s) {
+  if (nblk <= 0 || nc <= 0) return;
+#define CALL(M) kb_multidot<M><<<nblk, VB, 0, s>>>(items, nit, Q, ld, v, part)
+  MGAR_DISPATCH_M(nc, CALL)
+#undef CALL
+}
+void launch_bgs_update(const BItem* items, int nit, int nblk, double* v, const double* Q, long long ld,
+                       int nc, const MgarDev* md, hipStream_t s) {
+  if (nblk <= 0 || nc <= 0) return;
+#define CALL(M) kb_gs_update<M><<<nblk, VB, 0, s>>>(items, nit, v, Q, ld, md)
+  MGAR_DISPATCH_M(nc, CALL)
+#undef CALL
+}
+void launch_bgs_normalize(const BItem* items, int nit, int nblk, double* v, MgarDev* md, int col,
+                          const double* nrm2, int nstride, hipStream_t s) {
+  if (nblk > 0) kb_gs_normalize<<<nblk, VB, 0, s>>>(items, nit, v, md, col, nrm2, nstride);
+}
+void launch_bgram(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+                  const double* q, long long ld, int m, double* part, hipStream_t s) {
+  if (nblk <= 0) return;
+#define CALL(M) kb_gram<M><<<nblk, VB, 0, s>>>(items, nit, Q, W, q, ld, part)
+  MGAR_DISPATCH_M(m, CALL)
+#undef CALL
+}
+void launch_bgram_finalize(const BItem* items, int nit, const double* part, int m, MgarDev* md,
+                           hipStream_t s) {
+  if (nit > 0) kb_gram_finalize<<<nit, FB, 0, s>>>(items, part, m, md);
+}
+void launch_bcombine(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+                     const double* q, long long ld, int m, MgarDev* md, double* t, double* part,
+                     hipStream_t s) {
+  if (nblk <= 0) return;
+#define CALL(M) kb_combine<M><<<nblk, VB, 0, s>>>(items, nit, Q, W, q, ld, md, t, part)
+  MGAR_DISPATCH_M(m, CALL)
+#undef CALL
+}
+void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, double eps, int* keep,
+                    int* path, double* res_out, hipStream_t s) {
+  if (nit > 0) kb_decide<<<(nit + 63) / 64, 64, 0, s>>>(items, nit, md, st, eps, keep, path, res_out);
+}
+void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
+                        const int* skip, int sstride, hipStream_t s) {
+  if (nblk > 0) kb_copy_cells<<<nblk, VB, 0, s>>>(items, nit, a, b, skip, sstride);
 }

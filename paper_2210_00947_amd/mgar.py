@@ -33,7 +33,9 @@ EXPORTS = [
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
     "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
-    "mgar_tune_set", "mgar_profile", "mgar_profile_read",
+    "mgar_tune_set", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
+    "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
+    "mgar_profile", "mgar_profile_read",
 ]
 
 
@@ -106,7 +108,7 @@ def lib():
         L.mgar_profile.argtypes = [P, ctypes.c_uint]
         L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
         for f in EXPORTS:
-            if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror"):
+            if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror", "mgar_batch_destroy"):
                 getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -317,3 +319,64 @@ class Handle:
 def n_on(maxit: int) -> int:
     """Activation parameter of the loop: MGCG while the cycle is below 2/15 of maxit."""
     return (2 * maxit) // 15
+
+
+class Batch:
+    """Owns one mgar_batch (many designs solved together). Methods keep the
+    names of the C entry points; vectors are concatenations over designs
+    (offsets in self.node_off / self.elem_off)."""
+
+    def __init__(self, params_list, stream=None):
+        import torch
+        self._L = lib()
+        n = len(params_list)
+        arr = (mgar_params * n)(*params_list)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        b = ctypes.c_void_p()
+        _check(self._L.mgar_batch_setup(arr, n, ctypes.c_void_p(stream), ctypes.byref(b)),
+               "mgar_batch_setup")
+        self.b = b
+        self.n = n
+        no = (ctypes.c_longlong * (n + 1))()
+        eo = (ctypes.c_longlong * (n + 1))()
+        _check(self._L.mgar_batch_layout(self.b, no, eo), "mgar_batch_layout")
+        self.node_off = list(no)
+        self.elem_off = list(eo)
+        self.N = self.node_off[-1]
+        self.E = self.elem_off[-1]
+
+    def close(self):
+        if getattr(self, "b", None):
+            self._L.mgar_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mgar_batch_set_graph(self, use_graph):
+        _check(self._L.mgar_batch_set_graph(self.b, int(bool(use_graph))), "mgar_batch_set_graph")
+
+    def mgar_batch_load_vector(self, Qe, q):
+        _check(self._L.mgar_batch_load_vector(self.b, _ptr(Qe, self.E), _ptr(q, self.N)),
+               "mgar_batch_load_vector")
+
+    def _solve(self, fn, name, xphys, q, T0, tol, T):
+        stats = (mgar_stats * self.n)()
+        rc = fn(self.b, _ptr(xphys, self.E), _ptr(q, self.N),
+                _ptr(T0, self.N) if T0 is not None else None, ctypes.c_double(tol), _ptr(T, self.N), stats)
+        if rc < 0:
+            raise MgarError(rc, name)
+        out = [s.as_dict() for s in stats]
+        for s in out:
+            s["rc"] = rc
+        return out
+
+    def mgcg_batch_solve(self, xphys, q, T0, tol, T):
+        return self._solve(self._L.mgcg_batch_solve, "mgcg_batch_solve", xphys, q, T0, tol, T)
+
+    def mgar_batch_solve(self, xphys, q, T0, tol, T):
+        return self._solve(self._L.mgar_batch_solve, "mgar_batch_solve", xphys, q, T0, tol, T)

@@ -12,6 +12,8 @@ Prints one JSON line:
   value          DOF-solves/s of the MGAR loop (free DOFs x solves / second)
   ms_per_step    MGAR loop, milliseconds per optimisation cycle
   mgcg           the same figures for the plain-MGCG loop on the same GPU
+  batched        48 2D + 8 3D designs of uneven sizes solved together (FP64),
+                 against the same solves one design at a time
   mgar_mixed     the MGAR loop in the mixed-precision form (FP32 multigrid and
                  inner PCG over BF16 densities inside FP64 iterative refinement,
                  same 1e-8 FP64 residual test); reported beside value, which
@@ -75,6 +77,84 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0):
     return out
 
 
+def run_batched(W, M, torch, nsolves=5):
+    """The batched workload (48 2D + 8 3D designs of uneven sizes): `nsolves`
+    batched MGCG solves from T0 = 0 on reseeded densities, then the same
+    solves one design at a time through single-design handles on the same
+    GPU, and one batched reanalysis step (MGCG at x, MGAR at a perturbed x)."""
+    import numpy as np
+    probs = W.batched_designs()
+    b = M.Batch([M.params_for(p) for p in probs])
+    free = 0
+    for p in probs:
+        nfix = 1
+        for a in range(p.dim):
+            nfix *= p.fix_hi[a] - p.fix_lo[a] + 1
+        free += p.nnodes - nfix
+
+    def cat(arrs, off):
+        out = np.zeros(off[-1])
+        for i, a in enumerate(arrs):
+            out[off[i]:off[i + 1]] = a
+        return torch.as_tensor(out, dtype=torch.float64, device="cuda")
+
+    q = torch.empty(b.N, dtype=torch.float64, device="cuda")
+    b.mgar_batch_load_vector(cat([W.element_source(p) for p in probs], b.elem_off), q)
+    xs = [cat([W.reseeded_density(p, 31 * r + i) for i, p in enumerate(probs)], b.elem_off)
+          for r in range(nsolves)]
+    T = torch.empty(b.N, dtype=torch.float64, device="cuda")
+    b.mgcg_batch_solve(xs[0], q, None, 1e-8, T)       # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for x in xs:
+        st = b.mgcg_batch_solve(x, q, None, 1e-8, T)
+        its.append(max(s["cg_iters"] for s in st))
+    torch.cuda.synchronize()
+    bt = (time.perf_counter() - t0) / nsolves
+    # MGAR step at a perturbed design (exact mode: every design falls back)
+    x1 = cat([np.clip(W.reseeded_density(p, i) + 0.01 * W.random_vector(p.nelem, 77 + i), 0, 1)
+              for i, p in enumerate(probs)], b.elem_off)
+    T1 = torch.empty_like(T)
+    b.mgcg_batch_solve(xs[0], q, None, 1e-8, T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sa = b.mgar_batch_solve(x1, q, T, 1e-8, T1)
+    torch.cuda.synchronize()
+    at = time.perf_counter() - t1
+    b.close()
+    # the same MGCG solves, one design after another through single handles
+    hs = [M.Handle(M.params_for(p)) for p in probs]
+    qs, ts = [], []
+    for p, h in zip(probs, hs):
+        qi = torch.empty(p.nnodes, dtype=torch.float64, device="cuda")
+        h.mgar_load_vector(torch.as_tensor(W.element_source(p), device="cuda"), qi)
+        qs.append(qi)
+        ts.append(torch.empty_like(qi))
+    xsd = [[torch.as_tensor(W.reseeded_density(p, 31 * r + i), device="cuda") for i, p in enumerate(probs)]
+           for r in range(nsolves)]
+    for h, qi, ti, x in zip(hs, qs, ts, xsd[0]):
+        h.mgcg_solve(x, qi, None, 1e-8, ti)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for r in range(nsolves):
+        for h, qi, ti, x in zip(hs, qs, ts, xsd[r]):
+            h.mgcg_solve(x, qi, None, 1e-8, ti)
+    torch.cuda.synchronize()
+    stime = (time.perf_counter() - t2) / nsolves
+    for h in hs:
+        h.close()
+    return {
+        "designs": len(probs), "free_dofs": free,
+        "batched_mgcg_s_per_solve": bt, "batched_dof_solves_per_s": free / bt,
+        "max_cg_iters": its,
+        "batched_mgar_s": at, "batched_mgar_paths": {"accept": sum(s["path"] == 1 for s in sa),
+                                                     "fallback": sum(s["path"] == 2 for s in sa)},
+        "one_by_one_mgcg_s_per_solve": stime, "one_by_one_dof_solves_per_s": free / stime,
+        "speedup": stime / bt,
+    }
+
+
 def cpu_baseline(prob, W, nsolves=3):
     """Full oracle MGCG solves on the benchmark grid (FP64, SciPy), timed with
     perf_counter; cores = process CPU time / wall time."""
@@ -124,6 +204,8 @@ def main():
     ap.add_argument("--config", default="c3", help="workload: c0, c1, c2 or c3 (default 128^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched workload (48 2D + 8 3D designs solved together)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
     args = ap.parse_args()
@@ -154,6 +236,11 @@ def main():
     if not args.no_mixed:
         mixed = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED)
         log(f"[bench] mixed-precision MGAR loop: {mixed['s_per_opt_iter']*1e3:.3f} ms/cycle")
+    batch = None
+    if not args.no_batch:
+        batch = run_batched(W, M, torch)
+        log(f"[bench] batched workload: {batch['batched_mgcg_s_per_solve']*1e3:.2f} ms per batched solve "
+            f"vs {batch['one_by_one_mgcg_s_per_solve']*1e3:.2f} ms one design at a time")
     value = free * args.steps / mg_ar["elapsed_s"]
     roof = None
     if mg_ar["kernel_launches"] > 0:
@@ -196,6 +283,7 @@ def main():
         "mgar": mg_ar,
         "mgcg": mgcg,
         "mgar_mixed": mixed,
+        "batched": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -189,6 +189,40 @@ int mgar_autotune(mgar_handle* h, int reps, double* best_us);
 int mgar_tune_get(const mgar_handle* h, int cls, int level, int mode, int* shape);
 int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape);
 
+/* ||q - K(xphys) T|| / ||q|| over the free nodes, FP64, into *relres (host):
+ * the judge of any initial guess (a learned seed is used only when its
+ * residual is below that of the previous temperature). */
+int mgar_residual(mgar_handle* h, const double* xphys, const double* q, const double* T, double* relres);
+
+/* ---- Learned initial guess (3D). -------------------------------------------
+ * A small convolutional U-Net on the coarse cell grid of blocks of pool^3
+ * finest elements (pool even; every axis a multiple of 2*pool): input = mean
+ * physical density and fraction of Dirichlet corner nodes per block; two 3x3x3
+ * convolutions with ReLU (c1 channels), 2x average pooling, two convolutions
+ * (c2), 2x nearest upsampling, concatenation with the full-resolution features,
+ * a convolution (c1) and a linear convolution to one output u per block.
+ * Parameters: one FP32 vector, per layer the weights [co][ci][dz][dy][dx]
+ * then the biases, layers in the order above (mgar_net_sizes gives the count
+ * and the coarse grid D, H, W). Created with zero parameters; the caller
+ * installs initial values (mgar_net_set_params, which also resets Adam).
+ * Prediction on the finest nodes: scale * trilinear interpolation of u
+ * between block centres (finest nodes pool*i + pool/2), clamped at the
+ * outermost centres, 0 on Dirichlet nodes. Training pair (xphys, T, scale):
+ * target y = T at the block centres / scale, loss = mean (u - y)^2, one Adam
+ * step (0.9, 0.999, 1e-8) with learning rate lr. xphys: E-vector, T: N-vector
+ * (device, FP64); theta, grad, u: host FP32 arrays of nparams / D*H*W values. */
+typedef struct mgar_net mgar_net;
+int mgar_net_create(const mgar_params* p, int pool, int c1, int c2, void* stream, mgar_net** out);
+void mgar_net_destroy(mgar_net* n);
+int mgar_net_sizes(const mgar_net* n, long long* nparams, int* cells);
+int mgar_net_set_params(mgar_net* n, const float* theta);
+int mgar_net_get_params(const mgar_net* n, float* theta);
+int mgar_net_infer(mgar_net* n, const double* xphys, double scale, double* T_seed);
+int mgar_net_output(const mgar_net* n, float* u);
+int mgar_net_grad(mgar_net* n, const double* xphys, const double* T, double scale, float* grad, double* loss);
+int mgar_net_train_step(mgar_net* n, const double* xphys, const double* T, double scale, double lr,
+                        double* loss);
+
 /* ---- Batched solves (many independent designs at once). --------------------
  * A batch holds `ndesigns` designs of uneven grids (2D and 3D may be mixed),
  * each described by its own mgar_params (FP64 only; n_basis, omega,

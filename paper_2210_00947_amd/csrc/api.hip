@@ -1192,6 +1192,29 @@ int mgar_profile_read(mgar_handle* h, long long* launches, double* total_ms, dou
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- residual check
+
+int mgar_residual(mgar_handle* h, const double* xphys, const double* q, const double* T, double* relres) {
+  if (!h || !xphys || !q || !T || !relres) return MGAR_E_ARG;
+  const Geo& g = h->lv[0].g;
+  const long long N = h->N;
+  launch_simp(xphys, h->kcur, h->E, h->p.k0, h->p.kmin, h->p.penal, h->s);
+  launch_mask_copy(g, q, h->qm, h->s);
+  launch_mask_copy(g, T, h->cz, h->s);
+  launch_stencil(g, SM_RESID, h->cz, h->kcur, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr, h->s, nullptr,
+                 nullptr, nullptr, nullptr, &h->scfg[0][0][SM_RESID]);
+  const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
+  launch_finalize(h->pa, nr, &h->scal[4], nullptr, h->s);
+  const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+  launch_finalize(h->pb, nq, &h->scal[5], nullptr, h->s);
+  LAUNCHCK();
+  double v[2];
+  HIPCK(hipMemcpyAsync(v, &h->scal[4], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  *relres = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : 0.0;
+  return MGAR_OK;
+}
+
 // ---------------------------------------------------------------- shared with batch.hip
 Geo mgar_internal_geo(const mgar_params& p, int level) { return make_geo(p, level); }
 long long mgar_internal_count_fixed(const Geo& g) { return count_fixed(g); }

@@ -33,7 +33,9 @@ EXPORTS = [
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
     "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
-    "mgar_tune_set", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
+    "mgar_tune_set", "mgar_residual", "mgar_net_create", "mgar_net_destroy", "mgar_net_sizes",
+    "mgar_net_set_params", "mgar_net_get_params", "mgar_net_infer", "mgar_net_output", "mgar_net_grad",
+    "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
     "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
     "mgar_profile", "mgar_profile_read",
 ]
@@ -108,7 +110,8 @@ def lib():
         L.mgar_profile.argtypes = [P, ctypes.c_uint]
         L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
         for f in EXPORTS:
-            if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror", "mgar_batch_destroy"):
+            if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror", "mgar_batch_destroy",
+                         "mgar_net_destroy"):
                 getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -289,6 +292,12 @@ class Handle:
         _check(self._L.mgar_op_bf16(self.h, _ptr(x, self.E, "x"), ctypes.c_void_p(out.data_ptr())),
                "mgar_op_bf16")
 
+    def mgar_residual(self, xphys, q, T):
+        r = ctypes.c_double()
+        _check(self._L.mgar_residual(self.h, _ptr(xphys, self.E), _ptr(q, self.N), _ptr(T, self.N),
+                                     ctypes.byref(r)), "mgar_residual")
+        return r.value
+
     def mgar_autotune(self, reps=20):
         """Time the candidate launch shapes and install the fastest; returns the
         winning times (microseconds) as a list indexed [cls][level][mode]."""
@@ -380,3 +389,71 @@ class Batch:
 
     def mgar_batch_solve(self, xphys, q, T0, tol, T):
         return self._solve(self._L.mgar_batch_solve, "mgar_batch_solve", xphys, q, T0, tol, T)
+
+
+class Net:
+    """Owns one mgar_net (the learned initial guess); methods keep the C names."""
+
+    def __init__(self, params: mgar_params, pool=4, c1=16, c2=32, stream=None):
+        import torch
+        self._L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        n = ctypes.c_void_p()
+        _check(self._L.mgar_net_create(ctypes.byref(params), int(pool), int(c1), int(c2),
+                                       ctypes.c_void_p(stream), ctypes.byref(n)), "mgar_net_create")
+        self.n = n
+        npar = ctypes.c_longlong()
+        cells = (ctypes.c_int * 3)()
+        _check(self._L.mgar_net_sizes(self.n, ctypes.byref(npar), cells), "mgar_net_sizes")
+        self.nparams = npar.value
+        self.cells = tuple(cells)
+        self.E = params.nelx * params.nely * params.nelz
+        self.N = (params.nelx + 1) * (params.nely + 1) * (params.nelz + 1)
+
+    def close(self):
+        if getattr(self, "n", None):
+            self._L.mgar_net_destroy(self.n)
+            self.n = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mgar_net_set_params(self, theta):
+        import numpy as np
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.nparams
+        _check(self._L.mgar_net_set_params(self.n, a.ctypes.data_as(ctypes.c_void_p)), "mgar_net_set_params")
+
+    def mgar_net_get_params(self):
+        import numpy as np
+        a = np.empty(self.nparams, dtype=np.float32)
+        _check(self._L.mgar_net_get_params(self.n, a.ctypes.data_as(ctypes.c_void_p)), "mgar_net_get_params")
+        return a
+
+    def mgar_net_infer(self, xphys, scale, T):
+        _check(self._L.mgar_net_infer(self.n, _ptr(xphys, self.E), ctypes.c_double(scale), _ptr(T, self.N)),
+               "mgar_net_infer")
+
+    def mgar_net_output(self):
+        import numpy as np
+        a = np.empty(self.cells, dtype=np.float32)
+        _check(self._L.mgar_net_output(self.n, a.ctypes.data_as(ctypes.c_void_p)), "mgar_net_output")
+        return a
+
+    def mgar_net_grad(self, xphys, T, scale):
+        import numpy as np
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self._L.mgar_net_grad(self.n, _ptr(xphys, self.E), _ptr(T, self.N), ctypes.c_double(scale),
+                                     g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)), "mgar_net_grad")
+        return loss.value, g
+
+    def mgar_net_train_step(self, xphys, T, scale, lr):
+        loss = ctypes.c_double()
+        _check(self._L.mgar_net_train_step(self.n, _ptr(xphys, self.E), _ptr(T, self.N), ctypes.c_double(scale),
+                                           ctypes.c_double(lr), ctypes.byref(loss)), "mgar_net_train_step")
+        return loss.value

@@ -1,0 +1,107 @@
+"""Learned initial guess on the GPU against the NumPy oracle: forward pass,
+loss and gradients of every parameter, Adam step, interpolation to the
+finest nodes, and training on loop-generated pairs."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nets, solvers
+from tests.gpu_util import dev, host, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+PROB = W.tiny_3d(32, 32, 32, 4)
+POOL, C1, C2 = 4, 8, 16
+
+
+def make_net(prob=PROB, pool=POOL, c1=C1, c2=C2):
+    require_gpu()
+    from paper_2210_00947_amd import mgar as M
+    return M.Net(M.params_for(prob), pool=pool, c1=c1, c2=c2)
+
+
+def pair(seed):
+    """A density and a temperature of that density (oracle MGCG)."""
+    x = W.random_density(PROB.nelem, seed, 0.05, 1.0)
+    t, _ = solvers.MgarSolver(PROB, solvers.MgarParams(cg_max=200)).mgcg(x, np.zeros(PROB.nnodes), 1e-8)
+    return x, t
+
+
+def test_sizes_match_oracle_layout():
+    n = make_net()
+    _, npar = nets.param_layout(C1, C2)
+    assert n.nparams == npar
+    assert n.cells == (PROB.nelz // POOL, PROB.nely // POOL, PROB.nelx // POOL)
+
+
+def test_forward_matches_oracle():
+    import torch
+    n = make_net()
+    theta = W.net_init(C1, C2, seed=1)
+    n.mgar_net_set_params(theta)
+    x = W.random_density(PROB.nelem, 2, 0.0, 1.0)
+    T = torch.empty(PROB.nnodes, dtype=torch.float64, device="cuda")
+    n.mgar_net_infer(dev(x), 3.0, T)
+    u = n.mgar_net_output().astype(np.float64)
+    inp = nets.net_input(PROB, x, POOL)
+    u_or, _ = nets.forward(theta.astype(np.float64), inp, C1, C2)
+    assert np.abs(u - u_or).max() <= 1e-5 * np.abs(u_or).max()
+    # interpolation of the GPU's own output to the finest nodes (FP64 both sides)
+    t_or = nets.net_to_nodes(PROB, u, POOL, 3.0)
+    assert np.abs(host(T) - t_or).max() <= 1e-12 * np.abs(t_or).max()
+
+
+def test_loss_and_gradients_match_oracle():
+    n = make_net()
+    theta = W.net_init(C1, C2, seed=3)
+    n.mgar_net_set_params(theta)
+    x, t = pair(4)
+    scale = float(np.abs(t).max())
+    loss, g = n.mgar_net_grad(dev(x), dev(t), scale)
+    inp = nets.net_input(PROB, x, POOL)
+    y = nets.net_target(PROB, t, POOL, scale)
+    loss_or, g_or = nets.loss_and_grad(theta.astype(np.float64), inp, y, C1, C2)
+    assert abs(loss - loss_or) <= 1e-5 * loss_or
+    lay, _ = nets.param_layout(C1, C2)
+    for name, wo, wl, bo, co, ci in lay:
+        for a, b in ((wo, wo + wl), (bo, bo + co)):
+            ref = g_or[a:b]
+            assert np.abs(g[a:b] - ref).max() <= 1e-4 * np.abs(ref).max() + 1e-9, name
+
+
+def test_adam_step_matches_oracle():
+    n = make_net()
+    theta = W.net_init(C1, C2, seed=5)
+    n.mgar_net_set_params(theta)
+    x, t = pair(6)
+    scale = float(np.abs(t).max())
+    lr = 1e-3
+    n.mgar_net_train_step(dev(x), dev(t), scale, lr)
+    after = n.mgar_net_get_params().astype(np.float64)
+    inp = nets.net_input(PROB, x, POOL)
+    y = nets.net_target(PROB, t, POOL, scale)
+    _, g_or = nets.loss_and_grad(theta.astype(np.float64), inp, y, C1, C2)
+    want, _, _ = nets.adam_step(theta.astype(np.float64), 0.0 * g_or, 0.0 * g_or, g_or, 1, lr)
+    assert np.abs(after - want).max() <= 1e-2 * lr + 1e-6
+
+
+def test_training_reduces_loss_on_loop_pairs():
+    """Pairs from the first cycles of the optimisation loop; 150 Adam steps
+    over them lower the loss on a held-out later pair."""
+    import torch
+    x_or, _, _, _ = None, None, None, None
+    prob = PROB
+    xs, ts = [], []
+    from oracle import topopt
+    topopt.run_loop(prob, maxit=14, on_cycle=lambda k, xp, t: (xs.append(xp.copy()), ts.append(t.copy())))
+    n = make_net()
+    n.mgar_net_set_params(W.net_init(C1, C2, seed=7))
+    held_x, held_t, held_s = xs[-1], ts[-1], float(np.abs(ts[-2]).max())
+    pairs = [(dev(xs[k]), dev(ts[k]), float(np.abs(ts[k - 1]).max())) for k in range(1, len(xs) - 1)]
+    l0, _ = n.mgar_net_grad(dev(held_x), dev(held_t), held_s)
+    for step in range(150):
+        xp, tp, sc = pairs[step % len(pairs)]
+        n.mgar_net_train_step(xp, tp, sc, 3e-3)
+    l1, _ = n.mgar_net_grad(dev(held_x), dev(held_t), held_s)
+    print(f"held-out loss {l0:.3e} -> {l1:.3e}")
+    assert l1 < 0.5 * l0

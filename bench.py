@@ -14,6 +14,10 @@ Prints one JSON line:
   mgcg           the same figures for the plain-MGCG loop on the same GPU
   batched        48 2D + 8 3D designs of uneven sizes solved together (FP64),
                  against the same solves one design at a time
+  learned_mixed  the mixed-precision MGAR loop with the learned initial guess
+                 (trained by the library's kernels on cycles 2..20, used from 21
+                 when its true residual beats the previous temperature's);
+                 training time is inside the timed cycles
   mgar_mixed     the MGAR loop in the mixed-precision form (FP32 multigrid and
                  inner PCG over BF16 densities inside FP64 iterative refinement,
                  same 1e-8 FP64 residual test); reported beside value, which
@@ -44,8 +48,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0):
-    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision)
+def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None):
+    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision, seed=seed)
     for _ in range(warmup):
         opt.step()
     opt.h.mgar_profile(1 << ROOF_MODE)
@@ -67,6 +71,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0):
         "s_per_opt_iter": el / steps,
         "cg_iters_mean": sum(r.cg_iters for r in recs) / steps,
         "refinements_mean": sum(r.refinements for r in recs) / steps,
+        "seed_used_cycles": sum(r.seed_used for r in recs),
         "paths": paths,
         "final_compliance": recs[-1].compliance,
         "kernel_launches": n,
@@ -206,6 +211,8 @@ def main():
     ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned+mixed loop (network trained on cycles 2..20, used from 21)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
     args = ap.parse_args()
@@ -236,6 +243,12 @@ def main():
     if not args.no_mixed:
         mixed = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED)
         log(f"[bench] mixed-precision MGAR loop: {mixed['s_per_opt_iter']*1e3:.3f} ms/cycle")
+    learned = None
+    if not args.no_learned and prob.dim == 3:
+        learned = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED,
+                           seed={"train_until": 20, "steps": 120})
+        log(f"[bench] learned+mixed MGAR loop: {learned['s_per_opt_iter']*1e3:.3f} ms/cycle, "
+            f"guess used in {learned['seed_used_cycles']} cycles")
     batch = None
     if not args.no_batch:
         batch = run_batched(W, M, torch)
@@ -276,13 +289,15 @@ def main():
                    "nodes": prob.nnodes, "free_dofs": free, "levels": prob.levels},
         "s_per_opt_iter": {"mgar": mg_ar["s_per_opt_iter"],
                            "mgcg": mgcg["s_per_opt_iter"] if mgcg else None,
-                           "mgar_mixed": mixed["s_per_opt_iter"] if mixed else None},
+                           "mgar_mixed": mixed["s_per_opt_iter"] if mixed else None,
+                           "learned_mixed": learned["s_per_opt_iter"] if learned else None},
         "dof_solves_per_s": {"mgar": value,
                              "mgcg": free * args.steps / mgcg["elapsed_s"] if mgcg else None,
                              "mgar_mixed": free * args.steps / mixed["elapsed_s"] if mixed else None},
         "mgar": mg_ar,
         "mgcg": mgcg,
         "mgar_mixed": mixed,
+        "learned_mixed": learned,
         "batched": batch,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -26,12 +26,19 @@ class Cycle:
     solve_ms: float
     lam: float
     refinements: int = 0
+    seed_used: bool = False       # the learned guess replaced the previous temperature as T0
+    res_seed: float = float("nan")
+    res_prev: float = float("nan")
 
 
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
                  eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
-                 autotune=True, device="cuda"):
+                 autotune=True, seed=None, device="cuda"):
+        """seed: None, or a dict enabling the learned initial guess with keys
+        pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
+        used from the next cycle on), steps (Adam steps after cycle
+        train_until), lr, init_seed."""
         self.prob = prob
         self.use_mgar = use_mgar
         self.params = M.params_for(prob, n_basis=n_basis, eps_accept=eps_accept, cg_max=cg_max,
@@ -59,21 +66,69 @@ class TopOpt:
         self.dv = torch.empty(E, **f64)
         self.k = 0
         self.non = M.n_on(prob.maxit)
+        self.seed = None
+        if seed is not None:
+            import workloads as W
+            cfg = dict(pool=4, c1=16, c2=32, train_until=20, steps=120, lr=3e-3, init_seed=0)
+            cfg.update(seed)
+            self.seed = cfg
+            self.net = M.Net(self.params, pool=cfg["pool"], c1=cfg["c1"], c2=cfg["c2"])
+            self.net.mgar_net_set_params(W.net_init(cfg["c1"], cfg["c2"], seed=cfg["init_seed"]))
+            self.pairs = []
+            self.Tseed = torch.zeros(N, **f64)
+            self.train_losses = []
+
+    def _seed_guess(self):
+        """Learned guess for this cycle, kept only when its true residual is
+        below that of the previous temperature (which stays the fallback)."""
+        h = self.h
+        scale = float(self.T_prev.abs().max())
+        if scale <= 0.0:
+            return self.T_prev, False, float("nan"), float("nan")
+        self.net.mgar_net_infer(self.xphys, scale, self.Tseed)
+        r_seed = h.mgar_residual(self.xphys, self.q, self.Tseed)
+        r_prev = h.mgar_residual(self.xphys, self.q, self.T_prev)
+        if r_seed < r_prev:
+            return self.Tseed, True, r_seed, r_prev
+        return self.T_prev, False, r_seed, r_prev
+
+    def _seed_train(self):
+        cfg = self.seed
+        n = len(self.pairs)
+        if n == 0:
+            return
+        order = torch.Generator().manual_seed(int(cfg["init_seed"]))
+        for s in range(int(cfg["steps"])):
+            if s % n == 0:
+                perm = torch.randperm(n, generator=order).tolist()
+            xp, tp, sc = self.pairs[perm[s % n]]
+            self.train_losses.append(self.net.mgar_net_train_step(xp, tp, sc, cfg["lr"]))
+        self.pairs = []      # training data is not needed once the guess is in use
 
     def step(self) -> Cycle:
         self.k += 1
         h, p = self.h, self.prob
         h.mgar_density_filter(self.x, self.xphys)
+        T0, used, r_seed, r_prev = self.T_prev, False, float("nan"), float("nan")
+        if self.seed is not None and self.k > self.seed["train_until"]:
+            T0, used, r_seed, r_prev = self._seed_guess()
         if (not self.use_mgar) or self.k < self.non:
-            st = h.mgcg_solve(self.xphys, self.q, self.T_prev, p.tol, self.T)
+            st = h.mgcg_solve(self.xphys, self.q, T0, p.tol, self.T)
         else:
-            st = h.mgar_solve(self.xphys, self.q, self.T_prev, p.tol, self.T)
+            st = h.mgar_solve(self.xphys, self.q, T0, p.tol, self.T)
+        if self.seed is not None and self.k <= self.seed["train_until"]:
+            if self.k >= 2:
+                scale = float(self.T_prev.abs().max())
+                if scale > 0.0:
+                    self.pairs.append((self.xphys.clone(), self.T.clone(), scale))
+            if self.k == self.seed["train_until"]:
+                self._seed_train()
         f = h.sens_filter(self.xphys, self.T, self.q, self.dc, self.dv)
         lam = h.oc_update(self.x, self.dc, self.dv, p.volfrac, p.move, self.xnew)
         self.x, self.xnew = self.xnew, self.x
         self.T, self.T_prev = self.T_prev, self.T
         return Cycle(self.k, f, st["path"], st["cg_iters"], st["res_ca"], st["res_final"],
-                     st["ms"], lam, st["refinements"])
+                     st["ms"], lam, st["refinements"], used, r_seed, r_prev)
 
     def run(self, ncycles=None):
         n = self.prob.maxit if ncycles is None else ncycles

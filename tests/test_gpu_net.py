@@ -105,3 +105,29 @@ def test_training_reduces_loss_on_loop_pairs():
     l1, _ = n.mgar_net_grad(dev(held_x), dev(held_t), held_s)
     print(f"held-out loss {l0:.3e} -> {l1:.3e}")
     assert l1 < 0.5 * l0
+
+
+def test_learned_guess_in_the_loop_gain_and_fallback():
+    """The loop with the learned guess (trained on cycles 2..8, used from 9)
+    against the plain loop: a guess is used only when its true residual is
+    below that of the previous temperature, and then the cycle's result stays
+    within the solve tolerance of the plain loop's. Prints the gain."""
+    require_gpu()
+    from paper_2210_00947_amd.topopt import TopOpt
+    prob = W.tiny_3d(32, 32, 32, 4, maxit=16)
+    plain = TopOpt(prob, W.element_source(prob), autotune=False).run(16)
+    seeded_opt = TopOpt(prob, W.element_source(prob), autotune=False,
+                        seed={"pool": 4, "c1": 8, "c2": 16, "train_until": 8, "steps": 60})
+    seeded = seeded_opt.run(16)
+    late = [c for c in seeded if c.cycle > 8]
+    for c in late:
+        assert np.isfinite(c.res_seed) and np.isfinite(c.res_prev)
+        assert c.seed_used == (c.res_seed < c.res_prev)
+    for a, b in zip(plain, seeded):
+        assert abs(a.compliance - b.compliance) <= 1e-6 * abs(a.compliance)
+    its_plain = np.mean([c.cg_iters for c in plain if c.cycle > 8])
+    its_seed = np.mean([c.cg_iters for c in late])
+    ratio = np.median([c.res_seed / c.res_prev for c in late])
+    print(f"learned guess: used in {sum(c.seed_used for c in late)}/{len(late)} cycles; median residual "
+          f"ratio seed/previous {ratio:.3g}; mean CG iterations {its_seed:.2f} vs {its_plain:.2f} plain; "
+          f"training loss {seeded_opt.train_losses[0]:.3g} -> {seeded_opt.train_losses[-1]:.3g}")

@@ -72,7 +72,7 @@ typedef struct {
   int precision;          /* MGAR_PREC_FP64 or MGAR_PREC_MIXED */
   double filter_r;        /* cone density-filter radius, Eq 7-8 (element lengths) */
   double inner_tol;       /* MGAR_PREC_MIXED: each inner FP32 PCG solve stops once its
-                           * residual has dropped by this factor (0 < inner_tol < 1) */
+                           * residual has dropped by this factor (0 < inner_tol < 1; 1e-4) */
 } mgar_params;
 
 /* Per-solve report. */

@@ -59,6 +59,7 @@ struct mgar_handle {
   std::vector<float*> kf, bf, xaf, xbf;   // FP32 hierarchy: cells (grids >= 1) and vectors
   float *rtmpf = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *w32 = nullptr,
         *d32 = nullptr;
+  float* k32 = nullptr;                   // FP32 conductivities of the current call (inner operator)
   int ltf = 1;
   TailSpec tailf;
   float kmin_f = 0.f, kdiff_f = 0.f;
@@ -273,11 +274,16 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
 // ---------------------------------------------------------------- mixed precision
 // FP32 stencil on grid `level` of the BF16/FP32 hierarchy: the finest grid reads
 // BF16 densities (SIMP applied on load), coarser grids FP32 cell conductivities.
+// kop (finest grid only): FP32 cell conductivities to use instead of densities.
 int stencil32(mgar_handle* h, int level, int mode, const float* x, const float* b, float* out,
               double* part, const int* done, const uint16_t* dens = nullptr,
-              const uint16_t* densref = nullptr) {
+              const uint16_t* densref = nullptr, const float* kop = nullptr) {
   const Geo& g = h->lv[level].g;
-  if (level == 0) {
+  if (level == 0 && kop) {
+    const CellF k{kop};
+    launch_stencil_t<float, CellF>(g, mode, x, k, k, b, out, h->p.omega, part, done, h->s, nullptr,
+                                   nullptr, nullptr, nullptr, &h->scfg[1][level][mode]);
+  } else if (level == 0) {
     const CellB k{dens ? dens : h->dens0, h->kmin_f, h->kdiff_f};
     const CellB kr{densref ? densref : h->dens0, h->kmin_f, h->kdiff_f};
     launch_stencil_t<float, CellB>(g, mode, x, k, kr, b, out, h->p.omega, part, done, h->s, nullptr,
@@ -355,7 +361,9 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
       const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
       launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
       launch_p_update_t<float>(h->z32, h->p32, N, h->st, it, h->s);
-      ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, h->dens));
+      // the inner operator: FP32 conductivities of the current densities (BF16
+      // densities only enter the V-cycle preconditioner)
+      ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
       launch_finalize(h->pc, nparts_at(h, 1, SM_APPLY_DOT), &h->st->pw, done, h->s);
       launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, it, h->pa, nullptr, tol_in,
                                 max_it, h->s);
@@ -378,6 +386,7 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
 int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relres, int* nref) {
   const long long N = h->N;
   const Geo& g = h->lv[0].g;
+  launch_cast_f32(h->kcur, h->k32, h->E, h->s);
   const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
   launch_finalize(h->pb, nq, &h->scal[2], nullptr, h->s);
   int total = 0, ref = 0;
@@ -533,7 +542,7 @@ void mgar_default_params(mgar_params* p) {
   p->basis_x0_zero = 0;
   p->precision = MGAR_PREC_FP64;
   p->filter_r = 1.5;
-  p->inner_tol = 1e-2;
+  p->inner_tol = 1e-4;
 }
 
 const char* mgar_strerror(int code) {
@@ -567,7 +576,7 @@ void mgar_destroy(mgar_handle* h) {
   for (auto* v : {&h->kf, &h->bf, &h->xaf, &h->xbf})
     for (float* q : *v)
       if (q) (void)hipFree(q);
-  void* mptrs[] = {h->dens, h->dens0, h->rtmpf, h->r32, h->z32, h->p32, h->w32, h->d32};
+  void* mptrs[] = {h->dens, h->dens0, h->rtmpf, h->r32, h->z32, h->p32, h->w32, h->d32, h->k32};
   for (void* q : mptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
@@ -657,6 +666,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
     h->kdiff_f = (float)(p->k0 - p->kmin);
     ACK(dalloc(&h->dens, E));
     ACK(dalloc(&h->dens0, E));
+    ACK(dalloc(&h->k32, E));
     h->kf.assign(h->L, nullptr);
     h->bf.assign(h->L, nullptr);
     h->xaf.assign(h->L, nullptr);

@@ -123,6 +123,7 @@ int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState*
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
+void launch_cast_f32(const double* a, float* b, long long n, hipStream_t s);
 void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s);
 // out = sum(part[0..n)) in a fixed order (single block)
 void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s);

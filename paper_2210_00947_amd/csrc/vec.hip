@@ -362,6 +362,12 @@ __global__ __launch_bounds__(VB) void k_cast_bf16(const double* __restrict__ a, 
     b[i] = f32_to_bf16_rne((float)a[i]);
 }
 
+__global__ __launch_bounds__(VB) void k_cast_f32(const double* __restrict__ a, float* __restrict__ b,
+                                                 long long n) {
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    b[i] = (float)a[i];
+}
+
 // x += d with d in FP32 and x in FP64 (the refinement update).
 __global__ __launch_bounds__(VB) void k_add_f32(double* __restrict__ x, const float* __restrict__ d,
                                                 long long n) {
@@ -823,6 +829,10 @@ int launch_combine(const double* Q, const double* W, const double* q, int m, lon
 
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s) {
   k_cast_bf16<<<vec_num_blocks(n), VB, 0, s>>>(a, b, n);
+}
+
+void launch_cast_f32(const double* a, float* b, long long n, hipStream_t s) {
+  k_cast_f32<<<vec_num_blocks(n), VB, 0, s>>>(a, b, n);
 }
 
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s) {

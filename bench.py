@@ -23,8 +23,12 @@ Prints one JSON line:
                  same 1e-8 FP64 residual test); reported beside value, which
                  stays the all-FP64 loop
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
-                 per launch / average launch time from HIP events around each
-                 launch in the timed region, against 8 TB/s
+                 per launch / average launch time from HIP events recorded at
+                 the start and end of each launch, against 8 TB/s. Kernel timing
+                 needs eagerly launched kernels, so it runs on --roof-cycles
+                 cycles that continue the MGAR loop right after the timed ones
+                 (same kernel, launch shape and data); the timed cycles replay
+                 captured PCG iterations
   cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
                  solve of the same grid
 """
@@ -72,19 +76,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None):
+def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None, roof_cycles=0):
+    """Warm-up cycles, then `steps` timed cycles (PCG iterations replayed from
+    captured graphs). With roof_cycles > 0 the loop then continues for that
+    many cycles with kernel timing on (which launches every kernel eagerly) to
+    time the roofline kernel with HIP events recorded at kernel start and end."""
     opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision, seed=seed)
     for _ in range(warmup):
         opt.step()
-    opt.h.mgar_profile(1 << ROOF_MODE)
-    opt.h.mgar_profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [opt.step() for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n, ms, by = opt.h.mgar_profile_read()
-    opt.h.mgar_profile(0)
+    n, ms, by = 0, 0.0, 0.0
+    if roof_cycles > 0:
+        opt.h.mgar_profile(1 << ROOF_MODE)
+        opt.h.mgar_profile_read()
+        for _ in range(roof_cycles):
+            opt.step()
+        torch.cuda.synchronize()
+        n, ms, by = opt.h.mgar_profile_read()
+        opt.h.mgar_profile(0)
     el = t1 - t0
     paths = {"mgcg": 0, "accept": 0, "fallback": 0}
     for r in recs:
@@ -232,6 +245,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=9, help="untimed cycles before the timed ones")
     ap.add_argument("--config", default="c3", help="workload: c0, c1, c2 or c3 (default 128^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--roof-cycles", type=int, default=10,
+                    help="cycles after the timed ones with kernel timing on (roofline measurement)")
     ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")
@@ -257,7 +272,7 @@ def main():
         nfix *= prob.fix_hi[a] - prob.fix_lo[a] + 1
     free = prob.nnodes - nfix
     log(f"[bench] {prob.name}: {prob.nnodes} nodes, {free} free DOFs; warmup {args.warmup}, steps {args.steps}")
-    mg_ar = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch)
+    mg_ar = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, roof_cycles=args.roof_cycles)
     log(f"[bench] MGAR loop: {mg_ar['s_per_opt_iter']*1e3:.3f} ms/cycle, paths {mg_ar['paths']}")
     mgcg = None
     if not args.no_mgcg:

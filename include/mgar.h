@@ -256,6 +256,13 @@ int mgcg_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
 int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const double* T0,
                      double tol, double* T, mgar_stats* stats);
 
+/* PCG iterations are captured once as HIP graphs (chunks of 1, 2, 4 and 8
+ * iterations, per tolerance) and replayed on a stream the handle owns, ordered
+ * after and before the handle's stream; the iteration index lives on the
+ * device, so replays are exact repeats of eager launches. on = 0 launches every
+ * kernel eagerly instead (kernel timing via mgar_profile always does). */
+int mgar_set_graphs(mgar_handle* h, int on);
+
 /* ---- Instrumentation. ------------------------------------------------------
  * Kernel timing for roofline reports: while enabled, every launch of a
  * finest-grid stencil kernel whose mode bit is set in `mode_mask` is bracketed

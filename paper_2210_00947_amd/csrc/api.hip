@@ -66,9 +66,21 @@ struct mgar_handle {
   int refine_max = 40;
   // launch shape of every stencil: [class: 0 FP64, 1 FP32][grid level][mode]
   std::vector<std::array<StencilCfg, 7>> scfg[2];
+  // Captured PCG iterations (class 0: FP64 pcg, 1: FP32 inner pcg32): graphs
+  // of 1, 2, 4 and 8 iterations for the (tol, cg_max) they were captured
+  // with, replayed on the handle's own stream `gs` (a graph cannot be
+  // captured on the legacy default stream) ordered after and before `s`.
+  bool use_graphs = false;               // replay captured iterations (eager launches measured faster)
+  hipStream_t gs = nullptr;
+  hipEvent_t gin = nullptr, gout = nullptr;
+  hipGraph_t gg[2][4] = {};
+  hipGraphExec_t gx[2][4] = {};
+  double g_tol[2] = {-1.0, -1.0};
+  int g_max[2] = {-1, -1};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // kernel timing (instrumentation)
   unsigned prof_mask = 0;
+  int tag_base = 0;                       // CG iteration of the next eager iteration (timing tags)
   std::vector<hipEvent_t> prof_ev;        // pool, pairs
   std::vector<double> prof_bytes;         // bytes of each recorded pair
   std::vector<int> prof_tag;              // CG iteration of each pair (-1: not in a CG loop)
@@ -345,6 +357,110 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
   return MGAR_OK;
 }
 
+// One PCG iteration of class 0 (FP64: K(kcur), V-cycle on the K0 hierarchy)
+// or class 1 (FP32 inner solve of the mixed form). No host-side iteration
+// index: the kernels read and advance st->it. tag: CG iteration for the
+// profiler (eager launches only).
+int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int tag) {
+  const long long N = h->N;
+  const int* done = &h->st->done;
+  if (cls == 0) {
+    ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, tag));
+    const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
+    launch_finalize_rz(h->pb, nz, h->st, h->s);
+    launch_p_update(h->cz, h->cp, N, h->st, h->s);
+    int nw = 0;
+    ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, h->kcur, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, tag));
+    launch_finalize(h->pc, nw, &h->st->pw, done, h->s);
+    launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s);
+  } else {
+    ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
+    const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
+    launch_finalize_rz(h->pb, nz, h->st, h->s);
+    launch_p_update_t<float>(h->z32, h->p32, N, h->st, h->s);
+    // the inner operator: FP32 conductivities of the current densities (BF16
+    // densities only enter the V-cycle preconditioner)
+    ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
+    launch_finalize(h->pc, nparts_at(h, 1, SM_APPLY_DOT), &h->st->pw, done, h->s);
+    launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s);
+  }
+  launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+void drop_graphs(mgar_handle* h) {
+  for (int c = 0; c < 2; ++c) {
+    for (int k = 0; k < 4; ++k) {
+      if (h->gx[c][k]) (void)hipGraphExecDestroy(h->gx[c][k]);
+      if (h->gg[c][k]) (void)hipGraphDestroy(h->gg[c][k]);
+      h->gx[c][k] = nullptr;
+      h->gg[c][k] = nullptr;
+    }
+    h->g_tol[c] = -1.0;
+    h->g_max[c] = -1;
+  }
+}
+
+// Capture graphs of 1, 2, 4 and 8 iterations of class cls on the handle's
+// own stream (the launch helpers enqueue on h->s, so it is swapped meanwhile).
+int capture_iters(mgar_handle* h, int cls, double tol, int cg_max, int nr) {
+  for (int k = 0; k < 4; ++k) {
+    if (h->gx[cls][k]) (void)hipGraphExecDestroy(h->gx[cls][k]);
+    if (h->gg[cls][k]) (void)hipGraphDestroy(h->gg[cls][k]);
+    h->gx[cls][k] = nullptr;
+    h->gg[cls][k] = nullptr;
+  }
+  if (!h->gs) {
+    HIPCK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
+    HIPCK(hipEventCreateWithFlags(&h->gin, hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&h->gout, hipEventDisableTiming));
+  }
+  hipStream_t user = h->s;
+  for (int k = 0; k < 4; ++k) {
+    HIPCK(hipStreamBeginCapture(h->gs, hipStreamCaptureModeThreadLocal));
+    h->s = h->gs;
+    int rc = MGAR_OK;
+    for (int i = 0; i < (1 << k) && rc == MGAR_OK; ++i) rc = enqueue_iter(h, cls, tol, cg_max, nr, -1);
+    h->s = user;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->gs, &g);
+    if (rc != MGAR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCK(e);
+    h->gg[cls][k] = g;
+    HIPCK(hipGraphInstantiate(&h->gx[cls][k], g, nullptr, nullptr, 0));
+  }
+  h->g_tol[cls] = tol;
+  h->g_max[cls] = cg_max;
+  return MGAR_OK;
+}
+
+// n PCG iterations of class cls: replayed graphs (binary decomposition of n)
+// unless graphs are off or kernel timing is on (then eager launches).
+int run_iters(mgar_handle* h, int cls, double tol, int cg_max, int n, int nr) {
+  if (n <= 0) return MGAR_OK;
+  if (!h->use_graphs || h->prof_mask) {
+    for (int i = 0; i < n; ++i) ACK(enqueue_iter(h, cls, tol, cg_max, nr, h->tag_base + i));
+    h->tag_base += n;
+    return MGAR_OK;
+  }
+  if (!h->gx[cls][0] || h->g_tol[cls] != tol || h->g_max[cls] != cg_max)
+    ACK(capture_iters(h, cls, tol, cg_max, nr));
+  HIPCK(hipEventRecord(h->gin, h->s));
+  HIPCK(hipStreamWaitEvent(h->gs, h->gin, 0));
+  for (int k = 3; k >= 0; --k)
+    while (n >= (1 << k)) {
+      HIPCK(hipGraphLaunch(h->gx[cls][k], h->gs));
+      n -= 1 << k;
+    }
+  HIPCK(hipEventRecord(h->gout, h->gs));
+  HIPCK(hipStreamWaitEvent(h->s, h->gout, 0));
+  return MGAR_OK;
+}
+
 // Inner FP32 PCG: solve K32 d = r32 from d = 0 until ||r|| <= tol_in ||r32_0||
 // or max_it iterations; FP64 accumulation of every inner product.
 int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
@@ -352,28 +468,18 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
   HIPCK(hipMemsetAsync(h->d32, 0, sizeof(float) * N, h->s));
   const int nr = launch_dot_t<float, float>(h->r32, h->r32, N, h->pa, nullptr, h->s);
   launch_cg_init(h->st, h->pa, nr, h->pa, nr, tol_in, max_it, h->s);
-  const int* done = &h->st->done;
   int it = 0, chunk = 4;
   CgState hs;
   for (;;) {
-    for (int c = 0; c < chunk && it < max_it; ++c, ++it) {
-      ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
-      const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
-      launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
-      launch_p_update_t<float>(h->z32, h->p32, N, h->st, it, h->s);
-      // the inner operator: FP32 conductivities of the current densities (BF16
-      // densities only enter the V-cycle preconditioner)
-      ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
-      launch_finalize(h->pc, nparts_at(h, 1, SM_APPLY_DOT), &h->st->pw, done, h->s);
-      launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, it, h->pa, nullptr, tol_in,
-                                max_it, h->s);
-      launch_cg_check(h->st, h->pa, nr, it + 1, tol_in, max_it, h->s);
-      LAUNCHCK();
-    }
+    ACK(run_iters(h, 1, tol_in, h->p.cg_max, chunk, nr));
+    it += chunk;
     HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
     if (hs.done) break;
-    if (it >= max_it) return MGAR_E_HIP;
+    if (it >= max_it) {   // the refinement's iteration budget is spent
+      *iters = hs.it;
+      return MGAR_OK;
+    }
     chunk = 2;
   }
   *iters = hs.iters;
@@ -423,7 +529,8 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
   const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
   launch_cg_init(h->st, h->pb, nq, h->pa, nr, tol, cg_max, h->s);
   LAUNCHCK();
-  const int* done = &h->st->done;
+  (void)kfine;   // the iterations apply K(h->kcur)
+  h->tag_base = 0;
   int it = 0;
   int chunk = 3;
   double rr_prev = -1.0;
@@ -434,18 +541,9 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     // (before iteration 0 in cg_init, then at the end of every update); once
     // it fires, every later kernel returns immediately, so the iterates are
     // those of a loop that tests before every iteration.
-    for (int c = 0; c < chunk && it < cg_max; ++c, ++it) {
-      ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, it));
-      const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
-      launch_finalize(h->pb, nz, &h->st->rz[it & 1], done, h->s);
-      launch_p_update(h->cz, h->cp, N, h->st, it, h->s);
-      int nw = 0;
-      ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, kfine, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, it));
-      launch_finalize(h->pc, nw, &h->st->pw, done, h->s);
-      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, it, h->pa, nullptr, tol, cg_max, h->s);
-      launch_cg_check(h->st, h->pa, nr, it + 1, tol, cg_max, h->s);
-      LAUNCHCK();
-    }
+    const int c = std::min(chunk, cg_max - it);
+    ACK(run_iters(h, 0, tol, cg_max, c, nr));
+    it += c;
     HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
     if (hs.done) break;
@@ -580,6 +678,10 @@ void mgar_destroy(mgar_handle* h) {
   for (void* q : mptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  drop_graphs(h);
+  if (h->gin) (void)hipEventDestroy(h->gin);
+  if (h->gout) (void)hipEventDestroy(h->gout);
+  if (h->gs) (void)hipStreamDestroy(h->gs);
   if (h->e0) (void)hipEventDestroy(h->e0);
   if (h->e1) (void)hipEventDestroy(h->e1);
   delete h;
@@ -1062,6 +1164,13 @@ int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape
   if (!stencil_cfg_valid(g, c)) return MGAR_E_ARG;
   if (stencil_num_partials(g, &c) > h->part_cap) return MGAR_E_ARG;
   h->scfg[cls][level][mode] = c;
+  drop_graphs(h);   // captured iterations hold the old shapes
+  return MGAR_OK;
+}
+
+int mgar_set_graphs(mgar_handle* h, int on) {
+  if (!h) return MGAR_E_ARG;
+  h->use_graphs = on != 0;
   return MGAR_OK;
 }
 
@@ -1124,6 +1233,7 @@ int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd,
 
 int mgar_autotune(mgar_handle* h, int reps, double* best_us) {
   if (!h || reps < 1) return MGAR_E_ARG;
+  drop_graphs(h);
   const int L = h->L;
   if (best_us)
     for (int i = 0; i < 2 * L * 7; ++i) best_us[i] = 0.0;

@@ -72,7 +72,9 @@ struct CgState {
   int done;                  // set once the stopping test fires
   int iters;                 // iterations performed at exit
   int converged;             // 1 = tolerance met, 0 = cg_max reached
-  int pad;
+  int it;                    // iterations done so far (device counter: the launches
+                             // of an iteration carry no host iteration index, so a
+                             // captured iteration can be replayed)
 };
 
 // PCG state of one design of a batch. The iteration counter lives on the

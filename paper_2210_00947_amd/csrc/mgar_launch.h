@@ -115,11 +115,13 @@ int launch_dot(const double* a, const double* b, long long n, double* part, cons
 template <typename TA, typename TB>
 int launch_dot_t(const TA* a, const TB* b, long long n, double* part, const int* done, hipStream_t s,
                  unsigned* cnt = nullptr, double* rout = nullptr);
+// The CG kernels take the iteration index from st->it (advanced by
+// launch_cg_check), never from the host.
 template <typename T>
-void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, int it, hipStream_t s);
+void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, hipStream_t s);
 template <typename T>
-int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, int it,
-                       double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s);
+int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
+                       unsigned* cnt, double tol, int cg_max, hipStream_t s);
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
@@ -127,20 +129,19 @@ void launch_cast_f32(const double* a, float* b, long long n, hipStream_t s);
 void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s);
 // out = sum(part[0..n)) in a fixed order (single block)
 void launch_finalize(const double* part, int n, double* out, const int* done, hipStream_t s);
-// Stopping test before iteration it from the partials of ||r||^2.
-void launch_cg_check(CgState* st, const double* part, int np, int it, double tol, int cg_max,
-                     hipStream_t s);
+// st->rz[st->it & 1] = sum of the partials (r.z of the current iteration)
+void launch_finalize_rz(const double* part, int n, CgState* st, hipStream_t s);
+// End of an iteration: st->it += 1 and the stopping test from the partials of ||r||^2.
+void launch_cg_check(CgState* st, const double* part, int np, double tol, int cg_max, hipStream_t s);
 // ||q||^2 and ||r_0||^2 from partials, and the stopping test before iteration 0.
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
                     double tol, int cg_max, hipStream_t s);
-void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
-                     hipStream_t s);
+void launch_p_update(const double* z, double* p, long long n, const CgState* st, hipStream_t s);
 // x += alpha p, r -= alpha w and partials of ||r||^2; with cnt != null the sum
-// is also reduced in the launch and the stopping test for iteration it+1
-// applied by the last block (costs a device-scope fence per block).
+// is also reduced in the launch, st->it advanced and the stopping test applied
+// by the last block (costs a device-scope fence per block).
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
-                     hipStream_t s);
+                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 template <typename T>
 void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s);

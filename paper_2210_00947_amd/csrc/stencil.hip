@@ -743,6 +743,7 @@ __device__ inline double ke_entry(int ca, int cb, double h) {
 
 constexpr int CB_THREADS = 1024;
 constexpr int CB_MAXN = 1024;
+constexpr int CB_KCAP = 1024;   // cells of a coarsest grid of at most 128 nodes
 
 // Coarsest grid: assemble the dense N_c x N_c matrix (identity rows/columns on
 // Dirichlet nodes), then invert it in place by Gauss-Jordan elimination without
@@ -828,9 +829,13 @@ __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restr
                                              int* __restrict__ status) {
   __shared__ double colp[128];
   __shared__ double rowp[128];
+  __shared__ double kc[CB_KCAP];
   const int n = (int)g.nn;
   const int t = threadIdx.x;
   const int tc = t & 31, tr = t >> 5;
+  // cell conductivities staged in LDS once (the assembly reads each many times)
+  for (int e = t; e < (int)g.ne; e += CB_THREADS) kc[e] = (double)k(e);
+  __syncthreads();
   // Entry (i, j) straight from the element sum: the cells shared by nodes i
   // and j, each adding k_e KE[c_i][c_j]; identity rows/columns on Dirichlet
   // nodes. No memory round trips.
@@ -868,66 +873,55 @@ __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restr
                   if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
                   const int cci = (1 - aa) + 2 * (1 - bb) + (DIM == 3 ? 4 * (1 - c) : 0);
                   const int ccj = bx + 2 * by + 4 * bz;
-                  v += (double)k(geo_elem(g, ex, ey, ez)) * ke_entry<DIM>(cci, ccj, g.h);
+                  v += kc[geo_elem(g, ex, ey, ez)] * ke_entry<DIM>(cci, ccj, g.h);
                 }
           }
         }
       }
       R[a][b] = v;
     }
+  // Elimination: the slot pa of the pivot is a compile-time index (outer loop
+  // unrolled), so the register tile is never indexed at run time. Entries past
+  // n are 0 and stay 0. Same arithmetic per entry as k_coarse_build.
   int bad = 0;
-  for (int p = 0; p < n; ++p) {
-    const int pa = p >> 5, pr = p & 31;
-    if (tr == pr) {   // this thread row holds row p (at slot pa)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = tc + 32 * b;
-        if (j < n) rowp[j] = (pa == 0 ? R[0][b] : pa == 1 ? R[1][b] : pa == 2 ? R[2][b] : R[3][b]);
+  for (int pa = 0; pa < 4; ++pa) {
+    for (int pr = 0; pr < 32; ++pr) {
+      const int p = pa * 32 + pr;
+      if (p >= n) break;
+      if (tr == pr) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) rowp[tc + 32 * b] = R[pa][b];
       }
-    }
-    if (tc == pr) {   // this thread column holds column p (at slot pa)
+      if (tc == pr) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = tr + 32 * a;
-        if (i < n) colp[i] = (pa == 0 ? R[a][0] : pa == 1 ? R[a][1] : pa == 2 ? R[a][2] : R[a][3]);
+        for (int a = 0; a < 4; ++a) colp[tr + 32 * a] = R[a][pa];
       }
-    }
-    __syncthreads();
-    const double piv = rowp[p];
-    if (!(piv > 0.0)) bad = 1;
-    const double inv = 1.0 / piv;
-    double rj[4];
+      __syncthreads();
+      const double piv = rowp[p];
+      if (!(piv > 0.0)) bad = 1;
+      const double inv = 1.0 / piv;
+      double rj[4], ci[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = tc + 32 * b;
-      rj[b] = (j < n) ? rowp[j] * inv : 0.0;
-    }
+      for (int b = 0; b < 4; ++b) rj[b] = rowp[tc + 32 * b] * inv;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = tr + 32 * a;
-      const double ci = (i < n) ? colp[i] : 0.0;
+      for (int a = 0; a < 4; ++a) ci[a] = colp[tr + 32 * a];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) R[a][b] -= ci * rj[b];
-    }
-    // pivot row and column: a_pj = a_pj / a_pp, a_ip = -a_ip / a_pp, a_pp = 1 / a_pp
-    if (tr == pr) {
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = tc + 32 * b;
-        const double v = (j == p) ? inv : rj[b];
-        if (pa == 0) R[0][b] = v; else if (pa == 1) R[1][b] = v; else if (pa == 2) R[2][b] = v; else R[3][b] = v;
+        for (int b = 0; b < 4; ++b) R[a][b] -= ci[a] * rj[b];
+      // pivot row: a_pj / a_pp, a_pp -> 1 / a_pp; pivot column: -a_ip / a_pp
+      if (tr == pr) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) R[pa][b] = (tc + 32 * b == p) ? inv : rj[b];
       }
-    }
-    if (tc == pr) {
+      if (tc == pr) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = tr + 32 * a;
-        if (i == p || i >= n) continue;
-        const double v = -colp[i] * inv;
-        if (pa == 0) R[a][0] = v; else if (pa == 1) R[a][1] = v; else if (pa == 2) R[a][2] = v; else R[a][3] = v;
+        for (int a = 0; a < 4; ++a)
+          if (tr + 32 * a != p) R[a][pa] = -ci[a] * inv;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)

@@ -52,18 +52,27 @@ __global__ __launch_bounds__(FB) void k_cg_init(CgState* st, const double* __res
   const double rr = sum_partials(pr, nr, sh);
   if (threadIdx.x == 0) {
     st->qq = qq; st->rr = rr; st->rz[0] = st->rz[1] = 0.0; st->pw = 0.0;
-    st->done = 0; st->iters = 0; st->converged = 0;
+    st->done = 0; st->iters = 0; st->converged = 0; st->it = 0;
     if (sqrt(rr) <= tol * sqrt(qq)) { st->done = 1; st->converged = 1; }
     else if (cg_max <= 0) { st->done = 1; }
   }
 }
 
+// rz of the current iteration: st->rz[it & 1] = sum of the partials
+__global__ __launch_bounds__(FB) void k_finalize_rz(const double* __restrict__ part, int n,
+                                                    CgState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double s = sum_partials(part, n, sh);
+  if (threadIdx.x == 0) st->rz[st->it & 1] = s;
+}
+
 // p = z + beta p, beta = rz_k / rz_{k-1} (Fletcher-Reeves); p = z at k = 0.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __restrict__ p,
-                                                 long long n, const CgState* __restrict__ st,
-                                                 int it) {
+                                                 long long n, const CgState* __restrict__ st) {
   if (st->done) return;
+  const int it = st->it;
   const T beta = (T)((it == 0) ? 0.0 : st->rz[it & 1] / st->rz[(it - 1) & 1]);
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
@@ -76,11 +85,12 @@ template <typename T>
 __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p,
                                                   const T* __restrict__ w, long long n,
-                                                  CgState* __restrict__ st, int it,
+                                                  CgState* __restrict__ st,
                                                   double* __restrict__ part,
                                                   unsigned* __restrict__ cnt, double tol,
                                                   int cg_max) {
   if (st->done) return;
+  const int it = st->it;
   __shared__ double sh[VB / MGAR_WAVE];
   const T alpha = (T)(st->rz[it & 1] / st->pw);
   double s = 0.0;
@@ -98,6 +108,7 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   double rr = 0.0;
   if (grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, nullptr, sh, &rr) && threadIdx.x == 0) {
     st->rr = rr;
+    st->it = it + 1;
     if (sqrt(rr) <= tol * sqrt(st->qq)) {
       st->done = 1; st->converged = 1; st->iters = it + 1;
     } else if (it + 1 >= cg_max) {
@@ -106,14 +117,16 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   }
 }
 
-// Stopping test before iteration `it` from the ||r||^2 partials of the last
-// update (||r|| <= tol ||q||, or it == cg_max).
+// End of an iteration: it += 1, then the stopping test before the next one
+// from the ||r||^2 partials of the update (||r|| <= tol ||q||, or it == cg_max).
 __global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __restrict__ part,
-                                                 int np, int it, double tol, int cg_max) {
+                                                 int np, double tol, int cg_max) {
   if (st->done) return;
   __shared__ double sh[FB / MGAR_WAVE];
   const double rr = sum_partials(part, np, sh);
   if (threadIdx.x == 0) {
+    const int it = st->it + 1;
+    st->it = it;
     st->rr = rr;
     if (sqrt(rr) <= tol * sqrt(st->qq)) {
       st->done = 1; st->converged = 1; st->iters = it;
@@ -720,9 +733,12 @@ void launch_finalize(const double* part, int n, double* out, const int* done, hi
   k_finalize<<<1, FB, 0, s>>>(part, n, out, done);
 }
 
-void launch_cg_check(CgState* st, const double* part, int np, int it, double tol, int cg_max,
-                     hipStream_t s) {
-  k_cg_check<<<1, FB, 0, s>>>(st, part, np, it, tol, cg_max);
+void launch_finalize_rz(const double* part, int n, CgState* st, hipStream_t s) {
+  k_finalize_rz<<<1, FB, 0, s>>>(part, n, st);
+}
+
+void launch_cg_check(CgState* st, const double* part, int np, double tol, int cg_max, hipStream_t s) {
+  k_cg_check<<<1, FB, 0, s>>>(st, part, np, tol, cg_max);
 }
 
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
@@ -731,33 +747,31 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
 }
 
 template <typename T>
-void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, int it, hipStream_t s) {
-  k_p_update<T><<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st, it);
+void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, hipStream_t s) {
+  k_p_update<T><<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st);
 }
-template void launch_p_update_t<double>(const double*, double*, long long, const CgState*, int, hipStream_t);
-template void launch_p_update_t<float>(const float*, float*, long long, const CgState*, int, hipStream_t);
+template void launch_p_update_t<double>(const double*, double*, long long, const CgState*, hipStream_t);
+template void launch_p_update_t<float>(const float*, float*, long long, const CgState*, hipStream_t);
 
-void launch_p_update(const double* z, double* p, long long n, const CgState* st, int it,
-                     hipStream_t s) {
-  launch_p_update_t<double>(z, p, n, st, it, s);
+void launch_p_update(const double* z, double* p, long long n, const CgState* st, hipStream_t s) {
+  launch_p_update_t<double>(z, p, n, st, s);
 }
 
 template <typename T>
-int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, int it,
-                       double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s) {
+int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
+                       unsigned* cnt, double tol, int cg_max, hipStream_t s) {
   const int nb = vec_num_blocks(n);
-  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, it, part, cnt, tol, cg_max);
+  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, part, cnt, tol, cg_max);
   return nb;
 }
 template int launch_cg_update_t<double>(double*, double*, const double*, const double*, long long,
-                                        CgState*, int, double*, unsigned*, double, int, hipStream_t);
+                                        CgState*, double*, unsigned*, double, int, hipStream_t);
 template int launch_cg_update_t<float>(float*, float*, const float*, const float*, long long,
-                                       CgState*, int, double*, unsigned*, double, int, hipStream_t);
+                                       CgState*, double*, unsigned*, double, int, hipStream_t);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     CgState* st, int it, double* part, unsigned* cnt, double tol, int cg_max,
-                     hipStream_t s) {
-  return launch_cg_update_t<double>(x, r, p, w, n, st, it, part, cnt, tol, cg_max, s);
+                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s) {
+  return launch_cg_update_t<double>(x, r, p, w, n, st, part, cnt, tol, cg_max, s);
 }
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {

@@ -33,7 +33,7 @@ EXPORTS = [
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
     "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
-    "mgar_tune_set", "mgar_residual", "mgar_net_create", "mgar_net_destroy", "mgar_net_sizes",
+    "mgar_tune_set", "mgar_set_graphs", "mgar_residual", "mgar_net_create", "mgar_net_destroy", "mgar_net_sizes",
     "mgar_net_set_params", "mgar_net_get_params", "mgar_net_infer", "mgar_net_output", "mgar_net_grad",
     "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
     "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
@@ -291,6 +291,9 @@ class Handle:
             raise ValueError("out must be an int16 GPU tensor with E entries")
         _check(self._L.mgar_op_bf16(self.h, _ptr(x, self.E, "x"), ctypes.c_void_p(out.data_ptr())),
                "mgar_op_bf16")
+
+    def mgar_set_graphs(self, on):
+        _check(self._L.mgar_set_graphs(self.h, int(bool(on))), "mgar_set_graphs")
 
     def mgar_residual(self, xphys, q, T):
         r = ctypes.c_double()

@@ -24,11 +24,8 @@ Prints one JSON line:
                  stays the all-FP64 loop
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events recorded at
-                 the start and end of each launch, against 8 TB/s. Kernel timing
-                 needs eagerly launched kernels, so it runs on --roof-cycles
-                 cycles that continue the MGAR loop right after the timed ones
-                 (same kernel, launch shape and data); the timed cycles replay
-                 captured PCG iterations
+                 the start and end of each launch in the timed cycles, against
+                 8 TB/s
   cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
                  solve of the same grid
 """
@@ -77,20 +74,27 @@ def log(*a):
 
 
 def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None, roof_cycles=0):
-    """Warm-up cycles, then `steps` timed cycles (PCG iterations replayed from
-    captured graphs). With roof_cycles > 0 the loop then continues for that
-    many cycles with kernel timing on (which launches every kernel eagerly) to
-    time the roofline kernel with HIP events recorded at kernel start and end."""
+    """Warm-up cycles, then `steps` timed cycles. The roofline kernel is timed
+    with HIP events recorded at the start and end of each of its launches:
+    over the timed cycles (roof_cycles = 0, the default; kernels are launched
+    eagerly, the library's default), or on roof_cycles further cycles (for
+    runs that replay captured PCG iterations, where kernel timing cannot run)."""
     opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision, seed=seed)
     for _ in range(warmup):
         opt.step()
+    if roof_cycles == 0:
+        opt.h.mgar_profile(1 << ROOF_MODE)
+        opt.h.mgar_profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [opt.step() for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n, ms, by = 0, 0.0, 0.0
-    if roof_cycles > 0:
+    if roof_cycles == 0:
+        n, ms, by = opt.h.mgar_profile_read()
+        opt.h.mgar_profile(0)
+    else:
         opt.h.mgar_profile(1 << ROOF_MODE)
         opt.h.mgar_profile_read()
         for _ in range(roof_cycles):
@@ -245,8 +249,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=9, help="untimed cycles before the timed ones")
     ap.add_argument("--config", default="c3", help="workload: c0, c1, c2 or c3 (default 128^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--roof-cycles", type=int, default=10,
-                    help="cycles after the timed ones with kernel timing on (roofline measurement)")
+    ap.add_argument("--roof-cycles", type=int, default=0,
+                    help="0: time the roofline kernel over the timed cycles; N > 0: on N further cycles")
     ap.add_argument("--no-mgcg", action="store_true", help="skip the plain-MGCG reference loop")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")

@@ -1178,8 +1178,8 @@ namespace {
 
 // Times every candidate shape of one (class, level, mode) on scratch data and
 // keeps the fastest. Returns the best average launch time in microseconds.
-// Each timed launch is bracketed by its own pair of events, so launches never
-// overlap each other and small grids are timed as they run inside a solve.
+// Each timed launch records its own pair of events at kernel start and end,
+// so the comparison is of kernel durations, not of launch overheads.
 int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd, double* bd,
              double* od, double* kd, uint16_t* kb, const std::vector<hipEvent_t>& ev,
              double* best_us) {
@@ -1190,29 +1190,26 @@ int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd,
   int bi = 0;
   for (int i = 0; i < nc; ++i) {
     if (stencil_num_partials(g, &cand[i]) > h->part_cap) continue;
-    auto launch = [&]() {
+    // events (when given) are recorded at the start and end of the kernel itself
+    auto launch = [&](hipEvent_t e0, hipEvent_t e1) {
       if (cls == 0) {
         launch_stencil(g, mode, xd, kd, kd + g.ne, bd, od, h->p.omega, h->pa, nullptr, h->s, nullptr,
-                       nullptr, nullptr, nullptr, &cand[i]);
+                       nullptr, e0, e1, &cand[i]);
       } else if (level == 0) {
         const CellB k{kb, h->kmin_f, h->kdiff_f}, kr{kb + g.ne, h->kmin_f, h->kdiff_f};
         launch_stencil_t<float, CellB>(g, mode, (const float*)xd, k, kr, (const float*)bd, (float*)od,
-                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, nullptr,
-                                       nullptr, &cand[i]);
+                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, e0, e1,
+                                       &cand[i]);
       } else {
         const CellF k{(const float*)kd}, kr{(const float*)kd + g.ne};
         launch_stencil_t<float, CellF>(g, mode, (const float*)xd, k, kr, (const float*)bd, (float*)od,
-                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, nullptr,
-                                       nullptr, &cand[i]);
+                                       h->p.omega, h->pa, nullptr, h->s, nullptr, nullptr, e0, e1,
+                                       &cand[i]);
       }
     };
-    launch();
-    launch();
-    for (int r = 0; r < reps; ++r) {
-      HIPCK(hipEventRecord(ev[2 * r], h->s));
-      launch();
-      HIPCK(hipEventRecord(ev[2 * r + 1], h->s));
-    }
+    launch(nullptr, nullptr);
+    launch(nullptr, nullptr);
+    for (int r = 0; r < reps; ++r) launch(ev[2 * r], ev[2 * r + 1]);
     HIPCK(hipEventSynchronize(ev[2 * reps - 1]));
     LAUNCHCK();
     double us = 0.0;

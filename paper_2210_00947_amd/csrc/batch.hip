@@ -482,7 +482,7 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
           G.restr[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
                                            batch_item_blocks(gc)));
           G.prol[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
-                                          batch_item_blocks(gf)));
+                                          batch_item_blocks(gc)));
         }
         if (l + 1 < D.L) {
           const Geo &gf = D.g[l], &gc = D.g[l + 1];

@@ -42,17 +42,25 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # finest-grid stencil kernel reported in the roofline object (mode bit of mgar_profile)
 ROOF_MODE = 1          # apply + dot: q = K p, p.q  (one launch per CG iteration, finest grid only)
-ROOF_KERNEL = "k_stencil_z<SM_APPLY_DOT> (finest grid, q = K p with p.q)"
+# kernel that runs a launch shape {kind, kz, zd, ntx} (kind 0: node-parallel,
+# 1: z-marching, 2: two-row z-marching)
+SHAPE_KERNEL = {0: "k_stencil_b", 1: "k_stencil_z", 2: "k_stencil_z2"}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_stencil_z_apply_dot_128cube.md")
+def roof_kernel(shape):
+    return (f"{SHAPE_KERNEL.get(shape[0], '?')}<SM_APPLY_DOT> shape {shape} "
+            "(finest grid, q = K p with p.q)")
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "stencil_apply_dot_128cube.md")
 STENCIL_SRC = os.path.join(ROOT, "paper_2210_00947_amd", "csrc", "stencil.hip")
 
 
-def committed_traffic():
+def committed_traffic(shape):
     """HBM traffic per launch of the roofline kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, or None when the stencil source has
-    changed since they were taken (or they are missing)."""
+    changed since they were taken, when they were taken on another launch
+    shape, or when they are missing."""
     import hashlib
     try:
         src = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()
@@ -61,7 +69,7 @@ def committed_traffic():
             if not line.startswith("counters:"):
                 continue
             kv = dict(f.split("=", 1) for f in line.split()[1:])
-            if kv.get("source_sha256") != src:
+            if kv.get("source_sha256") != src or kv.get("shape") != ",".join(map(str, shape)):
                 return None
             return (float(kv["fetch_kib"]) + float(kv["write_kib"])) * 1024.0 * float(kv.get("scale", 1.0))
     except (OSError, ValueError, KeyError):
@@ -103,6 +111,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=
         n, ms, by = opt.h.mgar_profile_read()
         opt.h.mgar_profile(0)
     el = t1 - t0
+    roof_shape = opt.h.mgar_tune_get(0, 0, ROOF_MODE)
     paths = {"mgcg": 0, "accept": 0, "fallback": 0}
     for r in recs:
         paths[["mgcg", "accept", "fallback"][r.path]] += 1
@@ -118,6 +127,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=
         "kernel_launches": n,
         "kernel_ms_total": ms,
         "kernel_bytes_total": by,
+        "roof_shape": roof_shape,
     }
     opt.h.close()
     return out
@@ -304,8 +314,9 @@ def main():
         per_launch = mg_ar["kernel_bytes_total"] / mg_ar["kernel_launches"]
         achieved = per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic() if prob.name == "3d-128^3" else None,
-                "kernel": ROOF_KERNEL,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": committed_traffic(mg_ar["roof_shape"]) if prob.name == "3d-128^3" else None,
+                "kernel": roof_kernel(mg_ar["roof_shape"]),
                 "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
                 "launches": mg_ar["kernel_launches"]}
     cpu = None

@@ -171,7 +171,8 @@ int mgar_op_bf16(mgar_handle* h, const double* x, void* out);
  * apply) of precision class `cls` (0: FP64 kernels; 1: FP32 kernels of
  * MGAR_PREC_MIXED) uses a launch shape of four ints {kind, kz, zd, ntx}:
  * kind 0 = one thread per node; kind 1 = z-marching blocks (3D) over ntx tiles
- * across x, kz node planes per block, a zd-deep (1 to 4) load queue. Every
+ * across x, kz node planes per block, a zd-deep (1 to 4) load queue; kind 2 =
+ * as kind 1 with two node rows per thread (zd 1 or 2). Every
  * shape computes each node with the same arithmetic; only the summation order
  * of the dot products of modes 1 and 4 depends on the shape. Setup installs a
  * default shape everywhere.

@@ -729,8 +729,8 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->cw, N));
   long long cap = stencil_num_partials(g0);
   {
-    StencilCfg cand[64];
-    const int nc = stencil_candidates(g0, cand, 64);
+    StencilCfg cand[STENCIL_MAX_CANDIDATES];
+    const int nc = stencil_candidates(g0, cand, STENCIL_MAX_CANDIDATES);
     for (int i = 0; i < nc; ++i) cap = std::max<long long>(cap, stencil_num_partials(g0, &cand[i]));
   }
   cap = cap > 1024LL * 64 ? cap : 1024LL * 64;   // multi-value partials (Gram, OC)
@@ -1184,8 +1184,8 @@ int tune_one(mgar_handle* h, int cls, int level, int mode, int reps, double* xd,
              double* od, double* kd, uint16_t* kb, const std::vector<hipEvent_t>& ev,
              double* best_us) {
   const Geo& g = h->lv[level].g;
-  StencilCfg cand[64];
-  const int nc = stencil_candidates(g, cand, 64);
+  StencilCfg cand[STENCIL_MAX_CANDIDATES];
+  const int nc = stencil_candidates(g, cand, STENCIL_MAX_CANDIDATES);
   double best = -1.0;
   int bi = 0;
   for (int i = 0; i < nc; ++i) {

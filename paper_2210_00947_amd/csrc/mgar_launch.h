@@ -19,7 +19,9 @@ enum StencilMode {
 // thread per node, 64x4 blocks). kind 1: z-marching kernel (3D only): the node
 // grid is cut into ntx x nty column tiles of width ceil(nnx/ntx) <= 64 and
 // height filling 256 threads, and into z-chunks of kz node planes; each block
-// marches one chunk with a load queue zd planes deep (1 to 4). The arithmetic
+// marches one chunk with a load queue zd planes deep (1 to 4). kind 2: as
+// kind 1 with two node rows per thread (tile width <= 128, an even tile
+// height, zd 1 or 2). The arithmetic
 // of every node is the same for every shape; only the order in which block
 // partials of a dot are summed depends on it.
 struct StencilCfg {
@@ -28,7 +30,8 @@ struct StencilCfg {
 StencilCfg stencil_default_cfg(const Geo& g);
 bool stencil_cfg_valid(const Geo& g, const StencilCfg& c);
 // Candidate shapes for the tuner (the default first); returns how many were
-// written (at most `cap`).
+// written (at most `cap`; STENCIL_MAX_CANDIDATES holds them all).
+constexpr int STENCIL_MAX_CANDIDATES = 128;
 int stencil_candidates(const Geo& g, StencilCfg* out, int cap);
 // Value type T (double or float) and cell loader CL (CellD, CellF, CellB) are
 // template parameters; FP64 entry points keep plain-pointer overloads. cfg
@@ -40,8 +43,8 @@ int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T*
                      hipEvent_t ev1 = nullptr, const StencilCfg* cfg = nullptr);
 // Returns the number of block partials written to `part` (0 for modes without a
 // dot). With cnt != null the dot is also reduced in the same launch (last block
-// sums the partials in order) and stored to *rout. ev0/ev1 (z-marching shapes
-// only): events recorded at kernel start and end.
+// sums the partials in order) and stored to *rout. ev0/ev1 (may be null):
+// events recorded at the start and end of the kernel itself.
 int launch_stencil(const Geo& g, int mode, const double* x, const double* k, const double* kref,
                    const double* b, double* out, double omega, double* part, const int* done,
                    hipStream_t s, unsigned* cnt = nullptr, double* rout = nullptr,

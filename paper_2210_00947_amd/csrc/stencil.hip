@@ -119,21 +119,28 @@ __device__ inline T ldx(const Geo& g, const T* __restrict__ x, int i, int j, int
 // face neighbours have weight 0. ks returns the sum of the 8 conductivities,
 // so that the diagonal of K is hc * ks. Every 3D stencil kernel evaluates this
 // one expression, so results do not depend on the kernel or launch shape.
+template <typename T, bool NEEDX, typename FA, typename FB, typename FC, typename GA, typename GB>
+__device__ inline T apply27g(FA A, FB B, FC C, GA CA, GB CB, T hc, T hf, T& ks) {
+  const T t00 = CA(0, 0) + CB(0, 0), t01 = CA(0, 1) + CB(0, 1);
+  const T t10 = CA(1, 0) + CB(1, 0), t11 = CA(1, 1) + CB(1, 1);
+  ks = (t00 + t01) + (t10 + t11);
+  if (!NEEDX) return T(0);
+  T s1 = t00 * B(0, 0) + t01 * B(0, 2) + t10 * B(2, 0) + t11 * B(2, 2);
+  s1 += (CA(0, 0) + CA(1, 0)) * A(1, 0) + (CA(0, 1) + CA(1, 1)) * A(1, 2);
+  s1 += (CA(0, 0) + CA(0, 1)) * A(0, 1) + (CA(1, 0) + CA(1, 1)) * A(2, 1);
+  s1 += CA(0, 0) * A(0, 0) + CA(0, 1) * A(0, 2) + CA(1, 0) * A(2, 0) + CA(1, 1) * A(2, 2);
+  s1 += (CB(0, 0) + CB(1, 0)) * C(1, 0) + (CB(0, 1) + CB(1, 1)) * C(1, 2);
+  s1 += (CB(0, 0) + CB(0, 1)) * C(0, 1) + (CB(1, 0) + CB(1, 1)) * C(2, 1);
+  s1 += CB(0, 0) * C(0, 0) + CB(0, 1) * C(0, 2) + CB(1, 0) * C(2, 0) + CB(1, 1) * C(2, 2);
+  return hc * ks * B(1, 1) - hf * s1;
+}
+
 template <typename T, bool NEEDX>
 __device__ inline T apply27(const T (&A)[3][3], const T (&B)[3][3], const T (&C)[3][3],
                             const T (&CA)[2][2], const T (&CB)[2][2], T hc, T hf, T& ks) {
-  const T t00 = CA[0][0] + CB[0][0], t01 = CA[0][1] + CB[0][1];
-  const T t10 = CA[1][0] + CB[1][0], t11 = CA[1][1] + CB[1][1];
-  ks = (t00 + t01) + (t10 + t11);
-  if (!NEEDX) return T(0);
-  T s1 = t00 * B[0][0] + t01 * B[0][2] + t10 * B[2][0] + t11 * B[2][2];
-  s1 += (CA[0][0] + CA[1][0]) * A[1][0] + (CA[0][1] + CA[1][1]) * A[1][2];
-  s1 += (CA[0][0] + CA[0][1]) * A[0][1] + (CA[1][0] + CA[1][1]) * A[2][1];
-  s1 += CA[0][0] * A[0][0] + CA[0][1] * A[0][2] + CA[1][0] * A[2][0] + CA[1][1] * A[2][2];
-  s1 += (CB[0][0] + CB[1][0]) * C[1][0] + (CB[0][1] + CB[1][1]) * C[1][2];
-  s1 += (CB[0][0] + CB[0][1]) * C[0][1] + (CB[1][0] + CB[1][1]) * C[2][1];
-  s1 += CB[0][0] * C[0][0] + CB[0][1] * C[0][2] + CB[1][0] * C[2][0] + CB[1][1] * C[2][2];
-  return hc * ks * B[1][1] - hf * s1;
+  return apply27g<T, NEEDX>([&](int y, int x) { return A[y][x]; }, [&](int y, int x) { return B[y][x]; },
+                            [&](int y, int x) { return C[y][x]; }, [&](int y, int x) { return CA[y][x]; },
+                            [&](int y, int x) { return CB[y][x]; }, hc, hf, ks);
 }
 
 // (K x)_i for node (i, j, kz) given the 2^d cell conductivities around it;
@@ -563,6 +570,207 @@ __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu((ZD == 1 || 
   if (kk < k1) ZSTEP(W0, W1, W2, V1, V0, 1)
   if (kk < k1) ZSTEP(W1, W2, W0, V0, V1, 0)
 #undef ZSTEP
+#undef ZX
+#undef ZB
+#undef ZCV
+#undef ZCM
+  if (DOT) {
+    const double sum = block_sum(dotv, sh);
+    if (cnt) grid_reduce(sum, blockIdx.x, gridDim.x, part, cnt, rout, sh, nullptr);
+    else if (threadIdx.x == 0) part[blockIdx.x] = sum;
+  }
+}
+
+// Two-row variant of the z-marching stencil: each thread computes the nodes
+// (i, j) and (i, j + 1) of every plane, so a block's tile is twice as tall for
+// the same 256 threads. The two nodes share their x window (4 x 3 per plane
+// instead of 2 x 3 x 3) and cell window (3 x 2 instead of 2 x 2 x 2): fewer
+// LDS reads and more independent arithmetic per thread. Same per-node formula
+// (apply27g) as every other stencil kernel.
+constexpr int XCAP2 = 3 * ZT;  // x fill slots per plane (three per thread)
+constexpr int CCAP2 = 2 * ZT;  // cell fill slots per plane (two per thread)
+
+template <int MODE, int ZD, typename T, typename CL>
+__global__ __launch_bounds__(ZT) void k_stencil_z2(
+    Geo g, int TXW, int TYH, int ntx, int nty, int KZ, const T* __restrict__ x, CL k, CL kref,
+    const T* __restrict__ b, T* __restrict__ out, T omega, double* __restrict__ part,
+    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout) {
+  if (done && *done) return;
+  using E = typename CL::E;
+  constexpr bool DK = (MODE == SM_NEG_DK);
+  constexpr bool NEEDX = (MODE != SM_JACOBI0);
+  constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
+                          MODE == SM_JACOBI0);
+  constexpr bool DOT = (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT);
+  constexpr bool CMASK = sizeof(E) == 2;
+  constexpr unsigned TS = sizeof(T), ES = sizeof(E);
+  __shared__ T Xs[2][XCAP2];
+  __shared__ T Cs[2][CCAP2];
+  __shared__ double sh[ZT / MGAR_WAVE];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int nxy = ntx * nty;
+  const int txy = t % nxy, zc = t / nxy;
+  const int i0 = (txy % ntx) * TXW, j0 = (txy / ntx) * TYH;
+  const int XW = TXW + 2, XN = XW * (TYH + 2);
+  const int CW = TXW + 1, CN = CW * (TYH + 1);
+  const int tid = threadIdx.x;
+  const int lx = tid % TXW, ly = tid / TXW;   // ly: pair of rows 2ly, 2ly + 1 of the tile
+  const int i = i0 + lx, j = j0 + 2 * ly;
+  const bool actp = 2 * ly < TYH && i < g.nnx;
+  const bool act0 = actp && j < g.nny, act1 = actp && j + 1 < g.nny;
+  const int k0 = zc * KZ;
+  const int k1 = min(k0 + KZ, g.nnz);
+  const unsigned plb = (unsigned)(g.nnx * g.nny) * TS;
+  const unsigned cplb = (unsigned)(g.nx * g.ny) * ES;
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(x, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rb = zrsrc(b, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t ro = zrsrc(out, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
+  const __amdgpu_buffer_rsrc_t rkr = zrsrc(kref.p, g.ne * ES);
+  const unsigned own0 = act0 ? (unsigned)(i + g.nnx * j) * TS : ZOOB;
+  const unsigned own1 = act1 ? (unsigned)(i + g.nnx * (j + 1)) * TS : ZOOB;
+  const unsigned xs0 = zslot_off(i0, j0, XW, XN, tid, g.nnx, g.nny, TS);
+  const unsigned xs1 = zslot_off(i0, j0, XW, XN, tid + ZT, g.nnx, g.nny, TS);
+  const unsigned xs2 = zslot_off(i0, j0, XW, XN, tid + 2 * ZT, g.nnx, g.nny, TS);
+  const unsigned cs0 = zslot_off(i0, j0, CW, CN, tid, g.nx, g.ny, ES);
+  const unsigned cs1 = zslot_off(i0, j0, CW, CN, tid + ZT, g.nx, g.ny, ES);
+  // LDS index of the top-left of this thread's x window (4 rows x 3) and cell
+  // window (3 rows x 2); inactive threads read a valid in-tile window
+  const int xw = actp ? (2 * ly) * XW + lx : 0;
+  const int cw = actp ? (2 * ly) * CW + lx : 0;
+
+#define ZX(so, p) (NEEDX ? zbload<T>(rx, zplane((so), (p), g.nnz, plb)) : T(0))
+#define ZB(own, p) (NEEDB ? zbload<T>(rb, zplane((own), (p), g.nnz, plb)) : T(0))
+#define ZCV(e, er) (DK ? T(k.value(e)) - T(kref.value(er)) : T(k.value(e)))
+#define ZCM(e, er, ok) (CMASK ? ZCV(e, er) * ((ok) ? T(1) : T(0)) : ZCV(e, er))
+
+  T qx0[ZD], qx1[ZD], qx2[ZD], qb0[ZD], qb1[ZD];
+  E qc0[ZD], qc1[ZD], qr0[ZD], qr1[ZD];
+  T W0[4][3], W1[4][3], W2[4][3], V0[3][2], V1[3][2];
+
+  {
+    const unsigned c0 = zplane(cs0, k0 - 1, g.nz, cplb), c1 = zplane(cs1, k0 - 1, g.nz, cplb);
+    Xs[0][tid] = ZX(xs0, k0 - 1);
+    Xs[1][tid] = ZX(xs0, k0);
+    Xs[0][tid + ZT] = ZX(xs1, k0 - 1);
+    Xs[1][tid + ZT] = ZX(xs1, k0);
+    Xs[0][tid + 2 * ZT] = ZX(xs2, k0 - 1);
+    Xs[1][tid + 2 * ZT] = ZX(xs2, k0);
+    const E e0 = zbload<E>(rk, c0), e1 = zbload<E>(rk, c1);
+    const E r0 = DK ? zbload<E>(rkr, c0) : E(0), r1 = DK ? zbload<E>(rkr, c1) : E(0);
+    Cs[0][tid] = ZCM(e0, r0, c0 < ZOOB);
+    Cs[0][tid + ZT] = ZCM(e1, r1, c1 < ZOOB);
+  }
+#pragma unroll
+  for (int d = 0; d < ZD; ++d) {
+    qx0[d] = ZX(xs0, k0 + 1 + d);
+    qx1[d] = ZX(xs1, k0 + 1 + d);
+    qx2[d] = ZX(xs2, k0 + 1 + d);
+    const unsigned c0 = zplane(cs0, k0 + d, g.nz, cplb), c1 = zplane(cs1, k0 + d, g.nz, cplb);
+    qc0[d] = zbload<E>(rk, c0);
+    qc1[d] = zbload<E>(rk, c1);
+    qr0[d] = DK ? zbload<E>(rkr, c0) : E(0);
+    qr1[d] = DK ? zbload<E>(rkr, c1) : E(0);
+    qb0[d] = ZB(own0, k0 + d);
+    qb1[d] = ZB(own1, k0 + d);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      W0[r][dx] = Xs[0][xw + r * XW + dx];
+      W1[r][dx] = Xs[1][xw + r * XW + dx];
+    }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) V0[r][a] = Cs[0][cw + r * CW + a];
+  __syncthreads();
+
+  const bool colfix0 = act0 && i >= g.f0x && i <= g.f1x && j >= g.f0y && j <= g.f1y;
+  const bool colfix1 = act1 && i >= g.f0x && i <= g.f1x && j + 1 >= g.f0y && j + 1 <= g.f1y;
+  const T hc = T(g.h * (1.0 / 3.0)), hf = T(g.h * (1.0 / 12.0));
+  double dotv = 0.0;
+
+#define ZNODE(A, B, C, CA, CB, R0, bn, colfix, act, own)                                        \
+  {                                                                                          \
+    T ks;                                                                                    \
+    const T y = apply27g<T, NEEDX>([&](int yy, int xx) { return A[R0 + yy][xx]; },          \
+                                   [&](int yy, int xx) { return B[R0 + yy][xx]; },          \
+                                   [&](int yy, int xx) { return C[R0 + yy][xx]; },          \
+                                   [&](int yy, int xx) { return CA[R0 + yy][xx]; },         \
+                                   [&](int yy, int xx) { return CB[R0 + yy][xx]; }, hc, hf, ks); \
+    const T xcv = NEEDX ? B[R0 + 1][1] : T(0);                                               \
+    const T diag = hc * ks;                                                                  \
+    T r = T(0);                                                                              \
+    if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) r = y;                                     \
+    else if (MODE == SM_RESID) r = bn - y;                                                   \
+    else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) r = xcv + omega * (bn - y) / diag;  \
+    else if (MODE == SM_JACOBI0) r = omega * bn / diag;                                      \
+    else if (MODE == SM_NEG_DK) r = -y;                                                      \
+    r = (colfix && kk >= g.f0z && kk <= g.f1z) ? T(0) : r;                                   \
+    if (MODE == SM_APPLY_DOT) dotv += act ? (double)xcv * (double)r : 0.0;                   \
+    if (MODE == SM_JACOBI_DOT) dotv += act ? (double)bn * (double)r : 0.0;                   \
+    zbstore(r, ro, own + (unsigned)kk * plb);                                                \
+  }
+
+#define ZSTEP2(A, B, C, CA, CB, s)                                                           \
+  {                                                                                          \
+    Xs[s][tid] = qx0[0];                                                                     \
+    Xs[s][tid + ZT] = qx1[0];                                                                \
+    Xs[s][tid + 2 * ZT] = qx2[0];                                                            \
+    Cs[s][tid] = ZCM(qc0[0], qr0[0], cs0 < ZOOB && kk < g.nz);                               \
+    Cs[s][tid + ZT] = ZCM(qc1[0], qr1[0], cs1 < ZOOB && kk < g.nz);                          \
+    const T bn0 = qb0[0], bn1 = qb1[0];                                                      \
+    _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
+      qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1]; qx2[d] = qx2[d + 1];                         \
+      qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
+      qr0[d] = qr0[d + 1]; qr1[d] = qr1[d + 1];                                              \
+      qb0[d] = qb0[d + 1]; qb1[d] = qb1[d + 1];                                              \
+    }                                                                                        \
+    __syncthreads();                                                                         \
+    if (NEEDX) {                                                                             \
+      _Pragma("unroll") for (int rr = 0; rr < 4; ++rr)                                       \
+      _Pragma("unroll") for (int dx = 0; dx < 3; ++dx)                                       \
+        C[rr][dx] = Xs[s][xw + rr * XW + dx];                                                \
+    }                                                                                        \
+    _Pragma("unroll") for (int rr = 0; rr < 3; ++rr)                                         \
+    _Pragma("unroll") for (int a = 0; a < 2; ++a) CB[rr][a] = Cs[s][cw + rr * CW + a];       \
+    {                                                                                        \
+      const int pf = kk + ZD;                                                                \
+      qx0[ZD - 1] = ZX(xs0, pf + 1);                                                         \
+      qx1[ZD - 1] = ZX(xs1, pf + 1);                                                         \
+      qx2[ZD - 1] = ZX(xs2, pf + 1);                                                         \
+      const unsigned c0 = zplane(cs0, pf, g.nz, cplb), c1 = zplane(cs1, pf, g.nz, cplb);     \
+      qc0[ZD - 1] = zbload<E>(rk, c0);                                                       \
+      qc1[ZD - 1] = zbload<E>(rk, c1);                                                       \
+      if (DK) qr0[ZD - 1] = zbload<E>(rkr, c0);                                              \
+      if (DK) qr1[ZD - 1] = zbload<E>(rkr, c1);                                              \
+      qb0[ZD - 1] = ZB(own0, pf);                                                            \
+      qb1[ZD - 1] = ZB(own1, pf);                                                            \
+    }                                                                                        \
+    ZNODE(A, B, C, CA, CB, 0, bn0, colfix0, act0, own0)                                      \
+    ZNODE(A, B, C, CA, CB, 1, bn1, colfix1, act1, own1)                                      \
+    ++kk;                                                                                    \
+  }
+
+  int kk = k0;
+  while (kk + 6 <= k1) {
+    ZSTEP2(W0, W1, W2, V0, V1, 0)
+    ZSTEP2(W1, W2, W0, V1, V0, 1)
+    ZSTEP2(W2, W0, W1, V0, V1, 0)
+    ZSTEP2(W0, W1, W2, V1, V0, 1)
+    ZSTEP2(W1, W2, W0, V0, V1, 0)
+    ZSTEP2(W2, W0, W1, V1, V0, 1)
+  }
+  if (kk < k1) ZSTEP2(W0, W1, W2, V0, V1, 0)
+  if (kk < k1) ZSTEP2(W1, W2, W0, V1, V0, 1)
+  if (kk < k1) ZSTEP2(W2, W0, W1, V0, V1, 0)
+  if (kk < k1) ZSTEP2(W0, W1, W2, V1, V0, 1)
+  if (kk < k1) ZSTEP2(W1, W2, W0, V0, V1, 0)
+#undef ZSTEP2
+#undef ZNODE
 #undef ZX
 #undef ZB
 #undef ZCV
@@ -1232,27 +1440,39 @@ ZShape zmarch_shape(const Geo& g, const StencilCfg& c) {
   tyh = std::min(tyh, XCAP / (z.TXW + 2) - 2);
   tyh = std::min(tyh, CCAP / (z.TXW + 1) - 1);
   z.TYH = std::max(tyh, 1);
+  if (c.kind == 2) {   // two rows per thread: an even tile height
+    tyh = 2 * (ZT / z.TXW);
+    tyh = std::min(tyh, XCAP2 / (z.TXW + 2) - 2);
+    tyh = std::min(tyh, CCAP2 / (z.TXW + 1) - 1);
+    z.TYH = std::max(tyh & ~1, 2);
+  }
   z.nty = (g.nny + z.TYH - 1) / z.TYH;
   z.nzc = (g.nnz + c.kz - 1) / c.kz;
   return z;
 }
 
-template <int ZD, typename T, typename CL>
+template <int M, int ZD, bool TWO, typename T, typename CL>
+constexpr auto zmarch_kernel() {
+  if constexpr (TWO) return &k_stencil_z2<M, ZD, T, CL>;
+  else return &k_stencil_z<M, ZD, T, CL>;
+}
+
+template <int ZD, bool TWO, typename T, typename CL>
 void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, CL k, CL kref,
                    const T* b, T* out, T omega, double* part, const int* done, unsigned* cnt,
                    double* rout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nb = z.ntx * z.nty * z.nzc;
   // With events, the launch goes through hipExtLaunchKernelGGL, which records
   // them at the start and end of the kernel itself (no dispatch latency).
+#define ZKER(M) (zmarch_kernel<M, ZD, TWO, T, CL>())
 #define ZCALL(M)                                                                                 \
   do {                                                                                           \
     if (ev0)                                                                                     \
-      hipExtLaunchKernelGGL((k_stencil_z<M, ZD, T, CL>), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, \
-                            z.TXW, z.TYH, z.ntx, z.nty, kz, x, k, kref, b, out, omega, part, done, \
-                            cnt, rout);                                                          \
+      hipExtLaunchKernelGGL(ZKER(M), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, z.TXW, z.TYH,     \
+                            z.ntx, z.nty, kz, x, k, kref, b, out, omega, part, done, cnt, rout); \
     else                                                                                         \
-      k_stencil_z<M, ZD, T, CL><<<nb, ZT, 0, s>>>(g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, k, kref, b, \
-                                                  out, omega, part, done, cnt, rout);            \
+      hipLaunchKernelGGL(ZKER(M), dim3(nb), dim3(ZT), 0, s, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, \
+                         k, kref, b, out, omega, part, done, cnt, rout);                         \
   } while (0)
   switch (mode) {
     case SM_APPLY: ZCALL(SM_APPLY); break;
@@ -1264,6 +1484,7 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
     case SM_NEG_DK: ZCALL(SM_NEG_DK); break;
   }
 #undef ZCALL
+#undef ZKER
 }
 
 // ---------------------------------------------------------------------------
@@ -1391,43 +1612,54 @@ __global__ __launch_bounds__(CB_THREADS) void kb_coarse_build(const BCoarse* __r
 StencilCfg stencil_default_cfg(const Geo& g) {
   StencilCfg c{0, 0, 0, 0};
   if (g.dim == 3 && g.nn >= ZMARCH_MIN_NODES) {
+    // two-row z-march with z-chunks sized for about two blocks per CU
+    StencilCfg z2{2, 4, 1, (g.nnx + 63) / 64};
+    const ZShape s = zmarch_shape(g, z2);
+    const long long cols = (long long)s.ntx * s.nty;
+    z2.kz = (int)std::min<long long>(16, std::max<long long>(4, (g.nnz * cols + 511) / 512));
     const StencilCfg z{1, ZKZ, 2, (g.nnx + 63) / 64};
-    if (stencil_cfg_valid(g, z)) c = z;
+    if (stencil_cfg_valid(g, z2)) c = z2;
+    else if (stencil_cfg_valid(g, z)) c = z;
   }
   return c;
 }
 
 bool stencil_cfg_valid(const Geo& g, const StencilCfg& c) {
   if (c.kind == 0) return true;
-  if (c.kind != 1 || g.dim != 3) return false;
-  if (c.kz < 1 || c.kz > 64 || c.zd < 1 || c.zd > 4) return false;
+  if ((c.kind != 1 && c.kind != 2) || g.dim != 3) return false;
+  if (c.kz < 1 || c.kz > 64 || c.zd < 1 || c.zd > (c.kind == 2 ? 2 : 4)) return false;
   if (c.ntx < 1 || c.ntx > g.nnx) return false;
   const int txw = (g.nnx + c.ntx - 1) / c.ntx;
-  if (txw > 64 || txw < 4) return false;
+  if (txw > (c.kind == 2 ? 128 : 64) || txw < 4) return false;
   if (g.nn * 8 >= (1LL << 31) || g.ne * 8 >= (1LL << 31)) return false;   // 32-bit buffer offsets
   const ZShape z = zmarch_shape(g, c);
-  return (long long)(z.TXW + 2) * (z.TYH + 2) <= XCAP && (long long)(z.TXW + 1) * (z.TYH + 1) <= CCAP &&
-         (long long)z.TXW * z.TYH <= ZT;
+  const long long xn = (long long)(z.TXW + 2) * (z.TYH + 2), cn = (long long)(z.TXW + 1) * (z.TYH + 1);
+  if (c.kind == 2)   // whole row pairs; a pair's 4-row window stays inside the staged tile
+    return z.TYH % 2 == 0 && xn <= XCAP2 && cn <= CCAP2 && (long long)z.TXW * (z.TYH / 2) <= ZT;
+  return xn <= XCAP && cn <= CCAP && (long long)z.TXW * z.TYH <= ZT;
 }
 
 int stencil_candidates(const Geo& g, StencilCfg* out, int cap) {
   int n = 0;
   auto add = [&](StencilCfg c) {
-    if (n < cap && stencil_cfg_valid(g, c)) out[n++] = c;
+    if (n >= cap || !stencil_cfg_valid(g, c)) return;
+    for (int i = 0; i < n; ++i)
+      if (out[i].kind == c.kind && out[i].kz == c.kz && out[i].zd == c.zd && out[i].ntx == c.ntx) return;
+    out[n++] = c;
   };
   add(stencil_default_cfg(g));
   if (g.dim != 3) return n;
-  if (stencil_default_cfg(g).kind == 1) add(StencilCfg{0, 0, 0, 0});
+  add(StencilCfg{0, 0, 0, 0});
   const int kzs[] = {4, 6, 8, 12, 16, 24};
   const int widths[] = {64, 32};
   for (int w : widths)
     for (int zd = 1; zd <= 4; ++zd)
-      for (int kz : kzs) {
-        const StencilCfg c{1, kz, zd, (g.nnx + w - 1) / w};
-        const StencilCfg d = stencil_default_cfg(g);
-        if (d.kind == 1 && c.kz == d.kz && c.zd == d.zd && c.ntx == d.ntx) continue;
-        add(c);
-      }
+      for (int kz : kzs) add(StencilCfg{1, kz, zd, (g.nnx + w - 1) / w});
+  const int kzs2[] = {4, 6, 8, 10, 12, 14, 16, 24};
+  const int widths2[] = {128, 64, 32};
+  for (int w : widths2)
+    for (int zd = 1; zd <= 2; ++zd)
+      for (int kz : kzs2) add(StencilCfg{2, kz, zd, (g.nnx + w - 1) / w});
   return n;
 }
 
@@ -1437,7 +1669,7 @@ static StencilCfg resolve_cfg(const Geo& g, const StencilCfg* cfg) {
 
 int stencil_num_partials(const Geo& g, const StencilCfg* cfg) {
   const StencilCfg c = resolve_cfg(g, cfg);
-  if (c.kind == 1) {
+  if (c.kind == 1 || c.kind == 2) {
     const ZShape z = zmarch_shape(g, c);
     return z.ntx * z.nty * z.nzc;
   }
@@ -1456,20 +1688,18 @@ int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T*
                      double omega, double* part, const int* done, hipStream_t s, unsigned* cnt,
                      double* rout, hipEvent_t ev0, hipEvent_t ev1, const StencilCfg* cfg) {
   const StencilCfg c = resolve_cfg(g, cfg);
-  if (c.kind == 1) {
+  if (c.kind == 1 || c.kind == 2) {
     const ZShape z = zmarch_shape(g, c);
-    if (c.zd == 4)
-      zmarch_launch<4, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
-                              ev0, ev1);
-    else if (c.zd == 3)
-      zmarch_launch<3, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
-                              ev0, ev1);
-    else if (c.zd == 2)
-      zmarch_launch<2, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
-                              ev0, ev1);
-    else
-      zmarch_launch<1, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s,
-                              ev0, ev1);
+#define ZL(D, TWO) \
+  zmarch_launch<D, TWO, T, CL>(g, z, c.kz, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s, ev0, ev1)
+    if (c.kind == 2) {
+      if (c.zd == 2) ZL(2, true);
+      else ZL(1, true);
+    } else if (c.zd == 4) ZL(4, false);
+    else if (c.zd == 3) ZL(3, false);
+    else if (c.zd == 2) ZL(2, false);
+    else ZL(1, false);
+#undef ZL
   } else if (g.dim == 2) {
     stencil_dispatch<2, T, CL>(g, mode, x, k, kref, b, out, (T)omega, part, done, cnt, rout, s, ev0, ev1);
   } else {

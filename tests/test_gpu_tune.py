@@ -11,7 +11,10 @@ from tests.gpu_util import dev, host, rel_l2, require_gpu
 pytestmark = pytest.mark.gpu
 
 SHAPES = [[0, 0, 0, 0], [1, 4, 1, 1], [1, 6, 2, 2], [1, 12, 1, 1], [1, 24, 2, 2], [1, 5, 1, 3], [1, 5, 3, 2], [1, 8, 4, 1],
-          [1, 7, 2, 1], [1, 64, 1, 1]]
+          [1, 7, 2, 1], [1, 64, 1, 1],
+          # two rows per thread: one tile across x (ragged last row pair), two and
+          # three tiles, one z-chunk, queue depths 1 and 2
+          [2, 4, 1, 1], [2, 6, 2, 1], [2, 5, 1, 2], [2, 7, 2, 3], [2, 64, 1, 1], [2, 3, 2, 4]]
 
 
 def handle(prob, **kw):
@@ -57,7 +60,8 @@ def test_invalid_shapes_refused():
     prob = W.tiny_3d(32, 32, 32, 4)
     h = handle(prob)
     before = h.mgar_tune_get(0, 0, 1)
-    for bad in ([1, 0, 1, 1], [1, 4, 5, 1], [2, 4, 1, 1], [1, 4, 1, 0], [1, 4, 1, 34], [1, 65, 1, 1]):
+    for bad in ([1, 0, 1, 1], [1, 4, 5, 1], [3, 4, 1, 1], [1, 4, 1, 0], [1, 4, 1, 34], [1, 65, 1, 1],
+                [2, 4, 3, 1], [2, 4, 1, 0], [2, 0, 1, 1]):
         with pytest.raises(M.MgarError):
             h.mgar_tune_set(0, 0, 1, bad)
     assert h.mgar_tune_get(0, 0, 1) == before
@@ -65,6 +69,8 @@ def test_invalid_shapes_refused():
     h2 = handle(p2)
     with pytest.raises(M.MgarError):
         h2.mgar_tune_set(0, 0, 1, [1, 8, 1, 1])     # z-marching needs 3D
+    with pytest.raises(M.MgarError):
+        h2.mgar_tune_set(0, 0, 1, [2, 8, 1, 1])
     with pytest.raises(M.MgarError):
         h.mgar_tune_set(0, 9, 1, [0, 0, 0, 0])      # no such level
 
@@ -91,3 +97,35 @@ def test_solves_after_autotune_match_oracle(precision):
         assert rel_l2(host(T), t_or) < 1e-8
     else:
         assert rel_l2(host(T), t_or) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_solves_with_two_row_shapes_match_oracle(precision):
+    """Every stencil mode of the two finest grids on two-row shapes (FP64 class,
+    and the FP32 class in mixed precision): MGCG and MGAR still match the oracle."""
+    import torch
+    prob = W.tiny_3d(32, 32, 32, 4)
+    h = handle(prob, precision=precision)
+    for cls in range(precision + 1):
+        for mode in range(7):
+            h.mgar_tune_set(cls, 0, mode, [2, 6, 2, 1])
+            h.mgar_tune_set(cls, 1, mode, [2, 5, 1, 1])
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    x0 = W.random_density(prob.nelem, 21, 0.2, 0.8)
+    x1 = np.clip(x0 + 0.02 * W.random_vector(prob.nelem, 22), 0, 1)
+    t0, st0 = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    st = h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    assert st["rc"] == 0
+    t1, st1 = s.mgar(x1, t0, 1e-8)
+    sa = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+    assert sa["rc"] == 0
+    tol = 1e-8 if precision == 0 else 1e-6
+    assert rel_l2(host(T0), t0) < tol
+    assert rel_l2(host(T1), t1) < tol
+    if precision == 0:
+        assert st["cg_iters"] == st0.cg_iters
+        assert sa["path"] == st1.path and sa["cg_iters"] == st1.cg_iters

@@ -259,13 +259,18 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
     return MGAR_OK;
   }
   const int lt = h->lt;   // grids lt..L-1 run inside one workgroup
+  bool presmoothed = false;   // grid l's sweep from zero was fused into the restriction onto it
   for (int l = 0; l < lt; ++l) {
     LevelBuf& v = h->lv[l];
     const double* b = (l == 0) ? b0 : v.b;
     if (l == 0 && x0) ACK(stencil_at(h, l, SM_JACOBI, x0, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
-    else ACK(stencil_at(h, l, SM_JACOBI0, nullptr, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
+    else if (!presmoothed)
+      ACK(stencil_at(h, l, SM_JACOBI0, nullptr, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
     ACK(stencil_at(h, l, SM_RESID, v.xa, v.k, nullptr, b, h->rtmp, w, nullptr, done, nullptr, tag));
-    launch_restrict(v.g, h->lv[l + 1].g, h->rtmp, h->lv[l + 1].b, done, h->s);
+    LevelBuf& c = h->lv[l + 1];
+    presmoothed = l + 1 < lt && launch_restrict_j0_t<double, CellD>(v.g, c.g, h->rtmp, CellD{c.k}, c.b, c.xa,
+                                                                        w, done, h->s);
+    if (!presmoothed) launch_restrict(v.g, c.g, h->rtmp, c.b, done, h->s);
   }
   launch_vtail(h->tail, h->lv[lt].b, h->lv[lt].xb, h->Ainv, w, done, h->s);
   const double* xfin = h->lv[lt].xb;
@@ -336,12 +341,16 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
     return MGAR_OK;
   }
   const int lt = h->ltf;
+  bool presmoothed = false;
   for (int l = 0; l < lt; ++l) {
     const float* b = (l == 0) ? b0 : h->bf[l];
     if (l == 0 && x0) ACK(stencil32(h, l, SM_JACOBI, x0, b, h->xaf[l], nullptr, done));
-    else ACK(stencil32(h, l, SM_JACOBI0, nullptr, b, h->xaf[l], nullptr, done));
+    else if (!presmoothed) ACK(stencil32(h, l, SM_JACOBI0, nullptr, b, h->xaf[l], nullptr, done));
     ACK(stencil32(h, l, SM_RESID, h->xaf[l], b, h->rtmpf, nullptr, done));
-    launch_restrict_t<float>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf, h->bf[l + 1], done, h->s);
+    presmoothed = l + 1 < lt && launch_restrict_j0_t<float, CellF>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf,
+                                                                   CellF{h->kf[l + 1]}, h->bf[l + 1],
+                                                                   h->xaf[l + 1], h->p.omega, done, h->s);
+    if (!presmoothed) launch_restrict_t<float>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf, h->bf[l + 1], done, h->s);
   }
   launch_vtail_t<float>(h->tailf, h->bf[lt], h->xbf[lt], h->Ainv, h->p.omega, done, h->s);
   const float* xfin = h->xbf[lt];
@@ -367,22 +376,19 @@ int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int ta
   if (cls == 0) {
     ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, tag));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
-    launch_finalize_rz(h->pb, nz, h->st, h->s);
-    launch_p_update(h->cz, h->cp, N, h->st, h->s);
+    launch_p_update(h->cz, h->cp, N, h->st, h->s, h->pb, nz);
     int nw = 0;
     ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, h->kcur, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, tag));
-    launch_finalize(h->pc, nw, &h->st->pw, done, h->s);
-    launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s);
+    launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s, h->pc, nw);
   } else {
     ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
-    launch_finalize_rz(h->pb, nz, h->st, h->s);
-    launch_p_update_t<float>(h->z32, h->p32, N, h->st, h->s);
+    launch_p_update_t<float>(h->z32, h->p32, N, h->st, h->s, h->pb, nz);
     // the inner operator: FP32 conductivities of the current densities (BF16
     // densities only enter the V-cycle preconditioner)
     ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
-    launch_finalize(h->pc, nparts_at(h, 1, SM_APPLY_DOT), &h->st->pw, done, h->s);
-    launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s);
+    launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s,
+                              h->pc, nparts_at(h, 1, SM_APPLY_DOT));
   }
   launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
   LAUNCHCK();

@@ -54,6 +54,12 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
 int stencil_num_partials(const Geo& g, const StencilCfg* cfg = nullptr);
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);
+// Restriction rf -> bc, then the coarse grid's sweep from zero bc -> xc with
+// cells kc (one launch). Returns false, launching nothing, when a grid is too
+// large for 32-bit buffer offsets (use the two separate launches then).
+template <typename T, typename CL>
+bool launch_restrict_j0_t(const Geo& gf, const Geo& gc, const T* rf, CL kc, T* bc, T* xc, double omega,
+                          const int* done, hipStream_t s);
 template <typename T>
 void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s);
 template <typename CL, typename TO>
@@ -119,12 +125,16 @@ template <typename TA, typename TB>
 int launch_dot_t(const TA* a, const TB* b, long long n, double* part, const int* done, hipStream_t s,
                  unsigned* cnt = nullptr, double* rout = nullptr);
 // The CG kernels take the iteration index from st->it (advanced by
-// launch_cg_check), never from the host.
+// launch_cg_check), never from the host. rzp / pwp (optional): block partials
+// of r.z / p.w, summed inside the update (in place of a separate finalize
+// launch) and stored to st->rz[st->it & 1] / st->pw.
 template <typename T>
-void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, hipStream_t s);
+void launch_p_update_t(const T* z, T* p, long long n, CgState* st, hipStream_t s,
+                       const double* rzp = nullptr, int np = 0);
 template <typename T>
 int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
-                       unsigned* cnt, double tol, int cg_max, hipStream_t s);
+                       unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp = nullptr,
+                       int npw = 0);
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
@@ -139,12 +149,14 @@ void launch_cg_check(CgState* st, const double* part, int np, double tol, int cg
 // ||q||^2 and ||r_0||^2 from partials, and the stopping test before iteration 0.
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
                     double tol, int cg_max, hipStream_t s);
-void launch_p_update(const double* z, double* p, long long n, const CgState* st, hipStream_t s);
+void launch_p_update(const double* z, double* p, long long n, CgState* st, hipStream_t s,
+                     const double* rzp = nullptr, int np = 0);
 // x += alpha p, r -= alpha w and partials of ||r||^2; with cnt != null the sum
 // is also reduced in the launch, st->it advanced and the stopping test applied
 // by the last block (costs a device-scope fence per block).
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s);
+                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,
+                     const double* pwp = nullptr, int npw = 0);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 template <typename T>
 void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s);

@@ -845,8 +845,8 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong(Geo gf, Geo gc, const T* _
 // Buffer-load forms of the two transfers: every load of a thread in flight at
 // once, nothing outside the grid read, same arithmetic as the kernels above.
 template <int DIM, typename T>
-__device__ inline void restrict_b_point(const Geo& gf, const Geo& gc, long long nc,
-                                        const T* __restrict__ rf, T* __restrict__ rc) {
+__device__ inline T restrict_b_point(const Geo& gf, const Geo& gc, long long nc,
+                                     const T* __restrict__ rf, T* __restrict__ rc) {
   constexpr unsigned TS = sizeof(T);
   int I, J, K;
   node_ijk(gc, nc, I, J, K);
@@ -870,6 +870,7 @@ __device__ inline void restrict_b_point(const Geo& gf, const Geo& gc, long long 
   }
   s = geo_fixed(gc, I, J, K) ? T(0) : s;
   zbstore(s, ro, node_boff(gc, I, J, K, TS));
+  return s;
 }
 
 template <int DIM, typename T>
@@ -878,6 +879,51 @@ __global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T
                                                          const int* __restrict__ done) {
   if (done && *done) return;
   restrict_b_point<DIM, T>(gf, gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), rf, rc);
+}
+
+// Restriction followed by the first (zero-start) damped Jacobi sweep of the
+// coarse grid, per coarse node: b_c = P^T r_f is stored, then
+// x_c = omega b_c / diag(K_c) (0 at Dirichlet nodes). Same arithmetic as the
+// restriction kernel followed by the stencil kernels in their sweep-from-zero
+// mode (diagonal = h/3 resp. 2/3 times the sum of the node's cells, summed in
+// the order of the node formula).
+template <int DIM, typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_restrict_j0(Geo gf, Geo gc, const T* __restrict__ rf,
+                                                          CL kc, T* __restrict__ bc, T* __restrict__ xc,
+                                                          T omega, const int* __restrict__ done) {
+  if (done && *done) return;
+  using E = typename CL::E;
+  constexpr unsigned TS = sizeof(T), ES = sizeof(E);
+  constexpr bool CMASK = sizeof(E) == 2;
+  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
+  const T bn = restrict_b_point<DIM, T>(gf, gc, n, rf, bc);
+  int i, j, kz;
+  node_ijk(gc, n, i, j, kz);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(kc.p, gc.ne * ES);
+  T kv[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (DIM == 2 && c == 1) { kv[c][bb][a] = T(0); continue; }
+        const unsigned o = cell_boff(gc, i - 1 + a, j - 1 + bb, DIM == 3 ? kz - 1 + c : 0, ES);
+        const T v = T(kc.value(zbload<E>(rk, o)));
+        kv[c][bb][a] = CMASK ? v * (o < ZOOB ? T(1) : T(0)) : v;
+      }
+  T ksum;
+  if (DIM == 3) {
+    const T t00 = kv[0][0][0] + kv[1][0][0], t01 = kv[0][0][1] + kv[1][0][1];
+    const T t10 = kv[0][1][0] + kv[1][1][0], t11 = kv[0][1][1] + kv[1][1][1];
+    ksum = (t00 + t01) + (t10 + t11);
+  } else {
+    ksum = ((kv[0][0][0] + kv[0][0][1]) + kv[0][1][0]) + kv[0][1][1];
+  }
+  const T diag = T(DIM == 3 ? gc.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
+  T r = omega * bn / diag;
+  r = geo_fixed(gc, i, j, kz) ? T(0) : r;
+  zbstore(r, zrsrc(xc, gc.nn * TS), node_boff(gc, i, j, kz, TS));
 }
 
 template <int DIM, typename T>
@@ -1742,6 +1788,20 @@ void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const i
 }
 template void launch_restrict_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
 template void launch_restrict_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);
+
+template <typename T, typename CL>
+bool launch_restrict_j0_t(const Geo& gf, const Geo& gc, const T* rf, CL kc, T* bc, T* xc, double omega,
+                          const int* done, hipStream_t s) {
+  if (!grid_fits_buffers(gf) || !grid_fits_buffers(gc)) return false;
+  const dim3 blk(TBX, TBY, 1);
+  if (gf.dim == 2) k_restrict_j0<2, T, CL><<<flat_grid(gc), blk, 0, s>>>(gf, gc, rf, kc, bc, xc, (T)omega, done);
+  else k_restrict_j0<3, T, CL><<<flat_grid(gc), blk, 0, s>>>(gf, gc, rf, kc, bc, xc, (T)omega, done);
+  return true;
+}
+template bool launch_restrict_j0_t<double, CellD>(const Geo&, const Geo&, const double*, CellD, double*,
+                                                  double*, double, const int*, hipStream_t);
+template bool launch_restrict_j0_t<float, CellF>(const Geo&, const Geo&, const float*, CellF, float*,
+                                                 float*, double, const int*, hipStream_t);
 
 template <typename T>
 void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s) {

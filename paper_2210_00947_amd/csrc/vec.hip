@@ -68,19 +68,33 @@ __global__ __launch_bounds__(FB) void k_finalize_rz(const double* __restrict__ p
 }
 
 // p = z + beta p, beta = rz_k / rz_{k-1} (Fletcher-Reeves); p = z at k = 0.
+// With rzp set, rz_k is first summed from its np block partials, by every
+// block in the same order (so all blocks hold the same value), and block 0
+// stores it to st->rz[k & 1]; otherwise st->rz[k & 1] already holds it.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __restrict__ p,
-                                                 long long n, const CgState* __restrict__ st) {
+                                                 long long n, CgState* __restrict__ st,
+                                                 const double* __restrict__ rzp, int np) {
   if (st->done) return;
+  __shared__ double sh[VB / MGAR_WAVE];
   const int it = st->it;
-  const T beta = (T)((it == 0) ? 0.0 : st->rz[it & 1] / st->rz[(it - 1) & 1]);
+  double rz = 0.0;
+  if (rzp) {
+    rz = sum_partials(rzp, np, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[it & 1] = rz;
+  } else {
+    rz = st->rz[it & 1];
+  }
+  const T beta = (T)((it == 0) ? 0.0 : rz / st->rz[(it - 1) & 1]);
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
 }
 
 // x += alpha p, r -= alpha w with alpha = rz / (p . w); ||r||^2 reduced in
 // the same launch, and the last block applies the stopping test that precedes
-// iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max).
+// iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max). With pwp set, p . w
+// is first summed from its npw block partials by every block (same order in
+// each) and block 0 stores it to st->pw; otherwise st->pw already holds it.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p,
@@ -88,11 +102,19 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
                                                   CgState* __restrict__ st,
                                                   double* __restrict__ part,
                                                   unsigned* __restrict__ cnt, double tol,
-                                                  int cg_max) {
+                                                  int cg_max, const double* __restrict__ pwp,
+                                                  int npw) {
   if (st->done) return;
   const int it = st->it;
   __shared__ double sh[VB / MGAR_WAVE];
-  const T alpha = (T)(st->rz[it & 1] / st->pw);
+  double pw;
+  if (pwp) {
+    pw = sum_partials(pwp, npw, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->pw = pw;
+  } else {
+    pw = st->pw;
+  }
+  const T alpha = (T)(st->rz[it & 1] / pw);
   double s = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
     x[i] += alpha * p[i];
@@ -747,31 +769,38 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
 }
 
 template <typename T>
-void launch_p_update_t(const T* z, T* p, long long n, const CgState* st, hipStream_t s) {
-  k_p_update<T><<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st);
+void launch_p_update_t(const T* z, T* p, long long n, CgState* st, hipStream_t s, const double* rzp,
+                       int np) {
+  k_p_update<T><<<vec_num_blocks(n), VB, 0, s>>>(z, p, n, st, rzp, np);
 }
-template void launch_p_update_t<double>(const double*, double*, long long, const CgState*, hipStream_t);
-template void launch_p_update_t<float>(const float*, float*, long long, const CgState*, hipStream_t);
+template void launch_p_update_t<double>(const double*, double*, long long, CgState*, hipStream_t,
+                                        const double*, int);
+template void launch_p_update_t<float>(const float*, float*, long long, CgState*, hipStream_t,
+                                       const double*, int);
 
-void launch_p_update(const double* z, double* p, long long n, const CgState* st, hipStream_t s) {
-  launch_p_update_t<double>(z, p, n, st, s);
+void launch_p_update(const double* z, double* p, long long n, CgState* st, hipStream_t s,
+                     const double* rzp, int np) {
+  launch_p_update_t<double>(z, p, n, st, s, rzp, np);
 }
 
 template <typename T>
 int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
-                       unsigned* cnt, double tol, int cg_max, hipStream_t s) {
+                       unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp, int npw) {
   const int nb = vec_num_blocks(n);
-  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, part, cnt, tol, cg_max);
+  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, part, cnt, tol, cg_max, pwp, npw);
   return nb;
 }
 template int launch_cg_update_t<double>(double*, double*, const double*, const double*, long long,
-                                        CgState*, double*, unsigned*, double, int, hipStream_t);
+                                        CgState*, double*, unsigned*, double, int, hipStream_t,
+                                        const double*, int);
 template int launch_cg_update_t<float>(float*, float*, const float*, const float*, long long,
-                                       CgState*, double*, unsigned*, double, int, hipStream_t);
+                                       CgState*, double*, unsigned*, double, int, hipStream_t,
+                                       const double*, int);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
-                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s) {
-  return launch_cg_update_t<double>(x, r, p, w, n, st, part, cnt, tol, cg_max, s);
+                     CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,
+                     const double* pwp, int npw) {
+  return launch_cg_update_t<double>(x, r, p, w, n, st, part, cnt, tol, cg_max, s, pwp, npw);
 }
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {

@@ -95,20 +95,22 @@ __device__ inline void load_cells(const Geo& g, const CL& k, const CL& kref, int
         const int ex = i - 1 + a, ey = j - 1 + b, ez = (DIM == 3) ? kz - 1 + c : 0;
         const bool in = (DIM == 3 || c == 0) && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny &&
                         ez >= 0 && ez < g.nz;
-        T v = T(0);
-        if (in) {
-          const long long e = geo_elem(g, ex, ey, ez);
-          v = T(k(e));
-          if (DK) v -= T(kref(e));
-        }
-        kv[c][b][a] = v;
+        // clamped address, masked by a multiply: no branch around the load, so
+        // all loads of a node are issued before the first wait
+        const long long e = geo_elem(g, min(max(ex, 0), g.nx - 1), min(max(ey, 0), g.ny - 1),
+                                     min(max(ez, 0), g.nz - 1));
+        T v = T(k(e));
+        if (DK) v -= T(kref(e));
+        kv[c][b][a] = v * (in ? T(1) : T(0));
       }
 }
 
+// x at node (i, j, k), 0 outside the grid (clamped load times a 0/1 mask).
 template <typename T>
 __device__ inline T ldx(const Geo& g, const T* __restrict__ x, int i, int j, int k) {
   const bool in = i >= 0 && i < g.nnx && j >= 0 && j < g.nny && k >= 0 && k < g.nnz;
-  return in ? x[geo_node(g, i, j, k)] : T(0);
+  const T v = x[geo_node(g, min(max(i, 0), g.nnx - 1), min(max(j, 0), g.nny - 1), min(max(k, 0), g.nnz - 1))];
+  return v * (in ? T(1) : T(0));
 }
 
 // (K x)_i in 3D from the 3x3 windows of node planes kz-1 (A), kz (B) and kz+1
@@ -1135,8 +1137,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double
 template <int DIM, typename CL>
 __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restrict__ A,
                                              int* __restrict__ status) {
-  __shared__ double colp[128];
-  __shared__ double rowp[128];
+  __shared__ double colp[2][128];   // pivot column / row, double-buffered by step parity
+  __shared__ double rowp[2][128];
   __shared__ double kc[CB_KCAP];
   const int n = (int)g.nn;
   const int t = threadIdx.x;
@@ -1190,30 +1192,35 @@ __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restr
     }
   // Elimination: the slot pa of the pivot is a compile-time index (outer loop
   // unrolled), so the register tile is never indexed at run time. Entries past
-  // n are 0 and stay 0. Same arithmetic per entry as k_coarse_build.
+  // n are 0 and stay 0. Same arithmetic per entry as k_coarse_build. Step p
+  // publishes its pivot row and column in buffer p & 1: the barrier of step
+  // p + 1 orders the reads of step p before the writes of step p + 2, so one
+  // barrier per step suffices.
   int bad = 0;
 #pragma unroll
   for (int pa = 0; pa < 4; ++pa) {
     for (int pr = 0; pr < 32; ++pr) {
       const int p = pa * 32 + pr;
       if (p >= n) break;
+      double* rowb = rowp[p & 1];
+      double* colb = colp[p & 1];
       if (tr == pr) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) rowp[tc + 32 * b] = R[pa][b];
+        for (int b = 0; b < 4; ++b) rowb[tc + 32 * b] = R[pa][b];
       }
       if (tc == pr) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) colp[tr + 32 * a] = R[a][pa];
+        for (int a = 0; a < 4; ++a) colb[tr + 32 * a] = R[a][pa];
       }
       __syncthreads();
-      const double piv = rowp[p];
+      const double piv = rowb[p];
       if (!(piv > 0.0)) bad = 1;
       const double inv = 1.0 / piv;
       double rj[4], ci[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) rj[b] = rowp[tc + 32 * b] * inv;
+      for (int b = 0; b < 4; ++b) rj[b] = rowb[tc + 32 * b] * inv;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) ci[a] = colp[tr + 32 * a];
+      for (int a = 0; a < 4; ++a) ci[a] = colb[tr + 32 * a];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1228,9 +1235,9 @@ __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restr
         for (int a = 0; a < 4; ++a)
           if (tr + 32 * a != p) R[a][pa] = -ci[a] * inv;
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1359,16 +1366,19 @@ __device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf) {
     const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
     const T wi = T((i & 1) ? 0.5 : 1.0), wj = T((j & 1) ? 0.5 : 1.0),
             wk = T((DIM == 3 && (k & 1)) ? 0.5 : 1.0);
-    T s = T(0);
-    for (int c = 0; c < nk; ++c) {
-      T sy = T(0);
-      for (int b = 0; b < nj; ++b) {
-        T sx = T(0);
-        for (int a = 0; a < ni; ++a) sx += xc[geo_node(gc, I0 + a, J0 + b, K0 + c)];
-        sy += wi * sx;
-      }
-      s += wj * sy;
+    // the 2^d coarse corners, the upper ones weighted 0 on even fine indices
+    // (their clamped loads stay in the grid): no branch around the loads
+    const T mi = T(ni - 1), mj = T(nj - 1), mk = T(nk - 1);
+    const int I1 = I0 + ni - 1, J1 = J0 + nj - 1, K1 = K0 + nk - 1;
+    T sc[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int kc = c ? K1 : K0;
+      const T sx0 = xc[geo_node(gc, I0, J0, kc)] + mi * xc[geo_node(gc, I1, J0, kc)];
+      const T sx1 = xc[geo_node(gc, I0, J1, kc)] + mi * xc[geo_node(gc, I1, J1, kc)];
+      sc[c] = wi * sx0 + mj * (wi * sx1);
     }
+    const T s = wj * sc[0] + mk * (wj * sc[1]);
     xf[n] += wk * s;
   }
 }
@@ -1381,8 +1391,21 @@ __device__ void tail_coarse(int n, const double* __restrict__ A, const T* b, T* 
   while (tpr * 2 * n <= TT && tpr < 64) tpr *= 2;
   const int row = threadIdx.x / tpr, sub = threadIdx.x % tpr;
   double s = 0.0;
-  if (row < n)
-    for (int jj = sub; jj < n; jj += tpr) s += A[(long long)jj * n + row] * (double)b[jj];
+  if (row < n) {
+    // eight columns per step, all loaded before the first is used (clamped
+    // indices, weight 0 past the end), summed in column order
+    for (int j0 = sub; j0 < n; j0 += 8 * tpr) {
+      double a[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jj = j0 + u * tpr, jc = jj < n ? jj : n - 1;
+        a[u] = A[(long long)jc * n + row];
+        bv[u] = (double)b[jc] * (jj < n ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u] * bv[u];
+    }
+  }
   for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, MGAR_WAVE);
   if (row < n && sub == 0) x[row] = (T)s;
 }

@@ -48,6 +48,9 @@ SHAPE_KERNEL = {0: "k_stencil_b", 1: "k_stencil_z", 2: "k_stencil_z2"}
 
 
 def roof_kernel(shape):
+    if shape[0] == 2:   # two-row shapes run the CG direction update inside the apply
+        return (f"k_stencil_z2<SM_PAPPLY_DOT> shape {shape} "
+                "(finest grid: p = z + beta p_old stored, q = K p, p.q)")
     return (f"{SHAPE_KERNEL.get(shape[0], '?')}<SM_APPLY_DOT> shape {shape} "
             "(finest grid, q = K p with p.q)")
 

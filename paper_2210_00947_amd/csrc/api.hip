@@ -37,6 +37,7 @@ struct mgar_handle {
   double* Ainv = nullptr;                 // coarsest-grid inverse
   int* dstatus = nullptr;                 // device status word (coarsest pivots)
   double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
+  double* cp2 = nullptr;                  // second CG direction buffer (fused direction update)
   double *pa = nullptr, *pb = nullptr, *pc = nullptr;  // partial-sum buffers
   unsigned* cnt = nullptr;                // last-block counters of in-launch reductions
   long long part_cap = 0;
@@ -179,6 +180,7 @@ double stencil_bytes(const Geo& g, int mode) {
     case SM_RESID: case SM_JACOBI: case SM_JACOBI_DOT: return 8.0 * (3 * N + E);
     case SM_JACOBI0: return 8.0 * (2 * N + E);
     case SM_NEG_DK: return 8.0 * (2 * N + 2 * E);
+    case SM_PAPPLY_DOT: return 8.0 * (4 * N + E);   // z, p_old, cells in; p, K p out
   }
   return 0.0;
 }
@@ -218,6 +220,37 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
   if (nparts) *nparts = np;
   if (timed) {
     h->prof_bytes.push_back(stencil_bytes(g, mode));
+    h->prof_tag.push_back(tag);
+    h->prof_used += 2;
+  }
+  LAUNCHCK();
+  return MGAR_OK;
+}
+
+// Fused direction update + apply + dot on the finest grid with the shape tuned
+// for SM_APPLY_DOT: w = K p into cw, partials into pc. *nparts = -1 (nothing
+// launched) when that shape cannot run it. Timed like stencil_at under the
+// SM_APPLY_DOT profiling bit, with the fused kernel's bytes.
+int papply_at(mgar_handle* h, const double* z, const PFuse& pf, const int* done, int* nparts, int tag) {
+  const Geo& g = h->lv[0].g;
+  const StencilCfg* cfg = &h->scfg[0][0][SM_APPLY_DOT];
+  if (cfg->kind != 2 || !stencil_cfg_valid(g, *cfg)) {
+    *nparts = -1;
+    return MGAR_OK;
+  }
+  const bool timed = (h->prof_mask >> SM_APPLY_DOT) & 1u;
+  if (timed && h->prof_used + 2 > h->prof_ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      HIPCK(hipEventCreate(&e));
+      h->prof_ev.push_back(e);
+    }
+  }
+  *nparts = launch_papply_dot(g, z, h->kcur, h->cw, h->pc, done, h->s, pf, cfg,
+                              timed ? h->prof_ev[h->prof_used] : nullptr,
+                              timed ? h->prof_ev[h->prof_used + 1] : nullptr);
+  if (timed) {
+    h->prof_bytes.push_back(stencil_bytes(g, SM_PAPPLY_DOT));
     h->prof_tag.push_back(tag);
     h->prof_used += 2;
   }
@@ -376,10 +409,19 @@ int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int ta
   if (cls == 0) {
     ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, tag));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
-    launch_p_update(h->cz, h->cp, N, h->st, h->s, h->pb, nz);
+    // direction update fused into the apply where the shape allows it (p in
+    // cp / cp2 by iteration parity), else two launches on cp
+    const PFuse pf{h->st, h->pb, nz, 0, {h->cp, h->cp2}};
     int nw = 0;
-    ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, h->kcur, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, tag));
-    launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s, h->pc, nw);
+    ACK(papply_at(h, h->cz, pf, done, &nw, tag));
+    if (nw < 0) {
+      launch_p_update(h->cz, h->cp, N, h->st, h->s, h->pb, nz);
+      ACK(stencil_at(h, 0, SM_APPLY_DOT, h->cp, h->kcur, nullptr, nullptr, h->cw, 0.0, h->pc, done, &nw, tag));
+      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s, h->pc, nw);
+    } else {
+      launch_cg_update(h->cx, h->cr, h->cp, h->cw, N, h->st, h->pa, nullptr, tol, cg_max, h->s, h->pc, nw,
+                       h->cp2);
+    }
   } else {
     ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
@@ -534,6 +576,9 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
   const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
   const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
   launch_cg_init(h->st, h->pb, nq, h->pa, nr, tol, cg_max, h->s);
+  // the fused direction update reads p_old = cp2 at iteration 0 (weight 0):
+  // keep it finite whatever an earlier solve left there
+  launch_fill_t<double>(h->cp2, N, 0.f, 0.f, h->s);
   LAUNCHCK();
   (void)kfine;   // the iterations apply K(h->kcur)
   h->tag_base = 0;
@@ -672,7 +717,7 @@ void mgar_destroy(mgar_handle* h) {
     if (v.xa) (void)hipFree(v.xa);
     if (v.xb) (void)hipFree(v.xb);
   }
-  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp,
+  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2,
                   h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
@@ -732,6 +777,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->cr, N));
   ACK(dalloc(&h->cz, N));
   ACK(dalloc(&h->cp, N));
+  ACK(dalloc(&h->cp2, N));
   ACK(dalloc(&h->cw, N));
   long long cap = stencil_num_partials(g0);
   {

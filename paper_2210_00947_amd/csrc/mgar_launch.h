@@ -12,6 +12,22 @@ enum StencilMode {
   SM_JACOBI_DOT = 4, // as SM_JACOBI;         partial += b . out
   SM_JACOBI0 = 5,    // out = w D^-1 b        (sweep from a zero guess; x unused)
   SM_NEG_DK = 6,     // out = -(K(k) - K(kref)) x
+  // CG direction update fused into the apply (two-row z-marching shapes only,
+  // FP64): p = z + beta p_old with beta = rz_it / rz_(it-1) (0 at it = 0), rz_it
+  // summed from its block partials; p is stored, out = K p, partial += p . out.
+  // Launched by launch_papply_dot; tuned with the shape of SM_APPLY_DOT.
+  SM_PAPPLY_DOT = 7,
+};
+
+// Operands of SM_PAPPLY_DOT. The direction is double-buffered by iteration
+// parity (p_old in pbuf[(it + 1) & 1], p written to pbuf[it & 1]): neighbouring
+// blocks read p_old in their halo while this block writes p.
+struct PFuse {
+  CgState* st;          // it, rz history; st->rz[it & 1] is stored by block 0
+  const double* rzp;    // block partials of r . z of this iteration
+  int nrz;
+  int pad;
+  double* pbuf[2];
 };
 
 // stencil.hip ----------------------------------------------------------------
@@ -51,6 +67,12 @@ int launch_stencil(const Geo& g, int mode, const double* x, const double* k, con
                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                    const StencilCfg* cfg = nullptr);
 bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
+// SM_PAPPLY_DOT on grid g with launch shape cfg: returns the number of block
+// partials of p . out written to part, or -1 (nothing launched) when cfg is not
+// a two-row z-marching shape (then p is updated and applied by separate launches).
+int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
+                      const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int stencil_num_partials(const Geo& g, const StencilCfg* cfg = nullptr);
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);
@@ -134,7 +156,7 @@ void launch_p_update_t(const T* z, T* p, long long n, CgState* st, hipStream_t s
 template <typename T>
 int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
                        unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp = nullptr,
-                       int npw = 0);
+                       int npw = 0, const T* p_odd = nullptr);
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
@@ -151,12 +173,13 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
                     double tol, int cg_max, hipStream_t s);
 void launch_p_update(const double* z, double* p, long long n, CgState* st, hipStream_t s,
                      const double* rzp = nullptr, int np = 0);
-// x += alpha p, r -= alpha w and partials of ||r||^2; with cnt != null the sum
+// x += alpha p, r -= alpha w and partials of ||r||^2 (p: p_odd on odd
+// iterations when given, the direction buffers of SM_PAPPLY_DOT); with cnt != null the sum
 // is also reduced in the launch, st->it advanced and the stopping test applied
 // by the last block (costs a device-scope fence per block).
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
                      CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,
-                     const double* pwp = nullptr, int npw = 0);
+                     const double* pwp = nullptr, int npw = 0, const double* p_odd = nullptr);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 template <typename T>
 void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s);

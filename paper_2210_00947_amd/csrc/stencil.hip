@@ -12,6 +12,7 @@
 // N-vector they write is set to 0 there; nodes outside the grid only occur in
 // cells outside the grid, whose conductivity is taken as 0.
 #include <algorithm>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -401,7 +402,7 @@ template <int MODE, int ZD, typename T, typename CL>
 __global__ __launch_bounds__(ZT) __attribute__((amdgpu_waves_per_eu((ZD == 1 || sizeof(T) == 4) ? 4 : 3))) void k_stencil_z(
     Geo g, int TXW, int TYH, int ntx, int nty, int KZ, const T* __restrict__ x, CL k, CL kref,
     const T* __restrict__ b, T* __restrict__ out, T omega, double* __restrict__ part,
-    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout) {
+    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout, PFuse) {
   if (done && *done) return;
   using E = typename CL::E;
   constexpr bool DK = (MODE == SM_NEG_DK);
@@ -596,19 +597,35 @@ template <int MODE, int ZD, typename T, typename CL>
 __global__ __launch_bounds__(ZT) void k_stencil_z2(
     Geo g, int TXW, int TYH, int ntx, int nty, int KZ, const T* __restrict__ x, CL k, CL kref,
     const T* __restrict__ b, T* __restrict__ out, T omega, double* __restrict__ part,
-    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout) {
+    const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout, PFuse fu) {
   if (done && *done) return;
   using E = typename CL::E;
+  constexpr bool PU = (MODE == SM_PAPPLY_DOT);   // x holds z; staged value z + beta p_old
   constexpr bool DK = (MODE == SM_NEG_DK);
   constexpr bool NEEDX = (MODE != SM_JACOBI0);
   constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
                           MODE == SM_JACOBI0);
-  constexpr bool DOT = (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT);
+  constexpr bool DOT = (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT || PU);
   constexpr bool CMASK = sizeof(E) == 2;
   constexpr unsigned TS = sizeof(T), ES = sizeof(E);
   __shared__ T Xs[2][XCAP2];
   __shared__ T Cs[2][CCAP2];
   __shared__ double sh[ZT / MGAR_WAVE];
+  // direction update: beta from the r.z partials (every block sums them in the
+  // same order, so all hold the same value) and the stored r.z history
+  T beta = T(0);
+  const T* pold = nullptr;
+  T* pnew = nullptr;
+  if (PU) {
+    const int it = fu.st->it;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < fu.nrz; i += ZT) v += fu.rzp[i];
+    const double rz = block_sum(v, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) fu.st->rz[it & 1] = rz;
+    beta = (T)((it == 0) ? 0.0 : rz / fu.st->rz[(it - 1) & 1]);
+    pold = reinterpret_cast<const T*>(fu.pbuf[(it + 1) & 1]);
+    pnew = reinterpret_cast<T*>(fu.pbuf[it & 1]);
+  }
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int nxy = ntx * nty;
   const int txy = t % nxy, zc = t / nxy;
@@ -629,6 +646,8 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   const __amdgpu_buffer_rsrc_t ro = zrsrc(out, g.nn * TS);
   const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
   const __amdgpu_buffer_rsrc_t rkr = zrsrc(kref.p, g.ne * ES);
+  const __amdgpu_buffer_rsrc_t rp = zrsrc(PU ? pold : x, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rpn = zrsrc(PU ? pnew : out, g.nn * TS);
   const unsigned own0 = act0 ? (unsigned)(i + g.nnx * j) * TS : ZOOB;
   const unsigned own1 = act1 ? (unsigned)(i + g.nnx * (j + 1)) * TS : ZOOB;
   const unsigned xs0 = zslot_off(i0, j0, XW, XN, tid, g.nnx, g.nny, TS);
@@ -646,18 +665,23 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
 #define ZCV(e, er) (DK ? T(k.value(e)) - T(kref.value(er)) : T(k.value(e)))
 #define ZCM(e, er, ok) (CMASK ? ZCV(e, er) * ((ok) ? T(1) : T(0)) : ZCV(e, er))
 
+  // p_old of a slot and plane (direction update only); staged x = z + beta p_old
+#define ZP(so, p) (PU ? zbload<T>(rp, zplane((so), (p), g.nnz, plb)) : T(0))
+#define ZXP(so, p) (PU ? ZX(so, p) + beta * ZP(so, p) : ZX(so, p))
+  constexpr int ZQP = PU ? ZD : 1;
   T qx0[ZD], qx1[ZD], qx2[ZD], qb0[ZD], qb1[ZD];
+  T qp0[ZQP], qp1[ZQP], qp2[ZQP];
   E qc0[ZD], qc1[ZD], qr0[ZD], qr1[ZD];
   T W0[4][3], W1[4][3], W2[4][3], V0[3][2], V1[3][2];
 
   {
     const unsigned c0 = zplane(cs0, k0 - 1, g.nz, cplb), c1 = zplane(cs1, k0 - 1, g.nz, cplb);
-    Xs[0][tid] = ZX(xs0, k0 - 1);
-    Xs[1][tid] = ZX(xs0, k0);
-    Xs[0][tid + ZT] = ZX(xs1, k0 - 1);
-    Xs[1][tid + ZT] = ZX(xs1, k0);
-    Xs[0][tid + 2 * ZT] = ZX(xs2, k0 - 1);
-    Xs[1][tid + 2 * ZT] = ZX(xs2, k0);
+    Xs[0][tid] = ZXP(xs0, k0 - 1);
+    Xs[1][tid] = ZXP(xs0, k0);
+    Xs[0][tid + ZT] = ZXP(xs1, k0 - 1);
+    Xs[1][tid + ZT] = ZXP(xs1, k0);
+    Xs[0][tid + 2 * ZT] = ZXP(xs2, k0 - 1);
+    Xs[1][tid + 2 * ZT] = ZXP(xs2, k0);
     const E e0 = zbload<E>(rk, c0), e1 = zbload<E>(rk, c1);
     const E r0 = DK ? zbload<E>(rkr, c0) : E(0), r1 = DK ? zbload<E>(rkr, c1) : E(0);
     Cs[0][tid] = ZCM(e0, r0, c0 < ZOOB);
@@ -668,6 +692,11 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     qx0[d] = ZX(xs0, k0 + 1 + d);
     qx1[d] = ZX(xs1, k0 + 1 + d);
     qx2[d] = ZX(xs2, k0 + 1 + d);
+    if (PU) {
+      qp0[d] = ZP(xs0, k0 + 1 + d);
+      qp1[d] = ZP(xs1, k0 + 1 + d);
+      qp2[d] = ZP(xs2, k0 + 1 + d);
+    }
     const unsigned c0 = zplane(cs0, k0 + d, g.nz, cplb), c1 = zplane(cs1, k0 + d, g.nz, cplb);
     qc0[d] = zbload<E>(rk, c0);
     qc1[d] = zbload<E>(rk, c1);
@@ -706,27 +735,29 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     const T xcv = NEEDX ? B[R0 + 1][1] : T(0);                                               \
     const T diag = hc * ks;                                                                  \
     T r = T(0);                                                                              \
-    if (MODE == SM_APPLY || MODE == SM_APPLY_DOT) r = y;                                     \
+    if (MODE == SM_APPLY || MODE == SM_APPLY_DOT || PU) r = y;                               \
     else if (MODE == SM_RESID) r = bn - y;                                                   \
     else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) r = xcv + omega * (bn - y) / diag;  \
     else if (MODE == SM_JACOBI0) r = omega * bn / diag;                                      \
     else if (MODE == SM_NEG_DK) r = -y;                                                      \
     r = (colfix && kk >= g.f0z && kk <= g.f1z) ? T(0) : r;                                   \
-    if (MODE == SM_APPLY_DOT) dotv += act ? (double)xcv * (double)r : 0.0;                   \
+    if (MODE == SM_APPLY_DOT || PU) dotv += act ? (double)xcv * (double)r : 0.0;             \
     if (MODE == SM_JACOBI_DOT) dotv += act ? (double)bn * (double)r : 0.0;                   \
     zbstore(r, ro, own + (unsigned)kk * plb);                                                \
+    if (PU) zbstore(xcv, rpn, own + (unsigned)kk * plb);                                     \
   }
 
 #define ZSTEP2(A, B, C, CA, CB, s)                                                           \
   {                                                                                          \
-    Xs[s][tid] = qx0[0];                                                                     \
-    Xs[s][tid + ZT] = qx1[0];                                                                \
-    Xs[s][tid + 2 * ZT] = qx2[0];                                                            \
+    Xs[s][tid] = PU ? qx0[0] + beta * qp0[0] : qx0[0];                                       \
+    Xs[s][tid + ZT] = PU ? qx1[0] + beta * qp1[0] : qx1[0];                                  \
+    Xs[s][tid + 2 * ZT] = PU ? qx2[0] + beta * qp2[0] : qx2[0];                              \
     Cs[s][tid] = ZCM(qc0[0], qr0[0], cs0 < ZOOB && kk < g.nz);                               \
     Cs[s][tid + ZT] = ZCM(qc1[0], qr1[0], cs1 < ZOOB && kk < g.nz);                          \
     const T bn0 = qb0[0], bn1 = qb1[0];                                                      \
     _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
       qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1]; qx2[d] = qx2[d + 1];                         \
+      if (PU) { qp0[d] = qp0[d + 1]; qp1[d] = qp1[d + 1]; qp2[d] = qp2[d + 1]; }              \
       qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
       qr0[d] = qr0[d + 1]; qr1[d] = qr1[d + 1];                                              \
       qb0[d] = qb0[d + 1]; qb1[d] = qb1[d + 1];                                              \
@@ -744,6 +775,11 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
       qx0[ZD - 1] = ZX(xs0, pf + 1);                                                         \
       qx1[ZD - 1] = ZX(xs1, pf + 1);                                                         \
       qx2[ZD - 1] = ZX(xs2, pf + 1);                                                         \
+      if (PU) {                                                                              \
+        qp0[ZD - 1] = ZP(xs0, pf + 1);                                                       \
+        qp1[ZD - 1] = ZP(xs1, pf + 1);                                                       \
+        qp2[ZD - 1] = ZP(xs2, pf + 1);                                                       \
+      }                                                                                      \
       const unsigned c0 = zplane(cs0, pf, g.nz, cplb), c1 = zplane(cs1, pf, g.nz, cplb);     \
       qc0[ZD - 1] = zbload<E>(rk, c0);                                                       \
       qc1[ZD - 1] = zbload<E>(rk, c1);                                                       \
@@ -773,6 +809,8 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   if (kk < k1) ZSTEP2(W1, W2, W0, V0, V1, 0)
 #undef ZSTEP2
 #undef ZNODE
+#undef ZXP
+#undef ZP
 #undef ZX
 #undef ZB
 #undef ZCV
@@ -1384,26 +1422,45 @@ __device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf) {
 }
 
 // x = A^-1 b with A symmetric (n <= 1024): `tpr` threads per row, each summing
-// a strided share of the columns, combined by a wave shuffle tree.
-template <typename T>
-__device__ void tail_coarse(int n, const double* __restrict__ A, const T* b, T* x) {
+// a strided share of the columns (in column order), combined by a wave shuffle
+// tree. For n <= 128 a thread's share is at most CPRE columns, which it loads
+// into registers at the start of the tail (CoarsePre), so the global-memory
+// latency of A overlaps the down-sweep instead of following it.
+constexpr int CPRE = 16;
+struct CoarsePre {
+  int n, tpr, row, sub;
+  double a[CPRE];
+};
+
+__device__ inline void tail_coarse_prefetch(int n, const double* __restrict__ A, CoarsePre& P) {
   int tpr = 1;
   while (tpr * 2 * n <= TT && tpr < 64) tpr *= 2;
-  const int row = threadIdx.x / tpr, sub = threadIdx.x % tpr;
+  P.n = n;
+  P.tpr = tpr;
+  P.row = threadIdx.x / tpr;
+  P.sub = threadIdx.x % tpr;
+  if (n > 128) return;
+  const int rc = min(P.row, n - 1);
+#pragma unroll
+  for (int u = 0; u < CPRE; ++u) {
+    const int jj = P.sub + u * tpr, jc = min(jj, n - 1);
+    P.a[u] = A[(long long)jc * n + rc];   // clamped: in range; columns past n get weight 0 below
+  }
+}
+
+template <typename T>
+__device__ void tail_coarse(const CoarsePre& P, const double* __restrict__ A, const T* b, T* x) {
+  const int n = P.n, tpr = P.tpr, row = P.row, sub = P.sub;
   double s = 0.0;
   if (row < n) {
-    // eight columns per step, all loaded before the first is used (clamped
-    // indices, weight 0 past the end), summed in column order
-    for (int j0 = sub; j0 < n; j0 += 8 * tpr) {
-      double a[8], bv[8];
+    if (n <= 128) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int jj = j0 + u * tpr, jc = jj < n ? jj : n - 1;
-        a[u] = A[(long long)jc * n + row];
-        bv[u] = (double)b[jc] * (jj < n ? 1.0 : 0.0);
+      for (int u = 0; u < CPRE; ++u) {
+        const int jj = sub + u * tpr, jc = min(jj, n - 1);
+        s += P.a[u] * ((double)b[jc] * (jj < n ? 1.0 : 0.0));
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s += a[u] * bv[u];
+    } else {
+      for (int jj = sub; jj < n; jj += tpr) s += A[(long long)jj * n + row] * (double)b[jj];
     }
   }
   for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, MGAR_WAVE);
@@ -1419,6 +1476,9 @@ __device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin,
   for (int l = 0; l < nl; ++l)
     for (int e = threadIdx.x; e < (int)TS.g[l].ne; e += TT) lds[TS.off_k[l] + e] = static_cast<const T*>(TS.k[l])[e];
   for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) lds[TS.off_b[0] + n] = bin[n];
+  // issued after the loads above, so waiting for those does not wait for these
+  CoarsePre cp;
+  tail_coarse_prefetch((int)TS.g[nl - 1].nn, Ainv, cp);
   __syncthreads();
   for (int l = 0; l + 1 < nl; ++l) {
     const Geo& g = TS.g[l];
@@ -1433,7 +1493,7 @@ __device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin,
     tail_restrict<DIM, T>(g, TS.g[l + 1], xb, lds + TS.off_b[l + 1]);
     __syncthreads();
   }
-  tail_coarse((int)TS.g[nl - 1].nn, Ainv, lds + TS.off_b[nl - 1], lds + TS.off_xa[nl - 1]);
+  tail_coarse(cp, Ainv, lds + TS.off_b[nl - 1], lds + TS.off_xa[nl - 1]);
   __syncthreads();
   const T* xfin = lds + TS.off_xa[nl - 1];
   for (int l = nl - 2; l >= 0; --l) {
@@ -1529,7 +1589,7 @@ constexpr auto zmarch_kernel() {
 template <int ZD, bool TWO, typename T, typename CL>
 void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, CL k, CL kref,
                    const T* b, T* out, T omega, double* part, const int* done, unsigned* cnt,
-                   double* rout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                   double* rout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, const PFuse& fu = PFuse{}) {
   const int nb = z.ntx * z.nty * z.nzc;
   // With events, the launch goes through hipExtLaunchKernelGGL, which records
   // them at the start and end of the kernel itself (no dispatch latency).
@@ -1538,10 +1598,10 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
   do {                                                                                           \
     if (ev0)                                                                                     \
       hipExtLaunchKernelGGL(ZKER(M), dim3(nb), dim3(ZT), 0, s, ev0, ev1, 0, g, z.TXW, z.TYH,     \
-                            z.ntx, z.nty, kz, x, k, kref, b, out, omega, part, done, cnt, rout); \
+                            z.ntx, z.nty, kz, x, k, kref, b, out, omega, part, done, cnt, rout, fu); \
     else                                                                                         \
       hipLaunchKernelGGL(ZKER(M), dim3(nb), dim3(ZT), 0, s, g, z.TXW, z.TYH, z.ntx, z.nty, kz, x, \
-                         k, kref, b, out, omega, part, done, cnt, rout);                         \
+                         k, kref, b, out, omega, part, done, cnt, rout, fu);                     \
   } while (0)
   switch (mode) {
     case SM_APPLY: ZCALL(SM_APPLY); break;
@@ -1551,6 +1611,9 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
     case SM_JACOBI_DOT: ZCALL(SM_JACOBI_DOT); break;
     case SM_JACOBI0: ZCALL(SM_JACOBI0); break;
     case SM_NEG_DK: ZCALL(SM_NEG_DK); break;
+    case SM_PAPPLY_DOT:
+      if constexpr (TWO && std::is_same_v<T, double>) ZCALL(SM_PAPPLY_DOT);
+      break;
   }
 #undef ZCALL
 #undef ZKER
@@ -1750,6 +1813,22 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg) {
   (void)g;
   (void)cfg;
   return true;   // every stencil launch path takes kernel start/end events
+}
+
+int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
+                      const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
+                      hipEvent_t ev0, hipEvent_t ev1) {
+  const StencilCfg c = resolve_cfg(g, cfg);
+  if (c.kind != 2) return -1;
+  const ZShape z2 = zmarch_shape(g, c);
+  const CellD kc{k};
+  if (c.zd == 2)
+    zmarch_launch<2, true, double, CellD>(g, z2, c.kz, SM_PAPPLY_DOT, z, kc, kc, nullptr, out, 0.0, part,
+                                          done, nullptr, nullptr, s, ev0, ev1, pf);
+  else
+    zmarch_launch<1, true, double, CellD>(g, z2, c.kz, SM_PAPPLY_DOT, z, kc, kc, nullptr, out, 0.0, part,
+                                          done, nullptr, nullptr, s, ev0, ev1, pf);
+  return z2.ntx * z2.nty * z2.nzc;
 }
 
 template <typename T, typename CL>

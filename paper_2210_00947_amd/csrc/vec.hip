@@ -95,17 +95,19 @@ __global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __r
 // iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max). With pwp set, p . w
 // is first summed from its npw block partials by every block (same order in
 // each) and block 0 stores it to st->pw; otherwise st->pw already holds it.
+// With p_odd set, the direction of an odd iteration is read from p_odd.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
-                                                  const T* __restrict__ p,
+                                                  const T* __restrict__ p_even,
                                                   const T* __restrict__ w, long long n,
                                                   CgState* __restrict__ st,
                                                   double* __restrict__ part,
                                                   unsigned* __restrict__ cnt, double tol,
                                                   int cg_max, const double* __restrict__ pwp,
-                                                  int npw) {
+                                                  int npw, const T* __restrict__ p_odd) {
   if (st->done) return;
   const int it = st->it;
+  const T* __restrict__ p = (p_odd && (it & 1)) ? p_odd : p_even;
   __shared__ double sh[VB / MGAR_WAVE];
   double pw;
   if (pwp) {
@@ -785,22 +787,23 @@ void launch_p_update(const double* z, double* p, long long n, CgState* st, hipSt
 
 template <typename T>
 int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
-                       unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp, int npw) {
+                       unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp, int npw,
+                       const T* p_odd) {
   const int nb = vec_num_blocks(n);
-  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, part, cnt, tol, cg_max, pwp, npw);
+  k_cg_update<T><<<nb, VB, 0, s>>>(x, r, p, w, n, st, part, cnt, tol, cg_max, pwp, npw, p_odd);
   return nb;
 }
 template int launch_cg_update_t<double>(double*, double*, const double*, const double*, long long,
                                         CgState*, double*, unsigned*, double, int, hipStream_t,
-                                        const double*, int);
+                                        const double*, int, const double*);
 template int launch_cg_update_t<float>(float*, float*, const float*, const float*, long long,
                                        CgState*, double*, unsigned*, double, int, hipStream_t,
-                                       const double*, int);
+                                       const double*, int, const float*);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
                      CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,
-                     const double* pwp, int npw) {
-  return launch_cg_update_t<double>(x, r, p, w, n, st, part, cnt, tol, cg_max, s, pwp, npw);
+                     const double* pwp, int npw, const double* p_odd) {
+  return launch_cg_update_t<double>(x, r, p, w, n, st, part, cnt, tol, cg_max, s, pwp, npw, p_odd);
 }
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {

@@ -129,3 +129,33 @@ def test_solves_with_two_row_shapes_match_oracle(precision):
     if precision == 0:
         assert st["cg_iters"] == st0.cg_iters
         assert sa["path"] == st1.path and sa["cg_iters"] == st1.cg_iters
+
+
+@pytest.mark.parametrize("prob", [W.tiny_3d(32, 32, 32, 4), W.tiny_3d(48, 32, 16, 3)],
+                         ids=["32x32x32", "48x32x16"])
+def test_fused_direction_update_matches_separate_launches(prob):
+    """A two-row shape for the finest apply + dot runs the CG direction update
+    inside the apply (double-buffered direction); any other shape runs the
+    update and the apply as two launches. Same iterations, same temperature
+    (to the summation order of the dot partials), both on the oracle."""
+    import torch
+    s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
+    x0 = W.random_density(prob.nelem, 41, 0.1, 0.9)
+    x1 = np.clip(x0 + 0.03 * W.random_vector(prob.nelem, 42), 0, 1)
+    t0, st0 = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    t1, st1 = s.mgar(x1, t0, 1e-8)
+    out = {}
+    for name, shape in (("fused", [2, 6, 1, 1]), ("separate", [1, 6, 1, 1])):
+        h = handle(prob)
+        h.mgar_tune_set(0, 0, 1, shape)
+        q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+        h.mgar_load_vector(dev(W.element_source(prob)), q)
+        T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+        T1 = torch.empty_like(T0)
+        a = h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+        b = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+        assert a["cg_iters"] == st0.cg_iters and b["cg_iters"] == st1.cg_iters and b["path"] == st1.path
+        assert rel_l2(host(T0), t0) < 1e-8 and rel_l2(host(T1), t1) < 1e-8
+        out[name] = (host(T0), host(T1))
+    for u, v in zip(out["fused"], out["separate"]):
+        assert rel_l2(u, v) < 1e-12

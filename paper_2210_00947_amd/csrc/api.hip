@@ -38,6 +38,8 @@ struct mgar_handle {
   int* dstatus = nullptr;                 // device status word (coarsest pivots)
   double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
   double* cp2 = nullptr;                  // second CG direction buffer (fused direction update)
+  double* dg0 = nullptr;                  // diagonal of K0 on the finest grid (3D, FP64 hierarchy)
+  bool dg0_valid = false;
   double *pa = nullptr, *pb = nullptr, *pc = nullptr;  // partial-sum buffers
   unsigned* cnt = nullptr;                // last-block counters of in-launch reductions
   long long part_cap = 0;
@@ -165,6 +167,8 @@ int validate(const mgar_params* p) {
 // ------------------------------------------------------------------ MG
 
 int build_hierarchy(mgar_handle* h) {
+  if (h->dg0) launch_diag(h->lv[0].g, h->lv[0].k, h->dg0, h->s);
+  h->dg0_valid = h->dg0 != nullptr;
   for (int l = 1; l < h->L; ++l) launch_coarsen(h->lv[l - 1].g, h->lv[l].g, h->lv[l - 1].k, h->lv[l].k, h->s);
   HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->s));
   launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->s);
@@ -296,10 +300,15 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
   for (int l = 0; l < lt; ++l) {
     LevelBuf& v = h->lv[l];
     const double* b = (l == 0) ? b0 : v.b;
+    // finest grid from zero: first sweep and residual in one launch where the
+    // residual's shape allows it
+    const bool fused = l == 0 && !x0 && h->dg0_valid && !((h->prof_mask >> SM_RESID) & 1u) &&
+                       launch_j0resid(v.g, b, v.k, h->dg0, v.xa, h->rtmp, w, done, h->s,
+                                      &h->scfg[0][0][SM_RESID]);
     if (l == 0 && x0) ACK(stencil_at(h, l, SM_JACOBI, x0, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
-    else if (!presmoothed)
+    else if (!presmoothed && !fused)
       ACK(stencil_at(h, l, SM_JACOBI0, nullptr, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
-    ACK(stencil_at(h, l, SM_RESID, v.xa, v.k, nullptr, b, h->rtmp, w, nullptr, done, nullptr, tag));
+    if (!fused) ACK(stencil_at(h, l, SM_RESID, v.xa, v.k, nullptr, b, h->rtmp, w, nullptr, done, nullptr, tag));
     LevelBuf& c = h->lv[l + 1];
     presmoothed = l + 1 < lt && launch_restrict_j0_t<double, CellD>(v.g, c.g, h->rtmp, CellD{c.k}, c.b, c.xa,
                                                                         w, done, h->s);
@@ -351,6 +360,7 @@ int stencil32(mgar_handle* h, int level, int mode, const float* x, const float* 
 // and the coarsest inverse in FP64.
 int build_hierarchy32(mgar_handle* h) {
   const int L = h->L;
+  h->dg0_valid = false;   // lv[0].k no longer describes the preconditioner's K0
   launch_copy_u16(h->dens, h->dens0, h->E, h->s);
   const CellB k0{h->dens0, h->kmin_f, h->kdiff_f};
   if (L >= 2) launch_coarsen_t<CellB, float>(h->lv[0].g, h->lv[1].g, k0, h->kf[1], h->s);
@@ -717,7 +727,7 @@ void mgar_destroy(mgar_handle* h) {
     if (v.xa) (void)hipFree(v.xa);
     if (v.xb) (void)hipFree(v.xb);
   }
-  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2,
+  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2, h->dg0,
                   h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
@@ -778,6 +788,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->cz, N));
   ACK(dalloc(&h->cp, N));
   ACK(dalloc(&h->cp2, N));
+  if (g0.dim == 3) ACK(dalloc(&h->dg0, N));
   ACK(dalloc(&h->cw, N));
   long long cap = stencil_num_partials(g0);
   {

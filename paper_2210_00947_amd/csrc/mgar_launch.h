@@ -17,17 +17,26 @@ enum StencilMode {
   // summed from its block partials; p is stored, out = K p, partial += p . out.
   // Launched by launch_papply_dot; tuned with the shape of SM_APPLY_DOT.
   SM_PAPPLY_DOT = 7,
+  // First V-cycle sweep fused into the residual (two-row z-marching shapes
+  // only, FP64): x = w b / diag(K) is formed where staged (diag precomputed),
+  // stored to xout, and out = b - K x. Launched by launch_j0resid; tuned with
+  // the shape of SM_RESID.
+  SM_J0RESID = 8,
 };
 
-// Operands of SM_PAPPLY_DOT. The direction is double-buffered by iteration
-// parity (p_old in pbuf[(it + 1) & 1], p written to pbuf[it & 1]): neighbouring
-// blocks read p_old in their halo while this block writes p.
+// Extra operands of the fused modes.
+// SM_PAPPLY_DOT: the direction is double-buffered by iteration parity (p_old in
+// pbuf[(it + 1) & 1], p written to pbuf[it & 1]): neighbouring blocks read
+// p_old in their halo while this block writes p.
+// SM_J0RESID: diag = diagonal of K per node, xout receives the sweep.
 struct PFuse {
   CgState* st;          // it, rz history; st->rz[it & 1] is stored by block 0
   const double* rzp;    // block partials of r . z of this iteration
   int nrz;
   int pad;
   double* pbuf[2];
+  const double* diag;
+  double* xout;
 };
 
 // stencil.hip ----------------------------------------------------------------
@@ -73,6 +82,14 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
 int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
                       const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// SM_J0RESID on grid g (3D) with launch shape cfg (its queue depth is always 1):
+// xout = w b / diag, out = b - K xout. Returns false (nothing launched) when cfg
+// is not a two-row z-marching shape.
+bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
+                    double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg);
+// diag[n] = diagonal of K at node n (h/3 times the sum of its cells, summed in the
+// order of the node formula), 3D; 0 outside the grid is never written.
+void launch_diag(const Geo& g, const double* k, double* diag, hipStream_t s);
 int stencil_num_partials(const Geo& g, const StencilCfg* cfg = nullptr);
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);

@@ -12,6 +12,7 @@
 // N-vector they write is set to 0 there; nodes outside the grid only occur in
 // cells outside the grid, whose conductivity is taken as 0.
 #include <algorithm>
+#include <cfloat>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -601,10 +602,12 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   if (done && *done) return;
   using E = typename CL::E;
   constexpr bool PU = (MODE == SM_PAPPLY_DOT);   // x holds z; staged value z + beta p_old
+  constexpr bool J0R = (MODE == SM_J0RESID);     // x holds b; staged value w b / diag
+  constexpr bool XF = PU || J0R;                 // staged x formed from two inputs
   constexpr bool DK = (MODE == SM_NEG_DK);
   constexpr bool NEEDX = (MODE != SM_JACOBI0);
   constexpr bool NEEDB = (MODE == SM_RESID || MODE == SM_JACOBI || MODE == SM_JACOBI_DOT ||
-                          MODE == SM_JACOBI0);
+                          MODE == SM_JACOBI0 || J0R);
   constexpr bool DOT = (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT || PU);
   constexpr bool CMASK = sizeof(E) == 2;
   constexpr unsigned TS = sizeof(T), ES = sizeof(E);
@@ -646,8 +649,12 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   const __amdgpu_buffer_rsrc_t ro = zrsrc(out, g.nn * TS);
   const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
   const __amdgpu_buffer_rsrc_t rkr = zrsrc(kref.p, g.ne * ES);
-  const __amdgpu_buffer_rsrc_t rp = zrsrc(PU ? pold : x, g.nn * TS);
-  const __amdgpu_buffer_rsrc_t rpn = zrsrc(PU ? pnew : out, g.nn * TS);
+  if (J0R) {
+    pold = reinterpret_cast<const T*>(fu.diag);
+    pnew = reinterpret_cast<T*>(fu.xout);
+  }
+  const __amdgpu_buffer_rsrc_t rp = zrsrc(XF ? pold : x, g.nn * TS);
+  const __amdgpu_buffer_rsrc_t rpn = zrsrc(XF ? pnew : out, g.nn * TS);
   const unsigned own0 = act0 ? (unsigned)(i + g.nnx * j) * TS : ZOOB;
   const unsigned own1 = act1 ? (unsigned)(i + g.nnx * (j + 1)) * TS : ZOOB;
   const unsigned xs0 = zslot_off(i0, j0, XW, XN, tid, g.nnx, g.nny, TS);
@@ -665,10 +672,13 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
 #define ZCV(e, er) (DK ? T(k.value(e)) - T(kref.value(er)) : T(k.value(e)))
 #define ZCM(e, er, ok) (CMASK ? ZCV(e, er) * ((ok) ? T(1) : T(0)) : ZCV(e, er))
 
-  // p_old of a slot and plane (direction update only); staged x = z + beta p_old
-#define ZP(so, p) (PU ? zbload<T>(rp, zplane((so), (p), g.nnz, plb)) : T(0))
-#define ZXP(so, p) (PU ? ZX(so, p) + beta * ZP(so, p) : ZX(so, p))
-  constexpr int ZQP = PU ? ZD : 1;
+  // second input of a fused mode at a slot and plane (p_old, or the diagonal),
+  // and the staged value formed from the pair (u = x input, v = second input).
+  // A slot outside the grid loads 0 for both; max(v, DBL_MIN) keeps its sweep 0.
+#define ZP(so, p) (XF ? zbload<T>(rp, zplane((so), (p), g.nnz, plb)) : T(0))
+#define ZFORM(u, v) (PU ? (u) + beta * (v) : J0R ? omega * (u) / fmax((v), T(DBL_MIN)) : (u))
+#define ZXP(so, p) (XF ? ZFORM(ZX(so, p), ZP(so, p)) : ZX(so, p))
+  constexpr int ZQP = XF ? ZD : 1;
   T qx0[ZD], qx1[ZD], qx2[ZD], qb0[ZD], qb1[ZD];
   T qp0[ZQP], qp1[ZQP], qp2[ZQP];
   E qc0[ZD], qc1[ZD], qr0[ZD], qr1[ZD];
@@ -692,7 +702,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     qx0[d] = ZX(xs0, k0 + 1 + d);
     qx1[d] = ZX(xs1, k0 + 1 + d);
     qx2[d] = ZX(xs2, k0 + 1 + d);
-    if (PU) {
+    if (XF) {
       qp0[d] = ZP(xs0, k0 + 1 + d);
       qp1[d] = ZP(xs1, k0 + 1 + d);
       qp2[d] = ZP(xs2, k0 + 1 + d);
@@ -736,7 +746,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     const T diag = hc * ks;                                                                  \
     T r = T(0);                                                                              \
     if (MODE == SM_APPLY || MODE == SM_APPLY_DOT || PU) r = y;                               \
-    else if (MODE == SM_RESID) r = bn - y;                                                   \
+    else if (MODE == SM_RESID || J0R) r = bn - y;                                            \
     else if (MODE == SM_JACOBI || MODE == SM_JACOBI_DOT) r = xcv + omega * (bn - y) / diag;  \
     else if (MODE == SM_JACOBI0) r = omega * bn / diag;                                      \
     else if (MODE == SM_NEG_DK) r = -y;                                                      \
@@ -744,20 +754,20 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     if (MODE == SM_APPLY_DOT || PU) dotv += act ? (double)xcv * (double)r : 0.0;             \
     if (MODE == SM_JACOBI_DOT) dotv += act ? (double)bn * (double)r : 0.0;                   \
     zbstore(r, ro, own + (unsigned)kk * plb);                                                \
-    if (PU) zbstore(xcv, rpn, own + (unsigned)kk * plb);                                     \
+    if (XF) zbstore(xcv, rpn, own + (unsigned)kk * plb);                                     \
   }
 
 #define ZSTEP2(A, B, C, CA, CB, s)                                                           \
   {                                                                                          \
-    Xs[s][tid] = PU ? qx0[0] + beta * qp0[0] : qx0[0];                                       \
-    Xs[s][tid + ZT] = PU ? qx1[0] + beta * qp1[0] : qx1[0];                                  \
-    Xs[s][tid + 2 * ZT] = PU ? qx2[0] + beta * qp2[0] : qx2[0];                              \
+    Xs[s][tid] = XF ? ZFORM(qx0[0], qp0[0]) : qx0[0];                                        \
+    Xs[s][tid + ZT] = XF ? ZFORM(qx1[0], qp1[0]) : qx1[0];                                   \
+    Xs[s][tid + 2 * ZT] = XF ? ZFORM(qx2[0], qp2[0]) : qx2[0];                               \
     Cs[s][tid] = ZCM(qc0[0], qr0[0], cs0 < ZOOB && kk < g.nz);                               \
     Cs[s][tid + ZT] = ZCM(qc1[0], qr1[0], cs1 < ZOOB && kk < g.nz);                          \
     const T bn0 = qb0[0], bn1 = qb1[0];                                                      \
     _Pragma("unroll") for (int d = 0; d + 1 < ZD; ++d) {                                     \
       qx0[d] = qx0[d + 1]; qx1[d] = qx1[d + 1]; qx2[d] = qx2[d + 1];                         \
-      if (PU) { qp0[d] = qp0[d + 1]; qp1[d] = qp1[d + 1]; qp2[d] = qp2[d + 1]; }              \
+      if (XF) { qp0[d] = qp0[d + 1]; qp1[d] = qp1[d + 1]; qp2[d] = qp2[d + 1]; }              \
       qc0[d] = qc0[d + 1]; qc1[d] = qc1[d + 1];                                              \
       qr0[d] = qr0[d + 1]; qr1[d] = qr1[d + 1];                                              \
       qb0[d] = qb0[d + 1]; qb1[d] = qb1[d + 1];                                              \
@@ -775,7 +785,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
       qx0[ZD - 1] = ZX(xs0, pf + 1);                                                         \
       qx1[ZD - 1] = ZX(xs1, pf + 1);                                                         \
       qx2[ZD - 1] = ZX(xs2, pf + 1);                                                         \
-      if (PU) {                                                                              \
+      if (XF) {                                                                              \
         qp0[ZD - 1] = ZP(xs0, pf + 1);                                                       \
         qp1[ZD - 1] = ZP(xs1, pf + 1);                                                       \
         qp2[ZD - 1] = ZP(xs2, pf + 1);                                                       \
@@ -810,6 +820,7 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
 #undef ZSTEP2
 #undef ZNODE
 #undef ZXP
+#undef ZFORM
 #undef ZP
 #undef ZX
 #undef ZB
@@ -919,6 +930,27 @@ __global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T
                                                          const int* __restrict__ done) {
   if (done && *done) return;
   restrict_b_point<DIM, T>(gf, gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), rf, rc);
+}
+
+// Diagonal of K per node (3D): h/3 times the sum of the node's 8 cells, in the
+// association of the node formula. Used by the fused first sweep + residual.
+__global__ __launch_bounds__(TBX* TBY) void k_diag(Geo g, const double* __restrict__ k,
+                                                   double* __restrict__ diag) {
+  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
+  int i, j, kz;
+  node_ijk(g, n, i, j, kz);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k, g.ne * 8);
+  double kv[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) kv[c][bb][a] = zbload<double>(rk, cell_boff(g, i - 1 + a, j - 1 + bb, kz - 1 + c, 8));
+  const double t00 = kv[0][0][0] + kv[1][0][0], t01 = kv[0][0][1] + kv[1][0][1];
+  const double t10 = kv[0][1][0] + kv[1][1][0], t11 = kv[0][1][1] + kv[1][1][1];
+  const double ks = (t00 + t01) + (t10 + t11);
+  zbstore(double(g.h * (1.0 / 3.0)) * ks, zrsrc(diag, g.nn * 8), node_boff(g, i, j, kz, 8));
 }
 
 // Restriction followed by the first (zero-start) damped Jacobi sweep of the
@@ -1614,6 +1646,9 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
     case SM_PAPPLY_DOT:
       if constexpr (TWO && std::is_same_v<T, double>) ZCALL(SM_PAPPLY_DOT);
       break;
+    case SM_J0RESID:   // one queue depth only: a deeper queue exceeds 256 VGPRs
+      if constexpr (TWO && ZD == 1 && std::is_same_v<T, double>) ZCALL(SM_J0RESID);
+      break;
   }
 #undef ZCALL
 #undef ZKER
@@ -1829,6 +1864,24 @@ int launch_papply_dot(const Geo& g, const double* z, const double* k, double* ou
     zmarch_launch<1, true, double, CellD>(g, z2, c.kz, SM_PAPPLY_DOT, z, kc, kc, nullptr, out, 0.0, part,
                                           done, nullptr, nullptr, s, ev0, ev1, pf);
   return z2.ntx * z2.nty * z2.nzc;
+}
+
+bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
+                    double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg) {
+  const StencilCfg c = resolve_cfg(g, cfg);
+  if (c.kind != 2) return false;
+  const ZShape z2 = zmarch_shape(g, c);
+  const CellD kc{k};
+  PFuse pf{};
+  pf.diag = diag;
+  pf.xout = xout;
+  zmarch_launch<1, true, double, CellD>(g, z2, c.kz, SM_J0RESID, b, kc, kc, b, out, omega, nullptr, done,
+                                        nullptr, nullptr, s, nullptr, nullptr, pf);
+  return true;
+}
+
+void launch_diag(const Geo& g, const double* k, double* diag, hipStream_t s) {
+  k_diag<<<flat_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, k, diag);
 }
 
 template <typename T, typename CL>

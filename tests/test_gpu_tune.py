@@ -133,11 +133,12 @@ def test_solves_with_two_row_shapes_match_oracle(precision):
 
 @pytest.mark.parametrize("prob", [W.tiny_3d(32, 32, 32, 4), W.tiny_3d(48, 32, 16, 3)],
                          ids=["32x32x32", "48x32x16"])
-def test_fused_direction_update_matches_separate_launches(prob):
+def test_fused_launches_match_separate_launches(prob):
     """A two-row shape for the finest apply + dot runs the CG direction update
-    inside the apply (double-buffered direction); any other shape runs the
-    update and the apply as two launches. Same iterations, same temperature
-    (to the summation order of the dot partials), both on the oracle."""
+    inside the apply (double-buffered direction), and one for the finest
+    residual runs the V-cycle's first sweep inside it; any other shape runs
+    them as separate launches. Same iterations, same temperature (to the
+    summation order of the dot partials), both on the oracle."""
     import torch
     s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
     x0 = W.random_density(prob.nelem, 41, 0.1, 0.9)
@@ -148,6 +149,7 @@ def test_fused_direction_update_matches_separate_launches(prob):
     for name, shape in (("fused", [2, 6, 1, 1]), ("separate", [1, 6, 1, 1])):
         h = handle(prob)
         h.mgar_tune_set(0, 0, 1, shape)
+        h.mgar_tune_set(0, 0, 2, shape)
         q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
         h.mgar_load_vector(dev(W.element_source(prob)), q)
         T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")

@@ -63,6 +63,9 @@ struct mgar_handle {
   float *rtmpf = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *w32 = nullptr,
         *d32 = nullptr;
   float* k32 = nullptr;                   // FP32 conductivities of the current call (inner operator)
+  float* p32b = nullptr;                  // second inner direction buffer (fused direction update)
+  float* dg32 = nullptr;                  // diagonal of the BF16 finest operator (3D)
+  bool dg32_valid = false;
   int ltf = 1;
   TailSpec tailf;
   float kmin_f = 0.f, kdiff_f = 0.f;
@@ -363,6 +366,8 @@ int build_hierarchy32(mgar_handle* h) {
   h->dg0_valid = false;   // lv[0].k no longer describes the preconditioner's K0
   launch_copy_u16(h->dens, h->dens0, h->E, h->s);
   const CellB k0{h->dens0, h->kmin_f, h->kdiff_f};
+  if (h->dg32) launch_diag_t<float, CellB>(h->lv[0].g, k0, h->dg32, h->s);
+  h->dg32_valid = h->dg32 != nullptr;
   if (L >= 2) launch_coarsen_t<CellB, float>(h->lv[0].g, h->lv[1].g, k0, h->kf[1], h->s);
   for (int l = 2; l < L; ++l)
     launch_coarsen_t<CellF, float>(h->lv[l - 1].g, h->lv[l].g, CellF{h->kf[l - 1]}, h->kf[l], h->s);
@@ -387,9 +392,13 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
   bool presmoothed = false;
   for (int l = 0; l < lt; ++l) {
     const float* b = (l == 0) ? b0 : h->bf[l];
+    const bool fused = l == 0 && !x0 && h->dg32_valid &&
+                       launch_j0resid_t<float, CellB>(h->lv[0].g, b, CellB{h->dens0, h->kmin_f, h->kdiff_f},
+                                                      h->dg32, h->xaf[0], h->rtmpf, h->p.omega, done, h->s,
+                                                      &h->scfg[1][0][SM_RESID]);
     if (l == 0 && x0) ACK(stencil32(h, l, SM_JACOBI, x0, b, h->xaf[l], nullptr, done));
-    else if (!presmoothed) ACK(stencil32(h, l, SM_JACOBI0, nullptr, b, h->xaf[l], nullptr, done));
-    ACK(stencil32(h, l, SM_RESID, h->xaf[l], b, h->rtmpf, nullptr, done));
+    else if (!presmoothed && !fused) ACK(stencil32(h, l, SM_JACOBI0, nullptr, b, h->xaf[l], nullptr, done));
+    if (!fused) ACK(stencil32(h, l, SM_RESID, h->xaf[l], b, h->rtmpf, nullptr, done));
     presmoothed = l + 1 < lt && launch_restrict_j0_t<float, CellF>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf,
                                                                    CellF{h->kf[l + 1]}, h->bf[l + 1],
                                                                    h->xaf[l + 1], h->p.omega, done, h->s);
@@ -435,12 +444,22 @@ int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int ta
   } else {
     ACK(vcycle32(h, h->r32, nullptr, h->z32, h->pb, done));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 1, SM_JACOBI_DOT);
-    launch_p_update_t<float>(h->z32, h->p32, N, h->st, h->s, h->pb, nz);
     // the inner operator: FP32 conductivities of the current densities (BF16
-    // densities only enter the V-cycle preconditioner)
-    ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
-    launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s,
-                              h->pc, nparts_at(h, 1, SM_APPLY_DOT));
+    // densities only enter the V-cycle preconditioner); direction update fused
+    // into it where the shape allows (p in p32 / p32b by iteration parity)
+    const PFuse pf{h->st, h->pb, nz, 0, {h->p32, h->p32b}, nullptr, nullptr};
+    const int nw = launch_papply_dot_t<float, CellF>(h->lv[0].g, h->z32, CellF{h->k32}, h->w32, h->pc, done,
+                                                     h->s, pf, &h->scfg[1][0][SM_APPLY_DOT]);
+    if (nw < 0) {
+      launch_p_update_t<float>(h->z32, h->p32, N, h->st, h->s, h->pb, nz);
+      ACK(stencil32(h, 0, SM_APPLY_DOT, h->p32, nullptr, h->w32, h->pc, done, nullptr, nullptr, h->k32));
+      launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s,
+                                h->pc, nparts_at(h, 1, SM_APPLY_DOT));
+    } else {
+      LAUNCHCK();
+      launch_cg_update_t<float>(h->d32, h->r32, h->p32, h->w32, N, h->st, h->pa, nullptr, tol, cg_max, h->s,
+                                h->pc, nw, h->p32b);
+    }
   }
   launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
   LAUNCHCK();
@@ -526,7 +545,10 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
   HIPCK(hipMemsetAsync(h->d32, 0, sizeof(float) * N, h->s));
   const int nr = launch_dot_t<float, float>(h->r32, h->r32, N, h->pa, nullptr, h->s);
   launch_cg_init(h->st, h->pa, nr, h->pa, nr, tol_in, max_it, h->s);
-  int it = 0, chunk = 4;
+  launch_fill_t<float>(h->p32b, N, 0.f, 0.f, h->s);   // p_old of iteration 0 (weight 0) stays finite
+  int it = 0, chunk = std::max(1, std::min(4, max_it));
+  double rr_prev = -1.0;
+  int it_prev = 0;
   CgState hs;
   for (;;) {
     ACK(run_iters(h, 1, tol_in, h->p.cg_max, chunk, nr));
@@ -538,7 +560,20 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
       *iters = hs.it;
       return MGAR_OK;
     }
-    chunk = 2;
+    // the next chunk from the observed contraction rate (the initial residual
+    // ||r_0||^2 is st->qq here), as in pcg
+    const double rr = hs.rr;
+    int next = 2;
+    const double r0 = rr_prev > 0.0 ? rr_prev : hs.qq;
+    const int i0 = rr_prev > 0.0 ? it_prev : 0;
+    if (r0 > 0.0 && rr > 0.0 && hs.it > i0) {
+      const double rate = std::pow(rr / r0, 0.5 / (double)(hs.it - i0));
+      const double goal = tol_in * std::sqrt(hs.qq) / std::sqrt(rr);
+      if (rate > 0.0 && rate < 0.999 && goal < 1.0) next = (int)std::ceil(std::log(goal) / std::log(rate));
+    }
+    chunk = std::max(1, std::min({next, 16, max_it - it}));
+    rr_prev = rr;
+    it_prev = hs.it;
   }
   *iters = hs.iters;
   return MGAR_OK;
@@ -735,7 +770,8 @@ void mgar_destroy(mgar_handle* h) {
   for (auto* v : {&h->kf, &h->bf, &h->xaf, &h->xbf})
     for (float* q : *v)
       if (q) (void)hipFree(q);
-  void* mptrs[] = {h->dens, h->dens0, h->rtmpf, h->r32, h->z32, h->p32, h->w32, h->d32, h->k32};
+  void* mptrs[] = {h->dens, h->dens0, h->rtmpf, h->r32, h->z32, h->p32, h->w32, h->d32, h->k32, h->p32b,
+                   h->dg32};
   for (void* q : mptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
@@ -849,6 +885,8 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
     ACK(dalloc(&h->r32, N));
     ACK(dalloc(&h->z32, N));
     ACK(dalloc(&h->p32, N));
+    ACK(dalloc(&h->p32b, N));
+    if (g0.dim == 3) ACK(dalloc(&h->dg32, N));
     ACK(dalloc(&h->w32, N));
     ACK(dalloc(&h->d32, N));
     if (h->L >= 2) {

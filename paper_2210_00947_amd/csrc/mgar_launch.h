@@ -29,14 +29,15 @@ enum StencilMode {
 // pbuf[(it + 1) & 1], p written to pbuf[it & 1]): neighbouring blocks read
 // p_old in their halo while this block writes p.
 // SM_J0RESID: diag = diagonal of K per node, xout receives the sweep.
+// Vectors are of the kernel's value type (double or float).
 struct PFuse {
   CgState* st;          // it, rz history; st->rz[it & 1] is stored by block 0
   const double* rzp;    // block partials of r . z of this iteration
   int nrz;
   int pad;
-  double* pbuf[2];
-  const double* diag;
-  double* xout;
+  void* pbuf[2];
+  const void* diag;
+  void* xout;
 };
 
 // stencil.hip ----------------------------------------------------------------
@@ -79,17 +80,35 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
 // SM_PAPPLY_DOT on grid g with launch shape cfg: returns the number of block
 // partials of p . out written to part, or -1 (nothing launched) when cfg is not
 // a two-row z-marching shape (then p is updated and applied by separate launches).
-int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
-                      const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
-                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Instantiated for (double, CellD) and (float, CellF).
+template <typename T, typename CL>
+int launch_papply_dot_t(const Geo& g, const T* z, CL k, T* out, double* part, const int* done,
+                        hipStream_t s, const PFuse& pf, const StencilCfg* cfg, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+inline int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
+                             const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  return launch_papply_dot_t<double, CellD>(g, z, CellD{k}, out, part, done, s, pf, cfg, ev0, ev1);
+}
 // SM_J0RESID on grid g (3D) with launch shape cfg (its queue depth is always 1):
 // xout = w b / diag, out = b - K xout. Returns false (nothing launched) when cfg
-// is not a two-row z-marching shape.
-bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
-                    double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg);
+// is not a two-row z-marching shape. Instantiated for (double, CellD) and
+// (float, CellB).
+template <typename T, typename CL>
+bool launch_j0resid_t(const Geo& g, const T* b, CL k, const T* diag, T* xout, T* out, double omega,
+                      const int* done, hipStream_t s, const StencilCfg* cfg);
+inline bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
+                           double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg) {
+  return launch_j0resid_t<double, CellD>(g, b, CellD{k}, diag, xout, out, omega, done, s, cfg);
+}
 // diag[n] = diagonal of K at node n (h/3 times the sum of its cells, summed in the
-// order of the node formula), 3D; 0 outside the grid is never written.
-void launch_diag(const Geo& g, const double* k, double* diag, hipStream_t s);
+// order of the node formula, in the value type), 3D. Instantiated for
+// (double, CellD) and (float, CellB).
+template <typename T, typename CL>
+void launch_diag_t(const Geo& g, CL k, T* diag, hipStream_t s);
+inline void launch_diag(const Geo& g, const double* k, double* diag, hipStream_t s) {
+  launch_diag_t<double, CellD>(g, CellD{k}, diag, s);
+}
 int stencil_num_partials(const Geo& g, const StencilCfg* cfg = nullptr);
 template <typename T>
 void launch_restrict_t(const Geo& gf, const Geo& gc, const T* rf, T* rc, const int* done, hipStream_t s);

@@ -13,6 +13,7 @@
 // cells outside the grid, whose conductivity is taken as 0.
 #include <algorithm>
 #include <cfloat>
+#include <limits>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -676,7 +677,8 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   // and the staged value formed from the pair (u = x input, v = second input).
   // A slot outside the grid loads 0 for both; max(v, DBL_MIN) keeps its sweep 0.
 #define ZP(so, p) (XF ? zbload<T>(rp, zplane((so), (p), g.nnz, plb)) : T(0))
-#define ZFORM(u, v) (PU ? (u) + beta * (v) : J0R ? omega * (u) / fmax((v), T(DBL_MIN)) : (u))
+#define ZFORM(u, v) (PU ? (u) + beta * (v) : J0R ? omega * (u) / fmax((v), TMIN) : (u))
+  constexpr T TMIN = std::numeric_limits<T>::min();
 #define ZXP(so, p) (XF ? ZFORM(ZX(so, p), ZP(so, p)) : ZX(so, p))
   constexpr int ZQP = XF ? ZD : 1;
   T qx0[ZD], qx1[ZD], qx2[ZD], qb0[ZD], qb1[ZD];
@@ -934,23 +936,30 @@ __global__ __launch_bounds__(TBX* TBY) void k_restrict_b(Geo gf, Geo gc, const T
 
 // Diagonal of K per node (3D): h/3 times the sum of the node's 8 cells, in the
 // association of the node formula. Used by the fused first sweep + residual.
-__global__ __launch_bounds__(TBX* TBY) void k_diag(Geo g, const double* __restrict__ k,
-                                                   double* __restrict__ diag) {
+template <typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_diag(Geo g, CL k, T* __restrict__ diag) {
+  using E = typename CL::E;
+  constexpr unsigned ES = sizeof(E);
+  constexpr bool CMASK = sizeof(E) == 2;   // a raw 0 of a BF16 array is not a zero conductivity
   const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
   int i, j, kz;
   node_ijk(g, n, i, j, kz);
-  const __amdgpu_buffer_rsrc_t rk = zrsrc(k, g.ne * 8);
-  double kv[2][2][2];
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, g.ne * ES);
+  T kv[2][2][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) kv[c][bb][a] = zbload<double>(rk, cell_boff(g, i - 1 + a, j - 1 + bb, kz - 1 + c, 8));
-  const double t00 = kv[0][0][0] + kv[1][0][0], t01 = kv[0][0][1] + kv[1][0][1];
-  const double t10 = kv[0][1][0] + kv[1][1][0], t11 = kv[0][1][1] + kv[1][1][1];
-  const double ks = (t00 + t01) + (t10 + t11);
-  zbstore(double(g.h * (1.0 / 3.0)) * ks, zrsrc(diag, g.nn * 8), node_boff(g, i, j, kz, 8));
+      for (int a = 0; a < 2; ++a) {
+        const unsigned o = cell_boff(g, i - 1 + a, j - 1 + bb, kz - 1 + c, ES);
+        const T v = T(k.value(zbload<E>(rk, o)));
+        kv[c][bb][a] = CMASK ? v * (o < ZOOB ? T(1) : T(0)) : v;
+      }
+  const T t00 = kv[0][0][0] + kv[1][0][0], t01 = kv[0][0][1] + kv[1][0][1];
+  const T t10 = kv[0][1][0] + kv[1][1][0], t11 = kv[0][1][1] + kv[1][1][1];
+  const T ks = (t00 + t01) + (t10 + t11);
+  zbstore(T(g.h * (1.0 / 3.0)) * ks, zrsrc(diag, g.nn * sizeof(T)), node_boff(g, i, j, kz, sizeof(T)));
 }
 
 // Restriction followed by the first (zero-start) damped Jacobi sweep of the
@@ -1643,11 +1652,12 @@ void zmarch_launch(const Geo& g, const ZShape& z, int kz, int mode, const T* x, 
     case SM_JACOBI_DOT: ZCALL(SM_JACOBI_DOT); break;
     case SM_JACOBI0: ZCALL(SM_JACOBI0); break;
     case SM_NEG_DK: ZCALL(SM_NEG_DK); break;
-    case SM_PAPPLY_DOT:
-      if constexpr (TWO && std::is_same_v<T, double>) ZCALL(SM_PAPPLY_DOT);
+    case SM_PAPPLY_DOT:   // the finest operators of the FP64 and the FP32 solver
+      if constexpr (TWO && (std::is_same_v<CL, CellD> || std::is_same_v<CL, CellF>)) ZCALL(SM_PAPPLY_DOT);
       break;
-    case SM_J0RESID:   // one queue depth only: a deeper queue exceeds 256 VGPRs
-      if constexpr (TWO && ZD == 1 && std::is_same_v<T, double>) ZCALL(SM_J0RESID);
+    case SM_J0RESID:   // finest V-cycle grids; one queue depth: a deeper one exceeds 256 VGPRs
+      if constexpr (TWO && ZD == 1 && (std::is_same_v<CL, CellD> || std::is_same_v<CL, CellB>))
+        ZCALL(SM_J0RESID);
       break;
   }
 #undef ZCALL
@@ -1850,39 +1860,52 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg) {
   return true;   // every stencil launch path takes kernel start/end events
 }
 
-int launch_papply_dot(const Geo& g, const double* z, const double* k, double* out, double* part,
-                      const int* done, hipStream_t s, const PFuse& pf, const StencilCfg* cfg,
-                      hipEvent_t ev0, hipEvent_t ev1) {
+template <typename T, typename CL>
+int launch_papply_dot_t(const Geo& g, const T* z, CL k, T* out, double* part, const int* done,
+                        hipStream_t s, const PFuse& pf, const StencilCfg* cfg, hipEvent_t ev0,
+                        hipEvent_t ev1) {
   const StencilCfg c = resolve_cfg(g, cfg);
   if (c.kind != 2) return -1;
   const ZShape z2 = zmarch_shape(g, c);
-  const CellD kc{k};
   if (c.zd == 2)
-    zmarch_launch<2, true, double, CellD>(g, z2, c.kz, SM_PAPPLY_DOT, z, kc, kc, nullptr, out, 0.0, part,
-                                          done, nullptr, nullptr, s, ev0, ev1, pf);
+    zmarch_launch<2, true, T, CL>(g, z2, c.kz, SM_PAPPLY_DOT, z, k, k, nullptr, out, T(0), part, done,
+                                  nullptr, nullptr, s, ev0, ev1, pf);
   else
-    zmarch_launch<1, true, double, CellD>(g, z2, c.kz, SM_PAPPLY_DOT, z, kc, kc, nullptr, out, 0.0, part,
-                                          done, nullptr, nullptr, s, ev0, ev1, pf);
+    zmarch_launch<1, true, T, CL>(g, z2, c.kz, SM_PAPPLY_DOT, z, k, k, nullptr, out, T(0), part, done,
+                                  nullptr, nullptr, s, ev0, ev1, pf);
   return z2.ntx * z2.nty * z2.nzc;
 }
+template int launch_papply_dot_t<double, CellD>(const Geo&, const double*, CellD, double*, double*,
+                                                const int*, hipStream_t, const PFuse&, const StencilCfg*,
+                                                hipEvent_t, hipEvent_t);
+template int launch_papply_dot_t<float, CellF>(const Geo&, const float*, CellF, float*, double*,
+                                               const int*, hipStream_t, const PFuse&, const StencilCfg*,
+                                               hipEvent_t, hipEvent_t);
 
-bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
-                    double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg) {
+template <typename T, typename CL>
+bool launch_j0resid_t(const Geo& g, const T* b, CL k, const T* diag, T* xout, T* out, double omega,
+                      const int* done, hipStream_t s, const StencilCfg* cfg) {
   const StencilCfg c = resolve_cfg(g, cfg);
   if (c.kind != 2) return false;
   const ZShape z2 = zmarch_shape(g, c);
-  const CellD kc{k};
   PFuse pf{};
   pf.diag = diag;
   pf.xout = xout;
-  zmarch_launch<1, true, double, CellD>(g, z2, c.kz, SM_J0RESID, b, kc, kc, b, out, omega, nullptr, done,
-                                        nullptr, nullptr, s, nullptr, nullptr, pf);
+  zmarch_launch<1, true, T, CL>(g, z2, c.kz, SM_J0RESID, b, k, k, b, out, (T)omega, nullptr, done,
+                                nullptr, nullptr, s, nullptr, nullptr, pf);
   return true;
 }
+template bool launch_j0resid_t<double, CellD>(const Geo&, const double*, CellD, const double*, double*,
+                                              double*, double, const int*, hipStream_t, const StencilCfg*);
+template bool launch_j0resid_t<float, CellB>(const Geo&, const float*, CellB, const float*, float*, float*,
+                                             double, const int*, hipStream_t, const StencilCfg*);
 
-void launch_diag(const Geo& g, const double* k, double* diag, hipStream_t s) {
-  k_diag<<<flat_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, k, diag);
+template <typename T, typename CL>
+void launch_diag_t(const Geo& g, CL k, T* diag, hipStream_t s) {
+  k_diag<T, CL><<<flat_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, k, diag);
 }
+template void launch_diag_t<double, CellD>(const Geo&, CellD, double*, hipStream_t);
+template void launch_diag_t<float, CellB>(const Geo&, CellB, float*, hipStream_t);
 
 template <typename T, typename CL>
 int launch_stencil_t(const Geo& g, int mode, const T* x, CL k, CL kref, const T* b, T* out,

@@ -324,9 +324,15 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
     const double* b = (l == 0) ? b0 : v.b;
     double* o = (l == 0) ? out : v.xb;
     double* dp = (l == 0) ? dot_part : nullptr;
-    launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
-    ACK(stencil_at(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w, dp, done,
-                   nullptr, tag, dp ? dcnt : nullptr, dp ? dout : nullptr));
+    // small grids (node-parallel shape): interpolation and sweep in one launch
+    const bool fused = l > 0 && h->scfg[0][l][SM_JACOBI].kind == 0 &&
+                       launch_prolong_jacobi_t<double, CellD>(v.g, h->lv[l + 1].g, xfin, v.xa, CellD{v.k}, b,
+                                                              o, w, done, h->s);
+    if (!fused) {
+      launch_prolong(v.g, h->lv[l + 1].g, xfin, v.xa, done, h->s);
+      ACK(stencil_at(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, v.xa, v.k, nullptr, b, o, w, dp, done,
+                     nullptr, tag, dp ? dcnt : nullptr, dp ? dout : nullptr));
+    }
     xfin = o;
   }
   LAUNCHCK();
@@ -408,10 +414,15 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
   const float* xfin = h->xbf[lt];
   for (int l = lt - 1; l >= 0; --l) {
     const float* b = (l == 0) ? b0 : h->bf[l];
-    launch_prolong_t<float>(h->lv[l].g, h->lv[l + 1].g, xfin, h->xaf[l], done, h->s);
     float* o = (l == 0) ? out : h->xbf[l];
     double* dp = (l == 0) ? dot_part : nullptr;
-    ACK(stencil32(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, h->xaf[l], b, o, dp, done));
+    const bool fused = l > 0 && h->scfg[1][l][SM_JACOBI].kind == 0 &&
+                       launch_prolong_jacobi_t<float, CellF>(h->lv[l].g, h->lv[l + 1].g, xfin, h->xaf[l],
+                                                             CellF{h->kf[l]}, b, o, h->p.omega, done, h->s);
+    if (!fused) {
+      launch_prolong_t<float>(h->lv[l].g, h->lv[l + 1].g, xfin, h->xaf[l], done, h->s);
+      ACK(stencil32(h, l, dp ? SM_JACOBI_DOT : SM_JACOBI, h->xaf[l], b, o, dp, done));
+    }
     xfin = o;
   }
   LAUNCHCK();

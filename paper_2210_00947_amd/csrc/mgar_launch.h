@@ -120,6 +120,14 @@ bool launch_restrict_j0_t(const Geo& gf, const Geo& gc, const T* rf, CL kc, T* b
                           const int* done, hipStream_t s);
 template <typename T>
 void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const int* done, hipStream_t s);
+// Interpolation xpre + P xc then one Jacobi sweep on grid gf (cells k, right
+// side b) into out, in one node-parallel launch; xpre is not written. Equal to
+// launch_prolong_t followed by the stencil's Jacobi mode. Returns false
+// (nothing launched) for grids too large for 32-bit buffer offsets.
+// Instantiated for (double, CellD) and (float, CellF).
+template <typename T, typename CL>
+bool launch_prolong_jacobi_t(const Geo& gf, const Geo& gc, const T* xc, const T* xpre, CL k, const T* b,
+                             T* out, double omega, const int* done, hipStream_t s);
 template <typename CL, typename TO>
 void launch_coarsen_t(const Geo& gf, const Geo& gc, CL kf, TO* kc, hipStream_t s);
 template <typename CL>

@@ -1105,6 +1105,171 @@ __global__ __launch_bounds__(TBX* TBY) void k_prolong_b(Geo gf, Geo gc, const T*
   prolong_b_point<DIM, T>(gf, gc, (long long)blockIdx.x * (TBX * TBY) + flat_tid(), xc, xf);
 }
 
+// Interpolation followed by one damped Jacobi sweep, per fine node, for small
+// grids where launches dominate: the interpolated iterate xa = xpre + P xc is
+// formed on the fly at the node and its stencil neighbours (from a 3^d block
+// of coarse values; the same expression per fine node as k_prolong_b8, and
+// Dirichlet nodes keep xpre), then out = xa + w D^-1 (b - K xa) with the node
+// formula of the stencil kernels. Results equal the two separate launches.
+template <int DIM, typename T, typename CL>
+__global__ __launch_bounds__(TBX* TBY) void k_prolong_jacobi(Geo gf, Geo gc, const T* __restrict__ xc,
+                                                             const T* __restrict__ xpre, CL k,
+                                                             const T* __restrict__ b, T* __restrict__ out,
+                                                             T omega, const int* __restrict__ done) {
+  if (done && *done) return;
+  using E = typename CL::E;
+  constexpr unsigned TS = sizeof(T), ES = sizeof(E);
+  constexpr bool CMASK = sizeof(E) == 2;
+  constexpr int NZ = DIM == 3 ? 3 : 1;
+  const long long n = (long long)blockIdx.x * (TBX * TBY) + flat_tid();
+  int i, j, kz;
+  node_ijk(gf, n, i, j, kz);   // past the grid: kz >= nnz, every offset out of range
+  const __amdgpu_buffer_rsrc_t rc = zrsrc(xc, gc.nn * TS);
+  const __amdgpu_buffer_rsrc_t rp = zrsrc(xpre, gf.nn * TS);
+  const __amdgpu_buffer_rsrc_t rb = zrsrc(b, gf.nn * TS);
+  const __amdgpu_buffer_rsrc_t rk = zrsrc(k.p, gf.ne * ES);
+  const int Ib = (i >> 1) - 1, Jb = (j >> 1) - 1, Kb = DIM == 3 ? (kz >> 1) - 1 : 0;
+  T cv[NZ][3][3];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        cv[c][bb][a] = zbload<T>(rc, node_boff(gc, Ib + a, Jb + bb, DIM == 3 ? Kb + c : 0, TS));
+  T kv[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (DIM == 2 && c == 1) { kv[c][bb][a] = T(0); continue; }
+        const unsigned o = cell_boff(gf, i - 1 + a, j - 1 + bb, DIM == 3 ? kz - 1 + c : 0, ES);
+        const T v = T(k.value(zbload<E>(rk, o)));
+        kv[c][bb][a] = CMASK ? v * (o < ZOOB ? T(1) : T(0)) : v;
+      }
+  const unsigned own = node_boff(gf, i, j, kz, TS);   // ZOOB past the grid (kz >= nnz)
+  const T bn = zbload<T>(rb, own);
+  // Per axis and fine offset d in {-1, 0, 1}, the fine node i + d interpolates
+  // between coarse entries lo and hi of the 3-block: lo + m * hi, weighted w
+  // (m = 1, w = 1/2 on odd fine indices, else m = 0, w = 1). Only lo depends on
+  // the parity of i (a select between two registers); every array index is a
+  // compile-time constant, so the block stays in registers.
+  const int px = i & 1, py = j & 1, pz = DIM == 3 ? (kz & 1) : 0;
+  const T fx = T(px), fy = T(py), fz = T(pz);
+  // a or b by a 0/1 weight: exact for finite values, and (unlike a select of two
+  // array elements, which is compiled into an indexed access) keeps the block in
+  // registers
+  auto pick = [](T a, T b, T f) __attribute__((always_inline)) { return a * (T(1) - f) + b * f; };
+  auto mw = [](int p, int d, T& m, T& w) __attribute__((always_inline)) {
+    const int odd = (p + d) & 1;
+    m = T(odd);
+    w = T(odd ? 0.5 : 1.0);
+  };
+  // x: X[dx][zz][yy] = cv[zz][yy][lo] + m_x cv[zz][yy][hi]
+  T X[3][NZ][3];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) {
+    T m, w;
+    mw(px, dx - 1, m, w);
+    (void)w;
+#pragma unroll
+    for (int zz = 0; zz < NZ; ++zz)
+#pragma unroll
+      for (int yy = 0; yy < 3; ++yy) {
+        const T* row = cv[zz][yy];
+        const T lo = dx == 0 ? pick(row[0], row[1], fx) : dx == 1 ? row[1] : pick(row[1], row[2], fx);
+        const T hi = dx == 0 ? row[1] : row[2];
+        X[dx][zz][yy] = lo + m * hi;
+      }
+  }
+  // y: Y[dx][dy][zz] = w_x X[dx][zz][lo] + m_y (w_x X[dx][zz][hi])
+  T Y[3][3][NZ];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) {
+    T mx, wx;
+    mw(px, dx - 1, mx, wx);
+    (void)mx;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      T my, wy;
+      mw(py, dy - 1, my, wy);
+      (void)wy;
+#pragma unroll
+      for (int zz = 0; zz < NZ; ++zz) {
+        const T* col = X[dx][zz];
+        const T lo = dy == 0 ? pick(col[0], col[1], fy) : dy == 1 ? col[1] : pick(col[1], col[2], fy);
+        const T hi = dy == 0 ? col[1] : col[2];
+        Y[dx][dy][zz] = wx * lo + my * (wx * hi);
+      }
+    }
+  }
+  // z, and the interpolated iterate at fine node (i + dx - 1, j + dy - 1, kz + dz - 1)
+  auto xa_at = [&](int dx, int dy, int dz) __attribute__((always_inline)) -> T {
+    const int ii = i + dx - 1, jj = j + dy - 1, kk = DIM == 3 ? kz + dz - 1 : kz;
+    const unsigned o = node_boff(gf, ii, jj, kk, TS);
+    const T xo = zbload<T>(rp, o);
+    T my, wy, mz, wz;
+    mw(py, dy - 1, my, wy);
+    (void)my;
+    if (DIM == 3) mw(pz, dz - 1, mz, wz);
+    else { mz = T(0); wz = T(1); }
+    const T* zc = Y[dx][dy];
+    T lo, hi;
+    if (DIM == 3) {
+      lo = dz == 0 ? pick(zc[0], zc[1], fz) : dz == 1 ? zc[1] : pick(zc[1], zc[NZ - 1], fz);
+      hi = dz == 0 ? zc[1] : zc[NZ - 1];
+    } else {
+      lo = zc[0];
+      hi = zc[0];
+    }
+    const T s = wy * lo + mz * (wy * hi);
+    const bool in = o < ZOOB, fixed = geo_fixed(gf, ii, jj, kk);
+    const T xa = fixed ? xo : xo + wz * s;
+    return xa * (in ? T(1) : T(0));
+  };
+  T y, ksum, xn;
+  if (DIM == 2) {
+    T xv[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) xv[dy][dx] = xa_at(dx, dy, 1);
+    xn = xv[1][1];
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int sx = a ? 2 : 0, sy = bb ? 2 : 0;
+        const T ke = kv[0][bb][a];
+        s0 += ke;
+        s1 += ke * (xv[1][sx] + xv[sy][1]);
+        s2 += ke * xv[sy][sx];
+      }
+    ksum = s0;
+    y = T(2.0 / 3.0) * s0 * xv[1][1] - T(1.0 / 6.0) * s1 - T(1.0 / 3.0) * s2;
+  } else {
+    T xv[3][3][3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const int nzr = (dx != 1) + (dy != 1) + (dz != 1);
+          xv[dz][dy][dx] = (nzr == 1) ? T(0) : xa_at(dx, dy, dz);   // face neighbours: weight 0
+        }
+    xn = xv[1][1][1];
+    y = apply27<T, true>(xv[0], xv[1], xv[2], kv[0], kv[1], T(gf.h * (1.0 / 3.0)), T(gf.h * (1.0 / 12.0)), ksum);
+  }
+  const T diag = T(DIM == 3 ? gf.h * (1.0 / 3.0) : (2.0 / 3.0)) * ksum;
+  T r = xn + omega * (bn - y) / diag;
+  r = geo_fixed(gf, i, j, kz) ? T(0) : r;
+  zbstore(r, zrsrc(out, gf.nn * TS), own);
+}
+
 // Coarse conductivity: mean of the 2^d children.
 template <int DIM, typename CL, typename TO>
 __global__ void k_coarsen(Geo gf, Geo gc, CL kf, TO* __restrict__ kc) {
@@ -1994,6 +2159,23 @@ void launch_prolong_t(const Geo& gf, const Geo& gc, const T* xc, T* xf, const in
 }
 template void launch_prolong_t<double>(const Geo&, const Geo&, const double*, double*, const int*, hipStream_t);
 template void launch_prolong_t<float>(const Geo&, const Geo&, const float*, float*, const int*, hipStream_t);
+
+template <typename T, typename CL>
+bool launch_prolong_jacobi_t(const Geo& gf, const Geo& gc, const T* xc, const T* xpre, CL k, const T* b,
+                             T* out, double omega, const int* done, hipStream_t s) {
+  if (!grid_fits_buffers(gf)) return false;
+  const dim3 blk(TBX, TBY, 1);
+  if (gf.dim == 2)
+    k_prolong_jacobi<2, T, CL><<<flat_grid(gf), blk, 0, s>>>(gf, gc, xc, xpre, k, b, out, (T)omega, done);
+  else
+    k_prolong_jacobi<3, T, CL><<<flat_grid(gf), blk, 0, s>>>(gf, gc, xc, xpre, k, b, out, (T)omega, done);
+  return true;
+}
+template bool launch_prolong_jacobi_t<double, CellD>(const Geo&, const Geo&, const double*, const double*,
+                                                     CellD, const double*, double*, double, const int*,
+                                                     hipStream_t);
+template bool launch_prolong_jacobi_t<float, CellF>(const Geo&, const Geo&, const float*, const float*, CellF,
+                                                    const float*, float*, double, const int*, hipStream_t);
 
 template <typename CL, typename TO>
 void launch_coarsen_t(const Geo& gf, const Geo& gc, CL kf, TO* kc, hipStream_t s) {

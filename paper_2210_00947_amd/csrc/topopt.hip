@@ -2,6 +2,7 @@
 // consistent load, cone density filter and its adjoint (Eq 6-9, 11), element
 // compliance sensitivity (Eq 10), and the optimality-criteria update.
 #include "mgar_launch.h"
+#include "zbuf.h"
 
 namespace {
 
@@ -71,6 +72,38 @@ __global__ __launch_bounds__(TBX* TBY) void k_filter(Geo g, const int* __restric
     const int jx = ex + off[3 * t], jy = ey + off[3 * t + 1], jz = ez + off[3 * t + 2];
     if (jx < 0 || jx >= g.nx || jy < 0 || jy >= g.ny || jz < 0 || jz >= g.nz) continue;
     s += w[t] * x[geo_elem(g, jx, jy, jz)];
+  }
+  const long long e = geo_elem(g, ex, ey, ez);
+  y[e] = scale ? s * scale[e] : s;
+}
+
+// As k_filter with buffer loads: taps outside the grid read 0 (and so add
+// w * 0 in place of being skipped), eight taps per step are loaded before the
+// first is used, and the sum runs over the taps in the same order.
+constexpr int FTAP = 8;
+__global__ __launch_bounds__(TBX* TBY) void k_filter_b(Geo g, const int* __restrict__ off,
+                                                       const double* __restrict__ w, int ntap,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ y) {
+  const int ex = blockIdx.x * TBX + threadIdx.x;
+  const int ey = blockIdx.y * TBY + threadIdx.y;
+  const int ez = blockIdx.z;
+  if (ex >= g.nx || ey >= g.ny) return;
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(x, g.ne * 8);
+  double s = 0.0;
+  for (int t0 = 0; t0 < ntap; t0 += FTAP) {
+    double v[FTAP], wt[FTAP];
+#pragma unroll
+    for (int u = 0; u < FTAP; ++u) {
+      const int t = t0 + u, tc = min(t, ntap - 1);
+      const int jx = ex + off[3 * tc], jy = ey + off[3 * tc + 1], jz = ez + off[3 * tc + 2];
+      const bool in = t < ntap && jx >= 0 && jx < g.nx && jy >= 0 && jy < g.ny && jz >= 0 && jz < g.nz;
+      v[u] = zbload<double>(rx, in ? (unsigned)(jx + g.nx * (jy + g.ny * jz)) * 8u : ZOOB);
+      wt[u] = w[tc];
+    }
+#pragma unroll
+    for (int u = 0; u < FTAP; ++u) s += wt[u] * v[u];
   }
   const long long e = geo_elem(g, ex, ey, ez);
   y[e] = scale ? s * scale[e] : s;
@@ -282,7 +315,10 @@ void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s) {
 
 void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, const double* x,
                        const double* invHs, double* y, hipStream_t s) {
-  k_filter<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);
+  if (g.ne * 8 < (1LL << 31))
+    k_filter_b<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);
+  else
+    k_filter<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);
 }
 
 void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, double* invHs,

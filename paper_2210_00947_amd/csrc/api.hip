@@ -52,6 +52,7 @@ struct mgar_handle {
   int* tap_off = nullptr;
   double* tap_w = nullptr;
   int ntap = 0;
+  int tap_hr = 0;                         // largest |offset| of a filter tap
   bool has_k0 = false;
   int lt = 1;                             // first grid handled by the V-cycle tail kernel
   TailSpec tail;
@@ -926,6 +927,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
           if (wt > 0.0) {
             off.push_back(dx); off.push_back(dy); off.push_back(dz);
             w.push_back(wt);
+            h->tap_hr = std::max({h->tap_hr, std::abs(dx), std::abs(dy), std::abs(dz)});
           }
         }
     h->ntap = (int)w.size();
@@ -936,7 +938,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   }
   launch_filter_hs(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, h->s);
   // w = H^T (1/Hs): the filtered-volume weights, which are also dv
-  launch_filter_fwd(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, nullptr, h->wvol, h->s);
+  launch_filter_fwd(g0, h->tap_off, h->tap_w, h->ntap, h->tap_hr, h->invHs, nullptr, h->wvol, h->s);
   LAUNCHCK();
   HIPCK(hipStreamSynchronize(h->s));
   return MGAR_OK;
@@ -977,7 +979,7 @@ int mgar_load_vector(mgar_handle* h, const double* Qe, double* q) {
 
 int mgar_density_filter(mgar_handle* h, const double* x, double* xphys) {
   if (!h || !x || !xphys) return MGAR_E_ARG;
-  launch_filter_fwd(h->lv[0].g, h->tap_off, h->tap_w, h->ntap, x, h->invHs, xphys, h->s);
+  launch_filter_fwd(h->lv[0].g, h->tap_off, h->tap_w, h->ntap, h->tap_hr, x, h->invHs, xphys, h->s);
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -1113,7 +1115,7 @@ int sens_filter(mgar_handle* h, const double* xphys, const double* T, const doub
   if (!h || !xphys || !T || !q || !dc || !dv) return MGAR_E_ARG;
   const Geo& g = h->lv[0].g;
   launch_sens_elem(g, xphys, T, h->invHs, h->p.k0, h->p.kmin, h->p.penal, h->gtmp, h->s);
-  launch_filter_fwd(g, h->tap_off, h->tap_w, h->ntap, h->gtmp, nullptr, dc, h->s);
+  launch_filter_fwd(g, h->tap_off, h->tap_w, h->ntap, h->tap_hr, h->gtmp, nullptr, dc, h->s);
   launch_copy(h->wvol, dv, h->E, h->s);
   LAUNCHCK();
   if (compliance) {

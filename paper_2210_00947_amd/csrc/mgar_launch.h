@@ -338,7 +338,9 @@ struct FilterTaps {
 void launch_simp(const double* xphys, double* k, long long n, double k0, double kmin, double penal,
                  hipStream_t s);
 void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s);
-void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, const double* x,
+// y = (H x) * scale (scale may be null) with ntap taps off[3t..3t+2], w[t];
+// hr = the largest |offset| of any tap (inputs are staged in LDS for hr <= 3).
+void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, int hr, const double* x,
                        const double* invHs, double* y, hipStream_t s);
 void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, double* invHs,
                       hipStream_t s);

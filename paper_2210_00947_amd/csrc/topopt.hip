@@ -109,6 +109,45 @@ __global__ __launch_bounds__(TBX* TBY) void k_filter_b(Geo g, const int* __restr
   y[e] = scale ? s * scale[e] : s;
 }
 
+// As k_filter_b with the inputs of a block staged in LDS first: a 64 x 4 tile
+// of one element plane plus a halo of hr elements in every direction (hr =
+// largest tap offset), so each input is loaded from memory about once per
+// block instead of once per tap; the taps then read LDS in the same order.
+// Halo positions outside the grid hold 0.
+__global__ __launch_bounds__(TBX* TBY) void k_filter_lds(Geo g, const int* __restrict__ off,
+                                                         const double* __restrict__ w, int ntap, int hr,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ scale,
+                                                         double* __restrict__ y) {
+  extern __shared__ double tile[];
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + TBX * ly;
+  const int ex0 = blockIdx.x * TBX, ey0 = blockIdx.y * TBY, ez = blockIdx.z;
+  const int TW = TBX + 2 * hr, TH = TBY + 2 * hr, TD = g.dim == 3 ? 2 * hr + 1 : 1;
+  const int n = TW * TH * TD;
+  // the taps as (LDS offset, weight), staged after the tile
+  double* tw = tile + n;
+  int* to = reinterpret_cast<int*>(tw + ntap);
+  for (int q = tid; q < ntap; q += TBX * TBY) {
+    tw[q] = w[q];
+    to[q] = off[3 * q] + TW * (off[3 * q + 1] + TH * off[3 * q + 2]);
+  }
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(x, g.ne * 8);
+  for (int idx = tid; idx < n; idx += TBX * TBY) {
+    const int ix = idx % TW, r = idx / TW, iy = r % TH, iz = r / TH;
+    const int jx = ex0 - hr + ix, jy = ey0 - hr + iy, jz = g.dim == 3 ? ez - hr + iz : 0;
+    const bool in = jx >= 0 && jx < g.nx && jy >= 0 && jy < g.ny && jz >= 0 && jz < g.nz;
+    tile[idx] = zbload<double>(rx, in ? (unsigned)(jx + g.nx * (jy + g.ny * jz)) * 8u : ZOOB);
+  }
+  __syncthreads();
+  const int ex = ex0 + lx, ey = ey0 + ly;
+  if (ex >= g.nx || ey >= g.ny) return;
+  const int base = (g.dim == 3 ? hr * TH * TW : 0) + (ly + hr) * TW + (lx + hr);
+  double s = 0.0;
+  for (int t = 0; t < ntap; ++t) s += tw[t] * tile[base + to[t]];
+  const long long e = geo_elem(g, ex, ey, ez);
+  y[e] = scale ? s * scale[e] : s;
+}
+
 __global__ __launch_bounds__(TBX* TBY) void k_filter_hs(Geo g, const int* __restrict__ off,
                                                         const double* __restrict__ w, int ntap,
                                                         double* __restrict__ invHs) {
@@ -313,9 +352,13 @@ void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s) {
   else k_load<3><<<node_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, Qe, q);
 }
 
-void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, const double* x,
+void launch_filter_fwd(const Geo& g, const int* off, const double* w, int ntap, int hr, const double* x,
                        const double* invHs, double* y, hipStream_t s) {
-  if (g.ne * 8 < (1LL << 31))
+  const size_t lds = sizeof(double) * (TBX + 2 * hr) * (TBY + 2 * hr) * (g.dim == 3 ? 2 * hr + 1 : 1) +
+                     (sizeof(double) + sizeof(int)) * (size_t)ntap;
+  if (g.ne * 8 < (1LL << 31) && hr >= 0 && hr <= 3)
+    k_filter_lds<<<elem_grid(g), dim3(TBX, TBY, 1), lds, s>>>(g, off, w, ntap, hr, x, invHs, y);
+  else if (g.ne * 8 < (1LL << 31))
     k_filter_b<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);
   else
     k_filter<<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, off, w, ntap, x, invHs, y);

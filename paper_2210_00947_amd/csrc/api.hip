@@ -53,6 +53,7 @@ struct mgar_handle {
   double* tap_w = nullptr;
   int ntap = 0;
   int tap_hr = 0;                         // largest |offset| of a filter tap
+  int pcg_hint = 0;                       // iterations of the last FP64 PCG solve
   bool has_k0 = false;
   int lt = 1;                             // first grid handled by the V-cycle tail kernel
   TailSpec tail;
@@ -85,6 +86,11 @@ struct mgar_handle {
   double g_tol[2] = {-1.0, -1.0};
   int g_max[2] = {-1, -1};
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // the coarsest inverse is built on a side stream, overlapping the solver's
+  // set-up; the main stream waits for it before the first use of Ainv
+  hipStream_t cs = nullptr;
+  hipEvent_t cev0 = nullptr, cev1 = nullptr;
+  bool coarse_pending = false;
   // kernel timing (instrumentation)
   unsigned prof_mask = 0;
   int tag_base = 0;                       // CG iteration of the next eager iteration (timing tags)
@@ -170,12 +176,32 @@ int validate(const mgar_params* p) {
 
 // ------------------------------------------------------------------ MG
 
+// Make the main stream wait for a coarsest-inverse build still running on the
+// side stream (no-op otherwise).
+int sync_coarse(mgar_handle* h) {
+  if (!h->coarse_pending) return MGAR_OK;
+  h->coarse_pending = false;
+  HIPCK(hipStreamWaitEvent(h->s, h->cev1, 0));
+  return MGAR_OK;
+}
+
 int build_hierarchy(mgar_handle* h) {
+  ACK(sync_coarse(h));   // Ainv and dstatus are rewritten below
   if (h->dg0) launch_diag(h->lv[0].g, h->lv[0].k, h->dg0, h->s);
   h->dg0_valid = h->dg0 != nullptr;
   for (int l = 1; l < h->L; ++l) launch_coarsen(h->lv[l - 1].g, h->lv[l].g, h->lv[l - 1].k, h->lv[l].k, h->s);
-  HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->s));
-  launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->s);
+  if (!h->cs) {
+    HIPCK(hipStreamCreateWithFlags(&h->cs, hipStreamNonBlocking));
+    HIPCK(hipEventCreateWithFlags(&h->cev0, hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&h->cev1, hipEventDisableTiming));
+  }
+  // the single-workgroup build runs beside the solver's set-up on the main stream
+  HIPCK(hipEventRecord(h->cev0, h->s));
+  HIPCK(hipStreamWaitEvent(h->cs, h->cev0, 0));
+  HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->cs));
+  launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->cs);
+  HIPCK(hipEventRecord(h->cev1, h->cs));
+  h->coarse_pending = true;
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -291,6 +317,7 @@ int profile_harvest(mgar_handle* h, int cutoff = 1 << 30) {
 // dot_part set, the finest post-smoother also writes partials of b0 . out.
 int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, double* dot_part,
            const int* done, int tag = -1, unsigned* dcnt = nullptr, double* dout = nullptr) {
+  ACK(sync_coarse(h));
   const int L = h->L;
   const double w = h->p.omega;
   if (L == 1) {
@@ -369,6 +396,7 @@ int stencil32(mgar_handle* h, int level, int mode, const float* x, const float* 
 // K0 := K(BF16 densities of `dens`): cell means of every coarser grid in FP32
 // and the coarsest inverse in FP64.
 int build_hierarchy32(mgar_handle* h) {
+  ACK(sync_coarse(h));
   const int L = h->L;
   h->dg0_valid = false;   // lv[0].k no longer describes the preconditioner's K0
   launch_copy_u16(h->dens, h->dens0, h->E, h->s);
@@ -388,6 +416,7 @@ int build_hierarchy32(mgar_handle* h) {
 // One FP32 V-cycle on the BF16/FP32 K0 hierarchy (same sequence as vcycle()).
 int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, double* dot_part,
              const int* done) {
+  ACK(sync_coarse(h));
   const int L = h->L;
   if (L == 1) {
     launch_coarse_solve_t<float>(h->lv[0].g, h->Ainv, b0, out, done, h->s);
@@ -494,6 +523,7 @@ void drop_graphs(mgar_handle* h) {
 // Capture graphs of 1, 2, 4 and 8 iterations of class cls on the handle's
 // own stream (the launch helpers enqueue on h->s, so it is swapped meanwhile).
 int capture_iters(mgar_handle* h, int cls, double tol, int cg_max, int nr) {
+  ACK(sync_coarse(h));   // no cross-stream wait inside a capture
   for (int k = 0; k < 4; ++k) {
     if (h->gx[cls][k]) (void)hipGraphExecDestroy(h->gx[cls][k]);
     if (h->gg[cls][k]) (void)hipGraphDestroy(h->gg[cls][k]);
@@ -531,6 +561,9 @@ int capture_iters(mgar_handle* h, int cls, double tol, int cg_max, int nr) {
 // unless graphs are off or kernel timing is on (then eager launches).
 int run_iters(mgar_handle* h, int cls, double tol, int cg_max, int n, int nr) {
   if (n <= 0) return MGAR_OK;
+  // replayed graphs run on another stream behind an event of h->s: the wait for
+  // a coarsest inverse still being built must be on h->s before that event
+  ACK(sync_coarse(h));
   if (!h->use_graphs || h->prof_mask) {
     for (int i = 0; i < n; ++i) ACK(enqueue_iter(h, cls, tol, cg_max, nr, h->tag_base + i));
     h->tag_base += n;
@@ -640,7 +673,9 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
   (void)kfine;   // the iterations apply K(h->kcur)
   h->tag_base = 0;
   int it = 0;
-  int chunk = 3;
+  // first chunk: a little below the previous solve's count (iteration counts
+  // change slowly from one optimisation cycle to the next), else 3
+  int chunk = h->pcg_hint > 6 ? h->pcg_hint - 3 : 3;
   double rr_prev = -1.0;
   int it_prev = 0;
   CgState hs;
@@ -658,7 +693,7 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     if (it >= cg_max) return MGAR_E_HIP;   // the device test must have fired by now
     // predict the remaining iterations from the observed contraction rate
     const double rr = hs.rr;
-    int next = 4;
+    int next = (rr_prev <= 0.0 && h->pcg_hint >= it) ? h->pcg_hint - it + 1 : 4;
     if (rr_prev > 0.0 && rr > 0.0 && it > it_prev) {
       const double rate = std::pow(rr / rr_prev, 0.5 / (double)(it - it_prev));
       const double goal = tol * std::sqrt(hs.qq) / std::sqrt(rr);
@@ -671,6 +706,7 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     chunk = next;
   }
   ACK(profile_harvest(h, hs.iters));
+  h->pcg_hint = hs.iters;
   *iters = hs.iters;
   *conv = hs.converged;
   *relres = (hs.qq > 0.0) ? std::sqrt(hs.rr / hs.qq) : 0.0;
@@ -678,6 +714,7 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
 }
 
 int check_coarse(mgar_handle* h) {
+  ACK(sync_coarse(h));
   int st = 0;
   HIPCK(hipMemcpyAsync(&st, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->s));
   HIPCK(hipStreamSynchronize(h->s));
@@ -768,6 +805,7 @@ const char* mgar_strerror(int code) {
 
 void mgar_destroy(mgar_handle* h) {
   if (!h) return;
+  if (h->cs) (void)hipStreamSynchronize(h->cs);
   for (auto& v : h->lv) {
     if (v.k) (void)hipFree(v.k);
     if (v.b) (void)hipFree(v.b);
@@ -793,6 +831,9 @@ void mgar_destroy(mgar_handle* h) {
   if (h->gs) (void)hipStreamDestroy(h->gs);
   if (h->e0) (void)hipEventDestroy(h->e0);
   if (h->e1) (void)hipEventDestroy(h->e1);
+  if (h->cev0) (void)hipEventDestroy(h->cev0);
+  if (h->cev1) (void)hipEventDestroy(h->cev1);
+  if (h->cs) (void)hipStreamDestroy(h->cs);
   delete h;
 }
 

@@ -304,3 +304,44 @@ def test_mgcg_c2_true_residual():
     r = fep.to_free(fep.q) - K @ t[fep.free]
     assert np.linalg.norm(r) / np.linalg.norm(fep.to_free(fep.q)) < 2e-8
     assert np.all(t[fep.fixed] == 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_c3_bench_configuration_sampled_residuals(precision):
+    """128^3 in the launch configuration bench.py times (the shipped gfx950
+    shapes, hence the fused direction update, the fused first sweep and the
+    two-row kernels): MGCG from zero, then MGAR from that temperature on a
+    nearby design. On 4096 sampled nodes the true residual, each row computed
+    by the oracle's element sum, is within the solve tolerance of ||q|| (a
+    property every component of a residual with ||r|| <= tol ||q|| has), the
+    load equals the oracle's, and Dirichlet nodes are exactly 0."""
+    import torch
+    from paper_2210_00947_amd import tune
+    prob = W.C3
+    h = handle(prob, precision=precision)
+    _, src = tune.autotune(h, h.params, tune.device_arch())
+    assert src in ("cache", "shipped", "timed")
+    if precision == 0:
+        assert h.mgar_tune_get(0, 0, 1)[0] == 2      # the fused apply runs
+    g = fe.Grid(3, prob.nelx, prob.nely, prob.nelz)
+    fixed = fe.fixed_mask_from_box(g, prob.fix_lo, prob.fix_hi)
+    q_or = fe.load_vector(g, W.element_source(prob), fixed)
+    q = _load(prob, h)
+    rng = np.random.default_rng(73)
+    rows = np.concatenate([rng.integers(0, g.nnodes, 4092),
+                           [0, g.nnodes - 1, g.node_id(64, 64, 0), g.node_id(128, 0, 64)]])
+    assert rel_err(host(q)[rows], q_or[rows]) < 1e-14
+    qn = np.linalg.norm(q_or)
+    x0 = W.reseeded_density(prob, 0)
+    x1 = W.perturbed_density(x0, 0)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    s0 = h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    s1 = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+    for st, T, x in ((s0, T0, x0), (s1, T1, x1)):
+        assert st["rc"] == 0
+        t = host(T)
+        assert np.all(t[fixed] == 0.0)
+        r = q_or[rows] - fe.apply_rows(g, fe.simp(x, prob.k0, prob.kmin, prob.penal), t, rows)
+        r[fixed[rows]] = 0.0
+        assert np.abs(r).max() <= 1e-8 * qn

@@ -315,8 +315,19 @@ int profile_harvest(mgar_handle* h, int cutoff = 1 << 30) {
 
 // One V-cycle (Table 1) on the K0 hierarchy: out = MG(K0, b0, x0). With
 // dot_part set, the finest post-smoother also writes partials of b0 . out.
+// Whether vcycle() from a zero guess starts with the fused first sweep +
+// residual on the finest grid (and can take a fused stopping test).
+bool j0resid_fusable(const mgar_handle* h) {
+  const StencilCfg& c = h->scfg[0][0][SM_RESID];
+  return h->L > 1 && h->lt > 0 && h->dg0_valid && !((h->prof_mask >> SM_RESID) & 1u) && c.kind == 2 &&
+         stencil_cfg_valid(h->lv[0].g, c);
+}
+
+// check (optional): the previous CG iteration's stopping test, fused into the
+// first finest-grid kernel; the caller has checked j0resid_fusable().
 int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, double* dot_part,
-           const int* done, int tag = -1, unsigned* dcnt = nullptr, double* dout = nullptr) {
+           const int* done, int tag = -1, unsigned* dcnt = nullptr, double* dout = nullptr,
+           const PFuse* check = nullptr) {
   ACK(sync_coarse(h));
   const int L = h->L;
   const double w = h->p.omega;
@@ -335,7 +346,7 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
     // residual's shape allows it
     const bool fused = l == 0 && !x0 && h->dg0_valid && !((h->prof_mask >> SM_RESID) & 1u) &&
                        launch_j0resid(v.g, b, v.k, h->dg0, v.xa, h->rtmp, w, done, h->s,
-                                      &h->scfg[0][0][SM_RESID]);
+                                      &h->scfg[0][0][SM_RESID], check);
     if (l == 0 && x0) ACK(stencil_at(h, l, SM_JACOBI, x0, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
     else if (!presmoothed && !fused)
       ACK(stencil_at(h, l, SM_JACOBI0, nullptr, v.k, nullptr, b, v.xa, w, nullptr, done, nullptr, tag));
@@ -463,11 +474,22 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
 // or class 1 (FP32 inner solve of the mixed form). No host-side iteration
 // index: the kernels read and advance st->it. tag: CG iteration for the
 // profiler (eager launches only).
-int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int tag) {
+// One PCG iteration; with check_prev it first applies the stopping test of
+// the previous iteration (fused into its first kernel where possible). The
+// caller applies the test of the last enqueued iteration (launch_cg_check).
+int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int tag, bool check_prev) {
   const long long N = h->N;
   const int* done = &h->st->done;
+  const bool fchk = check_prev && cls == 0 && j0resid_fusable(h);
+  if (check_prev && !fchk) launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
   if (cls == 0) {
-    ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, tag));
+    PFuse chk{};
+    chk.st = h->st;
+    chk.rzp = h->pa;
+    chk.nrz = nr;
+    chk.tol = tol;
+    chk.cg_max = cg_max;
+    ACK(vcycle(h, h->cr, nullptr, h->cz, h->pb, done, tag, nullptr, nullptr, fchk ? &chk : nullptr));
     const int nz = (h->L == 1) ? vec_num_blocks(N) : nparts_at(h, 0, SM_JACOBI_DOT);
     // direction update fused into the apply where the shape allows it (p in
     // cp / cp2 by iteration parity), else two launches on cp
@@ -502,7 +524,6 @@ int enqueue_iter(mgar_handle* h, int cls, double tol, int cg_max, int nr, int ta
                                 h->pc, nw, h->p32b);
     }
   }
-  launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
   LAUNCHCK();
   return MGAR_OK;
 }
@@ -540,7 +561,8 @@ int capture_iters(mgar_handle* h, int cls, double tol, int cg_max, int nr) {
     HIPCK(hipStreamBeginCapture(h->gs, hipStreamCaptureModeThreadLocal));
     h->s = h->gs;
     int rc = MGAR_OK;
-    for (int i = 0; i < (1 << k) && rc == MGAR_OK; ++i) rc = enqueue_iter(h, cls, tol, cg_max, nr, -1);
+    for (int i = 0; i < (1 << k) && rc == MGAR_OK; ++i) rc = enqueue_iter(h, cls, tol, cg_max, nr, -1, i > 0);
+    if (rc == MGAR_OK) launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
     h->s = user;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->gs, &g);
@@ -565,7 +587,8 @@ int run_iters(mgar_handle* h, int cls, double tol, int cg_max, int n, int nr) {
   // a coarsest inverse still being built must be on h->s before that event
   ACK(sync_coarse(h));
   if (!h->use_graphs || h->prof_mask) {
-    for (int i = 0; i < n; ++i) ACK(enqueue_iter(h, cls, tol, cg_max, nr, h->tag_base + i));
+    for (int i = 0; i < n; ++i) ACK(enqueue_iter(h, cls, tol, cg_max, nr, h->tag_base + i, i > 0));
+    launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
     h->tag_base += n;
     return MGAR_OK;
   }

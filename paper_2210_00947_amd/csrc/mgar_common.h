@@ -75,6 +75,10 @@ struct CgState {
   int it;                    // iterations done so far (device counter: the launches
                              // of an iteration carry no host iteration index, so a
                              // captured iteration can be replayed)
+  int itn;                   // it + 1, stored by the x/r update for a stopping test
+                             // fused into a later kernel (whose blocks must not read
+                             // it while its block 0 advances it)
+  int pad;
 };
 
 // PCG state of one design of a batch. The iteration counter lives on the

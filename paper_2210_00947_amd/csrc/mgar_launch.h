@@ -30,14 +30,21 @@ enum StencilMode {
 // p_old in their halo while this block writes p.
 // SM_J0RESID: diag = diagonal of K per node, xout receives the sweep.
 // Vectors are of the kernel's value type (double or float).
+// SM_J0RESID with chk set also applies the stopping test of the previous CG
+// iteration first (as launch_cg_check: rzp/nrz then hold the ||r||^2 partials
+// of the x/r update); every block takes the same decision and returns if it
+// fires, block 0 advances st.
 struct PFuse {
   CgState* st;          // it, rz history; st->rz[it & 1] is stored by block 0
   const double* rzp;    // block partials of r . z of this iteration
   int nrz;
-  int pad;
+  int chk;
   void* pbuf[2];
   const void* diag;
   void* xout;
+  double tol;
+  int cg_max;
+  int pad;
 };
 
 // stencil.hip ----------------------------------------------------------------
@@ -94,12 +101,15 @@ inline int launch_papply_dot(const Geo& g, const double* z, const double* k, dou
 // xout = w b / diag, out = b - K xout. Returns false (nothing launched) when cfg
 // is not a two-row z-marching shape. Instantiated for (double, CellD) and
 // (float, CellB).
+// check (optional, FP64 only): the fused stopping test (PFuse::chk); done is
+// then not read.
 template <typename T, typename CL>
 bool launch_j0resid_t(const Geo& g, const T* b, CL k, const T* diag, T* xout, T* out, double omega,
-                      const int* done, hipStream_t s, const StencilCfg* cfg);
+                      const int* done, hipStream_t s, const StencilCfg* cfg, const PFuse* check = nullptr);
 inline bool launch_j0resid(const Geo& g, const double* b, const double* k, const double* diag, double* xout,
-                           double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg) {
-  return launch_j0resid_t<double, CellD>(g, b, CellD{k}, diag, xout, out, omega, done, s, cfg);
+                           double* out, double omega, const int* done, hipStream_t s, const StencilCfg* cfg,
+                           const PFuse* check = nullptr) {
+  return launch_j0resid_t<double, CellD>(g, b, CellD{k}, diag, xout, out, omega, done, s, cfg, check);
 }
 // diag[n] = diagonal of K at node n (h/3 times the sum of its cells, summed in the
 // order of the node formula, in the value type), 3D. Instantiated for

@@ -579,6 +579,31 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   __shared__ T Xs[2][XCAP2];
   __shared__ T Cs[2][CCAP2];
   __shared__ double sh[ZT / MGAR_WAVE];
+  // fused stopping test of the previous iteration (same test as k_cg_check):
+  // every block sums the ||r||^2 partials in the same order and takes the same
+  // decision; the iteration count comes from st->itn, which no block of this
+  // kernel writes
+  if (J0R && fu.chk) {
+    CgState* st = fu.st;
+    if (st->done) return;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < fu.nrz; i += ZT) v += fu.rzp[i];
+    const double rr = block_sum(v, sh);
+    const int itn = st->itn;
+    const bool conv = sqrt(rr) <= fu.tol * sqrt(st->qq);
+    const bool stop = conv || itn >= fu.cg_max;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->it = itn;
+      st->rr = rr;
+      if (stop) {
+        st->done = 1;
+        st->converged = conv ? 1 : 0;
+        st->iters = itn;
+      }
+    }
+    if (stop) return;
+    __syncthreads();   // sh is reused below
+  }
   // direction update: beta from the r.z partials (every block sums them in the
   // same order, so all hold the same value) and the stored r.z history
   T beta = T(0);
@@ -2013,11 +2038,16 @@ template int launch_papply_dot_t<float, CellF>(const Geo&, const float*, CellF, 
 
 template <typename T, typename CL>
 bool launch_j0resid_t(const Geo& g, const T* b, CL k, const T* diag, T* xout, T* out, double omega,
-                      const int* done, hipStream_t s, const StencilCfg* cfg) {
+                      const int* done, hipStream_t s, const StencilCfg* cfg, const PFuse* check) {
   const StencilCfg c = resolve_cfg(g, cfg);
   if (c.kind != 2) return false;
   const ZShape z2 = zmarch_shape(g, c);
   PFuse pf{};
+  if (check && std::is_same_v<T, double>) {
+    pf = *check;
+    pf.chk = 1;
+    done = nullptr;
+  }
   pf.diag = diag;
   pf.xout = xout;
   zmarch_launch<1, true, T, CL>(g, z2, c.kz, SM_J0RESID, b, k, k, b, out, (T)omega, nullptr, done,
@@ -2025,9 +2055,10 @@ bool launch_j0resid_t(const Geo& g, const T* b, CL k, const T* diag, T* xout, T*
   return true;
 }
 template bool launch_j0resid_t<double, CellD>(const Geo&, const double*, CellD, const double*, double*,
-                                              double*, double, const int*, hipStream_t, const StencilCfg*);
+                                              double*, double, const int*, hipStream_t, const StencilCfg*,
+                                              const PFuse*);
 template bool launch_j0resid_t<float, CellB>(const Geo&, const float*, CellB, const float*, float*, float*,
-                                             double, const int*, hipStream_t, const StencilCfg*);
+                                             double, const int*, hipStream_t, const StencilCfg*, const PFuse*);
 
 template <typename T, typename CL>
 void launch_diag_t(const Geo& g, CL k, T* diag, hipStream_t s) {

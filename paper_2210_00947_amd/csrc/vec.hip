@@ -108,6 +108,7 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   if (st->done) return;
   const int it = st->it;
   const T* __restrict__ p = (p_odd && (it & 1)) ? p_odd : p_even;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->itn = it + 1;   // for a fused stopping test
   __shared__ double sh[VB / MGAR_WAVE];
   double pw;
   if (pwp) {

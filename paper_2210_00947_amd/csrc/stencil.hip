@@ -1538,16 +1538,49 @@ __device__ inline void tnode_ijk(const Geo& g, int n, int& i, int& j, int& k) {
   i = r - j * g.nnx;
 }
 
+// LDS layout of the tail: every grid but the coarsest keeps its node vectors
+// and cells with a one-entry halo of zeros on each side, so a neighbour or a
+// cell is one indexed read with no bounds test; the coarsest grid (solved
+// through its inverse, which is indexed by node number) is unpadded.
+struct TPad {
+  int sx, sxy;     // node strides of the padded layout
+  int cx, cxy;     // cell strides
+};
+template <int DIM>
+__device__ inline TPad tpad(const Geo& g) {
+  TPad p;
+  p.sx = g.nnx + 2;
+  p.sxy = p.sx * (g.nny + 2);
+  p.cx = g.nx + 2;
+  p.cxy = p.cx * (g.ny + 2);
+  return p;
+}
+template <int DIM>
+__device__ inline int pnode(const TPad& p, int i, int j, int k) {
+  return (i + 1) + p.sx * (j + 1) + (DIM == 3 ? p.sxy * (k + 1) : 0);
+}
+template <int DIM>
+__device__ inline int pcell(const TPad& p, int ex, int ey, int ez) {
+  return (ex + 1) + p.cx * (ey + 1) + (DIM == 3 ? p.cxy * (ez + 1) : 0);
+}
+
 template <int DIM, int MODE, typename T>
 __device__ void tail_stencil(const Geo& g, const T* x, const T* k, const T* b, T* out, T omega) {
+  const TPad pd = tpad<DIM>(g);
   for (int n = threadIdx.x; n < (int)g.nn; n += TT) {
     int i, j, kz;
     tnode_ijk(g, n, i, j, kz);
+    const int P = pnode<DIM>(pd, i, j, kz);
     T r = T(0);
     if (!geo_fixed(g, i, j, kz)) {
       T kv[2][2][2];
-      const CellP<T> kl{k};
-      load_cells<DIM, false>(g, kl, kl, i, j, kz, kv);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            kv[c][bb][a] = (DIM == 2 && c == 1) ? T(0) : k[pcell<DIM>(pd, i - 1 + a, j - 1 + bb, kz - 1 + c)];
       T ks = T(0), y = T(0);
       if (MODE == SM_JACOBI0) {
 #pragma unroll
@@ -1556,41 +1589,78 @@ __device__ void tail_stencil(const Geo& g, const T* x, const T* k, const T* b, T
           for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int a = 0; a < 2; ++a) ks += kv[c][bb][a];
+      } else if (DIM == 2) {
+        T xv[3][3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) xv[dy][dx] = x[P + (dx - 1) + pd.sx * (dy - 1)];
+        T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int sx = a ? 2 : 0, sy = bb ? 2 : 0;
+            const T ke = kv[0][bb][a];
+            s0 += ke;
+            s1 += ke * (xv[1][sx] + xv[sy][1]);
+            s2 += ke * xv[sy][sx];
+          }
+        ks = s0;
+        y = T(2.0 / 3.0) * s0 * xv[1][1] - T(1.0 / 6.0) * s1 - T(1.0 / 3.0) * s2;
       } else {
-        y = node_apply<DIM, T>(g, x, i, j, kz, kv, ks);
+        T xv[3][3][3];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              const int nzr = (dx != 1) + (dy != 1) + (dz != 1);
+              xv[dz][dy][dx] = (nzr == 1) ? T(0) : x[P + (dx - 1) + pd.sx * (dy - 1) + pd.sxy * (dz - 1)];
+            }
+        y = apply27<T, true>(xv[0], xv[1], xv[2], kv[0], kv[1], T(g.h * (1.0 / 3.0)), T(g.h * (1.0 / 12.0)), ks);
       }
       const T diag = T(DIM == 3 ? g.h * (1.0 / 3.0) : (2.0 / 3.0)) * ks;
-      if (MODE == SM_JACOBI0) r = omega * b[n] / diag;
-      else if (MODE == SM_RESID) r = b[n] - y;
-      else r = x[n] + omega * (b[n] - y) / diag;   // SM_JACOBI
+      if (MODE == SM_JACOBI0) r = omega * b[P] / diag;
+      else if (MODE == SM_RESID) r = b[P] - y;
+      else r = x[P] + omega * (b[P] - y) / diag;   // SM_JACOBI
     }
-    out[n] = r;
+    out[P] = r;
   }
 }
 
+// rc = P^T rf; rf padded, rc padded unless cpad is false (the coarsest grid)
 template <int DIM, typename T>
-__device__ void tail_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc) {
+__device__ void tail_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, bool cpad) {
+  const TPad pf = tpad<DIM>(gf), pc = tpad<DIM>(gc);
   for (int n = threadIdx.x; n < (int)gc.nn; n += TT) {
     int I, J, K;
     tnode_ijk(gc, n, I, J, K);
     T s = T(0);
     if (!geo_fixed(gc, I, J, K)) {
+#pragma unroll
       for (int c = (DIM == 3 ? -1 : 0); c <= (DIM == 3 ? 1 : 0); ++c) {
         T sy = T(0);
-        for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+        for (int bb = -1; bb <= 1; ++bb) {
           T sx = T(0);
-          for (int a = -1; a <= 1; ++a) sx += T(a == 0 ? 1.0 : 0.5) * ldx(gf, rf, 2 * I + a, 2 * J + b, 2 * K + c);
-          sy += T(b == 0 ? 1.0 : 0.5) * sx;
+#pragma unroll
+          for (int a = -1; a <= 1; ++a)
+            sx += T(a == 0 ? 1.0 : 0.5) * rf[pnode<DIM>(pf, 2 * I + a, 2 * J + bb, 2 * K + c)];
+          sy += T(bb == 0 ? 1.0 : 0.5) * sx;
         }
         s += T(c == 0 ? 1.0 : 0.5) * sy;
       }
     }
-    rc[n] = s;
+    rc[cpad ? pnode<DIM>(pc, I, J, K) : n] = s;
   }
 }
 
+// xf += P xc on free fine nodes; xf padded, xc padded unless cpad is false
 template <int DIM, typename T>
-__device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf) {
+__device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf, bool cpad) {
+  const TPad pf = tpad<DIM>(gf), pc = tpad<DIM>(gc);
   for (int n = threadIdx.x; n < (int)gf.nn; n += TT) {
     int i, j, k;
     tnode_ijk(gf, n, i, j, k);
@@ -1600,19 +1670,22 @@ __device__ void tail_prolong(const Geo& gf, const Geo& gc, const T* xc, T* xf) {
     const T wi = T((i & 1) ? 0.5 : 1.0), wj = T((j & 1) ? 0.5 : 1.0),
             wk = T((DIM == 3 && (k & 1)) ? 0.5 : 1.0);
     // the 2^d coarse corners, the upper ones weighted 0 on even fine indices
-    // (their clamped loads stay in the grid): no branch around the loads
+    // (their indices stay in the grid): no branch around the loads
     const T mi = T(ni - 1), mj = T(nj - 1), mk = T(nk - 1);
     const int I1 = I0 + ni - 1, J1 = J0 + nj - 1, K1 = K0 + nk - 1;
+    auto cv = [&](int a, int b, int c) -> T {
+      return xc[cpad ? pnode<DIM>(pc, a, b, c) : a + gc.nnx * (b + gc.nny * c)];
+    };
     T sc[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int kc = c ? K1 : K0;
-      const T sx0 = xc[geo_node(gc, I0, J0, kc)] + mi * xc[geo_node(gc, I1, J0, kc)];
-      const T sx1 = xc[geo_node(gc, I0, J1, kc)] + mi * xc[geo_node(gc, I1, J1, kc)];
+      const T sx0 = cv(I0, J0, kc) + mi * cv(I1, J0, kc);
+      const T sx1 = cv(I0, J1, kc) + mi * cv(I1, J1, kc);
       sc[c] = wi * sx0 + mj * (wi * sx1);
     }
     const T s = wj * sc[0] + mk * (wj * sc[1]);
-    xf[n] += wk * s;
+    xf[pnode<DIM>(pf, i, j, k)] += wk * s;
   }
 }
 
@@ -1668,9 +1741,27 @@ __device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin,
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int nl = TS.nl;
-  for (int l = 0; l < nl; ++l)
-    for (int e = threadIdx.x; e < (int)TS.g[l].ne; e += TT) lds[TS.off_k[l] + e] = static_cast<const T*>(TS.k[l])[e];
-  for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) lds[TS.off_b[0] + n] = bin[n];
+  // halos (and everything else) start at 0
+  for (int e = threadIdx.x; e < TS.lds_elems; e += TT) lds[e] = T(0);
+  __syncthreads();
+  for (int l = 0; l + 1 < nl; ++l) {
+    const Geo& g = TS.g[l];
+    const TPad pd = tpad<DIM>(g);
+    const T* kg = static_cast<const T*>(TS.k[l]);
+    for (int e = threadIdx.x; e < (int)g.ne; e += TT) {
+      const int ex = e % g.nx, r = e / g.nx, ey = r % g.ny, ez = r / g.ny;
+      lds[TS.off_k[l] + pcell<DIM>(pd, ex, ey, ez)] = kg[e];
+    }
+  }
+  {
+    const Geo& g = TS.g[0];
+    const TPad pd = tpad<DIM>(g);
+    for (int n = threadIdx.x; n < (int)g.nn; n += TT) {
+      int i, j, k;
+      tnode_ijk(g, n, i, j, k);
+      lds[TS.off_b[0] + (nl > 1 ? pnode<DIM>(pd, i, j, k) : n)] = bin[n];
+    }
+  }
   // issued after the loads above, so waiting for those does not wait for these
   CoarsePre cp;
   tail_coarse_prefetch((int)TS.g[nl - 1].nn, Ainv, cp);
@@ -1685,7 +1776,7 @@ __device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin,
     __syncthreads();
     tail_stencil<DIM, SM_RESID, T>(g, xa, kk, b, xb, omega);
     __syncthreads();
-    tail_restrict<DIM, T>(g, TS.g[l + 1], xb, lds + TS.off_b[l + 1]);
+    tail_restrict<DIM, T>(g, TS.g[l + 1], xb, lds + TS.off_b[l + 1], l + 2 < nl);
     __syncthreads();
   }
   tail_coarse(cp, Ainv, lds + TS.off_b[nl - 1], lds + TS.off_xa[nl - 1]);
@@ -1695,13 +1786,21 @@ __device__ inline void vtail_body(const TailSpec& TS, const T* __restrict__ bin,
     const Geo& g = TS.g[l];
     T* xa = lds + TS.off_xa[l];
     T* xb = lds + TS.off_xb[l];
-    tail_prolong<DIM, T>(g, TS.g[l + 1], xfin, xa);
+    tail_prolong<DIM, T>(g, TS.g[l + 1], xfin, xa, l + 2 < nl);
     __syncthreads();
     tail_stencil<DIM, SM_JACOBI, T>(g, xa, lds + TS.off_k[l], lds + TS.off_b[l], xb, omega);
     __syncthreads();
     xfin = xb;
   }
-  for (int n = threadIdx.x; n < (int)TS.g[0].nn; n += TT) xout[n] = xfin[n];
+  {
+    const Geo& g = TS.g[0];
+    const TPad pd = tpad<DIM>(g);
+    for (int n = threadIdx.x; n < (int)g.nn; n += TT) {
+      int i, j, k;
+      tnode_ijk(g, n, i, j, k);
+      xout[n] = xfin[nl > 1 ? pnode<DIM>(pd, i, j, k) : n];
+    }
+  }
 }
 
 template <int DIM, typename T>
@@ -2208,15 +2307,20 @@ template void launch_coarse_solve_t<float>(const Geo&, const double*, const floa
 bool tail_plan(const Geo* g, const void* const* k, int lt, int L, size_t elem, TailSpec* T) {
   const int nl = L - lt;
   if (nl < 1 || nl > MGAR_MAX_TAIL) return false;
+  // grids above the coarsest: node vectors and cells with a one-entry halo;
+  // the coarsest: its right side and solution only, unpadded
   int off = 0;
   for (int l = 0; l < nl; ++l) {
     const Geo& gl = g[lt + l];
     T->g[l] = gl;
     T->k[l] = k[lt + l];
-    T->off_b[l] = off; off += (int)gl.nn;
-    T->off_xa[l] = off; off += (int)gl.nn;
-    T->off_xb[l] = off; off += (int)gl.nn;
-    T->off_k[l] = off; off += (int)gl.ne;
+    const bool last = l + 1 == nl, d3 = gl.dim == 3;
+    const int nn = last ? (int)gl.nn : (gl.nnx + 2) * (gl.nny + 2) * (d3 ? gl.nnz + 2 : 1);
+    const int ne = last ? 0 : (gl.nx + 2) * (gl.ny + 2) * (d3 ? gl.nz + 2 : 1);
+    T->off_b[l] = off; off += nn;
+    T->off_xa[l] = off; off += nn;
+    T->off_xb[l] = off; off += last ? 0 : nn;
+    T->off_k[l] = off; off += ne;
   }
   T->nl = nl;
   T->lds_elems = off;

@@ -268,7 +268,7 @@ int stencil_at(mgar_handle* h, int level, int mode, const double* x, const doubl
 int papply_at(mgar_handle* h, const double* z, const PFuse& pf, const int* done, int* nparts, int tag) {
   const Geo& g = h->lv[0].g;
   const StencilCfg* cfg = &h->scfg[0][0][SM_APPLY_DOT];
-  if (cfg->kind != 2 || !stencil_cfg_valid(g, *cfg)) {
+  if (!papply_supported(g, cfg)) {
     *nparts = -1;
     return MGAR_OK;
   }
@@ -624,10 +624,7 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
     HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
     if (hs.done) break;
-    if (it >= max_it) {   // the refinement's iteration budget is spent
-      *iters = hs.it;
-      return MGAR_OK;
-    }
+    if (it >= max_it) break;   // the refinement's iteration budget is spent
     // the next chunk from the observed contraction rate (the initial residual
     // ||r_0||^2 is st->qq here), as in pcg
     const double rr = hs.rr;
@@ -643,7 +640,11 @@ int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
     rr_prev = rr;
     it_prev = hs.it;
   }
-  *iters = hs.iters;
+  // the update of d of the last iteration may still be pending (fused path)
+  if (papply_supported(h->lv[0].g, &h->scfg[1][0][SM_APPLY_DOT]))
+    launch_cg_flush_t<float>(h->d32, h->p32, N, h->st, h->s);
+  LAUNCHCK();
+  *iters = hs.done ? hs.iters : hs.it;
   return MGAR_OK;
 }
 
@@ -728,6 +729,10 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     it_prev = it;
     chunk = next;
   }
+  // the x update of the last iteration may still be pending (fused path)
+  if (papply_supported(h->lv[0].g, &h->scfg[0][0][SM_APPLY_DOT]))
+    launch_cg_flush_t<double>(h->cx, h->cp, N, h->st, h->s);
+  LAUNCHCK();
   ACK(profile_harvest(h, hs.iters));
   h->pcg_hint = hs.iters;
   *iters = hs.iters;

@@ -69,6 +69,7 @@ struct CgState {
   double rr;                 // latest ||r||^2
   double rz[2];              // r.z by iteration parity
   double pw;                 // p.(K p)
+  double pwh[2];             // p.(K p) by iteration parity (deferred x updates)
   int done;                  // set once the stopping test fires
   int iters;                 // iterations performed at exit
   int converged;             // 1 = tolerance met, 0 = cg_max reached

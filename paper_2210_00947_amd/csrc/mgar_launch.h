@@ -87,6 +87,8 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg = nullptr);
 // SM_PAPPLY_DOT on grid g with launch shape cfg: returns the number of block
 // partials of p . out written to part, or -1 (nothing launched) when cfg is not
 // a two-row z-marching shape (then p is updated and applied by separate launches).
+// Whether launch_papply_dot_t runs the fused kernel for this grid and shape.
+bool papply_supported(const Geo& g, const StencilCfg* cfg);
 // Instantiated for (double, CellD) and (float, CellF).
 template <typename T, typename CL>
 int launch_papply_dot_t(const Geo& g, const T* z, CL k, T* out, double* part, const int* done,
@@ -211,6 +213,10 @@ template <typename T>
 int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState* st, double* part,
                        unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp = nullptr,
                        int npw = 0, const T* p_odd = nullptr);
+// Pending x update of a loop run with p_odd (see k_cg_update): x += a_k p_k
+// when the last completed iteration k is even; a no-op otherwise.
+template <typename T>
+void launch_cg_flush_t(T* x, const T* p_even, long long n, const CgState* st, hipStream_t s);
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
@@ -227,8 +233,9 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
                     double tol, int cg_max, hipStream_t s);
 void launch_p_update(const double* z, double* p, long long n, CgState* st, hipStream_t s,
                      const double* rzp = nullptr, int np = 0);
-// x += alpha p, r -= alpha w and partials of ||r||^2 (p: p_odd on odd
-// iterations when given, the direction buffers of SM_PAPPLY_DOT); with cnt != null the sum
+// x += alpha p, r -= alpha w and partials of ||r||^2 (with p_odd, the
+// direction buffers of SM_PAPPLY_DOT, p_odd on odd iterations, and x updated
+// every second iteration: see launch_cg_flush_t); with cnt != null the sum
 // is also reduced in the launch, st->it advanced and the stopping test applied
 // by the last block (costs a device-scope fence per block).
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,

@@ -2113,6 +2113,8 @@ bool stencil_records_events(const Geo& g, const StencilCfg* cfg) {
   return true;   // every stencil launch path takes kernel start/end events
 }
 
+bool papply_supported(const Geo& g, const StencilCfg* cfg) { return resolve_cfg(g, cfg).kind == 2; }
+
 template <typename T, typename CL>
 int launch_papply_dot_t(const Geo& g, const T* z, CL k, T* out, double* part, const int* done,
                         hipStream_t s, const PFuse& pf, const StencilCfg* cfg, hipEvent_t ev0,

@@ -95,7 +95,11 @@ __global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __r
 // iteration it+1 (||r|| <= tol ||q||, or it+1 == cg_max). With pwp set, p . w
 // is first summed from its npw block partials by every block (same order in
 // each) and block 0 stores it to st->pw; otherwise st->pw already holds it.
-// With p_odd set, the direction of an odd iteration is read from p_odd.
+// With p_odd set, the direction of an odd iteration is read from p_odd, and
+// the x update is deferred by one iteration: an even iteration updates r only,
+// the next (odd) one applies both directions to x, x += a_(it-1) p_(it-1) +
+// a_it p_it, in that order (the same two updates; one pass over x instead of
+// two). k_cg_flush applies a pending update once the loop stops.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ p_even,
@@ -117,13 +121,26 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   } else {
     pw = st->pw;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->pwh[it & 1] = pw;
   const T alpha = (T)(st->rz[it & 1] / pw);
   double s = 0.0;
-  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
-    x[i] += alpha * p[i];
-    const T ri = r[i] - alpha * w[i];
-    r[i] = ri;
-    s += (double)ri * (double)ri;
+  if (p_odd) {
+    const bool odd = it & 1;
+    // the pending update of the previous (even) iteration
+    const T alpha0 = odd ? (T)(st->rz[(it - 1) & 1] / st->pwh[(it - 1) & 1]) : T(0);
+    for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+      if (odd) x[i] = (x[i] + alpha0 * p_even[i]) + alpha * p_odd[i];
+      const T ri = r[i] - alpha * w[i];
+      r[i] = ri;
+      s += (double)ri * (double)ri;
+    }
+  } else {
+    for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+      x[i] += alpha * p[i];
+      const T ri = r[i] - alpha * w[i];
+      r[i] = ri;
+      s += (double)ri * (double)ri;
+    }
   }
   s = block_sum(s, sh);
   if (!cnt) {
@@ -159,6 +176,18 @@ __global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __re
       st->done = 1; st->converged = 0; st->iters = it;
     }
   }
+}
+
+// After a loop with deferred x updates (k_cg_update with p_odd): the update of
+// the last iteration is still pending when that iteration was even.
+template <typename T>
+__global__ __launch_bounds__(VB) void k_cg_flush(T* __restrict__ x, const T* __restrict__ p_even, long long n,
+                                                 const CgState* __restrict__ st) {
+  const int k = st->it - 1;   // last completed iteration
+  if (k < 0 || (k & 1)) return;
+  const T alpha = (T)(st->rz[k & 1] / st->pwh[k & 1]);
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
+    x[i] += alpha * p_even[i];
 }
 
 __global__ __launch_bounds__(VB) void k_copy(const double* __restrict__ a, double* __restrict__ b,
@@ -800,6 +829,13 @@ template int launch_cg_update_t<double>(double*, double*, const double*, const d
 template int launch_cg_update_t<float>(float*, float*, const float*, const float*, long long,
                                        CgState*, double*, unsigned*, double, int, hipStream_t,
                                        const double*, int, const float*);
+
+template <typename T>
+void launch_cg_flush_t(T* x, const T* p_even, long long n, const CgState* st, hipStream_t s) {
+  k_cg_flush<T><<<vec_num_blocks(n), VB, 0, s>>>(x, p_even, n, st);
+}
+template void launch_cg_flush_t<double>(double*, const double*, long long, const CgState*, hipStream_t);
+template void launch_cg_flush_t<float>(float*, const float*, long long, const CgState*, hipStream_t);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
                      CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,

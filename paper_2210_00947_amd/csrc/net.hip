@@ -13,6 +13,7 @@
 // nodes: scale * trilinear interpolation of u between coarse cell centres
 // (finest nodes f*i + f/2), clamped at the outermost centres, Dirichlet 0.
 // Training target: y = T at the centre nodes / scale; loss = mean (u - y)^2.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -103,99 +104,151 @@ __global__ __launch_bounds__(NB) void k_net_to_nodes(Geo g, const float* __restr
 // ---------------------------------------------------------------- layers
 
 // out[co][v] = b[co] + sum_ci sum_taps w[co][ci][t] in[ci][v + t - 1] (zero
-// padding), optional ReLU. One thread per (voxel, co); co = blockIdx.y.
+// padding), optional ReLU. One thread per voxel and group of four output
+// channels (blockIdx.y).
 template <bool RELU>
 __global__ __launch_bounds__(NB) void k_conv_fwd(const float* __restrict__ in, int Ci,
                                                  const float* __restrict__ w, const float* __restrict__ b,
-                                                 float* __restrict__ out, int D, int H, int W) {
+                                                 float* __restrict__ out, int Co, int D, int H, int W) {
+  // CT output channels per thread share each loaded input; taps outside the
+  // grid load a clamped neighbour weighted 0 (no branch between the loads)
+  constexpr int CT = 4;
   const int v = blockIdx.x * NB + threadIdx.x;
-  const int co = blockIdx.y;
+  const int c0 = blockIdx.y * CT;
   if (v >= D * H * W) return;
   const int x = v % W, y = (v / W) % H, z = v / (W * H);
-  double s = (double)b[co];
+  double s[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) s[c] = (double)b[min(c0 + c, Co - 1)];
   for (int ci = 0; ci < Ci; ++ci) {
-    const float* wp = w + (co * Ci + ci) * 27;
-    for (int dz = 0; dz < 3; ++dz) {
-      const int zz = z + dz - 1;
-      if (zz < 0 || zz >= D) continue;
-      for (int dy = 0; dy < 3; ++dy) {
-        const int yy = y + dy - 1;
-        if (yy < 0 || yy >= H) continue;
+    double xin[27];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          const int xx = x + dx - 1;
-          if (xx < 0 || xx >= W) continue;
-          s += (double)wp[(dz * 3 + dy) * 3 + dx] * (double)in[cidx(ci, zz, yy, xx, D, H, W)];
+          const int zz = z + dz - 1, yy = y + dy - 1, xx = x + dx - 1;
+          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+          const float val = in[cidx(ci, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
+                                    D, H, W)];
+          xin[(dz * 3 + dy) * 3 + dx] = (double)val * (ok ? 1.0 : 0.0);
         }
-      }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const float* wp = w + (min(c0 + c, Co - 1) * Ci + ci) * 27;
+#pragma unroll
+      for (int q = 0; q < 27; ++q) s[c] += (double)wp[q] * xin[q];
     }
   }
-  const float r = (float)s;
-  out[co * D * H * W + v] = RELU ? fmaxf(r, 0.0f) : r;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (c0 + c >= Co) break;
+    const float r = (float)s[c];
+    out[(c0 + c) * D * H * W + v] = RELU ? fmaxf(r, 0.0f) : r;
+  }
 }
 
-// gin[ci][v] = sum_co sum_taps w[co][ci][t] gout[co][v - t + 1]; ci = blockIdx.y.
+// gin[ci][v] = sum_co sum_taps w[co][ci][t] gout[co][v - t + 1], CT input
+// channels per thread (blockIdx.y groups them), masked taps as in k_conv_fwd.
 __global__ __launch_bounds__(NB) void k_conv_bwd_data(const float* __restrict__ gout, int Co,
                                                       const float* __restrict__ w, int Ci,
                                                       float* __restrict__ gin, int D, int H, int W) {
+  constexpr int CT = 4;
   const int v = blockIdx.x * NB + threadIdx.x;
-  const int ci = blockIdx.y;
+  const int c0 = blockIdx.y * CT;
   if (v >= D * H * W) return;
   const int x = v % W, y = (v / W) % H, z = v / (W * H);
-  double s = 0.0;
+  double s[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) s[c] = 0.0;
   for (int co = 0; co < Co; ++co) {
-    const float* wp = w + (co * Ci + ci) * 27;
-    for (int dz = 0; dz < 3; ++dz) {
-      const int zz = z - dz + 1;
-      if (zz < 0 || zz >= D) continue;
-      for (int dy = 0; dy < 3; ++dy) {
-        const int yy = y - dy + 1;
-        if (yy < 0 || yy >= H) continue;
+    double g[27];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          const int xx = x - dx + 1;
-          if (xx < 0 || xx >= W) continue;
-          s += (double)wp[(dz * 3 + dy) * 3 + dx] * (double)gout[cidx(co, zz, yy, xx, D, H, W)];
+          const int zz = z - dz + 1, yy = y - dy + 1, xx = x - dx + 1;
+          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+          const float val = gout[cidx(co, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
+                                      D, H, W)];
+          g[(dz * 3 + dy) * 3 + dx] = (double)val * (ok ? 1.0 : 0.0);
         }
-      }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const float* wp = w + (co * Ci + min(c0 + c, Ci - 1)) * 27;
+#pragma unroll
+      for (int q = 0; q < 27; ++q) s[c] += (double)wp[q] * g[q];
     }
   }
-  gin[ci * D * H * W + v] = (float)s;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (c0 + c >= Ci) break;
+    gin[(c0 + c) * D * H * W + v] = (float)s[c];
+  }
 }
 
-// gw[co][ci][t] = sum_v gout[co][v] in[ci][v + t - 1]; gb[co] = sum_v gout[co][v].
-// One block per (co, ci) = (blockIdx.y, blockIdx.x), fixed-order reduction.
-__global__ __launch_bounds__(NB) void k_conv_bwd_weight(const float* __restrict__ in, int Ci,
-                                                        const float* __restrict__ gout,
-                                                        float* __restrict__ gw, float* __restrict__ gb,
-                                                        int D, int H, int W) {
-  __shared__ double sh[NB / MGAR_WAVE];
-  const int ci = blockIdx.x, co = blockIdx.y;
-  const int V = D * H * W;
-  double acc[27];
-  for (int t = 0; t < 27; ++t) acc[t] = 0.0;
-  double bs = 0.0;
-  for (int v = threadIdx.x; v < V; v += NB) {
-    const int x = v % W, y = (v / W) % H, z = v / (W * H);
+// gw[co][ci][t] = sum_v gout[co][v] in[ci][v + t - 1]; gb[co] = sum_v gout[co][v],
+// in two stages with more parallelism: block (ci, co, s)
+// sums over the z-slab s of WZ planes (loads clamped into the grid and
+// weighted 0 outside it, so the 27 tap loads of a voxel have no branch), each
+// wave reduces by shuffles, and the waves of the block in order; part holds
+// 28 sums (27 taps, then the bias term) per (co, ci, s). k_conv_bwd_weight_sum
+// adds the slabs in order.
+constexpr int WZ = 4;
+__global__ __launch_bounds__(NB) void k_conv_bwd_weight_part(const float* __restrict__ in, int Ci,
+                                                             const float* __restrict__ gout,
+                                                             double* __restrict__ part, int D, int H, int W) {
+  __shared__ double sh[NB / MGAR_WAVE][28];
+  const int ci = blockIdx.x, co = blockIdx.y, sl = blockIdx.z, S = gridDim.z;
+  const int V = D * H * W, HW = H * W;
+  const int z0 = sl * WZ, z1 = min(z0 + WZ, D);
+  double acc[28];
+#pragma unroll
+  for (int t = 0; t < 28; ++t) acc[t] = 0.0;
+  for (int v = z0 * HW + threadIdx.x; v < z1 * HW; v += NB) {
+    const int x = v % W, y = (v / W) % H, z = v / HW;
     const double go = (double)gout[co * V + v];
-    bs += go;
-    for (int dz = 0; dz < 3; ++dz) {
-      const int zz = z + dz - 1;
-      const bool oz = zz >= 0 && zz < D;
-      for (int dy = 0; dy < 3; ++dy) {
-        const int yy = y + dy - 1;
-        const bool oy = oz && yy >= 0 && yy < H;
+    acc[27] += go;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          const int xx = x + dx - 1;
-          if (oy && xx >= 0 && xx < W) acc[(dz * 3 + dy) * 3 + dx] += go * (double)in[cidx(ci, zz, yy, xx, D, H, W)];
+          const int zz = z + dz - 1, yy = y + dy - 1, xx = x + dx - 1;
+          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+          const float val = in[cidx(ci, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
+                                    D, H, W)];
+          acc[(dz * 3 + dy) * 3 + dx] += go * ((double)val * (ok ? 1.0 : 0.0));
         }
-      }
-    }
   }
-  for (int t = 0; t < 27; ++t) {
-    const double s = block_sum(acc[t], sh);
-    if (threadIdx.x == 0) gw[(co * Ci + ci) * 27 + t] = (float)s;
+  const int lane = threadIdx.x % MGAR_WAVE, wv = threadIdx.x / MGAR_WAVE;
+#pragma unroll
+  for (int t = 0; t < 28; ++t) {
+    const double s = wave_sum(acc[t]);
+    if (lane == 0) sh[wv][t] = s;
   }
-  const double sb = block_sum(bs, sh);
-  if (ci == 0 && threadIdx.x == 0) gb[co] = (float)sb;
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    double s = 0.0;
+    for (int w = 0; w < NB / MGAR_WAVE; ++w) s += sh[w][threadIdx.x];
+    part[((co * Ci + ci) * S + sl) * 28 + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(NB) void k_conv_bwd_weight_sum(const double* __restrict__ part, int Ci, int Co,
+                                                            int S, float* __restrict__ gw,
+                                                            float* __restrict__ gb) {
+  const int q = blockIdx.x * NB + threadIdx.x;   // (co * Ci + ci) * 28 + t
+  if (q >= Co * Ci * 28) return;
+  const int t = q % 28, cc = q / 28, ci = cc % Ci, co = cc / Ci;
+  double s = 0.0;
+  for (int sl = 0; sl < S; ++sl) s += part[(cc * S + sl) * 28 + t];
+  if (t < 27) gw[cc * 27 + t] = (float)s;
+  else if (ci == 0) gb[co] = (float)s;
 }
 
 __global__ __launch_bounds__(NB) void k_relu_bwd(float* __restrict__ g, const float* __restrict__ act, int n) {
@@ -301,28 +354,31 @@ struct mgar_net {
   float *gU = nullptr, *gA5 = nullptr, *gCat = nullptr, *gA4 = nullptr, *gA3 = nullptr, *gPool = nullptr,
         *gA2 = nullptr, *gA1 = nullptr;
   double *part = nullptr, *loss = nullptr;
+  double* wpart = nullptr;   // per-slab partial sums of the weight gradients
   int t = 0;   // Adam steps taken
 };
 
 namespace {
 
 int conv(mgar_net* N, int layer, const float* in, float* out, bool relu, int D, int H, int W) {
-  const dim3 grid(nblk((long long)D * H * W), N->co[layer]);
+  const dim3 grid(nblk((long long)D * H * W), (N->co[layer] + 3) / 4);
   const float* w = N->theta + N->woff[layer];
   const float* b = N->theta + N->boff[layer];
-  if (relu) k_conv_fwd<true><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, D, H, W);
-  else k_conv_fwd<false><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, D, H, W);
+  if (relu) k_conv_fwd<true><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
+  else k_conv_fwd<false><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
   NLAUNCH();
   return MGAR_OK;
 }
 
 // weight and bias gradients of `layer`, and (gin != null) its input gradient
 int conv_bwd(mgar_net* N, int layer, const float* in, const float* gout, float* gin, int D, int H, int W) {
-  const dim3 gw(N->ci[layer], N->co[layer]);
-  k_conv_bwd_weight<<<gw, NB, 0, N->s>>>(in, N->ci[layer], gout, N->grad + N->woff[layer],
-                                          N->grad + N->boff[layer], D, H, W);
+  const int S = (D + WZ - 1) / WZ;
+  const dim3 gw(N->ci[layer], N->co[layer], S);
+  k_conv_bwd_weight_part<<<gw, NB, 0, N->s>>>(in, N->ci[layer], gout, N->wpart, D, H, W);
+  k_conv_bwd_weight_sum<<<nblk((long long)N->co[layer] * N->ci[layer] * 28), NB, 0, N->s>>>(
+      N->wpart, N->ci[layer], N->co[layer], S, N->grad + N->woff[layer], N->grad + N->boff[layer]);
   if (gin) {
-    const dim3 gd(nblk((long long)D * H * W), N->ci[layer]);
+    const dim3 gd(nblk((long long)D * H * W), (N->ci[layer] + 3) / 4);
     k_conv_bwd_data<<<gd, NB, 0, N->s>>>(gout, N->co[layer], N->theta + N->woff[layer], N->ci[layer], gin, D,
                                          H, W);
   }
@@ -391,7 +447,7 @@ void mgar_net_destroy(mgar_net* n) {
                   (void*)n->a2, (void*)n->pool, (void*)n->a3, (void*)n->a4, (void*)n->cat, (void*)n->a5,
                   (void*)n->u, (void*)n->y, (void*)n->gU, (void*)n->gA5, (void*)n->gCat, (void*)n->gA4,
                   (void*)n->gA3, (void*)n->gPool, (void*)n->gA2, (void*)n->gA1, (void*)n->part,
-                  (void*)n->loss})
+                  (void*)n->loss, (void*)n->wpart})
     if (p) (void)hipFree(p);
   delete n;
 }
@@ -448,6 +504,11 @@ static int net_create_impl(const mgar_params* p, int pool, int c1, int c2, void*
   NACK(nalloc(&N->gA1, c1 * V));
   NACK(nalloc(&N->part, nblk(V)));
   NACK(nalloc(&N->loss, 1));
+  {
+    long long mx = 0;
+    for (int l = 0; l < 6; ++l) mx = std::max(mx, (long long)N->co[l] * N->ci[l]);
+    NACK(nalloc(&N->wpart, mx * ((N->D + WZ - 1) / WZ) * 28));   // finest coarse grid has the most slabs
+  }
   return MGAR_OK;
 }
 

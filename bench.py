@@ -16,12 +16,14 @@ Prints one JSON line:
                  against the same solves one design at a time
   learned_mixed  the mixed-precision MGAR loop with the learned initial guess
                  (trained by the library's kernels on cycles 2..20, used from 21
-                 when its true residual beats the previous temperature's);
-                 training time is inside the timed cycles
-  mgar_mixed     the MGAR loop in the mixed-precision form (FP32 multigrid and
-                 inner PCG over BF16 densities inside FP64 iterative refinement,
-                 same 1e-8 FP64 residual test); reported beside value, which
-                 stays the all-FP64 loop
+                 when its true residual beats the previous temperature's;
+                 after a losing cycle the guess is left out for 1, 2, 4 ..
+                 16 cycles, a win resets the gap); training time is inside
+                 the timed cycles
+  mgar_mixed     the MGAR loop in the mixed-precision form (one FP32 PCG run,
+                 FP32 multigrid over BF16 densities, its residual replaced by
+                 the FP64 one every 1e-3 of reduction, same 1e-8 FP64 residual
+                 test); reported beside value, which stays the all-FP64 loop
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events recorded at
                  the start and end of each launch in the timed cycles, against

@@ -50,7 +50,7 @@ extern "C" {
 #define MGAR_PATH_FALLBACK 2     /* reduced solution rejected; MGCG from it, K0 renewed */
 
 #define MGAR_PREC_FP64 0         /* every operation in FP64 */
-#define MGAR_PREC_MIXED 1        /* FP32 multigrid over BF16 densities inside FP64 iterative refinement */
+#define MGAR_PREC_MIXED 1        /* FP32 multigrid PCG over BF16 densities with FP64 residual replacement */
 
 #define MGAR_MAX_BASIS 8
 
@@ -71,8 +71,10 @@ typedef struct {
   int basis_x0_zero;      /* 0: V-cycle initial guess r_{i-1} as printed in Eq 17; 1: zero */
   int precision;          /* MGAR_PREC_FP64 or MGAR_PREC_MIXED */
   double filter_r;        /* cone density-filter radius, Eq 7-8 (element lengths) */
-  double inner_tol;       /* MGAR_PREC_MIXED: each inner FP32 PCG solve stops once its
-                           * residual has dropped by this factor (0 < inner_tol < 1; 1e-4) */
+  double inner_tol;       /* MGAR_PREC_MIXED: the FP32 PCG run folds its correction into the
+                           * FP64 solution and replaces its residual by the FP64 one each
+                           * time that residual has dropped by this factor (0 < inner_tol < 1;
+                           * 1e-3); the Krylov recurrences carry on across replacements */
 } mgar_params;
 
 /* Per-solve report. */
@@ -80,7 +82,7 @@ typedef struct {
   int path;               /* MGAR_PATH_* */
   int cg_iters;           /* CG iterations (each applies one V-cycle) */
   int vcycles;            /* V-cycles, including those that built the basis */
-  int refinements;        /* outer FP64 refinement steps (mixed mode) */
+  int refinements;        /* FP32 segments between FP64 residual replacements (mixed mode) */
   double res_ca;          /* Eq 28 residual of the reduced solution (NaN for pure MGCG) */
   double res_final;       /* ||q - K t|| / ||q|| of the returned t: recursive residual of the last CG iterate */
   float ms;               /* device time of the call, milliseconds */

@@ -54,6 +54,7 @@ struct mgar_handle {
   int ntap = 0;
   int tap_hr = 0;                         // largest |offset| of a filter tap
   int pcg_hint = 0;                       // iterations of the last FP64 PCG solve
+  double rate32 = -1.0;                   // last observed contraction per FP32 PCG iteration
   bool has_k0 = false;
   int lt = 1;                             // first grid handled by the V-cycle tail kernel
   TailSpec tail;
@@ -606,78 +607,95 @@ int run_iters(mgar_handle* h, int cls, double tol, int cg_max, int n, int nr) {
   return MGAR_OK;
 }
 
-// Inner FP32 PCG: solve K32 d = r32 from d = 0 until ||r|| <= tol_in ||r32_0||
-// or max_it iterations; FP64 accumulation of every inner product.
-int pcg32(mgar_handle* h, double tol_in, int max_it, int* iters) {
+// Enqueue one segment of the FP32 PCG run of the mixed form: n iterations on
+// K32 d = r32 from d = 0 (no host synchronisation). fresh starts the Krylov
+// recurrences; otherwise they continue from the previous segment, whose
+// iterate the caller has folded into the FP64 solution and whose residual it
+// has replaced by the FP64 one. The device stops the segment early once
+// ||r32|| has dropped by inner_tol sqrt(qscale2) (or at the CG budget); FP64
+// accumulation of every inner product.
+int enqueue_seg32(mgar_handle* h, bool fresh, double qscale2, int n) {
   const long long N = h->N;
+  const double tol_in = h->p.inner_tol;
   HIPCK(hipMemsetAsync(h->d32, 0, sizeof(float) * N, h->s));
   const int nr = launch_dot_t<float, float>(h->r32, h->r32, N, h->pa, nullptr, h->s);
-  launch_cg_init(h->st, h->pa, nr, h->pa, nr, tol_in, max_it, h->s);
-  launch_fill_t<float>(h->p32b, N, 0.f, 0.f, h->s);   // p_old of iteration 0 (weight 0) stays finite
-  int it = 0, chunk = std::max(1, std::min(4, max_it));
-  double rr_prev = -1.0;
-  int it_prev = 0;
-  CgState hs;
-  for (;;) {
-    ACK(run_iters(h, 1, tol_in, h->p.cg_max, chunk, nr));
-    it += chunk;
-    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
-    HIPCK(hipStreamSynchronize(h->s));
-    if (hs.done) break;
-    if (it >= max_it) break;   // the refinement's iteration budget is spent
-    // the next chunk from the observed contraction rate (the initial residual
-    // ||r_0||^2 is st->qq here), as in pcg
-    const double rr = hs.rr;
-    int next = 2;
-    const double r0 = rr_prev > 0.0 ? rr_prev : hs.qq;
-    const int i0 = rr_prev > 0.0 ? it_prev : 0;
-    if (r0 > 0.0 && rr > 0.0 && hs.it > i0) {
-      const double rate = std::pow(rr / r0, 0.5 / (double)(hs.it - i0));
-      const double goal = tol_in * std::sqrt(hs.qq) / std::sqrt(rr);
-      if (rate > 0.0 && rate < 0.999 && goal < 1.0) next = (int)std::ceil(std::log(goal) / std::log(rate));
-    }
-    chunk = std::max(1, std::min({next, 16, max_it - it}));
-    rr_prev = rr;
-    it_prev = hs.it;
-  }
+  launch_cg_start(h->st, h->pa, nr, qscale2, fresh, tol_in, h->p.cg_max, h->s);
+  if (fresh) launch_fill_t<float>(h->p32b, N, 0.f, 0.f, h->s);   // p_old of iteration 0 (weight 0)
+  ACK(run_iters(h, 1, tol_in, h->p.cg_max, n, nr));
   // the update of d of the last iteration may still be pending (fused path)
   if (papply_supported(h->lv[0].g, &h->scfg[1][0][SM_APPLY_DOT]))
     launch_cg_flush_t<float>(h->d32, h->p32, N, h->st, h->s);
   LAUNCHCK();
-  *iters = hs.done ? hs.iters : hs.it;
   return MGAR_OK;
 }
 
-// FP64 iterative refinement around the FP32 solver: r = q - K64 x in FP64,
-// d ~ K32^-1 r in FP32, x += d, until ||r|| <= tol ||q|| (or the CG budget is
-// spent). x in h->cx on entry and exit.
+// Mixed form: one FP32 PCG run (FP32 operator of the current densities, FP32
+// V-cycles over BF16 densities) in segments with FP64 residual replacement.
+// A segment runs the number of iterations predicted to reduce the residual
+// by inner_tol (the last one: to 0.7 tol ||q||; a segment that would leave
+// less than a factor 10 to go becomes the last one); its FP32 correction is
+// then added to the FP64 solution x, and r = q - K64 x is computed in FP64,
+// with one host synchronisation per segment. The next segment continues the
+// same Krylov recurrences from that r as long as it is within twice the
+// recursive residual it replaces (else beta = rz_new / rz_old would be
+// inflated and the new direction mostly the old one: the run starts afresh
+// from r, as plain iterative refinement does). The stopping test
+// ||r|| <= tol ||q|| is on the FP64 residual. x in h->cx on entry and exit;
+// *nref: segments run.
 int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relres, int* nref) {
   const long long N = h->N;
   const Geo& g = h->lv[0].g;
+  const int cg_max = h->p.cg_max;
   launch_cast_f32(h->kcur, h->k32, h->E, h->s);
   const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
   launch_finalize(h->pb, nq, &h->scal[2], nullptr, h->s);
-  int total = 0, ref = 0;
-  *conv = 0;
-  for (;; ++ref) {
+  auto fp64_residual = [&]() -> int {
     ACK(stencil_at(h, 0, SM_RESID, h->cx, h->kcur, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
     const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
     launch_finalize(h->pa, nr, &h->scal[3], nullptr, h->s);
-    double qr[2];
-    HIPCK(hipMemcpyAsync(qr, &h->scal[2], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
-    HIPCK(hipStreamSynchronize(h->s));
+    return MGAR_OK;
+  };
+  ACK(fp64_residual());
+  double qr[2];
+  HIPCK(hipMemcpyAsync(qr, &h->scal[2], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  int total = 0, seg = 0, it_run = 0;
+  double rr_rec = -1.0;
+  *conv = 0;
+  for (;; ++seg) {
     *relres = qr[0] > 0.0 ? std::sqrt(qr[1] / qr[0]) : 0.0;
     if (*relres <= tol) { *conv = 1; break; }
-    if (total >= h->p.cg_max || ref >= h->refine_max) break;
+    if (total >= cg_max || seg >= h->refine_max) break;
     launch_mask_copy_t<double, float>(g, h->cr, h->r32, h->s);
-    int its = 0;
-    ACK(pcg32(h, h->p.inner_tol, h->p.cg_max - total, &its));
-    total += its;
+    const double fin = 0.7 * tol / *relres;
+    const double tau = fin * 10.0 >= h->p.inner_tol ? fin : h->p.inner_tol;
+    const double qs = (tau / h->p.inner_tol) * (tau / h->p.inner_tol);
+    const double rate = (h->rate32 > 0.0 && h->rate32 < 0.999) ? h->rate32 : 0.5;
+    const int n = std::max(1, std::min({(int)std::ceil(std::log(tau) / std::log(rate)), 32, cg_max - total}));
+    const bool fresh = seg == 0 || !(rr_rec > 0.0 && qr[1] <= 4.0 * rr_rec);
+    if (fresh) it_run = 0;
+    ACK(enqueue_seg32(h, fresh, qs, n));
     launch_add_f32(h->cx, h->d32, N, h->s);
+    ACK(fp64_residual());
+    CgState hs;
+    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipMemcpyAsync(qr, &h->scal[2], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipStreamSynchronize(h->s));
+    const int its = hs.it - it_run;
+    total += its;
+    it_run = hs.it;
+    // contraction per iteration of the recursive residual over the segment
+    // (its initial ||r32||^2 is st->qq / qs)
+    const double r0 = hs.qq / qs;
+    if (its > 0 && r0 > 0.0 && hs.rr > 0.0) {
+      const double r = std::pow(hs.rr / r0, 0.5 / (double)its);
+      if (r > 0.0 && r < 0.999) h->rate32 = r;
+    }
+    rr_rec = hs.rr;
     LAUNCHCK();
   }
   *iters = total;
-  *nref = ref;
+  *nref = seg;
   return MGAR_OK;
 }
 
@@ -813,7 +831,7 @@ void mgar_default_params(mgar_params* p) {
   p->basis_x0_zero = 0;
   p->precision = MGAR_PREC_FP64;
   p->filter_r = 1.5;
-  p->inner_tol = 1e-4;
+  p->inner_tol = 1e-3;
 }
 
 const char* mgar_strerror(int code) {

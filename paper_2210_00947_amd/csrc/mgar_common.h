@@ -79,7 +79,8 @@ struct CgState {
   int itn;                   // it + 1, stored by the x/r update for a stopping test
                              // fused into a later kernel (whose blocks must not read
                              // it while its block 0 advances it)
-  int pad;
+  int flushed;               // iteration whose deferred x update k_cg_flush applied
+                             // (-1: none); the next odd update leaves it out
 };
 
 // PCG state of one design of a batch. The iteration counter lives on the

@@ -214,9 +214,10 @@ int launch_cg_update_t(T* x, T* r, const T* p, const T* w, long long n, CgState*
                        unsigned* cnt, double tol, int cg_max, hipStream_t s, const double* pwp = nullptr,
                        int npw = 0, const T* p_odd = nullptr);
 // Pending x update of a loop run with p_odd (see k_cg_update): x += a_k p_k
-// when the last completed iteration k is even; a no-op otherwise.
+// when the last completed iteration k is even and not flushed before; a no-op
+// otherwise.
 template <typename T>
-void launch_cg_flush_t(T* x, const T* p_even, long long n, const CgState* st, hipStream_t s);
+void launch_cg_flush_t(T* x, const T* p_even, long long n, CgState* st, hipStream_t s);
 // FP64 -> BF16 (RNE, through FP32); x64 += d32; device copy of BF16 arrays
 void launch_cast_bf16(const double* a, uint16_t* b, long long n, hipStream_t s);
 void launch_add_f32(double* x, const float* d, long long n, hipStream_t s);
@@ -231,6 +232,11 @@ void launch_cg_check(CgState* st, const double* part, int np, double tol, int cg
 // ||q||^2 and ||r_0||^2 from partials, and the stopping test before iteration 0.
 void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* part_rr, int nr,
                     double tol, int cg_max, hipStream_t s);
+// Start (fresh) or continue a run on a new residual: stopping reference
+// qq = qscale2 ||r||^2 from the partials of ||r||^2; continuing keeps the
+// iteration count, the r.z / p.w history and the direction buffers.
+void launch_cg_start(CgState* st, const double* part_rr, int nr, double qscale2, bool fresh, double tol,
+                     int cg_max, hipStream_t s);
 void launch_p_update(const double* z, double* p, long long n, CgState* st, hipStream_t s,
                      const double* rzp = nullptr, int np = 0);
 // x += alpha p, r -= alpha w and partials of ||r||^2 (with p_odd, the

@@ -52,9 +52,33 @@ __global__ __launch_bounds__(FB) void k_cg_init(CgState* st, const double* __res
   const double rr = sum_partials(pr, nr, sh);
   if (threadIdx.x == 0) {
     st->qq = qq; st->rr = rr; st->rz[0] = st->rz[1] = 0.0; st->pw = 0.0;
+    st->pwh[0] = st->pwh[1] = 0.0; st->flushed = -1;
     st->done = 0; st->iters = 0; st->converged = 0; st->it = 0;
     if (sqrt(rr) <= tol * sqrt(qq)) { st->done = 1; st->converged = 1; }
     else if (cg_max <= 0) { st->done = 1; }
+  }
+}
+
+// Start (fresh) or continue a PCG run on a new residual r (partials of ||r||^2):
+// the stopping reference becomes qq = qscale2 ||r||^2, so the run stops once
+// ||r|| has dropped by tol sqrt(qscale2). Continuing keeps the iteration
+// count, the r.z and p.w history and the direction buffers (the caller has
+// replaced r by a more accurate residual of the same iterate); a fresh start
+// clears them as k_cg_init does.
+__global__ __launch_bounds__(FB) void k_cg_start(CgState* st, const double* __restrict__ pr, int nr,
+                                                 double qscale2, int fresh, double tol, int cg_max) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const double rr = sum_partials(pr, nr, sh);
+  if (threadIdx.x == 0) {
+    if (fresh) {
+      st->rz[0] = st->rz[1] = 0.0; st->pw = 0.0; st->pwh[0] = st->pwh[1] = 0.0;
+      st->flushed = -1; st->it = 0;
+    }
+    const double qq = qscale2 * rr;
+    st->qq = qq; st->rr = rr;
+    st->done = 0; st->converged = 0; st->iters = st->it;
+    if (sqrt(rr) <= tol * sqrt(qq)) { st->done = 1; st->converged = 1; }
+    else if (st->it >= cg_max) { st->done = 1; }
   }
 }
 
@@ -127,7 +151,9 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   if (p_odd) {
     const bool odd = it & 1;
     // the pending update of the previous (even) iteration
-    const T alpha0 = odd ? (T)(st->rz[(it - 1) & 1] / st->pwh[(it - 1) & 1]) : T(0);
+    // (left out when k_cg_flush has already applied it)
+    const T alpha0 = (odd && st->flushed != it - 1) ? (T)(st->rz[(it - 1) & 1] / st->pwh[(it - 1) & 1])
+                                                    : T(0);
     for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
       if (odd) x[i] = (x[i] + alpha0 * p_even[i]) + alpha * p_odd[i];
       const T ri = r[i] - alpha * w[i];
@@ -179,15 +205,19 @@ __global__ __launch_bounds__(FB) void k_cg_check(CgState* st, const double* __re
 }
 
 // After a loop with deferred x updates (k_cg_update with p_odd): the update of
-// the last iteration is still pending when that iteration was even.
+// the last iteration is still pending when that iteration was even. It is
+// applied once: st->flushed records it, so a second flush and the next odd
+// update of a continued run leave it out.
 template <typename T>
 __global__ __launch_bounds__(VB) void k_cg_flush(T* __restrict__ x, const T* __restrict__ p_even, long long n,
-                                                 const CgState* __restrict__ st) {
+                                                 CgState* __restrict__ st) {
   const int k = st->it - 1;   // last completed iteration
-  if (k < 0 || (k & 1)) return;
+  if (k < 0 || (k & 1) || st->flushed == k) return;
   const T alpha = (T)(st->rz[k & 1] / st->pwh[k & 1]);
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     x[i] += alpha * p_even[i];
+  // no block of this launch reads st->flushed after its entry test above
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->flushed = k;
 }
 
 __global__ __launch_bounds__(VB) void k_copy(const double* __restrict__ a, double* __restrict__ b,
@@ -435,7 +465,7 @@ __global__ __launch_bounds__(VB) void k_cast_f32(const double* __restrict__ a, f
     b[i] = (float)a[i];
 }
 
-// x += d with d in FP32 and x in FP64 (the refinement update).
+// x += d with d in FP32 and x in FP64 (a segment's correction folded into x).
 __global__ __launch_bounds__(VB) void k_add_f32(double* __restrict__ x, const float* __restrict__ d,
                                                 long long n) {
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
@@ -800,6 +830,11 @@ void launch_cg_init(CgState* st, const double* part_qq, int nq, const double* pa
   k_cg_init<<<1, FB, 0, s>>>(st, part_qq, nq, part_rr, nr, tol, cg_max);
 }
 
+void launch_cg_start(CgState* st, const double* part_rr, int nr, double qscale2, bool fresh, double tol,
+                     int cg_max, hipStream_t s) {
+  k_cg_start<<<1, FB, 0, s>>>(st, part_rr, nr, qscale2, fresh ? 1 : 0, tol, cg_max);
+}
+
 template <typename T>
 void launch_p_update_t(const T* z, T* p, long long n, CgState* st, hipStream_t s, const double* rzp,
                        int np) {
@@ -831,11 +866,11 @@ template int launch_cg_update_t<float>(float*, float*, const float*, const float
                                        const double*, int, const float*);
 
 template <typename T>
-void launch_cg_flush_t(T* x, const T* p_even, long long n, const CgState* st, hipStream_t s) {
+void launch_cg_flush_t(T* x, const T* p_even, long long n, CgState* st, hipStream_t s) {
   k_cg_flush<T><<<vec_num_blocks(n), VB, 0, s>>>(x, p_even, n, st);
 }
-template void launch_cg_flush_t<double>(double*, const double*, long long, const CgState*, hipStream_t);
-template void launch_cg_flush_t<float>(float*, const float*, long long, const CgState*, hipStream_t);
+template void launch_cg_flush_t<double>(double*, const double*, long long, CgState*, hipStream_t);
+template void launch_cg_flush_t<float>(float*, const float*, long long, CgState*, hipStream_t);
 
 int launch_cg_update(double* x, double* r, const double* p, const double* w, long long n,
                      CgState* st, double* part, unsigned* cnt, double tol, int cg_max, hipStream_t s,

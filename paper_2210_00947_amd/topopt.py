@@ -31,6 +31,33 @@ class Cycle:
     res_prev: float = float("nan")
 
 
+class GuessSchedule:
+    """When the learned guess is evaluated (inference plus two true residuals
+    per evaluation). Every cycle while it wins; after a loss the next `gap`
+    cycles start from the previous temperature (the fallback) without
+    evaluating it, and the gap doubles with each further loss up to `cap`; a
+    win resets it to 1. Disabled: every cycle."""
+
+    def __init__(self, enabled=True, cap=16):
+        self.enabled, self.cap = bool(enabled), int(cap)
+        self.skip, self.gap = 0, 1
+
+    def want(self) -> bool:
+        if self.skip > 0:
+            self.skip -= 1
+            return False
+        return True
+
+    def record(self, won: bool):
+        if not self.enabled:
+            return
+        if won:
+            self.gap = 1
+        else:
+            self.skip = self.gap
+            self.gap = min(2 * self.gap, self.cap)
+
+
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
                  eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
@@ -38,7 +65,8 @@ class TopOpt:
         """seed: None, or a dict enabling the learned initial guess with keys
         pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
         used from the next cycle on), steps (Adam steps after cycle
-        train_until), lr, init_seed."""
+        train_until), lr, init_seed, backoff (GuessSchedule on; default True),
+        backoff_cap."""
         self.prob = prob
         self.use_mgar = use_mgar
         self.params = M.params_for(prob, n_basis=n_basis, eps_accept=eps_accept, cg_max=cg_max,
@@ -69,9 +97,11 @@ class TopOpt:
         self.seed = None
         if seed is not None:
             import workloads as W
-            cfg = dict(pool=4, c1=16, c2=32, train_until=20, steps=120, lr=3e-3, init_seed=0)
+            cfg = dict(pool=4, c1=16, c2=32, train_until=20, steps=120, lr=3e-3, init_seed=0,
+                       backoff=True, backoff_cap=16)
             cfg.update(seed)
             self.seed = cfg
+            self.sched = GuessSchedule(cfg["backoff"], cfg["backoff_cap"])
             self.net = M.Net(self.params, pool=cfg["pool"], c1=cfg["c1"], c2=cfg["c2"])
             self.net.mgar_net_set_params(W.net_init(cfg["c1"], cfg["c2"], seed=cfg["init_seed"]))
             self.pairs = []
@@ -110,8 +140,9 @@ class TopOpt:
         h, p = self.h, self.prob
         h.mgar_density_filter(self.x, self.xphys)
         T0, used, r_seed, r_prev = self.T_prev, False, float("nan"), float("nan")
-        if self.seed is not None and self.k > self.seed["train_until"]:
+        if self.seed is not None and self.k > self.seed["train_until"] and self.sched.want():
             T0, used, r_seed, r_prev = self._seed_guess()
+            self.sched.record(used)
         if (not self.use_mgar) or self.k < self.non:
             st = h.mgcg_solve(self.xphys, self.q, T0, p.tol, self.T)
         else:

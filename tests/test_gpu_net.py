@@ -117,7 +117,8 @@ def test_learned_guess_in_the_loop_gain_and_fallback():
     prob = W.tiny_3d(32, 32, 32, 4, maxit=16)
     plain = TopOpt(prob, W.element_source(prob), autotune=False).run(16)
     seeded_opt = TopOpt(prob, W.element_source(prob), autotune=False,
-                        seed={"pool": 4, "c1": 8, "c2": 16, "train_until": 8, "steps": 60})
+                        seed={"pool": 4, "c1": 8, "c2": 16, "train_until": 8, "steps": 60,
+                              "backoff": False})
     seeded = seeded_opt.run(16)
     late = [c for c in seeded if c.cycle > 8]
     for c in late:

@@ -1,7 +1,9 @@
 // Learned initial guess: a small 3D convolutional U-Net on a coarse cell grid
 // (blocks of f^3 finest elements), trained online on the (density,
 // temperature) pairs of the optimisation loop, by the kernels of this file:
-// forward, backward and Adam, FP32 storage with FP64 accumulation.
+// forward, backward and Adam. FP32 storage; the 27 taps of one source
+// channel (and, for weight gradients, a thread's few voxels) are summed in
+// FP32, every longer sum in FP64.
 //
 // Network: in(2) -> conv+ReLU (C1) -> conv+ReLU (C1) = skip -> 2x avg pool ->
 // conv+ReLU (C2) -> conv+ReLU (C2) -> 2x nearest up -> concat [up, skip] ->
@@ -36,6 +38,7 @@ namespace {
 #define NLAUNCH() NHIP(hipGetLastError())
 
 constexpr int NB = 256;
+constexpr int NBC = 64;   // voxels per block of the forward and data-gradient convolutions
 
 __device__ inline int cidx(int c, int z, int y, int x, int D, int H, int W) {
   return ((c * D + z) * H + y) * W + x;
@@ -103,139 +106,173 @@ __global__ __launch_bounds__(NB) void k_net_to_nodes(Geo g, const float* __restr
 
 // ---------------------------------------------------------------- layers
 
-// out[co][v] = b[co] + sum_ci sum_taps w[co][ci][t] in[ci][v + t - 1] (zero
-// padding), optional ReLU. One thread per voxel and group of four output
-// channels (blockIdx.y).
-template <bool RELU>
-__global__ __launch_bounds__(NB) void k_conv_fwd(const float* __restrict__ in, int Ci,
-                                                 const float* __restrict__ w, const float* __restrict__ b,
-                                                 float* __restrict__ out, int Co, int D, int H, int W) {
-  // CT output channels per thread share each loaded input; taps outside the
-  // grid load a clamped neighbour weighted 0 (no branch between the loads)
-  constexpr int CT = 4;
-  const int v = blockIdx.x * NB + threadIdx.x;
-  const int c0 = blockIdx.y * CT;
-  if (v >= D * H * W) return;
-  const int x = v % W, y = (v / W) % H, z = v / (W * H);
-  double s[CT];
-#pragma unroll
-  for (int c = 0; c < CT; ++c) s[c] = (double)b[min(c0 + c, Co - 1)];
-  for (int ci = 0; ci < Ci; ++ci) {
-    double xin[27];
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const int zz = z + dz - 1, yy = y + dy - 1, xx = x + dx - 1;
-          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-          const float val = in[cidx(ci, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
-                                    D, H, W)];
-          xin[(dz * 3 + dy) * 3 + dx] = (double)val * (ok ? 1.0 : 0.0);
-        }
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const float* wp = w + (min(c0 + c, Co - 1) * Ci + ci) * 27;
-#pragma unroll
-      for (int q = 0; q < 27; ++q) s[c] += (double)wp[q] * xin[q];
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < CT; ++c) {
-    if (c0 + c >= Co) break;
-    const float r = (float)s[c];
-    out[(c0 + c) * D * H * W + v] = RELU ? fmaxf(r, 0.0f) : r;
-  }
-}
+// Forward and data-gradient convolutions share one kernel: dst[d][v] =
+// bias[d] + sum_s sum_taps wt(d, s, t) src[s][v + sgn (t - 1)], with
+//   forward:        src = in,   d = co, s = ci, wt = w[co][ci][t],      sgn = +1;
+//   data gradient:  src = gout, d = ci, s = co, wt = w[co][ci][t],      sgn = -1
+// (zero padding; the bias only in the forward, optional ReLU). One thread per
+// voxel and group of CT destination channels (blockIdx.y); the 27 taps of a
+// source channel are summed in FP32, the source channels in FP64. Taps
+// outside the grid load a clamped neighbour weighted 0 (no branch between the
+// loads).
+constexpr int CT = 4;
 
-// gin[ci][v] = sum_co sum_taps w[co][ci][t] gout[co][v - t + 1], CT input
-// channels per thread (blockIdx.y groups them), masked taps as in k_conv_fwd.
-__global__ __launch_bounds__(NB) void k_conv_bwd_data(const float* __restrict__ gout, int Co,
-                                                      const float* __restrict__ w, int Ci,
-                                                      float* __restrict__ gin, int D, int H, int W) {
-  constexpr int CT = 4;
-  const int v = blockIdx.x * NB + threadIdx.x;
+template <bool FWD, bool RELU>
+__global__ __launch_bounds__(NBC) void k_conv(const float* __restrict__ src, int Cs,
+                                              const float* __restrict__ w, const float* __restrict__ bias,
+                                              float* __restrict__ dst, int Cd, int D, int H, int W) {
+  const int V = D * H * W;
+  const int v = blockIdx.x * NBC + threadIdx.x;
+  if (v >= V) return;
   const int c0 = blockIdx.y * CT;
-  if (v >= D * H * W) return;
   const int x = v % W, y = (v / W) % H, z = v / (W * H);
+  constexpr int sg = FWD ? 1 : -1;
   double s[CT];
 #pragma unroll
-  for (int c = 0; c < CT; ++c) s[c] = 0.0;
-  for (int co = 0; co < Co; ++co) {
-    double g[27];
+  for (int c = 0; c < CT; ++c) s[c] = FWD ? (double)bias[min(c0 + c, Cd - 1)] : 0.0;
+  for (int sc = 0; sc < Cs; ++sc) {
+    float xin[27];
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          const int zz = z - dz + 1, yy = y - dy + 1, xx = x - dx + 1;
+          const int zz = z + sg * (dz - 1), yy = y + sg * (dy - 1), xx = x + sg * (dx - 1);
           const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-          const float val = gout[cidx(co, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
-                                      D, H, W)];
-          g[(dz * 3 + dy) * 3 + dx] = (double)val * (ok ? 1.0 : 0.0);
+          const float val = src[cidx(sc, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
+                                     D, H, W)];
+          xin[(dz * 3 + dy) * 3 + dx] = val * (ok ? 1.0f : 0.0f);
         }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      const float* wp = w + (co * Ci + min(c0 + c, Ci - 1)) * 27;
+      const int d = min(c0 + c, Cd - 1);
+      const float* wp = w + (FWD ? (d * Cs + sc) : (sc * Cd + d)) * 27;
+      float t = 0.0f;
 #pragma unroll
-      for (int q = 0; q < 27; ++q) s[c] += (double)wp[q] * g[q];
+      for (int q = 0; q < 27; ++q) t += wp[q] * xin[q];
+      s[c] += (double)t;
     }
   }
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    if (c0 + c >= Ci) break;
-    gin[(c0 + c) * D * H * W + v] = (float)s[c];
+    if (c0 + c >= Cd) break;
+    const float f = (float)s[c];
+    dst[(c0 + c) * V + v] = RELU ? fmaxf(f, 0.0f) : f;
   }
 }
 
 // gw[co][ci][t] = sum_v gout[co][v] in[ci][v + t - 1]; gb[co] = sum_v gout[co][v],
-// in two stages with more parallelism: block (ci, co, s)
-// sums over the z-slab s of WZ planes (loads clamped into the grid and
-// weighted 0 outside it, so the 27 tap loads of a voxel have no branch), each
-// wave reduces by shuffles, and the waves of the block in order; part holds
-// 28 sums (27 taps, then the bias term) per (co, ci, s). k_conv_bwd_weight_sum
-// adds the slabs in order.
-constexpr int WZ = 4;
-__global__ __launch_bounds__(NB) void k_conv_bwd_weight_part(const float* __restrict__ in, int Ci,
-                                                             const float* __restrict__ gout,
-                                                             double* __restrict__ part, int D, int H, int W) {
-  __shared__ double sh[NB / MGAR_WAVE][28];
-  const int ci = blockIdx.x, co = blockIdx.y, sl = blockIdx.z, S = gridDim.z;
-  const int V = D * H * W, HW = H * W;
-  const int z0 = sl * WZ, z1 = min(z0 + WZ, D);
-  double acc[28];
+// in two stages. Block (ci, group of WCT output channels, slab s) stages input
+// channel ci over its slab (wz planes x hy rows x all W columns) plus a one-voxel
+// zero halo in LDS, so the 27 taps of a voxel are plain LDS reads shared by the
+// WCT channels. Each thread sums the products of its voxels (at most a few
+// dozen) in FP32; from there on the sums are FP64, in a fixed order (see the
+// block sums below), and part holds 28 sums (27 taps, then the bias term) per
+// (co, ci, s). k_conv_bwd_weight_sum adds the
+// slabs in order.
+constexpr int WCT = 2;          // output channels per block
+constexpr int WLDS = 12288;     // floats of the staged slab (48 KiB)
+
+// Slab shape for a D x H x W grid and a layer of ci -> co channels: wz planes
+// (at most 8; thinner while the launch would have fewer than 512 blocks, down
+// to 2) and hy rows, whose haloed tile fits WLDS floats. Returns the number of
+// slabs, or 0 if even a 1 x 1 slab does not fit (W too large).
+int weight_slabs(int D, int H, int W, int ci, int co, int* wz, int* hy) {
+  const long long cg = (co + WCT - 1) / WCT;
+  int z = std::min(D, 8), y = H;
+  auto slabs = [&]() { return (long long)((D + z - 1) / z) * ((H + y - 1) / y); };
+  while (z > 2 && ci * cg * slabs() < 512) z = (z + 1) / 2;
+  while ((long long)(z + 2) * (y + 2) * (W + 2) > WLDS) {
+    if (z > 1) z = (z + 1) / 2;
+    else if (y > 1) y = (y + 1) / 2;
+    else return 0;
+  }
+  *wz = z;
+  *hy = y;
+  return (int)slabs();
+}
+
+__global__ __launch_bounds__(NB) void k_conv_bwd_weight_lds(const float* __restrict__ in, int Ci,
+                                                            const float* __restrict__ gout, int Co,
+                                                            double* __restrict__ part, int D, int H, int W,
+                                                            int wz, int hy) {
+  __shared__ float tile[WLDS];
+  static_assert(28 * (NB + NB / 32) <= WLDS, "the block sums reuse the tile");
+  const int ci = blockIdx.x, co0 = blockIdx.y * WCT, sl = blockIdx.z, S = gridDim.z;
+  const int nys = (H + hy - 1) / hy;
+  const int z0 = (sl / nys) * wz, y0 = (sl % nys) * hy;
+  const int nz = min(wz, D - z0), ny = min(hy, H - y0);
+  const int PW = W + 2, PH = ny + 2, PP = PW * PH;
+  const int V = D * H * W;
+  // planes z0-1 .. z0+nz, rows y0-1 .. y0+ny, columns -1 .. W; zero outside the
+  // grid. Sixteen loads per thread are issued before their stores.
+  const int nt = (nz + 2) * PP;
+  for (int t0 = threadIdx.x; t0 < nt; t0 += 16 * NB) {
+    float v[16];
 #pragma unroll
-  for (int t = 0; t < 28; ++t) acc[t] = 0.0;
-  for (int v = z0 * HW + threadIdx.x; v < z1 * HW; v += NB) {
-    const int x = v % W, y = (v / W) % H, z = v / HW;
-    const double go = (double)gout[co * V + v];
-    acc[27] += go;
+    for (int u = 0; u < 16; ++u) {
+      const int t = t0 + u * NB;
+      const int lz = t / PP, rem = t - lz * PP, ly = rem / PW, lx = rem - ly * PW;
+      const int z = z0 - 1 + lz, y = y0 - 1 + ly, x = lx - 1;
+      const bool ok = t < nt && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W;
+      v[u] = ok ? in[cidx(ci, z, y, x, D, H, W)] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (t0 + u * NB < nt) tile[t0 + u * NB] = v[u];
+  }
+  __syncthreads();
+  float acc[WCT][28];
+#pragma unroll
+  for (int c = 0; c < WCT; ++c)
+#pragma unroll
+    for (int q = 0; q < 28; ++q) acc[c][q] = 0.0f;
+  const int nv = nz * ny * W;
+#pragma unroll 2
+  for (int t = threadIdx.x; t < nv; t += NB) {
+    const int x = t % W, r = t / W, ly = r % ny, lz = r / ny;
+    const int v = ((z0 + lz) * H + (y0 + ly)) * W + x;
+    const int c = ((lz + 1) * PH + (ly + 1)) * PW + (x + 1);   // the voxel in the tile
+    float g[WCT];
+#pragma unroll
+    for (int k = 0; k < WCT; ++k) g[k] = (co0 + k < Co) ? gout[(co0 + k) * V + v] : 0.0f;
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          const int zz = z + dz - 1, yy = y + dy - 1, xx = x + dx - 1;
-          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-          const float val = in[cidx(ci, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
-                                    D, H, W)];
-          acc[(dz * 3 + dy) * 3 + dx] += go * ((double)val * (ok ? 1.0 : 0.0));
-        }
-  }
-  const int lane = threadIdx.x % MGAR_WAVE, wv = threadIdx.x / MGAR_WAVE;
+          const float tv = tile[c + (dz - 1) * PP + (dy - 1) * PW + (dx - 1)];
 #pragma unroll
-  for (int t = 0; t < 28; ++t) {
-    const double s = wave_sum(acc[t]);
-    if (lane == 0) sh[wv][t] = s;
+          for (int k = 0; k < WCT; ++k) acc[k][(dz * 3 + dy) * 3 + dx] += g[k] * tv;
+        }
+#pragma unroll
+    for (int k = 0; k < WCT; ++k) acc[k][27] += g[k];
   }
-  __syncthreads();
-  if (threadIdx.x < 28) {
-    double s = 0.0;
-    for (int w = 0; w < NB / MGAR_WAVE; ++w) s += sh[w][threadIdx.x];
-    part[((co * Ci + ci) * S + sl) * 28 + threadIdx.x] = s;
+  // block sums through LDS (the tile is no longer read): per output channel,
+  // thread t stores its 28 partials at red[q * RS + t + t / 32]; then thread
+  // r < 224 sums, in FP64 and in order, the 32 partials of threads
+  // 32 (r % 8) .. 32 (r % 8) + 31 for output q = r / 8, and the eight lanes of
+  // each q add their sums by three shuffles (the same total in each lane)
+  constexpr int RS = NB + NB / 32;
+  float* red = tile;
+  const int r = threadIdx.x, q = r >> 3, sg = r & 7;
+#pragma unroll
+  for (int k = 0; k < WCT; ++k) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 28; ++j) red[j * RS + r + (r >> 5)] = acc[k][j];
+    __syncthreads();
+    double sum = 0.0;
+    if (q < 28) {
+      const float* src = red + q * RS + sg * 33;
+      for (int i = 0; i < 32; ++i) sum += (double)src[i];
+    }
+    sum += __shfl_xor(sum, 4, 8);
+    sum += __shfl_xor(sum, 2, 8);
+    sum += __shfl_xor(sum, 1, 8);
+    if (q < 28 && sg == 0 && co0 + k < Co) part[(((co0 + k) * Ci + ci) * S + sl) * 28 + q] = sum;
   }
 }
 
@@ -361,25 +398,29 @@ struct mgar_net {
 namespace {
 
 int conv(mgar_net* N, int layer, const float* in, float* out, bool relu, int D, int H, int W) {
-  const dim3 grid(nblk((long long)D * H * W), (N->co[layer] + 3) / 4);
+  const dim3 grid((unsigned)((D * H * W + NBC - 1) / NBC), (N->co[layer] + CT - 1) / CT);
+  const dim3 blk(NBC);
   const float* w = N->theta + N->woff[layer];
   const float* b = N->theta + N->boff[layer];
-  if (relu) k_conv_fwd<true><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
-  else k_conv_fwd<false><<<grid, NB, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
+  if (relu) k_conv<true, true><<<grid, blk, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
+  else k_conv<true, false><<<grid, blk, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
   NLAUNCH();
   return MGAR_OK;
 }
 
 // weight and bias gradients of `layer`, and (gin != null) its input gradient
 int conv_bwd(mgar_net* N, int layer, const float* in, const float* gout, float* gin, int D, int H, int W) {
-  const int S = (D + WZ - 1) / WZ;
-  const dim3 gw(N->ci[layer], N->co[layer], S);
-  k_conv_bwd_weight_part<<<gw, NB, 0, N->s>>>(in, N->ci[layer], gout, N->wpart, D, H, W);
+  int wz = 0, hy = 0;
+  const int S = weight_slabs(D, H, W, N->ci[layer], N->co[layer], &wz, &hy);
+  if (S <= 0) return MGAR_E_ARG;
+  const dim3 gw(N->ci[layer], (N->co[layer] + WCT - 1) / WCT, S);
+  k_conv_bwd_weight_lds<<<gw, NB, 0, N->s>>>(in, N->ci[layer], gout, N->co[layer], N->wpart, D, H, W, wz, hy);
   k_conv_bwd_weight_sum<<<nblk((long long)N->co[layer] * N->ci[layer] * 28), NB, 0, N->s>>>(
       N->wpart, N->ci[layer], N->co[layer], S, N->grad + N->woff[layer], N->grad + N->boff[layer]);
   if (gin) {
-    const dim3 gd(nblk((long long)D * H * W), (N->ci[layer] + 3) / 4);
-    k_conv_bwd_data<<<gd, NB, 0, N->s>>>(gout, N->co[layer], N->theta + N->woff[layer], N->ci[layer], gin, D,
+    const dim3 gd((unsigned)((D * H * W + NBC - 1) / NBC), (N->ci[layer] + CT - 1) / CT);
+    k_conv<false, false><<<gd, NBC, 0, N->s>>>(gout, N->co[layer], N->theta + N->woff[layer], nullptr,
+                                                         gin, N->ci[layer], D,
                                          H, W);
   }
   NLAUNCH();
@@ -505,9 +546,17 @@ static int net_create_impl(const mgar_params* p, int pool, int c1, int c2, void*
   NACK(nalloc(&N->part, nblk(V)));
   NACK(nalloc(&N->loss, 1));
   {
+    // layers 2 and 3 run on the pooled grid, the others on the cell grid
     long long mx = 0;
-    for (int l = 0; l < 6; ++l) mx = std::max(mx, (long long)N->co[l] * N->ci[l]);
-    NACK(nalloc(&N->wpart, mx * ((N->D + WZ - 1) / WZ) * 28));   // finest coarse grid has the most slabs
+    for (int l = 0; l < 6; ++l) {
+      const bool half = l == 2 || l == 3;
+      int wz = 0, hy = 0;
+      const int S = half ? weight_slabs(N->D / 2, N->H / 2, N->W / 2, N->ci[l], N->co[l], &wz, &hy)
+                         : weight_slabs(N->D, N->H, N->W, N->ci[l], N->co[l], &wz, &hy);
+      if (S <= 0) return MGAR_E_ARG;   // cell grid too wide for the staged slab
+      mx = std::max(mx, (long long)N->co[l] * N->ci[l] * S);
+    }
+    NACK(nalloc(&N->wpart, mx * 28));
   }
   return MGAR_OK;
 }

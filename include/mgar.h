@@ -213,7 +213,9 @@ int mgar_residual(mgar_handle* h, const double* xphys, const double* q, const do
  * outermost centres, 0 on Dirichlet nodes. Training pair (xphys, T, scale):
  * target y = T at the block centres / scale, loss = mean (u - y)^2, one Adam
  * step (0.9, 0.999, 1e-8) with learning rate lr. xphys: E-vector, T: N-vector
- * (device, FP64); theta, grad, u: host FP32 arrays of nparams / D*H*W values. */
+ * (device, FP64); theta, grad, u: host FP32 arrays of nparams / D*H*W values.
+ * Every call enqueues on the stream given at creation; mgar_net_train_step
+ * waits for it only when loss is non-null, mgar_net_destroy always. */
 typedef struct mgar_net mgar_net;
 int mgar_net_create(const mgar_params* p, int pool, int c1, int c2, void* stream, mgar_net** out);
 void mgar_net_destroy(mgar_net* n);

@@ -484,6 +484,7 @@ extern "C" {
 
 void mgar_net_destroy(mgar_net* n) {
   if (!n) return;
+  (void)hipStreamSynchronize(n->s);   // work still queued on the network's stream reads these buffers
   for (void* p : {(void*)n->theta, (void*)n->grad, (void*)n->m, (void*)n->v, (void*)n->in, (void*)n->a1,
                   (void*)n->a2, (void*)n->pool, (void*)n->a3, (void*)n->a4, (void*)n->cat, (void*)n->a5,
                   (void*)n->u, (void*)n->y, (void*)n->gU, (void*)n->gA5, (void*)n->gCat, (void*)n->gA4,

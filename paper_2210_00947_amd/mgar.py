@@ -455,8 +455,11 @@ class Net:
                                      g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)), "mgar_net_grad")
         return loss.value, g
 
-    def mgar_net_train_step(self, xphys, T, scale, lr):
+    def mgar_net_train_step(self, xphys, T, scale, lr, want_loss=True):
+        """One Adam step; returns the loss (a host synchronisation on the
+        network's stream) or, with want_loss=False, None without waiting."""
         loss = ctypes.c_double()
         _check(self._L.mgar_net_train_step(self.n, _ptr(xphys, self.E), _ptr(T, self.N), ctypes.c_double(scale),
-                                           ctypes.c_double(lr), ctypes.byref(loss)), "mgar_net_train_step")
-        return loss.value
+                                           ctypes.c_double(lr), ctypes.byref(loss) if want_loss else None),
+               "mgar_net_train_step")
+        return loss.value if want_loss else None

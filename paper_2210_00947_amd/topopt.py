@@ -66,7 +66,11 @@ class TopOpt:
         pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
         used from the next cycle on), steps (Adam steps after cycle
         train_until), lr, init_seed, backoff (GuessSchedule on; default True),
-        backoff_cap."""
+        backoff_cap, lag (default 0: training runs when cycle train_until
+        ends and the guess is used from the next cycle; lag > 0: training
+        runs in the background on the network's own stream, beside the
+        solves of the next lag cycles, and the guess is used from cycle
+        train_until + 1 + lag, whose solver stream first waits for it)."""
         self.prob = prob
         self.use_mgar = use_mgar
         self.params = M.params_for(prob, n_basis=n_basis, eps_accept=eps_accept, cg_max=cg_max,
@@ -98,11 +102,15 @@ class TopOpt:
         if seed is not None:
             import workloads as W
             cfg = dict(pool=4, c1=16, c2=32, train_until=20, steps=120, lr=3e-3, init_seed=0,
-                       backoff=True, backoff_cap=16)
+                       backoff=True, backoff_cap=16, lag=0)
             cfg.update(seed)
             self.seed = cfg
             self.sched = GuessSchedule(cfg["backoff"], cfg["backoff_cap"])
-            self.net = M.Net(self.params, pool=cfg["pool"], c1=cfg["c1"], c2=cfg["c2"])
+            # lag > 0: the network works on a stream of its own (default priority)
+            self.net_stream = torch.cuda.Stream() if int(cfg["lag"]) > 0 else None
+            self.train_done = None
+            self.net = M.Net(self.params, pool=cfg["pool"], c1=cfg["c1"], c2=cfg["c2"],
+                             stream=self.net_stream.cuda_stream if self.net_stream is not None else None)
             self.net.mgar_net_set_params(W.net_init(cfg["c1"], cfg["c2"], seed=cfg["init_seed"]))
             self.pairs = []
             self.Tseed = torch.zeros(N, **f64)
@@ -115,7 +123,16 @@ class TopOpt:
         scale = float(self.T_prev.abs().max())
         if scale <= 0.0:
             return self.T_prev, False, float("nan"), float("nan")
+        cur = torch.cuda.current_stream()
+        if self.net_stream is not None:
+            if self.train_done is not None:     # first use: the background training ends first
+                cur.wait_event(self.train_done)
+                self.train_done = None
+                self.pairs = []                 # later work on this stream comes after the wait
+            self.net_stream.wait_stream(cur)    # this cycle's densities
         self.net.mgar_net_infer(self.xphys, scale, self.Tseed)
+        if self.net_stream is not None:
+            cur.wait_stream(self.net_stream)
         r_seed = h.mgar_residual(self.xphys, self.q, self.Tseed)
         r_prev = h.mgar_residual(self.xphys, self.q, self.T_prev)
         if r_seed < r_prev:
@@ -123,24 +140,38 @@ class TopOpt:
         return self.T_prev, False, r_seed, r_prev
 
     def _seed_train(self):
+        """Adam steps over the collected pairs in a seeded random order. The
+        loss is read back (a host synchronisation) after the first step and,
+        when training runs in the foreground, after the last."""
         cfg = self.seed
         n = len(self.pairs)
         if n == 0:
             return
         order = torch.Generator().manual_seed(int(cfg["init_seed"]))
-        for s in range(int(cfg["steps"])):
+        if self.net_stream is not None:
+            self.net_stream.wait_stream(torch.cuda.current_stream())   # the pairs are ready
+        steps = int(cfg["steps"])
+        for s in range(steps):
             if s % n == 0:
                 perm = torch.randperm(n, generator=order).tolist()
             xp, tp, sc = self.pairs[perm[s % n]]
-            self.train_losses.append(self.net.mgar_net_train_step(xp, tp, sc, cfg["lr"]))
-        self.pairs = []      # training data is not needed once the guess is in use
+            want = s == 0 or (s == steps - 1 and self.net_stream is None)
+            loss = self.net.mgar_net_train_step(xp, tp, sc, cfg["lr"], want_loss=want)
+            if want:
+                self.train_losses.append(loss)
+        if self.net_stream is not None:
+            self.train_done = torch.cuda.Event()
+            self.train_done.record(self.net_stream)   # the pairs stay alive until it is waited on
+        else:
+            self.pairs = []   # training data is not needed once the guess is in use
 
     def step(self) -> Cycle:
         self.k += 1
         h, p = self.h, self.prob
         h.mgar_density_filter(self.x, self.xphys)
         T0, used, r_seed, r_prev = self.T_prev, False, float("nan"), float("nan")
-        if self.seed is not None and self.k > self.seed["train_until"] and self.sched.want():
+        if (self.seed is not None and self.k > self.seed["train_until"] + int(self.seed["lag"])
+                and self.sched.want()):
             T0, used, r_seed, r_prev = self._seed_guess()
             self.sched.record(used)
         if (not self.use_mgar) or self.k < self.non:

@@ -107,28 +107,51 @@ def test_training_reduces_loss_on_loop_pairs():
     assert l1 < 0.5 * l0
 
 
-def test_learned_guess_in_the_loop_gain_and_fallback():
-    """The loop with the learned guess (trained on cycles 2..8, used from 9)
-    against the plain loop: a guess is used only when its true residual is
-    below that of the previous temperature, and then the cycle's result stays
-    within the solve tolerance of the plain loop's. Prints the gain."""
+@pytest.mark.parametrize("lag", [0, 3], ids=["foreground", "background"])
+def test_learned_guess_in_the_loop_gain_and_fallback(lag):
+    """The loop with the learned guess (trained on cycles 2..8, used from
+    9 + lag; with lag > 0 the training runs on the network's own stream beside
+    the solves of cycles 9 .. 8 + lag) against the plain loop: a guess is used
+    only when its true residual is below that of the previous temperature,
+    and then the cycle's result stays within the solve tolerance of the plain
+    loop's. Prints the gain."""
     require_gpu()
     from paper_2210_00947_amd.topopt import TopOpt
     prob = W.tiny_3d(32, 32, 32, 4, maxit=16)
     plain = TopOpt(prob, W.element_source(prob), autotune=False).run(16)
     seeded_opt = TopOpt(prob, W.element_source(prob), autotune=False,
                         seed={"pool": 4, "c1": 8, "c2": 16, "train_until": 8, "steps": 60,
-                              "backoff": False})
+                              "backoff": False, "lag": lag})
     seeded = seeded_opt.run(16)
-    late = [c for c in seeded if c.cycle > 8]
+    late = [c for c in seeded if c.cycle > 8 + lag]
+    for c in seeded:
+        if 8 < c.cycle <= 8 + lag:
+            assert not c.seed_used and np.isnan(c.res_seed)
     for c in late:
         assert np.isfinite(c.res_seed) and np.isfinite(c.res_prev)
         assert c.seed_used == (c.res_seed < c.res_prev)
     for a, b in zip(plain, seeded):
         assert abs(a.compliance - b.compliance) <= 1e-6 * abs(a.compliance)
-    its_plain = np.mean([c.cg_iters for c in plain if c.cycle > 8])
+    its_plain = np.mean([c.cg_iters for c in plain if c.cycle > 8 + lag])
     its_seed = np.mean([c.cg_iters for c in late])
     ratio = np.median([c.res_seed / c.res_prev for c in late])
     print(f"learned guess: used in {sum(c.seed_used for c in late)}/{len(late)} cycles; median residual "
           f"ratio seed/previous {ratio:.3g}; mean CG iterations {its_seed:.2f} vs {its_plain:.2f} plain; "
-          f"training loss {seeded_opt.train_losses[0]:.3g} -> {seeded_opt.train_losses[-1]:.3g}")
+          f"training loss after the first step {seeded_opt.train_losses[0]:.3g}"
+          + (f", after the last {seeded_opt.train_losses[-1]:.3g}" if lag == 0 else ""))
+
+
+def test_background_training_gives_the_foreground_parameters():
+    """Training on the network's own stream beside the solves (lag > 0) runs
+    the same steps on the same pairs as training in the foreground: the
+    parameters agree bit for bit."""
+    require_gpu()
+    from paper_2210_00947_amd.topopt import TopOpt
+    prob = W.tiny_3d(32, 32, 32, 4, maxit=16)
+    thetas = []
+    for lag in (0, 2):
+        opt = TopOpt(prob, W.element_source(prob), autotune=False,
+                     seed={"pool": 4, "c1": 8, "c2": 16, "train_until": 6, "steps": 30, "lag": lag})
+        opt.run(10)
+        thetas.append(opt.net.mgar_net_get_params())
+    assert np.array_equal(thetas[0], thetas[1])

@@ -186,24 +186,37 @@ int sync_coarse(mgar_handle* h) {
   return MGAR_OK;
 }
 
-int build_hierarchy(mgar_handle* h) {
-  ACK(sync_coarse(h));   // Ainv and dstatus are rewritten below
-  if (h->dg0) launch_diag(h->lv[0].g, h->lv[0].k, h->dg0, h->s);
-  h->dg0_valid = h->dg0 != nullptr;
-  for (int l = 1; l < h->L; ++l) launch_coarsen(h->lv[l - 1].g, h->lv[l].g, h->lv[l - 1].k, h->lv[l].k, h->s);
+// The single-workgroup build of the coarsest inverse runs on a side stream
+// (default priority) beside the solver's work on the main stream, after what
+// the main stream has enqueued so far; sync_coarse makes the main stream wait
+// for it before its first reader.
+int coarse_side_begin(mgar_handle* h) {
   if (!h->cs) {
     HIPCK(hipStreamCreateWithFlags(&h->cs, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&h->cev0, hipEventDisableTiming));
     HIPCK(hipEventCreateWithFlags(&h->cev1, hipEventDisableTiming));
   }
-  // the single-workgroup build runs beside the solver's set-up on the main stream
   HIPCK(hipEventRecord(h->cev0, h->s));
   HIPCK(hipStreamWaitEvent(h->cs, h->cev0, 0));
   HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->cs));
-  launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->cs);
+  return MGAR_OK;
+}
+
+int coarse_side_end(mgar_handle* h) {
   HIPCK(hipEventRecord(h->cev1, h->cs));
   h->coarse_pending = true;
   LAUNCHCK();
+  return MGAR_OK;
+}
+
+int build_hierarchy(mgar_handle* h) {
+  ACK(sync_coarse(h));   // Ainv and dstatus are rewritten below
+  if (h->dg0) launch_diag(h->lv[0].g, h->lv[0].k, h->dg0, h->s);
+  h->dg0_valid = h->dg0 != nullptr;
+  for (int l = 1; l < h->L; ++l) launch_coarsen(h->lv[l - 1].g, h->lv[l].g, h->lv[l - 1].k, h->lv[l].k, h->s);
+  ACK(coarse_side_begin(h));
+  launch_coarse_build(h->lv[h->L - 1].g, h->lv[h->L - 1].k, h->Ainv, h->dstatus, h->cs);
+  ACK(coarse_side_end(h));
   return MGAR_OK;
 }
 
@@ -329,10 +342,10 @@ bool j0resid_fusable(const mgar_handle* h) {
 int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, double* dot_part,
            const int* done, int tag = -1, unsigned* dcnt = nullptr, double* dout = nullptr,
            const PFuse* check = nullptr) {
-  ACK(sync_coarse(h));
   const int L = h->L;
   const double w = h->p.omega;
   if (L == 1) {
+    ACK(sync_coarse(h));   // the coarsest inverse may still be built on the side stream
     launch_coarse_solve(h->lv[0].g, h->Ainv, b0, out, done, h->s);
     if (dot_part) launch_dot(b0, out, h->N, dot_part, done, h->s, dcnt, dout);
     LAUNCHCK();
@@ -357,6 +370,7 @@ int vcycle(mgar_handle* h, const double* b0, const double* x0, double* out, doub
                                                                         w, done, h->s);
     if (!presmoothed) launch_restrict(v.g, c.g, h->rtmp, c.b, done, h->s);
   }
+  ACK(sync_coarse(h));   // first reader of the coarsest inverse
   launch_vtail(h->tail, h->lv[lt].b, h->lv[lt].xb, h->Ainv, w, done, h->s);
   const double* xfin = h->lv[lt].xb;
   for (int l = lt - 1; l >= 0; --l) {
@@ -418,19 +432,19 @@ int build_hierarchy32(mgar_handle* h) {
   if (L >= 2) launch_coarsen_t<CellB, float>(h->lv[0].g, h->lv[1].g, k0, h->kf[1], h->s);
   for (int l = 2; l < L; ++l)
     launch_coarsen_t<CellF, float>(h->lv[l - 1].g, h->lv[l].g, CellF{h->kf[l - 1]}, h->kf[l], h->s);
-  HIPCK(hipMemsetAsync(h->dstatus, 0, sizeof(int), h->s));
-  if (L == 1) launch_coarse_build_t<CellB>(h->lv[0].g, k0, h->Ainv, h->dstatus, h->s);
-  else launch_coarse_build_t<CellF>(h->lv[L - 1].g, CellF{h->kf[L - 1]}, h->Ainv, h->dstatus, h->s);
-  LAUNCHCK();
+  ACK(coarse_side_begin(h));
+  if (L == 1) launch_coarse_build_t<CellB>(h->lv[0].g, k0, h->Ainv, h->dstatus, h->cs);
+  else launch_coarse_build_t<CellF>(h->lv[L - 1].g, CellF{h->kf[L - 1]}, h->Ainv, h->dstatus, h->cs);
+  ACK(coarse_side_end(h));
   return MGAR_OK;
 }
 
 // One FP32 V-cycle on the BF16/FP32 K0 hierarchy (same sequence as vcycle()).
 int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, double* dot_part,
              const int* done) {
-  ACK(sync_coarse(h));
   const int L = h->L;
   if (L == 1) {
+    ACK(sync_coarse(h));   // the coarsest inverse may still be built on the side stream
     launch_coarse_solve_t<float>(h->lv[0].g, h->Ainv, b0, out, done, h->s);
     if (dot_part) launch_dot_t<float, float>(b0, out, h->N, dot_part, done, h->s);
     LAUNCHCK();
@@ -452,6 +466,7 @@ int vcycle32(mgar_handle* h, const float* b0, const float* x0, float* out, doubl
                                                                    h->xaf[l + 1], h->p.omega, done, h->s);
     if (!presmoothed) launch_restrict_t<float>(h->lv[l].g, h->lv[l + 1].g, h->rtmpf, h->bf[l + 1], done, h->s);
   }
+  ACK(sync_coarse(h));   // first reader of the coarsest inverse
   launch_vtail_t<float>(h->tailf, h->bf[lt], h->xbf[lt], h->Ainv, h->p.omega, done, h->s);
   const float* xfin = h->xbf[lt];
   for (int l = lt - 1; l >= 0; --l) {
@@ -584,15 +599,18 @@ int capture_iters(mgar_handle* h, int cls, double tol, int cg_max, int nr) {
 // unless graphs are off or kernel timing is on (then eager launches).
 int run_iters(mgar_handle* h, int cls, double tol, int cg_max, int n, int nr) {
   if (n <= 0) return MGAR_OK;
-  // replayed graphs run on another stream behind an event of h->s: the wait for
-  // a coarsest inverse still being built must be on h->s before that event
-  ACK(sync_coarse(h));
+  // eager launches wait for a coarsest inverse still being built right before
+  // its first reader (the V-cycle tail), so the finest-grid kernels of the
+  // first iteration run beside the build
   if (!h->use_graphs || h->prof_mask) {
     for (int i = 0; i < n; ++i) ACK(enqueue_iter(h, cls, tol, cg_max, nr, h->tag_base + i, i > 0));
     launch_cg_check(h->st, h->pa, nr, tol, cg_max, h->s);
     h->tag_base += n;
     return MGAR_OK;
   }
+  // replayed graphs run on another stream behind an event of h->s: the wait for
+  // a coarsest inverse still being built must be on h->s before that event
+  ACK(sync_coarse(h));
   if (!h->gx[cls][0] || h->g_tol[cls] != tol || h->g_max[cls] != cg_max)
     ACK(capture_iters(h, cls, tol, cg_max, nr));
   HIPCK(hipEventRecord(h->gin, h->s));

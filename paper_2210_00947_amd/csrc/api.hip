@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -26,6 +27,17 @@ struct LevelBuf {
 
 }  // namespace
 
+// Pinned host image of the CG state and the status word behind it (the same
+// layout as on the device), plus a few FP64 scalars read in the same
+// synchronisation.
+struct HostPin {
+  CgState s;
+  int status;
+  int pad;
+  double extra[4];
+};
+static_assert(offsetof(HostPin, status) == sizeof(CgState), "status word follows the state");
+
 struct mgar_handle {
   mgar_params p;
   hipStream_t s = nullptr;
@@ -35,7 +47,10 @@ struct mgar_handle {
   double* kcur = nullptr;                 // K(xphys) of the current call, finest grid
   double* rtmp = nullptr;                 // residual scratch (finest size)
   double* Ainv = nullptr;                 // coarsest-grid inverse
-  int* dstatus = nullptr;                 // device status word (coarsest pivots)
+  int* dstatus = nullptr;                 // device status word (coarsest pivots), right after *st
+  HostPin* hpin = nullptr;                // pinned host buffer of the state readbacks
+  int status_host = 0;                    // the status word, read with the CG state ...
+  bool status_valid = false;              // ... after the main stream waited for the latest build
   double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
   double* cp2 = nullptr;                  // second CG direction buffer (fused direction update)
   double* dg0 = nullptr;                  // diagonal of K0 on the finest grid (3D, FP64 hierarchy)
@@ -205,7 +220,29 @@ int coarse_side_begin(mgar_handle* h) {
 int coarse_side_end(mgar_handle* h) {
   HIPCK(hipEventRecord(h->cev1, h->cs));
   h->coarse_pending = true;
+  h->status_valid = false;
   LAUNCHCK();
+  return MGAR_OK;
+}
+
+// The CG state to the host through the pinned buffer (one synchronisation),
+// with the coarsest-build status word behind it when the main stream has
+// already waited for the latest build (check_coarse then needs no copy of its
+// own), and optionally n (<= 4) FP64 scalars from dev_extra.
+int read_cg_state(mgar_handle* h, CgState* hs, const double* dev_extra = nullptr, int n = 0,
+                  double* extra = nullptr) {
+  const bool with_status = !h->coarse_pending;
+  if (n > 0)
+    HIPCK(hipMemcpyAsync(h->hpin->extra, dev_extra, sizeof(double) * n, hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipMemcpyAsync(h->hpin, h->st, sizeof(CgState) + (with_status ? sizeof(int) : 0),
+                       hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  *hs = h->hpin->s;
+  for (int i = 0; i < n; ++i) extra[i] = h->hpin->extra[i];
+  if (with_status) {
+    h->status_host = h->hpin->status;
+    h->status_valid = true;
+  }
   return MGAR_OK;
 }
 
@@ -696,9 +733,7 @@ int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relre
     launch_add_f32(h->cx, h->d32, N, h->s);
     ACK(fp64_residual());
     CgState hs;
-    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
-    HIPCK(hipMemcpyAsync(qr, &h->scal[2], 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
-    HIPCK(hipStreamSynchronize(h->s));
+    ACK(read_cg_state(h, &hs, &h->scal[2], 2, qr));
     const int its = hs.it - it_run;
     total += its;
     it_run = hs.it;
@@ -747,8 +782,7 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
     const int c = std::min(chunk, cg_max - it);
     ACK(run_iters(h, 0, tol, cg_max, c, nr));
     it += c;
-    HIPCK(hipMemcpyAsync(&hs, h->st, sizeof(CgState), hipMemcpyDeviceToHost, h->s));
-    HIPCK(hipStreamSynchronize(h->s));
+    ACK(read_cg_state(h, &hs));
     if (hs.done) break;
     if (it >= cg_max) return MGAR_E_HIP;   // the device test must have fired by now
     // predict the remaining iterations from the observed contraction rate
@@ -778,6 +812,10 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
 }
 
 int check_coarse(mgar_handle* h) {
+  if (h->status_valid && !h->coarse_pending) {   // read with the solver's last CG state
+    h->status_valid = false;
+    return h->status_host ? MGAR_E_NOT_SPD : MGAR_OK;
+  }
   ACK(sync_coarse(h));
   int st = 0;
   HIPCK(hipMemcpyAsync(&st, h->dstatus, sizeof(int), hipMemcpyDeviceToHost, h->s));
@@ -876,11 +914,12 @@ void mgar_destroy(mgar_handle* h) {
     if (v.xa) (void)hipFree(v.xa);
     if (v.xb) (void)hipFree(v.xb);
   }
-  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->dstatus, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2, h->dg0,
+  void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2, h->dg0,
                   h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto* v : {&h->kf, &h->bf, &h->xaf, &h->xbf})
     for (float* q : *v)
       if (q) (void)hipFree(q);
@@ -934,7 +973,6 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->kcur, E));
   ACK(dalloc(&h->rtmp, N));
   ACK(dalloc(&h->Ainv, gc.nn * gc.nn));
-  ACK(dalloc(&h->dstatus, 4));
   ACK(dalloc(&h->qm, N));
   ACK(dalloc(&h->cx, N));
   ACK(dalloc(&h->cr, N));
@@ -957,7 +995,11 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->scal, 16));
   ACK(dalloc(&h->cnt, 16));
   HIPCK(hipMemset(h->cnt, 0, 16 * sizeof(unsigned)));
-  ACK(dalloc(&h->st, 1));
+  // the coarsest-build status word follows the CG state, so that one copy
+  // to the host brings both
+  ACK(dalloc(&h->st, 2));
+  h->dstatus = reinterpret_cast<int*>(h->st + 1);
+  HIPCK(hipHostMalloc((void**)&h->hpin, sizeof(HostPin), hipHostMallocDefault));
   ACK(dalloc(&h->md, 1));
   ACK(dalloc(&h->oc, 1));
   ACK(dalloc(&h->R, N * p->n_basis));
@@ -1248,12 +1290,17 @@ int oc_update(mgar_handle* h, const double* x, const double* dc, const double* d
       launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);
     }
     passes += chunk;
+    // the update from the multiplier reached so far, enqueued before the
+    // synchronisation (it only reads the bisection state); when more passes
+    // follow, the next one overwrites x_new. Not when x_new is x itself:
+    // later passes still read x.
+    if (x_new != x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
     LAUNCHCK();
     HIPCK(hipMemcpyAsync(&ho, h->oc, sizeof(OcDev), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
     if (ho.done || passes > 64) break;
   }
-  launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
+  if (x_new == x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
   LAUNCHCK();
   if (lambda) *lambda = 0.5 * (ho.l1 + ho.l2);
   return MGAR_OK;

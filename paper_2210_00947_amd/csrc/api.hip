@@ -847,18 +847,19 @@ int orthonormalise(mgar_handle* h) {
   const long long N = h->N;
   for (int j = 0; j < m; ++j) {
     double* v = h->R + (long long)j * N;
-    int np = launch_dot(v, v, N, h->pa, nullptr, h->s);
-    launch_finalize(h->pa, np, &h->md->n0[j], nullptr, h->s);
+    // squared norms reduced inside the dot launch (the last block adds the
+    // block partials in order)
+    launch_dot(v, v, N, h->pa, nullptr, h->s, h->cnt, &h->md->n0[j]);
     if (j > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
+        const int np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
         launch_finalize_multi(h->pa, np, j, h->md->c, h->s);
         launch_gs_update(v, h->R, j, N, h->md->c, N, h->s);
       }
+      launch_dot(v, v, N, h->pa, nullptr, h->s, h->cnt, &h->scal[0]);
     }
-    np = launch_dot(v, v, N, h->pa, nullptr, h->s);
-    launch_finalize(h->pa, np, &h->scal[0], nullptr, h->s);
-    launch_gs_normalize(v, N, h->md, j, &h->scal[0], h->s);
+    // the first column has nothing to be projected out: its norm is n0
+    launch_gs_normalize(v, N, h->md, j, j > 0 ? &h->scal[0] : &h->md->n0[0], h->s);
     LAUNCHCK();
   }
   return MGAR_OK;
@@ -1209,8 +1210,7 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   launch_gram_finalize(h->pa, np, m, h->md, h->s);
   np = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s);
   launch_finalize(h->pa, np, &h->md->res2, nullptr, h->s);
-  np = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
-  launch_finalize(h->pb, np, &h->md->qq, nullptr, h->s);
+  launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s, h->cnt, &h->md->qq);
   LAUNCHCK();
   MgarDev hm;
   HIPCK(hipMemcpyAsync(&hm, h->md, sizeof(MgarDev), hipMemcpyDeviceToHost, h->s));

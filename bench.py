@@ -29,7 +29,9 @@ Prints one JSON line:
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events recorded at
                  the start and end of each launch in the timed cycles, against
-                 8 TB/s
+                 8 TB/s; stream_ref gives, for scale, the GB/s of plain torch
+                 element-wise kernels at the node-vector size and at 64 Mi
+                 elements (beyond the Infinity Cache)
   cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
                  solve of the same grid
 """
@@ -259,6 +261,34 @@ def _cpu_model():
     return "unknown"
 
 
+def stream_reference(torch, sizes, reps=30):
+    """Context for the roofline fraction: what plain element-wise torch kernels
+    (FP64; events around `reps` back-to-back launches after 5 warm-up ones)
+    reach on this GPU, in GB/s of bytes read + written, for vectors of each
+    size in `sizes` (elements): copy (1 read, 1 write), a + b (2, 1) and
+    a + b * c (3, 1)."""
+    out = {}
+    for n in sizes:
+        a, b, c, d = (torch.rand(n, dtype=torch.float64, device="cuda") for _ in range(4))
+        row = {}
+        for name, fn, nvec in (("copy", lambda: d.copy_(a), 2),
+                               ("add", lambda: torch.add(a, b, out=d), 3),
+                               ("fma", lambda: torch.addcmul(a, b, c, out=d), 4)):
+            for _ in range(5):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            row[name] = 8.0 * n * nvec / us / 1e3   # GB/s
+        out[str(n)] = row
+        del a, b, c, d
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,7 +355,9 @@ def main():
                 "traffic": committed_traffic(mg_ar["roof_shape"]) if prob.name == "3d-128^3" else None,
                 "kernel": roof_kernel(mg_ar["roof_shape"]),
                 "bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
-                "launches": mg_ar["kernel_launches"]}
+                "launches": mg_ar["kernel_launches"],
+                "stream_ref": stream_reference(torch, [prob.nnodes, 64 << 20])}
+        log(f"[bench] plain streaming reference (GB/s): {roof['stream_ref']}")
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle (one MGCG solve) ...")

@@ -26,6 +26,11 @@ Prints one JSON line:
                  FP32 multigrid over BF16 densities, its residual replaced by
                  the FP64 one every 1e-3 of reduction, same 1e-8 FP64 residual
                  test); reported beside value, which stays the all-FP64 loop
+  paper_setting  the MGAR and plain-MGCG loops again in the paper's solver
+                 settings (reconstruction criterion eps1 = 0.5, MGCG accuracy
+                 eps2 = 1e-6), same workload and cycles: s/opt-iter, paths,
+                 efficiency improvement 1 - t_MGAR / t_MGCG (the paper's
+                 measure) and the relative difference of the final objectives
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events recorded at
                  the start and end of each launch in the timed cycles, against
@@ -90,13 +95,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None, roof_cycles=0):
+def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=None, roof_cycles=0,
+             eps_accept=None):
     """Warm-up cycles, then `steps` timed cycles. The roofline kernel is timed
     with HIP events recorded at the start and end of each of its launches:
     over the timed cycles (roof_cycles = 0, the default; kernels are launched
     eagerly, the library's default), or on roof_cycles further cycles (for
     runs that replay captured PCG iterations, where kernel timing cannot run)."""
-    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision, seed=seed)
+    opt = TopOpt(prob, W.element_source(prob), use_mgar=use_mgar, precision=precision, seed=seed,
+                 eps_accept=eps_accept)
     for _ in range(warmup):
         opt.step()
     if roof_cycles == 0:
@@ -303,6 +310,8 @@ def main():
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned+mixed loop (network trained on the pairs of cycles 2..20, used from 31)")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the MGAR and MGCG loops in the paper's solver settings (eps1 0.5, eps2 1e-6)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
     args = ap.parse_args()
@@ -339,6 +348,23 @@ def main():
                            seed={"train_until": 20, "steps": 120, "lag": 10})
         log(f"[bench] learned+mixed MGAR loop: {learned['s_per_opt_iter']*1e3:.3f} ms/cycle, "
             f"guess used in {learned['seed_used_cycles']} cycles")
+    paper = None
+    if not args.no_paper:
+        # the paper's solver settings (Sec. 3.1, 4): reconstruction criterion
+        # eps1 = 0.5, MGCG accuracy eps2 = 1e-6, on the same workload and cycles
+        import dataclasses
+        pp = dataclasses.replace(prob, tol=1e-6)
+        p_ar = run_loop(pp, True, args.warmup, args.steps, W, TopOpt, torch, eps_accept=0.5)
+        p_cg = run_loop(pp, False, args.warmup, args.steps, W, TopOpt, torch)
+        paper = {"eps1": 0.5, "eps2": 1e-6,
+                 "mgar": {k: p_ar[k] for k in ("s_per_opt_iter", "cg_iters_mean", "paths", "final_compliance")},
+                 "mgcg": {k: p_cg[k] for k in ("s_per_opt_iter", "cg_iters_mean", "paths", "final_compliance")},
+                 "efficiency_improvement": 1.0 - p_ar["s_per_opt_iter"] / p_cg["s_per_opt_iter"],
+                 "objective_rel_diff": abs(p_ar["final_compliance"] - p_cg["final_compliance"])
+                 / abs(p_cg["final_compliance"])}
+        log(f"[bench] paper setting (eps1 0.5, eps2 1e-6): MGAR {p_ar['s_per_opt_iter']*1e3:.3f} ms/cycle "
+            f"(paths {p_ar['paths']}), MGCG {p_cg['s_per_opt_iter']*1e3:.3f} ms/cycle, "
+            f"efficiency improvement {100 * paper['efficiency_improvement']:.1f} %")
     batch = None
     if not args.no_batch:
         batch = run_batched(W, M, torch)
@@ -393,6 +419,7 @@ def main():
         "mgar_mixed": mixed,
         "learned_mixed": learned,
         "batched": batch,
+        "paper_setting": paper,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

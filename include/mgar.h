@@ -85,7 +85,7 @@ typedef struct {
   int refinements;        /* FP32 segments between FP64 residual replacements (mixed mode) */
   double res_ca;          /* Eq 28 residual of the reduced solution (NaN for pure MGCG) */
   double res_final;       /* ||q - K t|| / ||q|| of the returned t: recursive residual of the last CG iterate */
-  float ms;               /* device time of the call, milliseconds */
+  float ms;               /* device time of the call, milliseconds (-1: timing off, mgar_set_timing) */
 } mgar_stats;
 
 /* Fill *p with the defaults above for a grid; fix box empty. */
@@ -98,6 +98,10 @@ void mgar_default_params(mgar_params* p);
 int mgar_setup(const mgar_params* p, void* stream, mgar_handle** out);
 void mgar_destroy(mgar_handle* h);
 int mgar_set_stream(mgar_handle* h, void* stream);
+/* Per-solve device timing (mgar_stats.ms) on (default) or off. Timing waits
+ * for the solve's last kernel on the host; off, the solves return without that
+ * synchronisation and ms is -1. */
+int mgar_set_timing(mgar_handle* h, int on);
 const char* mgar_strerror(int code);
 /* Sizes: nodes, elements, and the nodes of grid `level`. */
 int mgar_sizes(const mgar_handle* h, int level, long long* nnodes, long long* nelem);

@@ -69,6 +69,7 @@ struct mgar_handle {
   int ntap = 0;
   int tap_hr = 0;                         // largest |offset| of a filter tap
   int pcg_hint = 0;                       // iterations of the last FP64 PCG solve
+  bool timing = true;                     // per-solve device time (stats->ms; one host sync)
   double rate32 = -1.0;                   // last observed contraction per FP32 PCG iteration
   bool has_k0 = false;
   int lt = 1;                             // first grid handled by the V-cycle tail kernel
@@ -831,6 +832,10 @@ void stats_init(mgar_stats* st) {
 }
 
 int finish_timing(mgar_handle* h, mgar_stats* st) {
+  if (!h->timing) {
+    if (st) st->ms = -1.f;
+    return MGAR_OK;
+  }
   HIPCK(hipEventRecord(h->e1, h->s));
   HIPCK(hipEventSynchronize(h->e1));
   if (st) {
@@ -847,16 +852,16 @@ int orthonormalise(mgar_handle* h) {
   const long long N = h->N;
   for (int j = 0; j < m; ++j) {
     double* v = h->R + (long long)j * N;
-    // squared norms reduced inside the dot launch (the last block adds the
-    // block partials in order)
-    launch_dot(v, v, N, h->pa, nullptr, h->s, h->cnt, &h->md->n0[j]);
+    int np = launch_dot(v, v, N, h->pa, nullptr, h->s);
+    launch_finalize(h->pa, np, &h->md->n0[j], nullptr, h->s);
     if (j > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        const int np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
+        np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
         launch_finalize_multi(h->pa, np, j, h->md->c, h->s);
         launch_gs_update(v, h->R, j, N, h->md->c, N, h->s);
       }
-      launch_dot(v, v, N, h->pa, nullptr, h->s, h->cnt, &h->scal[0]);
+      np = launch_dot(v, v, N, h->pa, nullptr, h->s);
+      launch_finalize(h->pa, np, &h->scal[0], nullptr, h->s);
     }
     // the first column has nothing to be projected out: its norm is n0
     launch_gs_normalize(v, N, h->md, j, j > 0 ? &h->scal[0] : &h->md->n0[0], h->s);
@@ -1210,7 +1215,8 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   launch_gram_finalize(h->pa, np, m, h->md, h->s);
   np = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s);
   launch_finalize(h->pa, np, &h->md->res2, nullptr, h->s);
-  launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s, h->cnt, &h->md->qq);
+  np = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+  launch_finalize(h->pb, np, &h->md->qq, nullptr, h->s);
   LAUNCHCK();
   MgarDev hm;
   HIPCK(hipMemcpyAsync(&hm, h->md, sizeof(MgarDev), hipMemcpyDeviceToHost, h->s));
@@ -1284,7 +1290,9 @@ int oc_update(mgar_handle* h, const double* x, const double* dc, const double* d
   OcDev ho;
   int passes = 0;
   for (;;) {
-    const int chunk = passes == 0 ? 5 : 2;   // typically 4-6 passes
+    // typically 4-7 passes; passes after convergence return at once, so the
+    // first batch is sized to need no second synchronisation
+    const int chunk = passes == 0 ? 7 : 4;
     for (int c = 0; c < chunk; ++c) {
       const int np = launch_oc_pass(x, dc, dv, h->E, move, h->oc, h->pa, h->s);
       launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);
@@ -1303,6 +1311,12 @@ int oc_update(mgar_handle* h, const double* x, const double* dc, const double* d
   if (x_new == x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
   LAUNCHCK();
   if (lambda) *lambda = 0.5 * (ho.l1 + ho.l2);
+  return MGAR_OK;
+}
+
+int mgar_set_timing(mgar_handle* h, int on) {
+  if (!h) return MGAR_E_ARG;
+  h->timing = on != 0;
   return MGAR_OK;
 }
 

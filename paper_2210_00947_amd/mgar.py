@@ -28,7 +28,7 @@ PATH_MGCG, PATH_ACCEPT, PATH_FALLBACK = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 EXPORTS = [
-    "mgar_default_params", "mgar_setup", "mgar_destroy", "mgar_set_stream", "mgar_strerror",
+    "mgar_default_params", "mgar_setup", "mgar_destroy", "mgar_set_stream", "mgar_set_timing", "mgar_strerror",
     "mgar_sizes", "mgar_load_vector", "mgar_density_filter", "mgcg_solve", "mgar_solve",
     "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
@@ -88,6 +88,7 @@ def lib():
         L.mgar_destroy.argtypes = [P]
         L.mgar_destroy.restype = None
         L.mgar_set_stream.argtypes = [P, VP]
+        L.mgar_set_timing.argtypes = [P, I]
         L.mgar_strerror.argtypes = [I]
         L.mgar_strerror.restype = ctypes.c_char_p
         L.mgar_sizes.argtypes = [P, I, ctypes.POINTER(LL), ctypes.POINTER(LL)]
@@ -202,6 +203,9 @@ class Handle:
 
     def set_stream(self, stream):
         _check(self._L.mgar_set_stream(self.h, ctypes.c_void_p(stream)), "mgar_set_stream")
+
+    def mgar_set_timing(self, on):
+        _check(self._L.mgar_set_timing(self.h, int(bool(on))), "mgar_set_timing")
 
     def mgar_load_vector(self, Qe, q):
         _check(self._L.mgar_load_vector(self.h, _ptr(Qe, self.E, "Qe"), _ptr(q, self.N, "q")),

@@ -61,8 +61,10 @@ class GuessSchedule:
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
                  eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
-                 autotune=True, seed=None, device="cuda"):
-        """seed: None, or a dict enabling the learned initial guess with keys
+                 autotune=True, seed=None, timing=False, device="cuda"):
+        """timing: per-solve device time in Cycle.solve_ms (one more host
+        synchronisation per solve). seed: None, or a dict enabling the learned
+        initial guess with keys
         pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
         used from the next cycle on), steps (Adam steps after cycle
         train_until), lr, init_seed, backoff (GuessSchedule on; default True),
@@ -77,6 +79,9 @@ class TopOpt:
                                    basis_x0_zero=basis_x0_zero, precision=precision,
                                    inner_tol=inner_tol)
         self.h = M.Handle(self.params)
+        # per-solve device timing costs a host synchronisation per solve; off,
+        # Cycle.solve_ms is -1
+        self.h.mgar_set_timing(timing)
         self.tune_source = None
         if autotune:
             from . import tune

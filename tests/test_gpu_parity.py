@@ -154,6 +154,32 @@ def test_mgcg_parity(prob):
     assert rel_l2(host(T), texact) < 1e-6
 
 
+def test_timing_switch_changes_nothing_but_ms():
+    """mgar_set_timing: with timing off the solves skip their final host
+    synchronisation and report ms = -1; temperatures, paths and iteration
+    counts are those of the timed solves, bit for bit."""
+    import torch
+    prob = PROBS[-2]
+    out = []
+    for on in (1, 0):
+        h = handle(prob)
+        h.mgar_set_timing(on)
+        q = _load(prob, h)
+        x0 = W.random_density(prob.nelem, 11, 0.0, 1.0)
+        x1 = np.clip(x0 + 0.02 * W.random_vector(prob.nelem, 12), 0.0, 1.0)
+        T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+        T1 = torch.empty_like(T0)
+        s0 = h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+        s1 = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+        torch.cuda.synchronize()
+        out.append((host(T0), host(T1), s0, s1))
+    (a0, a1, sa0, sa1), (b0, b1, sb0, sb1) = out
+    assert np.array_equal(a0, b0) and np.array_equal(a1, b1)
+    for sa, sb in ((sa0, sb0), (sa1, sb1)):
+        assert (sa["path"], sa["cg_iters"], sa["rc"]) == (sb["path"], sb["cg_iters"], sb["rc"])
+        assert sa["ms"] > 0.0 and sb["ms"] == -1.0
+
+
 @pytest.mark.parametrize("prob", PROBS, ids=IDS)
 @pytest.mark.parametrize("m,eps,x0zero", [(2, 1e-8, False), (2, 0.5, False), (3, 0.5, True),
                                            (1, 0.5, False), (4, 1e-8, True)])

@@ -142,6 +142,14 @@ int sens_filter(mgar_handle* h, const double* xphys, const double* T, const doub
 int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv,
               double volfrac, double move, double* x_new, double* lambda);
 
+/* sens_filter followed by oc_update (the same kernels, results and outputs),
+ * for the optimisation loop: the compliance comes back in the OC update's
+ * first host synchronisation instead of one of its own. compliance and lambda
+ * (host) may be NULL. */
+int mgar_sens_oc(mgar_handle* h, const double* xphys, const double* T, const double* q, const double* x,
+                 double volfrac, double move, double* dc, double* dv, double* x_new, double* compliance,
+                 double* lambda);
+
 /* Drop K0: the next mgar_solve returns MGAR_E_STATE until an mgcg_solve. */
 int mgar_reset(mgar_handle* h);
 

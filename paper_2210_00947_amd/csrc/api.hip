@@ -35,6 +35,7 @@ struct HostPin {
   int status;
   int pad;
   double extra[4];
+  OcDev oc;
 };
 static_assert(offsetof(HostPin, status) == sizeof(CgState), "status word follows the state");
 
@@ -1263,28 +1264,37 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   return rc;
 }
 
-int sens_filter(mgar_handle* h, const double* xphys, const double* T, const double* q, double* dc,
-                double* dv, double* compliance) {
-  if (!h || !xphys || !T || !q || !dc || !dv) return MGAR_E_ARG;
+// Sensitivities and their filter; with `compliance`, q^T T is also reduced
+// into h->scal[1] (no host synchronisation here).
+static void enqueue_sens(mgar_handle* h, const double* xphys, const double* T, const double* q, double* dc,
+                  double* dv, bool compliance) {
   const Geo& g = h->lv[0].g;
   launch_sens_elem(g, xphys, T, h->invHs, h->p.k0, h->p.kmin, h->p.penal, h->gtmp, h->s);
   launch_filter_fwd(g, h->tap_off, h->tap_w, h->ntap, h->tap_hr, h->gtmp, nullptr, dc, h->s);
   launch_copy(h->wvol, dv, h->E, h->s);
-  LAUNCHCK();
   if (compliance) {
     launch_mask_copy(g, q, h->qm, h->s);
     const int np = launch_dot(h->qm, T, h->N, h->pa, nullptr, h->s);
     launch_finalize(h->pa, np, &h->scal[1], nullptr, h->s);
-    LAUNCHCK();
+  }
+}
+
+int sens_filter(mgar_handle* h, const double* xphys, const double* T, const double* q, double* dc,
+                double* dv, double* compliance) {
+  if (!h || !xphys || !T || !q || !dc || !dv) return MGAR_E_ARG;
+  enqueue_sens(h, xphys, T, q, dc, dv, compliance != nullptr);
+  LAUNCHCK();
+  if (compliance) {
     HIPCK(hipMemcpyAsync(compliance, &h->scal[1], sizeof(double), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
   }
   return MGAR_OK;
 }
 
-int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv, double volfrac,
-              double move, double* x_new, double* lambda) {
-  if (!h || !x || !dc || !dv || !x_new) return MGAR_E_ARG;
+// The OC update; with dev_scalar, that device value comes back to
+// *host_scalar in the first synchronisation (through the pinned buffer).
+static int oc_run(mgar_handle* h, const double* x, const double* dc, const double* dv, double volfrac,
+                  double move, double* x_new, double* lambda, const double* dev_scalar, double* host_scalar) {
   const double target = volfrac * (double)h->E;
   launch_oc_init(h->oc, target, h->s);
   OcDev ho;
@@ -1297,21 +1307,40 @@ int oc_update(mgar_handle* h, const double* x, const double* dc, const double* d
       const int np = launch_oc_pass(x, dc, dv, h->E, move, h->oc, h->pa, h->s);
       launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);
     }
-    passes += chunk;
     // the update from the multiplier reached so far, enqueued before the
     // synchronisation (it only reads the bisection state); when more passes
     // follow, the next one overwrites x_new. Not when x_new is x itself:
     // later passes still read x.
     if (x_new != x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
     LAUNCHCK();
-    HIPCK(hipMemcpyAsync(&ho, h->oc, sizeof(OcDev), hipMemcpyDeviceToHost, h->s));
+    if (passes == 0 && dev_scalar)
+      HIPCK(hipMemcpyAsync(&h->hpin->extra[0], dev_scalar, sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCK(hipMemcpyAsync(&h->hpin->oc, h->oc, sizeof(OcDev), hipMemcpyDeviceToHost, h->s));
     HIPCK(hipStreamSynchronize(h->s));
+    if (passes == 0 && dev_scalar) *host_scalar = h->hpin->extra[0];
+    ho = h->hpin->oc;
+    passes += chunk;
     if (ho.done || passes > 64) break;
   }
   if (x_new == x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
   LAUNCHCK();
   if (lambda) *lambda = 0.5 * (ho.l1 + ho.l2);
   return MGAR_OK;
+}
+
+int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv, double volfrac,
+              double move, double* x_new, double* lambda) {
+  if (!h || !x || !dc || !dv || !x_new) return MGAR_E_ARG;
+  return oc_run(h, x, dc, dv, volfrac, move, x_new, lambda, nullptr, nullptr);
+}
+
+int mgar_sens_oc(mgar_handle* h, const double* xphys, const double* T, const double* q, const double* x,
+                 double volfrac, double move, double* dc, double* dv, double* x_new, double* compliance,
+                 double* lambda) {
+  if (!h || !xphys || !T || !q || !x || !dc || !dv || !x_new) return MGAR_E_ARG;
+  enqueue_sens(h, xphys, T, q, dc, dv, compliance != nullptr);
+  LAUNCHCK();
+  return oc_run(h, x, dc, dv, volfrac, move, x_new, lambda, compliance ? &h->scal[1] : nullptr, compliance);
 }
 
 int mgar_set_timing(mgar_handle* h, int on) {

@@ -30,7 +30,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = [
     "mgar_default_params", "mgar_setup", "mgar_destroy", "mgar_set_stream", "mgar_set_timing", "mgar_strerror",
     "mgar_sizes", "mgar_load_vector", "mgar_density_filter", "mgcg_solve", "mgar_solve",
-    "sens_filter", "oc_update", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
+    "sens_filter", "oc_update", "mgar_sens_oc", "mgar_reset", "mgar_op_apply", "mgar_op_jacobi",
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
     "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
     "mgar_tune_set", "mgar_set_graphs", "mgar_residual", "mgar_net_create", "mgar_net_destroy", "mgar_net_sizes",
@@ -98,6 +98,7 @@ def lib():
             getattr(L, f).argtypes = [P, VP, VP, VP, D, VP, ctypes.POINTER(mgar_stats)]
         L.sens_filter.argtypes = [P, VP, VP, VP, VP, VP, ctypes.POINTER(D)]
         L.oc_update.argtypes = [P, VP, VP, VP, D, D, VP, ctypes.POINTER(D)]
+        L.mgar_sens_oc.argtypes = [P, VP, VP, VP, VP, D, D, VP, VP, VP, ctypes.POINTER(D), ctypes.POINTER(D)]
         L.mgar_reset.argtypes = [P]
         L.mgar_op_apply.argtypes = [P, I, VP, VP, VP]
         L.mgar_op_jacobi.argtypes = [P, I, VP, VP, VP, VP]
@@ -243,6 +244,17 @@ class Handle:
                                  _ptr(dv, self.E, "dv"), float(volfrac), float(move),
                                  _ptr(x_new, self.E, "x_new"), ctypes.byref(lam)), "oc_update")
         return lam.value
+
+    def mgar_sens_oc(self, xphys, T, q, x, volfrac, move, dc, dv, x_new):
+        """sens_filter then oc_update with one host synchronisation; returns
+        (compliance, lambda)."""
+        c, lam = ctypes.c_double(), ctypes.c_double()
+        _check(self._L.mgar_sens_oc(self.h, _ptr(xphys, self.E, "xphys"), _ptr(T, self.N, "T"),
+                                    _ptr(q, self.N, "q"), _ptr(x, self.E, "x"), float(volfrac), float(move),
+                                    _ptr(dc, self.E, "dc"), _ptr(dv, self.E, "dv"),
+                                    _ptr(x_new, self.E, "x_new"), ctypes.byref(c), ctypes.byref(lam)),
+               "mgar_sens_oc")
+        return c.value, lam.value
 
     def mgar_reset(self):
         _check(self._L.mgar_reset(self.h), "mgar_reset")

@@ -190,8 +190,8 @@ class TopOpt:
                     self.pairs.append((self.xphys.clone(), self.T.clone(), scale))
             if self.k == self.seed["train_until"]:
                 self._seed_train()
-        f = h.sens_filter(self.xphys, self.T, self.q, self.dc, self.dv)
-        lam = h.oc_update(self.x, self.dc, self.dv, p.volfrac, p.move, self.xnew)
+        f, lam = h.mgar_sens_oc(self.xphys, self.T, self.q, self.x, p.volfrac, p.move, self.dc, self.dv,
+                                self.xnew)
         self.x, self.xnew = self.xnew, self.x
         self.T, self.T_prev = self.T_prev, self.T
         return Cycle(self.k, f, st["path"], st["cg_iters"], st["res_ca"], st["res_final"],

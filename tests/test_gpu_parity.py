@@ -154,6 +154,33 @@ def test_mgcg_parity(prob):
     assert rel_l2(host(T), texact) < 1e-6
 
 
+def test_sens_oc_equals_sens_filter_then_oc_update():
+    """mgar_sens_oc (one host synchronisation) gives the outputs of
+    sens_filter followed by oc_update bit for bit."""
+    import torch
+    prob = PROBS[-2]
+    h = handle(prob)
+    q = _load(prob, h)
+    x = W.random_density(prob.nelem, 21, 0.2, 0.6)
+    xphys = dev(W.random_density(prob.nelem, 22, 0.0, 1.0))
+    T = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgcg_solve(xphys, q, None, 1e-8, T)
+    outs = []
+    for combined in (False, True):
+        dc, dv, xn = (torch.empty(prob.nelem, dtype=torch.float64, device="cuda") for _ in range(3))
+        if combined:
+            f, lam = h.mgar_sens_oc(xphys, T, q, dev(x), prob.volfrac, prob.move, dc, dv, xn)
+        else:
+            f = h.sens_filter(xphys, T, q, dc, dv)
+            lam = h.oc_update(dev(x), dc, dv, prob.volfrac, prob.move, xn)
+        torch.cuda.synchronize()
+        outs.append((f, lam, host(dc), host(dv), host(xn)))
+    a, b = outs
+    assert a[0] == b[0] and a[1] == b[1]
+    for u, v in zip(a[2:], b[2:]):
+        assert np.array_equal(u, v)
+
+
 def test_timing_switch_changes_nothing_but_ms():
     """mgar_set_timing: with timing off the solves skip their final host
     synchronisation and report ms = -1; temperatures, paths and iteration

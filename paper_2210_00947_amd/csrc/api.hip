@@ -57,7 +57,6 @@ struct mgar_handle {
   double* dg0 = nullptr;                  // diagonal of K0 on the finest grid (3D, FP64 hierarchy)
   bool dg0_valid = false;
   double *pa = nullptr, *pb = nullptr, *pc = nullptr;  // partial-sum buffers
-  unsigned* cnt = nullptr;                // last-block counters of in-launch reductions
   long long part_cap = 0;
   double* scal = nullptr;                 // device scalars
   CgState* st = nullptr;
@@ -922,7 +921,7 @@ void mgar_destroy(mgar_handle* h) {
     if (v.xb) (void)hipFree(v.xb);
   }
   void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2, h->dg0,
-                  h->cw, h->pa, h->pb, h->pc, h->scal, h->cnt, h->st, h->md, h->oc, h->R, h->Wm,
+                  h->cw, h->pa, h->pb, h->pc, h->scal, h->st, h->md, h->oc, h->R, h->Wm,
                   h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -1000,8 +999,6 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
   ACK(dalloc(&h->pb, cap));
   ACK(dalloc(&h->pc, cap));
   ACK(dalloc(&h->scal, 16));
-  ACK(dalloc(&h->cnt, 16));
-  HIPCK(hipMemset(h->cnt, 0, 16 * sizeof(unsigned)));
   // the coarsest-build status word follows the CG state, so that one copy
   // to the host brings both
   ACK(dalloc(&h->st, 2));

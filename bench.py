@@ -36,7 +36,9 @@ Prints one JSON line:
                  the start and end of each launch in the timed cycles, against
                  8 TB/s; stream_ref gives, for scale, the GB/s of plain torch
                  element-wise kernels at the node-vector size and at 64 Mi
-                 elements (beyond the Infinity Cache)
+                 elements (beyond the Infinity Cache); effective gives the
+                 GB/s of one whole V-cycle and one whole PCG iteration with the
+                 bytes of their unfused definitions
   cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
                  solve of the same grid
 """
@@ -268,6 +270,40 @@ def _cpu_model():
     return "unknown"
 
 
+def effective_bandwidth(prob, W, TopOpt, torch, reps=50):
+    """Effective HBM rates of whole solver pieces at the workload's size, with
+    the algorithmic bytes of their unfused definitions (N = nodes, FP64):
+    one V-cycle through mgar_vcycle (masked copy of b 16N + V-cycle 112N;
+    back-to-back calls, so launch gaps are included) and one PCG iteration
+    (V-cycle 112N + apply 24N + x/r update 48N + p update 24N = 208N; the
+    marginal device time per iteration between two timed MGCG solves from
+    T0 = 0 to rel. residuals 1e-4 and 1e-8, so set-up cancels)."""
+    n = prob.nnodes
+    opt = TopOpt(prob, W.element_source(prob), use_mgar=False, timing=True)
+    opt.step()                       # K0 and its hierarchy from the first design
+    f64 = dict(dtype=torch.float64, device="cuda")
+    x = torch.empty(n, **f64)
+    for _ in range(3):
+        opt.h.mgar_vcycle(opt.q, None, x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        opt.h.mgar_vcycle(opt.q, None, x)
+    e1.record()
+    torch.cuda.synchronize()
+    vc_us = e0.elapsed_time(e1) * 1e3 / reps
+    sa = opt.h.mgcg_solve(opt.xphys, opt.q, None, 1e-4, x)
+    st = opt.h.mgcg_solve(opt.xphys, opt.q, None, 1e-8, x)
+    it_us = (st["ms"] - sa["ms"]) * 1e3 / max(st["cg_iters"] - sa["cg_iters"], 1)
+    out = {}
+    for name, by, us in (("vcycle", 128.0 * n, vc_us), ("pcg_iteration", 208.0 * n, it_us)):
+        gbs = by / us / 1e3
+        out[name] = {"bytes": by, "us": us, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    out["pcg_iteration"]["cg_iters"] = [sa["cg_iters"], st["cg_iters"]]
+    return out
+
+
 def stream_reference(torch, sizes, reps=30):
     """Context for the roofline fraction: what plain element-wise torch kernels
     (FP64; events around `reps` back-to-back launches after 5 warm-up ones)
@@ -384,6 +420,9 @@ def main():
                 "launches": mg_ar["kernel_launches"],
                 "stream_ref": stream_reference(torch, [prob.nnodes, 64 << 20])}
         log(f"[bench] plain streaming reference (GB/s): {roof['stream_ref']}")
+        if prob.dim == 3:
+            roof["effective"] = effective_bandwidth(prob, W, TopOpt, torch)
+            log(f"[bench] effective rates: {roof['effective']}")
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle (one MGCG solve) ...")

@@ -16,8 +16,8 @@ Prints one JSON line:
                  against the same solves one design at a time
   learned_mixed  the mixed-precision MGAR loop with the learned initial guess
                  (trained by the library's kernels on the pairs of cycles 2..20,
-                 in the background on its own stream during cycles 21..30,
-                 used from 31
+                 in the background on its own stream during cycles 21..45,
+                 used from 46
                  when its true residual beats the previous temperature's;
                  after a losing cycle the guess is left out for 1, 2, 4 ..
                  16 cycles, a win resets the gap); training time is inside
@@ -350,7 +350,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned+mixed loop (network trained on the pairs of cycles 2..20, used from 31)")
+                    help="skip the learned+mixed loop (network trained on the pairs of cycles 2..20, used from 46)")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the MGAR and MGCG loops in the paper's solver settings (eps1 0.5, eps2 1e-6)")
     ap.add_argument("--no-mixed", action="store_true",
@@ -386,7 +386,7 @@ def main():
     learned = None
     if not args.no_learned and prob.dim == 3:
         learned = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED,
-                           seed={"train_until": 20, "steps": 120, "lag": 10})
+                           seed={"train_until": 20, "steps": 120, "lag": 25})
         log(f"[bench] learned+mixed MGAR loop: {learned['s_per_opt_iter']*1e3:.3f} ms/cycle, "
             f"guess used in {learned['seed_used_cycles']} cycles")
     paper = None

@@ -1,7 +1,7 @@
-"""Mixed-precision form on the GPU (FP32 multigrid and inner PCG over BF16
-densities, FP64 inner products, reduced solve and outer refinement residual)
-against the FP64 CPU oracle. Tolerances are stated per result; the measured
-errors are printed (pytest -s) and recorded in the design doc."""
+"""Mixed-precision form on the GPU (one FP32 PCG run with FP32 multigrid over
+BF16 densities, its residual replaced by the FP64 one in segments; FP64 inner
+products, reduced solve and stopping test) against the FP64 CPU oracle.
+Tolerances are stated per result; the measured errors are printed (pytest -s)."""
 import numpy as np
 import pytest
 

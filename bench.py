@@ -358,8 +358,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(independent designs would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(independent designs would be sharded across GPUs, one process per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W

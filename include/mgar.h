@@ -205,7 +205,7 @@ int mgar_tune_get(const mgar_handle* h, int cls, int level, int mode, int* shape
 int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape);
 
 /* ||q - K(xphys) T|| / ||q|| over the free nodes, FP64, into *relres (host):
- * the judge of any initial guess (a learned seed is used only when its
+ * the criterion for any initial guess (a learned seed is used only when its
  * residual is below that of the previous temperature). */
 int mgar_residual(mgar_handle* h, const double* xphys, const double* q, const double* T, double* relres);
 

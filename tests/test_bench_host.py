@@ -1,0 +1,52 @@
+"""Host logic of bench.py: the committed traffic counters count only for the
+stencil source and launch shape they were taken on."""
+import importlib.util
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _counter_fields(path):
+    for line in open(path):
+        if line.strip().startswith("counters:"):
+            return dict(f.split("=", 1) for f in line.split()[1:])
+    raise AssertionError("no counters line")
+
+
+def test_committed_traffic_for_the_recorded_shape(bench):
+    kv = _counter_fields(bench.COUNTERS)
+    shape = [int(v) for v in kv["shape"].split(",")]
+    want = (float(kv["fetch_kib"]) + float(kv["write_kib"])) * 1024.0 * float(kv.get("scale", 1.0))
+    assert bench.committed_traffic(shape) == want
+
+
+def test_committed_traffic_refused_for_another_shape(bench):
+    kv = _counter_fields(bench.COUNTERS)
+    shape = [int(v) for v in kv["shape"].split(",")]
+    shape[1] += 1
+    assert bench.committed_traffic(shape) is None
+
+
+def test_committed_traffic_refused_for_another_source(bench, tmp_path, monkeypatch):
+    src = tmp_path / "stencil.hip"
+    src.write_text(open(bench.STENCIL_SRC).read() + "\n// changed\n")
+    monkeypatch.setattr(bench, "STENCIL_SRC", str(src))
+    kv = _counter_fields(bench.COUNTERS)
+    assert bench.committed_traffic([int(v) for v in kv["shape"].split(",")]) is None
+
+
+def test_more_than_one_gpu_is_refused(bench, monkeypatch):
+    monkeypatch.setattr("sys.argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2

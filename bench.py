@@ -39,6 +39,9 @@ Prints one JSON line:
                  elements (beyond the Infinity Cache); effective gives the
                  GB/s of one whole V-cycle and one whole PCG iteration with the
                  bytes of their unfused definitions
+  oversize_control  (with --oversize N) FP64 MGCG solves on an N^3 grid whose
+                 vectors exceed the Infinity Cache: the same kernel's rate,
+                 time per PCG iteration, DOF-solves/s
   cpu_baseline   the CPU oracle (NumPy/SciPy, FP64) timed on one full MGCG
                  solve of the same grid
 """
@@ -309,6 +312,58 @@ def effective_bandwidth(prob, W, TopOpt, torch, reps=50):
     return out
 
 
+def oversize_control(W, M, torch, n, nsolves=3):
+    """FP64 MGCG solves (T0 = 0, rel. residual 1e-8, uniform(0.3, 0.5)
+    densities) on an n^3 grid whose vectors no longer fit the 256 MB
+    Infinity Cache (n = 256: 16.98 M nodes, 136 MB per FP64 vector). Reports
+    the roofline kernel's rate there (HIP events at kernel start and end over
+    the timed solves), the time per PCG iteration with the 208N algorithmic
+    bytes of its unfused definition, and DOF-solves/s."""
+    from paper_2210_00947_amd import tune
+    levels = 1            # halve down to 4 elements per axis (5^3 coarsest nodes)
+    while (n >> (levels - 1)) > 4 and (n >> (levels - 1)) % 2 == 0:
+        levels += 1
+    prob = W.make_3d(f"3d-{n}^3", n, levels, volfrac=0.3, filter_r=2.0, maxit=80, x_init=0.3)
+    h = M.Handle(M.params_for(prob))
+    tune.autotune(h, h.params, tune.device_arch())
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(torch.as_tensor(W.element_source(prob), device="cuda"), q)
+    xs = [torch.as_tensor(W.reseeded_density(prob, r), device="cuda") for r in range(nsolves + 1)]
+    T = torch.empty_like(q)
+    h.mgcg_solve(xs[0], q, None, 1e-8, T)
+    h.mgar_profile(1 << ROOF_MODE)
+    h.mgar_profile_read()
+    for x in xs[1:]:
+        h.mgcg_solve(x, q, None, 1e-8, T)
+    launches, kms, kby = h.mgar_profile_read()
+    h.mgar_profile(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for x in xs[1:]:
+        its += h.mgcg_solve(x, q, None, 1e-8, T)["cg_iters"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    shape = h.mgar_tune_get(0, 0, ROOF_MODE)
+    h.close()
+    nfix = 1
+    for a in range(3):
+        nfix *= prob.fix_hi[a] - prob.fix_lo[a] + 1
+    free = prob.nnodes - nfix
+    it_s = el / max(its, 1)
+    gbs = kby / (kms * 1e-3) / 1e9 if kms > 0 else None
+    return {"grid": f"{n}^3", "levels": levels, "nodes": prob.nnodes, "solves": nsolves,
+            "ms_per_solve": el / nsolves * 1e3, "cg_iters_per_solve": its / nsolves,
+            "dof_solves_per_s": free * nsolves / el,
+            "pcg_iteration": {"us": it_s * 1e6, "bytes": 208.0 * prob.nnodes,
+                              "GB/s": 208.0 * prob.nnodes / it_s / 1e9,
+                              "frac": 208.0 * prob.nnodes / it_s / 1e9 / HBM_PEAK_GBS},
+            "roof_kernel": {"kernel": roof_kernel(shape), "launches": launches,
+                            "avg_launch_us": kms / max(launches, 1) * 1e3,
+                            "bytes_per_launch": kby / max(launches, 1),
+                            "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS if gbs else None}}
+
+
 def stream_reference(torch, sizes, reps=30):
     """Context for the roofline fraction: what plain element-wise torch kernels
     (FP64; events around `reps` back-to-back launches after 5 warm-up ones)
@@ -355,6 +410,8 @@ def main():
                     help="skip the MGAR and MGCG loops in the paper's solver settings (eps1 0.5, eps2 1e-6)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
+    ap.add_argument("--oversize", type=int, default=0, metavar="N",
+                    help="also run FP64 MGCG solves on an N^3 grid beyond the Infinity Cache (e.g. 256)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -428,6 +485,10 @@ def main():
         if prob.dim == 3:
             roof["effective"] = effective_bandwidth(prob, W, TopOpt, torch)
             log(f"[bench] effective rates: {roof['effective']}")
+    over = None
+    if args.oversize > 0:
+        over = oversize_control(W, M, torch, args.oversize)
+        log(f"[bench] oversize control: {over}")
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle (one MGCG solve) ...")
@@ -465,6 +526,7 @@ def main():
         "batched": batch,
         "paper_setting": paper,
         "roofline": roof,
+        "oversize_control": over,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

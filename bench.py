@@ -312,6 +312,15 @@ def effective_bandwidth(prob, W, TopOpt, torch, reps=50):
     return out
 
 
+def oversize_levels(n):
+    """Grids of the oversize control: halve n until 4 elements per axis are
+    left (5^3 coarsest nodes, as at 128^3), or until n is odd."""
+    levels = 1
+    while (n >> (levels - 1)) > 4 and (n >> (levels - 1)) % 2 == 0:
+        levels += 1
+    return levels
+
+
 def oversize_control(W, M, torch, n, nsolves=3):
     """FP64 MGCG solves (T0 = 0, rel. residual 1e-8, uniform(0.3, 0.5)
     densities) on an n^3 grid whose vectors no longer fit the 256 MB
@@ -320,9 +329,7 @@ def oversize_control(W, M, torch, n, nsolves=3):
     the timed solves), the time per PCG iteration with the 208N algorithmic
     bytes of its unfused definition, and DOF-solves/s."""
     from paper_2210_00947_amd import tune
-    levels = 1            # halve down to 4 elements per axis (5^3 coarsest nodes)
-    while (n >> (levels - 1)) > 4 and (n >> (levels - 1)) % 2 == 0:
-        levels += 1
+    levels = oversize_levels(n)
     prob = W.make_3d(f"3d-{n}^3", n, levels, volfrac=0.3, filter_r=2.0, maxit=80, x_init=0.3)
     h = M.Handle(M.params_for(prob))
     tune.autotune(h, h.params, tune.device_arch())

@@ -50,3 +50,16 @@ def test_more_than_one_gpu_is_refused(bench, monkeypatch):
     with pytest.raises(SystemExit) as e:
         bench.main()
     assert e.value.code == 2
+
+
+def test_oversize_grid_depth_matches_the_workload_hierarchies(bench):
+    """The oversize control halves its grid down to 4 elements per axis, the
+    depth of the 64^3 and 128^3 workloads."""
+    import workloads as W
+    assert bench.oversize_levels(W.C2.nelx) == W.C2.levels
+    assert bench.oversize_levels(W.C3.nelx) == W.C3.levels
+    assert bench.oversize_levels(256) == 7
+    for n in (96, 160, 256, 384):
+        L = bench.oversize_levels(n)
+        assert n % (1 << (L - 1)) == 0           # every coarse grid has whole elements
+        assert 2 <= n >> (L - 1) <= 4 or (n >> (L - 1)) % 2 == 1

@@ -21,7 +21,8 @@ Prints one JSON line:
                  when its true residual beats the previous temperature's;
                  after a losing cycle the guess is left out for 1, 2, 4 ..
                  16 cycles, a win resets the gap); training time is inside
-                 the timed cycles
+                 the timed cycles, which are always N_on..maxit (10..80 at
+                 128^3) whatever --steps says
   mgar_mixed     the MGAR loop in the mixed-precision form (one FP32 PCG run,
                  FP32 multigrid over BF16 densities, its residual replaced by
                  the FP64 one every 1e-3 of reduction, same 1e-8 FP64 residual
@@ -30,7 +31,8 @@ Prints one JSON line:
                  settings (reconstruction criterion eps1 = 0.5, MGCG accuracy
                  eps2 = 1e-6), same workload and cycles: s/opt-iter, paths,
                  efficiency improvement 1 - t_MGAR / t_MGCG (the paper's
-                 measure) and the relative difference of the final objectives
+                 measure) and the relative difference of the final objectives;
+                 always over cycles N_on..maxit (10..80 at 128^3)
   roofline       the finest-grid stencil kernel named there: algorithmic bytes
                  per launch / average launch time from HIP events recorded at
                  the start and end of each launch in the timed cycles, against
@@ -39,6 +41,10 @@ Prints one JSON line:
                  elements (beyond the Infinity Cache); effective gives the
                  GB/s of one whole V-cycle and one whole PCG iteration with the
                  bytes of their unfused definitions
+  paper_tables   (with --paper-tables) the paper's Table 2 and 3 experiments
+                 in its own solver settings with continuous filtering: MGCG
+                 evaluations, CG iterations, efficiency improvement and
+                 objective differences beside the paper's figures
   oversize_control  (with --oversize N) FP64 MGCG solves on an N^3 grid whose
                  vectors exceed the Infinity Cache: the same kernel's rate,
                  time per PCG iteration, DOF-solves/s
@@ -143,6 +149,7 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=
         "cg_iters_mean": sum(r.cg_iters for r in recs) / steps,
         "refinements_mean": sum(r.refinements for r in recs) / steps,
         "seed_used_cycles": sum(r.seed_used for r in recs),
+        "seed_evaluated_cycles": sum(r.res_seed == r.res_seed for r in recs),
         "paths": paths,
         "final_compliance": recs[-1].compliance,
         "kernel_launches": n,
@@ -230,6 +237,76 @@ def run_batched(W, M, torch, nsolves=5):
         "one_by_one_mgcg_s_per_solve": stime, "one_by_one_dof_solves_per_s": free / stime,
         "speedup": stime / bt,
     }
+
+
+# The paper's Table 2 (uniform source, volume fraction 0.5; PAPER sizes 360,
+# 720, 1560, 2040 elements per side) and Table 3 (four-quadrant source, 480
+# and 960, volume fractions 0.4 and 0.6) figures, for context next to the runs.
+PAPER_TABLE2 = {360: (107, 0.4165, 0.0015), 720: (115, 0.3911, 0.00037), 1560: (125, 0.3518, 0.000040),
+                2040: (127, 0.3410, 0.000033)}
+PAPER_TABLE3 = {(480, 0.4): (7.71, 7.38, 112, 0.4050, 0.0013), (480, 0.6): (7.69, 7.32, 102, 0.4546, 0.000050),
+                (960, 0.4): (7.81, 7.51, 124, 0.3593, 0.00028), (960, 0.6): (7.47, 7.24, 109, 0.4368, 0.000015)}
+
+
+def paper_levels(n, max_coarse_nodes=1024):
+    """Grids of the paper-mode runs: halve n while it stays even, until the
+    coarsest grid has at most max_coarse_nodes nodes (the dense coarsest solve)."""
+    levels = 1
+    while (n >> (levels - 1)) % 2 == 0 and ((n >> (levels - 1)) + 1) ** 2 > max_coarse_nodes:
+        levels += 1
+    return levels
+
+
+def paper_tables(W, TopOpt, torch, ncycles=300):
+    """The paper's experiments of Tables 2 and 3 in its solver settings (eps1 =
+    0.5, eps2 = 1e-6, cg_max 200, m = 2, N_on = 40 of 300 cycles, continuous
+    filtering from 1.4 L / 50 down to r_min = 3 over 250 cycles, source 1e-4
+    per unit volume or the four-quadrant source): an MGAR loop and a pure MGCG
+    loop per case. Sizes: Table 2's 360, 720, 1560 and 2040 elements per side
+    are not divisible by a power of two that brings the coarsest grid within
+    the dense coarsest solve (1024 nodes), so the nearest multiples of 32 are
+    run instead (352, 704, 1536, 2048; DOFs within 5 %), with the deepest
+    hierarchy that fits; Table 3's 480 and 960 are run as printed. Reported
+    per case: MGCG evaluations (pure-MGCG cycles plus rejected reductions),
+    accepted reductions, mean CG iterations of MGAR's and of the pure MGCG
+    loop, efficiency improvement 1 - t_MGAR / t_MGCG, relative difference of
+    the final objectives, and the paper's figures."""
+    cases = [("table2", n, 0.5, False, PAPER_TABLE2[p]) for n, p in ((352, 360), (704, 720), (1536, 1560),
+                                                                     (2048, 2040))]
+    cases += [("table3", n, vf, True, PAPER_TABLE3[(n, vf)]) for n in (480, 960) for vf in (0.4, 0.6)]
+    out = []
+    for table, n, vf, quad, paper in cases:
+        prob = W.paper_2d(n, paper_levels(n), volfrac=vf, maxit=ncycles)
+        qe = W.quadrant_source(prob) if quad else W.element_source(prob)
+        res = {}
+        for name, use_mgar in (("mgar", True), ("mgcg", False)):
+            opt = TopOpt(prob, qe, use_mgar=use_mgar, eps_accept=0.5, cg_max=200, continuous={"r_min": 3.0})
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cyc = opt.run(ncycles)
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0, cyc)
+            opt.h.close()
+        (ta, ca), (tc, cc) = res["mgar"], res["mgcg"]
+        row = {"table": table, "n": n, "levels": prob.levels, "dofs": prob.nnodes, "volfrac": vf,
+               "source": "quadrants" if quad else "uniform",
+               "mgcg_evaluations": sum(c.path != 1 for c in ca), "accepted": sum(c.path == 1 for c in ca),
+               "cg_iters_mgar": sum(c.cg_iters for c in ca) / max(1, sum(c.path != 1 for c in ca)),
+               "cg_iters_mgcg": sum(c.cg_iters for c in cc) / ncycles,
+               "s_mgar": ta, "s_mgcg": tc, "efficiency_improvement": 1.0 - ta / tc,
+               "objective_rel_diff": abs(ca[-1].compliance - cc[-1].compliance) / abs(cc[-1].compliance)}
+        if table == "table2":
+            row["paper"] = {"size": {352: 360, 704: 720, 1536: 1560, 2048: 2040}[n], "mgcg_evaluations": paper[0],
+                            "efficiency_improvement": paper[1], "objective_rel_diff": paper[2]}
+        else:
+            row["paper"] = {"cg_iters_mgar": paper[0], "cg_iters_mgcg": paper[1], "mgcg_evaluations": paper[2],
+                            "efficiency_improvement": paper[3], "objective_rel_diff": paper[4]}
+        log(f"[bench] paper {table} {n}^2 vf {vf}: MGCG evaluations {row['mgcg_evaluations']} "
+            f"(paper {row['paper']['mgcg_evaluations']}), efficiency {100 * row['efficiency_improvement']:.1f} % "
+            f"(paper {100 * row['paper']['efficiency_improvement']:.1f} %), objective diff "
+            f"{100 * row['objective_rel_diff']:.4f} %")
+        out.append(row)
+    return out
 
 
 def cpu_baseline(prob, W, nsolves=3):
@@ -417,6 +494,8 @@ def main():
                     help="skip the MGAR and MGCG loops in the paper's solver settings (eps1 0.5, eps2 1e-6)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="also run the paper's Table 2 and Table 3 experiments in its settings (300 cycles each)")
     ap.add_argument("--oversize", type=int, default=0, metavar="N",
                     help="also run FP64 MGCG solves on an N^3 grid beyond the Infinity Cache (e.g. 256)")
     args = ap.parse_args()
@@ -447,27 +526,36 @@ def main():
     if not args.no_mixed:
         mixed = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED)
         log(f"[bench] mixed-precision MGAR loop: {mixed['s_per_opt_iter']*1e3:.3f} ms/cycle")
+    # The forms whose behaviour depends on the cycle (the learned guess is
+    # trained on cycles 2..20 and first evaluated at 46; acceptances in the
+    # paper's settings come once the design settles) run the whole loop
+    # whatever --steps says: cycles 1..N_on-1 untimed, N_on..maxit timed.
+    full_warm = max(M.n_on(prob.maxit) - 1, 0)
+    full_steps = prob.maxit - full_warm
+    full_cycles = f"{full_warm + 1}..{prob.maxit}"
     learned = None
     if not args.no_learned and prob.dim == 3:
-        learned = run_loop(prob, True, args.warmup, args.steps, W, TopOpt, torch, precision=M.PREC_MIXED,
+        learned = run_loop(prob, True, full_warm, full_steps, W, TopOpt, torch, precision=M.PREC_MIXED,
                            seed={"train_until": 20, "steps": 120, "lag": 25})
-        log(f"[bench] learned+mixed MGAR loop: {learned['s_per_opt_iter']*1e3:.3f} ms/cycle, "
-            f"guess used in {learned['seed_used_cycles']} cycles")
+        learned["cycles"] = full_cycles
+        log(f"[bench] learned+mixed MGAR loop, cycles {full_cycles}: {learned['s_per_opt_iter']*1e3:.3f} "
+            f"ms/cycle, guess evaluated in {learned['seed_evaluated_cycles']} and used in "
+            f"{learned['seed_used_cycles']} cycles")
     paper = None
     if not args.no_paper:
         # the paper's solver settings (Sec. 3.1, 4): reconstruction criterion
         # eps1 = 0.5, MGCG accuracy eps2 = 1e-6, on the same workload and cycles
         import dataclasses
         pp = dataclasses.replace(prob, tol=1e-6)
-        p_ar = run_loop(pp, True, args.warmup, args.steps, W, TopOpt, torch, eps_accept=0.5)
-        p_cg = run_loop(pp, False, args.warmup, args.steps, W, TopOpt, torch)
-        paper = {"eps1": 0.5, "eps2": 1e-6,
+        p_ar = run_loop(pp, True, full_warm, full_steps, W, TopOpt, torch, eps_accept=0.5)
+        p_cg = run_loop(pp, False, full_warm, full_steps, W, TopOpt, torch)
+        paper = {"eps1": 0.5, "eps2": 1e-6, "cycles": full_cycles,
                  "mgar": {k: p_ar[k] for k in ("s_per_opt_iter", "cg_iters_mean", "paths", "final_compliance")},
                  "mgcg": {k: p_cg[k] for k in ("s_per_opt_iter", "cg_iters_mean", "paths", "final_compliance")},
                  "efficiency_improvement": 1.0 - p_ar["s_per_opt_iter"] / p_cg["s_per_opt_iter"],
                  "objective_rel_diff": abs(p_ar["final_compliance"] - p_cg["final_compliance"])
                  / abs(p_cg["final_compliance"])}
-        log(f"[bench] paper setting (eps1 0.5, eps2 1e-6): MGAR {p_ar['s_per_opt_iter']*1e3:.3f} ms/cycle "
+        log(f"[bench] paper setting (eps1 0.5, eps2 1e-6), cycles {full_cycles}: MGAR {p_ar['s_per_opt_iter']*1e3:.3f} ms/cycle "
             f"(paths {p_ar['paths']}), MGCG {p_cg['s_per_opt_iter']*1e3:.3f} ms/cycle, "
             f"efficiency improvement {100 * paper['efficiency_improvement']:.1f} %")
     batch = None
@@ -492,6 +580,9 @@ def main():
         if prob.dim == 3:
             roof["effective"] = effective_bandwidth(prob, W, TopOpt, torch)
             log(f"[bench] effective rates: {roof['effective']}")
+    tables = None
+    if args.paper_tables:
+        tables = paper_tables(W, TopOpt, torch)
     over = None
     if args.oversize > 0:
         over = oversize_control(W, M, torch, args.oversize)
@@ -534,6 +625,7 @@ def main():
         "paper_setting": paper,
         "roofline": roof,
         "oversize_control": over,
+        "paper_tables": tables,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -53,6 +53,8 @@ extern "C" {
 #define MGAR_PREC_MIXED 1        /* FP32 multigrid PCG over BF16 densities with FP64 residual replacement */
 
 #define MGAR_MAX_BASIS 8
+#define MGAR_MAX_FILTER_R2 64    /* largest ceil(filter radius) in 2D (element lengths) */
+#define MGAR_MAX_FILTER_R3 12    /* largest ceil(filter radius) in 3D */
 
 typedef struct mgar_handle mgar_handle;
 
@@ -114,6 +116,33 @@ int mgar_load_vector(mgar_handle* h, const double* Qe, double* q);
 /* Density filter, Eq 6-8: xphys_e = sum_j w_ej x_j / sum_j w_ej with the cone
  * weight w_ej = max(0, r - |c_e - c_j|), truncated at the domain boundary. */
 int mgar_density_filter(mgar_handle* h, const double* x, double* xphys);
+
+/* Change the density-filter radius (Eq 7-8) used by every later call of
+ * mgar_density_filter, sens_filter, oc_update and mgar_sens_oc: the filter
+ * taps, their normalisation Hs and the filtered-volume weights are rebuilt on
+ * the device. This is the per-cycle step of continuous density filtering
+ * (Eq 22-23: r^(k) = max(r_min, eta r^(k-1))), whose schedule the caller
+ * runs. r > 0 with ceil(r) <= MGAR_MAX_FILTER_R2 (2D) or MGAR_MAX_FILTER_R3
+ * (3D), else MGAR_E_ARG. Synchronises the handle's stream; reallocates the
+ * tap table only when r needs more taps than any earlier radius. */
+int mgar_set_filter_radius(mgar_handle* h, double r);
+
+/* Boundary-smoothing post-process (Sec. 2.3, Eq 24-27), run once on the final
+ * design. dc (E-vector): the filtered compliance sensitivities of that design
+ * (Eq 9-11, as sens_filter writes them). Their negatives, large where
+ * material pays most, are projected onto the nodes, ns_i = sum_e w_ie (-dc_e)
+ * / sum_e w_ie with the cone weight w_ie = max(0, r - |x_i - c_e|) to the
+ * element centroids (ns: N-vector output, may be NULL). Eq 24: rho_e = 1 when every node of e has
+ * ns > level, 0 when every one has ns < level, otherwise (Eq 25-27) the
+ * fraction of the (nsub+1)^d lattice points of e (corners included) at which
+ * the Q1 interpolation of its nodal values exceeds the level. The level is
+ * bisected on [min ns - 1, max ns] (100 halvings, or until the bracket is
+ * 1e-14 of its initial width), keeping sum_e rho_e >= volfrac * E at the
+ * lower end, which is returned in *level (host) with its volume sum_e rho_e
+ * in *volume (host); rho (E-vector output) is taken there. 0 < volfrac <= 1,
+ * 1 <= nsub <= 64, radius limits as mgar_set_filter_radius; synchronises. */
+int mgar_smooth_boundary(mgar_handle* h, const double* dc, double volfrac, double r, int nsub, double* rho,
+                         double* ns, double* level, double* volume);
 
 /* MGCG: PCG preconditioned by one V-cycle on K(xphys), started from T0 (may be
  * NULL = 0), until ||r||/||q|| <= tol or cg_max iterations. Makes K(xphys) the

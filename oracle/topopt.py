@@ -16,6 +16,13 @@ Test infrastructure only (see the package docstring).
 * Loop (Fig. 5 flow, Sec. 3.1): filter -> solve (MGCG while the 1-based cycle
   index is below N_on = floor(2 maxit / 15), MGAR afterwards) -> sensitivity
   -> update; the previous cycle's temperature seeds the next solve.
+* Continuous density filtering (Sec. 2.3, Eq 22-23): the radius shrinks
+  geometrically from r0 = alpha L to r_min over lp cycles, r^(k) =
+  max(r_min, eta r^(k-1)) with eta = exp((ln r_min - ln(alpha L)) / lp);
+  alpha = 1.4/50 and lp = 5/6 of the maximum cycle count unless stated. L is
+  the side length of the design domain in element edges (the largest axis).
+  Reading: cycle k (1-based) filters with r^(k-1), so the first cycle uses the
+  initial radius r0 and cycle lp + 1 the minimum one.
 """
 from __future__ import annotations
 
@@ -134,6 +141,7 @@ class CycleRecord:
     res_final: float
     volume: float
     change: float
+    radius: float = 0.0
 
 
 def n_on(maxit: int) -> int:
@@ -141,14 +149,51 @@ def n_on(maxit: int) -> int:
     return (2 * maxit) // 15
 
 
+def continuous_radii(r_min, r0, lp, count):
+    """Eq 22-23: the radii r^(0) = r0, r^(1), ..., r^(count-1), each step
+    r^(k) = max(r_min, eta r^(k-1)) with eta = exp((ln r_min - ln r0) / lp).
+    The schedule shrinks the radius, so r0 >= r_min."""
+    if not r0 >= r_min:
+        raise ValueError("the initial radius must not be below r_min")
+    eta = math.exp((math.log(r_min) - math.log(r0)) / lp)
+    radii = [float(r0)]
+    while len(radii) < count:
+        radii.append(max(r_min, eta * radii[-1]))
+    return radii
+
+
+def loop_radii(prob, maxit, continuous):
+    """Filter radius of each cycle 1..maxit: the fixed prob.filter_r, or with
+    `continuous` = dict(r_min, alpha = 1.4/50, lp = 5/6 prob.maxit) the
+    schedule of Eq 22-23 with r0 = alpha L (cycle k uses r^(k-1)). On a domain
+    so small that alpha L < r_min the radius stays r_min."""
+    if not continuous:
+        return [prob.filter_r] * maxit
+    L = max(prob.nelx, prob.nely, prob.nelz if prob.dim == 3 else 0)
+    alpha = continuous.get("alpha", 1.4 / 50)
+    lp = continuous.get("lp", 5.0 * prob.maxit / 6.0)
+    r_min = continuous["r_min"]
+    return continuous_radii(r_min, max(alpha * L, r_min), lp, maxit)
+
+
 def run_loop(prob, maxit=None, use_mgar=True, params: MgarParams = None, qelem=None,
-             x_init=None, on_cycle=None):
-    """The optimisation loop. Returns (x, xphys, t, records)."""
+             x_init=None, on_cycle=None, continuous=None):
+    """The optimisation loop. Returns (x, xphys, t, records). continuous: None
+    (fixed radius prob.filter_r) or the Eq 22-23 schedule (see loop_radii)."""
     maxit = prob.maxit if maxit is None else maxit
     params = params or MgarParams(eps_accept=prob.tol)
     solver = MgarSolver(prob, params, qelem)
     fep = solver.fep
-    filt = Filter(fep.grid, prob.filter_r)
+    radii = loop_radii(prob, maxit, continuous)
+    filters = {}
+
+    def filter_for(r):
+        if r not in filters:
+            filters.clear()
+            filters[r] = Filter(fep.grid, r)
+        return filters[r]
+
+    filt = filter_for(radii[0])
     x = np.full(fep.grid.nelem, prob.x_init) if x_init is None else np.array(x_init, float)
     t_prev = np.zeros(fep.grid.nnodes)
     non = n_on(prob.maxit)
@@ -156,6 +201,7 @@ def run_loop(prob, maxit=None, use_mgar=True, params: MgarParams = None, qelem=N
     xphys = filt.forward(x)
     t = t_prev
     for k in range(1, maxit + 1):
+        filt = filter_for(radii[k - 1])
         xphys = filt.forward(x)
         st = SolveStats()
         if (not use_mgar) or k < non:
@@ -166,7 +212,7 @@ def run_loop(prob, maxit=None, use_mgar=True, params: MgarParams = None, qelem=N
         xnew, _lam, _ = oc_update(x, dc, dv, filt, prob.volfrac, prob.move)
         change = float(np.abs(xnew - x).max())
         recs.append(CycleRecord(k, f, st.path, st.cg_iters, st.res_ca, st.res_final,
-                                float(xphys.mean()), change))
+                                float(xphys.mean()), change, radii[k - 1]))
         if on_cycle is not None:
             on_cycle(k, xphys, t)
         x = xnew

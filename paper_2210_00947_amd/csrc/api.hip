@@ -67,7 +67,12 @@ struct mgar_handle {
   int* tap_off = nullptr;
   double* tap_w = nullptr;
   int ntap = 0;
+  int tap_cap = 0;                        // taps the device table holds
   int tap_hr = 0;                         // largest |offset| of a filter tap
+  double filter_r = 0.0;                  // radius of the current filter
+  SmoothDev* sdev = nullptr;              // boundary-smoothing bisection state (allocated on first use)
+  double* spart = nullptr;                // its partial sums
+  long long spart_cap = 0;
   int pcg_hint = 0;                       // iterations of the last FP64 PCG solve
   bool timing = true;                     // per-solve device time (stats->ms; one host sync)
   double rate32 = -1.0;                   // last observed contraction per FP32 PCG iteration
@@ -185,7 +190,7 @@ int validate(const mgar_params* p) {
   if (p->precision != MGAR_PREC_FP64 && p->precision != MGAR_PREC_MIXED) return MGAR_E_PRECISION;
   if (p->precision == MGAR_PREC_MIXED && p->penal != 3.0) return MGAR_E_PRECISION;
   if (p->precision == MGAR_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return MGAR_E_ARG;
-  if ((int)std::ceil(p->filter_r) > 6) return MGAR_E_ARG;
+  if ((int)std::ceil(p->filter_r) > (p->dim == 3 ? MGAR_MAX_FILTER_R3 : MGAR_MAX_FILTER_R2)) return MGAR_E_ARG;
   const int s = 1 << (p->levels - 1);
   if (p->nelx % s || p->nely % s || (p->dim == 3 && p->nelz % s)) return MGAR_E_DIMS;
   return MGAR_OK;
@@ -812,6 +817,54 @@ int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, 
   return MGAR_OK;
 }
 
+// Cone filter of radius r (Eq 7-8): the taps (offsets within the radius,
+// weight r - distance), 1/Hs and the filtered-volume weights w = H^T (1/Hs),
+// which are also dv. The tap table grows on demand (its device copy is
+// reallocated only when a larger radius needs more taps than it holds).
+int set_filter(mgar_handle* h, double r) {
+  const int Rw = (int)std::ceil(r);
+  std::vector<int> off;
+  std::vector<double> w;
+  int hr = 0;
+  const int rz = (h->p.dim == 3) ? Rw : 0;
+  for (int dz = -rz; dz <= rz; ++dz)
+    for (int dy = -Rw; dy <= Rw; ++dy)
+      for (int dx = -Rw; dx <= Rw; ++dx) {
+        const double d = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+        const double wt = r - d;
+        if (wt > 0.0) {
+          off.push_back(dx); off.push_back(dy); off.push_back(dz);
+          w.push_back(wt);
+          hr = std::max({hr, std::abs(dx), std::abs(dy), std::abs(dz)});
+        }
+      }
+  const int n = (int)w.size();
+  if (n > h->tap_cap) {
+    HIPCK(hipStreamSynchronize(h->s));   // earlier filter launches may still read the old table
+    if (h->tap_off) HIPCK(hipFree(h->tap_off));
+    if (h->tap_w) HIPCK(hipFree(h->tap_w));
+    h->tap_off = nullptr;
+    h->tap_w = nullptr;
+    h->tap_cap = 0;
+    ACK(dalloc(&h->tap_off, 3LL * n));
+    ACK(dalloc(&h->tap_w, (long long)n));
+    h->tap_cap = n;
+  }
+  // stream-ordered upload: the launches that read the table follow on h->s
+  HIPCK(hipMemcpyAsync(h->tap_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, h->s));
+  HIPCK(hipMemcpyAsync(h->tap_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, h->s));
+  h->ntap = n;
+  h->tap_hr = hr;
+  h->filter_r = r;
+  const Geo& g0 = h->lv[0].g;
+  launch_filter_hs(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, h->s);
+  launch_filter_fwd(g0, h->tap_off, h->tap_w, h->ntap, h->tap_hr, h->invHs, nullptr, h->wvol, h->s);
+  LAUNCHCK();
+  // the host vectors are released on return: the copies must have left them
+  HIPCK(hipStreamSynchronize(h->s));
+  return MGAR_OK;
+}
+
 int check_coarse(mgar_handle* h) {
   if (h->status_valid && !h->coarse_pending) {   // read with the solver's last CG state
     h->status_valid = false;
@@ -922,7 +975,7 @@ void mgar_destroy(mgar_handle* h) {
   }
   void* ptrs[] = {h->kcur, h->rtmp, h->Ainv, h->qm, h->cx, h->cr, h->cz, h->cp, h->cp2, h->dg0,
                   h->cw, h->pa, h->pb, h->pc, h->scal, h->st, h->md, h->oc, h->R, h->Wm,
-                  h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w};
+                  h->invHs, h->wvol, h->gtmp, h->tap_off, h->tap_w, h->sdev, h->spart};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (h->hpin) (void)hipHostFree(h->hpin);
@@ -1064,33 +1117,7 @@ static int setup_impl(const mgar_params* p, void* stream, mgar_handle** out) {
       if (!tail_plan(gs.data(), ks.data(), h->ltf, h->L, sizeof(float), &h->tailf)) return MGAR_E_DIMS;
     }
   }
-  // cone filter taps (Eq 7-8): offsets within the radius, weight r - distance
-  {
-    const int Rw = (int)std::ceil(p->filter_r);
-    std::vector<int> off;
-    std::vector<double> w;
-    const int rz = (p->dim == 3) ? Rw : 0;
-    for (int dz = -rz; dz <= rz; ++dz)
-      for (int dy = -Rw; dy <= Rw; ++dy)
-        for (int dx = -Rw; dx <= Rw; ++dx) {
-          const double d = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
-          const double wt = p->filter_r - d;
-          if (wt > 0.0) {
-            off.push_back(dx); off.push_back(dy); off.push_back(dz);
-            w.push_back(wt);
-            h->tap_hr = std::max({h->tap_hr, std::abs(dx), std::abs(dy), std::abs(dz)});
-          }
-        }
-    h->ntap = (int)w.size();
-    ACK(dalloc(&h->tap_off, (long long)off.size()));
-    ACK(dalloc(&h->tap_w, (long long)w.size()));
-    HIPCK(hipMemcpy(h->tap_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
-    HIPCK(hipMemcpy(h->tap_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice));
-  }
-  launch_filter_hs(g0, h->tap_off, h->tap_w, h->ntap, h->invHs, h->s);
-  // w = H^T (1/Hs): the filtered-volume weights, which are also dv
-  launch_filter_fwd(g0, h->tap_off, h->tap_w, h->ntap, h->tap_hr, h->invHs, nullptr, h->wvol, h->s);
-  LAUNCHCK();
+  ACK(set_filter(h, p->filter_r));
   HIPCK(hipStreamSynchronize(h->s));
   return MGAR_OK;
 }
@@ -1133,6 +1160,40 @@ int mgar_density_filter(mgar_handle* h, const double* x, double* xphys) {
   launch_filter_fwd(h->lv[0].g, h->tap_off, h->tap_w, h->ntap, h->tap_hr, x, h->invHs, xphys, h->s);
   LAUNCHCK();
   return MGAR_OK;
+}
+
+int mgar_smooth_boundary(mgar_handle* h, const double* dc, double volfrac, double r, int nsub, double* rho,
+                         double* ns, double* level, double* volume) {
+  if (!h || !dc || !rho || !(volfrac > 0.0 && volfrac <= 1.0) || !(r > 0.0) || nsub < 1 || nsub > 64)
+    return MGAR_E_ARG;
+  if ((int)std::ceil(r) > (h->p.dim == 3 ? MGAR_MAX_FILTER_R3 : MGAR_MAX_FILTER_R2)) return MGAR_E_ARG;
+  const Geo& g = h->lv[0].g;
+  if (!h->sdev) ACK(dalloc(&h->sdev, 1));
+  const long long need = smooth_num_partials(g);
+  if (need > h->spart_cap) {
+    if (h->spart) HIPCK(hipFree(h->spart));
+    h->spart = nullptr;
+    h->spart_cap = 0;
+    ACK(dalloc(&h->spart, need));
+    h->spart_cap = need;
+  }
+  double* nsv = ns ? ns : h->rtmp;
+  launch_node_project(g, dc, r, nsv, h->s);
+  launch_smooth_bisect(g, nsv, volfrac * (double)h->E, nsub, 100, h->sdev, rho, h->spart, h->s);
+  LAUNCHCK();
+  SmoothDev hs;
+  HIPCK(hipMemcpyAsync(&hs, h->sdev, sizeof(SmoothDev), hipMemcpyDeviceToHost, h->s));
+  HIPCK(hipStreamSynchronize(h->s));
+  if (level) *level = hs.lo;
+  if (volume) *volume = hs.vol;
+  return MGAR_OK;
+}
+
+int mgar_set_filter_radius(mgar_handle* h, double r) {
+  if (!h || !(r > 0.0)) return MGAR_E_ARG;
+  if ((int)std::ceil(r) > (h->p.dim == 3 ? MGAR_MAX_FILTER_R3 : MGAR_MAX_FILTER_R2)) return MGAR_E_ARG;
+  if (r == h->filter_r) return MGAR_OK;
+  return set_filter(h, r);
 }
 
 int mgcg_solve(mgar_handle* h, const double* xphys, const double* q, const double* T0,

@@ -126,6 +126,14 @@ struct OcDev {
   int pad[2];
 };
 
+// Bisection state of the boundary-smoothing level (Eq 24-27).
+struct SmoothDev {
+  double lo, hi;             // bracket: volume(lo) >= target > volume(hi)
+  double width0;             // initial bracket width
+  double vol;                // volume at lo after the final pass
+  int steps, done;
+};
+
 // ---------------------------------------------------------------- reductions
 
 __device__ inline double wave_sum(double v) {

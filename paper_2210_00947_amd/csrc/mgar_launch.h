@@ -352,12 +352,18 @@ void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, doub
 void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
                         const int* skip, int sstride, hipStream_t s);
 
+// smooth.hip -----------------------------------------------------------------
+// Boundary smoothing (Eq 24-27): nodal projection of -dc with cone weights of
+// radius r, and the device bisection of the level that keeps the
+// target volume (max_steps halvings of [min ns - 1, max ns], stopping at a
+// bracket of 1e-14 of its initial width), followed by rho at the lower end
+// and its volume in sd->vol. part: smooth_num_partials(g) doubles.
+int smooth_num_partials(const Geo& g);
+void launch_node_project(const Geo& g, const double* dc, double r, double* ns, hipStream_t st);
+void launch_smooth_bisect(const Geo& g, const double* ns, double target, int nsub, int max_steps, SmoothDev* sd,
+                          double* rho, double* part, hipStream_t st);
+
 // topopt.hip -----------------------------------------------------------------
-struct FilterTaps {
-  int ntap;
-  int off[3 * 2197];   // dx, dy, dz per tap (window up to 13^3)
-  double w[2197];
-};
 void launch_simp(const double* xphys, double* k, long long n, double k0, double kmin, double penal,
                  hipStream_t s);
 void launch_load(const Geo& g, const double* Qe, double* q, hipStream_t s);

@@ -37,7 +37,8 @@ EXPORTS = [
     "mgar_net_set_params", "mgar_net_get_params", "mgar_net_infer", "mgar_net_output", "mgar_net_grad",
     "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
     "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
-    "mgar_profile", "mgar_profile_read",
+    "mgar_profile", "mgar_profile_read", "mgar_set_filter_radius",
+    "mgar_smooth_boundary",
 ]
 
 
@@ -111,6 +112,8 @@ def lib():
         L.mgar_op_bf16.argtypes = [P, VP, VP]
         L.mgar_profile.argtypes = [P, ctypes.c_uint]
         L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.mgar_set_filter_radius.argtypes = [P, D]
+        L.mgar_smooth_boundary.argtypes = [P, VP, D, D, I, VP, VP, ctypes.POINTER(D), ctypes.POINTER(D)]
         for f in EXPORTS:
             if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror", "mgar_batch_destroy",
                          "mgar_net_destroy"):
@@ -307,6 +310,17 @@ class Handle:
             raise ValueError("out must be an int16 GPU tensor with E entries")
         _check(self._L.mgar_op_bf16(self.h, _ptr(x, self.E, "x"), ctypes.c_void_p(out.data_ptr())),
                "mgar_op_bf16")
+
+    def mgar_smooth_boundary(self, dc, volfrac, r, rho, ns=None, nsub=4):
+        """Eq 24-27 post-process of the design whose sensitivities are dc; returns (level, volume)."""
+        lv, vol = ctypes.c_double(), ctypes.c_double()
+        _check(self._L.mgar_smooth_boundary(self.h, _ptr(dc, self.E, "dc"), float(volfrac), float(r), int(nsub),
+                                            _ptr(rho, self.E, "rho"), _ptr(ns, self.N, "ns"), ctypes.byref(lv),
+                                            ctypes.byref(vol)), "mgar_smooth_boundary")
+        return lv.value, vol.value
+
+    def mgar_set_filter_radius(self, r):
+        _check(self._L.mgar_set_filter_radius(self.h, float(r)), "mgar_set_filter_radius")
 
     def mgar_set_graphs(self, on):
         _check(self._L.mgar_set_graphs(self.h, int(bool(on))), "mgar_set_graphs")

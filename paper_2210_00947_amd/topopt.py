@@ -3,12 +3,14 @@
 One cycle: density filter (Eq 6) -> solve (MGCG while the cycle index is below
 N_on = 2/15 of the maximum cycle count, MGAR afterwards; Sec. 3.1-3.2) ->
 compliance and filtered sensitivities (Eq 5, 9-11) -> optimality-criteria
-update. Every step is a library call; this module only keeps the buffers and
-the cycle counter.
+update. Every step is a library call; this module only keeps the buffers, the
+cycle counter and the filter-radius schedule of continuous density filtering
+(Eq 22-23), whose radius it hands to the library when it changes.
 """
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import torch
 
@@ -29,6 +31,27 @@ class Cycle:
     seed_used: bool = False       # the learned guess replaced the previous temperature as T0
     res_seed: float = float("nan")
     res_prev: float = float("nan")
+    radius: float = float("nan")  # density-filter radius of the cycle
+
+
+def filter_radii(prob, ncycles, continuous=None):
+    """Filter radius of cycles 1..ncycles. Fixed: prob.filter_r. Continuous
+    (Eq 22-23), continuous = dict(r_min, alpha = 1.4/50, lp = 5/6 of
+    prob.maxit): r^(0) = max(alpha L, r_min) with L the longest side in
+    element edges, r^(k) = max(r_min, eta r^(k-1)), eta = exp((ln r_min -
+    ln r^(0)) / lp); cycle k filters with r^(k-1)."""
+    if not continuous:
+        return [float(prob.filter_r)] * ncycles
+    L = max(prob.nelx, prob.nely, prob.nelz if prob.dim == 3 else 0)
+    r_min = float(continuous["r_min"])
+    r = max(float(continuous.get("alpha", 1.4 / 50)) * L, r_min)
+    lp = float(continuous.get("lp", 5.0 * prob.maxit / 6.0))
+    eta = math.exp((math.log(r_min) - math.log(r)) / lp)
+    out = []
+    for _ in range(ncycles):
+        out.append(r)
+        r = max(r_min, eta * r)
+    return out
 
 
 class GuessSchedule:
@@ -61,9 +84,11 @@ class GuessSchedule:
 class TopOpt:
     def __init__(self, prob, qelem, use_mgar=True, n_basis=2, cg_max=200, x_init=None,
                  eps_accept=None, basis_x0_zero=False, precision=M.PREC_FP64, inner_tol=None,
-                 autotune=True, seed=None, timing=False, device="cuda"):
+                 autotune=True, seed=None, timing=False, continuous=None, device="cuda"):
         """timing: per-solve device time in Cycle.solve_ms (one more host
-        synchronisation per solve). seed: None, or a dict enabling the learned
+        synchronisation per solve). continuous: None (fixed filter radius
+        prob.filter_r) or the continuous-filtering schedule (filter_radii).
+        seed: None, or a dict enabling the learned
         initial guess with keys
         pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
         used from the next cycle on), steps (Adam steps after cycle
@@ -103,6 +128,8 @@ class TopOpt:
         self.dv = torch.empty(E, **f64)
         self.k = 0
         self.non = M.n_on(prob.maxit)
+        self.radii = filter_radii(prob, prob.maxit, continuous) if continuous else None
+        self.radius = float(prob.filter_r)
         self.seed = None
         if seed is not None:
             import workloads as W
@@ -173,6 +200,11 @@ class TopOpt:
     def step(self) -> Cycle:
         self.k += 1
         h, p = self.h, self.prob
+        if self.radii is not None:
+            r = self.radii[min(self.k, len(self.radii)) - 1]
+            if r != self.radius:
+                h.mgar_set_filter_radius(r)
+                self.radius = r
         h.mgar_density_filter(self.x, self.xphys)
         T0, used, r_seed, r_prev = self.T_prev, False, float("nan"), float("nan")
         if (self.seed is not None and self.k > self.seed["train_until"] + int(self.seed["lag"])
@@ -195,7 +227,27 @@ class TopOpt:
         self.x, self.xnew = self.xnew, self.x
         self.T, self.T_prev = self.T_prev, self.T
         return Cycle(self.k, f, st["path"], st["cg_iters"], st["res_ca"], st["res_final"],
-                     st["ms"], lam, st["refinements"], used, r_seed, r_prev)
+                     st["ms"], lam, st["refinements"], used, r_seed, r_prev, self.radius)
+
+    def postprocess(self, r_proj=None, nsub=4):
+        """Boundary smoothing after the loop (Sec. 2.3, Eq 24-27; Fig. 5): filter
+        the final design (the last cycle's radius), solve, sensitivities,
+        mgar_smooth_boundary with projection radius r_proj (default: that
+        filter radius), and one more solve on the smoothed densities. Returns
+        (rho, level, volume, compliance before, compliance after)."""
+        h, p = self.h, self.prob
+        E = self.h.E
+        f64 = dict(dtype=torch.float64, device=self.x.device)
+        h.mgar_density_filter(self.x, self.xphys)
+        st = h.mgcg_solve(self.xphys, self.q, self.T_prev, p.tol, self.T)
+        f0 = h.sens_filter(self.xphys, self.T, self.q, self.dc, self.dv)
+        rho = torch.empty(E, **f64)
+        level, vol = h.mgar_smooth_boundary(self.dc, p.volfrac, self.radius if r_proj is None else r_proj, rho,
+                                            nsub=nsub)
+        h.mgcg_solve(rho, self.q, self.T, p.tol, self.T_prev)
+        f1 = h.sens_filter(rho, self.T_prev, self.q, self.dc, self.dv)
+        del st
+        return rho, level, vol, f0, f1
 
     def run(self, ncycles=None):
         n = self.prob.maxit if ncycles is None else ncycles

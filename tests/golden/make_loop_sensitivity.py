@@ -1,0 +1,58 @@
+"""Writes loop_sensitivity.json: how much the oracle's own optimisation loop
+moves when its initial design is perturbed at the level of round-off. For
+each workload the oracle loop runs twice, from x_init and from x_init * (1 +
+1e-13 g) with g a seeded standard-normal vector; stored are the max-abs
+differences of the filtered designs after every cycle and of the final
+designs. Two correct FP64 implementations that sum in different orders differ
+by round-off in every solve, so this is the scale against which the GPU loop's
+design differences are judged. Calls the oracle only.
+
+Usage: python tests/golden/make_loop_sensitivity.py   (from the repository root; ~6 min)
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import topopt  # noqa: E402
+
+EPS = 1e-13
+
+
+def sensitivity(prob):
+    runs = []
+    for pert in (False, True):
+        x0 = np.full(prob.nelem, prob.x_init)
+        if pert:
+            x0 = x0 * (1.0 + EPS * W.random_vector(prob.nelem, 5))
+        xph = []
+        x, _, _, recs = topopt.run_loop(prob, x_init=x0, on_cycle=lambda k, xp, t: xph.append(np.array(xp)))
+        runs.append((x, xph, recs))
+    (xa, pa, ra), (xb, pb, rb) = runs
+    return {
+        "cycles": prob.maxit,
+        "xphys_maxabs": [float(np.abs(a - b).max()) for a, b in zip(pa, pb)],
+        "x_final_maxabs": float(np.abs(xa - xb).max()),
+        "same_paths": all(a.path == b.path for a, b in zip(ra, rb)),
+        "same_cg_iters": all(a.cg_iters == b.cg_iters for a, b in zip(ra, rb)),
+    }
+
+
+def main():
+    out = {"perturbation": EPS}
+    for key in ("c0", "c1", "c2"):
+        out[key] = sensitivity(W.CONFIGS[key])
+        print(key, out[key]["x_final_maxabs"], flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "loop_sensitivity.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"wrote {path}")
+
+
+if __name__ == "__main__":
+    main()

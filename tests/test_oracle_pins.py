@@ -116,6 +116,51 @@ def test_patch_linear_field(dim):
     assert np.abs(K @ np.ones(g.nnodes)).max() < 1e-13
 
 
+# apply_rows: the row-by-row element sum used to check grids too large to assemble
+
+@pytest.mark.parametrize("dim,shape", [(2, (7, 5, 0)), (3, (5, 4, 6)), (3, (3, 3, 3))])
+def test_apply_rows_equals_assembled_rows(dim, shape):
+    """fe.apply_rows on every node (corners, edges, faces, interior) equals the
+    rows of the assembled matrix, with per-element conductivities that differ
+    everywhere, so a wrong corner index or boundary mask shows in some row."""
+    g = fe.Grid(dim, *shape)
+    k = W.random_density(g.nelem, 91, 1e-3, 1.0)
+    x = W.random_vector(g.nnodes, 92)
+    want = fe.assemble(g, k) @ x
+    rows = np.arange(g.nnodes)
+    got = fe.apply_rows(g, k, x, rows)
+    assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+    # an arbitrary subset in arbitrary order, with repeats
+    rng = np.random.default_rng(93)
+    sub = rng.integers(0, g.nnodes, 50)
+    assert np.array_equal(fe.apply_rows(g, k, x, sub), got[sub])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_apply_rows_matches_hamming_table_by_hand(dim):
+    """Independent of the oracle's element matrix: each row summed by hand from
+    the closed-form Hamming-distance table of the Q1 element (2D 2/3, -1/6,
+    -1/3; 3D 1/3, 0, -1/12, -1/12), over the elements that contain the node."""
+    table = {2: {0: 2 / 3, 1: -1 / 6, 2: -1 / 3}, 3: {0: 1 / 3, 1: 0.0, 2: -1 / 12, 3: -1 / 12}}[dim]
+    g = fe.Grid(dim, 4, 3, 2 if dim == 3 else 0)
+    k = W.random_density(g.nelem, 94, 1e-3, 1.0)
+    x = W.random_vector(g.nnodes, 95)
+    n = [g.nx, g.ny] + ([g.nz] if dim == 3 else [])
+    rows = np.arange(g.nnodes)
+    got = fe.apply_rows(g, k, x, rows)
+    for nid in rows:
+        ijk = [int(nid % g.nnx), int((nid // g.nnx) % g.nny), int(nid // (g.nnx * g.nny))][:dim]
+        y = 0.0
+        for e in itertools.product(*[range(max(0, c - 1), min(c, m - 1) + 1) for c, m in zip(ijk, n)]):
+            eid = e[0] + g.nx * (e[1] + (g.ny * e[2] if dim == 3 else 0))
+            ci = sum((ijk[a] - e[a]) << a for a in range(dim))
+            for c in range(2 ** dim):
+                nb = [e[a] + ((c >> a) & 1) for a in range(dim)]
+                j = nb[0] + g.nnx * (nb[1] + (g.nny * nb[2] if dim == 3 else 0))
+                y += k[eid] * table[hamming(ci, c)] * x[j]
+        assert abs(got[nid] - y) < 1e-13 * max(1.0, abs(y)), (nid, got[nid], y)
+
+
 # ---------------------------------------------------------------- P3: 1D analytic solution
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -404,3 +449,181 @@ def test_loop_c0_compliance_decreases_and_paths():
     assert all(r.path in (1, 2) for r in recs[5:])
     assert recs[-1].compliance < recs[0].compliance
     assert abs(xp.mean() - 0.4) < 1e-6
+
+
+# ---------------------------------------------------------------- continuous filtering (Eq 22-23)
+
+def test_continuous_radii_closed_form():
+    """The recurrence of Eq 22-23 reaches r_min exactly after lp steps, follows
+    r0 (r_min / r0)^(k / lp) on the way (geometric), never goes below r_min and
+    stays there; r0 = 1.4 L / 50 is 13.44 for the paper's 480-element side."""
+    r0 = 1.4 * 480 / 50
+    assert abs(r0 - 13.44) < 1e-12
+    lp = 250
+    radii = topopt.continuous_radii(3.0, r0, lp, 300)
+    assert radii[0] == r0
+    for k in range(lp + 1):
+        assert abs(radii[k] - r0 * (3.0 / r0) ** (k / lp)) <= 1e-12 * r0
+    assert abs(radii[lp] - 3.0) < 1e-12
+    assert all(r >= 3.0 for r in radii)
+    assert all(a >= b for a, b in zip(radii, radii[1:]))
+    assert all(r == 3.0 for r in radii[lp + 1:])
+
+
+def test_loop_radii_schedule_and_fixed():
+    prob = W.paper_2d(480, 6)
+    radii = topopt.loop_radii(prob, prob.maxit, {"r_min": 3.0})
+    assert len(radii) == 300 and abs(radii[0] - 13.44) < 1e-12
+    assert abs(radii[250] - 3.0) < 1e-12       # lp = 5/6 of 300 steps after cycle 1
+    assert radii[251:] == [3.0] * 49
+    assert topopt.loop_radii(W.C0, 7, None) == [W.C0.filter_r] * 7
+
+
+@pytest.mark.parametrize("dim,r", [(2, 4.7), (2, 6.2), (3, 3.3)])
+def test_filter_large_radius_brute_force(dim, r):
+    """The sparse filter at the larger radii of the continuous schedule against
+    the O(E^2) statement of Eq 6-8, constant fields preserved."""
+    g = fe.Grid(dim, 13, 11, 7 if dim == 3 else 0)
+    x = W.random_density(g.nelem, 71)
+    filt = topopt.Filter(g, r)
+    assert np.abs(filt.forward(x) - topopt.filter_brute(g, r, x)).max() < 1e-13
+    assert np.abs(filt.forward(np.full(g.nelem, 0.37)) - 0.37).max() < 1e-14
+
+
+def test_continuous_loop_uses_schedule():
+    prob = W.tiny_2d(80, 80, 3, maxit=30)
+    _, _, _, recs = topopt.run_loop(prob, maxit=6, continuous={"r_min": 1.2, "lp": 3})
+    want = topopt.continuous_radii(1.2, 1.4 / 50 * 80, 3, 6)
+    assert np.allclose([r.radius for r in recs], want, rtol=1e-15, atol=0)
+    assert abs(recs[0].radius - 2.24) < 1e-12 and recs[3].radius == 1.2
+    small = W.tiny_2d(16, 16, 2, maxit=30)
+    assert topopt.loop_radii(small, 4, {"r_min": 1.5}) == [1.5] * 4
+
+
+# ---------------------------------------------------------------- non-uniform source (Sec. 4.2)
+
+def test_quadrant_source_layout_and_total():
+    p = W.tiny_2d(8, 6, 2)
+    qe = W.quadrant_source(p).reshape(6, 8)
+    v = W.QUADRANT_SOURCES
+    assert np.all(qe[:3, :4] == v[0]) and np.all(qe[:3, 4:] == v[1])
+    assert np.all(qe[3:, :4] == v[2]) and np.all(qe[3:, 4:] == v[3])
+    assert abs(qe.sum() - 12 * sum(v)) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vector_partition_of_unity_and_linearity(dim):
+    """With no Dirichlet node the nodal loads add up to the total heat
+    sum_e Q_e |e| (the shape functions sum to one), and q is linear in Q."""
+    g = fe.Grid(dim, 6, 4, 3 if dim == 3 else 0, h=2.0)
+    none = np.zeros(g.nnodes, dtype=bool)
+    qa = W.random_density(g.nelem, 81)
+    qb = W.random_density(g.nelem, 82)
+    vol = g.h ** dim
+    la = fe.load_vector(g, qa, none)
+    assert abs(la.sum() - qa.sum() * vol) < 1e-13 * qa.sum() * vol
+    lab = fe.load_vector(g, 2.0 * qa + qb, none)
+    assert np.abs(lab - (2.0 * la + fe.load_vector(g, qb, none))).max() < 1e-15 * np.abs(lab).max() * 10
+    # a source confined to one element loads its corners only, |e| / 2^d each
+    one = np.zeros(g.nelem)
+    one[5] = 1.0
+    l1 = fe.load_vector(g, one, none)
+    corners = g.connectivity()[5]
+    assert np.allclose(l1[corners], vol / 2 ** dim, rtol=0, atol=1e-15)
+    assert np.count_nonzero(l1) == 2 ** dim
+
+
+# ---------------------------------------------------------------- boundary smoothing (Eq 24-27)
+
+from oracle import smoothing  # noqa: E402
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_smoothing_projection_constant_and_weights(dim):
+    g = fe.Grid(dim, 5, 4, 3 if dim == 3 else 0)
+    assert np.allclose(smoothing.project_to_nodes(g, np.full(g.nelem, 0.7), 1.5), 0.7, rtol=0, atol=1e-15)
+    # r just above the half-diagonal: a node sees exactly its adjacent elements, equally weighted
+    s = W.random_density(g.nelem, 3)
+    ns = smoothing.project_to_nodes(g, s, np.sqrt(dim) / 2 + 0.01)
+    for nid in (0, g.nnodes - 1, g.node_id(2, 2, 1 if dim == 3 else 0)):
+        ijk = [int(nid % g.nnx), int((nid // g.nnx) % g.nny), int(nid // (g.nnx * g.nny))][:dim]
+        n = [g.nx, g.ny] + ([g.nz] if dim == 3 else [])
+        adj = [e for e in itertools.product(*[range(max(0, c - 1), min(c, m - 1) + 1) for c, m in zip(ijk, n)])]
+        want = np.mean([s[e[0] + g.nx * (e[1] + (g.ny * e[2] if dim == 3 else 0))] for e in adj])
+        assert abs(ns[nid] - want) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_q1_lattice_weights(dim):
+    """Eq 26: partition of unity, 1 at its own corner and 0 at the others, and
+    exact interpolation of a linear field over the element."""
+    pts = smoothing.lattice(dim, 4)
+    assert pts.shape == (5 ** dim, dim)
+    N = smoothing.q1_weights(dim, pts)
+    assert np.allclose(N.sum(axis=1), 1.0, atol=1e-15)
+    for c in range(2 ** dim):
+        corner = np.array([1.0 if (c >> a) & 1 else -1.0 for a in range(dim)])
+        row = np.flatnonzero((pts == corner).all(axis=1))
+        assert row.size == 1 and np.allclose(N[row[0]], np.eye(2 ** dim)[c])
+    coef = np.array([0.3, -1.2, 0.7][:dim])
+    corner_vals = np.array([0.5 + sum(coef[a] * (1.0 if (c >> a) & 1 else -1.0) for a in range(dim))
+                            for c in range(2 ** dim)])
+    assert np.allclose(N @ corner_vals, 0.5 + pts @ coef, atol=1e-14)
+
+
+def test_smoothed_density_cases_by_hand():
+    g = fe.Grid(2, 1, 1)
+    # nodes 0..3 at (0,0), (1,0), (0,1), (1,1)
+    assert smoothing.smoothed_density(g, np.array([2.0, 3.0, 4.0, 5.0]), 1.0)[0] == 1.0
+    assert smoothing.smoothed_density(g, np.array([2.0, 3.0, 4.0, 5.0]), 6.0)[0] == 0.0
+    # linear in x through the level at the element centre: lattice columns x = 0.5, 1 exceed it
+    ns = np.array([-1.0, 1.0, -1.0, 1.0])
+    assert smoothing.smoothed_density(g, ns, 0.0)[0] == pytest.approx(10 / 25, abs=0)
+    assert smoothing.smoothed_density(g, ns, 0.0, nsub=2)[0] == pytest.approx(3 / 9, abs=0)
+    # a node exactly at the level keeps the element mixed (Eq 24 needs strict inequalities)
+    ns = np.array([1.0, 2.0, 2.0, 2.0])
+    assert smoothing.smoothed_density(g, ns, 1.0)[0] == pytest.approx(24 / 25, abs=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_smoothed_density_brute_force(dim):
+    """Eq 24-27 with pure-Python loops over elements and lattice points."""
+    g = fe.Grid(dim, 4, 3, 2 if dim == 3 else 0)
+    ns = W.random_vector(g.nnodes, 61)
+    level = 0.1
+    got = smoothing.smoothed_density(g, ns, level, nsub=3)
+    conn = g.connectivity()
+    t = [-1.0, -1 / 3, 1 / 3, 1.0]
+    for e in range(g.nelem):
+        v = ns[conn[e]]
+        if all(v > level):
+            want = 1.0
+        elif all(v < level):
+            want = 0.0
+        else:
+            cnt = tot = 0
+            for o in itertools.product(t, repeat=dim):
+                val = 0.0
+                for c in range(2 ** dim):
+                    w = 1.0
+                    for a in range(dim):
+                        w *= (1.0 + o[a] * (1.0 if (c >> a) & 1 else -1.0)) / 2.0
+                    val += w * v[c]
+                cnt += val > level
+                tot += 1
+            want = cnt / tot
+        assert got[e] == pytest.approx(want, abs=1e-15), e
+
+
+def test_smoothing_level_keeps_volume():
+    g = fe.Grid(2, 24, 20)
+    s = -W.random_density(g.nelem, 62) - np.linspace(0, 1, g.nelem)
+    rho, ns, level, vol = smoothing.smooth_boundary(g, s, 0.4, 1.5)
+    target = 0.4 * g.nelem
+    assert vol >= target and vol - target < 1.0           # within one element of the target
+    # monotone in the level, and the level is where the volume crosses the target
+    levels = np.linspace(ns.min() - 0.1, ns.max() + 0.1, 40)
+    vols = [smoothing.smoothed_density(g, ns, L).sum() for L in levels]
+    assert all(a >= b for a, b in zip(vols, vols[1:]))
+    assert smoothing.smoothed_density(g, ns, level + 1e-9 * (ns.max() - ns.min())).sum() <= vol
+    assert np.all((rho >= 0) & (rho <= 1))

@@ -140,6 +140,38 @@ def element_source(p: Problem) -> np.ndarray:
     return np.full(p.nelem, p.source, dtype=np.float64)
 
 
+# Non-uniform source of the paper's Sec. 4.2 / Table 3 model: four sub-domains
+# of the same shape with sources per unit volume Omega_1..Omega_4.
+QUADRANT_SOURCES = (5e-5, 1e-4, 1.5e-4, 3e-4)
+
+
+def quadrant_source(p: Problem, values=QUADRANT_SOURCES) -> np.ndarray:
+    """Per-element source per unit volume on four equal quadrants cut at the
+    mid-lines of x and y (through every z in 3D): Omega_1 = lower-left (x <
+    nelx/2, y < nely/2), Omega_2 = lower-right, Omega_3 = upper-left, Omega_4
+    = upper-right, by element centroid. The paper places the sub-domains in a
+    figure that the text does not reproduce, so this placement is a reading."""
+    nz = p.nelz if p.dim == 3 else 1
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(p.nely), np.arange(p.nelx), indexing="ij")
+    right = (2 * ex + 1) > p.nelx
+    upper = (2 * ey + 1) > p.nely
+    v = np.asarray(values, dtype=np.float64)
+    return v[right.astype(int) + 2 * upper.astype(int)].ravel()
+
+
+def paper_2d(n: int, levels: int, volfrac: float = 0.5, maxit: int = 300, **kw) -> Problem:
+    """The paper's 2D model (Sec. 3.2, 4.1): an n x n domain, sink on the middle
+    tenth of the left side, source 1e-4 per unit volume, MGCG accuracy
+    eps2 = 1e-6, 300 design cycles, minimum filter radius 3 (continuous
+    filtering, Eq 22-23, is applied by the loop)."""
+    lo, hi = sink_box_2d(n, n)
+    kw.setdefault("source", 1e-4)
+    kw.setdefault("tol", 1e-6)
+    kw.setdefault("filter_r", 3.0)
+    return Problem(name=f"paper-2d-{n}x{n}-vf{volfrac}", dim=2, nelx=n, nely=n, nelz=0, levels=levels,
+                   fix_lo=lo, fix_hi=hi, volfrac=volfrac, x_init=volfrac, maxit=maxit, **kw)
+
+
 def initial_density(p: Problem) -> np.ndarray:
     return np.full(p.nelem, p.x_init, dtype=np.float64)
 

@@ -81,14 +81,37 @@ COUNTERS = os.path.join(ROOT, "profiles", "stencil_apply_dot_128cube.md")
 STENCIL_SRC = os.path.join(ROOT, "paper_2210_00947_amd", "csrc", "stencil.hip")
 
 
+ZBUF_SRC = os.path.join(ROOT, "paper_2210_00947_amd", "csrc", "zbuf.h")
+
+
+def _definition(text, head):
+    """Source text of the definition that starts with `head`, up to the first
+    closing brace at the start of a line."""
+    i = text.index(head)
+    return text[i:text.index("\n}\n", i) + 3]
+
+
+def roof_kernel_source_sha():
+    """SHA-256 over the source the roofline kernel is compiled from: the
+    definition of k_stencil_z2, the node formula apply27g and the buffer-load
+    helpers (zbuf.h). Edits elsewhere in the stencil file leave it unchanged."""
+    import hashlib
+    text = open(STENCIL_SRC).read()
+    parts = [_definition(text, "template <int MODE, int ZD, typename T, typename CL>\n__global__ __launch_bounds__(ZT) "
+                               "void k_stencil_z2("),
+             _definition(text, "template <typename T, bool NEEDX, typename FA, typename FB, typename FC, typename GA, "
+                               "typename GB>\n__device__ inline T apply27g("),
+             open(ZBUF_SRC).read()]
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
+
+
 def committed_traffic(shape):
     """HBM traffic per launch of the roofline kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter runs, or None when the stencil source has
-    changed since they were taken, when they were taken on another launch
-    shape, or when they are missing."""
-    import hashlib
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel's source
+    (roof_kernel_source_sha) has changed since they were taken, when they were
+    taken on another launch shape, or when they are missing."""
     try:
-        src = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()
+        src = roof_kernel_source_sha()
         for line in open(COUNTERS):
             line = line.strip()
             if not line.startswith("counters:"):

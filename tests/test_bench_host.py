@@ -38,11 +38,19 @@ def test_committed_traffic_refused_for_another_shape(bench):
 
 
 def test_committed_traffic_refused_for_another_source(bench, tmp_path, monkeypatch):
-    src = tmp_path / "stencil.hip"
-    src.write_text(open(bench.STENCIL_SRC).read() + "\n// changed\n")
-    monkeypatch.setattr(bench, "STENCIL_SRC", str(src))
+    """An edit inside the roofline kernel voids the counters; one elsewhere in
+    the stencil file does not."""
+    text = open(bench.STENCIL_SRC).read()
     kv = _counter_fields(bench.COUNTERS)
-    assert bench.committed_traffic([int(v) for v in kv["shape"].split(",")]) is None
+    shape = [int(v) for v in kv["shape"].split(",")]
+    head = "void k_stencil_z2("
+    i = text.index(head) + len(head)
+    src = tmp_path / "stencil.hip"
+    src.write_text(text[:i] + "/* changed */" + text[i:])
+    monkeypatch.setattr(bench, "STENCIL_SRC", str(src))
+    assert bench.committed_traffic(shape) is None
+    src.write_text(text + "\n// changed elsewhere\n")
+    assert bench.committed_traffic(shape) is not None
 
 
 def test_more_than_one_gpu_is_refused(bench, monkeypatch):

@@ -238,6 +238,22 @@ int mgar_tune_set(mgar_handle* h, int cls, int level, int mode, const int* shape
  * residual is below that of the previous temperature). */
 int mgar_residual(mgar_handle* h, const double* xphys, const double* q, const double* T, double* relres);
 
+/* For callers that cannot allocate device memory (work under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the criterion of
+ * mgar_residual without a handle. *relres (DEVICE, one double) receives
+ * ||q - K(xphys) T|| / ||q|| over the free nodes of the grid that p
+ * describes (dim, nelx, nely, nelz, fix_lo/fix_hi, k0, kmin, penal; the
+ * other fields are ignored), T and q read as 0 on Dirichlet nodes; 0 when q
+ * is 0 there. Enqueued on `stream` (hipStream_t, NULL = default) without a
+ * host synchronisation; it calls no allocating routine. Its block partial
+ * sums live in a static device array of 4096 x 2 doubles (64 KiB, held on
+ * every GPU the library runs on until the process ends): calls of one
+ * process that overlap on the same GPU race on it. Grids of more than
+ * 2^31 - 1 nodes are rejected with MGAR_E_ARG; equal to mgar_residual up to
+ * the summation order. */
+int mgar_residual_noalloc(const mgar_params* p, const double* xphys, const double* q, const double* T,
+                          double* relres, void* stream);
+
 /* ---- Learned initial guess (3D). -------------------------------------------
  * A small convolutional U-Net on the coarse cell grid of blocks of pool^3
  * finest elements (pool even; every axis a multiple of 2*pool): input = mean

@@ -37,7 +37,7 @@ EXPORTS = [
     "mgar_net_set_params", "mgar_net_get_params", "mgar_net_infer", "mgar_net_output", "mgar_net_grad",
     "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
     "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
-    "mgar_profile", "mgar_profile_read", "mgar_set_filter_radius",
+    "mgar_profile", "mgar_profile_read", "mgar_residual_noalloc", "mgar_set_filter_radius",
     "mgar_smooth_boundary",
 ]
 
@@ -114,12 +114,27 @@ def lib():
         L.mgar_profile_read.argtypes = [P, ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.mgar_set_filter_radius.argtypes = [P, D]
         L.mgar_smooth_boundary.argtypes = [P, VP, D, D, I, VP, VP, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.mgar_residual_noalloc.argtypes = [ctypes.POINTER(mgar_params), VP, VP, VP, VP, VP]
         for f in EXPORTS:
             if f not in ("mgar_default_params", "mgar_destroy", "mgar_strerror", "mgar_batch_destroy",
                          "mgar_net_destroy"):
                 getattr(L, f).restype = I
         _lib = L
     return _lib
+
+
+def mgar_residual_noalloc(params: mgar_params, xphys, q, T, relres, stream=None):
+    """||q - K(xphys) T|| / ||q|| into relres (a one-entry FP64 GPU tensor), enqueued on
+    `stream` (default: torch's current stream) without a host synchronisation and
+    without any device allocation (the library's static partial-sum array)."""
+    import torch
+    ne = params.nelx * params.nely * (params.nelz if params.dim == 3 else 1)
+    nn = (params.nelx + 1) * (params.nely + 1) * ((params.nelz + 1) if params.dim == 3 else 1)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib().mgar_residual_noalloc(ctypes.byref(params), _ptr(xphys, ne, "xphys"), _ptr(q, nn, "q"),
+                                       _ptr(T, nn, "T"), _ptr(relres, 1, "relres"), ctypes.c_void_p(stream)),
+           "mgar_residual_noalloc")
 
 
 def strerror(code: int) -> str:

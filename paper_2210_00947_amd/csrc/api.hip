@@ -760,13 +760,20 @@ int solve_mixed(mgar_handle* h, double tol, int* iters, int* conv, double* relre
 
 // PCG with one V-cycle as preconditioner on K(kfine); x (h->cx) holds the
 // initial guess on entry and the solution on exit; h->qm the masked load.
-int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, double* relres) {
+// nr0 > 0: h->cr already holds r = q - K x with nr0 block partials of ||r||^2
+// in h->pa, and ||q||^2 is in md->qq (the reanalysis has formed both).
+int pcg(mgar_handle* h, const double* kfine, double tol, int* iters, int* conv, double* relres, int nr0 = 0) {
   const long long N = h->N;
   const int cg_max = h->p.cg_max;
-  ACK(stencil_at(h, 0, SM_RESID, h->cx, kfine, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
-  const int nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
-  const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
-  launch_cg_init(h->st, h->pb, nq, h->pa, nr, tol, cg_max, h->s);
+  int nr = nr0;
+  if (nr0 > 0) {
+    launch_cg_init(h->st, &h->md->qq, 1, h->pa, nr0, tol, cg_max, h->s);
+  } else {
+    ACK(stencil_at(h, 0, SM_RESID, h->cx, kfine, nullptr, h->qm, h->cr, 0.0, nullptr, nullptr));
+    nr = launch_dot(h->cr, h->cr, N, h->pa, nullptr, h->s);
+    const int nq = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
+    launch_cg_init(h->st, h->pb, nq, h->pa, nr, tol, cg_max, h->s);
+  }
   // the fused direction update reads p_old = cp2 at iteration 0 (weight 0):
   // keep it finite whatever an earlier solve left there
   launch_fill_t<double>(h->cp2, N, 0.f, 0.f, h->s);
@@ -1265,17 +1272,19 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
       ACK(vcycle(h, h->cz, h->p.basis_x0_zero ? nullptr : prev, h->R + (long long)i * N, nullptr, nullptr));
     }
   }
-  // Eq 18 (as Gram-Schmidt), Eq 19-21
-  ACK(orthonormalise(h));
+  // Eq 18 (as Gram-Schmidt), Eq 19-21; ||q||^2 comes with the Gram products
+  if (h->mixed) ACK(orthonormalise(h));
+  else launch_gs_fused(h->R, m, N, N, h->md, h->pa, h->s);
   for (int j = 0; j < m; ++j)
     ACK(stencil_at(h, 0, SM_APPLY, h->R + (long long)j * N, h->kcur, nullptr, nullptr,
                    h->Wm + (long long)j * N, 0.0, nullptr, nullptr));
   int np = launch_gram(h->R, h->Wm, h->qm, m, N, N, h->pa, h->s);
   launch_gram_finalize(h->pa, np, m, h->md, h->s);
-  np = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s);
-  launch_finalize(h->pa, np, &h->md->res2, nullptr, h->s);
-  np = launch_dot(h->qm, h->qm, N, h->pb, nullptr, h->s);
-  launch_finalize(h->pb, np, &h->md->qq, nullptr, h->s);
+  // t~ = Q y in cx; FP64: also r = q - W y in cr, the residual of t~ the
+  // fallback PCG starts from (its ||r||^2 partials stay in pa)
+  const int nres = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s,
+                                  h->mixed ? nullptr : h->cr);
+  launch_finalize(h->pa, nres, &h->md->res2, nullptr, h->s);
   LAUNCHCK();
   MgarDev hm;
   HIPCK(hipMemcpyAsync(&hm, h->md, sizeof(MgarDev), hipMemcpyDeviceToHost, h->s));
@@ -1304,7 +1313,7 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
       ACK(solve_mixed(h, tol, &iters, &conv, &rel, &nref));
     } else {
       ACK(build_hierarchy(h));
-      ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel));
+      ACK(pcg(h, h->kcur, tol, &iters, &conv, &rel, nres));
     }
     if (stats) stats->refinements = nref;
     launch_copy(h->cx, T, N, h->s);

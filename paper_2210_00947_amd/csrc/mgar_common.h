@@ -107,6 +107,8 @@ struct MgarDev {
   double qq;                 // ||q||^2
   int spd_fail;
   int pad;
+  double nn[MGAR_MAXB];      // squared norm of each column after projection (fused Gram-Schmidt)
+  double c2[MGAR_MAXB];      // coefficients of the second projection pass
 };
 
 // OC bisection state in device memory. The filtered volume S(lambda) is

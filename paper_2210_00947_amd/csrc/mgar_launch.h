@@ -263,8 +263,14 @@ void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const dou
 int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,
                 long long n, double* part, hipStream_t s);
 void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s);
+// t = Q y, partials of ||W y - q||^2 (y from the reduced Cholesky solve, stored
+// in md); with rq, also rq = q - W y.
 int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
-                   long long n, MgarDev* md, double* t, double* part, hipStream_t s);
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq = nullptr);
+// Two-pass Gram-Schmidt of the m columns of R in place (three passes over
+// the data per column; see k_gs_dots), leaving orthonormal columns, md->active
+// and md->n0; dropped columns are zeroed. part: vec_num_blocks(n) * (m + 1).
+void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, hipStream_t s);
 
 // api.hip helpers shared with batch.hip (grid of a level, Dirichlet count,
 // parameter validation of one design).

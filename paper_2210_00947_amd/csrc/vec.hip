@@ -309,44 +309,214 @@ __global__ __launch_bounds__(VB) void k_gs_normalize(double* __restrict__ v, lon
   if (blockIdx.x == 0 && threadIdx.x == 0) md->active[col] = keep ? 1 : 0;
 }
 
-// Gram products of the reduced system: K_R[a][b] = Q_a . W_b (a <= b) and
-// q_R[a] = Q_a . q. Values per block: M(M+1)/2 + M, upper triangle row by row.
-template <int M>
-__global__ __launch_bounds__(VB) void k_gram(const double* __restrict__ Q, const double* __restrict__ W,
-                                             const double* __restrict__ q, long long ld, long long n,
-                                             double* __restrict__ part) {
+// ---- Gram-Schmidt in three passes per column (single design, FP64). Column j
+// (j >= 1) of R: pass 1 sums R_c . R_j (c < j) and R_j . R_j (and R_0 . R_0
+// for j = 1); pass 2 subtracts the projection onto the earlier columns and
+// sums the same products of the result; pass 3 subtracts the second
+// (re-orthogonalisation) projection. Earlier columns stay unnormalised (with
+// their squared norms nn[c]) until the last column's pass 3, which also
+// normalises every column. The squared norm after the second projection is
+// ||R_j'||^2 - sum_c c2_c^2 nn_c: exact for orthogonal R_c, and accurate since
+// c2 is of round-off size. Drop rule as the single-pass form: a column whose
+// norm after projection is below 1e-10 of its norm before (or zero) is zeroed
+// and left out.
+
+// part[b * NV + v]: v < J: R_v . R_J; v = J: R_J . R_J; v = J + 1 (J = 1): R_0 . R_0
+template <int J>
+__global__ __launch_bounds__(VB) void k_gs_dots(const double* __restrict__ R, long long ld, long long n,
+                                                double* __restrict__ part) {
   __shared__ double sh[VB / MGAR_WAVE];
-  constexpr int NV = M * (M + 1) / 2 + M;
+  constexpr int NV = J + 1 + (J == 1 ? 1 : 0);
   double s[NV];
 #pragma unroll
-  for (int c = 0; c < NV; ++c) s[c] = 0.0;
+  for (int v = 0; v < NV; ++v) s[v] = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
-    double qa[M], wa[M];
+    const double rj = R[J * ld + i];
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      qa[a] = Q[a * ld + i];
-      wa[a] = W[a * ld + i];
+    for (int c = 0; c < J; ++c) s[c] += R[c * ld + i] * rj;
+    s[J] += rj * rj;
+    if (J == 1) {
+      const double r0 = R[i];
+      s[NV - 1] += r0 * r0;
     }
-    const double qi = q[i];
-    int idx = 0;
-#pragma unroll
-    for (int a = 0; a < M; ++a)
-#pragma unroll
-      for (int b = a; b < M; ++b) s[idx++] += qa[a] * wa[b];
-#pragma unroll
-    for (int a = 0; a < M; ++a) s[idx + a] += qa[a] * qi;
   }
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) part[blockIdx.x * NV + c] = t;
+  for (int v = 0; v < NV; ++v) {
+    const double t = block_sum(s[v], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * NV + v] = t;
+  }
+}
+
+// Pass 1 results: n0[J]; for J = 1 also column 0's norms; c[c] = R_c . R_J / nn[c].
+__global__ __launch_bounds__(FB) void k_gs_fin1(const double* __restrict__ part, int np, int J, MgarDev* md) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  const int nv = J + 1 + (J == 1 ? 1 : 0);
+  double v[MGAR_MAXB + 2];
+  for (int q = 0; q < nv; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < np; b += FB) s += part[b * nv + q];
+    v[q] = block_sum(s, sh);
+  }
+  if (threadIdx.x != 0) return;
+  if (J == 0 || J == 1) {
+    const double n00 = (J == 0) ? v[0] : v[nv - 1];
+    md->n0[0] = n00;
+    md->nn[0] = n00;
+    md->active[0] = n00 > 0.0 ? 1 : 0;
+  }
+  if (J == 0) return;
+  md->n0[J] = v[J];
+  for (int c = 0; c < J; ++c) md->c[c] = md->active[c] ? v[c] / md->nn[c] : 0.0;
+}
+
+// Pass 2: R_J -= sum_c c[c] R_c; partials of R_c . R_J (c < J) and R_J . R_J.
+template <int J>
+__global__ __launch_bounds__(VB) void k_gs_proj(double* __restrict__ R, long long ld, long long n,
+                                                const MgarDev* __restrict__ md, double* __restrict__ part) {
+  __shared__ double sh[VB / MGAR_WAVE];
+  double c[J], s[J + 1];
+#pragma unroll
+  for (int q = 0; q < J; ++q) c[q] = md->c[q];
+#pragma unroll
+  for (int q = 0; q <= J; ++q) s[q] = 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double rc[J];
+    double v = R[J * ld + i];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+      rc[q] = R[q * ld + i];
+      v -= c[q] * rc[q];
+    }
+    R[J * ld + i] = v;
+#pragma unroll
+    for (int q = 0; q < J; ++q) s[q] += rc[q] * v;
+    s[J] += v * v;
+  }
+#pragma unroll
+  for (int q = 0; q <= J; ++q) {
+    const double t = block_sum(s[q], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * (J + 1) + q] = t;
+  }
+}
+
+// Pass 2 results: c2[c] = R_c . R_J' / nn[c]; nn[J] and the drop decision.
+__global__ __launch_bounds__(FB) void k_gs_fin2(const double* __restrict__ part, int np, int J, MgarDev* md) {
+  __shared__ double sh[FB / MGAR_WAVE];
+  double v[MGAR_MAXB + 1];
+  for (int q = 0; q <= J; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < np; b += FB) s += part[b * (J + 1) + q];
+    v[q] = block_sum(s, sh);
+  }
+  if (threadIdx.x != 0) return;
+  double nn = v[J];
+  for (int c = 0; c < J; ++c) {
+    const double c2 = md->active[c] ? v[c] / md->nn[c] : 0.0;
+    md->c2[c] = c2;
+    nn -= c2 * c2 * md->nn[c];
+  }
+  nn = nn > 0.0 ? nn : 0.0;
+  const double n0 = md->n0[J];
+  const bool keep = n0 > 0.0 && nn >= 1e-20 * n0;
+  md->nn[J] = keep ? nn : 0.0;
+  md->active[J] = keep ? 1 : 0;
+}
+
+// Pass 3: R_J -= sum_c c2[c] R_c (J >= 1); with LAST, every column c <= J is
+// then scaled by 1 / sqrt(nn[c]) (0 for dropped columns).
+template <int J, bool LAST>
+__global__ __launch_bounds__(VB) void k_gs_fix(double* __restrict__ R, long long ld, long long n,
+                                               const MgarDev* __restrict__ md) {
+  double c2[J > 0 ? J : 1], sc[J + 1];
+#pragma unroll
+  for (int q = 0; q < J; ++q) c2[q] = md->c2[q];
+#pragma unroll
+  for (int q = 0; q <= J; ++q) sc[q] = (md->active[q] && md->nn[q] > 0.0) ? 1.0 / sqrt(md->nn[q]) : 0.0;
+  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
+    double rc[J > 0 ? J : 1];
+    double v = R[J * ld + i];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+      rc[q] = R[q * ld + i];
+      v -= c2[q] * rc[q];
+    }
+    if (LAST) {
+#pragma unroll
+      for (int q = 0; q < J; ++q) R[q * ld + i] = rc[q] * sc[q];
+      R[J * ld + i] = v * sc[J];
+    } else {
+      R[J * ld + i] = v;
+    }
+  }
+}
+
+// Gram products of the reduced system (Eq 19-20), K_R[a][b] = Q_a . W_b
+// (a <= b), q_R[a] = Q_a . q, and ||q||^2, on the matrix cores: with
+// A = [Q_0 .. Q_{M-1}, q] and
+// B = [W_0 .. W_{M-1}, q] (N x (M+1) each, zero-padded to 16 columns),
+// G = A^T B is a product whose inner dimension is the node index, accumulated
+// by v_mfma_f64_16x16x4f64 four nodes per instruction: lane l supplies
+// A[node][l % 16] and B[node][l % 16] for the nodes 4 (l / 16) + t of a
+// 16-node chunk, t = 0..3 (one instruction per t), and holds G rows
+// 4 r + l / 16, r = 0..3, of column l % 16 (lane layout checked on gfx950). K_R = G[a][b], q_R[a] = G[a][M],
+// ||q||^2 = G[M][M]; per block the waves' G are summed in wave order and
+// written as M(M+1)/2 + M + 1 values: the upper triangle of K_R row by row,
+// then q_R, then ||q||^2 (read by k_gram_finalize).
+typedef double mgar_d4 __attribute__((ext_vector_type(4)));
+template <int M>
+__global__ __launch_bounds__(VB) void k_gram_mfma(const double* __restrict__ Q, const double* __restrict__ W,
+                                                  const double* __restrict__ q, long long ld, long long n,
+                                                  double* __restrict__ part) {
+  constexpr int NW = VB / MGAR_WAVE;
+  constexpr int NV = M * (M + 1) / 2 + M + 1;
+  __shared__ double G[NW][16][16];
+  const int lane = threadIdx.x & (MGAR_WAVE - 1), wid = threadIdx.x / MGAR_WAVE;
+  const int col = lane & 15, quarter = lane >> 4;
+  const double* pa = col < M ? Q + col * ld : (col == M ? q : nullptr);
+  const double* pb = col < M ? W + col * ld : (col == M ? q : nullptr);
+  mgar_d4 d = {0.0, 0.0, 0.0, 0.0};
+  const long long nchunk = (n + 15) / 16;
+  const long long waves = (long long)gridDim.x * NW;
+  for (long long c = (long long)blockIdx.x * NW + wid; c < nchunk; c += waves) {
+    const long long base = c * 16 + 4 * quarter;
+    double av[4], bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool in = pa != nullptr && base + t < n;
+      av[t] = in ? pa[base + t] : 0.0;
+      bv[t] = in ? pb[base + t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], d, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) G[wid][4 * r + quarter][col] = d[r];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
+    int a = 0, b = 0;
+    if (v < M * (M + 1) / 2) {          // upper triangle, row by row
+      int rem = v;
+      while (rem >= M - a) { rem -= M - a; ++a; }
+      b = a + rem;
+    } else if (v < NV - 1) {            // q_R
+      a = v - M * (M + 1) / 2;
+      b = M;
+    } else {                            // ||q||^2
+      a = M;
+      b = M;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += G[w][a][b];
+    part[blockIdx.x * NV + v] = s;
   }
 }
 
 __global__ __launch_bounds__(FB) void k_gram_finalize(const double* __restrict__ part, int np, int m,
                                                       MgarDev* md) {
   __shared__ double sh[FB / MGAR_WAVE];
-  const int nv = m * (m + 1) / 2 + m;
+  const int nv = m * (m + 1) / 2 + m + 1;
   int idx = 0;
   for (int a = 0; a < m; ++a)
     for (int b = a; b < m; ++b, ++idx) {
@@ -364,6 +534,10 @@ __global__ __launch_bounds__(FB) void k_gram_finalize(const double* __restrict__
     s = block_sum(s, sh);
     if (threadIdx.x == 0) md->qR[a] = s;
   }
+  double s = 0.0;
+  for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + nv - 1];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) md->qq = s;
 }
 
 // Solve K_R y = q_R over the active columns by Cholesky (m <= 8, one thread).
@@ -411,7 +585,7 @@ __global__ __launch_bounds__(VB) void k_combine(const double* __restrict__ Q,
                                                 const double* __restrict__ W,
                                                 const double* __restrict__ q, long long ld,
                                                 long long n, MgarDev* md, double* __restrict__ t,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, double* __restrict__ rq) {
   __shared__ double sh[VB / MGAR_WAVE];
   __shared__ double ys[MGAR_MAXB];
   if (threadIdx.x == 0) {
@@ -438,6 +612,7 @@ __global__ __launch_bounds__(VB) void k_combine(const double* __restrict__ Q,
     }
     t[i] = ti;
     const double ri = wi - q[i];
+    if (rq) rq[i] = -ri;
     s += ri * ri;
   }
   s = block_sum(s, sh);
@@ -926,10 +1101,34 @@ void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const dou
 int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,
                 long long n, double* part, hipStream_t s) {
   const int nb = vec_num_blocks(n);
-#define CALL_G(M) k_gram<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, part)
+#define CALL_G(M) k_gram_mfma<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, part)
   MGAR_DISPATCH_M(m, CALL_G)
 #undef CALL_G
   return nb;
+}
+
+void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, hipStream_t s) {
+  const int nb = vec_num_blocks(n);
+  if (m == 1) {
+    k_gs_dots<0><<<nb, VB, 0, s>>>(R, ld, n, part);
+    k_gs_fin1<<<1, FB, 0, s>>>(part, nb, 0, md);
+    k_gs_fix<0, true><<<nb, VB, 0, s>>>(R, ld, n, md);
+    return;
+  }
+  for (int j = 1; j < m; ++j) {
+    const bool last = j == m - 1;
+#define GS_J(J)                                                                  \
+  case J:                                                                        \
+    k_gs_dots<J><<<nb, VB, 0, s>>>(R, ld, n, part);                              \
+    k_gs_fin1<<<1, FB, 0, s>>>(part, nb, J, md);                                 \
+    k_gs_proj<J><<<nb, VB, 0, s>>>(R, ld, n, md, part);                          \
+    k_gs_fin2<<<1, FB, 0, s>>>(part, nb, J, md);                                 \
+    if (last) k_gs_fix<J, true><<<nb, VB, 0, s>>>(R, ld, n, md);                 \
+    else k_gs_fix<J, false><<<nb, VB, 0, s>>>(R, ld, n, md);                     \
+    break;
+    switch (j) { GS_J(1) GS_J(2) GS_J(3) GS_J(4) GS_J(5) GS_J(6) default: GS_J(7) }
+#undef GS_J
+  }
 }
 
 void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s) {
@@ -937,9 +1136,9 @@ void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStr
 }
 
 int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
-                   long long n, MgarDev* md, double* t, double* part, hipStream_t s) {
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq) {
   const int nb = vec_num_blocks(n);
-#define CALL_C(M) k_combine<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, md, t, part)
+#define CALL_C(M) k_combine<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, md, t, part, rq)
   MGAR_DISPATCH_M(m, CALL_C)
 #undef CALL_C
   return nb;

@@ -92,47 +92,72 @@ def test_load_vector_quadrant_source():
 
 
 def _paper_loops(prob, ncycles, qelem, continuous):
-    """The MGAR loop in the paper's settings on the GPU and in the oracle."""
+    """The MGAR loop in the paper's settings on the GPU and in the oracle, with
+    the filtered design of every cycle."""
     from oracle.solvers import MgarParams
     from paper_2210_00947_amd.topopt import TopOpt
     params = MgarParams(eps_accept=0.5, cg_max=200)
-    x_or, _, _, recs = topopt.run_loop(prob, maxit=ncycles, params=params, qelem=qelem,
-                                       continuous=continuous)
+    xo = []
+    x_or, _, _, recs = topopt.run_loop(prob, maxit=ncycles, params=params, qelem=qelem, continuous=continuous,
+                                       on_cycle=lambda k, xp, t: xo.append(np.array(xp)))
     require_gpu()
     opt = TopOpt(prob, qelem, eps_accept=0.5, cg_max=200, continuous=continuous)
-    cyc = opt.run(ncycles)
+    cyc, xg_ph = [], []
+    for _ in range(ncycles):
+        cyc.append(opt.step())
+        xg_ph.append(host(opt.xphys))
     xg = host(opt.x)
     opt.h.close()
-    return cyc, xg, recs, x_or
+    return cyc, xg, recs, x_or, (xg_ph, xo)
 
 
-def _check(name, cyc, xg, recs, x_or):
+def _sens(key):
+    """The oracle loop's own response to a 1e-13 relative perturbation of its
+    initial design, per cycle (tests/golden/make_loop_sensitivity.py)."""
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "loop_sensitivity.json")))[key]
+
+
+def _check(name, cyc, xg, recs, x_or, xph, sens):
+    """Paths, CG iterations and filter radii identical in every cycle. The OC
+    updates amplify round-off differences between the two solvers over the
+    cycles (tests/test_gpu_fullsize.py), so compliance and the Eq 28 residual
+    are compared at max(1e-8, 100 x) and the filtered design at 100 x (+1e-12)
+    the oracle's own per-cycle response to a round-off-sized perturbation,
+    the final design at max(1e-6, 10 x) its final response."""
     assert len(cyc) == len(recs)
-    for a, b in zip(cyc, recs):
+    d = [float(np.abs(a - b).max()) for a, b in zip(*xph)]
+    for k, (a, b) in enumerate(zip(cyc, recs)):
         assert a.path == b.path, (name, a.cycle, a.path, b.path, a.res_ca, b.res_ca)
         assert a.cg_iters == b.cg_iters, (name, a.cycle, a.cg_iters, b.cg_iters)
-        assert abs(a.compliance - b.compliance) <= 1e-8 * b.compliance, (name, a.cycle)
         assert abs(a.radius - b.radius) <= 1e-12 * b.radius, (name, a.cycle, a.radius, b.radius)
+        ctol = max(1e-8, 100.0 * sens["compliance_rel"][k])
+        assert abs(a.compliance - b.compliance) <= ctol * b.compliance, (name, a.cycle)
         if b.path != 0:
-            # Res of Eq 28 decides the path (checked above); over hundreds of
-            # cycles the designs drift apart by round-off (OC amplifies it), so
-            # the residual values are compared at 1e-6
-            assert abs(a.res_ca - b.res_ca) <= 1e-6 * b.res_ca, (name, a.cycle, a.res_ca, b.res_ca)
+            rtol = max(1e-8, 100.0 * sens["res_ca_rel"][k])
+            assert abs(a.res_ca - b.res_ca) <= rtol * b.res_ca, (name, a.cycle, a.res_ca, b.res_ca)
+        assert d[k] <= 100.0 * sens["xphys_maxabs"][k] + 1e-12, (name, a.cycle, d[k], sens["xphys_maxabs"][k])
     xerr = float(np.abs(xg - x_or).max())
     mgcg_calls = sum(c.path != 1 for c in cyc)
     print(f"{name}: {len(cyc)} cycles, MGCG evaluations {mgcg_calls}, accepted {sum(c.path == 1 for c in cyc)}, "
-          f"radius {cyc[0].radius:.3f} -> {cyc[-1].radius:.3f}, final x max abs err {xerr:.2e}")
-    assert xerr <= 1e-6
+          f"radius {cyc[0].radius:.3f} -> {cyc[-1].radius:.3f}, final x max abs err {xerr:.2e} "
+          f"(oracle self-response {sens['x_final_maxabs']:.1e})")
+    assert xerr <= max(1e-6, 10.0 * sens["x_final_maxabs"])
 
 
 def test_paper_mode_loop_nl3():
     """96^2 at the paper's coarsening level nl = 3 (coarsest 24^2 elements),
-    paper settings, all 300 cycles (N_on = 40), uniform source 1e-4, the
-    minimum radius 3 throughout (alpha L = 2.69 < r_min on this grid)."""
+    paper settings (300-cycle schedule: N_on = 40), uniform source 1e-4, the
+    minimum radius 3 throughout (alpha L = 2.69 < r_min on this grid); the
+    first 150 cycles. Later in this loop the OC updates amplify round-off
+    until the paths themselves part: the oracle run from an initial design
+    perturbed by 1e-13 takes a different CG iteration count at cycle 217
+    (its filtered design already differs by 1.6e-2 at cycle 200)."""
     prob = W.paper_2d(96, 3)
-    cyc, xg, recs, x_or = _paper_loops(prob, 300, W.element_source(prob), {"r_min": 3.0})
+    cyc, xg, recs, x_or, xph = _paper_loops(prob, 150, W.element_source(prob), {"r_min": 3.0})
     assert sum(c.path == 1 for c in cyc) > 0        # reduced solutions are accepted
-    _check("paper mode 96^2 nl=3", cyc, xg, recs, x_or)
+    _check("paper mode 96^2 nl=3", cyc, xg, recs, x_or, xph, _sens("paper96"))
 
 
 def test_paper_mode_continuous_filter_quadrant_source():
@@ -141,9 +166,9 @@ def test_paper_mode_continuous_filter_quadrant_source():
     four-quadrant source of Sec. 4.2, volume fraction 0.4: the first 120 of
     300 cycles (pure MGCG up to 39, reanalysis from 40)."""
     prob = dataclasses.replace(W.paper_2d(160, 4, volfrac=0.4))
-    cyc, xg, recs, x_or = _paper_loops(prob, 120, W.quadrant_source(prob), {"r_min": 3.0})
+    cyc, xg, recs, x_or, xph = _paper_loops(prob, 120, W.quadrant_source(prob), {"r_min": 3.0})
     assert cyc[0].radius == pytest.approx(4.48, rel=1e-12) and cyc[-1].radius < 4.48
-    _check("paper mode 160^2 continuous filter, quadrant source", cyc, xg, recs, x_or)
+    _check("paper mode 160^2 continuous filter, quadrant source", cyc, xg, recs, x_or, xph, _sens("paper160"))
 
 
 @pytest.mark.parametrize("prob,r,nsub", [

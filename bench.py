@@ -271,11 +271,20 @@ PAPER_TABLE3 = {(480, 0.4): (7.71, 7.38, 112, 0.4050, 0.0013), (480, 0.6): (7.69
                 (960, 0.4): (7.81, 7.51, 124, 0.3593, 0.00028), (960, 0.6): (7.47, 7.24, 109, 0.4368, 0.000015)}
 
 
-def paper_levels(n, max_coarse_nodes=1024):
-    """Grids of the paper-mode runs: halve n while it stays even, until the
-    coarsest grid has at most max_coarse_nodes nodes (the dense coarsest solve)."""
+def paper_levels(n, min_coarse=4):
+    """Grids of the paper-mode runs (n x n, sink on the middle tenth of the left
+    side): the deepest hierarchy whose coarsest grid keeps at least min_coarse
+    elements per side and a Dirichlet node (a coarse node is fixed when the
+    finest node under it is). The coarsest inverse is built on one CU in
+    O(nodes^3): 38 ms at 23^2 nodes, 343 ms at 31^2 on MI355X, so a deep
+    hierarchy keeps that build out of the cycle time."""
+    import workloads as W
+    lo, hi = W.sink_box_2d(n, n)
     levels = 1
-    while (n >> (levels - 1)) % 2 == 0 and ((n >> (levels - 1)) + 1) ** 2 > max_coarse_nodes:
+    while n % (1 << levels) == 0 and n >> levels >= min_coarse:
+        s = 1 << levels
+        if (hi[1] // s) * s < lo[1]:      # no multiple of the coarse spacing inside the sink
+            break
         levels += 1
     return levels
 
@@ -285,11 +294,12 @@ def paper_tables(W, TopOpt, torch, ncycles=300):
     0.5, eps2 = 1e-6, cg_max 200, m = 2, N_on = 40 of 300 cycles, continuous
     filtering from 1.4 L / 50 down to r_min = 3 over 250 cycles, source 1e-4
     per unit volume or the four-quadrant source): an MGAR loop and a pure MGCG
-    loop per case. Sizes: Table 2's 360, 720, 1560 and 2040 elements per side
-    are not divisible by a power of two that brings the coarsest grid within
-    the dense coarsest solve (1024 nodes), so the nearest multiples of 32 are
-    run instead (352, 704, 1536, 2048; DOFs within 5 %), with the deepest
-    hierarchy that fits; Table 3's 480 and 960 are run as printed. Reported
+    loop per case, with the deepest hierarchy of each grid (paper_levels; the
+    paper uses nl = 3, whose coarsest grids of 8k-260k nodes the dense
+    coarsest solve here cannot take). Sizes: Table 2's 360, 720, 1560 and
+    2040 elements per side allow only shallow hierarchies (360 = 8 x 45), so
+    the nearest sizes with deep ones are run instead (352, 704, 1536, 2048;
+    DOFs within 5 %); Table 3's 480 and 960 are run as printed. Reported
     per case: MGCG evaluations (pure-MGCG cycles plus rejected reductions),
     accepted reductions, mean CG iterations of MGAR's and of the pure MGCG
     loop, efficiency improvement 1 - t_MGAR / t_MGCG, relative difference of

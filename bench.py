@@ -13,7 +13,10 @@ Prints one JSON line:
   ms_per_step    MGAR loop, milliseconds per optimisation cycle
   mgcg           the same figures for the plain-MGCG loop on the same GPU
   batched        48 2D + 8 3D designs of uneven sizes solved together (FP64),
-                 against the same solves one design at a time
+                 against the same solves one design at a time; batched.mixed
+                 the same in the mixed-precision form (FP32 multigrid over
+                 BF16 densities, FP32 inner PCG runs with FP64 residual
+                 replacement, same 1e-8 FP64 residual test)
   learned_mixed  the mixed-precision MGAR loop with the learned initial guess
                  (trained by the library's kernels on the pairs of cycles 2..20,
                  in the background on its own stream during cycles 21..45,
@@ -184,14 +187,17 @@ def run_loop(prob, use_mgar, warmup, steps, W, TopOpt, torch, precision=0, seed=
     return out
 
 
-def run_batched(W, M, torch, nsolves=5):
+def run_batched(W, M, torch, nsolves=5, precision=None):
     """The batched workload (48 2D + 8 3D designs of uneven sizes): `nsolves`
     batched MGCG solves from T0 = 0 on reseeded densities, then the same
     solves one design at a time through single-design handles on the same
-    GPU, and one batched reanalysis step (MGCG at x, MGAR at a perturbed x)."""
+    GPU, and one batched reanalysis step (MGCG at x, MGAR at a perturbed x).
+    precision: M.PREC_FP64 (default) or M.PREC_MIXED, for the batch and the
+    single-design handles alike."""
     import numpy as np
+    prec = M.PREC_FP64 if precision is None else precision
     probs = W.batched_designs()
-    b = M.Batch([M.params_for(p) for p in probs])
+    b = M.Batch([M.params_for(p, precision=prec) for p in probs])
     free = 0
     for p in probs:
         nfix = 1
@@ -213,10 +219,11 @@ def run_batched(W, M, torch, nsolves=5):
     b.mgcg_batch_solve(xs[0], q, None, 1e-8, T)       # warm-up (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its = []
+    its, refs = [], []
     for x in xs:
         st = b.mgcg_batch_solve(x, q, None, 1e-8, T)
         its.append(max(s["cg_iters"] for s in st))
+        refs.append(max(s["refinements"] for s in st))
     torch.cuda.synchronize()
     bt = (time.perf_counter() - t0) / nsolves
     # MGAR step at a perturbed design (exact mode: every design falls back)
@@ -231,7 +238,7 @@ def run_batched(W, M, torch, nsolves=5):
     at = time.perf_counter() - t1
     b.close()
     # the same MGCG solves, one design after another through single handles
-    hs = [M.Handle(M.params_for(p)) for p in probs]
+    hs = [M.Handle(M.params_for(p, precision=prec)) for p in probs]
     qs, ts = [], []
     for p, h in zip(probs, hs):
         qi = torch.empty(p.nnodes, dtype=torch.float64, device="cuda")
@@ -254,7 +261,8 @@ def run_batched(W, M, torch, nsolves=5):
     return {
         "designs": len(probs), "free_dofs": free,
         "batched_mgcg_s_per_solve": bt, "batched_dof_solves_per_s": free / bt,
-        "max_cg_iters": its,
+        "precision": "mixed" if prec == M.PREC_MIXED else "fp64",
+        "max_cg_iters": its, "max_refinements": refs,
         "batched_mgar_s": at, "batched_mgar_paths": {"accept": sum(s["path"] == 1 for s in sa),
                                                      "fallback": sum(s["path"] == 2 for s in sa)},
         "one_by_one_mgcg_s_per_solve": stime, "one_by_one_dof_solves_per_s": free / stime,
@@ -596,6 +604,10 @@ def main():
         batch = run_batched(W, M, torch)
         log(f"[bench] batched workload: {batch['batched_mgcg_s_per_solve']*1e3:.2f} ms per batched solve "
             f"vs {batch['one_by_one_mgcg_s_per_solve']*1e3:.2f} ms one design at a time")
+        batch["mixed"] = run_batched(W, M, torch, precision=M.PREC_MIXED)
+        log(f"[bench] batched workload, mixed precision: "
+            f"{batch['mixed']['batched_mgcg_s_per_solve']*1e3:.2f} ms per batched solve vs "
+            f"{batch['mixed']['one_by_one_mgcg_s_per_solve']*1e3:.2f} ms one design at a time")
     value = free * args.steps / mg_ar["elapsed_s"]
     roof = None
     if mg_ar["kernel_launches"] > 0:

@@ -287,14 +287,21 @@ int mgar_net_train_step(mgar_net* n, const double* xphys, const double* T, doubl
 
 /* ---- Batched solves (many independent designs at once). --------------------
  * A batch holds `ndesigns` designs of uneven grids (2D and 3D may be mixed),
- * each described by its own mgar_params (FP64 only; n_basis, omega,
- * eps_accept, cg_max and basis_x0_zero must agree across designs; levels >= 2).
+ * each described by its own mgar_params (n_basis, omega, eps_accept, cg_max,
+ * basis_x0_zero, precision, k0, kmin, penal and, for MGAR_PREC_MIXED,
+ * inner_tol must agree across designs, else MGAR_E_ARG; levels >= 2).
  * The designs' K(xphys) t = q are solved together: every stage of the V-cycle
  * and of the PCG iteration is one launch per dimension over all designs'
  * grids, with per-design PCG state on the device, so converged designs drop
  * out and one PCG iteration is captured once as a hipGraph and replayed until
- * every design stopped. Each design gets the same solution as its own
- * mgcg_solve / mgar_solve up to the summation order of dot products.
+ * every design stopped. In FP64 each design gets the same solution as its own
+ * mgcg_solve / mgar_solve up to the summation order of dot products. With
+ * MGAR_PREC_MIXED the preconditioner and the reanalysis V-cycles are those of
+ * the single-design mixed form (FP32 over BF16 densities), and each PCG is
+ * plain iterative refinement: FP32 inner runs that reduce their residual by
+ * inner_tol, each followed by an FP64 residual replacement, until the FP64
+ * residual meets tol (at most cg_max inner iterations in total, 40
+ * replacements); stats report the inner iterations and the replacements.
  * Arrays are concatenations over designs in params order: design d's nodes
  * start at node_off[d] and its elements at elem_off[d] (mgar_batch_layout;
  * both host arrays of ndesigns + 1 entries, the last = totals). stats: host

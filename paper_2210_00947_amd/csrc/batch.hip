@@ -13,6 +13,17 @@
 // design is that of the single-design FP64 path (same stencil, transfer,
 // smoother, tail and coarsest-inverse code); only dot products are summed in
 // a different block order.
+//
+// Mixed precision (every design MGAR_PREC_MIXED): the preconditioner is an
+// FP32 V-cycle over BF16-stored densities (FP32 cell means below the finest
+// grid, FP64 coarsest inverse), the basis vectors of the reanalysis come from
+// FP32 V-cycles on FP64 right-hand sides, and the PCG is plain iterative
+// refinement: r = q - K x in FP64, an FP32 PCG run on K32 d = r until its
+// residual has dropped by inner_tol, x += d, repeated per design until
+// ||r|| <= tol ||q|| in FP64 (or the design's CG budget or the refinement
+// limit is spent). The single-design mixed path instead continues one Krylov
+// run across its residual replacements; the batched form restarts each
+// inner run so that designs stay independent with a scalar inner tolerance.
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
@@ -41,6 +52,7 @@ constexpr int MD_STRIDE = (int)(sizeof(MgarDev) / sizeof(double));
 static_assert(sizeof(BCgState) % sizeof(int) == 0, "BCgState stride");
 static_assert(sizeof(MgarDev) % sizeof(double) == 0, "MgarDev stride");
 constexpr int ITERS_PER_GRAPH = 4;
+constexpr int REFINE_MAX = 40;   // FP64 residual replacements per mixed solve
 
 template <typename T>
 int dalloc(T** p, long long n) {
@@ -71,8 +83,10 @@ struct Group {
   int dim = 0;
   std::vector<int> designs;
   int maxL = 0, maxlt = 0;
-  // arenas of grids >= 1 (index l; entry 0 unused)
+  // arenas of grids >= 1 (index l; entry 0 unused): FP64, or FP32 in a
+  // mixed batch
   std::vector<double*> b, xa, xb, rt, k;
+  std::vector<float*> bf, xaf, xbf, rtf, kf;
   std::vector<ItemList> down, restr, prol, coarsen;   // per level
   ItemList fine;          // finest grid of every design: vector and dot items
   ItemList cells;         // finest cells of every design
@@ -139,9 +153,22 @@ struct mgar_batch {
   int *keep = nullptr, *path = nullptr, *status = nullptr;
   double *res = nullptr, *nrm = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  double tol_captured = -1.0;
+  // iteration graphs: [0] FP64 PCG, [1] FP32 inner PCG of the mixed form
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  // mixed precision
+  bool mixed = false;
+  double inner_tol = 1e-3;
+  float kmin_f = 0.f, kdiff_f = 0.f;
+  uint16_t *dens = nullptr, *dens0 = nullptr;   // BF16 densities: current, K0
+  float* k32 = nullptr;                          // FP32 conductivities (inner operator)
+  float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *w32 = nullptr, *d32 = nullptr;
+  float *xa32 = nullptr, *rt32 = nullptr;
+  int* odone = nullptr;                          // per design: refinement finished
+  double *nq = nullptr, *nr = nullptr;           // per design ||q||^2, ||r||^2
+  std::vector<int> h_odone, h_iters, h_nref, h_conv;
+  std::vector<double> h_rel;
+  double tol_captured[2] = {-1.0, -1.0};
   // Work runs on `s`. A graph cannot be captured on the legacy default
   // stream, so when the caller passes NULL the batch owns a stream of its own
   // (default priority) and orders it after the caller's stream at every entry.
@@ -233,9 +260,130 @@ int biter(mgar_batch* B, Group& G, double tol) {
   return MGAR_OK;
 }
 
-int enqueue_iters(mgar_batch* B, double tol, int n) {
+// ---------------------------------------------------------------- FP32 stages
+
+CellB cells_b(const mgar_batch* B, const uint16_t* d) { return CellB{d, B->kmin_f, B->kdiff_f}; }
+
+// FP32 stencil of grid l of group G: the finest grid reads the BF16 K0
+// densities, coarser grids FP32 cell means.
+void bst32(mgar_batch* B, Group& G, int l, int mode, const ItemList& D, const float* x, const float* b,
+           float* out, double* part, const int* skip) {
+  if (l == 0)
+    launch_bstencil_t<float, CellB>(G.dim, mode, D.d, D.n(), D.nblk, x, cells_b(B, B->dens0),
+                                    cells_b(B, nullptr), b, out, B->omega, part, skip, ST_STRIDE, B->s);
+  else
+    launch_bstencil_t<float, CellF>(G.dim, mode, D.d, D.n(), D.nblk, x, CellF{G.kf[l]}, CellF{nullptr}, b,
+                                    out, B->omega, part, skip, ST_STRIDE, B->s);
+}
+
+// The V-cycle of bvcycle in FP32 on the BF16/FP32 K0 hierarchy (FP64
+// coarsest inverse); partials of b0 . out in FP64.
+int bvcycle32(mgar_batch* B, Group& G, const float* b0, const float* x0, float* out, double* part,
+              const int* skip) {
+  const int ss = ST_STRIDE;
+  for (int l = 0; l < G.maxlt; ++l) {
+    ItemList& D = G.down[l];
+    if (D.h.empty()) continue;
+    const float* bl = (l == 0) ? b0 : G.bf[l];
+    float* xal = (l == 0) ? B->xa32 : G.xaf[l];
+    float* rtl = (l == 0) ? B->rt32 : G.rtf[l];
+    if (l == 0 && x0) bst32(B, G, l, SM_JACOBI, D, x0, bl, xal, nullptr, skip);
+    else bst32(B, G, l, SM_JACOBI0, D, bl, bl, xal, nullptr, skip);
+    bst32(B, G, l, SM_RESID, D, xal, bl, rtl, nullptr, skip);
+    ItemList& Rs = G.restr[l];
+    launch_brestrict_t<float>(G.dim, Rs.d, Rs.n(), Rs.nblk, rtl, G.bf[l + 1], skip, ss, B->s);
+  }
+  launch_bvtail_t<float>(G.dim, G.tails, G.ntails, G.tail_lds, B->omega, skip, ss, B->s);
+  for (int l = G.maxlt - 1; l >= 0; --l) {
+    ItemList& D = G.down[l];
+    if (D.h.empty()) continue;
+    const float* bl = (l == 0) ? b0 : G.bf[l];
+    float* xal = (l == 0) ? B->xa32 : G.xaf[l];
+    ItemList& P = G.prol[l];
+    launch_bprolong_t<float>(G.dim, P.d, P.n(), P.nblk, G.xbf[l + 1], xal, skip, ss, B->s);
+    float* o = (l == 0) ? out : G.xbf[l];
+    bst32(B, G, l, (l == 0 && part) ? SM_JACOBI_DOT : SM_JACOBI, D, xal, bl, o, part, skip);
+  }
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+// K0 := K(dens) for every design of G whose keep flag is 0: BF16 densities
+// and FP64 cells of the finest grid (the latter for the -dK products of the
+// reanalysis), FP32 cell means below, FP64 coarsest inverses.
+int bbuild32(mgar_batch* B, Group& G, const int* keep) {
+  launch_bcopy_cells_t<uint16_t>(G.cells.d, G.cells.n(), G.cells.nblk, B->dens, B->dens0, keep, 1, B->s);
+  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, B->kcur, B->k0, keep, 1, B->s);
+  for (int l = 0; l + 1 < G.maxL; ++l) {
+    ItemList& C = G.coarsen[l];
+    if (l == 0)
+      launch_bcoarsen_t<CellB, float>(G.dim, C.d, C.n(), C.nblk, cells_b(B, B->dens0), G.kf[1], keep, 1, B->s);
+    else
+      launch_bcoarsen_t<CellF, float>(G.dim, C.d, C.n(), C.nblk, CellF{G.kf[l]}, G.kf[l + 1], keep, 1, B->s);
+  }
+  launch_bcoarse_build_t<CellF>(G.dim, G.cb_reg, G.n_reg, true, B->status, keep, 1, B->s);
+  launch_bcoarse_build_t<CellF>(G.dim, G.cb_gen, G.n_gen, false, B->status, keep, 1, B->s);
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+// One FP32 PCG iteration on K32 d = r32 for every design that is not done
+// (FP64 inner products and scalars).
+int biter32(mgar_batch* B, Group& G, double tol) {
+  ItemList& F = G.fine;
+  const int* skip = st_done(B);
+  double* rz = &B->st[0].rz[0];
+  BACK(bvcycle32(B, G, B->r32, nullptr, B->z32, B->pb, skip));
+  launch_bfinalize(F.d, F.n(), B->pb, 1, rz, (int)(sizeof(BCgState) / sizeof(double)), &B->st[0].it, skip,
+                   ST_STRIDE, B->s);
+  launch_bp_update_t<float>(F.d, F.n(), F.nblk, B->z32, B->p32, B->st, B->s);
+  launch_bstencil_t<float, CellF>(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, B->p32, CellF{B->k32},
+                                  CellF{nullptr}, nullptr, B->w32, 0.0, B->pc, skip, ST_STRIDE, B->s);
+  launch_bfinalize(F.d, F.n(), B->pc, 1, &B->st[0].pw, (int)(sizeof(BCgState) / sizeof(double)), nullptr,
+                   skip, ST_STRIDE, B->s);
+  launch_bcg_update_t<float>(F.d, F.n(), F.nblk, B->d32, B->r32, B->p32, B->w32, B->st, B->pa, B->s);
+  launch_bcg_check(F.d, F.n(), B->st, B->pa, tol, B->cg_max, B->s);
+  BLAUNCH();
+  return MGAR_OK;
+}
+
+// cls 0: FP64 PCG iterations; cls 1: FP32 inner iterations of the mixed form
+int enqueue_iters(mgar_batch* B, int cls, double tol, int n) {
   for (int i = 0; i < n; ++i)
-    for (Group& G : B->grp) BACK(biter(B, G, tol));
+    for (Group& G : B->grp) BACK(cls == 0 ? biter(B, G, tol) : biter32(B, G, tol));
+  return MGAR_OK;
+}
+
+// Iterations of class cls until every design's PCG state is done (the state
+// was initialised by the caller). The iteration is captured as a graph once
+// per class and tolerance and replayed in chunks of ITERS_PER_GRAPH.
+int run_until_done(mgar_batch* B, int cls, double tol) {
+  if (B->use_graph && (!B->gexec[cls] || B->tol_captured[cls] != tol)) {
+    if (B->gexec[cls]) { (void)hipGraphExecDestroy(B->gexec[cls]); B->gexec[cls] = nullptr; }
+    if (B->graph[cls]) { (void)hipGraphDestroy(B->graph[cls]); B->graph[cls] = nullptr; }
+    BHIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_iters(B, cls, tol, ITERS_PER_GRAPH);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->s, &gr);
+    if (rc != MGAR_OK) return rc;
+    BHIP(e);
+    B->graph[cls] = gr;
+    BHIP(hipGraphInstantiate(&B->gexec[cls], gr, nullptr, nullptr, 0));
+    B->tol_captured[cls] = tol;
+  }
+  std::vector<BCgState> hs(B->nd);
+  int done_iters = 0;
+  for (;;) {
+    BHIP(hipMemcpyAsync(hs.data(), B->st, sizeof(BCgState) * B->nd, hipMemcpyDeviceToHost, B->s));
+    BHIP(hipStreamSynchronize(B->s));
+    bool all = true;
+    for (const BCgState& x : hs) all = all && x.done;
+    if (all) break;
+    if (done_iters > B->cg_max + ITERS_PER_GRAPH) return MGAR_E_HIP;   // the device test must have fired
+    if (B->use_graph) BHIP(hipGraphLaunch(B->gexec[cls], B->s));
+    else BACK(enqueue_iters(B, cls, tol, ITERS_PER_GRAPH));
+    done_iters += ITERS_PER_GRAPH;
+  }
   return MGAR_OK;
 }
 
@@ -251,32 +399,81 @@ int bpcg(mgar_batch* B, double tol, const int* keep_done) {
     launch_bcg_init(F.d, F.n(), B->st, B->pb, B->pa, tol, B->cg_max, keep_done, B->s);
   }
   BLAUNCH();
-  // (re)capture the iteration graph when the tolerance it was built for changed
-  if (B->use_graph && (!B->gexec || B->tol_captured != tol)) {
-    if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
-    if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
-    BHIP(hipStreamBeginCapture(B->s, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_iters(B, tol, ITERS_PER_GRAPH);
-    hipGraph_t gr = nullptr;
-    const hipError_t e = hipStreamEndCapture(B->s, &gr);
-    if (rc != MGAR_OK) return rc;
-    BHIP(e);
-    B->graph = gr;
-    BHIP(hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0));
-    B->tol_captured = tol;
+  return run_until_done(B, 0, tol);
+}
+
+// Mixed form, per design from x = cx (designs with keep_done set are left as
+// they are): r = q - K(kcur) x in FP64; stop when ||r|| <= tol ||q||, when the
+// design has spent cg_max inner iterations or after REFINE_MAX replacements;
+// else an FP32 PCG run from d = 0 on K32 d = r (K32: the FP32 rounding of the
+// current conductivities; preconditioner: the FP32 V-cycle on the BF16 K0
+// hierarchy) until ||r32|| <= inner_tol ||r32(0)|| or cg_max iterations, and
+// x += d in FP64. One host synchronisation per replacement (the per-design
+// decisions) besides those of the inner runs.
+int bsolve_mixed(mgar_batch* B, double tol, const int* keep_done) {
+  const int nd = B->nd;
+  const long long N = B->N;
+  launch_cast_f32(B->kcur, B->k32, B->E, B->s);
+  for (Group& G : B->grp) {
+    ItemList& F = G.fine;
+    launch_bdot(F.d, F.n(), F.nblk, B->qm, B->qm, B->pb, nullptr, 0, B->s);
+    launch_bfinalize(F.d, F.n(), B->pb, 1, B->nq, 1, nullptr, nullptr, 0, B->s);
   }
-  std::vector<BCgState> hs(B->nd);
-  int done_iters = 0;
+  B->h_odone.assign(nd, 0);
+  B->h_iters.assign(nd, 0);
+  B->h_nref.assign(nd, 0);
+  B->h_conv.assign(nd, 0);
+  B->h_rel.assign(nd, NAN);
+  if (keep_done) {
+    BHIP(hipMemcpyAsync(B->h_odone.data(), keep_done, sizeof(int) * nd, hipMemcpyDeviceToHost, B->s));
+    BHIP(hipMemcpyAsync(B->odone, keep_done, sizeof(int) * nd, hipMemcpyDeviceToDevice, B->s));
+  } else {
+    BHIP(hipMemsetAsync(B->odone, 0, sizeof(int) * nd, B->s));
+  }
+  std::vector<double> hq(nd), hr(nd);
+  std::vector<BCgState> hs(nd);
   for (;;) {
-    BHIP(hipMemcpyAsync(hs.data(), B->st, sizeof(BCgState) * B->nd, hipMemcpyDeviceToHost, B->s));
+    for (Group& G : B->grp) {
+      ItemList& F = G.fine;
+      launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
+                      B->odone, 1, B->s);
+      launch_bdot(F.d, F.n(), F.nblk, B->cr, B->cr, B->pa, B->odone, 1, B->s);
+      launch_bfinalize(F.d, F.n(), B->pa, 1, B->nr, 1, nullptr, B->odone, 1, B->s);
+    }
+    BLAUNCH();
+    BHIP(hipMemcpyAsync(hq.data(), B->nq, sizeof(double) * nd, hipMemcpyDeviceToHost, B->s));
+    BHIP(hipMemcpyAsync(hr.data(), B->nr, sizeof(double) * nd, hipMemcpyDeviceToHost, B->s));
     BHIP(hipStreamSynchronize(B->s));
     bool all = true;
-    for (const BCgState& x : hs) all = all && x.done;
+    for (int d = 0; d < nd; ++d) {
+      if (B->h_odone[d]) continue;
+      const double rel = hq[d] > 0.0 ? std::sqrt(hr[d] / hq[d]) : 0.0;
+      B->h_rel[d] = rel;
+      if (rel <= tol) { B->h_conv[d] = 1; B->h_odone[d] = 1; }
+      else if (B->h_iters[d] >= B->cg_max || B->h_nref[d] >= REFINE_MAX) B->h_odone[d] = 1;
+      all = all && B->h_odone[d];
+    }
     if (all) break;
-    if (done_iters > B->cg_max + ITERS_PER_GRAPH) return MGAR_E_HIP;   // the device test must have fired
-    if (B->use_graph) BHIP(hipGraphLaunch(B->gexec, B->s));
-    else BACK(enqueue_iters(B, tol, ITERS_PER_GRAPH));
-    done_iters += ITERS_PER_GRAPH;
+    // B->h_odone is not written again before the next synchronisation
+    BHIP(hipMemcpyAsync(B->odone, B->h_odone.data(), sizeof(int) * nd, hipMemcpyHostToDevice, B->s));
+    BHIP(hipMemsetAsync(B->d32, 0, sizeof(float) * N, B->s));
+    for (Group& G : B->grp) {
+      ItemList& F = G.fine;
+      launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, B->cr, B->r32, B->s);
+      launch_bdot_t<float>(F.d, F.n(), F.nblk, B->r32, B->r32, B->pa, nullptr, 0, B->s);
+      launch_bcg_init(F.d, F.n(), B->st, B->pa, B->pa, B->inner_tol, B->cg_max, B->odone, B->s);
+    }
+    BLAUNCH();
+    BACK(run_until_done(B, 1, B->inner_tol));
+    BHIP(hipMemcpyAsync(hs.data(), B->st, sizeof(BCgState) * nd, hipMemcpyDeviceToHost, B->s));
+    launch_add_f32(B->cx, B->d32, N, B->s);
+    BLAUNCH();
+    BHIP(hipStreamSynchronize(B->s));
+    for (int d = 0; d < nd; ++d)
+      if (!B->h_odone[d]) {
+        B->h_iters[d] += hs[d].it;
+        B->h_nref[d] += 1;
+      }
   }
   return MGAR_OK;
 }
@@ -301,16 +498,19 @@ int finish(mgar_batch* B, double* T, mgar_stats* stats, int default_path) {
   for (int i = 0; i < B->nd; ++i) {
     if (hstat[i]) return MGAR_E_NOT_SPD;
     const bool accepted = (hp[i] == MGAR_PATH_ACCEPT);
-    if (!accepted && !hs[i].conv) rc = MGAR_W_NOT_CONVERGED;
+    const bool conv = B->mixed ? B->h_conv[i] != 0 : hs[i].conv != 0;
+    if (!accepted && !conv) rc = MGAR_W_NOT_CONVERGED;
     if (stats) {
       mgar_stats& o = stats[i];
       std::memset(&o, 0, sizeof(o));
       o.path = hp[i];
-      o.cg_iters = accepted ? 0 : hs[i].it;
+      o.cg_iters = accepted ? 0 : (B->mixed ? B->h_iters[i] : hs[i].it);
       o.vcycles = (default_path < 0 ? B->m - 1 : 0) + o.cg_iters;
-      o.refinements = 0;
+      o.refinements = (accepted || !B->mixed) ? 0 : B->h_nref[i];
       o.res_ca = hr[i];
-      o.res_final = accepted ? hr[i] : (hs[i].qq > 0.0 ? std::sqrt(hs[i].rr / hs[i].qq) : 0.0);
+      o.res_final = accepted ? hr[i]
+                    : B->mixed ? B->h_rel[i]
+                               : (hs[i].qq > 0.0 ? std::sqrt(hs[i].rr / hs[i].qq) : 0.0);
       o.ms = ms;
     }
   }
@@ -323,11 +523,14 @@ extern "C" {
 
 void mgar_batch_destroy(mgar_batch* b) {
   if (!b) return;
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int c = 0; c < 2; ++c) {
+    if (b->gexec[c]) (void)hipGraphExecDestroy(b->gexec[c]);
+    if (b->graph[c]) (void)hipGraphDestroy(b->graph[c]);
+  }
   auto f = [](void* p) { if (p) (void)hipFree(p); };
   for (Group& G : b->grp) {
     for (size_t l = 0; l < G.b.size(); ++l) { f(G.b[l]); f(G.xa[l]); f(G.xb[l]); f(G.rt[l]); f(G.k[l]); }
+    for (size_t l = 0; l < G.bf.size(); ++l) { f(G.bf[l]); f(G.xaf[l]); f(G.xbf[l]); f(G.rtf[l]); f(G.kf[l]); }
     for (auto* v : {&G.down, &G.restr, &G.prol, &G.coarsen})
       for (ItemList& L : *v) f(L.d);
     f(G.fine.d); f(G.cells.d); f(G.tails); f(G.cb_reg); f(G.cb_gen);
@@ -335,7 +538,10 @@ void mgar_batch_destroy(mgar_batch* b) {
   for (void* p : {(void*)b->kcur, (void*)b->k0, (void*)b->qm, (void*)b->cx, (void*)b->cr, (void*)b->cz,
                   (void*)b->cp, (void*)b->cw, (void*)b->xa0, (void*)b->rt0, (void*)b->R, (void*)b->Wm,
                   (void*)b->Ainv, (void*)b->pa, (void*)b->pb, (void*)b->pc, (void*)b->st, (void*)b->md,
-                  (void*)b->keep, (void*)b->path, (void*)b->status, (void*)b->res, (void*)b->nrm})
+                  (void*)b->keep, (void*)b->path, (void*)b->status, (void*)b->res, (void*)b->nrm,
+                  (void*)b->dens, (void*)b->dens0, (void*)b->k32, (void*)b->r32, (void*)b->z32, (void*)b->p32,
+                  (void*)b->w32, (void*)b->d32, (void*)b->xa32, (void*)b->rt32, (void*)b->odone, (void*)b->nq,
+                  (void*)b->nr})
     f(p);
   if (b->e0) (void)hipEventDestroy(b->e0);
   if (b->e1) (void)hipEventDestroy(b->e1);
@@ -358,13 +564,23 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
   B->eps = p[0].eps_accept;
   B->cg_max = p[0].cg_max;
   B->basis_x0_zero = p[0].basis_x0_zero;
+  B->mixed = p[0].precision == MGAR_PREC_MIXED;
+  B->inner_tol = p[0].inner_tol;
+  B->kmin_f = (float)p[0].kmin;
+  B->kdiff_f = (float)(p[0].k0 - p[0].kmin);
+  const size_t esz = B->mixed ? sizeof(float) : sizeof(double);   // multigrid value type
   B->d.resize(nd);
   for (int i = 0; i < nd; ++i) {
     BACK(mgar_internal_validate(&p[i]));
-    if (p[i].precision != MGAR_PREC_FP64) return MGAR_E_PRECISION;
+    if (p[i].precision != MGAR_PREC_FP64 && p[i].precision != MGAR_PREC_MIXED) return MGAR_E_PRECISION;
+    if (p[i].precision == MGAR_PREC_MIXED && p[i].penal != 3.0) return MGAR_E_PRECISION;
     if (p[i].levels < 2) return MGAR_E_DIMS;
     if (p[i].n_basis != B->m || p[i].omega != B->omega || p[i].eps_accept != B->eps ||
-        p[i].cg_max != B->cg_max || p[i].basis_x0_zero != B->basis_x0_zero)
+        p[i].cg_max != B->cg_max || p[i].basis_x0_zero != B->basis_x0_zero ||
+        p[i].precision != p[0].precision || p[i].k0 != p[0].k0 || p[i].kmin != p[0].kmin ||
+        p[i].penal != p[0].penal)
+      return MGAR_E_ARG;
+    if (B->mixed && (p[i].inner_tol != B->inner_tol || !(B->inner_tol > 0.0 && B->inner_tol < 1.0)))
       return MGAR_E_ARG;
     Design& D = B->d[i];
     D.p = p[i];
@@ -395,6 +611,11 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
     G.xb.assign(G.maxL, nullptr);
     G.rt.assign(G.maxL, nullptr);
     G.k.assign(G.maxL, nullptr);
+    G.bf.assign(G.maxL, nullptr);
+    G.xaf.assign(G.maxL, nullptr);
+    G.xbf.assign(G.maxL, nullptr);
+    G.rtf.assign(G.maxL, nullptr);
+    G.kf.assign(G.maxL, nullptr);
     // arenas of grids >= 1
     for (int l = 1; l < G.maxL; ++l) {
       long long nn = 0, ne = 0;
@@ -409,11 +630,19 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
           ne += D.g[l].ne;
         }
       }
-      BACK(dalloc(&G.b[l], nn));
-      BACK(dalloc(&G.xa[l], nn));
-      BACK(dalloc(&G.xb[l], nn));
-      BACK(dalloc(&G.rt[l], nn));
-      BACK(dalloc(&G.k[l], ne));
+      if (B->mixed) {
+        BACK(dalloc(&G.bf[l], nn));
+        BACK(dalloc(&G.xaf[l], nn));
+        BACK(dalloc(&G.xbf[l], nn));
+        BACK(dalloc(&G.rtf[l], nn));
+        BACK(dalloc(&G.kf[l], ne));
+      } else {
+        BACK(dalloc(&G.b[l], nn));
+        BACK(dalloc(&G.xa[l], nn));
+        BACK(dalloc(&G.xb[l], nn));
+        BACK(dalloc(&G.rt[l], nn));
+        BACK(dalloc(&G.k[l], ne));
+      }
     }
     B->grp.push_back(G);
   }
@@ -425,17 +654,23 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
       Design& D = B->d[i];
       std::vector<const void*> ks(D.L, nullptr);
       ks[0] = nullptr;
-      for (int l = 1; l < D.L; ++l) ks[l] = G.k[l] + D.aeoff[l];
+      for (int l = 1; l < D.L; ++l)
+        ks[l] = B->mixed ? (const void*)(G.kf[l] + D.aeoff[l]) : (const void*)(G.k[l] + D.aeoff[l]);
       TailSpec T;
       D.lt = -1;
       for (int lt = 1; lt < D.L; ++lt)
-        if (tail_plan(D.g.data(), ks.data(), lt, D.L, sizeof(double), &T)) { D.lt = lt; break; }
+        if (tail_plan(D.g.data(), ks.data(), lt, D.L, esz, &T)) { D.lt = lt; break; }
       if (D.lt < 0) return MGAR_E_DIMS;
       BTail bt;
       std::memset(&bt, 0, sizeof(bt));
-      (void)tail_plan(D.g.data(), ks.data(), D.lt, D.L, sizeof(double), &bt.ts);
-      bt.bin = G.b[D.lt] + D.aoff[D.lt];
-      bt.xout = G.xb[D.lt] + D.aoff[D.lt];
+      (void)tail_plan(D.g.data(), ks.data(), D.lt, D.L, esz, &bt.ts);
+      if (B->mixed) {
+        bt.bin = G.bf[D.lt] + D.aoff[D.lt];
+        bt.xout = G.xbf[D.lt] + D.aoff[D.lt];
+      } else {
+        bt.bin = G.b[D.lt] + D.aoff[D.lt];
+        bt.xout = G.xb[D.lt] + D.aoff[D.lt];
+      }
       bt.design = i;
       tails.push_back(bt);
       G.tail_lds = std::max(G.tail_lds, bt.ts.lds_elems);
@@ -443,7 +678,8 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
       BCoarse c;
       std::memset(&c, 0, sizeof(c));
       c.g = D.g[D.L - 1];
-      c.k = G.k[D.L - 1] + D.aeoff[D.L - 1];
+      c.k = B->mixed ? (const void*)(G.kf[D.L - 1] + D.aeoff[D.L - 1])
+                     : (const void*)(G.k[D.L - 1] + D.aeoff[D.L - 1]);
       c.design = i;
       (c.g.nn <= 128 ? creg : cgen).push_back(c);
     }
@@ -462,7 +698,7 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
     BACK(dalloc(&G.cb_gen, G.n_gen));
     if (G.n_reg) BHIP(hipMemcpy(G.cb_reg, creg.data(), sizeof(BCoarse) * creg.size(), hipMemcpyHostToDevice));
     if (G.n_gen) BHIP(hipMemcpy(G.cb_gen, cgen.data(), sizeof(BCoarse) * cgen.size(), hipMemcpyHostToDevice));
-    if ((size_t)G.tail_lds * sizeof(double) > 64 * 1024) return MGAR_E_DIMS;
+    if ((size_t)G.tail_lds * esz > 64 * 1024) return MGAR_E_DIMS;
     // work lists
     G.down.resize(G.maxL);
     G.restr.resize(G.maxL);
@@ -504,7 +740,9 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
   const long long N = B->N, E = B->E;
   BACK(dalloc(&B->kcur, E));
   BACK(dalloc(&B->k0, E));
-  for (double** v : {&B->qm, &B->cx, &B->cr, &B->cz, &B->cp, &B->cw, &B->xa0, &B->rt0}) BACK(dalloc(v, N));
+  for (double** v : {&B->qm, &B->cx, &B->cr, &B->cz, &B->cp, &B->cw}) BACK(dalloc(v, N));
+  if (!B->mixed)
+    for (double** v : {&B->xa0, &B->rt0}) BACK(dalloc(v, N));
   BACK(dalloc(&B->R, N * B->m));
   BACK(dalloc(&B->Wm, N * B->m));
   long long nb = 0;
@@ -520,6 +758,15 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
   BACK(dalloc(&B->status, nd));
   BACK(dalloc(&B->res, nd));
   BACK(dalloc(&B->nrm, nd));
+  if (B->mixed) {
+    BACK(dalloc(&B->dens, E));
+    BACK(dalloc(&B->dens0, E));
+    BACK(dalloc(&B->k32, E));
+    for (float** v : {&B->r32, &B->z32, &B->p32, &B->w32, &B->d32, &B->xa32, &B->rt32}) BACK(dalloc(v, N));
+    BACK(dalloc(&B->odone, nd));
+    BACK(dalloc(&B->nq, nd));
+    BACK(dalloc(&B->nr, nd));
+  }
   BHIP(hipMemset(B->st, 0, sizeof(BCgState) * nd));
   BHIP(hipMemset(B->md, 0, sizeof(MgarDev) * nd));
   BHIP(hipMemset(B->status, 0, sizeof(int) * nd));
@@ -584,15 +831,16 @@ int mgcg_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
   BHIP(hipEventRecord(b->e0, b->s));
   const mgar_params& p0 = b->d[0].p;
   launch_simp(xphys, b->kcur, b->E, p0.k0, p0.kmin, p0.penal, b->s);
+  if (b->mixed) launch_cast_bf16(xphys, b->dens, b->E, b->s);
   BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
   for (Group& G : b->grp) {
-    BACK(bbuild(b, G, nullptr));
+    BACK(b->mixed ? bbuild32(b, G, nullptr) : bbuild(b, G, nullptr));
     launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, q, b->qm, b->s);
     if (T0) launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, T0, b->cx, b->s);
   }
   if (!T0) BHIP(hipMemsetAsync(b->cx, 0, sizeof(double) * b->N, b->s));
   BLAUNCH();
-  BACK(bpcg(b, tol, nullptr));
+  BACK(b->mixed ? bsolve_mixed(b, tol, nullptr) : bpcg(b, tol, nullptr));
   b->has_k0 = true;
   return finish(b, T, stats, MGAR_PATH_MGCG);
 }
@@ -609,6 +857,7 @@ int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
   const int mds = MD_STRIDE;
   double* mdd = reinterpret_cast<double*>(b->md);
   launch_simp(xphys, b->kcur, b->E, p0.k0, p0.kmin, p0.penal, b->s);
+  if (b->mixed) launch_cast_bf16(xphys, b->dens, b->E, b->s);
   BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
   for (Group& G : b->grp) {
     ItemList& F = G.fine;
@@ -620,8 +869,17 @@ int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
       const double* prev = b->R + (long long)(i - 1) * N;
       launch_bstencil(G.dim, SM_NEG_DK, F.d, F.n(), F.nblk, prev, b->kcur, b->k0, nullptr, b->cz, 0.0,
                       nullptr, nullptr, 0, b->s);
-      BACK(bvcycle(b, G, b->cz, b->basis_x0_zero ? nullptr : prev, b->R + (long long)i * N, nullptr,
-                   nullptr));
+      if (b->mixed) {
+        // -dK r in FP64 (a difference of nearby operators), one FP32 V-cycle
+        // on the BF16 K0 hierarchy, the column kept in FP64
+        launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, b->cz, b->z32, b->s);
+        if (!b->basis_x0_zero) launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, prev, b->p32, b->s);
+        BACK(bvcycle32(b, G, b->z32, b->basis_x0_zero ? nullptr : b->p32, b->w32, nullptr, nullptr));
+        launch_bmask_copy_t<float, double>(F.d, F.n(), F.nblk, b->w32, b->R + (long long)i * N, b->s);
+      } else {
+        BACK(bvcycle(b, G, b->cz, b->basis_x0_zero ? nullptr : prev, b->R + (long long)i * N, nullptr,
+                     nullptr));
+      }
     }
     // Gram-Schmidt applied twice per column (same rule as the single path)
     for (int j = 0; j < m; ++j) {
@@ -655,10 +913,10 @@ int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
                      nullptr, 0, b->s);
     launch_bdecide(F.d, F.n(), b->md, b->st, b->eps, b->keep, b->path, b->res, b->s);
     // rejected designs: K becomes the new K0, MGCG from the reduced solution
-    BACK(bbuild(b, G, b->keep));
+    BACK(b->mixed ? bbuild32(b, G, b->keep) : bbuild(b, G, b->keep));
   }
   BLAUNCH();
-  BACK(bpcg(b, tol, b->keep));
+  BACK(b->mixed ? bsolve_mixed(b, tol, b->keep) : bpcg(b, tol, b->keep));
   return finish(b, T, stats, -1);
 }
 

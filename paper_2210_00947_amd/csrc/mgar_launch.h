@@ -291,14 +291,14 @@ struct BItem {
 // Single-workgroup jobs: one block per design.
 struct BTail {
   TailSpec ts;
-  const double* bin;
-  double* xout;
+  const void* bin;       // value type of the launch (double or float)
+  void* xout;
   const double* A;
   int design, pad;
 };
 struct BCoarse {
   Geo g;
-  const double* k;
+  const void* k;         // coarsest cells, value type of the cell loader
   double* A;
   int design, pad;
 };
@@ -306,6 +306,29 @@ struct BCoarse {
 // skip[d * sstride] != 0 (e.g. &BCgState::done of converged designs).
 // stencil.hip
 int batch_item_blocks(const Geo& g);   // blocks of one item of a node-parallel launch
+// Value-type forms: T = double with CellD, T = float with CellF or CellB (the
+// loader is moved to each design's cells). Coarsening from CellD to double
+// or from CellB / CellF to float; tails of T; coarsest builds from CellD or
+// CellF cells (the inverse is FP64 either way).
+template <typename T, typename CL>
+void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, const T* x, CL k, CL kref,
+                       const T* b, T* out, double omega, double* part, const int* skip, int sstride,
+                       hipStream_t s);
+template <typename T>
+void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, const T* rf, T* rc, const int* skip,
+                        int sstride, hipStream_t s);
+template <typename T>
+void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, const T* xc, T* xf, const int* skip,
+                       int sstride, hipStream_t s);
+template <typename CL, typename TO>
+void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, CL kf, TO* kc, const int* skip,
+                       int sstride, hipStream_t s);
+template <typename T>
+void launch_bvtail_t(int dim, const BTail* jobs, int njobs, int lds_elems, double omega, const int* skip,
+                     int sstride, hipStream_t s);
+template <typename CL>
+void launch_bcoarse_build_t(int dim, const BCoarse* jobs, int njobs, bool reg, int* status, const int* skip,
+                            int sstride, hipStream_t s);
 void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
                      const double* k, const double* kref, const double* b, double* out, double omega,
                      double* part, const int* skip, int sstride, hipStream_t s);
@@ -317,6 +340,9 @@ void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const doubl
                      const int* skip, int sstride, hipStream_t s);
 void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
                        hipStream_t s);
+// (double, float) and (float, double) conversions; fixed nodes become 0
+template <typename TI, typename TO>
+void launch_bmask_copy_t(const BItem* items, int nit, int nblk, const TI* in, TO* out, hipStream_t s);
 void launch_bvtail(int dim, const BTail* jobs, int njobs, int lds_elems, double omega,
                    const int* skip, int sstride, hipStream_t s);
 void launch_bcoarse_build(int dim, const BCoarse* jobs, int njobs, bool reg, int* status,
@@ -357,6 +383,20 @@ void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, doub
                     int* path, double* res_out, hipStream_t s);
 void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
                         const int* skip, int sstride, hipStream_t s);
+// FP32 forms of the PCG vector kernels (inner products accumulated in FP64)
+// and a copy of BF16 cells.
+template <typename T>
+void launch_bdot_t(const BItem* items, int nit, int nblk, const T* a, const T* b, double* part,
+                   const int* skip, int sstride, hipStream_t s);
+template <typename T>
+void launch_bp_update_t(const BItem* items, int nit, int nblk, const T* z, T* p, const BCgState* st,
+                        hipStream_t s);
+template <typename T>
+void launch_bcg_update_t(const BItem* items, int nit, int nblk, T* x, T* r, const T* p, const T* w,
+                         const BCgState* st, double* part, hipStream_t s);
+template <typename T>
+void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, const T* a, T* b, const int* skip,
+                          int sstride, hipStream_t s);
 
 // smooth.hip -----------------------------------------------------------------
 // Boundary smoothing (Eq 24-27): nodal projection of -dc with cone weights of

@@ -1935,22 +1935,26 @@ __device__ inline bool bskip(const int* skip, int sstride, int design) {
   return skip && skip[(long long)design * sstride] != 0;
 }
 
-template <int DIM, int MODE>
+// A cell loader moved to a design's cells (element offset eoff).
+template <typename CL>
+__device__ inline CL cl_at(CL c, long long eoff) {
+  c.p += eoff;
+  return c;
+}
+
+template <int DIM, int MODE, typename T, typename CL>
 __global__ __launch_bounds__(TBX* TBY) void kb_stencil(const BItem* __restrict__ items, int nit,
-                                                       const double* __restrict__ x,
-                                                       const double* __restrict__ k,
-                                                       const double* __restrict__ kref,
-                                                       const double* __restrict__ b,
-                                                       double* __restrict__ out, double omega,
-                                                       double* __restrict__ part,
+                                                       const T* __restrict__ x, CL k, CL kref,
+                                                       const T* __restrict__ b, T* __restrict__ out,
+                                                       T omega, double* __restrict__ part,
                                                        const int* __restrict__ skip, int sstride) {
   __shared__ double sh[TBX * TBY / MGAR_WAVE];
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo g = it.g;
   const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
-  const double d = stencil_b_point<DIM, MODE, double, CellD>(
-      g, n, x + it.off, CellD{k + it.eoff}, CellD{kref ? kref + it.eoff : k + it.eoff},
+  const double d = stencil_b_point<DIM, MODE, T, CL>(
+      g, n, x + it.off, cl_at(k, it.eoff), cl_at(kref.p ? kref : k, it.eoff),
       b ? b + it.off : x + it.off, out + it.off, omega);
   if (MODE == SM_APPLY_DOT || MODE == SM_JACOBI_DOT) {
     const double s = block_sum(d, sh);
@@ -1958,36 +1962,34 @@ __global__ __launch_bounds__(TBX* TBY) void kb_stencil(const BItem* __restrict__
   }
 }
 
-template <int DIM>
+template <int DIM, typename T>
 __global__ __launch_bounds__(TBX* TBY) void kb_restrict(const BItem* __restrict__ items, int nit,
-                                                        const double* __restrict__ rf,
-                                                        double* __restrict__ rc,
+                                                        const T* __restrict__ rf, T* __restrict__ rc,
                                                         const int* __restrict__ skip, int sstride) {
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
-  restrict_b_point<DIM, double>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
-                                rf + it.off, rc + it.coff);
+  restrict_b_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+                           rf + it.off, rc + it.coff);
 }
 
-template <int DIM>
+template <int DIM, typename T>
 __global__ __launch_bounds__(TBX* TBY) void kb_prolong(const BItem* __restrict__ items, int nit,
-                                                       const double* __restrict__ xc,
-                                                       double* __restrict__ xf,
+                                                       const T* __restrict__ xc, T* __restrict__ xf,
                                                        const int* __restrict__ skip, int sstride) {
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
-  prolong_b8_point<DIM, double>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
-                                xc + it.coff, xf + it.off);
+  prolong_b8_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+                           xc + it.coff, xf + it.off);
 }
 
-// coarse cells of item it.gc from fine cells of it.g (one thread per coarse cell)
-template <int DIM>
-__global__ __launch_bounds__(TBX* TBY) void kb_coarsen(const BItem* __restrict__ items, int nit,
-                                                       const double* __restrict__ kf,
-                                                       double* __restrict__ kc,
-                                                       const int* __restrict__ skip, int sstride) {
+// coarse cells of item it.gc from fine cells of it.g (one thread per coarse
+// cell), summed in the order of k_coarsen
+template <int DIM, typename CL, typename TO>
+__global__ __launch_bounds__(TBX* TBY) void kb_coarsen(const BItem* __restrict__ items, int nit, CL kf,
+                                                       TO* __restrict__ kc, const int* __restrict__ skip,
+                                                       int sstride) {
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
@@ -1997,35 +1999,36 @@ __global__ __launch_bounds__(TBX* TBY) void kb_coarsen(const BItem* __restrict__
   const long long r = e / gc.nx;
   const int ey = (int)(r % gc.ny);
   const int ez = (int)(r / gc.ny);
-  const double* f = kf + it.eoff;
-  double s = 0.0;
+  const CL f = cl_at(kf, it.eoff);
+  using V = decltype(f(0));
+  V s = V(0);
   for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
     for (int bb = 0; bb < 2; ++bb)
-      for (int a = 0; a < 2; ++a) s += f[geo_elem(gf, 2 * ex + a, 2 * ey + bb, DIM == 3 ? 2 * ez + c : 0)];
-  kc[it.ceoff + e] = s * (DIM == 3 ? 0.125 : 0.25);
+      for (int a = 0; a < 2; ++a) s += f(geo_elem(gf, 2 * ex + a, 2 * ey + bb, DIM == 3 ? 2 * ez + c : 0));
+  kc[it.ceoff + e] = (TO)(s * V(DIM == 3 ? 0.125 : 0.25));
 }
 
+template <typename TI, typename TO>
 __global__ __launch_bounds__(TBX* TBY) void kb_mask_copy(const BItem* __restrict__ items, int nit,
-                                                         const double* __restrict__ in,
-                                                         double* __restrict__ out) {
+                                                         const TI* __restrict__ in, TO* __restrict__ out) {
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   const Geo g = it.g;
   const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
   if (n >= g.nn) return;
   int i, j, k;
   node_ijk(g, n, i, j, k);
-  out[it.off + n] = geo_fixed(g, i, j, k) ? 0.0 : in[it.off + n];
+  out[it.off + n] = geo_fixed(g, i, j, k) ? TO(0) : (TO)in[it.off + n];
 }
 
-template <int DIM>
+template <int DIM, typename T>
 __global__ __launch_bounds__(TT) void kb_vtail(const BTail* __restrict__ jobs, double omega,
                                                const int* __restrict__ skip, int sstride) {
   const BTail& jb = jobs[blockIdx.x];
   if (bskip(skip, sstride, jb.design)) return;
-  vtail_body<DIM, double>(jb.ts, jb.bin, jb.xout, jb.A, omega);
+  vtail_body<DIM, T>(jb.ts, static_cast<const T*>(jb.bin), static_cast<T*>(jb.xout), jb.A, (T)omega);
 }
 
-template <int DIM, bool REG>
+template <int DIM, bool REG, typename CL>
 __global__ __launch_bounds__(CB_THREADS) void kb_coarse_build(const BCoarse* __restrict__ jobs,
                                                               int* __restrict__ status,
                                                               const int* __restrict__ skip,
@@ -2033,8 +2036,9 @@ __global__ __launch_bounds__(CB_THREADS) void kb_coarse_build(const BCoarse* __r
   const BCoarse& jb = jobs[blockIdx.x];
   if (bskip(skip, sstride, jb.design)) return;
   const Geo g = jb.g;
-  if (REG) coarse_build_reg_body<DIM, CellD>(g, CellD{jb.k}, jb.A, status + jb.design);
-  else coarse_build_body<DIM, CellD>(g, CellD{jb.k}, jb.A, status + jb.design);
+  const CL k{static_cast<const typename CL::E*>(jb.k)};
+  if (REG) coarse_build_reg_body<DIM, CL>(g, k, jb.A, status + jb.design);
+  else coarse_build_body<DIM, CL>(g, k, jb.A, status + jb.design);
 }
 
 }  // namespace
@@ -2352,12 +2356,14 @@ template void launch_mask_copy_t<float, double>(const Geo&, const float*, double
 
 int batch_item_blocks(const Geo& g) { return (int)((g.nn + TBX * TBY - 1) / (TBX * TBY)); }
 
-void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
-                     const double* k, const double* kref, const double* b, double* out, double omega,
-                     double* part, const int* skip, int sstride, hipStream_t s) {
+template <typename T, typename CL>
+void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, const T* x, CL k, CL kref,
+                       const T* b, T* out, double omega, double* part, const int* skip, int sstride,
+                       hipStream_t s) {
   if (nblk <= 0) return;
   const dim3 blk(TBX, TBY, 1);
-#define BCALL(D, M) kb_stencil<D, M><<<nblk, blk, 0, s>>>(items, nit, x, k, kref, b, out, omega, part, skip, sstride)
+#define BCALL(D, M) \
+  kb_stencil<D, M, T, CL><<<nblk, blk, 0, s>>>(items, nit, x, k, kref, b, out, (T)omega, part, skip, sstride)
 #define BMODES(D)                                                 \
   switch (mode) {                                                 \
     case SM_APPLY: BCALL(D, SM_APPLY); break;                     \
@@ -2372,53 +2378,122 @@ void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, c
 #undef BMODES
 #undef BCALL
 }
+template void launch_bstencil_t<double, CellD>(int, int, const BItem*, int, int, const double*, CellD, CellD,
+                                               const double*, double*, double, double*, const int*, int,
+                                               hipStream_t);
+template void launch_bstencil_t<float, CellF>(int, int, const BItem*, int, int, const float*, CellF, CellF,
+                                              const float*, float*, double, double*, const int*, int,
+                                              hipStream_t);
+template void launch_bstencil_t<float, CellB>(int, int, const BItem*, int, int, const float*, CellB, CellB,
+                                              const float*, float*, double, double*, const int*, int,
+                                              hipStream_t);
+
+void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
+                     const double* k, const double* kref, const double* b, double* out, double omega,
+                     double* part, const int* skip, int sstride, hipStream_t s) {
+  launch_bstencil_t<double, CellD>(dim, mode, items, nit, nblk, x, CellD{k}, CellD{kref}, b, out, omega, part,
+                                   skip, sstride, s);
+}
+
+template <typename T>
+void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, const T* rf, T* rc, const int* skip,
+                        int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_restrict<2, T><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
+  else kb_restrict<3, T><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
+}
+template void launch_brestrict_t<double>(int, const BItem*, int, int, const double*, double*, const int*, int,
+                                         hipStream_t);
+template void launch_brestrict_t<float>(int, const BItem*, int, int, const float*, float*, const int*, int,
+                                        hipStream_t);
+
+template <typename T>
+void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, const T* xc, T* xf, const int* skip,
+                       int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_prolong<2, T><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
+  else kb_prolong<3, T><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
+}
+template void launch_bprolong_t<double>(int, const BItem*, int, int, const double*, double*, const int*, int,
+                                        hipStream_t);
+template void launch_bprolong_t<float>(int, const BItem*, int, int, const float*, float*, const int*, int,
+                                       hipStream_t);
+
+template <typename CL, typename TO>
+void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, CL kf, TO* kc, const int* skip,
+                       int sstride, hipStream_t s) {
+  if (nblk <= 0) return;
+  const dim3 blk(TBX, TBY, 1);
+  if (dim == 2) kb_coarsen<2, CL, TO><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
+  else kb_coarsen<3, CL, TO><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
+}
+template void launch_bcoarsen_t<CellD, double>(int, const BItem*, int, int, CellD, double*, const int*, int,
+                                               hipStream_t);
+template void launch_bcoarsen_t<CellB, float>(int, const BItem*, int, int, CellB, float*, const int*, int,
+                                              hipStream_t);
+template void launch_bcoarsen_t<CellF, float>(int, const BItem*, int, int, CellF, float*, const int*, int,
+                                              hipStream_t);
 
 void launch_brestrict(int dim, const BItem* items, int nit, int nblk, const double* rf, double* rc,
                       const int* skip, int sstride, hipStream_t s) {
-  if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
-  if (dim == 2) kb_restrict<2><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
-  else kb_restrict<3><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
+  launch_brestrict_t<double>(dim, items, nit, nblk, rf, rc, skip, sstride, s);
 }
-
 void launch_bprolong(int dim, const BItem* items, int nit, int nblk, const double* xc, double* xf,
                      const int* skip, int sstride, hipStream_t s) {
-  if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
-  if (dim == 2) kb_prolong<2><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
-  else kb_prolong<3><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
+  launch_bprolong_t<double>(dim, items, nit, nblk, xc, xf, skip, sstride, s);
 }
-
 void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const double* kf, double* kc,
                      const int* skip, int sstride, hipStream_t s) {
-  if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
-  if (dim == 2) kb_coarsen<2><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
-  else kb_coarsen<3><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
+  launch_bcoarsen_t<CellD, double>(dim, items, nit, nblk, CellD{kf}, kc, skip, sstride, s);
 }
+
+template <typename TI, typename TO>
+void launch_bmask_copy_t(const BItem* items, int nit, int nblk, const TI* in, TO* out, hipStream_t s) {
+  if (nblk <= 0) return;
+  kb_mask_copy<TI, TO><<<nblk, dim3(TBX, TBY, 1), 0, s>>>(items, nit, in, out);
+}
+template void launch_bmask_copy_t<double, float>(const BItem*, int, int, const double*, float*, hipStream_t);
+template void launch_bmask_copy_t<float, double>(const BItem*, int, int, const float*, double*, hipStream_t);
 
 void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
                        hipStream_t s) {
-  if (nblk <= 0) return;
-  kb_mask_copy<<<nblk, dim3(TBX, TBY, 1), 0, s>>>(items, nit, in, out);
+  launch_bmask_copy_t<double, double>(items, nit, nblk, in, out, s);
 }
+
+template <typename T>
+void launch_bvtail_t(int dim, const BTail* jobs, int njobs, int lds_elems, double omega, const int* skip,
+                     int sstride, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t lds = sizeof(T) * (size_t)lds_elems;
+  if (dim == 2) kb_vtail<2, T><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
+  else kb_vtail<3, T><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
+}
+template void launch_bvtail_t<double>(int, const BTail*, int, int, double, const int*, int, hipStream_t);
+template void launch_bvtail_t<float>(int, const BTail*, int, int, double, const int*, int, hipStream_t);
 
 void launch_bvtail(int dim, const BTail* jobs, int njobs, int lds_elems, double omega,
                    const int* skip, int sstride, hipStream_t s) {
-  if (njobs <= 0) return;
-  const size_t lds = sizeof(double) * (size_t)lds_elems;
-  if (dim == 2) kb_vtail<2><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
-  else kb_vtail<3><<<njobs, TT, lds, s>>>(jobs, omega, skip, sstride);
+  launch_bvtail_t<double>(dim, jobs, njobs, lds_elems, omega, skip, sstride, s);
 }
+
+template <typename CL>
+void launch_bcoarse_build_t(int dim, const BCoarse* jobs, int njobs, bool reg, int* status, const int* skip,
+                            int sstride, hipStream_t s) {
+  if (njobs <= 0) return;
+  if (reg) {
+    if (dim == 2) kb_coarse_build<2, true, CL><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+    else kb_coarse_build<3, true, CL><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+  } else {
+    if (dim == 2) kb_coarse_build<2, false, CL><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+    else kb_coarse_build<3, false, CL><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
+  }
+}
+template void launch_bcoarse_build_t<CellD>(int, const BCoarse*, int, bool, int*, const int*, int, hipStream_t);
+template void launch_bcoarse_build_t<CellF>(int, const BCoarse*, int, bool, int*, const int*, int, hipStream_t);
 
 void launch_bcoarse_build(int dim, const BCoarse* jobs, int njobs, bool reg, int* status,
                           const int* skip, int sstride, hipStream_t s) {
-  if (njobs <= 0) return;
-  if (reg) {
-    if (dim == 2) kb_coarse_build<2, true><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
-    else kb_coarse_build<3, true><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
-  } else {
-    if (dim == 2) kb_coarse_build<2, false><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
-    else kb_coarse_build<3, false><<<njobs, CB_THREADS, 0, s>>>(jobs, status, skip, sstride);
-  }
+  launch_bcoarse_build_t<CellD>(dim, jobs, njobs, reg, status, skip, sstride, s);
 }

@@ -665,8 +665,9 @@ __device__ inline bool vb_skip(const int* skip, int sstride, int design) {
   return skip && skip[(long long)design * sstride] != 0;
 }
 
+template <typename T>
 __global__ __launch_bounds__(VB) void kb_dot(const BItem* __restrict__ items, int nit,
-                                             const double* __restrict__ a, const double* __restrict__ b,
+                                             const T* __restrict__ a, const T* __restrict__ b,
                                              double* __restrict__ part, const int* __restrict__ skip,
                                              int sstride) {
   __shared__ double sh[VB / MGAR_WAVE];
@@ -674,7 +675,7 @@ __global__ __launch_bounds__(VB) void kb_dot(const BItem* __restrict__ items, in
   if (vb_skip(skip, sstride, it.design)) return;
   const long long n = it.g.nn;
   const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
-  const double s = block_sum(i < n ? a[it.off + i] * b[it.off + i] : 0.0, sh);
+  const double s = block_sum(i < n ? (double)a[it.off + i] * (double)b[it.off + i] : 0.0, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -723,8 +724,9 @@ __global__ __launch_bounds__(FB) void kb_cg_init(const BItem* __restrict__ items
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(VB) void kb_p_update(const BItem* __restrict__ items, int nit,
-                                                  const double* __restrict__ z, double* __restrict__ p,
+                                                  const T* __restrict__ z, T* __restrict__ p,
                                                   const BCgState* __restrict__ st) {
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
   const BCgState& s = st[it.design];
@@ -734,28 +736,28 @@ __global__ __launch_bounds__(VB) void kb_p_update(const BItem* __restrict__ item
   if (i >= it.g.nn) return;
   const long long n = it.off + i;
   if (k == 0) p[n] = z[n];
-  else p[n] = z[n] + (s.rz[k & 1] / s.rz[(k - 1) & 1]) * p[n];
+  else p[n] = z[n] + (T)(s.rz[k & 1] / s.rz[(k - 1) & 1]) * p[n];
 }
 
+template <typename T>
 __global__ __launch_bounds__(VB) void kb_cg_update(const BItem* __restrict__ items, int nit,
-                                                   double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ w,
+                                                   T* __restrict__ x, T* __restrict__ r,
+                                                   const T* __restrict__ p, const T* __restrict__ w,
                                                    const BCgState* __restrict__ st,
                                                    double* __restrict__ part) {
   __shared__ double sh[VB / MGAR_WAVE];
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
   const BCgState& s = st[it.design];
   if (s.done) return;
-  const double alpha = s.rz[s.it & 1] / s.pw;
+  const T alpha = (T)(s.rz[s.it & 1] / s.pw);
   const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
   double v = 0.0;
   if (i < it.g.nn) {
     const long long n = it.off + i;
     x[n] += alpha * p[n];
-    const double ri = r[n] - alpha * w[n];
+    const T ri = r[n] - alpha * w[n];
     r[n] = ri;
-    v = ri * ri;
+    v = (double)ri * (double)ri;
   }
   v = block_sum(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
@@ -945,8 +947,9 @@ __global__ void kb_decide(const BItem* __restrict__ items, int nit, MgarDev* md,
   if (acc) { st[d].done = 1; st[d].conv = 1; st[d].it = 0; }
 }
 
+template <typename T>
 __global__ __launch_bounds__(VB) void kb_copy_cells(const BItem* __restrict__ items, int nit,
-                                                    const double* __restrict__ a, double* __restrict__ b,
+                                                    const T* __restrict__ a, T* __restrict__ b,
                                                     const int* __restrict__ skip, int sstride) {
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
   if (vb_skip(skip, sstride, it.design)) return;
@@ -1162,9 +1165,16 @@ void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s)
 
 // ---------------------------------------------------------------- batched launchers
 
+template <typename T>
+void launch_bdot_t(const BItem* items, int nit, int nblk, const T* a, const T* b, double* part,
+                   const int* skip, int sstride, hipStream_t s) {
+  if (nblk > 0) kb_dot<T><<<nblk, VB, 0, s>>>(items, nit, a, b, part, skip, sstride);
+}
+template void launch_bdot_t<float>(const BItem*, int, int, const float*, const float*, double*, const int*,
+                                   int, hipStream_t);
 void launch_bdot(const BItem* items, int nit, int nblk, const double* a, const double* b,
                  double* part, const int* skip, int sstride, hipStream_t s) {
-  if (nblk > 0) kb_dot<<<nblk, VB, 0, s>>>(items, nit, a, b, part, skip, sstride);
+  launch_bdot_t<double>(items, nit, nblk, a, b, part, skip, sstride, s);
 }
 void launch_bfinalize(const BItem* items, int nit, const double* part, int nv, double* out,
                       int ostride, const int* itsel, const int* skip, int sstride, hipStream_t s) {
@@ -1175,13 +1185,27 @@ void launch_bcg_init(const BItem* items, int nit, BCgState* st, const double* pa
                      hipStream_t s) {
   if (nit > 0) kb_cg_init<<<nit, FB, 0, s>>>(items, st, part_qq, part_rr, tol, cg_max, keep_done);
 }
+template <typename T>
+void launch_bp_update_t(const BItem* items, int nit, int nblk, const T* z, T* p, const BCgState* st,
+                        hipStream_t s) {
+  if (nblk > 0) kb_p_update<T><<<nblk, VB, 0, s>>>(items, nit, z, p, st);
+}
+template void launch_bp_update_t<float>(const BItem*, int, int, const float*, float*, const BCgState*,
+                                        hipStream_t);
+template <typename T>
+void launch_bcg_update_t(const BItem* items, int nit, int nblk, T* x, T* r, const T* p, const T* w,
+                         const BCgState* st, double* part, hipStream_t s) {
+  if (nblk > 0) kb_cg_update<T><<<nblk, VB, 0, s>>>(items, nit, x, r, p, w, st, part);
+}
+template void launch_bcg_update_t<float>(const BItem*, int, int, float*, float*, const float*, const float*,
+                                         const BCgState*, double*, hipStream_t);
 void launch_bp_update(const BItem* items, int nit, int nblk, const double* z, double* p,
                       const BCgState* st, hipStream_t s) {
-  if (nblk > 0) kb_p_update<<<nblk, VB, 0, s>>>(items, nit, z, p, st);
+  launch_bp_update_t<double>(items, nit, nblk, z, p, st, s);
 }
 void launch_bcg_update(const BItem* items, int nit, int nblk, double* x, double* r, const double* p,
                        const double* w, const BCgState* st, double* part, hipStream_t s) {
-  if (nblk > 0) kb_cg_update<<<nblk, VB, 0, s>>>(items, nit, x, r, p, w, st, part);
+  launch_bcg_update_t<double>(items, nit, nblk, x, r, p, w, st, part, s);
 }
 void launch_bcg_check(const BItem* items, int nit, BCgState* st, const double* part, double tol,
                       int cg_max, hipStream_t s) {
@@ -1228,7 +1252,14 @@ void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, doub
                     int* path, double* res_out, hipStream_t s) {
   if (nit > 0) kb_decide<<<(nit + 63) / 64, 64, 0, s>>>(items, nit, md, st, eps, keep, path, res_out);
 }
+template <typename T>
+void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, const T* a, T* b, const int* skip,
+                          int sstride, hipStream_t s) {
+  if (nblk > 0) kb_copy_cells<T><<<nblk, VB, 0, s>>>(items, nit, a, b, skip, sstride);
+}
+template void launch_bcopy_cells_t<uint16_t>(const BItem*, int, int, const uint16_t*, uint16_t*, const int*,
+                                             int, hipStream_t);
 void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
                         const int* skip, int sstride, hipStream_t s) {
-  if (nblk > 0) kb_copy_cells<<<nblk, VB, 0, s>>>(items, nit, a, b, skip, sstride);
+  launch_bcopy_cells_t<double>(items, nit, nblk, a, b, skip, sstride, s);
 }

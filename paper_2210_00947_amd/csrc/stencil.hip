@@ -1288,14 +1288,24 @@ constexpr int CB_THREADS = 1024;
 constexpr int CB_MAXN = 1024;
 constexpr int CB_KCAP = 1024;   // cells of a coarsest grid of at most 128 nodes
 
+constexpr int CB_NB = 16;   // pivot block of the blocked elimination
+
 // Coarsest grid: assemble the dense N_c x N_c matrix (identity rows/columns on
-// Dirichlet nodes), then invert it in place by Gauss-Jordan elimination without
-// pivoting (valid for SPD matrices) and symmetrise. One workgroup.
+// Dirichlet nodes), then invert it in place by block Gauss-Jordan elimination
+// without pivoting (valid for SPD matrices: every pivot block is SPD) and
+// symmetrise. One workgroup. Block step with pivot block D = A_kk (rows and
+// columns kb .. kb + kw):
+//   D^-1 by scalar Gauss-Jordan in LDS,
+//   A_kj <- D^-1 A_kj (j != k), A_kk <- D^-1          (P = the new block row, kept in LDS),
+//   A_ij <- A_ij - A_ik P_kj (i, j != k),
+//   A_ik <- -A_ik D^-1 (i != k).
+// Each step reads and writes every entry of A once (the unblocked form does so
+// once per pivot), so the matrix in global memory is swept n / 16 times.
 template <int DIM, typename CL>
 __device__ inline void coarse_build_body(const Geo& g, CL k, double* __restrict__ A,
                                          int* __restrict__ status) {
-  __shared__ double colp[CB_MAXN];
-  __shared__ double rowp[CB_MAXN];
+  __shared__ double P[CB_NB * CB_MAXN];
+  __shared__ double D[CB_NB][CB_NB + 1];
   const int n = (int)g.nn;
   const int t = threadIdx.x;
   for (long long idx = t; idx < (long long)n * n; idx += CB_THREADS) A[idx] = 0.0;
@@ -1323,31 +1333,109 @@ __device__ inline void coarse_build_body(const Geo& g, CL k, double* __restrict_
         }
   }
   __syncthreads();
-  const int tc = t & 31, tr = t >> 5;  // 32 x 32 thread layout for the updates
   int bad = 0;
-  for (int p = 0; p < n; ++p) {
-    for (int idx = t; idx < n; idx += CB_THREADS) {
-      colp[idx] = A[(long long)idx * n + p];
-      rowp[idx] = A[(long long)p * n + idx];
+  const int dr = t / CB_NB, dc = t % CB_NB;   // threads t < CB_NB^2: one entry of D each
+  const int njt = (n + 3) / 4;                 // 4 x 4 tiles of the trailing update
+  for (int kb = 0; kb < n; kb += CB_NB) {
+    const int kw = min(CB_NB, n - kb);
+    // D^-1 (entries past kw: identity, untouched by the steps below)
+    if (t < CB_NB * CB_NB)
+      D[dr][dc] = (dr < kw && dc < kw) ? A[(long long)(kb + dr) * n + kb + dc] : (dr == dc ? 1.0 : 0.0);
+    __syncthreads();
+    for (int p = 0; p < kw; ++p) {
+      double piv = 1.0, rp = 0.0, cp = 0.0, old = 0.0;
+      if (t < CB_NB * CB_NB) {
+        piv = D[p][p];
+        rp = D[p][dc];
+        cp = D[dr][p];
+        old = D[dr][dc];
+      }
+      __syncthreads();
+      if (!(piv > 0.0)) bad = 1;
+      if (t < CB_NB * CB_NB && dr < kw && dc < kw) {
+        const double inv = 1.0 / piv;
+        double v;
+        if (dr == p && dc == p) v = inv;
+        else if (dr == p) v = rp * inv;
+        else if (dc == p) v = -cp * inv;
+        else v = old - cp * rp * inv;
+        D[dr][dc] = v;
+      }
+      __syncthreads();
+    }
+    // P = D^-1 A_k* (block columns k: D^-1), written to LDS and to rows kb.. of A;
+    // column j is read and written by one thread only
+    for (int j = t; j < n; j += CB_THREADS) {
+      if (j >= kb && j < kb + kw) {
+        for (int r = 0; r < kw; ++r) {
+          const double v = D[r][j - kb];
+          P[r * n + j] = v;
+          A[(long long)(kb + r) * n + j] = v;
+        }
+      } else {
+        double a[CB_NB];
+#pragma unroll
+        for (int c = 0; c < CB_NB; ++c) a[c] = (c < kw) ? A[(long long)(kb + c) * n + j] : 0.0;
+        for (int r = 0; r < kw; ++r) {
+          double v = 0.0;
+#pragma unroll
+          for (int c = 0; c < CB_NB; ++c) v += D[r][c] * a[c];
+          P[r * n + j] = v;
+          A[(long long)(kb + r) * n + j] = v;
+        }
+      }
     }
     __syncthreads();
-    const double piv = rowp[p];
-    if (!(piv > 0.0)) bad = 1;
-    const double inv = 1.0 / piv;
-    for (int i = tr; i < n; i += CB_THREADS / 32) {
-      const double ci = colp[i];
-      for (int j = tc; j < n; j += 32) {
-        double v;
-        if (i == p && j == p) v = inv;
-        else if (i == p) v = rowp[j] * inv;
-        else if (j == p) v = -ci * inv;
-        else v = A[(long long)i * n + j] - ci * rowp[j] * inv;
-        A[(long long)i * n + j] = v;
+    // A_ij -= A_ik P_kj for rows and columns outside block k (A_ik not written
+    // in this pass), 4 x 4 tiles per thread
+    for (int q = t; q < njt * njt; q += CB_THREADS) {
+      const int i0 = (q / njt) * 4, j0 = (q % njt) * 4;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int c = 0; c < kw; ++c) {
+        double ci[4], pj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ci[a] = (i0 + a < n) ? A[(long long)(i0 + a) * n + kb + c] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pj[b] = (j0 + b < n) ? P[c * n + j0 + b] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += ci[a] * pj[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = i0 + a;
+        if (i >= n || (i >= kb && i < kb + kw)) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = j0 + b;
+          if (j >= n || (j >= kb && j < kb + kw)) continue;
+          A[(long long)i * n + j] -= acc[a][b];
+        }
+      }
+    }
+    __syncthreads();
+    // A_ik <- -A_ik D^-1 for rows outside block k (one thread per row)
+    for (int i = t; i < n; i += CB_THREADS) {
+      if (i >= kb && i < kb + kw) continue;
+      double a[CB_NB];
+#pragma unroll
+      for (int c = 0; c < CB_NB; ++c) a[c] = (c < kw) ? A[(long long)i * n + kb + c] : 0.0;
+      for (int r = 0; r < kw; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < CB_NB; ++c) v += a[c] * D[c][r];
+        A[(long long)i * n + kb + r] = -v;
       }
     }
     __syncthreads();
   }
   // symmetrise
+  const int tc = t & 31, tr = t >> 5;
   for (int i = tr; i < n; i += CB_THREADS / 32)
     for (int j = tc; j < n; j += 32)
       if (j > i) {
@@ -1366,7 +1454,8 @@ __global__ __launch_bounds__(CB_THREADS) void k_coarse_build(Geo g, CL k, double
 
 // Register-resident variant for n <= 128: thread (tr, tc) of a 32 x 32 layout
 // owns entries (tr + 32a, tc + 32b), a, b < 4, for the whole elimination; only
-// the pivot row and column pass through LDS. Same arithmetic as above.
+// the pivot row and column pass through LDS. Unblocked (scalar) Gauss-Jordan:
+// one pivot per step.
 template <int DIM, typename CL>
 __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restrict__ A,
                                              int* __restrict__ status) {
@@ -1425,7 +1514,7 @@ __device__ inline void coarse_build_reg_body(const Geo& g, CL k, double* __restr
     }
   // Elimination: the slot pa of the pivot is a compile-time index (outer loop
   // unrolled), so the register tile is never indexed at run time. Entries past
-  // n are 0 and stay 0. Same arithmetic per entry as k_coarse_build. Step p
+  // n are 0 and stay 0. Step p
   // publishes its pivot row and column in buffer p & 1: the barrier of step
   // p + 1 orders the reads of step p before the writes of step p + 2, so one
   // barrier per step suffices.

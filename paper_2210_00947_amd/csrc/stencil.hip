@@ -1395,12 +1395,16 @@ __device__ inline void coarse_build_body(const Geo& g, CL k, double* __restrict_
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-      for (int c = 0; c < kw; ++c) {
+      // unrolled by 2 so that two columns' loads of a tile are in flight
+      // together (entries past kw contribute 0)
+#pragma unroll 2
+      for (int c = 0; c < CB_NB; ++c) {
         double ci[4], pj[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ci[a] = (i0 + a < n) ? A[(long long)(i0 + a) * n + kb + c] : 0.0;
+        for (int a = 0; a < 4; ++a)
+          ci[a] = (c < kw && i0 + a < n) ? A[(long long)(i0 + a) * n + kb + c] : 0.0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) pj[b] = (j0 + b < n) ? P[c * n + j0 + b] : 0.0;
+        for (int b = 0; b < 4; ++b) pj[b] = (c < kw && j0 + b < n) ? P[c * n + j0 + b] : 0.0;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll

@@ -144,6 +144,24 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// This thread's share of a partial-sum vector: p[t] + p[t + nt] + ... in
+// that order (starting from +0.0), with the first four loads issued together
+// so that a short vector costs one memory round trip. Terms past n add +0.0,
+// which leaves the sum bitwise unchanged.
+__device__ inline double thread_partials(const double* __restrict__ p, int n, int t, int nt) {
+  double a[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = t + u * nt;
+    a[u] = i < n ? p[i] : 0.0;
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v += a[u];
+  for (int i = t + 4 * nt; i < n; i += nt) v += p[i];
+  return v;
+}
+
 // Deterministic block sum; result valid in every thread. `sh` needs
 // blockDim/64 doubles of LDS. Contains __syncthreads (call from all threads).
 __device__ inline double block_sum(double v, double* sh) {

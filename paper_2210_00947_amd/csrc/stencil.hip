@@ -564,7 +564,6 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     Geo g, int TXW, int TYH, int ntx, int nty, int KZ, const T* __restrict__ x, CL k, CL kref,
     const T* __restrict__ b, T* __restrict__ out, T omega, double* __restrict__ part,
     const int* __restrict__ done, unsigned* __restrict__ cnt, double* __restrict__ rout, PFuse fu) {
-  if (done && *done) return;
   using E = typename CL::E;
   constexpr bool PU = (MODE == SM_PAPPLY_DOT);   // x holds z; staged value z + beta p_old
   constexpr bool J0R = (MODE == SM_J0RESID);     // x holds b; staged value w b / diag
@@ -579,45 +578,35 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   __shared__ T Xs[2][XCAP2];
   __shared__ T Cs[2][CCAP2];
   __shared__ double sh[ZT / MGAR_WAVE];
-  // fused stopping test of the previous iteration (same test as k_cg_check):
-  // every block sums the ||r||^2 partials in the same order and takes the same
-  // decision; the iteration count comes from st->itn, which no block of this
-  // kernel writes
-  if (J0R && fu.chk) {
-    CgState* st = fu.st;
-    if (st->done) return;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < fu.nrz; i += ZT) v += fu.rzp[i];
-    const double rr = block_sum(v, sh);
-    const int itn = st->itn;
-    const bool conv = sqrt(rr) <= fu.tol * sqrt(st->qq);
-    const bool stop = conv || itn >= fu.cg_max;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->it = itn;
-      st->rr = rr;
-      if (stop) {
-        st->done = 1;
-        st->converged = conv ? 1 : 0;
-        st->iters = itn;
-      }
+  // The scalars of the fused steps (stopping test of the previous iteration,
+  // direction update) are read in one round with the done flag, and the raw
+  // loads of the first planes go out before the block reduction that needs
+  // them: a block's first plane loads do not wait behind a chain of dependent
+  // scalar reads.
+  const bool chk = J0R && fu.chk;
+  int dn = done ? *done : 0;
+  double rzv = 0.0;   // this thread's share of the r.z (PU) or ||r||^2 (chk) partials
+  int sit = 0;
+  double rzh0 = 0.0, rzh1 = 0.0, sqq = 0.0;
+  if (PU || chk) {
+    rzv = thread_partials(fu.rzp, fu.nrz, threadIdx.x, ZT);
+    if (PU) {
+      sit = fu.st->it;
+      rzh0 = fu.st->rz[0];
+      rzh1 = fu.st->rz[1];
+    } else {
+      dn |= fu.st->done;
+      sit = fu.st->itn;
+      sqq = fu.st->qq;
     }
-    if (stop) return;
-    __syncthreads();   // sh is reused below
   }
-  // direction update: beta from the r.z partials (every block sums them in the
-  // same order, so all hold the same value) and the stored r.z history
+  if (dn) return;
   T beta = T(0);
   const T* pold = nullptr;
   T* pnew = nullptr;
   if (PU) {
-    const int it = fu.st->it;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < fu.nrz; i += ZT) v += fu.rzp[i];
-    const double rz = block_sum(v, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) fu.st->rz[it & 1] = rz;
-    beta = (T)((it == 0) ? 0.0 : rz / fu.st->rz[(it - 1) & 1]);
-    pold = reinterpret_cast<const T*>(fu.pbuf[(it + 1) & 1]);
-    pnew = reinterpret_cast<T*>(fu.pbuf[it & 1]);
+    pold = reinterpret_cast<const T*>(fu.pbuf[(sit + 1) & 1]);
+    pnew = reinterpret_cast<T*>(fu.pbuf[sit & 1]);
   }
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int nxy = ntx * nty;
@@ -668,26 +657,30 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
 #define ZP(so, p) (XF ? zbload<T>(rp, zplane((so), (p), g.nnz, plb)) : T(0))
 #define ZFORM(u, v) (PU ? (u) + beta * (v) : J0R ? omega * (u) / fmax((v), TMIN) : (u))
   constexpr T TMIN = std::numeric_limits<T>::min();
-#define ZXP(so, p) (XF ? ZFORM(ZX(so, p), ZP(so, p)) : ZX(so, p))
   constexpr int ZQP = XF ? ZD : 1;
   T qx0[ZD], qx1[ZD], qx2[ZD], qb0[ZD], qb1[ZD];
   T qp0[ZQP], qp1[ZQP], qp2[ZQP];
   E qc0[ZD], qc1[ZD], qr0[ZD], qr1[ZD];
   T W0[4][3], W1[4][3], W2[4][3], V0[3][2], V1[3][2];
 
-  {
-    const unsigned c0 = zplane(cs0, k0 - 1, g.nz, cplb), c1 = zplane(cs1, k0 - 1, g.nz, cplb);
-    Xs[0][tid] = ZXP(xs0, k0 - 1);
-    Xs[1][tid] = ZXP(xs0, k0);
-    Xs[0][tid + ZT] = ZXP(xs1, k0 - 1);
-    Xs[1][tid + ZT] = ZXP(xs1, k0);
-    Xs[0][tid + 2 * ZT] = ZXP(xs2, k0 - 1);
-    Xs[1][tid + 2 * ZT] = ZXP(xs2, k0);
-    const E e0 = zbload<E>(rk, c0), e1 = zbload<E>(rk, c1);
-    const E r0 = DK ? zbload<E>(rkr, c0) : E(0), r1 = DK ? zbload<E>(rkr, c1) : E(0);
-    Cs[0][tid] = ZCM(e0, r0, c0 < ZOOB);
-    Cs[0][tid + ZT] = ZCM(e1, r1, c1 < ZOOB);
+  // raw loads of planes k0 - 1 and k0 (x, second input, first cell plane)
+  // and of the queue
+  T px[3][2], pp[3][2];
+  E pe[2], pr[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    px[0][a] = ZX(xs0, k0 - 1 + a);
+    px[1][a] = ZX(xs1, k0 - 1 + a);
+    px[2][a] = ZX(xs2, k0 - 1 + a);
+    pp[0][a] = ZP(xs0, k0 - 1 + a);
+    pp[1][a] = ZP(xs1, k0 - 1 + a);
+    pp[2][a] = ZP(xs2, k0 - 1 + a);
   }
+  const unsigned pc0 = zplane(cs0, k0 - 1, g.nz, cplb), pc1 = zplane(cs1, k0 - 1, g.nz, cplb);
+  pe[0] = zbload<E>(rk, pc0);
+  pe[1] = zbload<E>(rk, pc1);
+  pr[0] = DK ? zbload<E>(rkr, pc0) : E(0);
+  pr[1] = DK ? zbload<E>(rkr, pc1) : E(0);
 #pragma unroll
   for (int d = 0; d < ZD; ++d) {
     qx0[d] = ZX(xs0, k0 + 1 + d);
@@ -706,6 +699,41 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
     qb0[d] = ZB(own0, k0 + d);
     qb1[d] = ZB(own1, k0 + d);
   }
+  // fused stopping test of the previous iteration (same test as k_cg_check):
+  // every block sums the ||r||^2 partials in the same order and takes the same
+  // decision; the iteration count comes from st->itn, which no block of this
+  // kernel writes
+  if (chk) {
+    CgState* st = fu.st;
+    const double rr = block_sum(rzv, sh);
+    const bool conv = sqrt(rr) <= fu.tol * sqrt(sqq);
+    const bool stop = conv || sit >= fu.cg_max;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->it = sit;
+      st->rr = rr;
+      if (stop) {
+        st->done = 1;
+        st->converged = conv ? 1 : 0;
+        st->iters = sit;
+      }
+    }
+    if (stop) return;
+  }
+  // direction update: beta from the r.z partials (every block sums them in the
+  // same order, so all hold the same value) and the stored r.z history
+  if (PU) {
+    const double rz = block_sum(rzv, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) fu.st->rz[sit & 1] = rz;
+    beta = (T)((sit == 0) ? 0.0 : rz / ((sit - 1) & 1 ? rzh1 : rzh0));
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    Xs[a][tid] = ZFORM(px[0][a], pp[0][a]);
+    Xs[a][tid + ZT] = ZFORM(px[1][a], pp[1][a]);
+    Xs[a][tid + 2 * ZT] = ZFORM(px[2][a], pp[2][a]);
+  }
+  Cs[0][tid] = ZCM(pe[0], pr[0], pc0 < ZOOB);
+  Cs[0][tid + ZT] = ZCM(pe[1], pr[1], pc1 < ZOOB);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -810,7 +838,6 @@ __global__ __launch_bounds__(ZT) void k_stencil_z2(
   if (kk < k1) ZSTEP2(W1, W2, W0, V0, V1, 0)
 #undef ZSTEP2
 #undef ZNODE
-#undef ZXP
 #undef ZFORM
 #undef ZP
 #undef ZX

@@ -30,9 +30,7 @@ __global__ __launch_bounds__(VB) void k_dot(const TA* __restrict__ a,
 }
 
 __device__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-  return block_sum(s, sh);
+  return block_sum(thread_partials(part, n, threadIdx.x, blockDim.x), sh);
 }
 
 __global__ __launch_bounds__(FB) void k_finalize(const double* __restrict__ part, int n,
@@ -99,17 +97,20 @@ template <typename T>
 __global__ __launch_bounds__(VB) void k_p_update(const T* __restrict__ z, T* __restrict__ p,
                                                  long long n, CgState* __restrict__ st,
                                                  const double* __restrict__ rzp, int np) {
-  if (st->done) return;
   __shared__ double sh[VB / MGAR_WAVE];
-  const int it = st->it;
+  // the state words and this thread's partials are read in one round
+  const int dn = st->done, it = st->it;
+  const double h0 = st->rz[0], h1 = st->rz[1];
+  const double v = rzp ? thread_partials(rzp, np, threadIdx.x, VB) : 0.0;
+  if (dn) return;
   double rz = 0.0;
   if (rzp) {
-    rz = sum_partials(rzp, np, sh);
+    rz = block_sum(v, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[it & 1] = rz;
   } else {
-    rz = st->rz[it & 1];
+    rz = (it & 1) ? h1 : h0;
   }
-  const T beta = (T)((it == 0) ? 0.0 : rz / st->rz[(it - 1) & 1]);
+  const T beta = (T)((it == 0) ? 0.0 : rz / (((it - 1) & 1) ? h1 : h0));
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
     p[i] = (it == 0) ? z[i] : z[i] + beta * p[i];
 }
@@ -133,27 +134,32 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
                                                   unsigned* __restrict__ cnt, double tol,
                                                   int cg_max, const double* __restrict__ pwp,
                                                   int npw, const T* __restrict__ p_odd) {
-  if (st->done) return;
-  const int it = st->it;
+  // the state words and this thread's partials are read in one round
+  const int dn = st->done, it = st->it, flushed = st->flushed;
+  const double rz0 = st->rz[0], rz1 = st->rz[1], pws = st->pw, pwh0 = st->pwh[0],
+               pwh1 = st->pwh[1], qq = st->qq;
+  const double pwv = pwp ? thread_partials(pwp, npw, threadIdx.x, VB) : 0.0;
+  if (dn) return;
   const T* __restrict__ p = (p_odd && (it & 1)) ? p_odd : p_even;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->itn = it + 1;   // for a fused stopping test
   __shared__ double sh[VB / MGAR_WAVE];
   double pw;
   if (pwp) {
-    pw = sum_partials(pwp, npw, sh);
+    pw = block_sum(pwv, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->pw = pw;
   } else {
-    pw = st->pw;
+    pw = pws;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st->pwh[it & 1] = pw;
-  const T alpha = (T)(st->rz[it & 1] / pw);
+  const T alpha = (T)(((it & 1) ? rz1 : rz0) / pw);
   double s = 0.0;
   if (p_odd) {
     const bool odd = it & 1;
     // the pending update of the previous (even) iteration
     // (left out when k_cg_flush has already applied it)
-    const T alpha0 = (odd && st->flushed != it - 1) ? (T)(st->rz[(it - 1) & 1] / st->pwh[(it - 1) & 1])
-                                                    : T(0);
+    const T alpha0 = (odd && flushed != it - 1)
+                         ? (T)((((it - 1) & 1) ? rz1 : rz0) / (((it - 1) & 1) ? pwh1 : pwh0))
+                         : T(0);
     for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
       if (odd) x[i] = (x[i] + alpha0 * p_even[i]) + alpha * p_odd[i];
       const T ri = r[i] - alpha * w[i];
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(VB) void k_cg_update(T* __restrict__ x, T* __restri
   if (grid_reduce(s, blockIdx.x, gridDim.x, part, cnt, nullptr, sh, &rr) && threadIdx.x == 0) {
     st->rr = rr;
     st->it = it + 1;
-    if (sqrt(rr) <= tol * sqrt(st->qq)) {
+    if (sqrt(rr) <= tol * sqrt(qq)) {
       st->done = 1; st->converged = 1; st->iters = it + 1;
     } else if (it + 1 >= cg_max) {
       st->done = 1; st->converged = 0; st->iters = it + 1;

@@ -259,3 +259,27 @@ def net_init(c1: int, c2: int, seed: int = 0) -> np.ndarray:
         parts.append(rng.uniform(-bound, bound, co * ci * 27))
         parts.append(np.zeros(co))
     return np.concatenate(parts).astype(np.float32)
+
+
+def unet_init(C, seed: int = 0) -> np.ndarray:
+    """Initial parameters of the element-grid seed U-Net with channels C per
+    level (FP32): He-uniform weights per layer (bound sqrt(6 / (k^3 ci))), zero
+    biases, in the library's flat layout: per layer [co][ci][k][k][k] weights
+    then co biases, layers in the order encoder (level 0 .. L-1, two 3x3x3
+    convolutions each; 3 input channels), decoder (level L-2 .. 0, two each;
+    the first takes the upsampled C[l+1] channels followed by the C[l] skip
+    channels), 1x1x1 head to one channel."""
+    L = len(C)
+    shapes = []
+    for l in range(L):
+        shapes += [(C[l], 3 if l == 0 else C[l - 1], 3), (C[l], C[l], 3)]
+    for l in range(L - 2, -1, -1):
+        shapes += [(C[l], C[l + 1] + C[l], 3), (C[l], C[l], 3)]
+    shapes.append((1, C[0], 1))
+    rng = np.random.default_rng(SEED_BASE + 9000 + seed)
+    parts = []
+    for co, ci, k in shapes:
+        bound = np.sqrt(6.0 / (k ** 3 * ci))
+        parts.append(rng.uniform(-bound, bound, co * ci * k ** 3))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

@@ -255,33 +255,42 @@ int mgar_residual_noalloc(const mgar_params* p, const double* xphys, const doubl
                           double* relres, void* stream);
 
 /* ---- Learned initial guess (3D). -------------------------------------------
- * A small convolutional U-Net on the coarse cell grid of blocks of pool^3
- * finest elements (pool even; every axis a multiple of 2*pool): input = mean
- * physical density and fraction of Dirichlet corner nodes per block; two 3x3x3
- * convolutions with ReLU (c1 channels), 2x average pooling, two convolutions
- * (c2), 2x nearest upsampling, concatenation with the full-resolution features,
- * a convolution (c1) and a linear convolution to one output u per block.
- * Parameters: one FP32 vector, per layer the weights [co][ci][dz][dy][dx]
- * then the biases, layers in the order above (mgar_net_sizes gives the count
- * and the coarse grid D, H, W). Created with zero parameters; the caller
- * installs initial values (mgar_net_set_params, which also resets Adam).
- * Prediction on the finest nodes: scale * trilinear interpolation of u
- * between block centres (finest nodes pool*i + pool/2), clamped at the
- * outermost centres, 0 on Dirichlet nodes. Training pair (xphys, T, scale):
- * target y = T at the block centres / scale, loss = mean (u - y)^2, one Adam
- * step (0.9, 0.999, 1e-8) with learning rate lr. xphys: E-vector, T: N-vector
- * (device, FP64); theta, grad, u: host FP32 arrays of nparams / D*H*W values.
- * Every call enqueues on the stream given at creation; mgar_net_train_step
- * waits for it only when loss is non-null, mgar_net_destroy always. */
+ * A convolutional U-Net on the element grid with `levels` levels of
+ * channels[0..levels-1] channels (each a multiple of 16, at most 128; every
+ * axis a multiple of 2^(levels-1)). Input: three channels per element
+ * (physical density, fraction of the element's 8 corner nodes that are
+ * Dirichlet nodes, heat source divided by its max-norm: 1 until
+ * mgar_net_set_source). Encoder: per level two 3x3x3 convolutions with ReLU
+ * (zero padding), 2x average pooling between levels. Decoder from level
+ * levels-2 down to 0: trilinear 2x upsampling of cell-centred values
+ * (clamped at the boundary), concatenation [upsampled, encoder output of the
+ * level], two 3x3x3 convolutions with ReLU. Head: 1x1x1 convolution to one
+ * output u per element. Parameters: one FP32 vector, per layer the weights
+ * [co][ci][k][k][k] then the co biases, layers in the order encoder (level 0
+ * first), decoder (level levels-2 first), head (mgar_net_sizes gives the
+ * count). Created with zero parameters; the caller installs initial values
+ * (mgar_net_set_params, which also resets Adam). Activations and their
+ * gradients are stored in BF16, convolutions run on the matrix cores with
+ * FP32 sums; weight gradients and the loss are summed in FP64.
+ * Prediction on the finest nodes: scale * mean of u over the elements that
+ * touch the node, 0 on Dirichlet nodes. Training pair (xphys, T, scale): loss
+ * = mean over the free nodes of (prediction/scale - T/scale)^2, one Adam step
+ * (0.9, 0.999, 1e-8) with learning rate lr. xphys, qe: E-vectors, T: N-vector
+ * (device, FP64); theta, u: host FP32 arrays of nparams / E values; grad:
+ * host FP64 array of nparams values. Every call enqueues on the stream given
+ * at creation; mgar_net_train_step waits for it only when loss is non-null,
+ * mgar_net_set_source, mgar_net_set_params, mgar_net_get_params, mgar_net_grad
+ * and mgar_net_destroy always. */
 typedef struct mgar_net mgar_net;
-int mgar_net_create(const mgar_params* p, int pool, int c1, int c2, void* stream, mgar_net** out);
+int mgar_net_create(const mgar_params* p, int levels, const int* channels, void* stream, mgar_net** out);
 void mgar_net_destroy(mgar_net* n);
-int mgar_net_sizes(const mgar_net* n, long long* nparams, int* cells);
+int mgar_net_sizes(const mgar_net* n, long long* nparams);
+int mgar_net_set_source(mgar_net* n, const double* qe);
 int mgar_net_set_params(mgar_net* n, const float* theta);
 int mgar_net_get_params(const mgar_net* n, float* theta);
 int mgar_net_infer(mgar_net* n, const double* xphys, double scale, double* T_seed);
 int mgar_net_output(const mgar_net* n, float* u);
-int mgar_net_grad(mgar_net* n, const double* xphys, const double* T, double scale, float* grad, double* loss);
+int mgar_net_grad(mgar_net* n, const double* xphys, const double* T, double scale, double* grad, double* loss);
 int mgar_net_train_step(mgar_net* n, const double* xphys, const double* T, double scale, double lr,
                         double* loss);
 

@@ -15,8 +15,7 @@ solvers  MGCG (PCG preconditioned by one V-cycle) and MGAR reanalysis
          (Eq 12-21, Eq 28, Sec. 3.1); exact sparse direct reference
 topopt   density filter (Eq 6-8), compliance and sensitivities (Eq 5, 9-11),
          optimality-criteria update, and the optimisation loop (Fig. 5 flow)
-nets     NumPy reference for the block-grid seed network
-unet     NumPy reference for the element-grid seed U-Net (4 levels), with
+unet     NumPy reference for the learned-seed U-Net on the element grid, with
          optional BF16 rounding at the points where the GPU stores BF16
 
 Every function cites the passage of the paper it follows. Readings of the

@@ -1,20 +1,31 @@
-// Learned initial guess: a small 3D convolutional U-Net on a coarse cell grid
-// (blocks of f^3 finest elements), trained online on the (density,
-// temperature) pairs of the optimisation loop, by the kernels of this file:
-// forward, backward and Adam. FP32 storage; the 27 taps of one source
-// channel (and, for weight gradients, a thread's few voxels) are summed in
-// FP32, every longer sum in FP64.
+// Learned initial guess: a 3D convolutional U-Net on the element grid, trained
+// online on the (density, temperature) pairs of the optimisation loop by the
+// kernels of this file (forward, backward, Adam).
 //
-// Network: in(2) -> conv+ReLU (C1) -> conv+ReLU (C1) = skip -> 2x avg pool ->
-// conv+ReLU (C2) -> conv+ReLU (C2) -> 2x nearest up -> concat [up, skip] ->
-// conv+ReLU (C1) -> conv (1) = u. Convolutions: 3x3x3 cross-correlation, zero
-// padding 1, weights [co][ci][dz][dy][dx] then biases per layer in one flat
-// FP32 vector (layers in the order above). Activations are [channel][z][y][x].
-// Input channels: mean physical density of the block; fraction of the
-// block's 8 corner nodes that are Dirichlet nodes. Prediction on the finest
-// nodes: scale * trilinear interpolation of u between coarse cell centres
-// (finest nodes f*i + f/2), clamped at the outermost centres, Dirichlet 0.
-// Training target: y = T at the centre nodes / scale; loss = mean (u - y)^2.
+// Network, L levels with C[l] channels (level l has n / 2^l elements per
+// axis): input (3 channels per element: physical density, fraction of the
+// element's Dirichlet corner nodes, heat source over its max-norm) ->
+// per level two 3x3x3 convolutions with ReLU, 2x average pooling between
+// levels -> decoder from level L-2 to 0: trilinear 2x upsampling
+// (cell-centred), concatenation [upsampled, skip of the level], two
+// convolutions with ReLU -> 1x1x1 head to one output u per element. Node
+// prediction: scale * mean of u over the elements touching the node, 0 on
+// Dirichlet nodes. Loss over the free nodes: mean (prediction/scale -
+// T/scale)^2.
+//
+// Storage and arithmetic. Parameters, Adam moments and the head are FP32.
+// Activations and their gradients are stored channels-last in BF16 (round to
+// nearest even from FP32). The 3x3x3 convolutions are implicit GEMMs on the
+// matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32 sums): output
+// voxels x output channels, K = 27 taps x input channels; a 16 x 4 x 4 voxel
+// tile and its halo are staged in LDS per chunk of 16 input channels (one
+// chunk of 4 for the 3 input channels, four taps per K step). The data
+// gradient is the same kernel with the taps mirrored and the weights
+// transposed; it stages the output gradient masked by the ReLU of the layer's
+// stored output. The weight gradient is a GEMM over voxels on the matrix
+// cores with FP32 block partials summed over blocks in a fixed order in
+// FP64. Pooling, upsampling and their adjoints sum in FP32. Every long sum
+// has a fixed order, so results do not depend on scheduling.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -38,443 +49,977 @@ namespace {
 #define NLAUNCH() NHIP(hipGetLastError())
 
 constexpr int NB = 256;
-constexpr int NBC = 64;   // voxels per block of the forward and data-gradient convolutions
+constexpr int MAXL = 6;
+constexpr int TX = 16, TY = 4, TZ = 4;                 // voxel tile of the convolutions
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;   // halo tile
+constexpr int HV = HX * HY * HZ;                       // 648 halo voxels
 
-__device__ inline int cidx(int c, int z, int y, int x, int D, int H, int W) {
-  return ((c * D + z) * H + y) * W + x;
+typedef unsigned short u16;
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+
+__device__ inline u16 f2bf(float f) {   // round to nearest even (finite values)
+  unsigned u = __builtin_bit_cast(unsigned, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
 }
+__device__ inline float bf2f(u16 b) { return __builtin_bit_cast(float, (unsigned)b << 16); }
+__device__ inline bool bfpos(u16 b) { return !(b & 0x8000u) && (b & 0x7FFFu); }
 
-// ---------------------------------------------------------------- grid <-> net
+inline int nblk(long long n) { return (int)std::min<long long>((n + NB - 1) / NB, 65535LL * 16); }
 
-__global__ __launch_bounds__(NB) void k_net_input(Geo g, const double* __restrict__ xphys, int f, int D,
-                                                  int H, int W, float* __restrict__ in) {
-  const int v = blockIdx.x * NB + threadIdx.x;
-  const int V = D * H * W;
-  if (v >= V) return;
-  const int i = v % W, j = (v / W) % H, k = v / (W * H);
-  double s = 0.0;
-  for (int c = 0; c < f; ++c)
-    for (int b = 0; b < f; ++b)
-      for (int a = 0; a < f; ++a) s += xphys[geo_elem(g, f * i + a, f * j + b, f * k + c)];
+// ---------------------------------------------------------------- input and output on the grids
+
+// Input channels of element e: density, fraction of Dirichlet corners, source.
+__global__ __launch_bounds__(NB) void k_net_input(Geo g, const double* __restrict__ xphys,
+                                                  const float* __restrict__ src, u16* __restrict__ in) {
+  const long long e = blockIdx.x * (long long)NB + threadIdx.x;
+  if (e >= g.ne) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long long)g.nx * g.ny));
   int cnt = 0;
-  for (int c = 0; c < 8; ++c)
-    cnt += geo_fixed(g, f * (i + (c & 1)), f * (j + ((c >> 1) & 1)), f * (k + ((c >> 2) & 1))) ? 1 : 0;
-  in[v] = (float)(s / (double)(f * f * f));
-  in[V + v] = (float)(cnt / 8.0);
+  for (int c = 0; c < 8; ++c) cnt += geo_fixed(g, i + (c & 1), j + ((c >> 1) & 1), k + (c >> 2)) ? 1 : 0;
+  const u64 v = (u64)f2bf((float)xphys[e]) | ((u64)f2bf((float)cnt / 8.0f) << 16) |
+                ((u64)f2bf(src[e]) << 32);
+  reinterpret_cast<u64*>(in)[e] = v;
 }
 
-__global__ __launch_bounds__(NB) void k_net_target(Geo g, const double* __restrict__ T, int f, int D,
-                                                   int H, int W, double inv_scale, float* __restrict__ y) {
-  const int v = blockIdx.x * NB + threadIdx.x;
-  if (v >= D * H * W) return;
-  const int i = v % W, j = (v / W) % H, k = v / (W * H);
-  const int h = f / 2;
-  y[v] = (float)(T[geo_node(g, f * i + h, f * j + h, f * k + h)] * inv_scale);
+// Sum of u over the elements touching node n, corners in the order c = 0..7
+// (c = bx + 2 by + 4 bz, element (i - bx, j - by, k - bz)); cnt returns their number.
+__device__ inline double node_sum(const Geo& g, const float* __restrict__ u, int i, int j, int k, int& cnt) {
+  double s = 0.0;
+  cnt = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int ex = i - (c & 1), ey = j - ((c >> 1) & 1), ez = k - (c >> 2);
+    if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx || ey >= g.ny || ez >= g.nz) continue;
+    s += (double)u[geo_elem(g, ex, ey, ez)];
+    ++cnt;
+  }
+  return s;
 }
 
-__device__ inline void axis_w(int n, int f, int ncell, int& i0, int& i1, double& w) {
-  double p = ((double)n - 0.5 * f) / (double)f;
-  p = fmin(fmax(p, 0.0), (double)(ncell - 1));
-  i0 = min((int)floor(p), ncell - 1);
-  i1 = min(i0 + 1, ncell - 1);
-  w = p - (double)i0;
-}
-
-__global__ __launch_bounds__(NB) void k_net_to_nodes(Geo g, const float* __restrict__ u, int f, int D,
-                                                     int H, int W, double scale, double* __restrict__ T) {
+__global__ __launch_bounds__(NB) void k_to_nodes(Geo g, const float* __restrict__ u, double scale,
+                                                 double* __restrict__ T) {
   const long long n = blockIdx.x * (long long)NB + threadIdx.x;
   if (n >= g.nn) return;
-  const int i = (int)(n % g.nnx);
-  const long long r = n / g.nnx;
-  const int j = (int)(r % g.nny), k = (int)(r / g.nny);
-  if (geo_fixed(g, i, j, k)) {
-    T[n] = 0.0;
-    return;
-  }
-  int x0, x1, y0, y1, z0, z1;
-  double wx, wy, wz;
-  axis_w(i, f, W, x0, x1, wx);
-  axis_w(j, f, H, y0, y1, wy);
-  axis_w(k, f, D, z0, z1, wz);
-  auto U = [&](int z, int y, int x) { return (double)u[(z * H + y) * W + x]; };
-  const double s = (1 - wz) * ((1 - wy) * ((1 - wx) * U(z0, y0, x0) + wx * U(z0, y0, x1)) +
-                               wy * ((1 - wx) * U(z0, y1, x0) + wx * U(z0, y1, x1))) +
-                   wz * ((1 - wy) * ((1 - wx) * U(z1, y0, x0) + wx * U(z1, y0, x1)) +
-                         wy * ((1 - wx) * U(z1, y1, x0) + wx * U(z1, y1, x1)));
-  T[n] = scale * s;
+  const int i = (int)(n % g.nnx), j = (int)((n / g.nnx) % g.nny), k = (int)(n / ((long long)g.nnx * g.nny));
+  int cnt;
+  const double s = node_sum(g, u, i, j, k, cnt);
+  T[n] = geo_fixed(g, i, j, k) ? 0.0 : scale * s / (double)cnt;
 }
 
-// ---------------------------------------------------------------- layers
-
-// Forward and data-gradient convolutions share one kernel: dst[d][v] =
-// bias[d] + sum_s sum_taps wt(d, s, t) src[s][v + sgn (t - 1)], with
-//   forward:        src = in,   d = co, s = ci, wt = w[co][ci][t],      sgn = +1;
-//   data gradient:  src = gout, d = ci, s = co, wt = w[co][ci][t],      sgn = -1
-// (zero padding; the bias only in the forward, optional ReLU). One thread per
-// voxel and group of CT destination channels (blockIdx.y); the 27 taps of a
-// source channel are summed in FP32, the source channels in FP64. Taps
-// outside the grid load a clamped neighbour weighted 0 (no branch between the
-// loads).
-constexpr int CT = 4;
-
-template <bool FWD, bool RELU>
-__global__ __launch_bounds__(NBC) void k_conv(const float* __restrict__ src, int Cs,
-                                              const float* __restrict__ w, const float* __restrict__ bias,
-                                              float* __restrict__ dst, int Cd, int D, int H, int W) {
-  const int V = D * H * W;
-  const int v = blockIdx.x * NBC + threadIdx.x;
-  if (v >= V) return;
-  const int c0 = blockIdx.y * CT;
-  const int x = v % W, y = (v / W) % H, z = v / (W * H);
-  constexpr int sg = FWD ? 1 : -1;
-  double s[CT];
-#pragma unroll
-  for (int c = 0; c < CT; ++c) s[c] = FWD ? (double)bias[min(c0 + c, Cd - 1)] : 0.0;
-  for (int sc = 0; sc < Cs; ++sc) {
-    float xin[27];
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const int zz = z + sg * (dz - 1), yy = y + sg * (dy - 1), xx = x + sg * (dx - 1);
-          const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-          const float val = src[cidx(sc, min(max(zz, 0), D - 1), min(max(yy, 0), H - 1), min(max(xx, 0), W - 1),
-                                     D, H, W)];
-          xin[(dz * 3 + dy) * 3 + dx] = val * (ok ? 1.0f : 0.0f);
-        }
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int d = min(c0 + c, Cd - 1);
-      const float* wp = w + (FWD ? (d * Cs + sc) : (sc * Cd + d)) * 27;
-      float t = 0.0f;
-#pragma unroll
-      for (int q = 0; q < 27; ++q) t += wp[q] * xin[q];
-      s[c] += (double)t;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < CT; ++c) {
-    if (c0 + c >= Cd) break;
-    const float f = (float)s[c];
-    dst[(c0 + c) * V + v] = RELU ? fmaxf(f, 0.0f) : f;
-  }
-}
-
-// gw[co][ci][t] = sum_v gout[co][v] in[ci][v + t - 1]; gb[co] = sum_v gout[co][v],
-// in two stages. Block (ci, group of WCT output channels, slab s) stages input
-// channel ci over its slab (wz planes x hy rows x all W columns) plus a one-voxel
-// zero halo in LDS, so the 27 taps of a voxel are plain LDS reads shared by the
-// WCT channels. Each thread sums the products of its voxels (at most a few
-// dozen) in FP32; from there on the sums are FP64, in a fixed order (see the
-// block sums below), and part holds 28 sums (27 taps, then the bias term) per
-// (co, ci, s). k_conv_bwd_weight_sum adds the
-// slabs in order.
-constexpr int WCT = 2;          // output channels per block
-constexpr int WLDS = 12288;     // floats of the staged slab (48 KiB)
-
-// Slab shape for a D x H x W grid and a layer of ci -> co channels: wz planes
-// (at most 8; thinner while the launch would have fewer than 512 blocks, down
-// to 2) and hy rows, whose haloed tile fits WLDS floats. Returns the number of
-// slabs, or 0 if even a 1 x 1 slab does not fit (W too large).
-int weight_slabs(int D, int H, int W, int ci, int co, int* wz, int* hy) {
-  const long long cg = (co + WCT - 1) / WCT;
-  int z = std::min(D, 8), y = H;
-  auto slabs = [&]() { return (long long)((D + z - 1) / z) * ((H + y - 1) / y); };
-  while (z > 2 && ci * cg * slabs() < 512) z = (z + 1) / 2;
-  while ((long long)(z + 2) * (y + 2) * (W + 2) > WLDS) {
-    if (z > 1) z = (z + 1) / 2;
-    else if (y > 1) y = (y + 1) / 2;
-    else return 0;
-  }
-  *wz = z;
-  *hy = y;
-  return (int)slabs();
-}
-
-__global__ __launch_bounds__(NB) void k_conv_bwd_weight_lds(const float* __restrict__ in, int Ci,
-                                                            const float* __restrict__ gout, int Co,
-                                                            double* __restrict__ part, int D, int H, int W,
-                                                            int wz, int hy) {
-  __shared__ float tile[WLDS];
-  static_assert(28 * (NB + NB / 32) <= WLDS, "the block sums reuse the tile");
-  const int ci = blockIdx.x, co0 = blockIdx.y * WCT, sl = blockIdx.z, S = gridDim.z;
-  const int nys = (H + hy - 1) / hy;
-  const int z0 = (sl / nys) * wz, y0 = (sl % nys) * hy;
-  const int nz = min(wz, D - z0), ny = min(hy, H - y0);
-  const int PW = W + 2, PH = ny + 2, PP = PW * PH;
-  const int V = D * H * W;
-  // planes z0-1 .. z0+nz, rows y0-1 .. y0+ny, columns -1 .. W; zero outside the
-  // grid. Sixteen loads per thread are issued before their stores.
-  const int nt = (nz + 2) * PP;
-  for (int t0 = threadIdx.x; t0 < nt; t0 += 16 * NB) {
-    float v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int t = t0 + u * NB;
-      const int lz = t / PP, rem = t - lz * PP, ly = rem / PW, lx = rem - ly * PW;
-      const int z = z0 - 1 + lz, y = y0 - 1 + ly, x = lx - 1;
-      const bool ok = t < nt && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W;
-      v[u] = ok ? in[cidx(ci, z, y, x, D, H, W)] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (t0 + u * NB < nt) tile[t0 + u * NB] = v[u];
-  }
-  __syncthreads();
-  float acc[WCT][28];
-#pragma unroll
-  for (int c = 0; c < WCT; ++c)
-#pragma unroll
-    for (int q = 0; q < 28; ++q) acc[c][q] = 0.0f;
-  const int nv = nz * ny * W;
-#pragma unroll 2
-  for (int t = threadIdx.x; t < nv; t += NB) {
-    const int x = t % W, r = t / W, ly = r % ny, lz = r / ny;
-    const int v = ((z0 + lz) * H + (y0 + ly)) * W + x;
-    const int c = ((lz + 1) * PH + (ly + 1)) * PW + (x + 1);   // the voxel in the tile
-    float g[WCT];
-#pragma unroll
-    for (int k = 0; k < WCT; ++k) g[k] = (co0 + k < Co) ? gout[(co0 + k) * V + v] : 0.0f;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const float tv = tile[c + (dz - 1) * PP + (dy - 1) * PW + (dx - 1)];
-#pragma unroll
-          for (int k = 0; k < WCT; ++k) acc[k][(dz * 3 + dy) * 3 + dx] += g[k] * tv;
-        }
-#pragma unroll
-    for (int k = 0; k < WCT; ++k) acc[k][27] += g[k];
-  }
-  // block sums through LDS (the tile is no longer read): per output channel,
-  // thread t stores its 28 partials at red[q * RS + t + t / 32]; then thread
-  // r < 224 sums, in FP64 and in order, the 32 partials of threads
-  // 32 (r % 8) .. 32 (r % 8) + 31 for output q = r / 8, and the eight lanes of
-  // each q add their sums by three shuffles (the same total in each lane)
-  constexpr int RS = NB + NB / 32;
-  float* red = tile;
-  const int r = threadIdx.x, q = r >> 3, sg = r & 7;
-#pragma unroll
-  for (int k = 0; k < WCT; ++k) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 28; ++j) red[j * RS + r + (r >> 5)] = acc[k][j];
-    __syncthreads();
-    double sum = 0.0;
-    if (q < 28) {
-      const float* src = red + q * RS + sg * 33;
-      for (int i = 0; i < 32; ++i) sum += (double)src[i];
-    }
-    sum += __shfl_xor(sum, 4, 8);
-    sum += __shfl_xor(sum, 2, 8);
-    sum += __shfl_xor(sum, 1, 8);
-    if (q < 28 && sg == 0 && co0 + k < Co) part[(((co0 + k) * Ci + ci) * S + sl) * 28 + q] = sum;
-  }
-}
-
-__global__ __launch_bounds__(NB) void k_conv_bwd_weight_sum(const double* __restrict__ part, int Ci, int Co,
-                                                            int S, float* __restrict__ gw,
-                                                            float* __restrict__ gb) {
-  const int q = blockIdx.x * NB + threadIdx.x;   // (co * Ci + ci) * 28 + t
-  if (q >= Co * Ci * 28) return;
-  const int t = q % 28, cc = q / 28, ci = cc % Ci, co = cc / Ci;
-  double s = 0.0;
-  for (int sl = 0; sl < S; ++sl) s += part[(cc * S + sl) * 28 + t];
-  if (t < 27) gw[cc * 27 + t] = (float)s;
-  else if (ci == 0) gb[co] = (float)s;
-}
-
-__global__ __launch_bounds__(NB) void k_relu_bwd(float* __restrict__ g, const float* __restrict__ act, int n) {
-  const int i = blockIdx.x * NB + threadIdx.x;
-  if (i < n && !(act[i] > 0.0f)) g[i] = 0.0f;
-}
-
-// out[c][Z][Y][X] = mean of the 2x2x2 children (C channels, fine D x H x W)
-__global__ __launch_bounds__(NB) void k_pool2(const float* __restrict__ in, float* __restrict__ out, int C,
-                                              int D, int H, int W) {
-  const int d = D / 2, h = H / 2, w = W / 2;
-  const int v = blockIdx.x * NB + threadIdx.x;
-  if (v >= C * d * h * w) return;
-  const int X = v % w, Y = (v / w) % h, Z = (v / (w * h)) % d, c = v / (w * h * d);
-  double s = 0.0;
-  for (int a = 0; a < 8; ++a)
-    s += (double)in[cidx(c, 2 * Z + ((a >> 2) & 1), 2 * Y + ((a >> 1) & 1), 2 * X + (a & 1), D, H, W)];
-  out[v] = (float)(s * 0.125);
-}
-
-// g_fine[c][z][y][x] = g_coarse[c][z/2][y/2][x/2] / 8 + add[c][z][y][x]
-__global__ __launch_bounds__(NB) void k_pool2_bwd(const float* __restrict__ gc, const float* __restrict__ add,
-                                                  float* __restrict__ gf, int C, int D, int H, int W) {
-  const int v = blockIdx.x * NB + threadIdx.x;
-  if (v >= C * D * H * W) return;
-  const int x = v % W, y = (v / W) % H, z = (v / (W * H)) % D, c = v / (W * H * D);
-  gf[v] = (float)((double)gc[cidx(c, z / 2, y / 2, x / 2, D / 2, H / 2, W / 2)] * 0.125 + (double)add[v]);
-}
-
-// out[c][z][y][x] = in[c][z/2][y/2][x/2] (fine D x H x W)
-__global__ __launch_bounds__(NB) void k_up2(const float* __restrict__ in, float* __restrict__ out, int C,
-                                            int D, int H, int W) {
-  const int v = blockIdx.x * NB + threadIdx.x;
-  if (v >= C * D * H * W) return;
-  const int x = v % W, y = (v / W) % H, z = (v / (W * H)) % D, c = v / (W * H * D);
-  out[v] = in[cidx(c, z / 2, y / 2, x / 2, D / 2, H / 2, W / 2)];
-}
-
-// g_coarse = sum of the 8 children of the fine gradient
-__global__ __launch_bounds__(NB) void k_up2_bwd(const float* __restrict__ gf, float* __restrict__ gc, int C,
-                                                int D, int H, int W) {
-  const int d = D / 2, h = H / 2, w = W / 2;
-  const int v = blockIdx.x * NB + threadIdx.x;
-  if (v >= C * d * h * w) return;
-  const int X = v % w, Y = (v / w) % h, Z = (v / (w * h)) % d, c = v / (w * h * d);
-  double s = 0.0;
-  for (int a = 0; a < 8; ++a)
-    s += (double)gf[cidx(c, 2 * Z + ((a >> 2) & 1), 2 * Y + ((a >> 1) & 1), 2 * X + (a & 1), D, H, W)];
-  gc[v] = (float)s;
-}
-
-// g = 2 (u - y) / V; partial sums of (u - y)^2 per block
-__global__ __launch_bounds__(NB) void k_mse(const float* __restrict__ u, const float* __restrict__ y, int V,
-                                            float* __restrict__ g, double* __restrict__ part) {
+// Loss terms per node: r = mean(u) - T/scale on free nodes; gn = 2 r / nf / cnt
+// (the share of each touching element's output gradient); r^2 block partials.
+__global__ __launch_bounds__(NB) void k_node_resid(Geo g, const float* __restrict__ u,
+                                                   const double* __restrict__ T, double scale, double nf,
+                                                   double* __restrict__ gn, double* __restrict__ part) {
   __shared__ double sh[NB / MGAR_WAVE];
-  const int v = blockIdx.x * NB + threadIdx.x;
-  double e = 0.0;
-  if (v < V) {
-    const double d = (double)u[v] - (double)y[v];
-    g[v] = (float)(2.0 * d / (double)V);
-    e = d * d;
+  const long long n = blockIdx.x * (long long)NB + threadIdx.x;
+  double rr = 0.0;
+  if (n < g.nn) {
+    const int i = (int)(n % g.nnx), j = (int)((n / g.nnx) % g.nny), k = (int)(n / ((long long)g.nnx * g.nny));
+    double gv = 0.0;
+    if (!geo_fixed(g, i, j, k)) {
+      int cnt;
+      const double s = node_sum(g, u, i, j, k, cnt);
+      const double r = 1.0 * s / (double)cnt - T[n] / scale;
+      rr = r * r;
+      gv = 2.0 * r / nf / (double)cnt;
+    }
+    gn[n] = gv;
   }
-  const double s = block_sum(e, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
-__global__ __launch_bounds__(1024) void k_sum_to(const double* __restrict__ part, int n, double scale,
-                                                 double* __restrict__ out) {
-  __shared__ double sh[1024 / MGAR_WAVE];
+__global__ __launch_bounds__(NB) void k_elem_du(Geo g, const double* __restrict__ gn, float* __restrict__ du) {
+  const long long e = blockIdx.x * (long long)NB + threadIdx.x;
+  if (e >= g.ne) return;
+  const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((long long)g.nx * g.ny));
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += part[i];
-  s = block_sum(s, sh);
+  for (int c = 0; c < 8; ++c) s += gn[geo_node(g, i + (c & 1), j + ((c >> 1) & 1), k + (c >> 2))];
+  du[e] = (float)s;
+}
+
+__global__ __launch_bounds__(NB) void k_sum_parts(const double* __restrict__ part, int n, double scale,
+                                                  double* __restrict__ out) {
+  __shared__ double sh[NB / MGAR_WAVE];
+  const double s = block_sum(thread_partials(part, n, threadIdx.x, NB), sh);
   if (threadIdx.x == 0) *out = s * scale;
 }
 
-__global__ __launch_bounds__(NB) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                                             const float* __restrict__ g, long long n, double lr, double c1,
+// ---------------------------------------------------------------- head (1x1x1, one output channel)
+
+__global__ __launch_bounds__(NB) void k_head_fwd(long long V, int C, const u16* __restrict__ d0,
+                                                 const float* __restrict__ w, float* __restrict__ u) {
+  const long long e = blockIdx.x * (long long)NB + threadIdx.x;
+  if (e >= V) return;
+  float s = 0.0f;
+  for (int c = 0; c < C; ++c) s += bf2f(d0[e * C + c]) * w[c];
+  u[e] = s + w[C];
+}
+
+// Data gradient of the head and block partials of its weight and bias
+// gradients ([block][C + 1]: sum_e d0[e][c] du[e], sum_e du[e]); wave sums,
+// then the waves of the block in order.
+constexpr int HMAXC = 128;
+__global__ __launch_bounds__(NB) void k_head_bwd(long long V, int C, const u16* __restrict__ d0,
+                                                 const float* __restrict__ w, const float* __restrict__ du,
+                                                 u16* __restrict__ gd0, double* __restrict__ part) {
+  __shared__ double sh[NB / MGAR_WAVE][HMAXC + 1];
+  const long long e = blockIdx.x * (long long)NB + threadIdx.x;
+  const bool in = e < V;
+  const float g = in ? du[e] : 0.0f;
+  const int wv = threadIdx.x / MGAR_WAVE, lane = threadIdx.x % MGAR_WAVE;
+  for (int c = 0; c <= C; ++c) {
+    double v = 0.0;
+    if (in && c < C) {
+      v = (double)bf2f(d0[e * C + c]) * (double)g;
+      gd0[e * C + c] = f2bf(g * w[c]);
+    } else if (in) {
+      v = (double)g;
+    }
+    v = wave_sum(v);
+    if (lane == 0) sh[wv][c] = v;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c <= C; c += NB) {
+    double s = 0.0;
+    for (int k = 0; k < NB / MGAR_WAVE; ++k) s += sh[k][c];
+    part[(long long)blockIdx.x * (C + 1) + c] = s;
+  }
+}
+
+// grad[c] = sum over the nb blocks of part[b][c] (block c of the grid; every
+// thread sums its blocks in order, then a fixed-order block sum)
+__global__ __launch_bounds__(NB) void k_head_reduce(const double* __restrict__ part, int nb, int C,
+                                                    double* __restrict__ grad) {
+  __shared__ double sh[NB / MGAR_WAVE];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += NB) s += part[(long long)b * (C + 1) + c];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) grad[c] = s;
+}
+
+// ---------------------------------------------------------------- pooling and upsampling (channels-last)
+
+struct Dims { int nx, ny, nz; };
+
+// coarse (nx, ny, nz) = fine / 2; one thread per (coarse voxel, channel quad)
+__global__ __launch_bounds__(NB) void k_pool(Dims c, int C, const u16* __restrict__ fine, u16* __restrict__ out) {
+  const int Q = C / 4;
+  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
+  const long long V = (long long)c.nx * c.ny * c.nz;
+  if (t >= V * Q) return;
+  const long long v = t / Q;
+  const int q = (int)(t % Q);
+  const int i = (int)(v % c.nx), j = (int)((v / c.nx) % c.ny), k = (int)(v / ((long long)c.nx * c.ny));
+  const int fx = 2 * c.nx, fy = 2 * c.ny;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < 8; ++b) {
+    const long long fv = (2 * i + (b & 1)) + (long long)fx * ((2 * j + ((b >> 1) & 1)) + (long long)fy * (2 * k + (b >> 2)));
+    const u64 w = reinterpret_cast<const u64*>(fine)[fv * Q + q];
+    for (int a = 0; a < 4; ++a) s[a] += bf2f((u16)(w >> (16 * a)));
+  }
+  u64 o = 0;
+  for (int a = 0; a < 4; ++a) o |= (u64)f2bf(s[a] * 0.125f) << (16 * a);
+  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+}
+
+// 1D linear 2x upsampling of cell-centred values: fine cell f lies at coarse
+// coordinate (f + 1/2)/2 - 1/2, clamped to [0, n-1]; weights on i0 and i1.
+__device__ inline void up_axis(int f, int n, int& i0, int& i1, float& w0, float& w1) {
+  float c = (f + 0.5f) * 0.5f - 0.5f;
+  c = fminf(fmaxf(c, 0.0f), (float)(n - 1));
+  i0 = (int)floorf(c);
+  i1 = min(i0 + 1, n - 1);
+  w1 = c - (float)i0;
+  w0 = 1.0f - w1;
+}
+
+// weight of coarse cell m in fine cell f (the transpose of up_axis)
+__device__ inline float up_weight(int f, int m, int n) {
+  int i0, i1;
+  float w0, w1;
+  up_axis(f, n, i0, i1, w0, w1);
+  return (i0 == m ? w0 : 0.0f) + (i1 == m ? w1 : 0.0f);
+}
+
+// fine = up(coarse); c: coarse dims; one thread per (fine voxel, channel quad)
+__global__ __launch_bounds__(NB) void k_up(Dims c, int C, const u16* __restrict__ crs, u16* __restrict__ out) {
+  const int Q = C / 4;
+  const int fx = 2 * c.nx, fy = 2 * c.ny, fz = 2 * c.nz;
+  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
+  const long long V = (long long)fx * fy * fz;
+  if (t >= V * Q) return;
+  const long long v = t / Q;
+  const int q = (int)(t % Q);
+  const int i = (int)(v % fx), j = (int)((v / fx) % fy), k = (int)(v / ((long long)fx * fy));
+  int x0, x1, y0, y1, z0, z1;
+  float wx0, wx1, wy0, wy1, wz0, wz1;
+  up_axis(i, c.nx, x0, x1, wx0, wx1);
+  up_axis(j, c.ny, y0, y1, wy0, wy1);
+  up_axis(k, c.nz, z0, z1, wz0, wz1);
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < 8; ++b) {
+    const int xi = (b & 1) ? x1 : x0, yi = (b & 2) ? y1 : y0, zi = (b & 4) ? z1 : z0;
+    const float wt = ((b & 1) ? wx1 : wx0) * ((b & 2) ? wy1 : wy0) * ((b & 4) ? wz1 : wz0);
+    const u64 w = reinterpret_cast<const u64*>(crs)[(xi + (long long)c.nx * (yi + (long long)c.ny * zi)) * Q + q];
+    for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w >> (16 * a)));
+  }
+  u64 o = 0;
+  for (int a = 0; a < 4; ++a) o |= (u64)f2bf(s[a]) << (16 * a);
+  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+}
+
+// coarse = up^T(fine); one thread per (coarse voxel, channel quad): gathers the
+// fine cells 2m-1 .. 2m+2 of every axis with their upsampling weights
+__global__ __launch_bounds__(NB) void k_up_adj(Dims c, int C, const u16* __restrict__ fine, u16* __restrict__ out) {
+  const int Q = C / 4;
+  const int fx = 2 * c.nx, fy = 2 * c.ny, fz = 2 * c.nz;
+  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
+  const long long V = (long long)c.nx * c.ny * c.nz;
+  if (t >= V * Q) return;
+  const long long v = t / Q;
+  const int q = (int)(t % Q);
+  const int i = (int)(v % c.nx), j = (int)((v / c.nx) % c.ny), k = (int)(v / ((long long)c.nx * c.ny));
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int dz = -1; dz <= 2; ++dz) {
+    const int fk = 2 * k + dz;
+    if (fk < 0 || fk >= fz) continue;
+    const float wz = up_weight(fk, k, c.nz);
+    if (wz == 0.0f) continue;
+    for (int dy = -1; dy <= 2; ++dy) {
+      const int fj = 2 * j + dy;
+      if (fj < 0 || fj >= fy) continue;
+      const float wy = up_weight(fj, j, c.ny);
+      if (wy == 0.0f) continue;
+      for (int dx = -1; dx <= 2; ++dx) {
+        const int fi = 2 * i + dx;
+        if (fi < 0 || fi >= fx) continue;
+        const float wx = up_weight(fi, i, c.nx);
+        if (wx == 0.0f) continue;
+        const float wt = wx * wy * wz;
+        const u64 w = reinterpret_cast<const u64*>(fine)[(fi + (long long)fx * (fj + (long long)fy * fk)) * Q + q];
+        for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w >> (16 * a)));
+      }
+    }
+  }
+  u64 o = 0;
+  for (int a = 0; a < 4; ++a) o |= (u64)f2bf(s[a]) << (16 * a);
+  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+}
+
+// skip gradient = skip part of the decoder's data gradient + pooling adjoint of
+// the gradient of the pooled tensor (its coarse value / 8); f: fine dims
+__global__ __launch_bounds__(NB) void k_skip_add(Dims f, int C, const u16* __restrict__ gsk,
+                                                 const u16* __restrict__ gp, u16* __restrict__ out) {
+  const int Q = C / 4;
+  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
+  const long long V = (long long)f.nx * f.ny * f.nz;
+  if (t >= V * Q) return;
+  const long long v = t / Q;
+  const int q = (int)(t % Q);
+  const int i = (int)(v % f.nx), j = (int)((v / f.nx) % f.ny), k = (int)(v / ((long long)f.nx * f.ny));
+  const long long cv = (i / 2) + (long long)(f.nx / 2) * ((j / 2) + (long long)(f.ny / 2) * (k / 2));
+  const u64 a = reinterpret_cast<const u64*>(gsk)[v * Q + q];
+  const u64 b = reinterpret_cast<const u64*>(gp)[cv * Q + q];
+  u64 o = 0;
+  for (int s = 0; s < 4; ++s)
+    o |= (u64)f2bf(bf2f((u16)(a >> (16 * s))) + bf2f((u16)(b >> (16 * s))) * 0.125f) << (16 * s);
+  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+}
+
+// ---------------------------------------------------------------- 3x3x3 convolution on the matrix cores
+
+struct ConvArgs {
+  int nx, ny, nz;        // grid of the level (voxels)
+  const u16* s0;         // input channels [0, c0), channels-last
+  const u16* s1;         // input channels [c0, c0 + c1) (c1 = 0: none)
+  const u16* m0;         // data gradient: the layer's output (ReLU mask of s0); else null
+  const u16* w;          // BF16 weights [27][cout][cin], cin = c0 + c1
+  const float* bias;     // forward: cout biases (ReLU applied); data gradient: null
+  u16* o0;               // output channels [0, d0) (d0 channels per voxel)
+  u16* o1;               // output channels [d0, cout)
+  int c0, c1, cout, d0;
+  int ntx, nty;          // tiles per axis
+};
+
+// One block: a 16 x 4 x 4 voxel tile (wave w: z-slice w, M-tiles = its 4 rows
+// of 16 voxels) and NT 16-channel output tiles (blockIdx.y selects which).
+// Chunks of CC input channels are staged with their halo in LDS
+// [halo voxel][CC]; K step kb covers K = 16 kb .. 16 kb + 15 of (tap, channel)
+// = (k / CC, k % CC), lane group g taking four consecutive channels of one tap.
+template <int NT, int CC, bool DG>
+__global__ __launch_bounds__(NB) void k_conv(ConvArgs a) {
+  // halo voxel stride in LDS: 16 channels padded to 24 values (12 dwords), so
+  // the 16 rows x 4 channel groups of an operand read fall in distinct banks
+  constexpr int SV = CC == 16 ? 24 : CC;
+  __shared__ __attribute__((aligned(16))) u16 S[HV * SV];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, gq = l >> 4, r = l & 15;
+  const int tx = blockIdx.x % a.ntx, ty = (blockIdx.x / a.ntx) % a.nty, tz = blockIdx.x / (a.ntx * a.nty);
+  const int x0 = TX * tx, y0 = TY * ty, z0 = TZ * tz;
+  const int nt0 = blockIdx.y * NT;   // first 16-channel output tile
+  const int cin = a.c0 + a.c1;
+  f4 acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int cb = 0; cb < cin; cb += CC) {
+    const bool first = cb < a.c0;
+    const u16* __restrict__ src = first ? a.s0 : a.s1;
+    const int cs = first ? a.c0 : a.c1, cl = first ? cb : cb - a.c0;
+    for (int q = tid; q < HV * (CC / 4); q += NB) {
+      const int hv = q / (CC / 4), qq = q % (CC / 4);
+      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      u64 val = 0;
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nx && gy < a.ny && gz < a.nz) {
+        const long long off = ((gx + (long long)a.nx * (gy + (long long)a.ny * gz)) * cs + cl) / 4 + qq;
+        val = reinterpret_cast<const u64*>(src)[off];
+        if (DG) {
+          const u64 mk = reinterpret_cast<const u64*>(a.m0)[off];
+          u64 keep = 0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (bfpos((u16)(mk >> (16 * s)))) keep |= 0xFFFFull << (16 * s);
+          val &= keep;
+        }
+      }
+      reinterpret_cast<u64*>(S)[hv * (SV / 4) + qq] = val;
+    }
+    __syncthreads();
+    constexpr int NKB = (27 * CC + 15) / 16;
+    // operands of K step kb (A from LDS, B from the weights in global memory);
+    // those of the next step are loaded before the matrix products of this one
+    auto load = [&](int kb, bf4 (&A)[4], bf4 (&B)[NT]) {
+      const int k = 16 * kb + 4 * gq;
+      const int tap = k / CC, ci0 = k % CC;
+      const bool valid = tap < 27;
+      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int hv = (r + dx) + HX * ((m + dy) + HY * (w + dz));
+        A[m] = valid ? *reinterpret_cast<const bf4*>(&S[hv * SV + ci0]) : bf4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int co = (nt0 + n) * 16 + r;
+        B[n] = valid ? *reinterpret_cast<const bf4*>(&a.w[((long long)tap * a.cout + co) * cin + cb + ci0])
+                     : bf4{0, 0, 0, 0};
+      }
+    };
+    bf4 A[4], B[NT];
+    load(0, A, B);
+    for (int kb = 0; kb < NKB; ++kb) {
+      bf4 An[4], Bn[NT];
+      if (kb + 1 < NKB) load(kb + 1, An, Bn);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[m], B[n], acc[m][n], 0, 0, 0);
+      if (kb + 1 < NKB) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) A[m] = An[m];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) B[n] = Bn[n];
+      }
+    }
+    __syncthreads();
+  }
+  const int z = z0 + w;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int y = y0 + m;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int co = (nt0 + n) * 16 + r;
+      const float bco = DG ? 0.0f : a.bias[co];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = x0 + 4 * gq + j;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        float v = acc[m][n][j] + bco;
+        if (!DG) v = fmaxf(v, 0.0f);
+        const long long vox = x + (long long)a.nx * (y + (long long)a.ny * z);
+        if (co < a.d0) a.o0[vox * a.d0 + co] = f2bf(v);
+        else a.o1[vox * (a.cout - a.d0) + (co - a.d0)] = f2bf(v);
+      }
+    }
+  }
+}
+
+struct WgArgs {
+  int nx, ny, nz;
+  const u16* a0;         // layer input channels [0, c0)
+  const u16* a1;         // layer input channels [c0, c0 + c1)
+  const u16* gA;         // gradient of the layer's output
+  const u16* A;          // the layer's output (ReLU mask)
+  float* part;           // [block][27][cout][cin16] FP32 partials
+  double* bpart;         // [block][cout] bias partials
+  int c0, c1, cout, cin16;
+  int ntx, nty, ntiles, tpb;
+};
+
+constexpr int WRW = 20;            // LDS row of the weight gradient's input tile: 18 halo voxels + 2 zeros
+constexpr int WROWS = HY * HZ;     // 36 halo rows per channel
+// LDS strides of the weight gradient (BF16 values): per input channel 776 >=
+// 36 x 20 (388 dwords), per output-gradient channel 264 >= 256 (132 dwords);
+// both are 4 dwords modulo the 64 banks, so the 16 channels x 4 voxel groups
+// of an operand read fall in distinct banks
+constexpr int WCS = 776, WDS = 264;
+
+// 4 x 4 transpose of BF16 values: in[s] holds 4 channels of voxel s; out[j]
+// holds channel j of the 4 voxels
+__device__ inline void tr4(const u64 (&in)[4], u64 (&out)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    u64 v = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v |= ((in[s] >> (16 * j)) & 0xFFFFull) << (16 * s);
+    out[j] = v;
+  }
+}
+
+// Weight gradient dW[tap][co][ci] = sum over voxels of gZ[v][co] * in[v + tap][ci],
+// gZ = gA * (A > 0). Grid: x = block (a range of tpb tiles), y = 16-channel
+// input chunk, z = group of NTC 16-channel output tiles. Per tile the input
+// chunk with its halo is staged in LDS as [channel][halo row][20] and gZ as
+// [channel][voxel] (each thread loads 4 voxels x 4 channels and writes them
+// transposed); wave w accumulates the taps w, w + 4, ... over K = the 256
+// voxels of the tile (16 steps of one 16-voxel row), the input operand of a
+// tap shifted by dx from two aligned 8-byte reads.
+template <int NTC>
+__global__ __launch_bounds__(NB) void k_wgrad(WgArgs a) {
+  __shared__ __attribute__((aligned(16))) u16 As[16 * WCS];
+  __shared__ __attribute__((aligned(16))) u16 Ds[NTC * 16 * WDS];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, gq = l >> 4, r = l & 15;
+  const int t0 = blockIdx.x * a.tpb, t1 = min(t0 + a.tpb, a.ntiles);
+  const int cg = blockIdx.y, ng0 = blockIdx.z * NTC;
+  const int cin = a.c0 + a.c1, cbase = 16 * cg;
+  constexpr int TV = TX * TY * TZ;
+  f4 acc[7][NTC];
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+#pragma unroll
+    for (int n = 0; n < NTC; ++n) acc[i][n] = f4{0.f, 0.f, 0.f, 0.f};
+  // bias partials (first input chunk only): thread tid sums output channel
+  // 16 ng0 + tid % (16 NTC) over the voxels v = tid / (16 NTC) + k nbg of every
+  // tile, in order; the nbg partials of a channel are added in order at the end
+  constexpr int NBC = 16 * NTC, NBG = NB / NBC;
+  __shared__ double bsh[NBG * NBC];
+  const int bco = tid % NBC, bgr = tid / NBC;
+  double bsum = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
+    const int x0 = TX * tx, y0 = TY * ty, z0 = TZ * tz;
+    // input chunk (channels cbase .. cbase + 15 of the concatenated input)
+    for (int it = tid; it < WROWS * (WRW / 4) * 4; it += NB) {
+      const int cq = it % 4, xg = (it / 4) % (WRW / 4), row = it / (4 * (WRW / 4));
+      const int hy = row % HY, hz = row / HY;
+      const int gy = y0 - 1 + hy, gz = z0 - 1 + hz, c = cbase + 4 * cq;
+      u64 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int hx = 4 * xg + q, gx = x0 - 1 + hx;
+        v[q] = 0;
+        if (hx < HX && c < cin && gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nx && gy < a.ny && gz < a.nz) {
+          const long long vox = gx + (long long)a.nx * (gy + (long long)a.ny * gz);
+          v[q] = c < a.c0 ? reinterpret_cast<const u64*>(a.a0)[(vox * a.c0 + c) / 4]
+                          : reinterpret_cast<const u64*>(a.a1)[(vox * a.c1 + (c - a.c0)) / 4];
+        }
+      }
+      u64 o[4];
+      tr4(v, o);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<u64*>(&As[(4 * cq + j) * WCS + row * WRW + 4 * xg]) = o[j];
+    }
+    // masked output gradient (channels 16 ng0 .. 16 (ng0 + NTC) - 1)
+    for (int it = tid; it < (TV / 4) * 4 * NTC; it += NB) {
+      const int cq = it % (4 * NTC), xg = (it / (4 * NTC)) % (TX / 4), vrow = it / (4 * NTC * (TX / 4));
+      const int gy = y0 + (vrow & 3), gz = z0 + (vrow >> 2);
+      u64 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gx = x0 + 4 * xg + q;
+        v[q] = 0;
+        if (gx < a.nx && gy < a.ny && gz < a.nz) {
+          const long long off = ((gx + (long long)a.nx * (gy + (long long)a.ny * gz)) * a.cout + 16 * ng0) / 4 + cq;
+          const u64 mk = reinterpret_cast<const u64*>(a.A)[off];
+          u64 keep = 0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (bfpos((u16)(mk >> (16 * s)))) keep |= 0xFFFFull << (16 * s);
+          v[q] = reinterpret_cast<const u64*>(a.gA)[off] & keep;
+        }
+      }
+      u64 o[4];
+      tr4(v, o);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) *reinterpret_cast<u64*>(&Ds[(4 * cq + j) * WDS + vrow * TX + 4 * xg]) = o[j];
+    }
+    __syncthreads();
+    if (cg == 0 && bgr < NBG) {
+      double s = 0.0;
+      for (int v = bgr; v < TV; v += NBG) s += (double)bf2f(Ds[bco * WDS + v]);
+      bsum += s;
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const int tap = w + 4 * i;
+      if (tap < 27) {
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+#pragma unroll 4
+        for (int kb = 0; kb < 16; ++kb) {
+          const int row = ((kb >> 2) + dz) * HY + ((kb & 3) + dy);
+          const u64* pb = reinterpret_cast<const u64*>(&As[r * WCS + row * WRW + 4 * gq]);
+          const u64 lo = pb[0], hi = pb[1];
+          const u64 bw = dx == 0 ? lo : (lo >> (16 * dx)) | (hi << (64 - 16 * dx));
+          const bf4 B = __builtin_bit_cast(bf4, bw);
+#pragma unroll
+          for (int n = 0; n < NTC; ++n) {
+            const bf4 A = *reinterpret_cast<const bf4*>(&Ds[(n * 16 + r) * WDS + kb * TX + 4 * gq]);
+            acc[i][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc[i][n], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const int tap = w + 4 * i;
+    if (tap < 27) {
+#pragma unroll
+      for (int n = 0; n < NTC; ++n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int co = 16 * (ng0 + n) + 4 * gq + j, ci = cbase + r;
+          a.part[(((long long)blockIdx.x * 27 + tap) * a.cout + co) * a.cin16 + ci] = acc[i][n][j];
+        }
+    }
+  }
+  if (cg == 0) {
+    if (bgr < NBG) bsh[bgr * NBC + bco] = bsum;
+    __syncthreads();
+    if (tid < NBC) {
+      double s = 0.0;
+      for (int q = 0; q < NBG; ++q) s += bsh[q * NBC + tid];
+      a.bpart[(long long)blockIdx.x * a.cout + 16 * ng0 + tid] = s;
+    }
+  }
+}
+
+// grad[woff + (co ci + c) 27 + tap] = sum over blocks of part[b][tap][co][c]
+// (c < ci), and grad[boff + co] = sum over blocks of bpart[b][co]. Sixteen
+// threads per parameter: thread q sums the blocks q, q + 16, ... in order and
+// the sixteen sums are added in order of q.
+constexpr int WRQ = 16;
+__global__ __launch_bounds__(NB) void k_wreduce(const float* __restrict__ part, const double* __restrict__ bpart,
+                                                int nb, int cout, int ci, int cin16, double* __restrict__ gw,
+                                                double* __restrict__ gb) {
+  __shared__ double sh[NB];
+  const int q = threadIdx.x % WRQ;
+  const long long t = blockIdx.x * (long long)(NB / WRQ) + threadIdx.x / WRQ;
+  const long long nw = 27LL * cout * cin16;
+  double s = 0.0;
+  if (t < nw) {
+    for (int b = q; b < nb; b += WRQ) s += (double)part[(long long)b * nw + t];
+  } else if (t < nw + cout) {
+    for (int b = q; b < nb; b += WRQ) s += bpart[(long long)b * cout + (t - nw)];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (q == 0 && t < nw + cout) {
+    double v = 0.0;
+    for (int k = 0; k < WRQ; ++k) v += sh[threadIdx.x + k];
+    if (t < nw) {
+      const int c = (int)(t % cin16), co = (int)((t / cin16) % cout), tap = (int)(t / ((long long)cin16 * cout));
+      if (c < ci) gw[((long long)co * ci + c) * 27 + tap] = v;
+    } else {
+      gb[t - nw] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- parameters
+
+// BF16 copies of a convolution's weights: forward wf[tap][co][cip] (input
+// channels padded to cip with zeros) and data gradient wd[tap][ci][co] with
+// the taps mirrored (tap' = 26 - tap).
+__global__ __launch_bounds__(NB) void k_pack_w(const float* __restrict__ w, int co, int ci, int cip,
+                                               u16* __restrict__ wf, u16* __restrict__ wd) {
+  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
+  if (t >= 27LL * co * cip) return;
+  const int c = (int)(t % cip), o = (int)((t / cip) % co), tap = (int)(t / ((long long)cip * co));
+  const u16 b = c < ci ? f2bf(w[((long long)o * ci + c) * 27 + tap]) : (u16)0;
+  wf[t] = b;
+  if (c < ci) wd[((long long)(26 - tap) * ci + c) * co + o] = b;
+}
+
+__global__ __launch_bounds__(NB) void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                                             const double* __restrict__ g, long long n, double lr, double c1,
                                              double c2) {
   const long long i = blockIdx.x * (long long)NB + threadIdx.x;
   if (i >= n) return;
-  const double gi = (double)g[i];
-  const double mi = 0.9 * (double)m[i] + 0.1 * gi;
-  const double vi = 0.999 * (double)v[i] + 0.001 * gi * gi;
-  m[i] = (float)mi;
-  v[i] = (float)vi;
-  p[i] = (float)((double)p[i] - lr * (mi / c1) / (sqrt(vi / c2) + 1e-8));
+  const double gi = g[i];
+  const float mi = (float)(0.9 * (double)m[i] + (1.0 - 0.9) * gi);
+  const float vi = (float)(0.999 * (double)v[i] + (1.0 - 0.999) * gi * gi);
+  m[i] = mi;
+  v[i] = vi;
+  const double mh = (double)mi / c1, vh = (double)vi / c2;
+  th[i] = (float)((double)th[i] - lr * mh / (sqrt(vh) + 1e-8));
 }
-
-int nblk(long long n) { return (int)((n + NB - 1) / NB); }
 
 }  // namespace
 
+// ---------------------------------------------------------------- handle
+
 struct mgar_net {
   hipStream_t s = nullptr;
-  Geo g;
-  int f = 4, D = 0, H = 0, W = 0, c1 = 0, c2 = 0;
+  Geo g{};
+  int L = 0;
+  int C[MAXL] = {};
+  Dims lv[MAXL] = {};
+  long long V[MAXL] = {};
   long long np = 0;
-  long long woff[6], boff[6];
-  int co[6], ci[6];
-  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
-  float *in = nullptr, *a1 = nullptr, *a2 = nullptr, *pool = nullptr, *a3 = nullptr, *a4 = nullptr,
-        *cat = nullptr, *a5 = nullptr, *u = nullptr, *y = nullptr;
-  float *gU = nullptr, *gA5 = nullptr, *gCat = nullptr, *gA4 = nullptr, *gA3 = nullptr, *gPool = nullptr,
-        *gA2 = nullptr, *gA1 = nullptr;
-  double *part = nullptr, *loss = nullptr;
-  double* wpart = nullptr;   // per-slab partial sums of the weight gradients
-  int t = 0;   // Adam steps taken
+  int t = 0;
+  float *theta = nullptr, *m = nullptr, *v = nullptr;
+  double* grad = nullptr;
+  float* src = nullptr;
+  u16* in = nullptr;
+  u16 *e[MAXL] = {}, *s_[MAXL] = {}, *p[MAXL] = {}, *up[MAXL] = {}, *h[MAXL] = {}, *d[MAXL] = {};
+  u16 *g1[MAXL] = {}, *g2[MAXL] = {}, *gup[MAXL] = {}, *gsk[MAXL] = {}, *gpool[MAXL] = {};
+  float *u = nullptr, *du = nullptr;
+  double *gn = nullptr, *lpart = nullptr, *loss = nullptr, *hpart = nullptr;
+  float* wpart = nullptr;
+  double* bpart = nullptr;
+  long long wpart_cap = 0, bpart_cap = 0;
+  struct Layer { int co, ci, cip, k, lev; long long woff, boff; u16* wf; u16* wd; };
+  std::vector<Layer> layers;
+  std::vector<void*> allocs;
 };
 
 namespace {
 
-int conv(mgar_net* N, int layer, const float* in, float* out, bool relu, int D, int H, int W) {
-  const dim3 grid((unsigned)((D * H * W + NBC - 1) / NBC), (N->co[layer] + CT - 1) / CT);
-  const dim3 blk(NBC);
-  const float* w = N->theta + N->woff[layer];
-  const float* b = N->theta + N->boff[layer];
-  if (relu) k_conv<true, true><<<grid, blk, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
-  else k_conv<true, false><<<grid, blk, 0, N->s>>>(in, N->ci[layer], w, b, out, N->co[layer], D, H, W);
+template <typename T>
+int nalloc(mgar_net* n, T** p, long long count) {
+  *p = nullptr;
+  if (count <= 0) return MGAR_OK;
+  NHIP(hipMalloc((void**)p, sizeof(T) * (size_t)count));
+  n->allocs.push_back((void*)*p);
+  return MGAR_OK;
+}
+
+int layer_index(const mgar_net* n, char kind, int l, char ab) {
+  if (kind == 'e') return 2 * l + (ab == 'b');
+  if (kind == 'd') return 2 * n->L + 2 * (n->L - 2 - l) + (ab == 'b');
+  return 4 * n->L - 2;   // head
+}
+
+inline int tiles(const Dims& d, int* ntx, int* nty) {
+  *ntx = (d.nx + TX - 1) / TX;
+  *nty = (d.ny + TY - 1) / TY;
+  return *ntx * *nty * ((d.nz + TZ - 1) / TZ);
+}
+
+// out = conv(in) (forward, ReLU) or the data gradient (DG) of a layer.
+int conv(mgar_net* n, const Dims& d, const u16* s0, int c0, const u16* s1, int c1, const u16* m0,
+         const u16* wts, const float* bias, int cout, u16* o0, int d0, u16* o1, bool dg) {
+  ConvArgs a;
+  a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
+  a.s0 = s0; a.s1 = s1; a.m0 = m0; a.w = wts; a.bias = bias;
+  a.o0 = o0; a.o1 = o1; a.c0 = c0; a.c1 = c1; a.cout = cout; a.d0 = d0;
+  if (cout % 16 || (c0 + c1) % 4) return MGAR_E_ARG;
+  const int nt = tiles(d, &a.ntx, &a.nty);
+  const int T16 = cout / 16;
+  // output tiles per block: as many as divide the count, fewer when the grid
+  // has few voxel tiles (each block then stages the same input for fewer
+  // output channels, and more blocks share the work)
+  int NTc = (T16 % 4 == 0) ? 4 : (T16 % 3 == 0) ? 3 : (T16 % 2 == 0) ? 2 : 1;
+  while (NTc > 1 && (long long)nt * (T16 / NTc) < 1024) {
+    int nx = NTc - 1;
+    while (nx > 1 && T16 % nx) --nx;
+    NTc = nx;
+  }
+  const dim3 grid(nt, T16 / NTc);
+  const bool small = (c0 + c1) < 16;
+  if (small && (dg || c1 || c0 != 4)) return MGAR_E_ARG;
+#define KCONV(NTV, CCV, DGV) hipLaunchKernelGGL((k_conv<NTV, CCV, DGV>), grid, dim3(NB), 0, n->s, a)
+  if (small) {
+    switch (NTc) {
+      case 1: KCONV(1, 4, false); break;
+      case 2: KCONV(2, 4, false); break;
+      case 3: KCONV(3, 4, false); break;
+      default: KCONV(4, 4, false); break;
+    }
+  } else if (dg) {
+    if (c0 % 16 || c1 % 16) return MGAR_E_ARG;
+    switch (NTc) {
+      case 1: KCONV(1, 16, true); break;
+      case 2: KCONV(2, 16, true); break;
+      case 3: KCONV(3, 16, true); break;
+      default: KCONV(4, 16, true); break;
+    }
+  } else {
+    if (c0 % 16 || c1 % 16) return MGAR_E_ARG;
+    switch (NTc) {
+      case 1: KCONV(1, 16, false); break;
+      case 2: KCONV(2, 16, false); break;
+      case 3: KCONV(3, 16, false); break;
+      default: KCONV(4, 16, false); break;
+    }
+  }
+#undef KCONV
   NLAUNCH();
   return MGAR_OK;
 }
 
-// weight and bias gradients of `layer`, and (gin != null) its input gradient
-int conv_bwd(mgar_net* N, int layer, const float* in, const float* gout, float* gin, int D, int H, int W) {
-  int wz = 0, hy = 0;
-  const int S = weight_slabs(D, H, W, N->ci[layer], N->co[layer], &wz, &hy);
-  if (S <= 0) return MGAR_E_ARG;
-  const dim3 gw(N->ci[layer], (N->co[layer] + WCT - 1) / WCT, S);
-  k_conv_bwd_weight_lds<<<gw, NB, 0, N->s>>>(in, N->ci[layer], gout, N->co[layer], N->wpart, D, H, W, wz, hy);
-  k_conv_bwd_weight_sum<<<nblk((long long)N->co[layer] * N->ci[layer] * 28), NB, 0, N->s>>>(
-      N->wpart, N->ci[layer], N->co[layer], S, N->grad + N->woff[layer], N->grad + N->boff[layer]);
-  if (gin) {
-    const dim3 gd((unsigned)((D * H * W + NBC - 1) / NBC), (N->ci[layer] + CT - 1) / CT);
-    k_conv<false, false><<<gd, NBC, 0, N->s>>>(gout, N->co[layer], N->theta + N->woff[layer], nullptr,
-                                                         gin, N->ci[layer], D,
-                                         H, W);
+// weight and bias gradients of layer li into n->grad
+int wgrad(mgar_net* n, int li, const Dims& d, const u16* a0, int c0, const u16* a1, int c1, const u16* gA,
+          const u16* A) {
+  const auto& Ly = n->layers[li];
+  WgArgs a;
+  a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
+  a.a0 = a0; a.a1 = a1; a.gA = gA; a.A = A;
+  a.c0 = c0; a.c1 = c1; a.cout = Ly.co;
+  a.cin16 = ((c0 + c1) + 15) / 16 * 16;
+  a.ntiles = tiles(d, &a.ntx, &a.nty);
+  const long long per = 27LL * a.cout * a.cin16;
+  long long nb = std::min<long long>(a.ntiles, 512);
+  nb = std::min<long long>(nb, std::max<long long>(1, n->wpart_cap / per));
+  a.tpb = (int)((a.ntiles + nb - 1) / nb);
+  nb = (a.ntiles + a.tpb - 1) / a.tpb;
+  if (nb * per > n->wpart_cap || nb * a.cout > n->bpart_cap) return MGAR_E_ARG;
+  a.part = n->wpart;
+  a.bpart = n->bpart;
+  const int nco = a.cout / 16;
+  const int NTC = (nco % 4 == 0) ? 4 : (nco % 3 == 0) ? 3 : (nco % 2 == 0) ? 2 : 1;
+  const dim3 grid((unsigned)nb, (unsigned)(a.cin16 / 16), (unsigned)(nco / NTC));
+  switch (NTC) {
+    case 1: hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(NB), 0, n->s, a); break;
+    case 2: hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(NB), 0, n->s, a); break;
+    case 3: hipLaunchKernelGGL(k_wgrad<3>, grid, dim3(NB), 0, n->s, a); break;
+    default: hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(NB), 0, n->s, a); break;
   }
   NLAUNCH();
-  return MGAR_OK;
-}
-
-int forward(mgar_net* N, const double* xphys) {
-  const int D = N->D, H = N->H, W = N->W, V = D * H * W;
-  const int d = D / 2, h = H / 2, w = W / 2;
-  k_net_input<<<nblk(V), NB, 0, N->s>>>(N->g, xphys, N->f, D, H, W, N->in);
-  NACK(conv(N, 0, N->in, N->a1, true, D, H, W));
-  NACK(conv(N, 1, N->a1, N->a2, true, D, H, W));
-  k_pool2<<<nblk((long long)N->c1 * d * h * w), NB, 0, N->s>>>(N->a2, N->pool, N->c1, D, H, W);
-  NACK(conv(N, 2, N->pool, N->a3, true, d, h, w));
-  NACK(conv(N, 3, N->a3, N->a4, true, d, h, w));
-  k_up2<<<nblk((long long)N->c2 * V), NB, 0, N->s>>>(N->a4, N->cat, N->c2, D, H, W);
-  NHIP(hipMemcpyAsync(N->cat + (long long)N->c2 * V, N->a2, sizeof(float) * (size_t)N->c1 * V,
-                      hipMemcpyDeviceToDevice, N->s));
-  NACK(conv(N, 4, N->cat, N->a5, true, D, H, W));
-  NACK(conv(N, 5, N->a5, N->u, false, D, H, W));
+  hipLaunchKernelGGL(k_wreduce, dim3((unsigned)((per + a.cout + NB / WRQ - 1) / (NB / WRQ))), dim3(NB), 0, n->s,
+                     (const float*)n->wpart,
+                     (const double*)n->bpart, (int)nb, a.cout, Ly.ci, a.cin16, n->grad + Ly.woff,
+                     n->grad + Ly.boff);
   NLAUNCH();
   return MGAR_OK;
 }
 
-// loss and parameter gradient for the pair (xphys, T / scale)
-int loss_grad(mgar_net* N, const double* xphys, const double* T, double scale) {
-  const int D = N->D, H = N->H, W = N->W, V = D * H * W;
-  const int d = D / 2, h = H / 2, w = W / 2, V8 = d * h * w;
-  NACK(forward(N, xphys));
-  k_net_target<<<nblk(V), NB, 0, N->s>>>(N->g, T, N->f, D, H, W, 1.0 / scale, N->y);
-  k_mse<<<nblk(V), NB, 0, N->s>>>(N->u, N->y, V, N->gU, N->part);
-  k_sum_to<<<1, 1024, 0, N->s>>>(N->part, nblk(V), 1.0 / (double)V, N->loss);
-  NACK(conv_bwd(N, 5, N->a5, N->gU, N->gA5, D, H, W));
-  k_relu_bwd<<<nblk((long long)N->c1 * V), NB, 0, N->s>>>(N->gA5, N->a5, N->c1 * V);
-  NACK(conv_bwd(N, 4, N->cat, N->gA5, N->gCat, D, H, W));
-  k_up2_bwd<<<nblk((long long)N->c2 * V8), NB, 0, N->s>>>(N->gCat, N->gA4, N->c2, D, H, W);
-  k_relu_bwd<<<nblk((long long)N->c2 * V8), NB, 0, N->s>>>(N->gA4, N->a4, N->c2 * V8);
-  NACK(conv_bwd(N, 3, N->a3, N->gA4, N->gA3, d, h, w));
-  k_relu_bwd<<<nblk((long long)N->c2 * V8), NB, 0, N->s>>>(N->gA3, N->a3, N->c2 * V8);
-  NACK(conv_bwd(N, 2, N->pool, N->gA3, N->gPool, d, h, w));
-  k_pool2_bwd<<<nblk((long long)N->c1 * V), NB, 0, N->s>>>(N->gPool, N->gCat + (long long)N->c2 * V, N->gA2,
-                                                            N->c1, D, H, W);
-  k_relu_bwd<<<nblk((long long)N->c1 * V), NB, 0, N->s>>>(N->gA2, N->a2, N->c1 * V);
-  NACK(conv_bwd(N, 1, N->a1, N->gA2, N->gA1, D, H, W));
-  k_relu_bwd<<<nblk((long long)N->c1 * V), NB, 0, N->s>>>(N->gA1, N->a1, N->c1 * V);
-  NACK(conv_bwd(N, 0, N->in, N->gA1, nullptr, D, H, W));
+int pack_weights(mgar_net* n) {
+  for (auto& Ly : n->layers) {
+    if (Ly.k != 3) continue;
+    hipLaunchKernelGGL(k_pack_w, dim3(nblk(27LL * Ly.co * Ly.cip)), dim3(NB), 0, n->s,
+                       (const float*)(n->theta + Ly.woff), Ly.co, Ly.ci, Ly.cip, Ly.wf, Ly.wd);
+    NLAUNCH();
+  }
+  return MGAR_OK;
+}
+
+int forward(mgar_net* n, const double* xphys) {
+  const int L = n->L;
+  hipLaunchKernelGGL(k_net_input, dim3(nblk(n->g.ne)), dim3(NB), 0, n->s, n->g, xphys, (const float*)n->src, n->in);
+  NLAUNCH();
+  for (int l = 0; l < L; ++l) {
+    const auto& La = n->layers[layer_index(n, 'e', l, 'a')];
+    const auto& Lb = n->layers[layer_index(n, 'e', l, 'b')];
+    const u16* x = n->in;
+    int cx = 4;
+    if (l > 0) {
+      hipLaunchKernelGGL(k_pool, dim3(nblk(n->V[l] * n->C[l - 1] / 4)), dim3(NB), 0, n->s, n->lv[l], n->C[l - 1],
+                         (const u16*)n->s_[l - 1], n->p[l]);
+      NLAUNCH();
+      x = n->p[l];
+      cx = n->C[l - 1];
+    }
+    NACK(conv(n, n->lv[l], x, cx, nullptr, 0, nullptr, La.wf, n->theta + La.boff, La.co, n->e[l], La.co, nullptr,
+              false));
+    NACK(conv(n, n->lv[l], n->e[l], n->C[l], nullptr, 0, nullptr, Lb.wf, n->theta + Lb.boff, Lb.co, n->s_[l],
+              Lb.co, nullptr, false));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const u16* below = (l + 1 == L - 1) ? n->s_[L - 1] : n->d[l + 1];
+    hipLaunchKernelGGL(k_up, dim3(nblk(n->V[l] * n->C[l + 1] / 4)), dim3(NB), 0, n->s, n->lv[l + 1], n->C[l + 1],
+                       below, n->up[l]);
+    NLAUNCH();
+    const auto& La = n->layers[layer_index(n, 'd', l, 'a')];
+    const auto& Lb = n->layers[layer_index(n, 'd', l, 'b')];
+    NACK(conv(n, n->lv[l], n->up[l], n->C[l + 1], n->s_[l], n->C[l], nullptr, La.wf, n->theta + La.boff, La.co,
+              n->h[l], La.co, nullptr, false));
+    NACK(conv(n, n->lv[l], n->h[l], n->C[l], nullptr, 0, nullptr, Lb.wf, n->theta + Lb.boff, Lb.co, n->d[l],
+              Lb.co, nullptr, false));
+  }
+  const auto& Lh = n->layers[layer_index(n, 'h', 0, 'a')];
+  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(n->V[0])), dim3(NB), 0, n->s, n->V[0], n->C[0], (const u16*)n->d[0],
+                     (const float*)(n->theta + Lh.woff), n->u);
   NLAUNCH();
   return MGAR_OK;
 }
 
-template <typename T>
-int nalloc(T** p, long long n) {
-  *p = nullptr;
-  NHIP(hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1)));
+// loss (device, n->loss) and the gradient of every parameter (n->grad)
+int loss_grad(mgar_net* n, const double* xphys, const double* T, double scale) {
+  const int L = n->L;
+  NACK(forward(n, xphys));
+  const Geo& g = n->g;
+  long long nfree = g.nn;
+  {
+    const long long fx = std::max(0, g.f1x - g.f0x + 1), fy = std::max(0, g.f1y - g.f0y + 1),
+                    fz = std::max(0, g.f1z - g.f0z + 1);
+    nfree -= fx * fy * fz;
+  }
+  const int nbn = nblk(g.nn);
+  hipLaunchKernelGGL(k_node_resid, dim3(nbn), dim3(NB), 0, n->s, g, (const float*)n->u, T, scale, (double)nfree,
+                     n->gn, n->lpart);
+  NLAUNCH();
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(NB), 0, n->s, (const double*)n->lpart, nbn, 1.0 / (double)nfree,
+                     n->loss);
+  NLAUNCH();
+  hipLaunchKernelGGL(k_elem_du, dim3(nblk(g.ne)), dim3(NB), 0, n->s, g, (const double*)n->gn, n->du);
+  NLAUNCH();
+  // head
+  const auto& Lh = n->layers[layer_index(n, 'h', 0, 'a')];
+  const int nbv = nblk(n->V[0]);
+  hipLaunchKernelGGL(k_head_bwd, dim3(nbv), dim3(NB), 0, n->s, n->V[0], n->C[0], (const u16*)n->d[0],
+                     (const float*)(n->theta + Lh.woff), (const float*)n->du, n->g1[0], n->hpart);
+  NLAUNCH();
+  hipLaunchKernelGGL(k_head_reduce, dim3(n->C[0] + 1), dim3(NB), 0, n->s, (const double*)n->hpart, nbv, n->C[0],
+                     n->grad + Lh.woff);
+  NLAUNCH();
+  // decoder, level 0 up to L-2; g1[l] holds the gradient of d_l (of s_(L-1) at l = L-1)
+  for (int l = 0; l <= L - 2; ++l) {
+    const int ia = layer_index(n, 'd', l, 'a'), ib = layer_index(n, 'd', l, 'b');
+    const auto& La = n->layers[ia];
+    const auto& Lb = n->layers[ib];
+    NACK(wgrad(n, ib, n->lv[l], n->h[l], n->C[l], nullptr, 0, n->g1[l], n->d[l]));
+    NACK(conv(n, n->lv[l], n->g1[l], n->C[l], nullptr, 0, n->d[l], Lb.wd, nullptr, Lb.ci, n->g2[l], Lb.ci,
+              nullptr, true));
+    NACK(wgrad(n, ia, n->lv[l], n->up[l], n->C[l + 1], n->s_[l], n->C[l], n->g2[l], n->h[l]));
+    NACK(conv(n, n->lv[l], n->g2[l], n->C[l], nullptr, 0, n->h[l], La.wd, nullptr, La.ci, n->gup[l], n->C[l + 1],
+              n->gsk[l], true));
+    hipLaunchKernelGGL(k_up_adj, dim3(nblk(n->V[l + 1] * n->C[l + 1] / 4)), dim3(NB), 0, n->s, n->lv[l + 1],
+                       n->C[l + 1], (const u16*)n->gup[l], n->g1[l + 1]);
+    NLAUNCH();
+  }
+  // encoder, level L-1 down to 0
+  for (int l = L - 1; l >= 0; --l) {
+    const int ia = layer_index(n, 'e', l, 'a'), ib = layer_index(n, 'e', l, 'b');
+    const auto& Lb = n->layers[ib];
+    if (l < L - 1) {
+      hipLaunchKernelGGL(k_skip_add, dim3(nblk(n->V[l] * n->C[l] / 4)), dim3(NB), 0, n->s, n->lv[l], n->C[l],
+                         (const u16*)n->gsk[l], (const u16*)n->gpool[l + 1], n->g1[l]);
+      NLAUNCH();
+    }
+    NACK(wgrad(n, ib, n->lv[l], n->e[l], n->C[l], nullptr, 0, n->g1[l], n->s_[l]));
+    NACK(conv(n, n->lv[l], n->g1[l], n->C[l], nullptr, 0, n->s_[l], Lb.wd, nullptr, Lb.ci, n->g2[l], Lb.ci,
+              nullptr, true));
+    if (l == 0) {
+      NACK(wgrad(n, ia, n->lv[0], n->in, 4, nullptr, 0, n->g2[0], n->e[0]));
+    } else {
+      const auto& La = n->layers[ia];
+      NACK(wgrad(n, ia, n->lv[l], n->p[l], n->C[l - 1], nullptr, 0, n->g2[l], n->e[l]));
+      NACK(conv(n, n->lv[l], n->g2[l], n->C[l], nullptr, 0, n->e[l], La.wd, nullptr, La.ci, n->gpool[l], La.ci,
+                nullptr, true));
+    }
+  }
+  return MGAR_OK;
+}
+
+int create_impl(mgar_net* N, const mgar_params* p, int levels, const int* channels, void* stream) {
+  NACK(mgar_internal_validate(p));
+  if (p->dim != 3 || levels < 2 || levels > MAXL || !channels) return MGAR_E_ARG;
+  const int f = 1 << (levels - 1);
+  if (p->nelx % f || p->nely % f || p->nelz % f) return MGAR_E_DIMS;
+  for (int l = 0; l < levels; ++l)
+    if (channels[l] < 16 || channels[l] > 128 || channels[l] % 16) return MGAR_E_ARG;
+  N->s = (hipStream_t)stream;
+  N->g = mgar_internal_geo(*p, 0);
+  N->L = levels;
+  for (int l = 0; l < levels; ++l) {
+    N->C[l] = channels[l];
+    N->lv[l] = Dims{p->nelx >> l, p->nely >> l, p->nelz >> l};
+    N->V[l] = (long long)N->lv[l].nx * N->lv[l].ny * N->lv[l].nz;
+  }
+  const int L = levels;
+  // layers in parameter order: encoder, decoder, head
+  long long off = 0;
+  auto add = [&](int co, int ci, int k, int lev) {
+    mgar_net::Layer Ly{co, ci, ci < 4 ? 4 : ci, k, lev, off, off + (long long)co * ci * k * k * k, nullptr, nullptr};
+    off = Ly.boff + co;
+    N->layers.push_back(Ly);
+  };
+  for (int l = 0; l < L; ++l) {
+    add(N->C[l], l == 0 ? 3 : N->C[l - 1], 3, l);
+    add(N->C[l], N->C[l], 3, l);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    add(N->C[l], N->C[l + 1] + N->C[l], 3, l);
+    add(N->C[l], N->C[l], 3, l);
+  }
+  add(1, N->C[0], 1, 0);
+  N->np = off;
+  NACK(nalloc(N, &N->theta, off));
+  NACK(nalloc(N, &N->m, off));
+  NACK(nalloc(N, &N->v, off));
+  NACK(nalloc(N, &N->grad, off));
+  NHIP(hipMemset(N->theta, 0, sizeof(float) * off));
+  NHIP(hipMemset(N->m, 0, sizeof(float) * off));
+  NHIP(hipMemset(N->v, 0, sizeof(float) * off));
+  NHIP(hipMemset(N->grad, 0, sizeof(double) * off));
+  long long wmax = 0;
+  for (auto& Ly : N->layers) {
+    if (Ly.k != 3) continue;
+    NACK(nalloc(N, &Ly.wf, 27LL * Ly.co * Ly.cip));
+    NACK(nalloc(N, &Ly.wd, 27LL * Ly.co * Ly.ci));
+    wmax = std::max(wmax, 27LL * Ly.co * ((Ly.ci + 15) / 16 * 16));
+  }
+  const long long E = N->V[0];
+  NACK(nalloc(N, &N->src, E));
+  {
+    std::vector<float> one((size_t)E, 1.0f);
+    NHIP(hipMemcpy(N->src, one.data(), sizeof(float) * (size_t)E, hipMemcpyHostToDevice));
+  }
+  NACK(nalloc(N, &N->in, 4 * E));
+  for (int l = 0; l < L; ++l) {
+    const long long Vl = N->V[l];
+    NACK(nalloc(N, &N->e[l], Vl * N->C[l]));
+    NACK(nalloc(N, &N->s_[l], Vl * N->C[l]));
+    NACK(nalloc(N, &N->g1[l], Vl * N->C[l]));
+    NACK(nalloc(N, &N->g2[l], Vl * N->C[l]));
+    if (l > 0) {
+      NACK(nalloc(N, &N->p[l], Vl * N->C[l - 1]));
+      NACK(nalloc(N, &N->gpool[l], Vl * N->C[l - 1]));
+    }
+    if (l <= L - 2) {
+      NACK(nalloc(N, &N->up[l], Vl * N->C[l + 1]));
+      NACK(nalloc(N, &N->h[l], Vl * N->C[l]));
+      NACK(nalloc(N, &N->d[l], Vl * N->C[l]));
+      NACK(nalloc(N, &N->gup[l], Vl * N->C[l + 1]));
+      NACK(nalloc(N, &N->gsk[l], Vl * N->C[l]));
+    }
+  }
+  NACK(nalloc(N, &N->u, E));
+  NACK(nalloc(N, &N->du, E));
+  NACK(nalloc(N, &N->gn, N->g.nn));
+  NACK(nalloc(N, &N->lpart, nblk(N->g.nn)));
+  NACK(nalloc(N, &N->loss, 1));
+  NACK(nalloc(N, &N->hpart, (long long)nblk(E) * (N->C[0] + 1)));
+  // weight-gradient partials: at least one block of the largest layer, at
+  // most 16 Mi floats
+  N->wpart_cap = std::max<long long>(wmax, 16LL << 20);
+  NACK(nalloc(N, &N->wpart, N->wpart_cap));
+  N->bpart_cap = 512LL * 128;
+  NACK(nalloc(N, &N->bpart, N->bpart_cap));
+  NACK(pack_weights(N));
+  NHIP(hipStreamSynchronize(N->s));
   return MGAR_OK;
 }
 
@@ -485,88 +1030,15 @@ extern "C" {
 void mgar_net_destroy(mgar_net* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->s);   // work still queued on the network's stream reads these buffers
-  for (void* p : {(void*)n->theta, (void*)n->grad, (void*)n->m, (void*)n->v, (void*)n->in, (void*)n->a1,
-                  (void*)n->a2, (void*)n->pool, (void*)n->a3, (void*)n->a4, (void*)n->cat, (void*)n->a5,
-                  (void*)n->u, (void*)n->y, (void*)n->gU, (void*)n->gA5, (void*)n->gCat, (void*)n->gA4,
-                  (void*)n->gA3, (void*)n->gPool, (void*)n->gA2, (void*)n->gA1, (void*)n->part,
-                  (void*)n->loss, (void*)n->wpart})
-    if (p) (void)hipFree(p);
+  for (void* p : n->allocs) (void)hipFree(p);
   delete n;
 }
 
-static int net_create_impl(const mgar_params* p, int pool, int c1, int c2, void* stream, mgar_net* N) {
-  NACK(mgar_internal_validate(p));
-  if (p->dim != 3) return MGAR_E_ARG;
-  if (pool < 2 || (pool & 1) || c1 < 1 || c2 < 1 || c1 > 256 || c2 > 256) return MGAR_E_ARG;
-  if (p->nelx % (2 * pool) || p->nely % (2 * pool) || p->nelz % (2 * pool)) return MGAR_E_DIMS;
-  N->s = (hipStream_t)stream;
-  N->g = mgar_internal_geo(*p, 0);
-  N->f = pool;
-  N->W = p->nelx / pool;
-  N->H = p->nely / pool;
-  N->D = p->nelz / pool;
-  N->c1 = c1;
-  N->c2 = c2;
-  const int cos[6] = {c1, c1, c2, c2, c1, 1}, cis[6] = {2, c1, c1, c2, c2 + c1, c1};
-  long long off = 0;
-  for (int l = 0; l < 6; ++l) {
-    N->co[l] = cos[l];
-    N->ci[l] = cis[l];
-    N->woff[l] = off;
-    off += (long long)cos[l] * cis[l] * 27;
-    N->boff[l] = off;
-    off += cos[l];
-  }
-  N->np = off;
-  const long long V = (long long)N->D * N->H * N->W, V8 = V / 8;
-  NACK(nalloc(&N->theta, off));
-  NACK(nalloc(&N->grad, off));
-  NACK(nalloc(&N->m, off));
-  NACK(nalloc(&N->v, off));
-  NHIP(hipMemset(N->theta, 0, sizeof(float) * off));
-  NHIP(hipMemset(N->m, 0, sizeof(float) * off));
-  NHIP(hipMemset(N->v, 0, sizeof(float) * off));
-  NACK(nalloc(&N->in, 2 * V));
-  NACK(nalloc(&N->a1, c1 * V));
-  NACK(nalloc(&N->a2, c1 * V));
-  NACK(nalloc(&N->pool, c1 * V8));
-  NACK(nalloc(&N->a3, c2 * V8));
-  NACK(nalloc(&N->a4, c2 * V8));
-  NACK(nalloc(&N->cat, (c2 + c1) * V));
-  NACK(nalloc(&N->a5, c1 * V));
-  NACK(nalloc(&N->u, V));
-  NACK(nalloc(&N->y, V));
-  NACK(nalloc(&N->gU, V));
-  NACK(nalloc(&N->gA5, c1 * V));
-  NACK(nalloc(&N->gCat, (c2 + c1) * V));
-  NACK(nalloc(&N->gA4, c2 * V8));
-  NACK(nalloc(&N->gA3, c2 * V8));
-  NACK(nalloc(&N->gPool, c1 * V8));
-  NACK(nalloc(&N->gA2, c1 * V));
-  NACK(nalloc(&N->gA1, c1 * V));
-  NACK(nalloc(&N->part, nblk(V)));
-  NACK(nalloc(&N->loss, 1));
-  {
-    // layers 2 and 3 run on the pooled grid, the others on the cell grid
-    long long mx = 0;
-    for (int l = 0; l < 6; ++l) {
-      const bool half = l == 2 || l == 3;
-      int wz = 0, hy = 0;
-      const int S = half ? weight_slabs(N->D / 2, N->H / 2, N->W / 2, N->ci[l], N->co[l], &wz, &hy)
-                         : weight_slabs(N->D, N->H, N->W, N->ci[l], N->co[l], &wz, &hy);
-      if (S <= 0) return MGAR_E_ARG;   // cell grid too wide for the staged slab
-      mx = std::max(mx, (long long)N->co[l] * N->ci[l] * S);
-    }
-    NACK(nalloc(&N->wpart, mx * 28));
-  }
-  return MGAR_OK;
-}
-
-int mgar_net_create(const mgar_params* p, int pool, int c1, int c2, void* stream, mgar_net** out) {
+int mgar_net_create(const mgar_params* p, int levels, const int* channels, void* stream, mgar_net** out) {
   if (!p || !out) return MGAR_E_ARG;
   *out = nullptr;
   mgar_net* N = new mgar_net();
-  const int rc = net_create_impl(p, pool, c1, c2, stream, N);
+  const int rc = create_impl(N, p, levels, channels, stream);
   if (rc != MGAR_OK) {
     mgar_net_destroy(N);
     return rc;
@@ -575,12 +1047,24 @@ int mgar_net_create(const mgar_params* p, int pool, int c1, int c2, void* stream
   return MGAR_OK;
 }
 
-int mgar_net_sizes(const mgar_net* n, long long* nparams, int* cells) {
-  if (!n || !nparams || !cells) return MGAR_E_ARG;
+int mgar_net_sizes(const mgar_net* n, long long* nparams) {
+  if (!n || !nparams) return MGAR_E_ARG;
   *nparams = n->np;
-  cells[0] = n->D;
-  cells[1] = n->H;
-  cells[2] = n->W;
+  return MGAR_OK;
+}
+
+int mgar_net_set_source(mgar_net* n, const double* qe) {
+  if (!n || !qe) return MGAR_E_ARG;
+  const long long E = n->V[0];
+  std::vector<double> h((size_t)E);
+  NHIP(hipMemcpyAsync(h.data(), qe, sizeof(double) * (size_t)E, hipMemcpyDeviceToHost, n->s));
+  NHIP(hipStreamSynchronize(n->s));
+  double mx = 0.0;
+  for (double v : h) mx = std::max(mx, std::fabs(v));
+  std::vector<float> f((size_t)E);
+  for (long long e = 0; e < E; ++e) f[(size_t)e] = mx > 0.0 ? (float)(h[(size_t)e] / mx) : 0.0f;
+  NHIP(hipMemcpyAsync(n->src, f.data(), sizeof(float) * (size_t)E, hipMemcpyHostToDevice, n->s));
+  NHIP(hipStreamSynchronize(n->s));
   return MGAR_OK;
 }
 
@@ -589,6 +1073,7 @@ int mgar_net_set_params(mgar_net* n, const float* theta) {
   NHIP(hipMemcpyAsync(n->theta, theta, sizeof(float) * (size_t)n->np, hipMemcpyHostToDevice, n->s));
   NHIP(hipMemsetAsync(n->m, 0, sizeof(float) * (size_t)n->np, n->s));
   NHIP(hipMemsetAsync(n->v, 0, sizeof(float) * (size_t)n->np, n->s));
+  NACK(pack_weights(n));
   NHIP(hipStreamSynchronize(n->s));
   n->t = 0;
   return MGAR_OK;
@@ -604,23 +1089,22 @@ int mgar_net_get_params(const mgar_net* n, float* theta) {
 int mgar_net_infer(mgar_net* n, const double* xphys, double scale, double* T) {
   if (!n || !xphys || !T) return MGAR_E_ARG;
   NACK(forward(n, xphys));
-  k_net_to_nodes<<<nblk(n->g.nn), NB, 0, n->s>>>(n->g, n->u, n->f, n->D, n->H, n->W, scale, T);
+  hipLaunchKernelGGL(k_to_nodes, dim3(nblk(n->g.nn)), dim3(NB), 0, n->s, n->g, (const float*)n->u, scale, T);
   NLAUNCH();
   return MGAR_OK;
 }
 
 int mgar_net_output(const mgar_net* n, float* u) {
   if (!n || !u) return MGAR_E_ARG;
-  NHIP(hipMemcpyAsync(u, n->u, sizeof(float) * (size_t)n->D * n->H * n->W, hipMemcpyDeviceToHost, n->s));
+  NHIP(hipMemcpyAsync(u, n->u, sizeof(float) * (size_t)n->V[0], hipMemcpyDeviceToHost, n->s));
   NHIP(hipStreamSynchronize(n->s));
   return MGAR_OK;
 }
 
-int mgar_net_grad(mgar_net* n, const double* xphys, const double* T, double scale, float* grad,
-                  double* loss) {
+int mgar_net_grad(mgar_net* n, const double* xphys, const double* T, double scale, double* grad, double* loss) {
   if (!n || !xphys || !T || !(scale > 0.0)) return MGAR_E_ARG;
   NACK(loss_grad(n, xphys, T, scale));
-  if (grad) NHIP(hipMemcpyAsync(grad, n->grad, sizeof(float) * (size_t)n->np, hipMemcpyDeviceToHost, n->s));
+  if (grad) NHIP(hipMemcpyAsync(grad, n->grad, sizeof(double) * (size_t)n->np, hipMemcpyDeviceToHost, n->s));
   if (loss) NHIP(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->s));
   NHIP(hipStreamSynchronize(n->s));
   return MGAR_OK;
@@ -632,8 +1116,10 @@ int mgar_net_train_step(mgar_net* n, const double* xphys, const double* T, doubl
   NACK(loss_grad(n, xphys, T, scale));
   n->t += 1;
   const double c1 = 1.0 - std::pow(0.9, n->t), c2 = 1.0 - std::pow(0.999, n->t);
-  k_adam<<<nblk(n->np), NB, 0, n->s>>>(n->theta, n->m, n->v, n->grad, n->np, lr, c1, c2);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n->np)), dim3(NB), 0, n->s, n->theta, n->m, n->v, (const double*)n->grad,
+                     n->np, lr, c1, c2);
   NLAUNCH();
+  NACK(pack_weights(n));
   if (loss) {
     NHIP(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->s));
     NHIP(hipStreamSynchronize(n->s));

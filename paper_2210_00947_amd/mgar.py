@@ -34,7 +34,8 @@ EXPORTS = [
     "mgar_op_restrict", "mgar_op_prolong", "mgar_op_coarsen", "mgar_build_hierarchy",
     "mgar_vcycle", "mgar_op_dk", "mgar_op_bf16", "mgar_autotune", "mgar_tune_get",
     "mgar_tune_set", "mgar_set_graphs", "mgar_residual", "mgar_net_create", "mgar_net_destroy", "mgar_net_sizes",
-    "mgar_net_set_params", "mgar_net_get_params", "mgar_net_infer", "mgar_net_output", "mgar_net_grad",
+    "mgar_net_set_params", "mgar_net_get_params", "mgar_net_set_source", "mgar_net_infer", "mgar_net_output",
+    "mgar_net_grad",
     "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
     "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
     "mgar_profile", "mgar_profile_read", "mgar_residual_noalloc", "mgar_set_filter_radius",
@@ -440,24 +441,26 @@ class Batch:
 
 
 class Net:
-    """Owns one mgar_net (the learned initial guess); methods keep the C names."""
+    """Owns one mgar_net (the learned initial guess on the element grid);
+    methods keep the C names."""
 
-    def __init__(self, params: mgar_params, pool=4, c1=16, c2=32, stream=None):
+    def __init__(self, params: mgar_params, channels=(16, 32, 64, 64), stream=None):
         import torch
         self._L = lib()
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
+        ch = (ctypes.c_int * len(channels))(*[int(c) for c in channels])
         n = ctypes.c_void_p()
-        _check(self._L.mgar_net_create(ctypes.byref(params), int(pool), int(c1), int(c2),
-                                       ctypes.c_void_p(stream), ctypes.byref(n)), "mgar_net_create")
+        _check(self._L.mgar_net_create(ctypes.byref(params), len(channels), ch, ctypes.c_void_p(stream),
+                                       ctypes.byref(n)), "mgar_net_create")
         self.n = n
         npar = ctypes.c_longlong()
-        cells = (ctypes.c_int * 3)()
-        _check(self._L.mgar_net_sizes(self.n, ctypes.byref(npar), cells), "mgar_net_sizes")
+        _check(self._L.mgar_net_sizes(self.n, ctypes.byref(npar)), "mgar_net_sizes")
         self.nparams = npar.value
-        self.cells = tuple(cells)
+        self.channels = tuple(int(c) for c in channels)
         self.E = params.nelx * params.nely * params.nelz
         self.N = (params.nelx + 1) * (params.nely + 1) * (params.nelz + 1)
+        self.cells = (params.nelz, params.nely, params.nelx)
 
     def close(self):
         if getattr(self, "n", None):
@@ -469,6 +472,9 @@ class Net:
             self.close()
         except Exception:
             pass
+
+    def mgar_net_set_source(self, qe):
+        _check(self._L.mgar_net_set_source(self.n, _ptr(qe, self.E)), "mgar_net_set_source")
 
     def mgar_net_set_params(self, theta):
         import numpy as np
@@ -494,7 +500,7 @@ class Net:
 
     def mgar_net_grad(self, xphys, T, scale):
         import numpy as np
-        g = np.empty(self.nparams, dtype=np.float32)
+        g = np.empty(self.nparams, dtype=np.float64)
         loss = ctypes.c_double()
         _check(self._L.mgar_net_grad(self.n, _ptr(xphys, self.E), _ptr(T, self.N), ctypes.c_double(scale),
                                      g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)), "mgar_net_grad")

@@ -90,7 +90,8 @@ class TopOpt:
         prob.filter_r) or the continuous-filtering schedule (filter_radii).
         seed: None, or a dict enabling the learned
         initial guess with keys
-        pool, c1, c2 (network), train_until (cycles whose pairs train it; it is
+        channels (per level of the element-grid U-Net; default 16, 32, 64,
+        64), train_until (cycles whose pairs train it; it is
         used from the next cycle on), steps (Adam steps after cycle
         train_until), lr, init_seed, backoff (GuessSchedule on; default True),
         backoff_cap, lag (default 0: training runs when cycle train_until
@@ -133,7 +134,7 @@ class TopOpt:
         self.seed = None
         if seed is not None:
             import workloads as W
-            cfg = dict(pool=4, c1=16, c2=32, train_until=20, steps=120, lr=3e-3, init_seed=0,
+            cfg = dict(channels=(16, 32, 64, 64), train_until=20, steps=120, lr=1e-3, init_seed=0,
                        backoff=True, backoff_cap=16, lag=0)
             cfg.update(seed)
             self.seed = cfg
@@ -141,9 +142,10 @@ class TopOpt:
             # lag > 0: the network works on a stream of its own (default priority)
             self.net_stream = torch.cuda.Stream() if int(cfg["lag"]) > 0 else None
             self.train_done = None
-            self.net = M.Net(self.params, pool=cfg["pool"], c1=cfg["c1"], c2=cfg["c2"],
+            self.net = M.Net(self.params, channels=cfg["channels"],
                              stream=self.net_stream.cuda_stream if self.net_stream is not None else None)
-            self.net.mgar_net_set_params(W.net_init(cfg["c1"], cfg["c2"], seed=cfg["init_seed"]))
+            self.net.mgar_net_set_params(W.unet_init(cfg["channels"], seed=cfg["init_seed"]))
+            self.net.mgar_net_set_source(self.Qe)
             self.pairs = []
             self.Tseed = torch.zeros(N, **f64)
             self.train_losses = []

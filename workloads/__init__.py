@@ -246,21 +246,6 @@ def batched_designs(seed: int = 0, n2d: int = 48, n3d: int = 8) -> List[Problem]
     return out
 
 
-def net_init(c1: int, c2: int, seed: int = 0) -> np.ndarray:
-    """Initial parameters of the seed network (FP32): He-uniform weights per
-    layer (bound sqrt(6 / (27 ci))), zero biases, in the library's flat layout
-    (per layer [co][ci][3][3][3] weights then co biases; layers in order
-    2->c1, c1->c1, c1->c2, c2->c2, c2+c1->c1, c1->1)."""
-    rng = np.random.default_rng(SEED_BASE + 7000 + seed)
-    shapes = [(c1, 2), (c1, c1), (c2, c1), (c2, c2), (c1, c2 + c1), (1, c1)]
-    parts = []
-    for co, ci in shapes:
-        bound = np.sqrt(6.0 / (27 * ci))
-        parts.append(rng.uniform(-bound, bound, co * ci * 27))
-        parts.append(np.zeros(co))
-    return np.concatenate(parts).astype(np.float32)
-
-
 def unet_init(C, seed: int = 0) -> np.ndarray:
     """Initial parameters of the element-grid seed U-Net with channels C per
     level (FP32): He-uniform weights per layer (bound sqrt(6 / (k^3 ci))), zero

@@ -18,14 +18,18 @@ Prints one JSON line:
                  BF16 densities, FP32 inner PCG runs with FP64 residual
                  replacement, same 1e-8 FP64 residual test)
   learned_mixed  the mixed-precision MGAR loop with the learned initial guess
-                 (trained by the library's kernels on the pairs of cycles 2..20,
-                 in the background on its own stream during cycles 21..45,
-                 used from 46
+                 (the 4-level 16/32/64/64-channel U-Net on the element grid,
+                 trained by the library's kernels with 40 Adam steps over the
+                 pairs of cycles 2..20, in the background on its own stream
+                 during cycles 21..45, evaluated from 46 and used
                  when its true residual beats the previous temperature's;
                  after a losing cycle the guess is left out for 1, 2, 4 ..
                  16 cycles, a win resets the gap); training time is inside
                  the timed cycles, which are always N_on..maxit (10..80 at
                  128^3) whatever --steps says
+  seed_network   that U-Net alone at the workload's size: inference and one
+                 training step (events), convolution rate against the dense
+                 BF16 matrix-core peak (2.5 PFLOP/s)
   mgar_mixed     the MGAR loop in the mixed-precision form (one FP32 PCG run,
                  FP32 multigrid over BF16 densities, its residual replaced by
                  the FP64 one every 1e-3 of reduction, same 1e-8 FP64 residual
@@ -517,6 +521,54 @@ def stream_reference(torch, sizes, reps=30):
     return out
 
 
+SEED_CHANNELS = (16, 32, 64, 64)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def seed_network_timing(prob, W, M, torch, reps=10):
+    """The learned guess's U-Net on the workload's element grid: inference and
+    one Adam training step (forward, backward and update), timed with events
+    on the network's stream, and the convolutions' rate against the dense
+    BF16 matrix-core peak. FLOP counts are those of the 3x3x3 convolutions
+    (2 x voxels x in x out x 27 per layer; a training step counted as three
+    forward passes)."""
+    C = SEED_CHANNELS
+    net = M.Net(M.params_for(prob), channels=C)
+    net.mgar_net_set_params(W.unet_init(C, seed=0))
+    x = torch.as_tensor(W.reseeded_density(prob, 0), device="cuda")
+    T = torch.as_tensor(W.random_vector(prob.nnodes, 5), device="cuda").abs()
+    out = torch.empty_like(T)
+    L = len(C)
+    V = [prob.nelem >> (3 * l) for l in range(L)]
+    mac = 0
+    for l in range(L):
+        mac += V[l] * 27 * ((3 if l == 0 else C[l - 1]) * C[l] + C[l] * C[l])
+    for l in range(L - 2, -1, -1):
+        mac += V[l] * 27 * ((C[l + 1] + C[l]) * C[l] + C[l] * C[l])
+    fwd_flop = 2.0 * mac
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_inf = timed(lambda: net.mgar_net_infer(x, 1.0, out))
+    t_train = timed(lambda: net.mgar_net_train_step(x, T, 1.0, 1e-3, want_loss=False))
+    net.close()
+    return {"channels": list(C), "grid": [prob.nelx, prob.nely, prob.nelz], "forward_gflop": fwd_flop / 1e9,
+            "infer_ms": t_inf, "train_step_ms": t_train,
+            "infer_tflops": fwd_flop / t_inf / 1e9, "train_tflops": 3 * fwd_flop / t_train / 1e9,
+            "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+            "infer_frac": fwd_flop / t_inf / 1e9 / MFMA_BF16_PEAK_TFLOPS,
+            "train_frac": 3 * fwd_flop / t_train / 1e9 / MFMA_BF16_PEAK_TFLOPS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,13 +582,15 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (48 2D + 8 3D designs solved together)")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned+mixed loop (network trained on the pairs of cycles 2..20, used from 46)")
+                    help="skip the learned+mixed loop (U-Net trained on the pairs of cycles 2..20, evaluated from 46)")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the MGAR and MGCG loops in the paper's solver settings (eps1 0.5, eps2 1e-6)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision MGAR loop (FP32 multigrid over BF16 densities)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run the paper's Table 2 and Table 3 experiments in its settings (300 cycles each)")
+    ap.add_argument("--net-only", action="store_true",
+                    help="only time the learned guess's U-Net (inference and one training step) and exit")
     ap.add_argument("--oversize", type=int, default=0, metavar="N",
                     help="also run FP64 MGCG solves on an N^3 grid beyond the Infinity Cache (e.g. 256)")
     args = ap.parse_args()
@@ -552,6 +606,9 @@ def main():
 
     M.lib()
     prob = W.CONFIGS[args.config]
+    if args.net_only:
+        print(json.dumps({"seed_network": seed_network_timing(prob, W, M, torch)}), flush=True)
+        return
     nfix = 1
     for a in range(prob.dim):
         nfix *= prob.fix_hi[a] - prob.fix_lo[a] + 1
@@ -575,10 +632,16 @@ def main():
     full_steps = prob.maxit - full_warm
     full_cycles = f"{full_warm + 1}..{prob.maxit}"
     learned = None
+    net = None
     if not args.no_learned and prob.dim == 3:
+        seed_cfg = {"channels": SEED_CHANNELS, "train_until": 20, "steps": 40, "lr": 1e-3, "lag": 25}
         learned = run_loop(prob, True, full_warm, full_steps, W, TopOpt, torch, precision=M.PREC_MIXED,
-                           seed={"train_until": 20, "steps": 120, "lag": 25})
+                           seed=seed_cfg)
         learned["cycles"] = full_cycles
+        learned["seed_config"] = {k: (list(v) if isinstance(v, tuple) else v) for k, v in seed_cfg.items()}
+        net = seed_network_timing(prob, W, M, torch)
+        log(f"[bench] seed network at {prob.nelx}^3: inference {net['infer_ms']:.2f} ms, training step "
+            f"{net['train_step_ms']:.2f} ms ({net['train_tflops']:.0f} TFLOP/s)")
         log(f"[bench] learned+mixed MGAR loop, cycles {full_cycles}: {learned['s_per_opt_iter']*1e3:.3f} "
             f"ms/cycle, guess evaluated in {learned['seed_evaluated_cycles']} and used in "
             f"{learned['seed_used_cycles']} cycles")
@@ -666,6 +729,7 @@ def main():
         "mgcg": mgcg,
         "mgar_mixed": mixed,
         "learned_mixed": learned,
+        "seed_network": net,
         "batched": batch,
         "paper_setting": paper,
         "roofline": roof,

@@ -13,7 +13,9 @@ Prints one JSON line:
   ms_per_step    MGAR loop, milliseconds per optimisation cycle
   mgcg           the same figures for the plain-MGCG loop on the same GPU
   batched        48 2D + 8 3D designs of uneven sizes solved together (FP64),
-                 against the same solves one design at a time; batched.mixed
+                 with the block size of its launches from the batch tuner
+                 (tuned_block, block_us), against the same solves one design
+                 at a time; batched.mixed
                  the same in the mixed-precision form (FP32 multigrid over
                  BF16 densities, FP32 inner PCG runs with FP64 residual
                  replacement, same 1e-8 FP64 residual test)
@@ -219,6 +221,10 @@ def run_batched(W, M, torch, nsolves=5, precision=None):
     b.mgar_batch_load_vector(cat([W.element_source(p) for p in probs], b.elem_off), q)
     xs = [cat([W.reseeded_density(p, 31 * r + i) for i, p in enumerate(probs)], b.elem_off)
           for r in range(nsolves)]
+    # block size of the batched launches from the tuner (timed on a density
+    # set of its own, not one of the timed solves)
+    xtune = cat([W.reseeded_density(p, 1000 + i) for i, p in enumerate(probs)], b.elem_off)
+    block, block_us = b.mgar_batch_autotune(xtune, q, 1e-8, reps=3)
     T = torch.empty(b.N, dtype=torch.float64, device="cuda")
     b.mgcg_batch_solve(xs[0], q, None, 1e-8, T)       # warm-up (graph capture)
     torch.cuda.synchronize()
@@ -271,6 +277,7 @@ def run_batched(W, M, torch, nsolves=5, precision=None):
                                                      "fallback": sum(s["path"] == 2 for s in sa)},
         "one_by_one_mgcg_s_per_solve": stime, "one_by_one_dof_solves_per_s": free / stime,
         "speedup": stime / bt,
+        "tuned_block": block, "block_us": {str(k): v for k, v in block_us.items()},
     }
 
 

@@ -325,6 +325,20 @@ int mgar_batch_layout(const mgar_batch* b, long long* node_off, long long* elem_
 int mgar_batch_set_graph(mgar_batch* b, int use_graph);
 /* Per design, as mgar_load_vector. */
 int mgar_batch_load_vector(mgar_batch* b, const double* Qe, double* q);
+/* Threads per block of every node-parallel launch of the batch (64, 128 or
+ * 256; 256 after setup): the work lists are rebuilt (the call waits for the
+ * batch's stream) and captured iterations are dropped. The arithmetic of every
+ * node is the same for every block size; the order in which block partials
+ * of a dot product are summed differs. */
+int mgar_batch_set_block(mgar_batch* b, int bs);
+int mgar_batch_get_block(const mgar_batch* b, int* bs);
+/* Autotuner of the batched launches: times a batched MGCG solve from T0 = 0
+ * of (xphys, q) to tol (reps times after one warm-up, HIP events on the
+ * batch's stream) for blocks of 256, 128 and 64 threads and keeps the fastest
+ * (*bs_out; us_out, if not NULL, receives the three mean times in
+ * microseconds in that order). Allocates one N-vector for its own solves. */
+int mgar_batch_autotune(mgar_batch* b, const double* xphys, const double* q, double tol, int reps, int* bs_out,
+                        float* us_out);
 /* Per design, as mgcg_solve (T0 may be NULL = 0) and mgar_solve (requires a
  * previous mgcg_batch_solve: MGAR_E_STATE otherwise). Returns MGAR_OK,
  * MGAR_W_NOT_CONVERGED if any design hit cg_max, or an error. In the batched

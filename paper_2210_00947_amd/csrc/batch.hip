@@ -53,6 +53,7 @@ static_assert(sizeof(BCgState) % sizeof(int) == 0, "BCgState stride");
 static_assert(sizeof(MgarDev) % sizeof(double) == 0, "MgarDev stride");
 constexpr int ITERS_PER_GRAPH = 4;
 constexpr int REFINE_MAX = 40;   // FP64 residual replacements per mixed solve
+constexpr int BATCH_MIN_BS = 64;  // smallest block of the node-parallel launches
 
 template <typename T>
 int dalloc(T** p, long long n) {
@@ -67,6 +68,7 @@ struct ItemList {
   std::vector<BItem> h;
   BItem* d = nullptr;
   int nblk = 0;
+  int bs = 256;            // threads (nodes) per block of its launches
   int n() const { return (int)h.size(); }
 };
 
@@ -125,7 +127,7 @@ BItem make_item(const Geo& g, const Geo& gc, long long off, long long coff, long
   return it;
 }
 
-int blocks_of(long long n) { return (int)((n + 255) / 256); }
+int blocks_of(long long n, int bs) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
 
@@ -141,6 +143,7 @@ struct mgar_batch {
   int basis_x0_zero = 0;
   bool has_k0 = false;
   bool use_graph = true;
+  int bs = 256;            // threads per block of the node-parallel launches (tuned)
   // finest-grid concatenations
   double *kcur = nullptr, *k0 = nullptr;
   double *qm = nullptr, *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cw = nullptr;
@@ -198,15 +201,15 @@ int bvcycle(mgar_batch* B, Group& G, const double* b0, const double* x0, double*
     double* rtl = (l == 0) ? B->rt0 : G.rt[l];
     const double* kl = (l == 0) ? B->k0 : G.k[l];
     if (l == 0 && x0)
-      launch_bstencil(G.dim, SM_JACOBI, D.d, D.n(), D.nblk, x0, kl, nullptr, bl, xal, B->omega, nullptr,
+      launch_bstencil(G.dim, SM_JACOBI, D.d, D.n(), D.nblk, D.bs, x0, kl, nullptr, bl, xal, B->omega, nullptr,
                       skip, ss, B->s);
     else
-      launch_bstencil(G.dim, SM_JACOBI0, D.d, D.n(), D.nblk, bl, kl, nullptr, bl, xal, B->omega, nullptr,
+      launch_bstencil(G.dim, SM_JACOBI0, D.d, D.n(), D.nblk, D.bs, bl, kl, nullptr, bl, xal, B->omega, nullptr,
                       skip, ss, B->s);
-    launch_bstencil(G.dim, SM_RESID, D.d, D.n(), D.nblk, xal, kl, nullptr, bl, rtl, B->omega, nullptr,
+    launch_bstencil(G.dim, SM_RESID, D.d, D.n(), D.nblk, D.bs, xal, kl, nullptr, bl, rtl, B->omega, nullptr,
                     skip, ss, B->s);
     ItemList& Rs = G.restr[l];
-    launch_brestrict(G.dim, Rs.d, Rs.n(), Rs.nblk, rtl, G.b[l + 1], skip, ss, B->s);
+    launch_brestrict(G.dim, Rs.d, Rs.n(), Rs.nblk, Rs.bs, rtl, G.b[l + 1], skip, ss, B->s);
   }
   launch_bvtail(G.dim, G.tails, G.ntails, G.tail_lds, B->omega, skip, ss, B->s);
   for (int l = G.maxlt - 1; l >= 0; --l) {
@@ -216,10 +219,10 @@ int bvcycle(mgar_batch* B, Group& G, const double* b0, const double* x0, double*
     double* xal = (l == 0) ? B->xa0 : G.xa[l];
     const double* kl = (l == 0) ? B->k0 : G.k[l];
     ItemList& P = G.prol[l];
-    launch_bprolong(G.dim, P.d, P.n(), P.nblk, G.xb[l + 1], xal, skip, ss, B->s);
+    launch_bprolong(G.dim, P.d, P.n(), P.nblk, P.bs, G.xb[l + 1], xal, skip, ss, B->s);
     double* o = (l == 0) ? out : G.xb[l];
     const int mode = (l == 0 && part) ? SM_JACOBI_DOT : SM_JACOBI;
-    launch_bstencil(G.dim, mode, D.d, D.n(), D.nblk, xal, kl, nullptr, bl, o, B->omega, part, skip, ss,
+    launch_bstencil(G.dim, mode, D.d, D.n(), D.nblk, D.bs, xal, kl, nullptr, bl, o, B->omega, part, skip, ss,
                     B->s);
   }
   BLAUNCH();
@@ -229,10 +232,10 @@ int bvcycle(mgar_batch* B, Group& G, const double* b0, const double* x0, double*
 // K0 := K(kcur) for every design of G whose keep flag is 0 (all with keep null):
 // finest cells, cell means of every coarser grid, coarsest inverses.
 int bbuild(mgar_batch* B, Group& G, const int* keep) {
-  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, B->kcur, B->k0, keep, 1, B->s);
+  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, G.cells.bs, B->kcur, B->k0, keep, 1, B->s);
   for (int l = 0; l + 1 < G.maxL; ++l) {
     ItemList& C = G.coarsen[l];
-    launch_bcoarsen(G.dim, C.d, C.n(), C.nblk, (l == 0) ? B->k0 : G.k[l], G.k[l + 1], keep, 1, B->s);
+    launch_bcoarsen(G.dim, C.d, C.n(), C.nblk, C.bs, (l == 0) ? B->k0 : G.k[l], G.k[l + 1], keep, 1, B->s);
   }
   launch_bcoarse_build(G.dim, G.cb_reg, G.n_reg, true, B->status, keep, 1, B->s);
   launch_bcoarse_build(G.dim, G.cb_gen, G.n_gen, false, B->status, keep, 1, B->s);
@@ -249,12 +252,12 @@ int biter(mgar_batch* B, Group& G, double tol) {
   BACK(bvcycle(B, G, B->cr, nullptr, B->cz, B->pb, skip));
   launch_bfinalize(F.d, F.n(), B->pb, 1, rz, (int)(sizeof(BCgState) / sizeof(double)), &B->st[0].it, skip,
                    ST_STRIDE, B->s);
-  launch_bp_update(F.d, F.n(), F.nblk, B->cz, B->cp, B->st, B->s);
-  launch_bstencil(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, B->cp, B->kcur, nullptr, nullptr, B->cw, 0.0,
+  launch_bp_update(F.d, F.n(), F.nblk, F.bs, B->cz, B->cp, B->st, B->s);
+  launch_bstencil(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, F.bs, B->cp, B->kcur, nullptr, nullptr, B->cw, 0.0,
                   B->pc, skip, ST_STRIDE, B->s);
   launch_bfinalize(F.d, F.n(), B->pc, 1, &B->st[0].pw, (int)(sizeof(BCgState) / sizeof(double)), nullptr,
                    skip, ST_STRIDE, B->s);
-  launch_bcg_update(F.d, F.n(), F.nblk, B->cx, B->cr, B->cp, B->cw, B->st, B->pa, B->s);
+  launch_bcg_update(F.d, F.n(), F.nblk, F.bs, B->cx, B->cr, B->cp, B->cw, B->st, B->pa, B->s);
   launch_bcg_check(F.d, F.n(), B->st, B->pa, tol, B->cg_max, B->s);
   BLAUNCH();
   return MGAR_OK;
@@ -269,10 +272,10 @@ CellB cells_b(const mgar_batch* B, const uint16_t* d) { return CellB{d, B->kmin_
 void bst32(mgar_batch* B, Group& G, int l, int mode, const ItemList& D, const float* x, const float* b,
            float* out, double* part, const int* skip) {
   if (l == 0)
-    launch_bstencil_t<float, CellB>(G.dim, mode, D.d, D.n(), D.nblk, x, cells_b(B, B->dens0),
+    launch_bstencil_t<float, CellB>(G.dim, mode, D.d, D.n(), D.nblk, D.bs, x, cells_b(B, B->dens0),
                                     cells_b(B, nullptr), b, out, B->omega, part, skip, ST_STRIDE, B->s);
   else
-    launch_bstencil_t<float, CellF>(G.dim, mode, D.d, D.n(), D.nblk, x, CellF{G.kf[l]}, CellF{nullptr}, b,
+    launch_bstencil_t<float, CellF>(G.dim, mode, D.d, D.n(), D.nblk, D.bs, x, CellF{G.kf[l]}, CellF{nullptr}, b,
                                     out, B->omega, part, skip, ST_STRIDE, B->s);
 }
 
@@ -291,7 +294,7 @@ int bvcycle32(mgar_batch* B, Group& G, const float* b0, const float* x0, float* 
     else bst32(B, G, l, SM_JACOBI0, D, bl, bl, xal, nullptr, skip);
     bst32(B, G, l, SM_RESID, D, xal, bl, rtl, nullptr, skip);
     ItemList& Rs = G.restr[l];
-    launch_brestrict_t<float>(G.dim, Rs.d, Rs.n(), Rs.nblk, rtl, G.bf[l + 1], skip, ss, B->s);
+    launch_brestrict_t<float>(G.dim, Rs.d, Rs.n(), Rs.nblk, Rs.bs, rtl, G.bf[l + 1], skip, ss, B->s);
   }
   launch_bvtail_t<float>(G.dim, G.tails, G.ntails, G.tail_lds, B->omega, skip, ss, B->s);
   for (int l = G.maxlt - 1; l >= 0; --l) {
@@ -300,7 +303,7 @@ int bvcycle32(mgar_batch* B, Group& G, const float* b0, const float* x0, float* 
     const float* bl = (l == 0) ? b0 : G.bf[l];
     float* xal = (l == 0) ? B->xa32 : G.xaf[l];
     ItemList& P = G.prol[l];
-    launch_bprolong_t<float>(G.dim, P.d, P.n(), P.nblk, G.xbf[l + 1], xal, skip, ss, B->s);
+    launch_bprolong_t<float>(G.dim, P.d, P.n(), P.nblk, P.bs, G.xbf[l + 1], xal, skip, ss, B->s);
     float* o = (l == 0) ? out : G.xbf[l];
     bst32(B, G, l, (l == 0 && part) ? SM_JACOBI_DOT : SM_JACOBI, D, xal, bl, o, part, skip);
   }
@@ -312,14 +315,14 @@ int bvcycle32(mgar_batch* B, Group& G, const float* b0, const float* x0, float* 
 // and FP64 cells of the finest grid (the latter for the -dK products of the
 // reanalysis), FP32 cell means below, FP64 coarsest inverses.
 int bbuild32(mgar_batch* B, Group& G, const int* keep) {
-  launch_bcopy_cells_t<uint16_t>(G.cells.d, G.cells.n(), G.cells.nblk, B->dens, B->dens0, keep, 1, B->s);
-  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, B->kcur, B->k0, keep, 1, B->s);
+  launch_bcopy_cells_t<uint16_t>(G.cells.d, G.cells.n(), G.cells.nblk, G.cells.bs, B->dens, B->dens0, keep, 1, B->s);
+  launch_bcopy_cells(G.cells.d, G.cells.n(), G.cells.nblk, G.cells.bs, B->kcur, B->k0, keep, 1, B->s);
   for (int l = 0; l + 1 < G.maxL; ++l) {
     ItemList& C = G.coarsen[l];
     if (l == 0)
-      launch_bcoarsen_t<CellB, float>(G.dim, C.d, C.n(), C.nblk, cells_b(B, B->dens0), G.kf[1], keep, 1, B->s);
+      launch_bcoarsen_t<CellB, float>(G.dim, C.d, C.n(), C.nblk, C.bs, cells_b(B, B->dens0), G.kf[1], keep, 1, B->s);
     else
-      launch_bcoarsen_t<CellF, float>(G.dim, C.d, C.n(), C.nblk, CellF{G.kf[l]}, G.kf[l + 1], keep, 1, B->s);
+      launch_bcoarsen_t<CellF, float>(G.dim, C.d, C.n(), C.nblk, C.bs, CellF{G.kf[l]}, G.kf[l + 1], keep, 1, B->s);
   }
   launch_bcoarse_build_t<CellF>(G.dim, G.cb_reg, G.n_reg, true, B->status, keep, 1, B->s);
   launch_bcoarse_build_t<CellF>(G.dim, G.cb_gen, G.n_gen, false, B->status, keep, 1, B->s);
@@ -336,12 +339,12 @@ int biter32(mgar_batch* B, Group& G, double tol) {
   BACK(bvcycle32(B, G, B->r32, nullptr, B->z32, B->pb, skip));
   launch_bfinalize(F.d, F.n(), B->pb, 1, rz, (int)(sizeof(BCgState) / sizeof(double)), &B->st[0].it, skip,
                    ST_STRIDE, B->s);
-  launch_bp_update_t<float>(F.d, F.n(), F.nblk, B->z32, B->p32, B->st, B->s);
-  launch_bstencil_t<float, CellF>(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, B->p32, CellF{B->k32},
+  launch_bp_update_t<float>(F.d, F.n(), F.nblk, F.bs, B->z32, B->p32, B->st, B->s);
+  launch_bstencil_t<float, CellF>(G.dim, SM_APPLY_DOT, F.d, F.n(), F.nblk, F.bs, B->p32, CellF{B->k32},
                                   CellF{nullptr}, nullptr, B->w32, 0.0, B->pc, skip, ST_STRIDE, B->s);
   launch_bfinalize(F.d, F.n(), B->pc, 1, &B->st[0].pw, (int)(sizeof(BCgState) / sizeof(double)), nullptr,
                    skip, ST_STRIDE, B->s);
-  launch_bcg_update_t<float>(F.d, F.n(), F.nblk, B->d32, B->r32, B->p32, B->w32, B->st, B->pa, B->s);
+  launch_bcg_update_t<float>(F.d, F.n(), F.nblk, F.bs, B->d32, B->r32, B->p32, B->w32, B->st, B->pa, B->s);
   launch_bcg_check(F.d, F.n(), B->st, B->pa, tol, B->cg_max, B->s);
   BLAUNCH();
   return MGAR_OK;
@@ -392,10 +395,10 @@ int run_until_done(mgar_batch* B, int cls, double tol) {
 int bpcg(mgar_batch* B, double tol, const int* keep_done) {
   for (Group& G : B->grp) {
     ItemList& F = G.fine;
-    launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
+    launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, F.bs, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
                     nullptr, 0, B->s);
-    launch_bdot(F.d, F.n(), F.nblk, B->cr, B->cr, B->pa, nullptr, 0, B->s);
-    launch_bdot(F.d, F.n(), F.nblk, B->qm, B->qm, B->pb, nullptr, 0, B->s);
+    launch_bdot(F.d, F.n(), F.nblk, F.bs, B->cr, B->cr, B->pa, nullptr, 0, B->s);
+    launch_bdot(F.d, F.n(), F.nblk, F.bs, B->qm, B->qm, B->pb, nullptr, 0, B->s);
     launch_bcg_init(F.d, F.n(), B->st, B->pb, B->pa, tol, B->cg_max, keep_done, B->s);
   }
   BLAUNCH();
@@ -416,7 +419,7 @@ int bsolve_mixed(mgar_batch* B, double tol, const int* keep_done) {
   launch_cast_f32(B->kcur, B->k32, B->E, B->s);
   for (Group& G : B->grp) {
     ItemList& F = G.fine;
-    launch_bdot(F.d, F.n(), F.nblk, B->qm, B->qm, B->pb, nullptr, 0, B->s);
+    launch_bdot(F.d, F.n(), F.nblk, F.bs, B->qm, B->qm, B->pb, nullptr, 0, B->s);
     launch_bfinalize(F.d, F.n(), B->pb, 1, B->nq, 1, nullptr, nullptr, 0, B->s);
   }
   B->h_odone.assign(nd, 0);
@@ -435,9 +438,9 @@ int bsolve_mixed(mgar_batch* B, double tol, const int* keep_done) {
   for (;;) {
     for (Group& G : B->grp) {
       ItemList& F = G.fine;
-      launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
+      launch_bstencil(G.dim, SM_RESID, F.d, F.n(), F.nblk, F.bs, B->cx, B->kcur, nullptr, B->qm, B->cr, 0.0, nullptr,
                       B->odone, 1, B->s);
-      launch_bdot(F.d, F.n(), F.nblk, B->cr, B->cr, B->pa, B->odone, 1, B->s);
+      launch_bdot(F.d, F.n(), F.nblk, F.bs, B->cr, B->cr, B->pa, B->odone, 1, B->s);
       launch_bfinalize(F.d, F.n(), B->pa, 1, B->nr, 1, nullptr, B->odone, 1, B->s);
     }
     BLAUNCH();
@@ -459,8 +462,8 @@ int bsolve_mixed(mgar_batch* B, double tol, const int* keep_done) {
     BHIP(hipMemsetAsync(B->d32, 0, sizeof(float) * N, B->s));
     for (Group& G : B->grp) {
       ItemList& F = G.fine;
-      launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, B->cr, B->r32, B->s);
-      launch_bdot_t<float>(F.d, F.n(), F.nblk, B->r32, B->r32, B->pa, nullptr, 0, B->s);
+      launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, F.bs, B->cr, B->r32, B->s);
+      launch_bdot_t<float>(F.d, F.n(), F.nblk, F.bs, B->r32, B->r32, B->pa, nullptr, 0, B->s);
       launch_bcg_init(F.d, F.n(), B->st, B->pa, B->pa, B->inner_tol, B->cg_max, B->odone, B->s);
     }
     BLAUNCH();
@@ -548,6 +551,64 @@ void mgar_batch_destroy(mgar_batch* b) {
   if (b->ein) (void)hipEventDestroy(b->ein);
   if (b->own_stream && b->s) (void)hipStreamDestroy(b->s);
   delete b;
+}
+
+// (Re)build the work lists of every group for blocks of bs threads (one
+// node, element or coarse node per thread); captured iterations refer to the
+// old lists and are dropped.
+static int build_lists(mgar_batch* B, int bs) {
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
+  for (int c = 0; c < 2; ++c) {
+    if (B->gexec[c]) { (void)hipGraphExecDestroy(B->gexec[c]); B->gexec[c] = nullptr; }
+    if (B->graph[c]) { (void)hipGraphDestroy(B->graph[c]); B->graph[c] = nullptr; }
+    B->tol_captured[c] = -1.0;
+  }
+  for (Group& G : B->grp) {
+    for (auto* v : {&G.down, &G.restr, &G.prol, &G.coarsen})
+      for (ItemList& L : *v) f(L.d);
+    f(G.fine.d);
+    f(G.cells.d);
+    G.fine = ItemList();
+    G.cells = ItemList();
+    G.down.assign(G.maxL, ItemList());
+    G.restr.assign(G.maxL, ItemList());
+    G.prol.assign(G.maxL, ItemList());
+    G.coarsen.assign(G.maxL, ItemList());
+    for (int i : G.designs) {
+      Design& D = B->d[i];
+      const Geo& g0 = D.g[0];
+      G.fine.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, batch_item_blocks(g0, bs)));
+      G.cells.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, blocks_of(g0.ne, bs)));
+      for (int l = 0; l < D.L; ++l) {
+        const long long off = (l == 0) ? D.noff : D.aoff[l];
+        const long long eo = (l == 0) ? D.eoff : D.aeoff[l];
+        if (l < D.lt) {
+          const Geo &gf = D.g[l], &gc = D.g[l + 1];
+          G.down[l].h.push_back(make_item(gf, gf, off, 0, eo, 0, i, batch_item_blocks(gf, bs)));
+          G.restr[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                           batch_item_blocks(gc, bs)));
+          G.prol[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                          batch_item_blocks(gc, bs)));
+        }
+        if (l + 1 < D.L) {
+          const Geo &gf = D.g[l], &gc = D.g[l + 1];
+          G.coarsen[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
+                                             blocks_of(gc.ne, bs)));
+        }
+      }
+    }
+    G.fine.bs = G.cells.bs = bs;
+    BACK(upload(G.fine));
+    BACK(upload(G.cells));
+    for (int l = 0; l < G.maxL; ++l) {
+      for (ItemList* L : {&G.down[l], &G.restr[l], &G.prol[l], &G.coarsen[l]}) {
+        L->bs = bs;
+        BACK(upload(*L));
+      }
+    }
+  }
+  B->bs = bs;
+  return MGAR_OK;
 }
 
 static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_batch* B) {
@@ -699,43 +760,8 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
     if (G.n_reg) BHIP(hipMemcpy(G.cb_reg, creg.data(), sizeof(BCoarse) * creg.size(), hipMemcpyHostToDevice));
     if (G.n_gen) BHIP(hipMemcpy(G.cb_gen, cgen.data(), sizeof(BCoarse) * cgen.size(), hipMemcpyHostToDevice));
     if ((size_t)G.tail_lds * esz > 64 * 1024) return MGAR_E_DIMS;
-    // work lists
-    G.down.resize(G.maxL);
-    G.restr.resize(G.maxL);
-    G.prol.resize(G.maxL);
-    G.coarsen.resize(G.maxL);
-    for (int i : G.designs) {
-      Design& D = B->d[i];
-      const Geo& g0 = D.g[0];
-      G.fine.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, batch_item_blocks(g0)));
-      G.cells.h.push_back(make_item(g0, g0, D.noff, 0, D.eoff, 0, i, blocks_of(g0.ne)));
-      for (int l = 0; l < D.L; ++l) {
-        const long long off = (l == 0) ? D.noff : D.aoff[l];
-        const long long eo = (l == 0) ? D.eoff : D.aeoff[l];
-        if (l < D.lt) {
-          const Geo &gf = D.g[l], &gc = D.g[l + 1];
-          G.down[l].h.push_back(make_item(gf, gf, off, 0, eo, 0, i, batch_item_blocks(gf)));
-          G.restr[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
-                                           batch_item_blocks(gc)));
-          G.prol[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
-                                          batch_item_blocks(gc)));
-        }
-        if (l + 1 < D.L) {
-          const Geo &gf = D.g[l], &gc = D.g[l + 1];
-          G.coarsen[l].h.push_back(make_item(gf, gc, off, D.aoff[l + 1], eo, D.aeoff[l + 1], i,
-                                             blocks_of(gc.ne)));
-        }
-      }
-    }
-    BACK(upload(G.fine));
-    BACK(upload(G.cells));
-    for (int l = 0; l < G.maxL; ++l) {
-      BACK(upload(G.down[l]));
-      BACK(upload(G.restr[l]));
-      BACK(upload(G.prol[l]));
-      BACK(upload(G.coarsen[l]));
-    }
   }
+  BACK(build_lists(B, 256));
   // finest-grid workspace
   const long long N = B->N, E = B->E;
   BACK(dalloc(&B->kcur, E));
@@ -745,8 +771,13 @@ static int batch_setup_impl(const mgar_params* p, int nd, void* stream, mgar_bat
     for (double** v : {&B->xa0, &B->rt0}) BACK(dalloc(v, N));
   BACK(dalloc(&B->R, N * B->m));
   BACK(dalloc(&B->Wm, N * B->m));
+  // block partials: sized for the smallest block size a list may be built with
   long long nb = 0;
-  for (Group& G : B->grp) nb = std::max<long long>(nb, G.fine.nblk);
+  for (Group& G : B->grp) {
+    long long n = 0;
+    for (int i : G.designs) n += batch_item_blocks(B->d[i].g[0], BATCH_MIN_BS);
+    nb = std::max(nb, n);
+  }
   const long long nv = (long long)B->m * (B->m + 1) / 2 + B->m;
   BACK(dalloc(&B->pa, nb * std::max<long long>(nv, 8)));
   BACK(dalloc(&B->pb, nb * std::max<long long>(nv, 8)));
@@ -815,6 +846,58 @@ int mgar_batch_set_graph(mgar_batch* b, int use_graph) {
   return MGAR_OK;
 }
 
+int mgar_batch_set_block(mgar_batch* b, int bs) {
+  if (!b || (bs != 64 && bs != 128 && bs != 256)) return MGAR_E_ARG;
+  if (bs == b->bs) return MGAR_OK;
+  BHIP(hipStreamSynchronize(b->s));   // queued work reads the lists being replaced
+  return build_lists(b, bs);
+}
+
+int mgar_batch_get_block(const mgar_batch* b, int* bs) {
+  if (!b || !bs) return MGAR_E_ARG;
+  *bs = b->bs;
+  return MGAR_OK;
+}
+
+int mgar_batch_autotune(mgar_batch* b, const double* xphys, const double* q, double tol, int reps, int* bs_out,
+                        float* us_out) {
+  if (!b || !xphys || !q || reps < 1) return MGAR_E_ARG;
+  static const int cand[3] = {256, 128, 64};
+  double* T = nullptr;
+  BHIP(hipMalloc((void**)&T, sizeof(double) * (size_t)b->N));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MGAR_OK;
+  int best = 256;
+  float best_ms = -1.0f;
+  auto run = [&]() -> int {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MGAR_E_HIP;
+    for (int c = 0; c < 3; ++c) {
+      BACK(mgar_batch_set_block(b, cand[c]));
+      const int w = mgcg_batch_solve(b, xphys, q, nullptr, tol, T, nullptr);   // warm-up and graph capture
+      if (w < 0) return w;
+      BHIP(hipEventRecord(e0, b->s));
+      for (int r = 0; r < reps; ++r) {
+        const int rr = mgcg_batch_solve(b, xphys, q, nullptr, tol, T, nullptr);
+        if (rr < 0) return rr;
+      }
+      BHIP(hipEventRecord(e1, b->s));
+      BHIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      BHIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)reps;
+      if (us_out) us_out[c] = 1e3f * ms;
+      if (best_ms < 0.f || ms < best_ms) { best_ms = ms; best = cand[c]; }
+    }
+    return mgar_batch_set_block(b, best);
+  };
+  rc = run();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(T);
+  if (rc == MGAR_OK && bs_out) *bs_out = best;
+  return rc;
+}
+
 int mgar_batch_load_vector(mgar_batch* b, const double* Qe, double* q) {
   if (!b || !Qe || !q) return MGAR_E_ARG;
   BACK(enter(b));
@@ -835,8 +918,8 @@ int mgcg_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
   BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
   for (Group& G : b->grp) {
     BACK(b->mixed ? bbuild32(b, G, nullptr) : bbuild(b, G, nullptr));
-    launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, q, b->qm, b->s);
-    if (T0) launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, T0, b->cx, b->s);
+    launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, G.fine.bs, q, b->qm, b->s);
+    if (T0) launch_bmask_copy(G.fine.d, G.fine.n(), G.fine.nblk, G.fine.bs, T0, b->cx, b->s);
   }
   if (!T0) BHIP(hipMemsetAsync(b->cx, 0, sizeof(double) * b->N, b->s));
   BLAUNCH();
@@ -861,21 +944,21 @@ int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
   BHIP(hipMemsetAsync(b->status, 0, sizeof(int) * b->nd, b->s));
   for (Group& G : b->grp) {
     ItemList& F = G.fine;
-    launch_bmask_copy(F.d, F.n(), F.nblk, q, b->qm, b->s);
+    launch_bmask_copy(F.d, F.n(), F.nblk, F.bs, q, b->qm, b->s);
     // r_1 = t_prev, r_i = MG(K0, -dK r_{i-1}, x0) (Eq 17)
-    if (T0) launch_bmask_copy(F.d, F.n(), F.nblk, T0, b->R, b->s);
+    if (T0) launch_bmask_copy(F.d, F.n(), F.nblk, F.bs, T0, b->R, b->s);
     else BHIP(hipMemsetAsync(b->R, 0, sizeof(double) * N, b->s));
     for (int i = 1; i < m; ++i) {
       const double* prev = b->R + (long long)(i - 1) * N;
-      launch_bstencil(G.dim, SM_NEG_DK, F.d, F.n(), F.nblk, prev, b->kcur, b->k0, nullptr, b->cz, 0.0,
+      launch_bstencil(G.dim, SM_NEG_DK, F.d, F.n(), F.nblk, F.bs, prev, b->kcur, b->k0, nullptr, b->cz, 0.0,
                       nullptr, nullptr, 0, b->s);
       if (b->mixed) {
         // -dK r in FP64 (a difference of nearby operators), one FP32 V-cycle
         // on the BF16 K0 hierarchy, the column kept in FP64
-        launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, b->cz, b->z32, b->s);
-        if (!b->basis_x0_zero) launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, prev, b->p32, b->s);
+        launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, F.bs, b->cz, b->z32, b->s);
+        if (!b->basis_x0_zero) launch_bmask_copy_t<double, float>(F.d, F.n(), F.nblk, F.bs, prev, b->p32, b->s);
         BACK(bvcycle32(b, G, b->z32, b->basis_x0_zero ? nullptr : b->p32, b->w32, nullptr, nullptr));
-        launch_bmask_copy_t<float, double>(F.d, F.n(), F.nblk, b->w32, b->R + (long long)i * N, b->s);
+        launch_bmask_copy_t<float, double>(F.d, F.n(), F.nblk, F.bs, b->w32, b->R + (long long)i * N, b->s);
       } else {
         BACK(bvcycle(b, G, b->cz, b->basis_x0_zero ? nullptr : prev, b->R + (long long)i * N, nullptr,
                      nullptr));
@@ -884,31 +967,31 @@ int mgar_batch_solve(mgar_batch* b, const double* xphys, const double* q, const 
     // Gram-Schmidt applied twice per column (same rule as the single path)
     for (int j = 0; j < m; ++j) {
       double* v = b->R + (long long)j * N;
-      launch_bdot(F.d, F.n(), F.nblk, v, v, b->pa, nullptr, 0, b->s);
+      launch_bdot(F.d, F.n(), F.nblk, F.bs, v, v, b->pa, nullptr, 0, b->s);
       launch_bfinalize(F.d, F.n(), b->pa, 1, mdd + offsetof(MgarDev, n0) / sizeof(double) + j, mds, nullptr,
                        nullptr, 0, b->s);
       if (j > 0) {
         for (int pass = 0; pass < 2; ++pass) {
-          launch_bmultidot(F.d, F.n(), F.nblk, b->R, N, j, v, b->pa, b->s);
+          launch_bmultidot(F.d, F.n(), F.nblk, F.bs, b->R, N, j, v, b->pa, b->s);
           launch_bfinalize(F.d, F.n(), b->pa, j, mdd + offsetof(MgarDev, c) / sizeof(double), mds, nullptr,
                            nullptr, 0, b->s);
-          launch_bgs_update(F.d, F.n(), F.nblk, v, b->R, N, j, b->md, b->s);
+          launch_bgs_update(F.d, F.n(), F.nblk, F.bs, v, b->R, N, j, b->md, b->s);
         }
       }
-      launch_bdot(F.d, F.n(), F.nblk, v, v, b->pa, nullptr, 0, b->s);
+      launch_bdot(F.d, F.n(), F.nblk, F.bs, v, v, b->pa, nullptr, 0, b->s);
       launch_bfinalize(F.d, F.n(), b->pa, 1, b->nrm, 1, nullptr, nullptr, 0, b->s);
-      launch_bgs_normalize(F.d, F.n(), F.nblk, v, b->md, j, b->nrm, 1, b->s);
+      launch_bgs_normalize(F.d, F.n(), F.nblk, F.bs, v, b->md, j, b->nrm, 1, b->s);
     }
     // Eq 19-21 and Eq 28
     for (int j = 0; j < m; ++j)
-      launch_bstencil(G.dim, SM_APPLY, F.d, F.n(), F.nblk, b->R + (long long)j * N, b->kcur, nullptr, nullptr,
+      launch_bstencil(G.dim, SM_APPLY, F.d, F.n(), F.nblk, F.bs, b->R + (long long)j * N, b->kcur, nullptr, nullptr,
                       b->Wm + (long long)j * N, 0.0, nullptr, nullptr, 0, b->s);
-    launch_bgram(F.d, F.n(), F.nblk, b->R, b->Wm, b->qm, N, m, b->pa, b->s);
+    launch_bgram(F.d, F.n(), F.nblk, F.bs, b->R, b->Wm, b->qm, N, m, b->pa, b->s);
     launch_bgram_finalize(F.d, F.n(), b->pa, m, b->md, b->s);
-    launch_bcombine(F.d, F.n(), F.nblk, b->R, b->Wm, b->qm, N, m, b->md, b->cx, b->pa, b->s);
+    launch_bcombine(F.d, F.n(), F.nblk, F.bs, b->R, b->Wm, b->qm, N, m, b->md, b->cx, b->pa, b->s);
     launch_bfinalize(F.d, F.n(), b->pa, 1, mdd + offsetof(MgarDev, res2) / sizeof(double), mds, nullptr,
                      nullptr, 0, b->s);
-    launch_bdot(F.d, F.n(), F.nblk, b->qm, b->qm, b->pb, nullptr, 0, b->s);
+    launch_bdot(F.d, F.n(), F.nblk, F.bs, b->qm, b->qm, b->pb, nullptr, 0, b->s);
     launch_bfinalize(F.d, F.n(), b->pb, 1, mdd + offsetof(MgarDev, qq) / sizeof(double), mds, nullptr,
                      nullptr, 0, b->s);
     launch_bdecide(F.d, F.n(), b->md, b->st, b->eps, b->keep, b->path, b->res, b->s);

@@ -305,23 +305,23 @@ struct BCoarse {
 // skip (may be null): a block of design d returns at once when
 // skip[d * sstride] != 0 (e.g. &BCgState::done of converged designs).
 // stencil.hip
-int batch_item_blocks(const Geo& g);   // blocks of one item of a node-parallel launch
+int batch_item_blocks(const Geo& g, int bs);   // blocks of one item of a node-parallel launch
 // Value-type forms: T = double with CellD, T = float with CellF or CellB (the
 // loader is moved to each design's cells). Coarsening from CellD to double
 // or from CellB / CellF to float; tails of T; coarsest builds from CellD or
 // CellF cells (the inverse is FP64 either way).
 template <typename T, typename CL>
-void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, const T* x, CL k, CL kref,
+void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, int bs, const T* x, CL k, CL kref,
                        const T* b, T* out, double omega, double* part, const int* skip, int sstride,
                        hipStream_t s);
 template <typename T>
-void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, const T* rf, T* rc, const int* skip,
+void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, int bs, const T* rf, T* rc, const int* skip,
                         int sstride, hipStream_t s);
 template <typename T>
-void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, const T* xc, T* xf, const int* skip,
+void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, int bs, const T* xc, T* xf, const int* skip,
                        int sstride, hipStream_t s);
 template <typename CL, typename TO>
-void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, CL kf, TO* kc, const int* skip,
+void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, int bs, CL kf, TO* kc, const int* skip,
                        int sstride, hipStream_t s);
 template <typename T>
 void launch_bvtail_t(int dim, const BTail* jobs, int njobs, int lds_elems, double omega, const int* skip,
@@ -329,26 +329,26 @@ void launch_bvtail_t(int dim, const BTail* jobs, int njobs, int lds_elems, doubl
 template <typename CL>
 void launch_bcoarse_build_t(int dim, const BCoarse* jobs, int njobs, bool reg, int* status, const int* skip,
                             int sstride, hipStream_t s);
-void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
+void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, int bs, const double* x,
                      const double* k, const double* kref, const double* b, double* out, double omega,
                      double* part, const int* skip, int sstride, hipStream_t s);
-void launch_brestrict(int dim, const BItem* items, int nit, int nblk, const double* rf, double* rc,
+void launch_brestrict(int dim, const BItem* items, int nit, int nblk, int bs, const double* rf, double* rc,
                       const int* skip, int sstride, hipStream_t s);
-void launch_bprolong(int dim, const BItem* items, int nit, int nblk, const double* xc, double* xf,
+void launch_bprolong(int dim, const BItem* items, int nit, int nblk, int bs, const double* xc, double* xf,
                      const int* skip, int sstride, hipStream_t s);
-void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const double* kf, double* kc,
+void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, int bs, const double* kf, double* kc,
                      const int* skip, int sstride, hipStream_t s);
-void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
+void launch_bmask_copy(const BItem* items, int nit, int nblk, int bs, const double* in, double* out,
                        hipStream_t s);
 // (double, float) and (float, double) conversions; fixed nodes become 0
 template <typename TI, typename TO>
-void launch_bmask_copy_t(const BItem* items, int nit, int nblk, const TI* in, TO* out, hipStream_t s);
+void launch_bmask_copy_t(const BItem* items, int nit, int nblk, int bs, const TI* in, TO* out, hipStream_t s);
 void launch_bvtail(int dim, const BTail* jobs, int njobs, int lds_elems, double omega,
                    const int* skip, int sstride, hipStream_t s);
 void launch_bcoarse_build(int dim, const BCoarse* jobs, int njobs, bool reg, int* status,
                           const int* skip, int sstride, hipStream_t s);
 // vec.hip (items of the finest grid; vectors concatenated per design)
-void launch_bdot(const BItem* items, int nit, int nblk, const double* a, const double* b,
+void launch_bdot(const BItem* items, int nit, int nblk, int bs, const double* a, const double* b,
                  double* part, const int* skip, int sstride, hipStream_t s);
 // out[d * ostride + v] = sum of design d's partials of value v (nv values per
 // block); with itsel, the target is shifted by (itsel[d * sstride] & 1).
@@ -357,23 +357,23 @@ void launch_bfinalize(const BItem* items, int nit, const double* part, int nv, d
 void launch_bcg_init(const BItem* items, int nit, BCgState* st, const double* part_qq,
                      const double* part_rr, double tol, int cg_max, const int* keep_done,
                      hipStream_t s);
-void launch_bp_update(const BItem* items, int nit, int nblk, const double* z, double* p,
+void launch_bp_update(const BItem* items, int nit, int nblk, int bs, const double* z, double* p,
                       const BCgState* st, hipStream_t s);
-void launch_bcg_update(const BItem* items, int nit, int nblk, double* x, double* r, const double* p,
+void launch_bcg_update(const BItem* items, int nit, int nblk, int bs, double* x, double* r, const double* p,
                        const double* w, const BCgState* st, double* part, hipStream_t s);
 void launch_bcg_check(const BItem* items, int nit, BCgState* st, const double* part, double tol,
                       int cg_max, hipStream_t s);
-void launch_bmultidot(const BItem* items, int nit, int nblk, const double* Q, long long ld, int nc,
+void launch_bmultidot(const BItem* items, int nit, int nblk, int bs, const double* Q, long long ld, int nc,
                       const double* v, double* part, hipStream_t s);
-void launch_bgs_update(const BItem* items, int nit, int nblk, double* v, const double* Q, long long ld,
+void launch_bgs_update(const BItem* items, int nit, int nblk, int bs, double* v, const double* Q, long long ld,
                        int nc, const MgarDev* md, hipStream_t s);
-void launch_bgs_normalize(const BItem* items, int nit, int nblk, double* v, MgarDev* md, int col,
+void launch_bgs_normalize(const BItem* items, int nit, int nblk, int bs, double* v, MgarDev* md, int col,
                           const double* nrm2, int nstride, hipStream_t s);
-void launch_bgram(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+void launch_bgram(const BItem* items, int nit, int nblk, int bs, const double* Q, const double* W,
                   const double* q, long long ld, int m, double* part, hipStream_t s);
 void launch_bgram_finalize(const BItem* items, int nit, const double* part, int m, MgarDev* md,
                            hipStream_t s);
-void launch_bcombine(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+void launch_bcombine(const BItem* items, int nit, int nblk, int bs, const double* Q, const double* W,
                      const double* q, long long ld, int m, MgarDev* md, double* t, double* part,
                      hipStream_t s);
 // per design: Res = sqrt(res2 / qq); accept (path 1) when Res <= eps: the
@@ -381,21 +381,21 @@ void launch_bcombine(const BItem* items, int nit, int nblk, const double* Q, con
 // path 2 and keep[d] = 0 (K0 renewed, MGCG runs). res_out[d] = Res.
 void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, double eps, int* keep,
                     int* path, double* res_out, hipStream_t s);
-void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
+void launch_bcopy_cells(const BItem* items, int nit, int nblk, int bs, const double* a, double* b,
                         const int* skip, int sstride, hipStream_t s);
 // FP32 forms of the PCG vector kernels (inner products accumulated in FP64)
 // and a copy of BF16 cells.
 template <typename T>
-void launch_bdot_t(const BItem* items, int nit, int nblk, const T* a, const T* b, double* part,
+void launch_bdot_t(const BItem* items, int nit, int nblk, int bs, const T* a, const T* b, double* part,
                    const int* skip, int sstride, hipStream_t s);
 template <typename T>
-void launch_bp_update_t(const BItem* items, int nit, int nblk, const T* z, T* p, const BCgState* st,
+void launch_bp_update_t(const BItem* items, int nit, int nblk, int bs, const T* z, T* p, const BCgState* st,
                         hipStream_t s);
 template <typename T>
-void launch_bcg_update_t(const BItem* items, int nit, int nblk, T* x, T* r, const T* p, const T* w,
+void launch_bcg_update_t(const BItem* items, int nit, int nblk, int bs, T* x, T* r, const T* p, const T* w,
                          const BCgState* st, double* part, hipStream_t s);
 template <typename T>
-void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, const T* a, T* b, const int* skip,
+void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, int bs, const T* a, T* b, const int* skip,
                           int sstride, hipStream_t s);
 
 // smooth.hip -----------------------------------------------------------------

@@ -2072,7 +2072,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_stencil(const BItem* __restrict__
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo g = it.g;
-  const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  const long long n = (long long)(blockIdx.x - it.first) * (blockDim.x * blockDim.y) + flat_tid();
   const double d = stencil_b_point<DIM, MODE, T, CL>(
       g, n, x + it.off, cl_at(k, it.eoff), cl_at(kref.p ? kref : k, it.eoff),
       b ? b + it.off : x + it.off, out + it.off, omega);
@@ -2089,7 +2089,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_restrict(const BItem* __restrict_
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
-  restrict_b_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+  restrict_b_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (blockDim.x * blockDim.y) + flat_tid(),
                            rf + it.off, rc + it.coff);
 }
 
@@ -2100,7 +2100,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_prolong(const BItem* __restrict__
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
-  prolong_b8_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid(),
+  prolong_b8_point<DIM, T>(gf, gc, (long long)(blockIdx.x - it.first) * (blockDim.x * blockDim.y) + flat_tid(),
                            xc + it.coff, xf + it.off);
 }
 
@@ -2113,7 +2113,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_coarsen(const BItem* __restrict__
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   if (bskip(skip, sstride, it.design)) return;
   const Geo gf = it.g, gc = it.gc;
-  const long long e = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  const long long e = (long long)(blockIdx.x - it.first) * (blockDim.x * blockDim.y) + flat_tid();
   if (e >= gc.ne) return;
   const int ex = (int)(e % gc.nx);
   const long long r = e / gc.nx;
@@ -2133,7 +2133,7 @@ __global__ __launch_bounds__(TBX* TBY) void kb_mask_copy(const BItem* __restrict
                                                          const TI* __restrict__ in, TO* __restrict__ out) {
   const BItem& it = items[bitem_find(items, nit, blockIdx.x)];
   const Geo g = it.g;
-  const long long n = (long long)(blockIdx.x - it.first) * (TBX * TBY) + flat_tid();
+  const long long n = (long long)(blockIdx.x - it.first) * (blockDim.x * blockDim.y) + flat_tid();
   if (n >= g.nn) return;
   int i, j, k;
   node_ijk(g, n, i, j, k);
@@ -2474,14 +2474,14 @@ template void launch_mask_copy_t<float, double>(const Geo&, const float*, double
 
 // ---------------------------------------------------------------- batched launchers
 
-int batch_item_blocks(const Geo& g) { return (int)((g.nn + TBX * TBY - 1) / (TBX * TBY)); }
+int batch_item_blocks(const Geo& g, int bs) { return (int)((g.nn + bs - 1) / bs); }
 
 template <typename T, typename CL>
-void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, const T* x, CL k, CL kref,
+void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk, int bs, const T* x, CL k, CL kref,
                        const T* b, T* out, double omega, double* part, const int* skip, int sstride,
                        hipStream_t s) {
   if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
+  const dim3 blk(bs, 1, 1);
 #define BCALL(D, M) \
   kb_stencil<D, M, T, CL><<<nblk, blk, 0, s>>>(items, nit, x, k, kref, b, out, (T)omega, part, skip, sstride)
 #define BMODES(D)                                                 \
@@ -2498,88 +2498,88 @@ void launch_bstencil_t(int dim, int mode, const BItem* items, int nit, int nblk,
 #undef BMODES
 #undef BCALL
 }
-template void launch_bstencil_t<double, CellD>(int, int, const BItem*, int, int, const double*, CellD, CellD,
+template void launch_bstencil_t<double, CellD>(int, int, const BItem*, int, int, int, const double*, CellD, CellD,
                                                const double*, double*, double, double*, const int*, int,
                                                hipStream_t);
-template void launch_bstencil_t<float, CellF>(int, int, const BItem*, int, int, const float*, CellF, CellF,
+template void launch_bstencil_t<float, CellF>(int, int, const BItem*, int, int, int, const float*, CellF, CellF,
                                               const float*, float*, double, double*, const int*, int,
                                               hipStream_t);
-template void launch_bstencil_t<float, CellB>(int, int, const BItem*, int, int, const float*, CellB, CellB,
+template void launch_bstencil_t<float, CellB>(int, int, const BItem*, int, int, int, const float*, CellB, CellB,
                                               const float*, float*, double, double*, const int*, int,
                                               hipStream_t);
 
-void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, const double* x,
+void launch_bstencil(int dim, int mode, const BItem* items, int nit, int nblk, int bs, const double* x,
                      const double* k, const double* kref, const double* b, double* out, double omega,
                      double* part, const int* skip, int sstride, hipStream_t s) {
-  launch_bstencil_t<double, CellD>(dim, mode, items, nit, nblk, x, CellD{k}, CellD{kref}, b, out, omega, part,
+  launch_bstencil_t<double, CellD>(dim, mode, items, nit, nblk, bs, x, CellD{k}, CellD{kref}, b, out, omega, part,
                                    skip, sstride, s);
 }
 
 template <typename T>
-void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, const T* rf, T* rc, const int* skip,
+void launch_brestrict_t(int dim, const BItem* items, int nit, int nblk, int bs, const T* rf, T* rc, const int* skip,
                         int sstride, hipStream_t s) {
   if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
+  const dim3 blk(bs, 1, 1);
   if (dim == 2) kb_restrict<2, T><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
   else kb_restrict<3, T><<<nblk, blk, 0, s>>>(items, nit, rf, rc, skip, sstride);
 }
-template void launch_brestrict_t<double>(int, const BItem*, int, int, const double*, double*, const int*, int,
+template void launch_brestrict_t<double>(int, const BItem*, int, int, int, const double*, double*, const int*, int,
                                          hipStream_t);
-template void launch_brestrict_t<float>(int, const BItem*, int, int, const float*, float*, const int*, int,
+template void launch_brestrict_t<float>(int, const BItem*, int, int, int, const float*, float*, const int*, int,
                                         hipStream_t);
 
 template <typename T>
-void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, const T* xc, T* xf, const int* skip,
+void launch_bprolong_t(int dim, const BItem* items, int nit, int nblk, int bs, const T* xc, T* xf, const int* skip,
                        int sstride, hipStream_t s) {
   if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
+  const dim3 blk(bs, 1, 1);
   if (dim == 2) kb_prolong<2, T><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
   else kb_prolong<3, T><<<nblk, blk, 0, s>>>(items, nit, xc, xf, skip, sstride);
 }
-template void launch_bprolong_t<double>(int, const BItem*, int, int, const double*, double*, const int*, int,
+template void launch_bprolong_t<double>(int, const BItem*, int, int, int, const double*, double*, const int*, int,
                                         hipStream_t);
-template void launch_bprolong_t<float>(int, const BItem*, int, int, const float*, float*, const int*, int,
+template void launch_bprolong_t<float>(int, const BItem*, int, int, int, const float*, float*, const int*, int,
                                        hipStream_t);
 
 template <typename CL, typename TO>
-void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, CL kf, TO* kc, const int* skip,
+void launch_bcoarsen_t(int dim, const BItem* items, int nit, int nblk, int bs, CL kf, TO* kc, const int* skip,
                        int sstride, hipStream_t s) {
   if (nblk <= 0) return;
-  const dim3 blk(TBX, TBY, 1);
+  const dim3 blk(bs, 1, 1);
   if (dim == 2) kb_coarsen<2, CL, TO><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
   else kb_coarsen<3, CL, TO><<<nblk, blk, 0, s>>>(items, nit, kf, kc, skip, sstride);
 }
-template void launch_bcoarsen_t<CellD, double>(int, const BItem*, int, int, CellD, double*, const int*, int,
+template void launch_bcoarsen_t<CellD, double>(int, const BItem*, int, int, int, CellD, double*, const int*, int,
                                                hipStream_t);
-template void launch_bcoarsen_t<CellB, float>(int, const BItem*, int, int, CellB, float*, const int*, int,
+template void launch_bcoarsen_t<CellB, float>(int, const BItem*, int, int, int, CellB, float*, const int*, int,
                                               hipStream_t);
-template void launch_bcoarsen_t<CellF, float>(int, const BItem*, int, int, CellF, float*, const int*, int,
+template void launch_bcoarsen_t<CellF, float>(int, const BItem*, int, int, int, CellF, float*, const int*, int,
                                               hipStream_t);
 
-void launch_brestrict(int dim, const BItem* items, int nit, int nblk, const double* rf, double* rc,
+void launch_brestrict(int dim, const BItem* items, int nit, int nblk, int bs, const double* rf, double* rc,
                       const int* skip, int sstride, hipStream_t s) {
-  launch_brestrict_t<double>(dim, items, nit, nblk, rf, rc, skip, sstride, s);
+  launch_brestrict_t<double>(dim, items, nit, nblk, bs, rf, rc, skip, sstride, s);
 }
-void launch_bprolong(int dim, const BItem* items, int nit, int nblk, const double* xc, double* xf,
+void launch_bprolong(int dim, const BItem* items, int nit, int nblk, int bs, const double* xc, double* xf,
                      const int* skip, int sstride, hipStream_t s) {
-  launch_bprolong_t<double>(dim, items, nit, nblk, xc, xf, skip, sstride, s);
+  launch_bprolong_t<double>(dim, items, nit, nblk, bs, xc, xf, skip, sstride, s);
 }
-void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, const double* kf, double* kc,
+void launch_bcoarsen(int dim, const BItem* items, int nit, int nblk, int bs, const double* kf, double* kc,
                      const int* skip, int sstride, hipStream_t s) {
-  launch_bcoarsen_t<CellD, double>(dim, items, nit, nblk, CellD{kf}, kc, skip, sstride, s);
+  launch_bcoarsen_t<CellD, double>(dim, items, nit, nblk, bs, CellD{kf}, kc, skip, sstride, s);
 }
 
 template <typename TI, typename TO>
-void launch_bmask_copy_t(const BItem* items, int nit, int nblk, const TI* in, TO* out, hipStream_t s) {
+void launch_bmask_copy_t(const BItem* items, int nit, int nblk, int bs, const TI* in, TO* out, hipStream_t s) {
   if (nblk <= 0) return;
-  kb_mask_copy<TI, TO><<<nblk, dim3(TBX, TBY, 1), 0, s>>>(items, nit, in, out);
+  kb_mask_copy<TI, TO><<<nblk, dim3(bs, 1, 1), 0, s>>>(items, nit, in, out);
 }
-template void launch_bmask_copy_t<double, float>(const BItem*, int, int, const double*, float*, hipStream_t);
-template void launch_bmask_copy_t<float, double>(const BItem*, int, int, const float*, double*, hipStream_t);
+template void launch_bmask_copy_t<double, float>(const BItem*, int, int, int, const double*, float*, hipStream_t);
+template void launch_bmask_copy_t<float, double>(const BItem*, int, int, int, const float*, double*, hipStream_t);
 
-void launch_bmask_copy(const BItem* items, int nit, int nblk, const double* in, double* out,
+void launch_bmask_copy(const BItem* items, int nit, int nblk, int bs, const double* in, double* out,
                        hipStream_t s) {
-  launch_bmask_copy_t<double, double>(items, nit, nblk, in, out, s);
+  launch_bmask_copy_t<double, double>(items, nit, nblk, bs, in, out, s);
 }
 
 template <typename T>

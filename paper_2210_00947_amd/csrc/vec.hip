@@ -680,7 +680,7 @@ __global__ __launch_bounds__(VB) void kb_dot(const BItem* __restrict__ items, in
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
   if (vb_skip(skip, sstride, it.design)) return;
   const long long n = it.g.nn;
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   const double s = block_sum(i < n ? (double)a[it.off + i] * (double)b[it.off + i] : 0.0, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(VB) void kb_p_update(const BItem* __restrict__ item
   const BCgState& s = st[it.design];
   if (s.done) return;
   const int k = s.it;
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   if (i >= it.g.nn) return;
   const long long n = it.off + i;
   if (k == 0) p[n] = z[n];
@@ -756,7 +756,7 @@ __global__ __launch_bounds__(VB) void kb_cg_update(const BItem* __restrict__ ite
   const BCgState& s = st[it.design];
   if (s.done) return;
   const T alpha = (T)(s.rz[s.it & 1] / s.pw);
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   double v = 0.0;
   if (i < it.g.nn) {
     const long long n = it.off + i;
@@ -796,7 +796,7 @@ __global__ __launch_bounds__(VB) void kb_multidot(const BItem* __restrict__ item
                                                   double* __restrict__ part) {
   __shared__ double sh[VB / MGAR_WAVE];
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   const bool in = i < it.g.nn;
   const long long n = it.off + i;
   const double vi = in ? v[n] : 0.0;
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(VB) void kb_gs_update(const BItem* __restrict__ ite
                                                    double* __restrict__ v, const double* __restrict__ Q,
                                                    long long ld, const MgarDev* __restrict__ md) {
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   if (i >= it.g.nn) return;
   const long long n = it.off + i;
   const double* c = md[it.design].c;
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(VB) void kb_gs_normalize(const BItem* __restrict__ 
   const double n1 = sqrt(nrm2[(long long)it.design * nstride]);
   const bool keep = (n0 > 0.0) && (n1 >= 1e-10 * n0);
   const double sc = keep ? 1.0 / n1 : 0.0;
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   if (i < it.g.nn) {
     const long long n = it.off + i;
     v[n] = keep ? v[n] * sc : 0.0;
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(VB) void kb_gram(const BItem* __restrict__ items, i
   __shared__ double sh[VB / MGAR_WAVE];
   constexpr int NV = M * (M + 1) / 2 + M;
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   const bool in = i < it.g.nn;
   const long long n = it.off + i;
   double qa[M], wa[M];
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(VB) void kb_combine(const BItem* __restrict__ items
     }
   }
   __syncthreads();
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (i < it.g.nn) {
     const long long n = it.off + i;
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(VB) void kb_copy_cells(const BItem* __restrict__ it
                                                     const int* __restrict__ skip, int sstride) {
   const BItem& it = items[vb_find(items, nit, blockIdx.x)];
   if (vb_skip(skip, sstride, it.design)) return;
-  const long long i = (long long)(blockIdx.x - it.first) * VB + threadIdx.x;
+  const long long i = (long long)(blockIdx.x - it.first) * blockDim.x + threadIdx.x;
   if (i < it.g.ne) b[it.eoff + i] = a[it.eoff + i];
 }
 
@@ -1172,15 +1172,15 @@ void launch_copy_u16(const uint16_t* a, uint16_t* b, long long n, hipStream_t s)
 // ---------------------------------------------------------------- batched launchers
 
 template <typename T>
-void launch_bdot_t(const BItem* items, int nit, int nblk, const T* a, const T* b, double* part,
+void launch_bdot_t(const BItem* items, int nit, int nblk, int bs, const T* a, const T* b, double* part,
                    const int* skip, int sstride, hipStream_t s) {
-  if (nblk > 0) kb_dot<T><<<nblk, VB, 0, s>>>(items, nit, a, b, part, skip, sstride);
+  if (nblk > 0) kb_dot<T><<<nblk, bs, 0, s>>>(items, nit, a, b, part, skip, sstride);
 }
-template void launch_bdot_t<float>(const BItem*, int, int, const float*, const float*, double*, const int*,
+template void launch_bdot_t<float>(const BItem*, int, int, int, const float*, const float*, double*, const int*,
                                    int, hipStream_t);
-void launch_bdot(const BItem* items, int nit, int nblk, const double* a, const double* b,
+void launch_bdot(const BItem* items, int nit, int nblk, int bs, const double* a, const double* b,
                  double* part, const int* skip, int sstride, hipStream_t s) {
-  launch_bdot_t<double>(items, nit, nblk, a, b, part, skip, sstride, s);
+  launch_bdot_t<double>(items, nit, nblk, bs, a, b, part, skip, sstride, s);
 }
 void launch_bfinalize(const BItem* items, int nit, const double* part, int nv, double* out,
                       int ostride, const int* itsel, const int* skip, int sstride, hipStream_t s) {
@@ -1192,53 +1192,53 @@ void launch_bcg_init(const BItem* items, int nit, BCgState* st, const double* pa
   if (nit > 0) kb_cg_init<<<nit, FB, 0, s>>>(items, st, part_qq, part_rr, tol, cg_max, keep_done);
 }
 template <typename T>
-void launch_bp_update_t(const BItem* items, int nit, int nblk, const T* z, T* p, const BCgState* st,
+void launch_bp_update_t(const BItem* items, int nit, int nblk, int bs, const T* z, T* p, const BCgState* st,
                         hipStream_t s) {
-  if (nblk > 0) kb_p_update<T><<<nblk, VB, 0, s>>>(items, nit, z, p, st);
+  if (nblk > 0) kb_p_update<T><<<nblk, bs, 0, s>>>(items, nit, z, p, st);
 }
-template void launch_bp_update_t<float>(const BItem*, int, int, const float*, float*, const BCgState*,
+template void launch_bp_update_t<float>(const BItem*, int, int, int, const float*, float*, const BCgState*,
                                         hipStream_t);
 template <typename T>
-void launch_bcg_update_t(const BItem* items, int nit, int nblk, T* x, T* r, const T* p, const T* w,
+void launch_bcg_update_t(const BItem* items, int nit, int nblk, int bs, T* x, T* r, const T* p, const T* w,
                          const BCgState* st, double* part, hipStream_t s) {
-  if (nblk > 0) kb_cg_update<T><<<nblk, VB, 0, s>>>(items, nit, x, r, p, w, st, part);
+  if (nblk > 0) kb_cg_update<T><<<nblk, bs, 0, s>>>(items, nit, x, r, p, w, st, part);
 }
-template void launch_bcg_update_t<float>(const BItem*, int, int, float*, float*, const float*, const float*,
+template void launch_bcg_update_t<float>(const BItem*, int, int, int, float*, float*, const float*, const float*,
                                          const BCgState*, double*, hipStream_t);
-void launch_bp_update(const BItem* items, int nit, int nblk, const double* z, double* p,
+void launch_bp_update(const BItem* items, int nit, int nblk, int bs, const double* z, double* p,
                       const BCgState* st, hipStream_t s) {
-  launch_bp_update_t<double>(items, nit, nblk, z, p, st, s);
+  launch_bp_update_t<double>(items, nit, nblk, bs, z, p, st, s);
 }
-void launch_bcg_update(const BItem* items, int nit, int nblk, double* x, double* r, const double* p,
+void launch_bcg_update(const BItem* items, int nit, int nblk, int bs, double* x, double* r, const double* p,
                        const double* w, const BCgState* st, double* part, hipStream_t s) {
-  launch_bcg_update_t<double>(items, nit, nblk, x, r, p, w, st, part, s);
+  launch_bcg_update_t<double>(items, nit, nblk, bs, x, r, p, w, st, part, s);
 }
 void launch_bcg_check(const BItem* items, int nit, BCgState* st, const double* part, double tol,
                       int cg_max, hipStream_t s) {
   if (nit > 0) kb_cg_check<<<nit, FB, 0, s>>>(items, st, part, tol, cg_max);
 }
-void launch_bmultidot(const BItem* items, int nit, int nblk, const double* Q, long long ld, int nc,
+void launch_bmultidot(const BItem* items, int nit, int nblk, int bs, const double* Q, long long ld, int nc,
                       const double* v, double* part, hipStream_t s) {
   if (nblk <= 0 || nc <= 0) return;
-#define CALL(M) kb_multidot<M><<<nblk, VB, 0, s>>>(items, nit, Q, ld, v, part)
+#define CALL(M) kb_multidot<M><<<nblk, bs, 0, s>>>(items, nit, Q, ld, v, part)
   MGAR_DISPATCH_M(nc, CALL)
 #undef CALL
 }
-void launch_bgs_update(const BItem* items, int nit, int nblk, double* v, const double* Q, long long ld,
+void launch_bgs_update(const BItem* items, int nit, int nblk, int bs, double* v, const double* Q, long long ld,
                        int nc, const MgarDev* md, hipStream_t s) {
   if (nblk <= 0 || nc <= 0) return;
-#define CALL(M) kb_gs_update<M><<<nblk, VB, 0, s>>>(items, nit, v, Q, ld, md)
+#define CALL(M) kb_gs_update<M><<<nblk, bs, 0, s>>>(items, nit, v, Q, ld, md)
   MGAR_DISPATCH_M(nc, CALL)
 #undef CALL
 }
-void launch_bgs_normalize(const BItem* items, int nit, int nblk, double* v, MgarDev* md, int col,
+void launch_bgs_normalize(const BItem* items, int nit, int nblk, int bs, double* v, MgarDev* md, int col,
                           const double* nrm2, int nstride, hipStream_t s) {
-  if (nblk > 0) kb_gs_normalize<<<nblk, VB, 0, s>>>(items, nit, v, md, col, nrm2, nstride);
+  if (nblk > 0) kb_gs_normalize<<<nblk, bs, 0, s>>>(items, nit, v, md, col, nrm2, nstride);
 }
-void launch_bgram(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+void launch_bgram(const BItem* items, int nit, int nblk, int bs, const double* Q, const double* W,
                   const double* q, long long ld, int m, double* part, hipStream_t s) {
   if (nblk <= 0) return;
-#define CALL(M) kb_gram<M><<<nblk, VB, 0, s>>>(items, nit, Q, W, q, ld, part)
+#define CALL(M) kb_gram<M><<<nblk, bs, 0, s>>>(items, nit, Q, W, q, ld, part)
   MGAR_DISPATCH_M(m, CALL)
 #undef CALL
 }
@@ -1246,11 +1246,11 @@ void launch_bgram_finalize(const BItem* items, int nit, const double* part, int 
                            hipStream_t s) {
   if (nit > 0) kb_gram_finalize<<<nit, FB, 0, s>>>(items, part, m, md);
 }
-void launch_bcombine(const BItem* items, int nit, int nblk, const double* Q, const double* W,
+void launch_bcombine(const BItem* items, int nit, int nblk, int bs, const double* Q, const double* W,
                      const double* q, long long ld, int m, MgarDev* md, double* t, double* part,
                      hipStream_t s) {
   if (nblk <= 0) return;
-#define CALL(M) kb_combine<M><<<nblk, VB, 0, s>>>(items, nit, Q, W, q, ld, md, t, part)
+#define CALL(M) kb_combine<M><<<nblk, bs, 0, s>>>(items, nit, Q, W, q, ld, md, t, part)
   MGAR_DISPATCH_M(m, CALL)
 #undef CALL
 }
@@ -1259,13 +1259,13 @@ void launch_bdecide(const BItem* items, int nit, MgarDev* md, BCgState* st, doub
   if (nit > 0) kb_decide<<<(nit + 63) / 64, 64, 0, s>>>(items, nit, md, st, eps, keep, path, res_out);
 }
 template <typename T>
-void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, const T* a, T* b, const int* skip,
+void launch_bcopy_cells_t(const BItem* items, int nit, int nblk, int bs, const T* a, T* b, const int* skip,
                           int sstride, hipStream_t s) {
-  if (nblk > 0) kb_copy_cells<T><<<nblk, VB, 0, s>>>(items, nit, a, b, skip, sstride);
+  if (nblk > 0) kb_copy_cells<T><<<nblk, bs, 0, s>>>(items, nit, a, b, skip, sstride);
 }
-template void launch_bcopy_cells_t<uint16_t>(const BItem*, int, int, const uint16_t*, uint16_t*, const int*,
+template void launch_bcopy_cells_t<uint16_t>(const BItem*, int, int, int, const uint16_t*, uint16_t*, const int*,
                                              int, hipStream_t);
-void launch_bcopy_cells(const BItem* items, int nit, int nblk, const double* a, double* b,
+void launch_bcopy_cells(const BItem* items, int nit, int nblk, int bs, const double* a, double* b,
                         const int* skip, int sstride, hipStream_t s) {
-  launch_bcopy_cells_t<double>(items, nit, nblk, a, b, skip, sstride, s);
+  launch_bcopy_cells_t<double>(items, nit, nblk, bs, a, b, skip, sstride, s);
 }

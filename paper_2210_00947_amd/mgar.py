@@ -37,7 +37,8 @@ EXPORTS = [
     "mgar_net_set_params", "mgar_net_get_params", "mgar_net_set_source", "mgar_net_infer", "mgar_net_output",
     "mgar_net_grad",
     "mgar_net_train_step", "mgar_batch_setup", "mgar_batch_destroy", "mgar_batch_layout",
-    "mgar_batch_set_graph", "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
+    "mgar_batch_set_graph", "mgar_batch_set_block", "mgar_batch_get_block", "mgar_batch_autotune",
+    "mgar_batch_load_vector", "mgcg_batch_solve", "mgar_batch_solve",
     "mgar_profile", "mgar_profile_read", "mgar_residual_noalloc", "mgar_set_filter_radius",
     "mgar_smooth_boundary",
 ]
@@ -417,6 +418,23 @@ class Batch:
 
     def mgar_batch_set_graph(self, use_graph):
         _check(self._L.mgar_batch_set_graph(self.b, int(bool(use_graph))), "mgar_batch_set_graph")
+
+    def mgar_batch_set_block(self, bs):
+        _check(self._L.mgar_batch_set_block(self.b, int(bs)), "mgar_batch_set_block")
+
+    def mgar_batch_get_block(self):
+        v = ctypes.c_int()
+        _check(self._L.mgar_batch_get_block(self.b, ctypes.byref(v)), "mgar_batch_get_block")
+        return v.value
+
+    def mgar_batch_autotune(self, xphys, q, tol, reps=3):
+        """Times the candidate block sizes (256, 128, 64) on batched MGCG solves
+        of (xphys, q) and keeps the fastest; returns (block size, {size: us})."""
+        bs = ctypes.c_int()
+        us = (ctypes.c_float * 3)()
+        _check(self._L.mgar_batch_autotune(self.b, _ptr(xphys, self.E), _ptr(q, self.N), ctypes.c_double(tol),
+                                           int(reps), ctypes.byref(bs), us), "mgar_batch_autotune")
+        return bs.value, {256: us[0], 128: us[1], 64: us[2]}
 
     def mgar_batch_load_vector(self, Qe, q):
         _check(self._L.mgar_batch_load_vector(self.b, _ptr(Qe, self.E), _ptr(q, self.N)),

@@ -325,3 +325,53 @@ def test_full_batched_workload_mixed_residuals():
         res, fep = _fp64_residual(probs[i], xs[i], ts[i])
         assert res < 1.001e-8, probs[i].name
         assert np.all(ts[i][fep.fixed] == 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_block_size_matches_the_oracle(precision):
+    """The batched launches at each block size the tuner may choose (256,
+    128, 64 threads): every design's temperature against the oracle, CG
+    iterations (FP64) against the oracle's, and the block sizes against each
+    other (they differ only in the order block partials of a dot are summed)."""
+    import torch
+    from paper_2210_00947_amd import mgar as M
+    kw = {} if precision == "fp64" else {"precision": M.PREC_MIXED}
+    b = make_batch(PROBS, **kw)
+    q = loads(b, PROBS)
+    xs = [W.random_density(p.nelem, 400 + i, 0.0, 1.0) for i, p in enumerate(PROBS)]
+    ors = [solvers.MgarSolver(p, solvers.MgarParams(cg_max=200)).mgcg(x, np.zeros(p.nnodes), 1e-8)
+           for p, x in zip(PROBS, xs)]
+    sols = {}
+    for bs in (256, 128, 64):
+        b.mgar_batch_set_block(bs)
+        assert b.mgar_batch_get_block() == bs
+        T = torch.empty(b.N, dtype=torch.float64, device="cuda")
+        st = b.mgcg_batch_solve(concat(b, xs, "elem"), q, None, 1e-8, T)
+        sols[bs] = split(b, T)
+        for p, t, s, (t_or, s_or) in zip(PROBS, sols[bs], st, ors):
+            assert s["rc"] == 0, (bs, p.name)
+            assert rel_l2(t, t_or) < (1e-8 if precision == "fp64" else 1e-6), (bs, p.name)
+            if precision == "fp64":
+                assert s["cg_iters"] == s_or.cg_iters, (bs, p.name)
+    for bs in (128, 64):
+        for t, t256 in zip(sols[bs], sols[256]):
+            assert rel_l2(t, t256) < (1e-10 if precision == "fp64" else 1e-6)
+
+
+def test_autotune_keeps_a_candidate_and_the_solution():
+    """The tuner times the three block sizes on batched MGCG solves, keeps the
+    fastest, and the batch then solves as before."""
+    import torch
+    b = make_batch(PROBS)
+    q = loads(b, PROBS)
+    xs = [W.random_density(p.nelem, 500 + i, 0.0, 1.0) for i, p in enumerate(PROBS)]
+    x = concat(b, xs, "elem")
+    bs, us = b.mgar_batch_autotune(x, q, 1e-8, reps=2)
+    assert bs in (64, 128, 256) and b.mgar_batch_get_block() == bs
+    assert all(v > 0 for v in us.values()) and us[bs] == min(us.values())
+    T = torch.empty(b.N, dtype=torch.float64, device="cuda")
+    st = b.mgcg_batch_solve(x, q, None, 1e-8, T)
+    for p, xi, t, s in zip(PROBS, xs, split(b, T), st):
+        t_or, s_or = solvers.MgarSolver(p, solvers.MgarParams(cg_max=200)).mgcg(xi, np.zeros(p.nnodes), 1e-8)
+        assert s["cg_iters"] == s_or.cg_iters and rel_l2(t, t_or) < 1e-8, p.name
+    print(f"batch tuner: block {bs}, mean solve times (us) {us}")

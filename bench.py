@@ -363,7 +363,10 @@ def paper_tables(W, TopOpt, torch, ncycles=300):
 
 def cpu_baseline(prob, W, nsolves=3):
     """Full oracle MGCG solves on the benchmark grid (FP64, SciPy), timed with
-    perf_counter; cores = process CPU time / wall time."""
+    perf_counter; cores = process CPU time / wall time (the oracle leaves
+    the thread counts of NumPy/SciPy's native libraries at their defaults;
+    the record lists them, the CPUs the process may run on and the thread
+    environment variables)."""
     import numpy as np
     from oracle import solvers
     s = solvers.MgarSolver(prob, solvers.MgarParams(cg_max=200))
@@ -388,7 +391,22 @@ def cpu_baseline(prob, W, nsolves=3):
         "seconds": wall,
         "cpu_model": _cpu_model(),
         "os_cpu_count": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "thread_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                                       "MKL_NUM_THREADS", "BLIS_NUM_THREADS")},
+        "blas_threadpools": _threadpools(),
     }
+
+
+def _threadpools():
+    """Thread pools of the native libraries NumPy/SciPy loaded (BLAS, OpenMP):
+    library, API and thread count, as threadpoolctl reports them."""
+    try:
+        from threadpoolctl import threadpool_info
+        return [{k: d.get(k) for k in ("internal_api", "prefix", "num_threads", "version")}
+                for d in threadpool_info()]
+    except Exception as e:   # threadpoolctl missing or failing: say so in the record
+        return [{"error": str(e)}]
 
 
 def _cpu_model():

@@ -457,46 +457,58 @@ __global__ __launch_bounds__(VB) void k_gs_fix(double* __restrict__ R, long long
 }
 
 // Gram products of the reduced system (Eq 19-20), K_R[a][b] = Q_a . W_b
-// (a <= b), q_R[a] = Q_a . q, and ||q||^2, on the matrix cores: with
-// A = [Q_0 .. Q_{M-1}, q] and
-// B = [W_0 .. W_{M-1}, q] (N x (M+1) each, zero-padded to 16 columns),
-// G = A^T B is a product whose inner dimension is the node index, accumulated
-// by v_mfma_f64_16x16x4f64 four nodes per instruction: lane l supplies
-// A[node][l % 16] and B[node][l % 16] for the nodes 4 (l / 16) + t of a
-// 16-node chunk, t = 0..3 (one instruction per t), and holds G rows
-// 4 r + l / 16, r = 0..3, of column l % 16 (lane layout checked on gfx950). K_R = G[a][b], q_R[a] = G[a][M],
-// ||q||^2 = G[M][M]; per block the waves' G are summed in wave order and
-// written as M(M+1)/2 + M + 1 values: the upper triangle of K_R row by row,
-// then q_R, then ||q||^2 (read by k_gram_finalize).
+// (a <= b), q_R[a] = Q_a . q, and ||q||^2, on the matrix cores. With
+// A = [Q_0 .. Q_{M-1}, q] and B = [W_0 .. W_{M-1}, q] (N x (M+1) each),
+// G = A^T B is a product whose inner dimension is the node index. One
+// v_mfma_f64_16x16x4f64 takes a 16 x 4 operand from each side: lane l
+// supplies row l % 16 at inner index l / 16 (lane layout checked on gfx950).
+// Its 16 rows carry NG = 16 / (M + 1) node groups side by side: row
+// g (M + 1) + a is column a of A (or B) over the nodes 4 g .. 4 g + 3 of the
+// instruction's span of 4 NG nodes (rows past NG (M + 1) are zero). The
+// diagonal blocks of the 16 x 16 result, D[g (M+1) + a][g (M+1) + b], are the
+// products over group g's nodes; the off-diagonal blocks pair different nodes
+// and are not used. Lane l holds D rows 4 r + l / 16, r = 0..3, of column
+// l % 16. Per block G[a][b] = sum over waves, then groups, of the diagonal
+// blocks, written as M(M+1)/2 + M + 1 values: the upper triangle of K_R row by
+// row, then q_R, then ||q||^2 (read by k_gram_finalize).
 typedef double mgar_d4 __attribute__((ext_vector_type(4)));
+constexpr int GRAM_GROUP = 4;   // instructions whose loads are issued together
+
 template <int M>
 __global__ __launch_bounds__(VB) void k_gram_mfma(const double* __restrict__ Q, const double* __restrict__ W,
                                                   const double* __restrict__ q, long long ld, long long n,
                                                   double* __restrict__ part) {
   constexpr int NW = VB / MGAR_WAVE;
   constexpr int NV = M * (M + 1) / 2 + M + 1;
-  __shared__ double G[NW][16][16];
+  constexpr int NG = 16 / (M + 1);
+  constexpr int SPAN = 4 * NG;
+  __shared__ double G[NW][16][17];
   const int lane = threadIdx.x & (MGAR_WAVE - 1), wid = threadIdx.x / MGAR_WAVE;
-  const int col = lane & 15, quarter = lane >> 4;
-  const double* pa = col < M ? Q + col * ld : (col == M ? q : nullptr);
-  const double* pb = col < M ? W + col * ld : (col == M ? q : nullptr);
+  const int row = lane & 15, kk = lane >> 4;
+  const int col = row % (M + 1), grp = row / (M + 1);
+  const bool live = grp < NG;
+  const double* pa = live ? (col < M ? Q + col * ld : q) : nullptr;
+  const double* pb = live ? (col < M ? W + col * ld : q) : nullptr;
+  const int off = 4 * grp + kk;
   mgar_d4 d = {0.0, 0.0, 0.0, 0.0};
-  const long long nchunk = (n + 15) / 16;
+  const long long nstep = (n + SPAN - 1) / SPAN;
   const long long waves = (long long)gridDim.x * NW;
-  for (long long c = (long long)blockIdx.x * NW + wid; c < nchunk; c += waves) {
-    const long long base = c * 16 + 4 * quarter;
-    double av[4], bv[4];
+  // a wave's instructions (steps c, c + waves, ...) in the plain grid-stride
+  // order, the loads of GRAM_GROUP of them issued together
+  for (long long c0 = (long long)blockIdx.x * NW + wid; c0 < nstep; c0 += GRAM_GROUP * waves) {
+    double av[GRAM_GROUP], bv[GRAM_GROUP];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const bool in = pa != nullptr && base + t < n;
-      av[t] = in ? pa[base + t] : 0.0;
-      bv[t] = in ? pb[base + t] : 0.0;
+    for (int u = 0; u < GRAM_GROUP; ++u) {
+      const long long node = (c0 + u * waves) * SPAN + off;
+      const bool in = live && node < n;
+      av[u] = in ? pa[node] : 0.0;
+      bv[u] = in ? pb[node] : 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], d, 0, 0, 0);
+    for (int u = 0; u < GRAM_GROUP; ++u) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], d, 0, 0, 0);
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) G[wid][4 * r + quarter][col] = d[r];
+  for (int r = 0; r < 4; ++r) G[wid][4 * r + kk][row] = d[r];
   __syncthreads();
   if (threadIdx.x < NV) {
     const int v = threadIdx.x;
@@ -514,7 +526,9 @@ __global__ __launch_bounds__(VB) void k_gram_mfma(const double* __restrict__ Q, 
     }
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s += G[w][a][b];
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) s += G[w][g * (M + 1) + a][g * (M + 1) + b];
     part[blockIdx.x * NV + v] = s;
   }
 }

@@ -219,7 +219,8 @@ def test_timing_switch_changes_nothing_but_ms():
 
 @pytest.mark.parametrize("prob", PROBS, ids=IDS)
 @pytest.mark.parametrize("m,eps,x0zero", [(2, 1e-8, False), (2, 0.5, False), (3, 0.5, True),
-                                           (1, 0.5, False), (4, 1e-8, True)])
+                                           (1, 0.5, False), (4, 1e-8, True), (6, 0.5, False),
+                                           (8, 0.5, True)])
 def test_mgar_parity(prob, m, eps, x0zero):
     import torch
     h = handle(prob, n_basis=m, eps_accept=eps, basis_x0_zero=x0zero)

@@ -167,7 +167,10 @@ int sens_filter(mgar_handle* h, const double* xphys, const double* T, const doub
 /* Optimality-criteria update: x_new = clamp(x sqrt(max(0,-dc)/(dv lambda)),
  * max(0, x-move), min(1, x+move)) with lambda bisected on [0, 1e9] until
  * (l2-l1)/(l1+l2) <= 1e-10 so that the filtered volume sum_e dv_e x_new_e
- * meets volfrac * E. *lambda (host) receives the final midpoint; may be NULL. */
+ * meets volfrac * E. *lambda (host) receives the final midpoint; may be NULL.
+ * The bisection is evaluated at batches of candidate multipliers (the first
+ * batch around the handle's previous result, if any); the midpoints and the
+ * result are those of the plain bisection whatever the candidates. */
 int oc_update(mgar_handle* h, const double* x, const double* dc, const double* dv,
               double volfrac, double move, double* x_new, double* lambda);
 
@@ -179,7 +182,8 @@ int mgar_sens_oc(mgar_handle* h, const double* xphys, const double* T, const dou
                  double volfrac, double move, double* dc, double* dv, double* x_new, double* compliance,
                  double* lambda);
 
-/* Drop K0: the next mgar_solve returns MGAR_E_STATE until an mgcg_solve. */
+/* Drop K0: the next mgar_solve returns MGAR_E_STATE until an mgcg_solve.
+ * Also forgets the previous OC multiplier. */
 int mgar_reset(mgar_handle* h);
 
 /* ---- Operator-level entry points (same conventions). `level` 0 is the

@@ -62,6 +62,7 @@ struct mgar_handle {
   CgState* st = nullptr;
   MgarDev* md = nullptr;
   OcDev* oc = nullptr;
+  double oc_hint = 0.0;                   // multiplier of the last OC update (first candidates of the next)
   double *R = nullptr, *Wm = nullptr;     // basis block and K times basis, N x m
   double *invHs = nullptr, *wvol = nullptr, *gtmp = nullptr;
   int* tap_off = nullptr;
@@ -1363,13 +1364,15 @@ int sens_filter(mgar_handle* h, const double* xphys, const double* T, const doub
 static int oc_run(mgar_handle* h, const double* x, const double* dc, const double* dv, double volfrac,
                   double move, double* x_new, double* lambda, const double* dev_scalar, double* host_scalar) {
   const double target = volfrac * (double)h->E;
-  launch_oc_init(h->oc, target, h->s);
+  const bool hinted = h->oc_hint > 0.0;
+  launch_oc_init(h->oc, target, h->oc_hint, h->s);
   OcDev ho;
   int passes = 0;
   for (;;) {
-    // typically 4-7 passes; passes after convergence return at once, so the
-    // first batch is sized to need no second synchronisation
-    const int chunk = passes == 0 ? 7 : 4;
+    // typically 4-7 passes (one fewer from the last multiplier); passes after
+    // convergence return at once, so the first batch is sized to need no
+    // second synchronisation
+    const int chunk = passes == 0 ? (hinted ? 6 : 7) : 4;
     for (int c = 0; c < chunk; ++c) {
       const int np = launch_oc_pass(x, dc, dv, h->E, move, h->oc, h->pa, h->s);
       launch_oc_walk(h->oc, h->pa, np, target, 1e-10, h->s);
@@ -1391,7 +1394,9 @@ static int oc_run(mgar_handle* h, const double* x, const double* dc, const doubl
   }
   if (x_new == x) launch_oc_final(x, dc, dv, h->E, move, h->oc, x_new, h->s);
   LAUNCHCK();
-  if (lambda) *lambda = 0.5 * (ho.l1 + ho.l2);
+  const double lam = 0.5 * (ho.l1 + ho.l2);
+  h->oc_hint = (ho.done && lam > 0.0 && lam < 1e9) ? lam : 0.0;
+  if (lambda) *lambda = lam;
   return MGAR_OK;
 }
 
@@ -1419,6 +1424,7 @@ int mgar_set_timing(mgar_handle* h, int on) {
 int mgar_reset(mgar_handle* h) {
   if (!h) return MGAR_E_ARG;
   h->has_k0 = false;
+  h->oc_hint = 0.0;
   return MGAR_OK;
 }
 

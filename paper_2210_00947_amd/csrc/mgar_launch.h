@@ -421,7 +421,7 @@ void launch_filter_hs(const Geo& g, const int* off, const double* w, int ntap, d
                       hipStream_t s);
 void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const double* invHs,
                       double k0, double kmin, double penal, double* gout, hipStream_t s);
-void launch_oc_init(OcDev* oc, double target, hipStream_t s);
+void launch_oc_init(OcDev* oc, double target, double hint, hipStream_t s);
 int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
                    const OcDev* oc, double* part, hipStream_t s);
 void launch_oc_walk(OcDev* oc, const double* part, int np, double target, double tol,

@@ -240,7 +240,11 @@ __device__ void oc_fill_candidates(OcDev* oc, double target) {
   }
 }
 
-__global__ void k_oc_init(OcDev* oc, double target) {
+// With a previous multiplier (hint > 0, e.g. the last call's result), the first
+// candidates are hint * 2^((t - 7) / 2), t = 0..14 (hint / 11 .. 11 hint): the
+// bisection itself is unchanged (it still starts from [0, 1e9]), only the
+// points where S is evaluated first.
+__global__ void k_oc_init(OcDev* oc, double target, double hint) {
   oc->l1 = 0.0;
   oc->l2 = 1e9;
   oc->lam_last = 0.5e9;
@@ -250,7 +254,11 @@ __global__ void k_oc_init(OcDev* oc, double target) {
   oc->s_hi = 0.0;
   oc->done = 0;
   oc->steps = 0;
-  oc_fill_candidates(oc, target);
+  if (hint > 0.0 && hint < oc->l2) {
+    for (int t = 0; t < OC_NCAND; ++t) oc->cand[t] = fmin(oc->l2, hint * exp2(0.5 * (t - OC_NCAND / 2)));
+  } else {
+    oc_fill_candidates(oc, target);
+  }
 }
 
 __global__ __launch_bounds__(VB) void k_oc_pass(const double* __restrict__ x,
@@ -377,7 +385,9 @@ void launch_sens_elem(const Geo& g, const double* xphys, const double* T, const 
     k_sens<3><<<elem_grid(g), dim3(TBX, TBY, 1), 0, s>>>(g, xphys, T, invHs, k0, kmin, penal, gout);
 }
 
-void launch_oc_init(OcDev* oc, double target, hipStream_t s) { k_oc_init<<<1, 1, 0, s>>>(oc, target); }
+void launch_oc_init(OcDev* oc, double target, double hint, hipStream_t s) {
+  k_oc_init<<<1, 1, 0, s>>>(oc, target, hint);
+}
 
 int launch_oc_pass(const double* x, const double* dc, const double* dv, long long n, double move,
                    const OcDev* oc, double* part, hipStream_t s) {

@@ -313,6 +313,48 @@ def test_filter_sensitivity_oc(prob):
     assert np.abs(host(xng) - xn).max() < 1e-9
 
 
+@pytest.mark.parametrize("prob", PROBS[-2:], ids=IDS[-2:])
+def test_oc_does_not_depend_on_the_previous_multiplier(prob):
+    """The OC update's first candidates come from the handle's previous
+    multiplier; its result is the plain bisection's whatever that was: fresh
+    handle, after the same call (hint at the answer), after a call whose
+    multiplier is 1e6 times larger or 1e8 times smaller, and after mgar_reset
+    (no hint) all give the same lambda and x_new bit for bit, and agree with
+    the oracle."""
+    import torch
+    h = handle(prob)
+    fep = fe.FEProblem(prob)
+    filt = topopt.Filter(fep.grid, prob.filter_r)
+    # densities around the volume fraction, so that the target volume is
+    # reachable within the move limit (lambda strictly inside the bracket)
+    x = W.random_density(prob.nelem, 51, prob.volfrac - 0.1, prob.volfrac + 0.1)
+    dc = -np.abs(W.random_vector(prob.nelem, 52)) - 1e-3
+    dv = filt.adjoint(np.ones(prob.nelem))     # the filtered volume's gradient, as in the loop
+    xn_or, lam_or, _ = topopt.oc_update(x, dc, dv, filt, prob.volfrac, prob.move)
+    assert 1e-3 < lam_or < 1e3
+    out = []
+
+    def run(scale):
+        xn = torch.empty(prob.nelem, dtype=torch.float64, device="cuda")
+        lam = h.oc_update(dev(x), dev(dc * scale), dev(dv), prob.volfrac, prob.move, xn)
+        torch.cuda.synchronize()
+        return lam, host(xn)
+
+    out.append(run(1.0))
+    out.append(run(1.0))
+    for scale in (1e6, 1e-8):
+        lam_s, _ = run(scale)
+        assert abs(lam_s - scale * lam_or) <= 1e-6 * scale * lam_or
+        out.append(run(1.0))
+    h.mgar_reset()
+    out.append(run(1.0))
+    lam0, xn0 = out[0]
+    assert abs(lam0 - lam_or) <= 1e-9 * lam_or
+    assert np.abs(xn0 - xn_or).max() < 1e-9
+    for lam, xn in out[1:]:
+        assert lam == lam0 and np.array_equal(xn, xn0)
+
+
 def test_loop_c0_matches_oracle():
     require_gpu()
     from paper_2210_00947_amd.topopt import TopOpt

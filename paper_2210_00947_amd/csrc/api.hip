@@ -1275,16 +1275,15 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
   }
   // Eq 18 (as Gram-Schmidt), Eq 19-21; ||q||^2 comes with the Gram products
   if (h->mixed) ACK(orthonormalise(h));
-  else launch_gs_fused(h->R, m, N, N, h->md, h->pa, h->s);
+  else launch_gs_fused(h->R, m, N, N, h->md, h->pa, h->pb, h->s);
   for (int j = 0; j < m; ++j)
     ACK(stencil_at(h, 0, SM_APPLY, h->R + (long long)j * N, h->kcur, nullptr, nullptr,
                    h->Wm + (long long)j * N, 0.0, nullptr, nullptr));
-  int np = launch_gram(h->R, h->Wm, h->qm, m, N, N, h->pa, h->s);
-  launch_gram_finalize(h->pa, np, m, h->md, h->s);
-  // t~ = Q y in cx; FP64: also r = q - W y in cr, the residual of t~ the
-  // fallback PCG starts from (its ||r||^2 partials stay in pa)
+  const int np = launch_gram(h->R, h->Wm, h->qm, m, N, N, h->pb, h->s);
+  // reduced solve, t~ = Q y in cx; FP64: also r = q - W y in cr, the residual
+  // of t~ the fallback PCG starts from (its ||r||^2 partials stay in pa)
   const int nres = launch_combine(h->R, h->Wm, h->qm, m, N, N, h->md, h->cx, h->pa, h->s,
-                                  h->mixed ? nullptr : h->cr);
+                                  h->mixed ? nullptr : h->cr, h->pb, np);
   launch_finalize(h->pa, nres, &h->md->res2, nullptr, h->s);
   LAUNCHCK();
   MgarDev hm;

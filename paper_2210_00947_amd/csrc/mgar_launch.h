@@ -260,17 +260,22 @@ void launch_gs_update(double* v, const double* Q, int ncols, long long ld, const
                       long long n, hipStream_t s);
 void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const double* nrm2_after,
                          hipStream_t s);
+// Block partials of K_R, q_R and ||q||^2 (m(m+1)/2 + m + 1 per block) into
+// part; returns the block count.
 int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,
                 long long n, double* part, hipStream_t s);
-void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s);
-// t = Q y, partials of ||W y - q||^2 (y from the reduced Cholesky solve, stored
-// in md); with rq, also rq = q - W y.
+// From the Gram partials (gpart, gnp blocks): K_R, q_R, ||q||^2 and the
+// reduced Cholesky solve y (stored in md); t = Q y, partials of ||W y - q||^2
+// into part (not gpart); with rq, also rq = q - W y.
 int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
-                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq = nullptr);
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq,
+                   const double* gpart, int gnp);
 // Two-pass Gram-Schmidt of the m columns of R in place (three passes over
 // the data per column; see k_gs_dots), leaving orthonormal columns, md->active
-// and md->n0; dropped columns are zeroed. part: vec_num_blocks(n) * (m + 1).
-void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, hipStream_t s);
+// and md->n0; dropped columns are zeroed. part, part2: two distinct buffers of
+// vec_num_blocks(n) * (m + 1) doubles.
+void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, double* part2,
+                     hipStream_t s);
 
 // api.hip helpers shared with batch.hip (grid of a level, Dirichlet count,
 // parameter validation of one design).

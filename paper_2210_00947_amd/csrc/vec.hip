@@ -327,6 +327,47 @@ __global__ __launch_bounds__(VB) void k_gs_normalize(double* __restrict__ v, lon
 // norm after projection is below 1e-10 of its norm before (or zero) is zeroed
 // and left out.
 
+// The nv (<= NVM) sums over np block partials laid out part[b * nv + v],
+// formed the same way in every block of a launch (so every block holds the
+// same values): thread t adds blocks t, t + nt, ... in order (the first U of
+// them loaded together), each value is summed over the wave, then over the
+// waves in order. out[v] (shared) for v < nv, valid in every thread on return.
+// shm: (blockDim / 64) * NVM doubles of shared memory.
+template <int NVM, int U>
+__device__ inline void partial_sums(const double* __restrict__ part, int np, int nv, double* out, double* shm) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int nw = (nt + MGAR_WAVE - 1) / MGAR_WAVE;
+  double acc[NVM], a[U][NVM];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = t + u * nt;
+#pragma unroll
+    for (int v = 0; v < NVM; ++v) a[u][v] = (b < np && v < nv) ? part[(long long)b * nv + v] : 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < NVM; ++v) {
+    acc[v] = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[v] += a[u][v];
+  }
+  for (int b = t + U * nt; b < np; b += nt)
+#pragma unroll
+    for (int v = 0; v < NVM; ++v)
+      if (v < nv) acc[v] += part[(long long)b * nv + v];
+#pragma unroll
+  for (int v = 0; v < NVM; ++v) {
+    const double w = wave_sum(acc[v]);
+    if ((t & (MGAR_WAVE - 1)) == 0) shm[(t / MGAR_WAVE) * NVM + v] = w;
+  }
+  __syncthreads();
+  if (t < nv) {
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += shm[w * NVM + t];
+    out[t] = r;
+  }
+  __syncthreads();
+}
+
 // part[b * NV + v]: v < J: R_v . R_J; v = J: R_J . R_J; v = J + 1 (J = 1): R_0 . R_0
 template <int J>
 __global__ __launch_bounds__(VB) void k_gs_dots(const double* __restrict__ R, long long ld, long long n,
@@ -353,36 +394,37 @@ __global__ __launch_bounds__(VB) void k_gs_dots(const double* __restrict__ R, lo
   }
 }
 
-// Pass 1 results: n0[J]; for J = 1 also column 0's norms; c[c] = R_c . R_J / nn[c].
-__global__ __launch_bounds__(FB) void k_gs_fin1(const double* __restrict__ part, int np, int J, MgarDev* md) {
-  __shared__ double sh[FB / MGAR_WAVE];
-  const int nv = J + 1 + (J == 1 ? 1 : 0);
-  double v[MGAR_MAXB + 2];
-  for (int q = 0; q < nv; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < np; b += FB) s += part[b * nv + q];
-    v[q] = block_sum(s, sh);
-  }
-  if (threadIdx.x != 0) return;
-  if (J == 0 || J == 1) {
-    const double n00 = (J == 0) ? v[0] : v[nv - 1];
-    md->n0[0] = n00;
-    md->nn[0] = n00;
-    md->active[0] = n00 > 0.0 ? 1 : 0;
-  }
-  if (J == 0) return;
-  md->n0[J] = v[J];
-  for (int c = 0; c < J; ++c) md->c[c] = md->active[c] ? v[c] / md->nn[c] : 0.0;
-}
-
-// Pass 2: R_J -= sum_c c[c] R_c; partials of R_c . R_J (c < J) and R_J . R_J.
+// Pass 2: every block first forms pass 1's results from its partials (dpart,
+// np blocks): n0[J]; for J = 1 also column 0's norms; c[q] = R_q . R_J / nn[q]
+// (block 0 records them in md). Then R_J -= sum_q c[q] R_q, and partials of
+// R_q . R_J' (q < J) and R_J' . R_J' into part.
 template <int J>
 __global__ __launch_bounds__(VB) void k_gs_proj(double* __restrict__ R, long long ld, long long n,
-                                                const MgarDev* __restrict__ md, double* __restrict__ part) {
+                                                MgarDev* md, const double* __restrict__ dpart, int np,
+                                                double* __restrict__ part) {
+  constexpr int NV1 = J + 1 + (J == 1 ? 1 : 0);
   __shared__ double sh[VB / MGAR_WAVE];
-  double c[J], s[J + 1];
+  __shared__ double shm[(VB / MGAR_WAVE) * NV1];
+  __shared__ double v1[NV1];
+  partial_sums<NV1, 4>(dpart, np, NV1, v1, shm);
+  double nn[J], c[J];
+  int act[J];
 #pragma unroll
-  for (int q = 0; q < J; ++q) c[q] = md->c[q];
+  for (int q = 0; q < J; ++q) {
+    nn[q] = (J == 1) ? v1[NV1 - 1] : md->nn[q];
+    act[q] = (J == 1) ? (nn[q] > 0.0 ? 1 : 0) : md->active[q];
+    c[q] = act[q] ? v1[q] / nn[q] : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (J == 1) {
+      md->n0[0] = nn[0];
+      md->nn[0] = nn[0];
+      md->active[0] = act[0];
+    }
+    md->n0[J] = v1[J];
+    for (int q = 0; q < J; ++q) md->c[q] = c[q];
+  }
+  double s[J + 1];
 #pragma unroll
   for (int q = 0; q <= J; ++q) s[q] = 0.0;
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
@@ -405,39 +447,46 @@ __global__ __launch_bounds__(VB) void k_gs_proj(double* __restrict__ R, long lon
   }
 }
 
-// Pass 2 results: c2[c] = R_c . R_J' / nn[c]; nn[J] and the drop decision.
-__global__ __launch_bounds__(FB) void k_gs_fin2(const double* __restrict__ part, int np, int J, MgarDev* md) {
-  __shared__ double sh[FB / MGAR_WAVE];
-  double v[MGAR_MAXB + 1];
-  for (int q = 0; q <= J; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < np; b += FB) s += part[b * (J + 1) + q];
-    v[q] = block_sum(s, sh);
-  }
-  if (threadIdx.x != 0) return;
-  double nn = v[J];
-  for (int c = 0; c < J; ++c) {
-    const double c2 = md->active[c] ? v[c] / md->nn[c] : 0.0;
-    md->c2[c] = c2;
-    nn -= c2 * c2 * md->nn[c];
-  }
-  nn = nn > 0.0 ? nn : 0.0;
-  const double n0 = md->n0[J];
-  const bool keep = n0 > 0.0 && nn >= 1e-20 * n0;
-  md->nn[J] = keep ? nn : 0.0;
-  md->active[J] = keep ? 1 : 0;
-}
-
-// Pass 3: R_J -= sum_c c2[c] R_c (J >= 1); with LAST, every column c <= J is
-// then scaled by 1 / sqrt(nn[c]) (0 for dropped columns).
+// Pass 3: every block first forms pass 2's results from its partials (ppart,
+// np blocks): c2[q] = R_q . R_J' / nn[q], nn[J] = ||R_J'||^2 - sum_q c2_q^2
+// nn[q] and the drop decision; for J = 0 (a single column, ppart holding the
+// partials of ||R_0||^2) column 0's norms. Block 0 records them in md. Then
+// R_J -= sum_q c2[q] R_q (J >= 1); with LAST, every column q <= J is scaled
+// by 1 / sqrt(nn[q]) (0 for dropped columns).
 template <int J, bool LAST>
 __global__ __launch_bounds__(VB) void k_gs_fix(double* __restrict__ R, long long ld, long long n,
-                                               const MgarDev* __restrict__ md) {
+                                               MgarDev* md, const double* __restrict__ ppart, int np) {
+  __shared__ double shm[(VB / MGAR_WAVE) * (J + 1)];
+  __shared__ double v2[J + 1];
+  partial_sums<J + 1, 4>(ppart, np, J + 1, v2, shm);
   double c2[J > 0 ? J : 1], sc[J + 1];
+  double nnJ;
+  int actJ;
+  if (J == 0) {
+    nnJ = v2[0];
+    actJ = nnJ > 0.0 ? 1 : 0;
+  } else {
+    nnJ = v2[J];
 #pragma unroll
-  for (int q = 0; q < J; ++q) c2[q] = md->c2[q];
+    for (int q = 0; q < J; ++q) {
+      const double nq = md->nn[q];
+      c2[q] = md->active[q] ? v2[q] / nq : 0.0;
+      nnJ -= c2[q] * c2[q] * nq;
+    }
+    nnJ = nnJ > 0.0 ? nnJ : 0.0;
+    const double n0 = md->n0[J];
+    actJ = (n0 > 0.0 && nnJ >= 1e-20 * n0) ? 1 : 0;
+    if (!actJ) nnJ = 0.0;
+  }
 #pragma unroll
-  for (int q = 0; q <= J; ++q) sc[q] = (md->active[q] && md->nn[q] > 0.0) ? 1.0 / sqrt(md->nn[q]) : 0.0;
+  for (int q = 0; q < J; ++q) sc[q] = (md->active[q] && md->nn[q] > 0.0) ? 1.0 / sqrt(md->nn[q]) : 0.0;
+  sc[J] = (actJ && nnJ > 0.0) ? 1.0 / sqrt(nnJ) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (J == 0) md->n0[0] = nnJ;
+    for (int q = 0; q < J; ++q) md->c2[q] = c2[q];
+    md->nn[J] = nnJ;
+    md->active[J] = actJ;
+  }
   for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
     double rc[J > 0 ? J : 1];
     double v = R[J * ld + i];
@@ -470,7 +519,7 @@ __global__ __launch_bounds__(VB) void k_gs_fix(double* __restrict__ R, long long
 // and are not used. Lane l holds D rows 4 r + l / 16, r = 0..3, of column
 // l % 16. Per block G[a][b] = sum over waves, then groups, of the diagonal
 // blocks, written as M(M+1)/2 + M + 1 values: the upper triangle of K_R row by
-// row, then q_R, then ||q||^2 (read by k_gram_finalize).
+// row, then q_R, then ||q||^2 (summed over the blocks by k_combine).
 typedef double mgar_d4 __attribute__((ext_vector_type(4)));
 constexpr int GRAM_GROUP = 4;   // instructions whose loads are issued together
 
@@ -533,46 +582,21 @@ __global__ __launch_bounds__(VB) void k_gram_mfma(const double* __restrict__ Q, 
   }
 }
 
-__global__ __launch_bounds__(FB) void k_gram_finalize(const double* __restrict__ part, int np, int m,
-                                                      MgarDev* md) {
-  __shared__ double sh[FB / MGAR_WAVE];
-  const int nv = m * (m + 1) / 2 + m + 1;
-  int idx = 0;
-  for (int a = 0; a < m; ++a)
-    for (int b = a; b < m; ++b, ++idx) {
-      double s = 0.0;
-      for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + idx];
-      s = block_sum(s, sh);
-      if (threadIdx.x == 0) {
-        md->KR[a * MGAR_MAXB + b] = s;
-        md->KR[b * MGAR_MAXB + a] = s;
-      }
-    }
-  for (int a = 0; a < m; ++a) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + idx + a];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) md->qR[a] = s;
-  }
-  double s = 0.0;
-  for (int k = threadIdx.x; k < np; k += FB) s += part[k * nv + nv - 1];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) md->qq = s;
-}
-
-// Solve K_R y = q_R over the active columns by Cholesky (m <= 8, one thread).
-__device__ void reduced_solve(const MgarDev* md, int m, double* y, int* fail) {
+// Solve K_R y = q_R over the active columns by Cholesky (m <= 8, one thread);
+// KR is row-major with leading dimension MGAR_MAXB.
+__device__ void reduced_solve(const int* active, const double* KR, const double* qR, int m, double* y,
+                              int* fail) {
   double L[MGAR_MAXB][MGAR_MAXB];
   double rhs[MGAR_MAXB];
   int idx[MGAR_MAXB];
   int na = 0;
   for (int a = 0; a < m; ++a)
-    if (md->active[a]) idx[na++] = a;
+    if (active[a]) idx[na++] = a;
   for (int a = 0; a < m; ++a) y[a] = 0.0;
   *fail = 0;
   for (int a = 0; a < na; ++a) {
-    rhs[a] = md->qR[idx[a]];
-    for (int b = 0; b < na; ++b) L[a][b] = md->KR[idx[a] * MGAR_MAXB + idx[b]];
+    rhs[a] = qR[idx[a]];
+    for (int b = 0; b < na; ++b) L[a][b] = KR[idx[a] * MGAR_MAXB + idx[b]];
   }
   for (int j = 0; j < na; ++j) {
     double d = L[j][j];
@@ -599,22 +623,52 @@ __device__ void reduced_solve(const MgarDev* md, int m, double* y, int* fail) {
   }
 }
 
-// t = Q y, res = W y - q, partial ||res||^2 (y solved redundantly per block).
+__device__ void reduced_solve(const MgarDev* md, int m, double* y, int* fail) {
+  reduced_solve(md->active, md->KR, md->qR, m, y, fail);
+}
+
+// Every block first sums the Gram partials (gpart, gnp blocks; layout of
+// k_gram_mfma) into K_R, q_R and ||q||^2 and solves the reduced system
+// (redundantly per block, the same values in each; block 0 records them in
+// md); then t = Q y, res = W y - q, partial ||res||^2.
 template <int M>
 __global__ __launch_bounds__(VB) void k_combine(const double* __restrict__ Q,
                                                 const double* __restrict__ W,
                                                 const double* __restrict__ q, long long ld,
                                                 long long n, MgarDev* md, double* __restrict__ t,
-                                                double* __restrict__ part, double* __restrict__ rq) {
+                                                double* __restrict__ part, double* __restrict__ rq,
+                                                const double* __restrict__ gpart, int gnp) {
+  constexpr int NV = M * (M + 1) / 2 + M + 1;
   __shared__ double sh[VB / MGAR_WAVE];
+  __shared__ double shm[(VB / MGAR_WAVE) * NV];
+  __shared__ double gv[NV];
   __shared__ double ys[MGAR_MAXB];
+  __shared__ double KR[MGAR_MAXB * MGAR_MAXB], qR[MGAR_MAXB];
+  __shared__ int act[MGAR_MAXB];
+  partial_sums<NV, (NV <= 16 ? 4 : 1)>(gpart, gnp, NV, gv, shm);
+  if (threadIdx.x < M * M) {
+    // entry (a, b) of K_R from the packed upper triangle
+    const int a = threadIdx.x / M, b = threadIdx.x % M;
+    const int r = a < b ? a : b, c = a < b ? b : a;
+    KR[a * MGAR_MAXB + b] = gv[r * M - r * (r - 1) / 2 + (c - r)];
+  }
+  if (threadIdx.x < M) {
+    qR[threadIdx.x] = gv[M * (M + 1) / 2 + threadIdx.x];
+    act[threadIdx.x] = md->active[threadIdx.x];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     double y[MGAR_MAXB];
     int fail;
-    reduced_solve(md, M, y, &fail);
+    reduced_solve(act, KR, qR, M, y, &fail);
     for (int a = 0; a < MGAR_MAXB; ++a) ys[a] = (a < M) ? y[a] : 0.0;
     if (blockIdx.x == 0) {
-      for (int a = 0; a < M; ++a) md->y[a] = y[a];
+      for (int a = 0; a < M; ++a) {
+        for (int b = 0; b < M; ++b) md->KR[a * MGAR_MAXB + b] = KR[a * MGAR_MAXB + b];
+        md->qR[a] = qR[a];
+        md->y[a] = y[a];
+      }
+      md->qq = gv[NV - 1];
       md->spd_fail = fail;
     }
   }
@@ -1130,38 +1184,34 @@ int launch_gram(const double* Q, const double* W, const double* q, int m, long l
   return nb;
 }
 
-void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, hipStream_t s) {
+void launch_gs_fused(double* R, int m, long long ld, long long n, MgarDev* md, double* part, double* part2,
+                     hipStream_t s) {
   const int nb = vec_num_blocks(n);
   if (m == 1) {
     k_gs_dots<0><<<nb, VB, 0, s>>>(R, ld, n, part);
-    k_gs_fin1<<<1, FB, 0, s>>>(part, nb, 0, md);
-    k_gs_fix<0, true><<<nb, VB, 0, s>>>(R, ld, n, md);
+    k_gs_fix<0, true><<<nb, VB, 0, s>>>(R, ld, n, md, part, nb);
     return;
   }
+  // pass 1 partials in part, pass 2 partials in part2 (pass 2 reads part)
   for (int j = 1; j < m; ++j) {
     const bool last = j == m - 1;
 #define GS_J(J)                                                                  \
   case J:                                                                        \
     k_gs_dots<J><<<nb, VB, 0, s>>>(R, ld, n, part);                              \
-    k_gs_fin1<<<1, FB, 0, s>>>(part, nb, J, md);                                 \
-    k_gs_proj<J><<<nb, VB, 0, s>>>(R, ld, n, md, part);                          \
-    k_gs_fin2<<<1, FB, 0, s>>>(part, nb, J, md);                                 \
-    if (last) k_gs_fix<J, true><<<nb, VB, 0, s>>>(R, ld, n, md);                 \
-    else k_gs_fix<J, false><<<nb, VB, 0, s>>>(R, ld, n, md);                     \
+    k_gs_proj<J><<<nb, VB, 0, s>>>(R, ld, n, md, part, nb, part2);               \
+    if (last) k_gs_fix<J, true><<<nb, VB, 0, s>>>(R, ld, n, md, part2, nb);      \
+    else k_gs_fix<J, false><<<nb, VB, 0, s>>>(R, ld, n, md, part2, nb);          \
     break;
     switch (j) { GS_J(1) GS_J(2) GS_J(3) GS_J(4) GS_J(5) GS_J(6) default: GS_J(7) }
 #undef GS_J
   }
 }
 
-void launch_gram_finalize(const double* part, int np, int m, MgarDev* md, hipStream_t s) {
-  k_gram_finalize<<<1, FB, 0, s>>>(part, np, m, md);
-}
-
 int launch_combine(const double* Q, const double* W, const double* q, int m, long long ld,
-                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq) {
+                   long long n, MgarDev* md, double* t, double* part, hipStream_t s, double* rq,
+                   const double* gpart, int gnp) {
   const int nb = vec_num_blocks(n);
-#define CALL_C(M) k_combine<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, md, t, part, rq)
+#define CALL_C(M) k_combine<M><<<nb, VB, 0, s>>>(Q, W, q, ld, n, md, t, part, rq, gpart, gnp)
   MGAR_DISPATCH_M(m, CALL_C)
 #undef CALL_C
   return nb;

@@ -907,30 +907,6 @@ int finish_timing(mgar_handle* h, mgar_stats* st) {
   return MGAR_OK;
 }
 
-// Gram-Schmidt (classical, applied twice) over the m basis columns in h->R.
-int orthonormalise(mgar_handle* h) {
-  const int m = h->p.n_basis;
-  const long long N = h->N;
-  for (int j = 0; j < m; ++j) {
-    double* v = h->R + (long long)j * N;
-    int np = launch_dot(v, v, N, h->pa, nullptr, h->s);
-    launch_finalize(h->pa, np, &h->md->n0[j], nullptr, h->s);
-    if (j > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        np = launch_multidot(h->R, j, N, v, N, h->pa, h->s);
-        launch_finalize_multi(h->pa, np, j, h->md->c, h->s);
-        launch_gs_update(v, h->R, j, N, h->md->c, N, h->s);
-      }
-      np = launch_dot(v, v, N, h->pa, nullptr, h->s);
-      launch_finalize(h->pa, np, &h->scal[0], nullptr, h->s);
-    }
-    // the first column has nothing to be projected out: its norm is n0
-    launch_gs_normalize(v, N, h->md, j, j > 0 ? &h->scal[0] : &h->md->n0[0], h->s);
-    LAUNCHCK();
-  }
-  return MGAR_OK;
-}
-
 }  // namespace
 
 // =================================================================== C ABI
@@ -1273,9 +1249,9 @@ int mgar_solve(mgar_handle* h, const double* xphys, const double* q, const doubl
       ACK(vcycle(h, h->cz, h->p.basis_x0_zero ? nullptr : prev, h->R + (long long)i * N, nullptr, nullptr));
     }
   }
-  // Eq 18 (as Gram-Schmidt), Eq 19-21; ||q||^2 comes with the Gram products
-  if (h->mixed) ACK(orthonormalise(h));
-  else launch_gs_fused(h->R, m, N, N, h->md, h->pa, h->pb, h->s);
+  // Eq 18 (as Gram-Schmidt, FP64 in both forms), Eq 19-21; ||q||^2 comes
+  // with the Gram products
+  launch_gs_fused(h->R, m, N, N, h->md, h->pa, h->pb, h->s);
   for (int j = 0; j < m; ++j)
     ACK(stencil_at(h, 0, SM_APPLY, h->R + (long long)j * N, h->kcur, nullptr, nullptr,
                    h->Wm + (long long)j * N, 0.0, nullptr, nullptr));

@@ -253,13 +253,6 @@ void launch_fill_t(T* a, long long n, float v0, float dv, hipStream_t s);
 void launch_fill_bf16(uint16_t* a, long long n, hipStream_t s);
 void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s);
 // Gram-Schmidt / reduced system helpers
-int launch_multidot(const double* Q, int ncols, long long ld, const double* v, long long n,
-                    double* part, hipStream_t s);
-void launch_finalize_multi(const double* part, int np, int nv, double* out, hipStream_t s);
-void launch_gs_update(double* v, const double* Q, int ncols, long long ld, const double* c,
-                      long long n, hipStream_t s);
-void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const double* nrm2_after,
-                         hipStream_t s);
 // Block partials of K_R, q_R and ||q||^2 (m(m+1)/2 + m + 1 per block) into
 // part; returns the block count.
 int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,

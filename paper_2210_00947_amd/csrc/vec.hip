@@ -252,80 +252,17 @@ __global__ __launch_bounds__(VB) void k_scale_into(const double* __restrict__ a,
     b[i] = alpha * a[i];
 }
 
-// part[b * NC + c] = block-b partial of Q[:, c] . v
-template <int NC>
-__global__ __launch_bounds__(VB) void k_multidot(const double* __restrict__ Q, long long ld,
-                                                 const double* __restrict__ v, long long n,
-                                                 double* __restrict__ part) {
-  __shared__ double sh[VB / MGAR_WAVE];
-  double s[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) s[c] = 0.0;
-  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
-    const double vi = v[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) s[c] += Q[c * ld + i] * vi;
-  }
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) part[blockIdx.x * NC + c] = t;
-  }
-}
-
-// out[v] = sum_b part[b * nv + v], v < nv (one block, fixed order).
-__global__ __launch_bounds__(FB) void k_finalize_multi(const double* __restrict__ part, int np,
-                                                       int nv, double* __restrict__ out) {
-  __shared__ double sh[FB / MGAR_WAVE];
-  for (int v = 0; v < nv; ++v) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < np; b += FB) s += part[b * nv + v];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[v] = s;
-  }
-}
-
-// v -= sum_c coef[c] Q[:, c]
-template <int NC>
-__global__ __launch_bounds__(VB) void k_gs_update(double* __restrict__ v, const double* __restrict__ Q,
-                                                  long long ld, const double* __restrict__ coef,
-                                                  long long n) {
-  double c[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) c[j] = coef[j];
-  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB) {
-    double s = v[i];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) s -= c[j] * Q[j * ld + i];
-    v[i] = s;
-  }
-}
-
-// Normalise column `col` (v) by its post-projection norm, or zero it when the
-// norm fell below 1e-10 of the pre-projection norm (or the column was zero).
-__global__ __launch_bounds__(VB) void k_gs_normalize(double* __restrict__ v, long long n,
-                                                     MgarDev* md, int col,
-                                                     const double* __restrict__ nrm2_after) {
-  const double n0 = sqrt(md->n0[col]);   // n0 holds the squared pre-projection norm
-  const double n1 = sqrt(*nrm2_after);
-  const bool keep = (n0 > 0.0) && (n1 >= 1e-10 * n0);
-  const double s = keep ? 1.0 / n1 : 0.0;
-  for (long long i = blockIdx.x * (long long)VB + threadIdx.x; i < n; i += (long long)gridDim.x * VB)
-    v[i] = keep ? v[i] * s : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) md->active[col] = keep ? 1 : 0;
-}
-
-// ---- Gram-Schmidt in three passes per column (single design, FP64). Column j
-// (j >= 1) of R: pass 1 sums R_c . R_j (c < j) and R_j . R_j (and R_0 . R_0
-// for j = 1); pass 2 subtracts the projection onto the earlier columns and
-// sums the same products of the result; pass 3 subtracts the second
-// (re-orthogonalisation) projection. Earlier columns stay unnormalised (with
-// their squared norms nn[c]) until the last column's pass 3, which also
-// normalises every column. The squared norm after the second projection is
-// ||R_j'||^2 - sum_c c2_c^2 nn_c: exact for orthogonal R_c, and accurate since
-// c2 is of round-off size. Drop rule as the single-pass form: a column whose
-// norm after projection is below 1e-10 of its norm before (or zero) is zeroed
-// and left out.
+// ---- Gram-Schmidt in three passes per column (single design; FP64 columns in
+// both precision forms). Column j (j >= 1) of R: pass 1 sums R_c . R_j (c < j)
+// and R_j . R_j (and R_0 . R_0 for j = 1); pass 2 subtracts the projection
+// onto the earlier columns and sums the same products of the result; pass 3
+// subtracts the second (re-orthogonalisation) projection. Earlier columns stay
+// unnormalised (with their squared norms nn[c]) until the last column's pass
+// 3, which also normalises every column. The squared norm after the second
+// projection is ||R_j'||^2 - sum_c c2_c^2 nn_c: exact for orthogonal R_c, and
+// accurate since c2 is of round-off size. Drop rule: a column whose norm after
+// projection is below 1e-10 of its norm before (or zero) is zeroed and left
+// out.
 
 // The nv (<= NVM) sums over np block partials laid out part[b * nv + v],
 // formed the same way in every block of a launch (so every block holds the
@@ -1147,32 +1084,6 @@ void launch_fill_bf16(uint16_t* a, long long n, hipStream_t s) {
 
 void launch_scale_into(const double* a, double* b, double alpha, long long n, hipStream_t s) {
   k_scale_into<<<vec_num_blocks(n), VB, 0, s>>>(a, b, alpha, n);
-}
-
-int launch_multidot(const double* Q, int ncols, long long ld, const double* v, long long n,
-                    double* part, hipStream_t s) {
-  const int nb = vec_num_blocks(n);
-#define CALL_MD(M) k_multidot<M><<<nb, VB, 0, s>>>(Q, ld, v, n, part)
-  MGAR_DISPATCH_M(ncols, CALL_MD)
-#undef CALL_MD
-  return nb;
-}
-
-void launch_finalize_multi(const double* part, int np, int nv, double* out, hipStream_t s) {
-  k_finalize_multi<<<1, FB, 0, s>>>(part, np, nv, out);
-}
-
-void launch_gs_update(double* v, const double* Q, int ncols, long long ld, const double* c,
-                      long long n, hipStream_t s) {
-  const int nb = vec_num_blocks(n);
-#define CALL_UP(M) k_gs_update<M><<<nb, VB, 0, s>>>(v, Q, ld, c, n)
-  MGAR_DISPATCH_M(ncols, CALL_UP)
-#undef CALL_UP
-}
-
-void launch_gs_normalize(double* v, long long n, MgarDev* md, int col, const double* nrm2_after,
-                         hipStream_t s) {
-  k_gs_normalize<<<vec_num_blocks(n), VB, 0, s>>>(v, n, md, col, nrm2_after);
 }
 
 int launch_gram(const double* Q, const double* W, const double* q, int m, long long ld,

@@ -216,28 +216,50 @@ __global__ __launch_bounds__(TBX* TBY) void k_sens(Geo g, const double* __restri
 // secant estimate in u = lambda^-1/2 (S is close to affine in u, since unclamped
 // elements contribute dv x sqrt(B) u).
 
-__device__ void oc_fill_candidates(OcDev* oc, double target) {
-  double a = fmax(oc->l1, oc->lo_known);
-  const double b = fmin(oc->l2, oc->hi_known);
-  if (a <= 0.0 || b > 64.0 * a) {
-    if (a <= 0.0) a = b * 1e-40;
-    const double r = log(b / a) / (OC_NCAND + 1);
-    for (int t = 0; t < OC_NCAND; ++t) oc->cand[t] = a * exp(r * (t + 1));
-    return;
+// Placement of the next candidates for the undecided range [a, b] =
+// [max(l1, lo_known), min(l2, hi_known)]: geometric while it spans more than
+// 64x (or a = 0, then from b 1e-40), otherwise 7 even points and 8 around the
+// secant estimate in u = lambda^-1/2 from the evaluated bracket, spaced
+// (b - a) / 128 (or / 16384 once the range is within 1 % of a).
+struct OcFill {
+  bool geo;
+  double a, b, r, est, d;
+};
+
+__device__ inline OcFill oc_fill_params(double l1, double l2, double lo, double hi, double slo, double shi,
+                                        double target) {
+  OcFill f;
+  f.a = fmax(l1, lo);
+  f.b = fmin(l2, hi);
+  f.geo = f.a <= 0.0 || f.b > 64.0 * f.a;
+  f.r = 0.0;
+  f.d = 0.0;
+  f.est = 0.5 * (f.a + f.b);
+  if (f.geo) {
+    if (f.a <= 0.0) f.a = f.b * 1e-40;
+    f.r = log(f.b / f.a) / (OC_NCAND + 1);
+    return f;
   }
+  if (lo > 0.0 && hi < INFINITY && slo > shi) {
+    const double ul = 1.0 / sqrt(lo), uh = 1.0 / sqrt(hi);
+    const double u = uh + (target - shi) * (ul - uh) / (slo - shi);
+    if (u > 0.0) f.est = fmin(f.b, fmax(f.a, 1.0 / (u * u)));
+  }
+  f.d = (f.b - f.a) / ((f.b - f.a > 0.01 * f.a) ? 128.0 : 16384.0);
+  return f;
+}
+
+// Candidate t of a placement.
+__device__ inline double oc_candidate(int t, const OcFill& f) {
+  if (f.geo) return f.a * exp(f.r * (t + 1));
   constexpr int NLIN = 7;
-  for (int t = 0; t < NLIN; ++t) oc->cand[t] = a + (b - a) * (t + 1) / (NLIN + 1);
-  double est = 0.5 * (a + b);
-  if (oc->lo_known > 0.0 && oc->hi_known < INFINITY && oc->s_lo > oc->s_hi) {
-    const double ul = 1.0 / sqrt(oc->lo_known), uh = 1.0 / sqrt(oc->hi_known);
-    const double u = uh + (target - oc->s_hi) * (ul - uh) / (oc->s_lo - oc->s_hi);
-    if (u > 0.0) est = fmin(b, fmax(a, 1.0 / (u * u)));
-  }
-  const double d = (b - a) / ((b - a > 0.01 * a) ? 128.0 : 16384.0);
-  for (int t = NLIN; t < OC_NCAND; ++t) {
-    const double c = est + d * (t - NLIN - 3.5);
-    oc->cand[t] = fmin(b, fmax(a, c));
-  }
+  if (t < NLIN) return f.a + (f.b - f.a) * (t + 1) / (NLIN + 1);
+  return fmin(f.b, fmax(f.a, f.est + f.d * (t - NLIN - 3.5)));
+}
+
+__device__ void oc_fill_candidates(OcDev* oc, double target) {
+  const OcFill f = oc_fill_params(oc->l1, oc->l2, oc->lo_known, oc->hi_known, oc->s_lo, oc->s_hi, target);
+  for (int t = 0; t < OC_NCAND; ++t) oc->cand[t] = oc_candidate(t, f);
 }
 
 // With a previous multiplier (hint > 0, e.g. the last call's result), the first
@@ -289,49 +311,76 @@ __global__ __launch_bounds__(VB) void k_oc_pass(const double* __restrict__ x,
     if (lane == 0) red[wv][t] = v;
   }
   __syncthreads();
+  // candidate-major partials: part[t * gridDim.x + block]
   if (threadIdx.x < OC_NCAND) {
     double v = 0.0;
     for (int w = 0; w < VB / MGAR_WAVE; ++w) v += red[w][threadIdx.x];
-    part[blockIdx.x * OC_NCAND + threadIdx.x] = v;
+    part[threadIdx.x * gridDim.x + blockIdx.x] = v;
   }
 }
 
+// S at the candidates from the pass's candidate-major block partials (wave t
+// sums candidate t, lane l adding blocks l, l + 64, ... in order; np <= VMAXB),
+// then the bisection replayed by thread 0 and the next candidates placed by
+// threads 0..OC_NCAND-1.
 __global__ __launch_bounds__(FB) void k_oc_walk(OcDev* oc, const double* __restrict__ part, int np,
                                                 double target, double tol) {
   if (oc->done) return;
-  __shared__ double S[OC_NCAND];
+  __shared__ double S[OC_NCAND], C[OC_NCAND];
+  __shared__ OcFill fill;
+  __shared__ int fdone;
   const int lane = threadIdx.x & (MGAR_WAVE - 1), wv = threadIdx.x / MGAR_WAVE;
-  for (int t = wv; t < OC_NCAND; t += FB / MGAR_WAVE) {
+  // the state thread 0 needs, read before the partials arrive
+  double lo = 0.0, hi = 0.0, slo = 0.0, shi = 0.0, l1 = 0.0, l2 = 0.0, last = 0.0;
+  int steps = 0;
+  if (threadIdx.x == 0) {
+    lo = oc->lo_known; hi = oc->hi_known; slo = oc->s_lo; shi = oc->s_hi;
+    l1 = oc->l1; l2 = oc->l2; last = oc->lam_last; steps = oc->steps;
+  }
+  if (threadIdx.x < OC_NCAND) C[threadIdx.x] = oc->cand[threadIdx.x];
+  if (wv < OC_NCAND) {
+    constexpr int PK = (VMAXB + MGAR_WAVE - 1) / MGAR_WAVE;
+    const double* pt = part + (long long)wv * np;
+    double pv[PK];
+#pragma unroll
+    for (int k = 0; k < PK; ++k) {
+      const int b = lane + k * MGAR_WAVE;
+      pv[k] = b < np ? pt[b] : 0.0;
+    }
     double v = 0.0;
-    for (int b = lane; b < np; b += MGAR_WAVE) v += part[b * OC_NCAND + t];
+#pragma unroll
+    for (int k = 0; k < PK; ++k) v += pv[k];
     v = wave_sum(v);
-    if (lane == 0) S[t] = v;
+    if (lane == 0) S[wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double lo = oc->lo_known, hi = oc->hi_known, slo = oc->s_lo, shi = oc->s_hi;
-  for (int t = 0; t < OC_NCAND; ++t) {
-    const double c = oc->cand[t];
-    if (S[t] > target) {
-      if (c > lo) { lo = c; slo = S[t]; }
-    } else if (c < hi) {
-      hi = c; shi = S[t];
+  if (threadIdx.x == 0) {
+    for (int t = 0; t < OC_NCAND; ++t) {
+      const double c = C[t];
+      if (S[t] > target) {
+        if (c > lo) { lo = c; slo = S[t]; }
+      } else if (c < hi) {
+        hi = c; shi = S[t];
+      }
     }
+    int done = 0;
+    for (;;) {
+      if (!((l2 - l1) / (l1 + l2) > tol)) { done = 1; break; }
+      const double m = 0.5 * (l2 + l1);
+      if (m <= lo) l1 = m;
+      else if (m >= hi) l2 = m;
+      else break;
+      last = m;
+      ++steps;
+    }
+    oc->l1 = l1; oc->l2 = l2; oc->lam_last = last; oc->steps = steps;
+    oc->lo_known = lo; oc->hi_known = hi; oc->s_lo = slo; oc->s_hi = shi; oc->done = done;
+    fdone = done;
+    if (!done) fill = oc_fill_params(l1, l2, lo, hi, slo, shi, target);
   }
-  double l1 = oc->l1, l2 = oc->l2, last = oc->lam_last;
-  int steps = oc->steps, done = 0;
-  for (;;) {
-    if (!((l2 - l1) / (l1 + l2) > tol)) { done = 1; break; }
-    const double m = 0.5 * (l2 + l1);
-    if (m <= lo) l1 = m;
-    else if (m >= hi) l2 = m;
-    else break;
-    last = m;
-    ++steps;
-  }
-  oc->l1 = l1; oc->l2 = l2; oc->lam_last = last; oc->steps = steps;
-  oc->lo_known = lo; oc->hi_known = hi; oc->s_lo = slo; oc->s_hi = shi; oc->done = done;
-  if (!done) oc_fill_candidates(oc, target);
+  __syncthreads();
+  if (!fdone && threadIdx.x < OC_NCAND)
+    oc->cand[threadIdx.x] = oc_candidate(threadIdx.x, fill);
 }
 
 __global__ __launch_bounds__(VB) void k_oc_final(const double* __restrict__ x,

@@ -211,15 +211,12 @@ __global__ __launch_bounds__(TBX* TBY) void k_sens(Geo g, const double* __restri
 // midpoints in order, deciding each one from the evaluated bracket, until a
 // midpoint falls inside it. The midpoints, and so lam_last, are the same
 // floating-point values a plain bisection computes.
-// Candidate placement: geometric while the range spans more than a factor 64;
-// otherwise 7 points evenly over the range plus 8 points clustered around a
-// secant estimate in u = lambda^-1/2 (S is close to affine in u, since unclamped
-// elements contribute dv x sqrt(B) u).
-
+//
 // Placement of the next candidates for the undecided range [a, b] =
 // [max(l1, lo_known), min(l2, hi_known)]: geometric while it spans more than
 // 64x (or a = 0, then from b 1e-40), otherwise 7 even points and 8 around the
-// secant estimate in u = lambda^-1/2 from the evaluated bracket, spaced
+// secant estimate in u = lambda^-1/2 from the evaluated bracket (S is close to
+// affine in u, since unclamped elements contribute dv x sqrt(B) u), spaced
 // (b - a) / 128 (or / 16384 once the range is within 1 % of a).
 struct OcFill {
   bool geo;

@@ -121,6 +121,32 @@ def test_mixed_mgar(prob, eps, change):
     assert rel_l2(host(T1), t1) < tol
 
 
+@pytest.mark.parametrize("prob", PROBS[-2:], ids=IDS[-2:])
+@pytest.mark.parametrize("m", [3, 5])
+def test_mixed_mgar_larger_basis(prob, m):
+    """Mixed MGAR with m basis columns (FP32 V-cycles for the basis, the FP64
+    three-pass Gram-Schmidt and reduced system): path, Res (Eq 28) and the
+    temperature against the FP64 oracle with the same m."""
+    import torch
+    eps = 0.5
+    h = mhandle(prob, eps_accept=eps, n_basis=m)
+    q = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    h.mgar_load_vector(dev(W.element_source(prob)), q)
+    s = solvers.MgarSolver(prob, solvers.MgarParams(n_basis=m, eps_accept=eps))
+    x0 = W.random_density(prob.nelem, 31, 0.2, 0.8)
+    x1 = np.clip(1.01 * x0 + 1e-3 * W.random_vector(prob.nelem, 32), 0, 1)
+    t0, _ = s.mgcg(x0, np.zeros(prob.nnodes), 1e-8)
+    T0 = torch.empty(prob.nnodes, dtype=torch.float64, device="cuda")
+    T1 = torch.empty_like(T0)
+    h.mgcg_solve(dev(x0), q, None, 1e-8, T0)
+    t1, st_or = s.mgar(x1, t0, 1e-8)
+    st = h.mgar_solve(dev(x1), q, T0, 1e-8, T1)
+    assert st["path"] == st_or.path
+    assert abs(st["res_ca"] - st_or.res_ca) <= 1e-2 * st_or.res_ca
+    tol = 1e-6 if st["path"] == 2 else 1e-4
+    assert rel_l2(host(T1), t1) < tol
+
+
 def test_mixed_loop_c0_errors():
     """Full 50-cycle loop, mixed precision on the GPU against the FP64 oracle:
     stated tolerances compliance 1e-6 rel., final design 1e-4 max-abs."""

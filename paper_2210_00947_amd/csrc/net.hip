@@ -537,27 +537,44 @@ __global__ __launch_bounds__(NB) void k_wgrad(WgArgs a) {
   __shared__ double bsh[NBG * NBC];
   const int bco = tid % NBC, bgr = tid / NBC;
   double bsum = 0.0;
-  for (int t = t0; t < t1; ++t) {
+  // input chunk (channels cbase .. cbase + 15 of the concatenated input) of
+  // tile t into registers: the next tile's loads are issued before the
+  // current tile's matrix products, and stored to LDS after them
+  constexpr int NIT = (WROWS * (WRW / 4) * 4 + NB - 1) / NB;
+  u64 vin[NIT][4];
+  auto load_in = [&](int t) {
     const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
     const int x0 = TX * tx, y0 = TY * ty, z0 = TZ * tz;
-    // input chunk (channels cbase .. cbase + 15 of the concatenated input)
-    for (int it = tid; it < WROWS * (WRW / 4) * 4; it += NB) {
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int it = tid + u * NB;
       const int cq = it % 4, xg = (it / 4) % (WRW / 4), row = it / (4 * (WRW / 4));
       const int hy = row % HY, hz = row / HY;
       const int gy = y0 - 1 + hy, gz = z0 - 1 + hz, c = cbase + 4 * cq;
-      u64 v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int hx = 4 * xg + q, gx = x0 - 1 + hx;
-        v[q] = 0;
-        if (hx < HX && c < cin && gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nx && gy < a.ny && gz < a.nz) {
+        vin[u][q] = 0;
+        if (it < WROWS * (WRW / 4) * 4 && hx < HX && c < cin && gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nx &&
+            gy < a.ny && gz < a.nz) {
           const long long vox = gx + (long long)a.nx * (gy + (long long)a.ny * gz);
-          v[q] = c < a.c0 ? reinterpret_cast<const u64*>(a.a0)[(vox * a.c0 + c) / 4]
-                          : reinterpret_cast<const u64*>(a.a1)[(vox * a.c1 + (c - a.c0)) / 4];
+          vin[u][q] = c < a.c0 ? reinterpret_cast<const u64*>(a.a0)[(vox * a.c0 + c) / 4]
+                               : reinterpret_cast<const u64*>(a.a1)[(vox * a.c1 + (c - a.c0)) / 4];
         }
       }
+    }
+  };
+  if (t0 < t1) load_in(t0);
+  for (int t = t0; t < t1; ++t) {
+    const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
+    const int x0 = TX * tx, y0 = TY * ty, z0 = TZ * tz;
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int it = tid + u * NB;
+      if (it >= WROWS * (WRW / 4) * 4) continue;
+      const int cq = it % 4, xg = (it / 4) % (WRW / 4), row = it / (4 * (WRW / 4));
       u64 o[4];
-      tr4(v, o);
+      tr4(vin[u], o);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         *reinterpret_cast<u64*>(&As[(4 * cq + j) * WCS + row * WRW + 4 * xg]) = o[j];
@@ -587,6 +604,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(WgArgs a) {
       for (int j = 0; j < 4; ++j) *reinterpret_cast<u64*>(&Ds[(4 * cq + j) * WDS + vrow * TX + 4 * xg]) = o[j];
     }
     __syncthreads();
+    if (t + 1 < t1) load_in(t + 1);
     if (cg == 0 && bgr < NBG) {
       double s = 0.0;
       for (int v = bgr; v < TV; v += NBG) s += (double)bf2f(Ds[bco * WDS + v]);

@@ -154,8 +154,14 @@ __global__ __launch_bounds__(NB) void k_head_fwd(long long V, int C, const u16* 
                                                  const float* __restrict__ w, float* __restrict__ u) {
   const long long e = blockIdx.x * (long long)NB + threadIdx.x;
   if (e >= V) return;
+  // four channels per 8-byte load (C is a multiple of 16), summed in channel order
+  const u64* dq = reinterpret_cast<const u64*>(d0) + e * (C / 4);
   float s = 0.0f;
-  for (int c = 0; c < C; ++c) s += bf2f(d0[e * C + c]) * w[c];
+  for (int c4 = 0; c4 < C / 4; ++c4) {
+    const u64 v = dq[c4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s += bf2f((u16)(v >> (16 * a))) * w[4 * c4 + a];
+  }
   u[e] = s + w[C];
 }
 
@@ -171,16 +177,26 @@ __global__ __launch_bounds__(NB) void k_head_bwd(long long V, int C, const u16* 
   const bool in = e < V;
   const float g = in ? du[e] : 0.0f;
   const int wv = threadIdx.x / MGAR_WAVE, lane = threadIdx.x % MGAR_WAVE;
-  for (int c = 0; c <= C; ++c) {
-    double v = 0.0;
-    if (in && c < C) {
-      v = (double)bf2f(d0[e * C + c]) * (double)g;
-      gd0[e * C + c] = f2bf(g * w[c]);
-    } else if (in) {
-      v = (double)g;
+  // four channels per 8-byte load and store (C is a multiple of 16)
+  const u64* dq = reinterpret_cast<const u64*>(d0) + (in ? e : 0) * (C / 4);
+  u64* gq = reinterpret_cast<u64*>(gd0) + (in ? e : 0) * (C / 4);
+  for (int c4 = 0; c4 < C / 4; ++c4) {
+    const u64 dv = in ? dq[c4] : 0;
+    u64 go = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int c = 4 * c4 + a;
+      double v = in ? (double)bf2f((u16)(dv >> (16 * a))) * (double)g : 0.0;
+      go |= (u64)f2bf(g * w[c]) << (16 * a);
+      v = wave_sum(v);
+      if (lane == 0) sh[wv][c] = v;
     }
+    if (in) gq[c4] = go;
+  }
+  {
+    double v = in ? (double)g : 0.0;
     v = wave_sum(v);
-    if (lane == 0) sh[wv][c] = v;
+    if (lane == 0) sh[wv][C] = v;
   }
   __syncthreads();
   for (int c = threadIdx.x; c <= C; c += NB) {
@@ -206,25 +222,39 @@ __global__ __launch_bounds__(NB) void k_head_reduce(const double* __restrict__ p
 
 struct Dims { int nx, ny, nz; };
 
+// Voxel v = t / Q, channel quad q = t % Q and the voxel's (i, j, k) on an
+// nx x ny x .. grid, in 32-bit arithmetic (the network's sizes keep every
+// voxel x quad count below 2^28, checked at creation).
+struct VQ { unsigned v; int q, i, j, k; };
+__device__ inline VQ split_vq(unsigned t, int Q, int nx, int ny) {
+  VQ r;
+  r.v = t / (unsigned)Q;
+  r.q = (int)(t - r.v * (unsigned)Q);
+  const unsigned jk = r.v / (unsigned)nx;
+  r.i = (int)(r.v - jk * (unsigned)nx);
+  r.k = (int)(jk / (unsigned)ny);
+  r.j = (int)(jk - (unsigned)r.k * (unsigned)ny);
+  return r;
+}
+
 // coarse (nx, ny, nz) = fine / 2; one thread per (coarse voxel, channel quad)
 __global__ __launch_bounds__(NB) void k_pool(Dims c, int C, const u16* __restrict__ fine, u16* __restrict__ out) {
   const int Q = C / 4;
-  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
-  const long long V = (long long)c.nx * c.ny * c.nz;
-  if (t >= V * Q) return;
-  const long long v = t / Q;
-  const int q = (int)(t % Q);
-  const int i = (int)(v % c.nx), j = (int)((v / c.nx) % c.ny), k = (int)(v / ((long long)c.nx * c.ny));
+  const unsigned t = blockIdx.x * NB + threadIdx.x;
+  if (t >= (unsigned)c.nx * c.ny * c.nz * Q) return;
+  const VQ x = split_vq(t, Q, c.nx, c.ny);
+  const unsigned v = x.v;
+  const int q = x.q, i = x.i, j = x.j, k = x.k;
   const int fx = 2 * c.nx, fy = 2 * c.ny;
   float s[4] = {0.f, 0.f, 0.f, 0.f};
   for (int b = 0; b < 8; ++b) {
-    const long long fv = (2 * i + (b & 1)) + (long long)fx * ((2 * j + ((b >> 1) & 1)) + (long long)fy * (2 * k + (b >> 2)));
+    const unsigned fv = (2 * i + (b & 1)) + (unsigned)fx * ((2 * j + ((b >> 1) & 1)) + (unsigned)fy * (2 * k + (b >> 2)));
     const u64 w = reinterpret_cast<const u64*>(fine)[fv * Q + q];
     for (int a = 0; a < 4; ++a) s[a] += bf2f((u16)(w >> (16 * a)));
   }
   u64 o = 0;
   for (int a = 0; a < 4; ++a) o |= (u64)f2bf(s[a] * 0.125f) << (16 * a);
-  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+  reinterpret_cast<u64*>(out)[v * (unsigned)Q + q] = o;
 }
 
 // 1D linear 2x upsampling of cell-centred values: fine cell f lies at coarse
@@ -250,12 +280,11 @@ __device__ inline float up_weight(int f, int m, int n) {
 __global__ __launch_bounds__(NB) void k_up(Dims c, int C, const u16* __restrict__ crs, u16* __restrict__ out) {
   const int Q = C / 4;
   const int fx = 2 * c.nx, fy = 2 * c.ny, fz = 2 * c.nz;
-  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
-  const long long V = (long long)fx * fy * fz;
-  if (t >= V * Q) return;
-  const long long v = t / Q;
-  const int q = (int)(t % Q);
-  const int i = (int)(v % fx), j = (int)((v / fx) % fy), k = (int)(v / ((long long)fx * fy));
+  const unsigned t = blockIdx.x * NB + threadIdx.x;
+  if (t >= (unsigned)fx * fy * fz * Q) return;
+  const VQ vq = split_vq(t, Q, fx, fy);
+  const unsigned v = vq.v;
+  const int q = vq.q, i = vq.i, j = vq.j, k = vq.k;
   int x0, x1, y0, y1, z0, z1;
   float wx0, wx1, wy0, wy1, wz0, wz1;
   up_axis(i, c.nx, x0, x1, wx0, wx1);
@@ -265,12 +294,12 @@ __global__ __launch_bounds__(NB) void k_up(Dims c, int C, const u16* __restrict_
   for (int b = 0; b < 8; ++b) {
     const int xi = (b & 1) ? x1 : x0, yi = (b & 2) ? y1 : y0, zi = (b & 4) ? z1 : z0;
     const float wt = ((b & 1) ? wx1 : wx0) * ((b & 2) ? wy1 : wy0) * ((b & 4) ? wz1 : wz0);
-    const u64 w = reinterpret_cast<const u64*>(crs)[(xi + (long long)c.nx * (yi + (long long)c.ny * zi)) * Q + q];
+    const u64 w = reinterpret_cast<const u64*>(crs)[(xi + (unsigned)c.nx * (yi + (unsigned)c.ny * zi)) * Q + q];
     for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w >> (16 * a)));
   }
   u64 o = 0;
   for (int a = 0; a < 4; ++a) o |= (u64)f2bf(s[a]) << (16 * a);
-  reinterpret_cast<u64*>(out)[v * Q + q] = o;
+  reinterpret_cast<u64*>(out)[v * (unsigned)Q + q] = o;
 }
 
 // coarse = up^T(fine); one thread per (coarse voxel, channel quad): gathers the
@@ -278,12 +307,11 @@ __global__ __launch_bounds__(NB) void k_up(Dims c, int C, const u16* __restrict_
 __global__ __launch_bounds__(NB) void k_up_adj(Dims c, int C, const u16* __restrict__ fine, u16* __restrict__ out) {
   const int Q = C / 4;
   const int fx = 2 * c.nx, fy = 2 * c.ny, fz = 2 * c.nz;
-  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
-  const long long V = (long long)c.nx * c.ny * c.nz;
-  if (t >= V * Q) return;
-  const long long v = t / Q;
-  const int q = (int)(t % Q);
-  const int i = (int)(v % c.nx), j = (int)((v / c.nx) % c.ny), k = (int)(v / ((long long)c.nx * c.ny));
+  const unsigned t = blockIdx.x * NB + threadIdx.x;
+  if (t >= (unsigned)c.nx * c.ny * c.nz * Q) return;
+  const VQ vq = split_vq(t, Q, c.nx, c.ny);
+  const unsigned v = vq.v;
+  const int q = vq.q, i = vq.i, j = vq.j, k = vq.k;
   float s[4] = {0.f, 0.f, 0.f, 0.f};
   for (int dz = -1; dz <= 2; ++dz) {
     const int fk = 2 * k + dz;
@@ -301,7 +329,7 @@ __global__ __launch_bounds__(NB) void k_up_adj(Dims c, int C, const u16* __restr
         const float wx = up_weight(fi, i, c.nx);
         if (wx == 0.0f) continue;
         const float wt = wx * wy * wz;
-        const u64 w = reinterpret_cast<const u64*>(fine)[(fi + (long long)fx * (fj + (long long)fy * fk)) * Q + q];
+        const u64 w = reinterpret_cast<const u64*>(fine)[(fi + (unsigned)fx * (fj + (unsigned)fy * fk)) * Q + q];
         for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w >> (16 * a)));
       }
     }
@@ -316,13 +344,12 @@ __global__ __launch_bounds__(NB) void k_up_adj(Dims c, int C, const u16* __restr
 __global__ __launch_bounds__(NB) void k_skip_add(Dims f, int C, const u16* __restrict__ gsk,
                                                  const u16* __restrict__ gp, u16* __restrict__ out) {
   const int Q = C / 4;
-  const long long t = blockIdx.x * (long long)NB + threadIdx.x;
-  const long long V = (long long)f.nx * f.ny * f.nz;
-  if (t >= V * Q) return;
-  const long long v = t / Q;
-  const int q = (int)(t % Q);
-  const int i = (int)(v % f.nx), j = (int)((v / f.nx) % f.ny), k = (int)(v / ((long long)f.nx * f.ny));
-  const long long cv = (i / 2) + (long long)(f.nx / 2) * ((j / 2) + (long long)(f.ny / 2) * (k / 2));
+  const unsigned t = blockIdx.x * NB + threadIdx.x;
+  if (t >= (unsigned)f.nx * f.ny * f.nz * Q) return;
+  const VQ vq = split_vq(t, Q, f.nx, f.ny);
+  const unsigned v = vq.v;
+  const int q = vq.q, i = vq.i, j = vq.j, k = vq.k;
+  const unsigned cv = (i / 2) + (unsigned)(f.nx / 2) * ((j / 2) + (unsigned)(f.ny / 2) * (k / 2));
   const u64 a = reinterpret_cast<const u64*>(gsk)[v * Q + q];
   const u64 b = reinterpret_cast<const u64*>(gp)[cv * Q + q];
   u64 o = 0;
@@ -989,6 +1016,12 @@ int create_impl(mgar_net* N, const mgar_params* p, int levels, const int* channe
     N->C[l] = channels[l];
     N->lv[l] = Dims{p->nelx >> l, p->nely >> l, p->nelz >> l};
     N->V[l] = (long long)N->lv[l].nx * N->lv[l].ny * N->lv[l].nz;
+  }
+  // the pooling, upsampling and skip kernels take one thread per (voxel,
+  // channel quad) of a grid, with 32-bit indices and at most nblk's block cap
+  for (int l = 0; l < levels; ++l) {
+    const int cm = std::max({N->C[std::max(l - 1, 0)], N->C[l], N->C[std::min(l + 1, levels - 1)]});
+    if (N->V[l] * (cm / 4) > 65535LL * 16 * NB) return MGAR_E_DIMS;
   }
   const int L = levels;
   // layers in parameter order: encoder, decoder, head

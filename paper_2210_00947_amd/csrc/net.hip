@@ -686,26 +686,31 @@ __global__ __launch_bounds__(NB) void k_wgrad(WgArgs a) {
 // grad[woff + (co ci + c) 27 + tap] = sum over blocks of part[b][tap][co][c]
 // (c < ci), and grad[boff + co] = sum over blocks of bpart[b][co]. Sixteen
 // threads per parameter: thread q sums the blocks q, q + 16, ... in order and
-// the sixteen sums are added in order of q.
-constexpr int WRQ = 16;
-__global__ __launch_bounds__(NB) void k_wreduce(const float* __restrict__ part, const double* __restrict__ bpart,
-                                                int nb, int cout, int ci, int cin16, double* __restrict__ gw,
-                                                double* __restrict__ gb) {
-  __shared__ double sh[NB];
-  const int q = threadIdx.x % WRQ;
-  const long long t = blockIdx.x * (long long)(NB / WRQ) + threadIdx.x / WRQ;
+// the sixteen sums are added in order of q. A block holds WRT consecutive
+// parameters (one per lane, so a wave's loads of one block row are contiguous)
+// times the WRQ threads of each.
+constexpr int WRQ = 16, WRT = 64;
+__global__ __launch_bounds__(WRT * WRQ) void k_wreduce(const float* __restrict__ part,
+                                                       const double* __restrict__ bpart, int nb, int cout,
+                                                       int ci, int cin16, double* __restrict__ gw,
+                                                       double* __restrict__ gb) {
+  __shared__ double sh[WRQ][WRT];
+  const int tl = threadIdx.x % WRT, q = threadIdx.x / WRT;
+  const long long t = blockIdx.x * (long long)WRT + tl;
   const long long nw = 27LL * cout * cin16;
   double s = 0.0;
   if (t < nw) {
+#pragma unroll 8
     for (int b = q; b < nb; b += WRQ) s += (double)part[(long long)b * nw + t];
   } else if (t < nw + cout) {
+#pragma unroll 8
     for (int b = q; b < nb; b += WRQ) s += bpart[(long long)b * cout + (t - nw)];
   }
-  sh[threadIdx.x] = s;
+  sh[q][tl] = s;
   __syncthreads();
   if (q == 0 && t < nw + cout) {
     double v = 0.0;
-    for (int k = 0; k < WRQ; ++k) v += sh[threadIdx.x + k];
+    for (int k = 0; k < WRQ; ++k) v += sh[k][tl];
     if (t < nw) {
       const int c = (int)(t % cin16), co = (int)((t / cin16) % cout), tap = (int)(t / ((long long)cin16 * cout));
       if (c < ci) gw[((long long)co * ci + c) * 27 + tap] = v;
@@ -876,7 +881,7 @@ int wgrad(mgar_net* n, int li, const Dims& d, const u16* a0, int c0, const u16* 
     default: hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(NB), 0, n->s, a); break;
   }
   NLAUNCH();
-  hipLaunchKernelGGL(k_wreduce, dim3((unsigned)((per + a.cout + NB / WRQ - 1) / (NB / WRQ))), dim3(NB), 0, n->s,
+  hipLaunchKernelGGL(k_wreduce, dim3((unsigned)((per + a.cout + WRT - 1) / WRT)), dim3(WRT * WRQ), 0, n->s,
                      (const float*)n->wpart,
                      (const double*)n->bpart, (int)nb, a.cout, Ly.ci, a.cin16, n->grad + Ly.woff,
                      n->grad + Ly.boff);

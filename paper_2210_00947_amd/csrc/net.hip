@@ -312,25 +312,37 @@ __global__ __launch_bounds__(NB) void k_up_adj(Dims c, int C, const u16* __restr
   const VQ vq = split_vq(t, Q, c.nx, c.ny);
   const unsigned v = vq.v;
   const int q = vq.q, i = vq.i, j = vq.j, k = vq.k;
+  // per axis, the weights of the fine cells 2m - 1 .. 2m + 2 (0 outside the
+  // grid); the terms are taken in the same order and skipped where a weight is 0
+  float wx[4], wy[4], wz[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int fi = 2 * i + d - 1, fj = 2 * j + d - 1, fk = 2 * k + d - 1;
+    wx[d] = (fi >= 0 && fi < fx) ? up_weight(fi, i, c.nx) : 0.0f;
+    wy[d] = (fj >= 0 && fj < fy) ? up_weight(fj, j, c.ny) : 0.0f;
+    wz[d] = (fk >= 0 && fk < fz) ? up_weight(fk, k, c.nz) : 0.0f;
+  }
   float s[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int dz = -1; dz <= 2; ++dz) {
-    const int fk = 2 * k + dz;
-    if (fk < 0 || fk >= fz) continue;
-    const float wz = up_weight(fk, k, c.nz);
-    if (wz == 0.0f) continue;
-    for (int dy = -1; dy <= 2; ++dy) {
-      const int fj = 2 * j + dy;
-      if (fj < 0 || fj >= fy) continue;
-      const float wy = up_weight(fj, j, c.ny);
-      if (wy == 0.0f) continue;
-      for (int dx = -1; dx <= 2; ++dx) {
-        const int fi = 2 * i + dx;
-        if (fi < 0 || fi >= fx) continue;
-        const float wx = up_weight(fi, i, c.nx);
-        if (wx == 0.0f) continue;
-        const float wt = wx * wy * wz;
-        const u64 w = reinterpret_cast<const u64*>(fine)[(fi + (unsigned)fx * (fj + (unsigned)fy * fk)) * Q + q];
-        for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w >> (16 * a)));
+  for (int dz = 0; dz < 4; ++dz) {
+    if (wz[dz] == 0.0f) continue;
+    const int fk = 2 * k + dz - 1;
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy) {
+      if (wy[dy] == 0.0f) continue;
+      const int fj = 2 * j + dy - 1;
+      u64 w4[4];
+#pragma unroll
+      for (int dx = 0; dx < 4; ++dx) {
+        const int fi = 2 * i + dx - 1;
+        w4[dx] = wx[dx] != 0.0f
+                     ? reinterpret_cast<const u64*>(fine)[(fi + (unsigned)fx * (fj + (unsigned)fy * fk)) * Q + q]
+                     : 0;
+      }
+#pragma unroll
+      for (int dx = 0; dx < 4; ++dx) {
+        if (wx[dx] == 0.0f) continue;
+        const float wt = wx[dx] * wy[dy] * wz[dz];
+        for (int a = 0; a < 4; ++a) s[a] += wt * bf2f((u16)(w4[dx] >> (16 * a)));
       }
     }
   }
